@@ -1,0 +1,175 @@
+"""CPU oracle for DFG discovery (test infrastructure only).
+
+Loads ``libpm4g_oracle.so`` built from ``pm4g_oracle.c`` in this directory
+(building it with gcc if it is missing) and wraps each function for numpy
+arrays.  Only the tests, the smoke check and the CPU-baseline leg of the
+benchmark import this package; the HIP library never does.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pm4g_oracle.c")
+_LIB = os.path.join(_HERE, "libpm4g_oracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, plain C11)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-Wall", "-Wextra", "-shared", "-fPIC",
+                               _SRC, "-o", tmp])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64, i32 = ctypes.c_int64, ctypes.c_int32
+        L.orc_prepare.argtypes = [i64, P, P, P, i32, P, P, P, P, P, P, P]
+        L.orc_dfg.argtypes = [i64, P, P, P, i32, P, P, P, P, P, P, P, P, P, P, P]
+        L.orc_variants.argtypes = [i64, P, P, P, i32, P, P, P, P, P, P, P, P, P]
+        L.orc_view.argtypes = [i64, P, P, P, i32, i32, i32, i64, i64, P,
+                               P, P, P, P, P, P, P, P, P, P, P]
+        for f in (L.orc_prepare, L.orc_dfg, L.orc_variants, L.orc_view):
+            f.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__({-1: "invalid argument", -2: "activity out of range"}.get(code, str(code)))
+        self.code = code
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _cols(case, act, ts):
+    case = np.ascontiguousarray(case, dtype=np.int32)
+    act = np.ascontiguousarray(act, dtype=np.int32)
+    ts = np.ascontiguousarray(ts, dtype=np.int64)
+    if not (case.shape == act.shape == ts.shape and case.ndim == 1):
+        raise ValueError("case, act, ts must be 1-D and of equal length")
+    return case, act, ts
+
+
+def prepare(case, act, ts, A: int) -> dict:
+    """The formatted log: rows in (case, ts, row) order plus the case table."""
+    case, act, ts = _cols(case, act, ts)
+    n = case.shape[0]
+    m = max(n, 1)
+    out = dict(row=np.empty(m, np.int64), case_s=np.empty(m, np.int32), act_s=np.empty(m, np.int32),
+               ts_s=np.empty(m, np.int64), case_off=np.empty(m + 1, np.int64),
+               case_code=np.empty(m, np.int32))
+    C = np.zeros(1, np.int64)
+    rc = _load().orc_prepare(n, _p(case), _p(act), _p(ts), A, _p(out["row"]), _p(out["case_s"]),
+                             _p(out["act_s"]), _p(out["ts_s"]), _p(out["case_off"]),
+                             _p(out["case_code"]), _p(C))
+    if rc:
+        raise OracleError(rc)
+    c = int(C[0])
+    for k in ("row", "case_s", "act_s", "ts_s"):
+        out[k] = out[k][:n]
+    out["case_off"] = out["case_off"][:c + 1]
+    out["case_code"] = out["case_code"][:c]
+    out["n_cases"] = c
+    return out
+
+
+def dfg(case, act, ts, A: int, with_perm: bool = False) -> dict:
+    """Frequency/performance DFG with start/end/activity counts (dense A x A)."""
+    case, act, ts = _cols(case, act, ts)
+    n = case.shape[0]
+    cells = A * A
+    o = dict(count=np.empty(cells, np.int64), dt_sum=np.empty(cells, np.int64),
+             dt_min=np.empty(cells, np.int64), dt_max=np.empty(cells, np.int64),
+             dt_mean=np.empty(cells, np.float64), start_count=np.empty(A, np.int64),
+             end_count=np.empty(A, np.int64), act_count=np.empty(A, np.int64))
+    perm = np.empty(max(n, 1), np.int64) if with_perm else None
+    C = np.zeros(1, np.int64)
+    ov = np.zeros(1, np.int32)
+    rc = _load().orc_dfg(n, _p(case), _p(act), _p(ts), A, _p(perm) if perm is not None else None,
+                         _p(o["count"]), _p(o["dt_sum"]), _p(o["dt_min"]), _p(o["dt_max"]),
+                         _p(o["dt_mean"]), _p(o["start_count"]), _p(o["end_count"]),
+                         _p(o["act_count"]), _p(C), _p(ov))
+    if rc:
+        raise OracleError(rc)
+    for k in ("count", "dt_sum", "dt_min", "dt_max", "dt_mean"):
+        o[k] = o[k].reshape(A, A)
+    o["n_cases"] = int(C[0])
+    o["overflow"] = int(ov[0])
+    if perm is not None:
+        o["perm"] = perm[:n]
+    return o
+
+
+def variants(case, act, ts, A: int) -> dict:
+    """Exact trace variants, ids in (count desc, representative asc) order."""
+    case, act, ts = _cols(case, act, ts)
+    n = case.shape[0]
+    m = max(n, 1)
+    o = dict(var_count=np.empty(m, np.int64), var_len=np.empty(m, np.int32),
+             var_rep=np.empty(m, np.int32), var_off=np.empty(m + 1, np.int64),
+             var_acts=np.empty(m, np.int32), case_code=np.empty(m, np.int32),
+             case_variant=np.empty(m, np.int32))
+    V = np.zeros(1, np.int64)
+    C = np.zeros(1, np.int64)
+    rc = _load().orc_variants(n, _p(case), _p(act), _p(ts), A, _p(V), _p(o["var_count"]),
+                              _p(o["var_len"]), _p(o["var_rep"]), _p(o["var_off"]),
+                              _p(o["var_acts"]), _p(o["case_code"]), _p(o["case_variant"]), _p(C))
+    if rc:
+        raise OracleError(rc)
+    v, c = int(V[0]), int(C[0])
+    for k in ("var_count", "var_len", "var_rep"):
+        o[k] = o[k][:v]
+    o["var_off"] = o["var_off"][:v + 1]
+    o["var_acts"] = o["var_acts"][:int(o["var_off"][v])]
+    o["case_code"] = o["case_code"][:c]
+    o["case_variant"] = o["case_variant"][:c]
+    o["n_variants"] = v
+    o["n_cases"] = c
+    return o
+
+
+def view(case, act, ts, A: int, case_lo: int, case_hi: int, t_lo: int, t_hi: int,
+         mask) -> dict:
+    """DFG of the events retained by one drill-down view (dense A x A)."""
+    case, act, ts = _cols(case, act, ts)
+    n = case.shape[0]
+    W = (A + 63) // 64
+    mask = np.ascontiguousarray(mask, dtype=np.uint64)
+    if mask.shape != (W,):
+        raise ValueError("mask must have ceil(A/64) words")
+    cells = A * A
+    o = dict(count=np.empty(cells, np.int64), dt_sum=np.empty(cells, np.int64),
+             dt_min=np.empty(cells, np.int64), dt_max=np.empty(cells, np.int64),
+             dt_mean=np.empty(cells, np.float64), start_count=np.empty(A, np.int64),
+             end_count=np.empty(A, np.int64), act_count=np.empty(A, np.int64))
+    C = np.zeros(1, np.int64)
+    ov = np.zeros(1, np.int32)
+    ne = np.zeros(1, np.int64)
+    rc = _load().orc_view(n, _p(case), _p(act), _p(ts), A, int(case_lo), int(case_hi), int(t_lo),
+                          int(t_hi), _p(mask), _p(o["count"]), _p(o["dt_sum"]), _p(o["dt_min"]),
+                          _p(o["dt_max"]), _p(o["dt_mean"]), _p(o["start_count"]),
+                          _p(o["end_count"]), _p(o["act_count"]), _p(C), _p(ov), _p(ne))
+    if rc:
+        raise OracleError(rc)
+    for k in ("count", "dt_sum", "dt_min", "dt_max", "dt_mean"):
+        o[k] = o[k].reshape(A, A)
+    o["n_cases"] = int(C[0])
+    o["overflow"] = int(ov[0])
+    o["n_events"] = int(ne[0])
+    return o

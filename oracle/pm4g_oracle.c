@@ -1,0 +1,367 @@
+/*
+ * pm4g_oracle.c -- plain, slow, single-threaded CPU oracle for directly-follows
+ * graph (DFG) discovery over a columnar event log (case id, activity, timestamp).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the checker the GPU path is compared
+ * against.  Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load it.  It shares no code, header, table or helper with the
+ * HIP library; it does not include pm4g.h.
+ *
+ * Every function writes out the plain definition of what the method computes
+ * (PM4Py-GPU, Berti, Phan Nghia, van der Aalst, arXiv 2204.04898):
+ *
+ *   order      Sec. 3, first formatting step: events are ordered by case
+ *              identifier, then timestamp, then absolute row index.
+ *   shift      Sec. 3, second formatting step: each event sees the activity
+ *              and timestamp of the previous event of its case.
+ *   DFG        Sec. 3, "directly-follows level" aggregation: the frequency /
+ *              performance directly-follows graph.  The paper names no
+ *              performance aggregate; here it is the exact int64 count, sum,
+ *              min and max of the time gaps, with the FP64 mean sum/count.
+ *   endpoints  Sec. 3, start/end activities module, and the event-level
+ *              example "occurrences per activity".
+ *   variants   Sec. 3, variant-level aggregation (cases grouped by their
+ *              activity sequence; a double aggregation).
+ *   views      Sec. 1 drill-down ("smaller views on the dataset"), Sec. 3
+ *              timestamp filter on events and attribute (activity) filter,
+ *              composed as a conjunction; the DFG is re-discovered on the
+ *              retained events.
+ *
+ * Readings where the paper is silent (each is listed in the design notes):
+ *   - the row tie-break is the 0-based row index in the caller's arrays;
+ *   - a gap is t_next - t_prev computed modulo 2^64 and read as int64; sums
+ *     wrap modulo 2^64; min/max compare as signed int64;
+ *   - empty DFG cell: count 0, sum 0, min INT64_MAX, max INT64_MIN, mean NaN;
+ *   - overflow flag: set iff the sum over cases of (t_last - t_first),
+ *     evaluated exactly, exceeds INT64_MAX;
+ *   - variants are exact sequence classes, numbered by (count desc,
+ *     representative asc) where the representative is the smallest case code;
+ *   - a view keeps event i iff case_lo <= c_i < case_hi, t_lo <= t_i <= t_hi
+ *     and the activity bit of a_i is set in the mask.
+ *
+ * Status codes: 0 ok, -1 invalid argument, -2 activity out of [0, A).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+
+#define ORC_OK 0
+#define ORC_E_INVALID -1
+#define ORC_E_RANGE -2
+
+typedef struct {
+    int32_t c;
+    int64_t t;
+    int64_t row;
+} orc_event;
+
+/* The total order of the first formatting step: (case, timestamp, row). */
+static int cmp_event(const void *pa, const void *pb)
+{
+    const orc_event *a = (const orc_event *)pa, *b = (const orc_event *)pb;
+    if (a->c != b->c) return a->c < b->c ? -1 : 1;
+    if (a->t != b->t) return a->t < b->t ? -1 : 1;
+    if (a->row != b->row) return a->row < b->row ? -1 : 1;
+    return 0;
+}
+
+static int check_acts(int64_t n, const int32_t *act, int32_t A)
+{
+    for (int64_t i = 0; i < n; i++)
+        if (act[i] < 0 || act[i] >= A) return ORC_E_RANGE;
+    return ORC_OK;
+}
+
+/* Returns a malloc'ed array of the n events in (case, ts, row) order. */
+static orc_event *sorted_events(int64_t n, const int32_t *case_id, const int64_t *ts)
+{
+    orc_event *e = (orc_event *)malloc((size_t)(n > 0 ? n : 1) * sizeof(orc_event));
+    if (!e) return NULL;
+    for (int64_t i = 0; i < n; i++) {
+        e[i].c = case_id[i];
+        e[i].t = ts[i];
+        e[i].row = i;
+    }
+    qsort(e, (size_t)n, sizeof(orc_event), cmp_event);
+    return e;
+}
+
+/*
+ * orc_prepare: the formatted log.  Writes, for k = 0..n-1 in (case, ts, row)
+ * order, the row, case, activity and timestamp of the k-th event, and the case
+ * table: case_code[j] is the j-th distinct case (ascending), its events are
+ * positions case_off[j] .. case_off[j+1]-1.  Any output pointer may be NULL.
+ */
+int orc_prepare(int64_t n, const int32_t *case_id, const int32_t *act, const int64_t *ts,
+                int32_t A, int64_t *row_out, int32_t *case_s, int32_t *act_s, int64_t *ts_s,
+                int64_t *case_off, int32_t *case_code, int64_t *n_cases)
+{
+    if (n < 0 || A < 1) return ORC_E_INVALID;
+    if (check_acts(n, act, A)) return ORC_E_RANGE;
+    orc_event *e = sorted_events(n, case_id, ts);
+    if (!e) return ORC_E_INVALID;
+    int64_t C = 0;
+    for (int64_t k = 0; k < n; k++) {
+        int64_t r = e[k].row;
+        if (row_out) row_out[k] = r;
+        if (case_s) case_s[k] = e[k].c;
+        if (act_s) act_s[k] = act[r];
+        if (ts_s) ts_s[k] = ts[r];
+        if (k == 0 || e[k].c != e[k - 1].c) {
+            if (case_off) case_off[C] = k;
+            if (case_code) case_code[C] = e[k].c;
+            C++;
+        }
+    }
+    if (case_off) case_off[C] = n;
+    if (n_cases) *n_cases = C;
+    free(e);
+    return ORC_OK;
+}
+
+/*
+ * orc_dfg: frequency and performance DFG, start/end/activity counts.
+ * count, dt_sum, dt_min, dt_max, dt_mean are [A*A] row-major (src*A + dst);
+ * start_count, end_count, act_count are [A].  perm (optional, [n]) receives
+ * the row of the k-th event in order.
+ */
+int orc_dfg(int64_t n, const int32_t *case_id, const int32_t *act, const int64_t *ts,
+            int32_t A, int64_t *perm, int64_t *count, int64_t *dt_sum, int64_t *dt_min,
+            int64_t *dt_max, double *dt_mean, int64_t *start_count, int64_t *end_count,
+            int64_t *act_count, int64_t *n_cases, int32_t *overflow)
+{
+    if (n < 0 || A < 1) return ORC_E_INVALID;
+    if (check_acts(n, act, A)) return ORC_E_RANGE;
+    const int64_t cells = (int64_t)A * A;
+    for (int64_t x = 0; x < cells; x++) {
+        count[x] = 0;
+        dt_sum[x] = 0;
+        dt_min[x] = INT64_MAX;
+        dt_max[x] = INT64_MIN;
+    }
+    for (int32_t a = 0; a < A; a++) start_count[a] = end_count[a] = act_count[a] = 0;
+
+    orc_event *e = sorted_events(n, case_id, ts);
+    if (!e) return ORC_E_INVALID;
+
+    int64_t C = 0;
+    unsigned __int128 total_span = 0;   /* exact sum over cases of t_last - t_first */
+    int64_t case_first_t = 0;
+    for (int64_t k = 0; k < n; k++) {
+        int64_t r = e[k].row;
+        int32_t a = act[r];
+        if (perm) perm[k] = r;
+        act_count[a] += 1;
+        int new_case = (k == 0) || (e[k].c != e[k - 1].c);
+        if (new_case) {
+            if (k > 0) {
+                /* close the previous case: its last event is k-1 */
+                end_count[act[e[k - 1].row]] += 1;
+                total_span += (unsigned __int128)((uint64_t)e[k - 1].t - (uint64_t)case_first_t);
+            }
+            start_count[a] += 1;
+            case_first_t = e[k].t;
+            C++;
+        } else {
+            /* event k directly follows event k-1 of the same case */
+            int32_t x = act[e[k - 1].row];
+            int64_t cell = (int64_t)x * A + a;
+            uint64_t gap_u = (uint64_t)e[k].t - (uint64_t)e[k - 1].t;
+            int64_t gap = (int64_t)gap_u;
+            count[cell] += 1;
+            dt_sum[cell] = (int64_t)((uint64_t)dt_sum[cell] + gap_u);
+            if (gap < dt_min[cell]) dt_min[cell] = gap;
+            if (gap > dt_max[cell]) dt_max[cell] = gap;
+        }
+    }
+    if (n > 0) {
+        end_count[act[e[n - 1].row]] += 1;
+        total_span += (unsigned __int128)((uint64_t)e[n - 1].t - (uint64_t)case_first_t);
+    }
+    /* performance DFG mean: one int64 -> double conversion of each operand and
+       one IEEE division; empty cells get NaN */
+    for (int64_t x = 0; x < cells; x++)
+        dt_mean[x] = count[x] > 0 ? (double)dt_sum[x] / (double)count[x] : NAN;
+    *n_cases = C;
+    *overflow = total_span > (unsigned __int128)INT64_MAX ? 1 : 0;
+    free(e);
+    return ORC_OK;
+}
+
+/* ---- variants -------------------------------------------------------- */
+
+typedef struct {
+    int32_t code;      /* case code */
+    int64_t off, len;  /* its events in the ordered activity array */
+} orc_case;
+
+static const int32_t *g_seq_acts;   /* qsort has no context argument */
+
+/* Lexicographic order of activity sequences, a shorter prefix first. */
+static int cmp_case_seq(const void *pa, const void *pb)
+{
+    const orc_case *a = (const orc_case *)pa, *b = (const orc_case *)pb;
+    int64_t m = a->len < b->len ? a->len : b->len;
+    for (int64_t k = 0; k < m; k++) {
+        int32_t x = g_seq_acts[a->off + k], y = g_seq_acts[b->off + k];
+        if (x != y) return x < y ? -1 : 1;
+    }
+    if (a->len != b->len) return a->len < b->len ? -1 : 1;
+    return 0;
+}
+
+static int same_seq(const orc_case *a, const orc_case *b)
+{
+    if (a->len != b->len) return 0;
+    return memcmp(g_seq_acts + a->off, g_seq_acts + b->off, (size_t)a->len * sizeof(int32_t)) == 0;
+}
+
+typedef struct {
+    int64_t first, size;   /* index range in the sequence-sorted case array */
+    int64_t n;             /* number of cases */
+    int32_t rep;           /* smallest case code */
+} orc_class;
+
+static int cmp_class(const void *pa, const void *pb)
+{
+    const orc_class *a = (const orc_class *)pa, *b = (const orc_class *)pb;
+    if (a->n != b->n) return a->n > b->n ? -1 : 1;     /* count descending */
+    if (a->rep != b->rep) return a->rep < b->rep ? -1 : 1;   /* rep ascending */
+    return 0;
+}
+
+static int cmp_case_code(const void *pa, const void *pb)
+{
+    const orc_case *a = (const orc_case *)pa, *b = (const orc_case *)pb;
+    return a->code < b->code ? -1 : (a->code > b->code ? 1 : 0);
+}
+
+/*
+ * orc_variants: exact trace variants.
+ * Outputs (caller sizes them by n, which bounds both V and C):
+ *   n_variants                     V
+ *   var_count[V], var_len[V], var_rep[V]
+ *   var_off[V+1], var_acts[sum of lengths]   CSR of the sequences
+ *   case_code[C]                   distinct cases ascending
+ *   case_variant[C]                variant id of case_code[j]
+ *   n_cases                        C
+ */
+int orc_variants(int64_t n, const int32_t *case_id, const int32_t *act, const int64_t *ts,
+                 int32_t A, int64_t *n_variants, int64_t *var_count, int32_t *var_len,
+                 int32_t *var_rep, int64_t *var_off, int32_t *var_acts, int32_t *case_code,
+                 int32_t *case_variant, int64_t *n_cases)
+{
+    if (n < 0 || A < 1) return ORC_E_INVALID;
+    if (check_acts(n, act, A)) return ORC_E_RANGE;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    int32_t *acts_sorted = (int32_t *)malloc(nn * sizeof(int32_t));
+    int64_t *off = (int64_t *)malloc((nn + 1) * sizeof(int64_t));
+    int32_t *codes = (int32_t *)malloc(nn * sizeof(int32_t));
+    int64_t C = 0;
+    int rc = orc_prepare(n, case_id, act, ts, A, NULL, NULL, acts_sorted, NULL, off, codes, &C);
+    if (rc) { free(acts_sorted); free(off); free(codes); return rc; }
+
+    orc_case *cs = (orc_case *)malloc((size_t)(C > 0 ? C : 1) * sizeof(orc_case));
+    for (int64_t j = 0; j < C; j++) {
+        cs[j].code = codes[j];
+        cs[j].off = off[j];
+        cs[j].len = off[j + 1] - off[j];
+    }
+    /* group: sort the cases by their sequence, equal sequences become adjacent */
+    g_seq_acts = acts_sorted;
+    qsort(cs, (size_t)C, sizeof(orc_case), cmp_case_seq);
+
+    orc_class *cl = (orc_class *)malloc((size_t)(C > 0 ? C : 1) * sizeof(orc_class));
+    int64_t V = 0;
+    for (int64_t j = 0; j < C; j++) {
+        if (j == 0 || !same_seq(&cs[j - 1], &cs[j])) {
+            cl[V].first = j;
+            cl[V].size = 0;
+            cl[V].rep = cs[j].code;
+            V++;
+        }
+        orc_class *k = &cl[V - 1];
+        k->size += 1;
+        if (cs[j].code < k->rep) k->rep = cs[j].code;
+    }
+    for (int64_t v = 0; v < V; v++) cl[v].n = cl[v].size;
+    qsort(cl, (size_t)V, sizeof(orc_class), cmp_class);
+
+    /* emit: CSR of sequences, and each case's variant id */
+    int64_t pos = 0;
+    for (int64_t v = 0; v < V; v++) {
+        const orc_case *first = &cs[cl[v].first];
+        var_count[v] = cl[v].n;
+        var_len[v] = (int32_t)first->len;
+        var_rep[v] = cl[v].rep;
+        var_off[v] = pos;
+        memcpy(var_acts + pos, acts_sorted + first->off, (size_t)first->len * sizeof(int32_t));
+        pos += first->len;
+    }
+    var_off[V] = pos;
+    /* case_variant in ascending case-code order */
+    int32_t *vid_of_seqpos = (int32_t *)malloc((size_t)(C > 0 ? C : 1) * sizeof(int32_t));
+    for (int64_t v = 0; v < V; v++)
+        for (int64_t j = cl[v].first; j < cl[v].first + cl[v].size; j++) vid_of_seqpos[j] = (int32_t)v;
+    /* carry the ids along (in the no longer needed len field) while putting
+       the cases back in code order */
+    for (int64_t j = 0; j < C; j++) cs[j].len = vid_of_seqpos[j];
+    qsort(cs, (size_t)C, sizeof(orc_case), cmp_case_code);
+    for (int64_t j = 0; j < C; j++) {
+        case_code[j] = cs[j].code;
+        case_variant[j] = (int32_t)cs[j].len;
+    }
+    *n_variants = V;
+    *n_cases = C;
+    free(vid_of_seqpos);
+    free(cl);
+    free(cs);
+    free(acts_sorted);
+    free(off);
+    free(codes);
+    return ORC_OK;
+}
+
+/* ---- views ---------------------------------------------------------- */
+
+/*
+ * orc_view: the DFG of a drill-down view.  The retained events are
+ *   R = { i : case_lo <= c_i < case_hi, t_lo <= t_i <= t_hi, bit a_i of mask set },
+ * kept in their original row order (so the row tie-break is unchanged); the
+ * DFG, endpoints and case count are then those of R as a log of its own.
+ * mask has ceil(A/64) words; bit a is (mask[a/64] >> (a%64)) & 1.
+ * n_events receives |R|.
+ */
+int orc_view(int64_t n, const int32_t *case_id, const int32_t *act, const int64_t *ts,
+             int32_t A, int32_t case_lo, int32_t case_hi, int64_t t_lo, int64_t t_hi,
+             const uint64_t *mask, int64_t *count, int64_t *dt_sum, int64_t *dt_min,
+             int64_t *dt_max, double *dt_mean, int64_t *start_count, int64_t *end_count,
+             int64_t *act_count, int64_t *n_cases, int32_t *overflow, int64_t *n_events)
+{
+    if (n < 0 || A < 1) return ORC_E_INVALID;
+    if (check_acts(n, act, A)) return ORC_E_RANGE;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    int32_t *rc_ = (int32_t *)malloc(nn * sizeof(int32_t));
+    int32_t *ra = (int32_t *)malloc(nn * sizeof(int32_t));
+    int64_t *rt = (int64_t *)malloc(nn * sizeof(int64_t));
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; i++) {
+        int32_t a = act[i];
+        int keep = case_id[i] >= case_lo && case_id[i] < case_hi && ts[i] >= t_lo && ts[i] <= t_hi &&
+                   ((mask[a / 64] >> (a % 64)) & 1u);
+        if (keep) {
+            rc_[m] = case_id[i];
+            ra[m] = a;
+            rt[m] = ts[i];
+            m++;
+        }
+    }
+    int r = orc_dfg(m, rc_, ra, rt, A, NULL, count, dt_sum, dt_min, dt_max, dt_mean, start_count,
+                    end_count, act_count, n_cases, overflow);
+    *n_events = m;
+    free(rc_);
+    free(ra);
+    free(rt);
+    return r;
+}

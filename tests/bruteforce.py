@@ -1,0 +1,122 @@
+"""Literal, brute-force restatement of the method's definitions, for tiny logs.
+
+It is written independently of the C oracle so the two pin each other: no
+sorting routine, no single linear walk.  The directly-follows relation is
+checked by definition with an explicit search for an intermediate event
+(Sec. 3: an event and the previous event of its case), cases are the
+distinct case identifiers, variants are compared by list equality.
+"""
+from __future__ import annotations
+
+import math
+
+INT64_MAX = 2**63 - 1
+INT64_MIN = -(2**63)
+
+
+def precedes(c, t, i, j):
+    """Event i comes before event j in the (case, timestamp, row) order."""
+    return (c[i], t[i], i) < (c[j], t[j], j)
+
+
+def to_i64(x: int) -> int:
+    x &= (1 << 64) - 1
+    return x - (1 << 64) if x >= (1 << 63) else x
+
+
+def _by_case(c):
+    groups = {}
+    for i, ci in enumerate(c):
+        groups.setdefault(ci, []).append(i)
+    return groups
+
+
+def directly_follows_pairs(c, t):
+    """All (i, j) with j directly following i: same case, i before j, nothing between."""
+    pairs = []
+    for members in _by_case(c).values():
+        for i in members:
+            for j in members:
+                if i == j or not precedes(c, t, i, j):
+                    continue
+                between = any(precedes(c, t, i, k) and precedes(c, t, k, j) for k in members if k not in (i, j))
+                if not between:
+                    pairs.append((i, j))
+    return pairs
+
+
+def trace(c, t, a, members):
+    """Activities of one case, taking the earliest remaining event each time."""
+    rest = list(members)
+    out = []
+    while rest:
+        first = rest[0]
+        for k in rest[1:]:
+            if precedes(c, t, k, first):
+                first = k
+        out.append(a[first])
+        rest.remove(first)
+    return out
+
+
+def dfg(c, a, t, A):
+    cnt = [[0] * A for _ in range(A)]
+    s = [[0] * A for _ in range(A)]
+    mn = [[INT64_MAX] * A for _ in range(A)]
+    mx = [[INT64_MIN] * A for _ in range(A)]
+    for i, j in directly_follows_pairs(c, t):
+        x, y = a[i], a[j]
+        gap = to_i64(t[j] - t[i])
+        cnt[x][y] += 1
+        s[x][y] = to_i64(s[x][y] + gap)
+        mn[x][y] = min(mn[x][y], gap)
+        mx[x][y] = max(mx[x][y], gap)
+    mean = [[(float(s[x][y]) / float(cnt[x][y]) if cnt[x][y] else math.nan) for y in range(A)] for x in range(A)]
+    start = [0] * A
+    end = [0] * A
+    freq = [0] * A
+    for i in range(len(a)):
+        freq[a[i]] += 1
+    span_total = 0
+    groups = _by_case(c)
+    for members in groups.values():
+        first = [i for i in members if not any(precedes(c, t, k, i) for k in members)]
+        last = [i for i in members if not any(precedes(c, t, i, k) for k in members)]
+        assert len(first) == 1 and len(last) == 1
+        start[a[first[0]]] += 1
+        end[a[last[0]]] += 1
+        span_total += t[last[0]] - t[first[0]]
+    return dict(count=cnt, dt_sum=s, dt_min=mn, dt_max=mx, dt_mean=mean, start_count=start,
+                end_count=end, act_count=freq, n_cases=len(groups),
+                overflow=int(span_total > INT64_MAX))
+
+
+def variants(c, a, t):
+    groups = _by_case(c)
+    classes = []   # [sequence, [case codes]]
+    for code, members in groups.items():
+        seq = trace(c, t, a, members)
+        for cl in classes:
+            if cl[0] == seq:
+                cl[1].append(code)
+                break
+        else:
+            classes.append([seq, [code]])
+    classes.sort(key=lambda cl: (-len(cl[1]), min(cl[1])))
+    var_id = {}
+    for v, cl in enumerate(classes):
+        for code in cl[1]:
+            var_id[code] = v
+    codes = sorted(groups)
+    return dict(n_variants=len(classes), var_count=[len(cl[1]) for cl in classes],
+                var_len=[len(cl[0]) for cl in classes], var_rep=[min(cl[1]) for cl in classes],
+                sequences=[cl[0] for cl in classes], case_code=codes,
+                case_variant=[var_id[x] for x in codes])
+
+
+def view(c, a, t, A, case_lo, case_hi, t_lo, t_hi, members_of_subset):
+    keep = [i for i in range(len(c)) if case_lo <= c[i] < case_hi and t_lo <= t[i] <= t_hi
+            and a[i] in members_of_subset]
+    out = dfg([c[i] for i in keep], [a[i] for i in keep], [t[i] for i in keep], A)
+    out["n_events"] = len(keep)
+    return out
