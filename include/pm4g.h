@@ -1,0 +1,228 @@
+/*
+ * pm4g.h -- C ABI of the MI355X (gfx950) library for directly-follows graph
+ * discovery over a columnar event log.
+ *
+ * The operations follow PM4Py-GPU (Berti, Phan Nghia, van der Aalst,
+ * arXiv 2204.04898):
+ *   - Sec. 3, formatting: the log is ordered by (case identifier, timestamp,
+ *     absolute row index); each event is paired with the previous event of its
+ *     case; a per-case table is built.                       -> pm4g_prepare
+ *   - Sec. 3, directly-follows level: the frequency / performance
+ *     directly-follows graph; start/end activities; occurrences per
+ *     activity.                                               -> pm4g_dfg
+ *   - Sec. 3, variant level: cases grouped by their activity sequence
+ *     (a double aggregation).                                 -> pm4g_variants
+ *   - Sec. 1 drill-down views combined with the Sec. 3 event-level timestamp
+ *     filter and activity (attribute) filter, many views per launch
+ *                                                             -> pm4g_dfg_batched
+ *
+ * Conventions shared by every entry point:
+ *   - Every array argument is DEVICE memory allocated by the caller, unless the
+ *     comment says "host".  The library never allocates or frees device memory;
+ *     scratch space is the caller's workspace `ws` of at least
+ *     pm4g_workspace_bytes(...) bytes (256-byte aligned).
+ *   - Work is enqueued on `stream` (a hipStream_t passed as void*; NULL is the
+ *     default stream).  Functions taking a raw (unsorted) log synchronise the
+ *     stream once or twice to read a few bytes (key ranges, a long-case flag);
+ *     functions taking a prepared log do not synchronise.
+ *   - Host-detectable errors (NULL pointer, negative size, A outside
+ *     [1, PM4G_MAX_ACTIVITIES], n_events >= 2^31, unknown flags, workspace too
+ *     small) are returned before anything is enqueued.
+ *   - Data-dependent errors (activity out of range, a false PM4G_PRESORTED
+ *     claim, output capacity) are written to the caller's device `status`
+ *     word; a call that synchronises anyway also returns them.  When a status
+ *     is non-zero the other outputs are undefined.
+ *   - Failures of HIP calls return PM4G_E_DEVICE; pm4g_last_error() (thread
+ *     local) describes the last failure of the calling thread.
+ *   - No C++ exception crosses this interface.  Calls on different streams with
+ *     disjoint workspaces and outputs may run concurrently.
+ */
+#ifndef PM4G_H
+#define PM4G_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PM4G_ABI_VERSION 1
+#define PM4G_MAX_ACTIVITIES 4096
+
+/* Return and status codes. */
+enum {
+    PM4G_OK = 0,
+    PM4G_E_INVALID = -1,     /* bad argument (host-detected) */
+    PM4G_E_RANGE = -2,       /* an activity code outside [0, n_activities) */
+    PM4G_E_NOT_SORTED = -3,  /* PM4G_PRESORTED given but rows are not in (case, ts, row) order */
+    PM4G_E_CAPACITY = -4,    /* an output arena is too small; the required size is reported */
+    PM4G_E_WORKSPACE = -5,   /* ws_bytes < pm4g_workspace_bytes(...) */
+    PM4G_E_DEVICE = -6       /* a HIP runtime call failed */
+};
+
+/* pm4g_log.flags */
+enum {
+    PM4G_PRESORTED = 1u      /* caller promises (case, ts, row) order; it is verified */
+};
+
+/* Operations, for pm4g_workspace_bytes. */
+enum {
+    PM4G_OP_PREPARE = 1,
+    PM4G_OP_DFG = 2,             /* pm4g_dfg on a raw log */
+    PM4G_OP_DFG_PREPARED = 3,
+    PM4G_OP_VARIANTS = 4,        /* pm4g_variants on a raw log */
+    PM4G_OP_VARIANTS_PREPARED = 5,
+    PM4G_OP_DFG_BATCHED = 6
+};
+
+/*
+ * A raw event log: row i is the event (case_id[i], activity[i], timestamp[i]).
+ * Case ids are any int32 (ordered as signed); activities are codes in
+ * [0, n_activities); timestamps are int64 in any unit (ordered as signed).
+ * 0 <= n_events < 2^31.
+ */
+typedef struct {
+    const int32_t *case_id;
+    const int32_t *activity;
+    const int64_t *timestamp;
+    int64_t n_events;
+    int32_t n_activities;
+    uint32_t flags;
+} pm4g_log;
+
+/*
+ * A prepared (formatted) log, Sec. 3: the events in (case, ts, row) order and
+ * the per-case table.  Caller-owned device arrays, each with room for
+ * n_events entries (case_off: n_events + 1).  pm4g_prepare fills them; the
+ * *_prepared entry points and pm4g_dfg_batched only read them.
+ *   case_s[k], act_s[k], ts_s[k]  the k-th event in order
+ *   case_code[j]                  the j-th distinct case id, ascending
+ *   case_off[j]..case_off[j+1]-1  positions of case j's events
+ *   n_cases                       device scalar: number of distinct cases C
+ *   status                        device status word of pm4g_prepare
+ */
+typedef struct {
+    int32_t *case_s;
+    int32_t *act_s;
+    int64_t *ts_s;
+    int64_t *case_off;
+    int32_t *case_code;
+    int64_t *n_cases;
+    int32_t *status;
+    int64_t n_events;
+    int32_t n_activities;
+} pm4g_prepared;
+
+/*
+ * DFG outputs, Sec. 3 frequency / performance directly-follows graph.
+ * Dense row-major tables of A*A cells, cell (x, y) at x*A + y, over all pairs
+ * where an event with activity y directly follows one with activity x in the
+ * same case:
+ *   count     number of such pairs
+ *   dt_sum    sum of gaps t_y - t_x, modulo 2^64, as int64
+ *   dt_min    minimum gap (INT64_MAX for an empty cell)
+ *   dt_max    maximum gap (INT64_MIN for an empty cell)
+ *   dt_mean   (double)dt_sum / (double)count, NaN for an empty cell; may be NULL
+ * Per-activity counts [A]: start_count (first event of a case), end_count
+ * (last event of a case), act_count (all events).
+ * Device scalars: n_cases; overflow = 1 iff the exact sum over cases of
+ * (t_last - t_first) exceeds INT64_MAX (then some dt_sum may have wrapped);
+ * status.
+ */
+typedef struct {
+    int64_t *count;
+    int64_t *dt_sum;
+    int64_t *dt_min;
+    int64_t *dt_max;
+    double *dt_mean;
+    int64_t *start_count;
+    int64_t *end_count;
+    int64_t *act_count;
+    int64_t *n_cases;
+    int32_t *overflow;
+    int32_t *status;
+} pm4g_dfg_out;
+
+/*
+ * Variant outputs, Sec. 3 variant level.  Cases are grouped by their exact
+ * activity sequence; variant ids 0..V-1 are ordered by (number of cases
+ * descending, representative ascending), the representative being the
+ * smallest case id of the variant.  Arrays have room for n_events entries
+ * (var_off: n_events + 1), which bounds V and the total sequence length, so
+ * no capacity error can occur.
+ *   n_variants         device scalar V
+ *   var_count[v]       number of cases
+ *   var_len[v]         sequence length
+ *   var_rep[v]         representative case id
+ *   var_off[v]..var_off[v+1]-1   the sequence, in var_acts
+ *   case_variant[j]    variant of the j-th distinct case (ascending case id);
+ *                      may be NULL
+ */
+typedef struct {
+    int64_t *n_variants;
+    int64_t *var_count;
+    int32_t *var_len;
+    int32_t *var_rep;
+    int64_t *var_off;
+    int32_t *var_acts;
+    int32_t *case_variant;
+    int32_t *status;
+} pm4g_variants_out;
+
+/*
+ * Bytes of workspace an operation needs for a log of n_events events and
+ * n_activities activities (n_views for PM4G_OP_DFG_BATCHED, else ignored).
+ * Returns 0 for invalid arguments.
+ */
+size_t pm4g_workspace_bytes(int op, int64_t n_events, int32_t n_activities, int32_t n_views);
+
+/*
+ * Formats a raw log (Sec. 3, first formatting step and the cases table):
+ * writes `out`'s arrays and device scalars.  With PM4G_PRESORTED the order is
+ * verified instead of computed (status PM4G_E_NOT_SORTED if it does not
+ * hold).  Synchronises `stream` once (twice if a case has more than 2049
+ * events).  out->n_events and out->n_activities must equal the log's.
+ */
+int pm4g_prepare(const pm4g_log *log, const pm4g_prepared *out, void *ws, size_t ws_bytes,
+                 void *stream);
+
+/* DFG of a raw log: pm4g_prepare into the workspace, then pm4g_dfg_prepared. */
+int pm4g_dfg(const pm4g_log *log, const pm4g_dfg_out *out, void *ws, size_t ws_bytes,
+             void *stream);
+
+/* DFG of a prepared log.  Does not synchronise. */
+int pm4g_dfg_prepared(const pm4g_prepared *log, const pm4g_dfg_out *out, void *ws,
+                      size_t ws_bytes, void *stream);
+
+/* Variants of a raw log: pm4g_prepare into the workspace, then pm4g_variants_prepared. */
+int pm4g_variants(const pm4g_log *log, const pm4g_variants_out *out, void *ws, size_t ws_bytes,
+                  void *stream);
+
+/* Variants of a prepared log.  Does not synchronise. */
+int pm4g_variants_prepared(const pm4g_prepared *log, const pm4g_variants_out *out, void *ws,
+                           size_t ws_bytes, void *stream);
+
+/* Text for a status code (static storage). */
+const char *pm4g_status_string(int code);
+
+/* Description of the calling thread's last failure (thread-local storage). */
+const char *pm4g_last_error(void);
+
+/*
+ * Test hook for the variant grouping (Sec. 3, variant level): truncates the
+ * sequence hash used by the calling thread's later variant calls to `bits`
+ * bits (0 or >= 64: the full 64-bit hash), so that hash collisions, which the
+ * exact regrouping must resolve, can be forced on small logs.  Results do not
+ * depend on it.  Returns the previous setting.
+ */
+int pm4g_debug_variant_hash_bits(int bits);
+
+/* PM4G_ABI_VERSION of the loaded library. */
+int pm4g_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PM4G_H */

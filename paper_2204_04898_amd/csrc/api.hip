@@ -1,0 +1,392 @@
+// C ABI of libpm4g (declared in include/pm4g.h): argument validation,
+// workspace layout, kernel sequencing and error reporting.  Host code only;
+// every step of the computation runs in the kernels of the other files.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "../../include/pm4g.h"
+#include "internal.hpp"
+
+using namespace pm4g;
+
+namespace {
+
+thread_local char g_err[512] = "";
+thread_local int g_variant_hash_bits = 0;   // test hook, 0 = full 64-bit hash
+
+void set_err(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+#define PM4G_HIP(x)                                                                        \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess) {                                                            \
+            set_err("%s failed: %s (%s:%d)", #x, hipGetErrorString(e_), __FILE__, __LINE__); \
+            return PM4G_E_DEVICE;                                                          \
+        }                                                                                  \
+    } while (0)
+
+#define PM4G_CHECK(cond, ...)        \
+    do {                             \
+        if (!(cond)) {               \
+            set_err(__VA_ARGS__);    \
+            return PM4G_E_INVALID;   \
+        }                            \
+    } while (0)
+
+constexpr int64_t kMaxEvents = (int64_t(1) << 31) - 1;
+
+__global__ void k_set_status(int32_t* status, int32_t code) { *status = code; }
+
+// Workspace of the formatting step.
+struct PrepWs {
+    RangeInfo* info;
+    SortBufs a, b;
+    uint32_t* hist;
+    uint32_t* rowsum;
+    uint32_t* caseblk;
+};
+
+PrepWs prep_ws_layout(Bump& bp, int64_t n) {
+    PrepWs w{};
+    const size_t m = (size_t)(n > 0 ? n : 1);
+    w.info = bp.take<RangeInfo>(1);
+    w.a.key = bp.take<uint32_t>(m);
+    w.a.ts = bp.take<int64_t>(m);
+    w.a.act = bp.take<uint32_t>(m);
+    w.b.key = bp.take<uint32_t>(m);
+    w.b.ts = bp.take<int64_t>(m);
+    w.b.act = bp.take<uint32_t>(m);
+    w.hist = bp.take<uint32_t>(256 * (size_t)(radix_blocks(n) + 1));
+    w.rowsum = bp.take<uint32_t>(256);
+    w.caseblk = bp.take<uint32_t>((size_t)case_blocks(n) + 1);
+    return w;
+}
+
+// Prepared-log arrays carved out of a workspace (raw-log entry points).
+pm4g_prepared prepared_in_ws(Bump& bp, int64_t n, int32_t A) {
+    pm4g_prepared p{};
+    const size_t m = (size_t)(n > 0 ? n : 1);
+    p.case_s = bp.take<int32_t>(m);
+    p.act_s = bp.take<int32_t>(m);
+    p.ts_s = bp.take<int64_t>(m);
+    p.case_off = bp.take<int64_t>(m + 1);
+    p.case_code = bp.take<int32_t>(m);
+    p.n_cases = bp.take<int64_t>(1);
+    p.status = bp.take<int32_t>(1);
+    p.n_events = n;
+    p.n_activities = A;
+    return p;
+}
+
+int check_log(const pm4g_log* log) {
+    PM4G_CHECK(log != nullptr, "log is NULL");
+    PM4G_CHECK(log->n_events >= 0 && log->n_events <= kMaxEvents, "n_events %lld outside [0, 2^31)",
+               (long long)log->n_events);
+    PM4G_CHECK(log->n_activities >= 1 && log->n_activities <= PM4G_MAX_ACTIVITIES,
+               "n_activities %d outside [1, %d]", log->n_activities, PM4G_MAX_ACTIVITIES);
+    PM4G_CHECK((log->flags & ~(uint32_t)PM4G_PRESORTED) == 0, "unknown flags 0x%x", log->flags);
+    PM4G_CHECK(log->n_events == 0 || (log->case_id && log->activity && log->timestamp),
+               "a log column is NULL");
+    return PM4G_OK;
+}
+
+int check_prepared(const pm4g_prepared* p, bool need_case_table) {
+    PM4G_CHECK(p != nullptr, "prepared log is NULL");
+    PM4G_CHECK(p->n_events >= 0 && p->n_events <= kMaxEvents, "n_events %lld outside [0, 2^31)",
+               (long long)p->n_events);
+    PM4G_CHECK(p->n_activities >= 1 && p->n_activities <= PM4G_MAX_ACTIVITIES,
+               "n_activities %d outside [1, %d]", p->n_activities, PM4G_MAX_ACTIVITIES);
+    PM4G_CHECK(p->n_events == 0 || (p->case_s && p->act_s && p->ts_s), "a prepared column is NULL");
+    if (need_case_table)
+        PM4G_CHECK(p->case_off && p->n_cases && (p->n_events == 0 || p->case_code),
+                   "the prepared case table is NULL");
+    return PM4G_OK;
+}
+
+int bits_of(uint64_t range) {
+    int b = 0;
+    while (b < 64 && (range >> b) != 0) ++b;
+    return b;
+}
+
+// Formatting step into `out` (caller's arrays or workspace arrays).
+int run_prepare(const pm4g_log* log, const pm4g_prepared* out, bool case_table, Bump& bp,
+                hipStream_t s) {
+    const int64_t n = log->n_events;
+    const int32_t A = log->n_activities;
+    const bool presorted = (log->flags & PM4G_PRESORTED) != 0;
+    PrepWs w = prep_ws_layout(bp, n);
+    k_set_status<<<1, 1, 0, s>>>(out->status, 0);
+    PM4G_HIP(launch_range_scan(log->case_id, log->activity, log->timestamp, n, A, presorted, false,
+                               w.info, s));
+    RangeInfo h{};
+    PM4G_HIP(hipMemcpyAsync(&h, w.info, sizeof(h), hipMemcpyDeviceToHost, s));
+    PM4G_HIP(hipStreamSynchronize(s));
+    if (h.status != 0) {
+        k_set_status<<<1, 1, 0, s>>>(out->status, h.status);
+        PM4G_HIP(hipGetLastError());
+        set_err("%s", h.status == PM4G_E_RANGE ? "activity outside [0, n_activities)"
+                                               : "rows are not in (case, timestamp, row) order");
+        return h.status;
+    }
+    if (presorted) {
+        PM4G_HIP(launch_copy_log(log->case_id, log->activity, log->timestamp, n, out->case_s,
+                                 out->act_s, out->ts_s, s));
+    } else if (n > 0) {
+        const SortBufs raw{(uint32_t*)log->case_id, (int64_t*)log->timestamp, (uint32_t*)log->activity};
+        const int case_bits = bits_of((uint64_t)(uint32_t)(h.case_max - h.case_min));
+        int passes = (case_bits + 7) / 8;
+        if (passes == 0) passes = 1;   // a single case: one pass still biases the keys
+        SortBufs bufs[2] = {w.a, w.b};
+        SortBufs in = raw;
+        int cur = 0;
+        for (int p = 0; p < passes; ++p) {
+            PM4G_HIP(launch_radix_pass(in, bufs[cur], n, 0, 8 * p, p == 0, w.info, w.hist, w.rowsum, s));
+            in = bufs[cur];
+            cur ^= 1;
+        }
+        PM4G_HIP(launch_segsort(in, n, w.info, out->case_s, out->act_s, out->ts_s, s));
+        PM4G_HIP(hipMemcpyAsync(&h, w.info, sizeof(h), hipMemcpyDeviceToHost, s));
+        PM4G_HIP(hipStreamSynchronize(s));
+        if (h.long_case) {
+            // Full-key fallback: stable passes on the timestamp bits, then the case bits.
+            PM4G_HIP(launch_ts_range(log->timestamp, n, w.info, s));
+            PM4G_HIP(hipMemcpyAsync(&h, w.info, sizeof(h), hipMemcpyDeviceToHost, s));
+            PM4G_HIP(hipStreamSynchronize(s));
+            const int ts_bits = bits_of((uint64_t)h.ts_max - (uint64_t)h.ts_min);
+            const int ts_passes = (ts_bits + 7) / 8;
+            in = raw;
+            cur = 0;
+            bool first = true;
+            for (int p = 0; p < ts_passes; ++p, first = false) {
+                PM4G_HIP(launch_radix_pass(in, bufs[cur], n, 1, 8 * p, first, w.info, w.hist, w.rowsum, s));
+                in = bufs[cur];
+                cur ^= 1;
+            }
+            for (int p = 0; p < passes; ++p, first = false) {
+                PM4G_HIP(launch_radix_pass(in, bufs[cur], n, 0, 8 * p, first, w.info, w.hist, w.rowsum, s));
+                in = bufs[cur];
+                cur ^= 1;
+            }
+            PM4G_HIP(launch_unbias_copy(in, n, w.info, out->case_s, out->act_s, out->ts_s, s));
+        }
+    }
+    if (case_table)
+        PM4G_HIP(launch_case_table(out->case_s, n, w.caseblk, out->case_off, out->case_code,
+                                   out->n_cases, s));
+    return PM4G_OK;
+}
+
+DfgOutDev dev_out(const pm4g_dfg_out* o) {
+    return DfgOutDev{o->count, o->dt_sum, o->dt_min, o->dt_max, o->dt_mean, o->start_count,
+                     o->end_count, o->act_count, o->n_cases, o->overflow, o->status};
+}
+
+int check_dfg_out(const pm4g_dfg_out* o) {
+    PM4G_CHECK(o != nullptr, "dfg output is NULL");
+    PM4G_CHECK(o->count && o->dt_sum && o->dt_min && o->dt_max && o->start_count && o->end_count &&
+                   o->act_count && o->n_cases && o->overflow && o->status,
+               "a dfg output array is NULL (only dt_mean may be NULL)");
+    return PM4G_OK;
+}
+
+int check_var_out(const pm4g_variants_out* o) {
+    PM4G_CHECK(o != nullptr, "variants output is NULL");
+    PM4G_CHECK(o->n_variants && o->var_count && o->var_len && o->var_rep && o->var_off && o->var_acts &&
+                   o->status,
+               "a variants output array is NULL (only case_variant may be NULL)");
+    return PM4G_OK;
+}
+
+size_t ws_bytes(int op, int64_t n, int32_t A) {
+    Bump b(nullptr);
+    switch (op) {
+        case PM4G_OP_PREPARE:
+            prep_ws_layout(b, n);
+            break;
+        case PM4G_OP_DFG_PREPARED:
+            dfg_ws_layout(b, n, A);
+            break;
+        case PM4G_OP_DFG: {
+            prepared_in_ws(b, n, A);
+            Bump b2(nullptr);
+            prep_ws_layout(b2, n);
+            Bump b3(nullptr);
+            dfg_ws_layout(b3, n, A);
+            b.off += (b2.off > b3.off ? b2.off : b3.off) + 256;
+            break;
+        }
+        case PM4G_OP_VARIANTS_PREPARED:
+            var_ws_layout(b, n);
+            break;
+        case PM4G_OP_VARIANTS: {
+            prepared_in_ws(b, n, A);
+            Bump b2(nullptr);
+            prep_ws_layout(b2, n);
+            Bump b3(nullptr);
+            var_ws_layout(b3, n);
+            b.off += (b2.off > b3.off ? b2.off : b3.off) + 256;
+            break;
+        }
+        default:
+            return 0;
+    }
+    return b.off + 256;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pm4g_abi_version(void) { return PM4G_ABI_VERSION; }
+
+const char* pm4g_last_error(void) { return g_err; }
+
+int pm4g_debug_variant_hash_bits(int bits) {
+    const int old = g_variant_hash_bits;
+    g_variant_hash_bits = (bits < 0 || bits >= 64) ? 0 : bits;
+    return old;
+}
+
+const char* pm4g_status_string(int code) {
+    switch (code) {
+        case PM4G_OK: return "ok";
+        case PM4G_E_INVALID: return "invalid argument";
+        case PM4G_E_RANGE: return "activity outside [0, n_activities)";
+        case PM4G_E_NOT_SORTED: return "rows are not in (case, timestamp, row) order";
+        case PM4G_E_CAPACITY: return "output capacity exceeded";
+        case PM4G_E_WORKSPACE: return "workspace too small";
+        case PM4G_E_DEVICE: return "HIP runtime error";
+        default: return "unknown status";
+    }
+}
+
+size_t pm4g_workspace_bytes(int op, int64_t n_events, int32_t n_activities, int32_t n_views) {
+    (void)n_views;
+    if (n_events < 0 || n_events > kMaxEvents) return 0;
+    if (n_activities < 1 || n_activities > PM4G_MAX_ACTIVITIES) return 0;
+    return ws_bytes(op, n_events, n_activities);
+}
+
+int pm4g_prepare(const pm4g_log* log, const pm4g_prepared* out, void* ws, size_t ws_size,
+                 void* stream) {
+    if (int rc = check_log(log)) return rc;
+    PM4G_CHECK(out && out->case_off && out->n_cases && out->status &&
+                   (log->n_events == 0 || (out->case_s && out->act_s && out->ts_s && out->case_code)),
+               "a prepared output array is NULL");
+    PM4G_CHECK(out->n_events == log->n_events && out->n_activities == log->n_activities,
+               "prepared n_events/n_activities differ from the log's");
+    const size_t need = ws_bytes(PM4G_OP_PREPARE, log->n_events, log->n_activities);
+    if (ws_size < need || (need && !ws)) {
+        set_err("workspace of %zu bytes, %zu needed", ws_size, need);
+        return PM4G_E_WORKSPACE;
+    }
+    Bump bp(ws);
+    return run_prepare(log, out, true, bp, (hipStream_t)stream);
+}
+
+int pm4g_dfg_prepared(const pm4g_prepared* log, const pm4g_dfg_out* out, void* ws, size_t ws_size,
+                      void* stream) {
+    if (int rc = check_prepared(log, false)) return rc;
+    if (int rc = check_dfg_out(out)) return rc;
+    const size_t need = ws_bytes(PM4G_OP_DFG_PREPARED, log->n_events, log->n_activities);
+    if (ws_size < need || !ws) {
+        set_err("workspace of %zu bytes, %zu needed", ws_size, need);
+        return PM4G_E_WORKSPACE;
+    }
+    Bump bp(ws);
+    DfgWs w = dfg_ws_layout(bp, log->n_events, log->n_activities);
+    PM4G_HIP(launch_dfg(log->case_s, log->act_s, log->ts_s, log->n_events, log->n_activities,
+                        log->status, w, dev_out(out), (hipStream_t)stream));
+    return PM4G_OK;
+}
+
+int pm4g_dfg(const pm4g_log* log, const pm4g_dfg_out* out, void* ws, size_t ws_size, void* stream) {
+    if (int rc = check_log(log)) return rc;
+    if (int rc = check_dfg_out(out)) return rc;
+    const size_t need = ws_bytes(PM4G_OP_DFG, log->n_events, log->n_activities);
+    if (ws_size < need || !ws) {
+        set_err("workspace of %zu bytes, %zu needed", ws_size, need);
+        return PM4G_E_WORKSPACE;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    Bump bp(ws);
+    pm4g_prepared p = prepared_in_ws(bp, log->n_events, log->n_activities);
+    const size_t rest = bp.off;
+    {
+        Bump b2(static_cast<char*>(ws) + ((rest + 255) & ~size_t(255)));
+        int rc = run_prepare(log, &p, false, b2, s);
+        if (rc != PM4G_OK) {
+            if (rc != PM4G_E_DEVICE) {
+                k_set_status<<<1, 1, 0, s>>>(out->status, rc);
+                PM4G_HIP(hipGetLastError());
+            }
+            return rc;
+        }
+    }
+    Bump b3(static_cast<char*>(ws) + ((rest + 255) & ~size_t(255)));
+    DfgWs w = dfg_ws_layout(b3, log->n_events, log->n_activities);
+    PM4G_HIP(launch_dfg(p.case_s, p.act_s, p.ts_s, p.n_events, p.n_activities, p.status, w,
+                        dev_out(out), s));
+    return PM4G_OK;
+}
+
+int pm4g_variants_prepared(const pm4g_prepared* log, const pm4g_variants_out* out, void* ws,
+                           size_t ws_size, void* stream) {
+    if (int rc = check_prepared(log, true)) return rc;
+    if (int rc = check_var_out(out)) return rc;
+    const size_t need = ws_bytes(PM4G_OP_VARIANTS_PREPARED, log->n_events, log->n_activities);
+    if (ws_size < need || !ws) {
+        set_err("workspace of %zu bytes, %zu needed", ws_size, need);
+        return PM4G_E_WORKSPACE;
+    }
+    Bump bp(ws);
+    VarWs w = var_ws_layout(bp, log->n_events);
+    const VarOutDev o{out->n_variants, out->var_count, out->var_len, out->var_rep,
+                      out->var_off,    out->var_acts,  out->case_variant, out->status};
+    PM4G_HIP(launch_variants(log->act_s, log->case_off, log->case_code, log->n_cases, log->status,
+                             log->n_events, w, o, (uint32_t)g_variant_hash_bits,
+                             (hipStream_t)stream));
+    return PM4G_OK;
+}
+
+int pm4g_variants(const pm4g_log* log, const pm4g_variants_out* out, void* ws, size_t ws_size,
+                  void* stream) {
+    if (int rc = check_log(log)) return rc;
+    if (int rc = check_var_out(out)) return rc;
+    const size_t need = ws_bytes(PM4G_OP_VARIANTS, log->n_events, log->n_activities);
+    if (ws_size < need || !ws) {
+        set_err("workspace of %zu bytes, %zu needed", ws_size, need);
+        return PM4G_E_WORKSPACE;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    Bump bp(ws);
+    pm4g_prepared p = prepared_in_ws(bp, log->n_events, log->n_activities);
+    const size_t rest = bp.off;
+    {
+        Bump b2(static_cast<char*>(ws) + ((rest + 255) & ~size_t(255)));
+        int rc = run_prepare(log, &p, true, b2, s);
+        if (rc != PM4G_OK) {
+            if (rc != PM4G_E_DEVICE) {
+                k_set_status<<<1, 1, 0, s>>>(out->status, rc);
+                PM4G_HIP(hipGetLastError());
+            }
+            return rc;
+        }
+    }
+    Bump b3(static_cast<char*>(ws) + ((rest + 255) & ~size_t(255)));
+    VarWs w = var_ws_layout(b3, log->n_events);
+    const VarOutDev o{out->n_variants, out->var_count, out->var_len, out->var_rep,
+                      out->var_off,    out->var_acts,  out->case_variant, out->status};
+    PM4G_HIP(launch_variants(p.act_s, p.case_off, p.case_code, p.n_cases, p.status, p.n_events, w, o,
+                             (uint32_t)g_variant_hash_bits, s));
+    return PM4G_OK;
+}
+
+}  // extern "C"

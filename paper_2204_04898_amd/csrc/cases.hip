@@ -1,0 +1,89 @@
+// Case table of a prepared log (Sec. 3, third formatting step, "cases
+// dataframe"; Sec. 2.1 group identification): case_code[j] is the j-th
+// distinct case id in order and case_off[j] the position of its first event.
+// Reduce-then-scan compaction of the boundary flags
+// flag(i) = (i == 0) || case_s[i] != case_s[i-1]:
+//   k_case_count  per-tile flag counts
+//   k_case_scan   exclusive scan of the tile counts, n_cases, case_off[C] = N
+//   k_case_emit   per-tile ranks -> case_off / case_code
+// Bytes per event: 4 + 4 read (the column is read twice).
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace pm4g {
+
+constexpr int kCB = 256;
+constexpr int kCI = kCaseTile / kCB;   // 16
+
+__global__ __launch_bounds__(kCB) void k_case_count(const int32_t* __restrict__ case_s, int64_t n,
+                                                    uint32_t* blockcnt) {
+    __shared__ uint32_t tmp[kCB / kWave + 1];
+    const int64_t base = (int64_t)blockIdx.x * kCaseTile;
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kCI; ++k) {
+        const int64_t i = base + k * kCB + threadIdx.x;
+        if (i < n && (i == 0 || case_s[i] != case_s[i - 1])) ++c;
+    }
+    uint32_t total;
+    block_excl_sum<kCB>(c, tmp, &total);
+    if (threadIdx.x == 0) blockcnt[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(1024) void k_case_scan(uint32_t* blockcnt, int64_t nb, int64_t n,
+                                                    int64_t* case_off, int64_t* n_cases) {
+    __shared__ uint32_t tmp[1024 / kWave + 1];
+    uint32_t run = 0;
+    for (int64_t c0 = 0; c0 < nb; c0 += 1024) {
+        const int64_t i = c0 + threadIdx.x;
+        const uint32_t v = i < nb ? blockcnt[i] : 0u;
+        uint32_t total;
+        const uint32_t ex = block_excl_sum<1024>(v, tmp, &total);
+        if (i < nb) blockcnt[i] = run + ex;
+        run += total;
+    }
+    if (threadIdx.x == 0) {
+        *n_cases = run;
+        case_off[run] = n;
+    }
+}
+
+__global__ __launch_bounds__(kCB) void k_case_emit(const int32_t* __restrict__ case_s, int64_t n,
+                                                   const uint32_t* blockoff, int64_t* case_off,
+                                                   int32_t* case_code) {
+    __shared__ uint32_t tmp[kCB / kWave + 1];
+    // blocked layout so that ranks follow positions
+    const int64_t base = (int64_t)blockIdx.x * kCaseTile + (int64_t)threadIdx.x * kCI;
+    uint32_t flags = 0;
+    int32_t cv[kCI];
+#pragma unroll
+    for (int q = 0; q < kCI; ++q) {
+        const int64_t i = base + q;
+        cv[q] = 0;
+        if (i < n) {
+            cv[q] = case_s[i];
+            if (i == 0 || cv[q] != case_s[i - 1]) flags |= 1u << q;
+        }
+    }
+    uint32_t total;
+    uint32_t r = block_excl_sum<kCB>((uint32_t)__popc(flags), tmp, &total) + blockoff[blockIdx.x];
+#pragma unroll
+    for (int q = 0; q < kCI; ++q) {
+        if (flags & (1u << q)) {
+            case_off[r] = base + q;
+            case_code[r] = cv[q];
+            ++r;
+        }
+    }
+}
+
+hipError_t launch_case_table(const int32_t* case_s, int64_t n, uint32_t* blockcnt, int64_t* case_off,
+                             int32_t* case_code, int64_t* n_cases, hipStream_t s) {
+    const int64_t nb = case_blocks(n);
+    if (nb > 0) k_case_count<<<(unsigned)nb, kCB, 0, s>>>(case_s, n, blockcnt);
+    k_case_scan<<<1, 1024, 0, s>>>(blockcnt, nb, n, case_off, n_cases);
+    if (nb > 0) k_case_emit<<<(unsigned)nb, kCB, 0, s>>>(case_s, n, blockcnt, case_off, case_code);
+    return hipGetLastError();
+}
+
+}  // namespace pm4g

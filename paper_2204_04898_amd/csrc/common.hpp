@@ -1,0 +1,109 @@
+// Device helpers shared by the pm4g kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pm4g {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane() { return __lane_id(); }
+
+// Mask of the lanes below this one.
+__device__ __forceinline__ uint64_t lanes_below() {
+    return (uint64_t(1) << lane()) - uint64_t(1);
+}
+
+// Lanes of this wave whose 8-bit digit equals this lane's, among `active`.
+__device__ __forceinline__ uint64_t match_digit8(uint32_t d, uint64_t active) {
+    uint64_t peers = active;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+    }
+    return peers;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_sum(T v) {
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        T u = __shfl_up(v, o);
+        if (lane() >= o) v += u;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        T u = __shfl_xor(v, o);
+        v = u < v ? u : v;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        T u = __shfl_xor(v, o);
+        v = u > v ? u : v;
+    }
+    return v;
+}
+
+// Exclusive prefix sum over a block of BLOCK threads (one value per thread).
+// `tmp` must hold BLOCK/64 + 1 entries of T in LDS.  Returns the exclusive
+// sum; *total receives the block total.  Contains __syncthreads().
+template <int BLOCK, typename T>
+__device__ __forceinline__ T block_excl_sum(T v, T* tmp, T* total) {
+    constexpr int NW = BLOCK / kWave;
+    const int w = threadIdx.x / kWave;
+    T inc = wave_incl_sum(v);
+    if (lane() == kWave - 1) tmp[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T run = 0;
+        for (int i = 0; i < NW; ++i) {
+            T x = tmp[i];
+            tmp[i] = run;
+            run += x;
+        }
+        tmp[NW] = run;
+    }
+    __syncthreads();
+    T r = tmp[w] + inc - v;
+    *total = tmp[NW];
+    __syncthreads();
+    return r;
+}
+
+// Saturating add of non-negative 64-bit amounts, capped at 2^63 (any value
+// >= 2^63 means "exceeds INT64_MAX").  Inputs must already be <= 2^63.
+__device__ __forceinline__ uint64_t sat_add63(uint64_t a, uint64_t b) {
+    constexpr uint64_t cap = uint64_t(1) << 63;
+    return (a > cap - b) ? cap : a + b;
+}
+__device__ __forceinline__ uint64_t cap63(uint64_t a) {
+    constexpr uint64_t cap = uint64_t(1) << 63;
+    return a > cap ? cap : a;
+}
+
+// Record a data-dependent error; the first one wins.
+__device__ __forceinline__ void set_status(int32_t* status, int32_t code) {
+    atomicCAS(status, 0, code);
+}
+
+}  // namespace pm4g

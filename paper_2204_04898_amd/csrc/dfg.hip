@@ -1,0 +1,491 @@
+// Directly-follows graph aggregation over a prepared log (Sec. 3,
+// directly-follows level: frequency / performance DFG; start/end activities;
+// occurrences per activity).  For position i of the ordered log, the event
+// directly follows i-1 iff both have the same case; the pair contributes to
+// cell act_s[i-1]*A + act_s[i] with gap ts_s[i] - ts_s[i-1] (mod 2^64).
+//
+// Two aggregation paths, both free of per-event global atomics (global
+// atomics run at ~25 G/s on MI355X, LDS atomics at ~700 G/s):
+//   A*A <= 4096  k_dfg_lds: 256 persistent blocks, one privatised LDS table
+//                each (count u32, sum u64, min, max: 112 KB), partial tables
+//                written out and reduced per cell.
+//   A*A >  4096  k_dfg_part: per 4096-event tile, edges are bucketed by
+//                cell >> 12 in LDS and written as runs (u16 cell, u64 gap);
+//                k_dfg_agg: blocks take equal shares of each bucket's edges
+//                (work split by edge counts, so Zipf-heavy buckets get more
+//                blocks), aggregate in a 4096-cell LDS table, write partials.
+// k_dfg_reduce folds the partial tables, writes the dense outputs and the
+// FP64 mean; k_dfg_acts / k_dfg_final fold the activity counts, n_cases and the
+// overflow flag.
+// Bytes per event: 16 read (+ 10 write + 10 read per edge on the bucketed path).
+#include <math.h>
+
+#include "common.hpp"
+#include "internal.hpp"
+#include "../../include/pm4g.h"
+
+namespace pm4g {
+
+constexpr int kLB = 1024;   // threads of k_dfg_lds
+constexpr int kPB = 512;    // threads of k_dfg_part
+constexpr int kAB = 512;    // threads of k_dfg_agg
+
+static int64_t dfg_tiles(int64_t n) { return (n + kDfgTile - 1) / kDfgTile; }
+static int64_t n_buckets(int32_t A) {
+    return ((int64_t)A * A + kCellsPerTable - 1) / kCellsPerTable;
+}
+
+DfgWs dfg_ws_layout(Bump& b, int64_t n, int32_t A) {
+    DfgWs w{};
+    if (A <= kDfgLdsMaxA) {
+        const int64_t slots = kDfgLdsBlocks;
+        w.n_slots_max = (int32_t)slots;
+        w.n_act_blocks = kDfgLdsBlocks;
+        w.pcount = b.take<uint32_t>(slots * kCellsPerTable);
+        w.psum = b.take<uint64_t>(slots * kCellsPerTable);
+        w.pmin = b.take<int64_t>(slots * kCellsPerTable);
+        w.pmax = b.take<int64_t>(slots * kCellsPerTable);
+    } else {
+        const int64_t nbk = n_buckets(A);
+        const int64_t nbt = dfg_tiles(n);
+        const int64_t slots = nbk + kDfgAggTarget;
+        w.n_slots_max = (int32_t)slots;
+        const int64_t g = nbt < kDfgPartBlocks ? (nbt < 1 ? 1 : nbt) : kDfgPartBlocks;
+        w.n_act_blocks = (int32_t)g;
+        w.pcount = b.take<uint32_t>(slots * kCellsPerTable);
+        w.psum = b.take<uint64_t>(slots * kCellsPerTable);
+        w.pmin = b.take<int64_t>(slots * kCellsPerTable);
+        w.pmax = b.take<int64_t>(slots * kCellsPerTable);
+        w.ecell = b.take<uint16_t>((size_t)nbt * kDfgTile);
+        w.egap = b.take<uint64_t>((size_t)nbt * kDfgTile);
+        w.ecnt = b.take<uint32_t>(nbk * nbt);
+        w.ebeg = b.take<uint32_t>(nbk * nbt);
+        w.escan = b.take<uint32_t>(nbk * nbt);
+        w.btotal = b.take<uint32_t>(nbk);
+        w.bfirst = b.take<uint32_t>(nbk);
+        w.bslots = b.take<uint32_t>(nbk);
+        w.plan = b.take<int4>(slots);
+        w.nplan = b.take<uint32_t>(1);
+    }
+    w.pfreq = b.take<uint32_t>((size_t)w.n_act_blocks * A);
+    w.pstart = b.take<uint32_t>((size_t)w.n_act_blocks * A);
+    w.pend = b.take<uint32_t>((size_t)w.n_act_blocks * A);
+    w.pspan = b.take<uint64_t>(w.n_act_blocks);
+    return w;
+}
+
+// ---------------------------------------------------------------------------
+// A*A <= 4096: privatised LDS tables
+
+__global__ __launch_bounds__(kLB) void k_dfg_lds(const int32_t* __restrict__ case_s,
+                                                 const int32_t* __restrict__ act_s,
+                                                 const int64_t* __restrict__ ts_s, int64_t n,
+                                                 int32_t A, DfgWs ws, int32_t* status) {
+    __shared__ uint32_t scount[kCellsPerTable];
+    __shared__ uint64_t ssum[kCellsPerTable];
+    __shared__ int64_t smin[kCellsPerTable];
+    __shared__ int64_t smax[kCellsPerTable];
+    __shared__ uint32_t sfreq[kDfgLdsMaxA], sstart[kDfgLdsMaxA], send[kDfgLdsMaxA];
+    __shared__ uint64_t sspan[kLB / kWave];
+
+    const int cells = A * A;
+    for (int c = threadIdx.x; c < cells; c += kLB) {
+        scount[c] = 0;
+        ssum[c] = 0;
+        smin[c] = INT64_MAX;
+        smax[c] = INT64_MIN;
+    }
+    if (threadIdx.x < A) sfreq[threadIdx.x] = sstart[threadIdx.x] = send[threadIdx.x] = 0;
+    __syncthreads();
+
+    uint64_t span = 0;
+    bool bad = false;
+    const int64_t stride = (int64_t)gridDim.x * kLB;
+    for (int64_t i = (int64_t)blockIdx.x * kLB + threadIdx.x; i < n; i += stride) {
+        const int32_t c = case_s[i];
+        const int32_t a = act_s[i];
+        if ((uint32_t)a >= (uint32_t)A) {
+            bad = true;
+            continue;
+        }
+        const bool first = (i == 0) || case_s[i - 1] != c;
+        const bool last = (i == n - 1) || case_s[i + 1] != c;
+        atomicAdd(&sfreq[a], 1u);
+        if (first) atomicAdd(&sstart[a], 1u);
+        if (last) atomicAdd(&send[a], 1u);
+        if (!first) {
+            const int32_t p = act_s[i - 1];
+            if ((uint32_t)p >= (uint32_t)A) continue;
+            const int cell = p * A + a;
+            const uint64_t gap = (uint64_t)ts_s[i] - (uint64_t)ts_s[i - 1];
+            const int64_t g = (int64_t)gap;
+            atomicAdd(&scount[cell], 1u);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&ssum[cell]), (unsigned long long)gap);
+            if (g < __hip_atomic_load(&smin[cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+                __hip_atomic_fetch_min(&smin[cell], g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (g > __hip_atomic_load(&smax[cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+                __hip_atomic_fetch_max(&smax[cell], g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            span = sat_add63(span, cap63(gap));
+        }
+    }
+    if (__ballot(bad) != 0 && lane() == 0) set_status(status, PM4G_E_RANGE);
+    // saturating block sum of the span
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) span = sat_add63(span, __shfl_xor(span, o));
+    if (lane() == 0) sspan[threadIdx.x / kWave] = span;
+    __syncthreads();
+
+    const size_t slot = (size_t)blockIdx.x * kCellsPerTable;
+    for (int c = threadIdx.x; c < cells; c += kLB) {
+        ws.pcount[slot + c] = scount[c];
+        ws.psum[slot + c] = ssum[c];
+        ws.pmin[slot + c] = smin[c];
+        ws.pmax[slot + c] = smax[c];
+    }
+    const size_t ab = (size_t)blockIdx.x * A;
+    if (threadIdx.x < A) {
+        ws.pfreq[ab + threadIdx.x] = sfreq[threadIdx.x];
+        ws.pstart[ab + threadIdx.x] = sstart[threadIdx.x];
+        ws.pend[ab + threadIdx.x] = send[threadIdx.x];
+    }
+    if (threadIdx.x == 0) {
+        uint64_t s = 0;
+        for (int k = 0; k < kLB / kWave; ++k) s = sat_add63(s, sspan[k]);
+        ws.pspan[blockIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// A*A > 4096: bucketed edges
+
+__global__ __launch_bounds__(kPB) void k_dfg_part(const int32_t* __restrict__ case_s,
+                                                  const int32_t* __restrict__ act_s,
+                                                  const int64_t* __restrict__ ts_s, int64_t n,
+                                                  int32_t A, int64_t nbt, int64_t nbk, DfgWs ws,
+                                                  int32_t* status) {
+    __shared__ uint32_t sfreq[PM4G_MAX_ACTIVITIES], sstart[PM4G_MAX_ACTIVITIES],
+        send[PM4G_MAX_ACTIVITIES];
+    __shared__ uint32_t bcnt[kCellsPerTable];   // bucket counters (nbk <= 4096)
+    __shared__ uint32_t tmp[kPB / kWave + 1];
+    __shared__ uint64_t sspan[kPB / kWave];
+    constexpr int kPI = kDfgTile / kPB;          // 8 events per thread
+
+    for (int a = threadIdx.x; a < A; a += kPB) sfreq[a] = sstart[a] = send[a] = 0;
+    uint64_t span = 0;
+    bool bad = false;
+
+    for (int64_t t = blockIdx.x; t < nbt; t += gridDim.x) {
+        for (int k = threadIdx.x; k < nbk; k += kPB) bcnt[k] = 0;
+        __syncthreads();
+        uint32_t ecell[kPI], ebk[kPI], eslot[kPI];
+        uint64_t egap[kPI];
+        const int64_t base = t * kDfgTile;
+#pragma unroll
+        for (int q = 0; q < kPI; ++q) {
+            const int64_t i = base + q * kPB + threadIdx.x;
+            ebk[q] = 0xFFFFFFFFu;
+            if (i >= n) continue;
+            const int32_t c = case_s[i];
+            const int32_t a = act_s[i];
+            if ((uint32_t)a >= (uint32_t)A) {
+                bad = true;
+                continue;
+            }
+            const bool first = (i == 0) || case_s[i - 1] != c;
+            const bool last = (i == n - 1) || case_s[i + 1] != c;
+            atomicAdd(&sfreq[a], 1u);
+            if (first) atomicAdd(&sstart[a], 1u);
+            if (last) atomicAdd(&send[a], 1u);
+            if (!first) {
+                const int32_t p = act_s[i - 1];
+                if ((uint32_t)p >= (uint32_t)A) continue;
+                const uint32_t cell = (uint32_t)p * (uint32_t)A + (uint32_t)a;
+                const uint64_t gap = (uint64_t)ts_s[i] - (uint64_t)ts_s[i - 1];
+                span = sat_add63(span, cap63(gap));
+                ecell[q] = cell & (kCellsPerTable - 1);
+                ebk[q] = cell >> 12;
+                egap[q] = gap;
+                eslot[q] = atomicAdd(&bcnt[ebk[q]], 1u);
+            }
+        }
+        __syncthreads();
+        // exclusive scan of the bucket counts; publish count and start per bucket
+        uint32_t run = 0;
+        for (int64_t k0 = 0; k0 < nbk; k0 += kPB) {
+            const int64_t k = k0 + threadIdx.x;
+            const uint32_t v = k < nbk ? bcnt[k] : 0u;
+            uint32_t total;
+            const uint32_t ex = block_excl_sum<kPB>(v, tmp, &total);
+            if (k < nbk) {
+                ws.ecnt[k * nbt + t] = v;
+                ws.ebeg[k * nbt + t] = run + ex;
+                bcnt[k] = run + ex;
+            }
+            run += total;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kPI; ++q) {
+            if (ebk[q] != 0xFFFFFFFFu) {
+                const size_t at = (size_t)base + bcnt[ebk[q]] + eslot[q];
+                ws.ecell[at] = (uint16_t)ecell[q];
+                ws.egap[at] = egap[q];
+            }
+        }
+        __syncthreads();
+    }
+    if (__ballot(bad) != 0 && lane() == 0) set_status(status, PM4G_E_RANGE);
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) span = sat_add63(span, __shfl_xor(span, o));
+    if (lane() == 0) sspan[threadIdx.x / kWave] = span;
+    __syncthreads();
+    const size_t ab = (size_t)blockIdx.x * A;
+    for (int a = threadIdx.x; a < A; a += kPB) {
+        ws.pfreq[ab + a] = sfreq[a];
+        ws.pstart[ab + a] = sstart[a];
+        ws.pend[ab + a] = send[a];
+    }
+    if (threadIdx.x == 0) {
+        uint64_t s = 0;
+        for (int k = 0; k < kPB / kWave; ++k) s = sat_add63(s, sspan[k]);
+        ws.pspan[blockIdx.x] = s;
+    }
+}
+
+// One block per bucket: exclusive scan over its tiles' counts, bucket total.
+__global__ __launch_bounds__(256) void k_dfg_bucket_scan(int64_t nbt, DfgWs ws) {
+    __shared__ uint32_t tmp[256 / kWave + 1];
+    const int64_t b = blockIdx.x;
+    uint32_t run = 0;
+    for (int64_t t0 = 0; t0 < nbt; t0 += 256) {
+        const int64_t t = t0 + threadIdx.x;
+        const uint32_t v = t < nbt ? ws.ecnt[b * nbt + t] : 0u;
+        uint32_t total;
+        const uint32_t ex = block_excl_sum<256>(v, tmp, &total);
+        if (t < nbt) ws.escan[b * nbt + t] = run + ex;
+        run += total;
+    }
+    if (threadIdx.x == 0) ws.btotal[b] = run;
+}
+
+// Splits every bucket into slots of about total/kDfgAggTarget edges.
+__global__ __launch_bounds__(1024) void k_dfg_plan(int64_t nbk, DfgWs ws) {
+    __shared__ uint64_t red[1024 / kWave];
+    __shared__ uint32_t tmp[1024 / kWave + 1];
+    uint64_t tot = 0;
+    for (int64_t b = threadIdx.x; b < nbk; b += 1024) tot += ws.btotal[b];
+    tot = wave_sum(tot);
+    if (lane() == 0) red[threadIdx.x / kWave] = tot;
+    __syncthreads();
+    uint64_t all = 0;
+    for (int k = 0; k < 1024 / kWave; ++k) all += red[k];
+    uint64_t chunk = (all + kDfgAggTarget - 1) / kDfgAggTarget;
+    if (chunk < 1) chunk = 1;
+    uint32_t run = 0;
+    for (int64_t b0 = 0; b0 < nbk; b0 += 1024) {
+        const int64_t b = b0 + threadIdx.x;
+        uint32_t sl = 0, tb = 0;
+        if (b < nbk) {
+            tb = ws.btotal[b];
+            sl = (uint32_t)((tb + chunk - 1) / chunk);
+        }
+        uint32_t total;
+        const uint32_t ex = block_excl_sum<1024>(sl, tmp, &total);
+        if (b < nbk) {
+            const uint32_t first = run + ex;
+            ws.bfirst[b] = first;
+            ws.bslots[b] = sl;
+            for (uint32_t s = 0; s < sl; ++s) {
+                const uint64_t v0 = (uint64_t)s * chunk;
+                const uint64_t v1 = v0 + chunk < tb ? v0 + chunk : tb;
+                ws.plan[first + s] = make_int4((int)b, (int)v0, (int)v1, 0);
+            }
+        }
+        run += total;
+    }
+    if (threadIdx.x == 0) *ws.nplan = run;
+}
+
+__global__ __launch_bounds__(kAB) void k_dfg_agg(int64_t nbt, DfgWs ws) {
+    __shared__ uint32_t scount[kCellsPerTable];
+    __shared__ uint64_t ssum[kCellsPerTable];
+    __shared__ int64_t smin[kCellsPerTable];
+    __shared__ int64_t smax[kCellsPerTable];
+    __shared__ int64_t tfirst;
+
+    const uint32_t g = blockIdx.x;
+    if (g >= *ws.nplan) return;
+    const int4 pl = ws.plan[g];
+    const int64_t b = pl.x;
+    const uint32_t v0 = (uint32_t)pl.y, v1 = (uint32_t)pl.z;
+    for (int c = threadIdx.x; c < kCellsPerTable; c += kAB) {
+        scount[c] = 0;
+        ssum[c] = 0;
+        smin[c] = INT64_MAX;
+        smax[c] = INT64_MIN;
+    }
+    const uint32_t* scan = ws.escan + b * nbt;
+    const uint32_t* cnt = ws.ecnt + b * nbt;
+    const uint32_t* beg = ws.ebeg + b * nbt;
+    if (threadIdx.x == 0) {
+        // last tile whose run starts at or before v0 and is non-empty past it
+        int64_t lo = 0, hi = nbt - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) / 2;
+            if (scan[mid] <= v0) lo = mid;
+            else hi = mid - 1;
+        }
+        // skip empty runs that end exactly at v0
+        while (lo < nbt && scan[lo] + cnt[lo] <= v0) ++lo;
+        tfirst = lo;
+    }
+    __syncthreads();
+    const int w = threadIdx.x / kWave;
+    constexpr int kAW = kAB / kWave;
+    for (int64_t t = tfirst + w; t < nbt; t += kAW) {
+        const uint32_t r0 = scan[t];
+        if (r0 >= v1) break;
+        const uint32_t rl = cnt[t];
+        const uint32_t lo = r0 > v0 ? r0 : v0;
+        const uint32_t hi = (r0 + rl) < v1 ? (r0 + rl) : v1;
+        const size_t at0 = (size_t)t * kDfgTile + beg[t];
+        for (uint32_t v = lo + lane(); v < hi; v += kWave) {
+            const size_t at = at0 + (v - r0);
+            const uint32_t cell = ws.ecell[at];
+            const uint64_t gap = ws.egap[at];
+            const int64_t gg = (int64_t)gap;
+            atomicAdd(&scount[cell], 1u);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&ssum[cell]), (unsigned long long)gap);
+            if (gg < __hip_atomic_load(&smin[cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+                __hip_atomic_fetch_min(&smin[cell], gg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (gg > __hip_atomic_load(&smax[cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+                __hip_atomic_fetch_max(&smax[cell], gg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+    __syncthreads();
+    const size_t slot = (size_t)g * kCellsPerTable;
+    for (int c = threadIdx.x; c < kCellsPerTable; c += kAB) {
+        ws.pcount[slot + c] = scount[c];
+        ws.psum[slot + c] = ssum[c];
+        ws.pmin[slot + c] = smin[c];
+        ws.pmax[slot + c] = smax[c];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fold partial tables into the dense outputs.
+// direct_slots > 0: every cell's partials are slots 0..direct_slots-1 (LDS path).
+// direct_slots == 0: cell -> bucket cell>>12 -> slots bfirst..bfirst+bslots.
+__global__ __launch_bounds__(256) void k_dfg_reduce(int32_t A, int32_t direct_slots, DfgWs ws,
+                                                    DfgOutDev out) {
+    const int64_t cells = (int64_t)A * A;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= cells) return;
+    int64_t lc, s0, s1;
+    if (direct_slots > 0) {
+        lc = e;
+        s0 = 0;
+        s1 = direct_slots;
+    } else {
+        const int64_t b = e >> 12;
+        lc = e & (kCellsPerTable - 1);
+        s0 = ws.bfirst[b];
+        s1 = s0 + ws.bslots[b];
+    }
+    uint64_t cnt = 0, sum = 0;
+    int64_t mn = INT64_MAX, mx = INT64_MIN;
+    for (int64_t s = s0; s < s1; ++s) {
+        const size_t at = (size_t)s * kCellsPerTable + lc;
+        cnt += ws.pcount[at];
+        sum += ws.psum[at];
+        const int64_t a = ws.pmin[at], b = ws.pmax[at];
+        mn = a < mn ? a : mn;
+        mx = b > mx ? b : mx;
+    }
+    out.count[e] = (int64_t)cnt;
+    out.dt_sum[e] = (int64_t)sum;
+    out.dt_min[e] = mn;
+    out.dt_max[e] = mx;
+    if (out.dt_mean) out.dt_mean[e] = cnt ? (double)(int64_t)sum / (double)(int64_t)cnt : (double)NAN;
+}
+
+__global__ void k_dfg_zero_acts(int32_t A, DfgOutDev out) {
+    for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < A; a += gridDim.x * blockDim.x)
+        out.act_count[a] = out.start_count[a] = out.end_count[a] = 0;
+}
+
+// grid (ceil(A/256), kActRows): block (x, r) folds partial rows r, r+kActRows, ...
+constexpr int kActRows = 32;
+__global__ __launch_bounds__(256) void k_dfg_acts(int32_t A, int32_t nblk, DfgWs ws, DfgOutDev out) {
+    const int a = blockIdx.x * 256 + threadIdx.x;
+    if (a >= A) return;
+    uint64_t f = 0, st = 0, en = 0;
+    for (int k = blockIdx.y; k < nblk; k += kActRows) {
+        f += ws.pfreq[(size_t)k * A + a];
+        st += ws.pstart[(size_t)k * A + a];
+        en += ws.pend[(size_t)k * A + a];
+    }
+    atomicAdd(reinterpret_cast<unsigned long long*>(&out.act_count[a]), (unsigned long long)f);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&out.start_count[a]), (unsigned long long)st);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&out.end_count[a]), (unsigned long long)en);
+}
+
+// One block: overflow flag from the span partials, n_cases = sum of start counts.
+__global__ __launch_bounds__(1024) void k_dfg_final(int32_t A, int32_t nblk, DfgWs ws,
+                                                    const int32_t* status_in, DfgOutDev out) {
+    __shared__ uint64_t r1[1024 / kWave], r2[1024 / kWave];
+    uint64_t sp = 0, c = 0;
+    for (int k = threadIdx.x; k < nblk; k += 1024) sp = sat_add63(sp, ws.pspan[k]);
+    for (int a = threadIdx.x; a < A; a += 1024) c += (uint64_t)out.start_count[a];
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) sp = sat_add63(sp, __shfl_xor(sp, o));
+    c = wave_sum(c);
+    if (lane() == 0) {
+        r1[threadIdx.x / kWave] = sp;
+        r2[threadIdx.x / kWave] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t s = 0, t = 0;
+        for (int k = 0; k < 1024 / kWave; ++k) {
+            s = sat_add63(s, r1[k]);
+            t += r2[k];
+        }
+        *out.overflow = s > (uint64_t)INT64_MAX ? 1 : 0;
+        *out.n_cases = (int64_t)t;
+        if (status_in && *status_in != 0) set_status(out.status, *status_in);
+    }
+}
+
+static void launch_acts(int32_t A, int32_t nblk, DfgWs ws, const int32_t* status_in, DfgOutDev out,
+                        hipStream_t s) {
+    k_dfg_zero_acts<<<(unsigned)((A + 255) / 256), 256, 0, s>>>(A, out);
+    k_dfg_acts<<<dim3((unsigned)((A + 255) / 256), kActRows), 256, 0, s>>>(A, nblk, ws, out);
+    k_dfg_final<<<1, 1024, 0, s>>>(A, nblk, ws, status_in, out);
+}
+
+__global__ void k_status_init(int32_t* status) { *status = 0; }
+
+hipError_t launch_dfg(const int32_t* case_s, const int32_t* act_s, const int64_t* ts_s, int64_t n,
+                      int32_t A, const int32_t* status_in, DfgWs ws, DfgOutDev out, hipStream_t s) {
+    k_status_init<<<1, 1, 0, s>>>(out.status);
+    const int64_t cells = (int64_t)A * A;
+    if (A <= kDfgLdsMaxA) {
+        k_dfg_lds<<<kDfgLdsBlocks, kLB, 0, s>>>(case_s, act_s, ts_s, n, A, ws, out.status);
+        k_dfg_reduce<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(A, kDfgLdsBlocks, ws, out);
+        launch_acts(A, kDfgLdsBlocks, ws, status_in, out, s);
+    } else {
+        const int64_t nbt = dfg_tiles(n);
+        const int64_t nbk = n_buckets(A);
+        k_dfg_part<<<(unsigned)ws.n_act_blocks, kPB, 0, s>>>(case_s, act_s, ts_s, n, A, nbt, nbk, ws,
+                                                             out.status);
+        k_dfg_bucket_scan<<<(unsigned)nbk, 256, 0, s>>>(nbt, ws);
+        k_dfg_plan<<<1, 1024, 0, s>>>(nbk, ws);
+        k_dfg_agg<<<(unsigned)ws.n_slots_max, kAB, 0, s>>>(nbt, ws);
+        k_dfg_reduce<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(A, 0, ws, out);
+        launch_acts(A, ws.n_act_blocks, ws, status_in, out, s);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pm4g

@@ -1,0 +1,169 @@
+// Internal interface between the C-ABI layer (api.hip) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace pm4g {
+
+// Device header written by the range scan and read back by the host.
+struct RangeInfo {
+    int32_t case_min;
+    int32_t case_max;
+    int32_t status;     // first data-dependent error (PM4G_E_*), 0 if none
+    int32_t long_case;  // the case-segment sort met a case beyond its LDS window
+    int64_t ts_min;
+    int64_t ts_max;
+    int64_t reserved[4];
+};
+
+// Bump allocator over the caller's workspace.  With base == nullptr it only
+// measures (used by pm4g_workspace_bytes), so the layout has one definition.
+struct Bump {
+    char* base;
+    size_t off = 0;
+    explicit Bump(void* b) : base(static_cast<char*>(b)) {}
+    template <typename T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+// ---- range scan (range.hip) ----
+hipError_t launch_range_scan(const int32_t* case_id, const int32_t* act, const int64_t* ts, int64_t n,
+                             int32_t A, bool presorted, bool want_ts, RangeInfo* info, hipStream_t s);
+hipError_t launch_ts_range(const int64_t* ts, int64_t n, RangeInfo* info, hipStream_t s);
+
+// ---- LSD radix passes over (case key u32, ts i64, act u32) elements (radix.hip) ----
+struct SortBufs {
+    uint32_t* key;
+    int64_t* ts;
+    uint32_t* act;
+};
+constexpr int kRadixTile = 4096;
+inline int64_t radix_blocks(int64_t n) { return (n + kRadixTile - 1) / kRadixTile; }
+// One stable pass on an 8-bit digit.  digit_src 0: (key >> shift) & 255;
+// digit_src 1: ((ts - ts_min) >> shift) & 255.  With `first`, the input is
+// the raw log (in.key is the int32 case id, biased by case_min on the fly).
+hipError_t launch_radix_pass(SortBufs in, SortBufs out, int64_t n, int digit_src, int shift,
+                             bool first, const RangeInfo* info, uint32_t* hist, uint32_t* rowsum,
+                             hipStream_t s);
+
+// ---- per-case ordering of a case-grouped sequence (segsort.hip) ----
+constexpr int kSegWindow = 2048;
+constexpr int kSegCap = 4096;
+inline int64_t segsort_blocks(int64_t n) { return (n + kSegWindow - 1) / kSegWindow; }
+hipError_t launch_segsort(SortBufs in, int64_t n, RangeInfo* info, int32_t* case_s, int32_t* act_s,
+                          int64_t* ts_s, hipStream_t s);
+// Copies fully sorted buffers (fallback path) into the prepared arrays.
+hipError_t launch_unbias_copy(SortBufs in, int64_t n, const RangeInfo* info, int32_t* case_s,
+                              int32_t* act_s, int64_t* ts_s, hipStream_t s);
+// Copies a presorted raw log into the prepared arrays.
+hipError_t launch_copy_log(const int32_t* c, const int32_t* a, const int64_t* t, int64_t n,
+                           int32_t* case_s, int32_t* act_s, int64_t* ts_s, hipStream_t s);
+
+// ---- case table (cases.hip) ----
+constexpr int kCaseTile = 4096;
+inline int64_t case_blocks(int64_t n) { return (n + kCaseTile - 1) / kCaseTile; }
+hipError_t launch_case_table(const int32_t* case_s, int64_t n, uint32_t* blockcnt, int64_t* case_off,
+                             int32_t* case_code, int64_t* n_cases, hipStream_t s);
+
+// ---- DFG aggregation (dfg.hip) ----
+constexpr int kCellsPerTable = 4096;     // one LDS table of cells
+constexpr int kDfgLdsMaxA = 64;          // A*A <= 4096: one privatised table per block
+constexpr int kDfgLdsBlocks = 256;
+constexpr int kDfgTile = 4096;
+constexpr int kDfgPartBlocks = 1024;
+constexpr int kDfgAggTarget = 512;
+
+struct DfgWs {
+    // partial tables, slot-major [slot][kCellsPerTable]
+    uint32_t* pcount;
+    uint64_t* psum;
+    int64_t* pmin;
+    int64_t* pmax;
+    // per-block activity partials [block][A] and span partials [block]
+    uint32_t* pfreq;
+    uint32_t* pstart;
+    uint32_t* pend;
+    uint64_t* pspan;
+    // partition path
+    uint16_t* ecell;
+    uint64_t* egap;
+    uint32_t* ecnt;
+    uint32_t* ebeg;
+    uint32_t* escan;
+    uint32_t* btotal;
+    uint32_t* bfirst;
+    uint32_t* bslots;
+    int4* plan;
+    uint32_t* nplan;
+    int32_t n_act_blocks;
+    int32_t n_slots_max;
+};
+DfgWs dfg_ws_layout(Bump& b, int64_t n, int32_t A);
+struct DfgOutDev {
+    int64_t* count;
+    int64_t* dt_sum;
+    int64_t* dt_min;
+    int64_t* dt_max;
+    double* dt_mean;
+    int64_t* start_count;
+    int64_t* end_count;
+    int64_t* act_count;
+    int64_t* n_cases;
+    int32_t* overflow;
+    int32_t* status;
+};
+// n_cases is the number of case starts seen; status_in (may be NULL) is the
+// producing prepare's status word, propagated to out.status.
+hipError_t launch_dfg(const int32_t* case_s, const int32_t* act_s, const int64_t* ts_s, int64_t n,
+                      int32_t A, const int32_t* status_in, DfgWs ws, DfgOutDev out, hipStream_t s);
+
+// ---- variants (variants.hip) ----
+struct VarWs {
+    uint64_t* hash;      // [C] sequence hash per case, then sorted (ping-pong with hash2)
+    uint64_t* hash2;
+    uint32_t* idx;       // [C] case index carried through the hash sort (ping-pong with idx2)
+    uint32_t* idx2;
+    uint32_t* hist;      // radix histograms
+    uint32_t* rowsum;    // [256]
+    uint32_t* flag;      // [C] group start flags in hash order
+    uint32_t* sid;       // [C] exclusive count of group starts
+    uint32_t* sstart;    // [V+1] group start positions
+    uint32_t* repflag;   // [C] 1 for representative cases
+    uint32_t* rrank;     // [C] representative-order index of representative cases
+    uint32_t* vcount;    // [V] cases per variant (representative order)
+    uint32_t* vrepcase;  // [V] representative case index (representative order)
+    uint32_t* cvar;      // [C] representative-order variant of each case
+    uint32_t* vkey;      // [V] ordering keys (ping-pong with vkey2)
+    uint32_t* vkey2;
+    uint32_t* vidx;      // [V] representative-order ids (ping-pong with vidx2)
+    uint32_t* vidx2;
+    uint32_t* fid;       // [V] final id of each representative-order variant
+    uint32_t* lens;      // [V] sequence lengths in final order
+    uint32_t* part32;    // scan partials
+    int64_t* part64;
+    int64_t* scal;       // [0] C, [1] V, [2] total sequence length
+    uint32_t* u32scal;   // [0] collision flag, [1] V
+};
+VarWs var_ws_layout(Bump& b, int64_t n);
+struct VarOutDev {
+    int64_t* n_variants;
+    int64_t* var_count;
+    int32_t* var_len;
+    int32_t* var_rep;
+    int64_t* var_off;
+    int32_t* var_acts;
+    int32_t* case_variant;
+    int32_t* status;
+};
+hipError_t launch_variants(const int32_t* act_s, const int64_t* case_off, const int32_t* case_code,
+                           const int64_t* n_cases, const int32_t* status_in, int64_t n, VarWs ws,
+                           VarOutDev out, uint32_t debug_hash_bits, hipStream_t s);
+
+}  // namespace pm4g

@@ -1,0 +1,210 @@
+// Stable LSD radix passes over (key u32, ts i64, act u32) elements, 8-bit
+// digits, reduce-then-scan:
+//   k_radix_hist     per-tile digit histograms, digit-major [256][tiles]
+//   k_radix_scan     exclusive scan of each digit row, row totals
+//   k_radix_scatter  wave64 ballot ranking (stable: wave, item, lane order),
+//                    LDS staging in digit order, coalesced-run writes
+// The first pass reads the raw log columns directly (case id biased by the
+// case minimum), so the caller's arrays are never copied.
+//
+// This is the grouping step of Sec. 3's first formatting step: events of a
+// case become adjacent while keeping their row order (stability); the
+// per-case timestamp order is applied afterwards in LDS (segsort.hip).
+// Bytes per event per pass: 4 (hist) + 16 read + 16 write.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace pm4g {
+
+constexpr int kRB = 512;               // threads per block
+constexpr int kRI = kRadixTile / kRB;  // items per thread (8)
+constexpr int kRW = kRB / kWave;       // waves per block (8)
+
+template <int SRC>
+__device__ __forceinline__ uint32_t digit_of(uint32_t key, int64_t ts, int shift, int64_t ts_min) {
+    if (SRC == 0) return (key >> shift) & 255u;
+    return (uint32_t)(((uint64_t)ts - (uint64_t)ts_min) >> shift) & 255u;
+}
+
+template <bool FIRST>
+__device__ __forceinline__ uint32_t load_key(const uint32_t* key, int64_t i, int32_t case_min) {
+    if (FIRST) return (uint32_t)reinterpret_cast<const int32_t*>(key)[i] - (uint32_t)case_min;
+    return key[i];
+}
+
+template <int SRC, bool FIRST>
+__global__ __launch_bounds__(kRB) void k_radix_hist(SortBufs in, int64_t n, int shift,
+                                                    const RangeInfo* info, uint32_t* hist,
+                                                    int64_t nb) {
+    __shared__ uint32_t h[256];
+    if (threadIdx.x < 256) h[threadIdx.x] = 0;
+    __syncthreads();
+    const int32_t case_min = info->case_min;
+    const int64_t ts_min = info->ts_min;
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+#pragma unroll
+    for (int k = 0; k < kRI; ++k) {
+        const int64_t i = base + k * kRB + threadIdx.x;
+        if (i < n) {
+            uint32_t d;
+            if (SRC == 0) d = digit_of<0>(load_key<FIRST>(in.key, i, case_min), 0, shift, 0);
+            else d = digit_of<1>(0, in.ts[i], shift, ts_min);
+            atomicAdd(&h[d], 1u);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 256) hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+// One block per digit: exclusive scan of hist[d][0..nb) in place, row total.
+__global__ __launch_bounds__(256) void k_radix_scan(uint32_t* hist, int64_t nb, uint32_t* rowsum) {
+    __shared__ uint32_t tmp[256 / kWave + 1];
+    uint32_t* row = hist + (int64_t)blockIdx.x * nb;
+    uint32_t run = 0;
+    for (int64_t c0 = 0; c0 < nb; c0 += 256 * 4) {
+        uint32_t v[4];
+        uint32_t s = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = c0 + threadIdx.x * 4 + q;
+            v[q] = i < nb ? row[i] : 0u;
+            s += v[q];
+        }
+        uint32_t total;
+        uint32_t ex = block_excl_sum<256>(s, tmp, &total);
+        uint32_t r = run + ex;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = c0 + threadIdx.x * 4 + q;
+            if (i < nb) row[i] = r;
+            r += v[q];
+        }
+        run += total;
+    }
+    if (threadIdx.x == 0) rowsum[blockIdx.x] = run;
+}
+
+template <int SRC, bool FIRST>
+__global__ __launch_bounds__(kRB) void k_radix_scatter(SortBufs in, SortBufs out, int64_t n, int shift,
+                                                       const RangeInfo* info, const uint32_t* hist,
+                                                       const uint32_t* rowsum, int64_t nb) {
+    __shared__ uint32_t cnt[kRW * 256];       // per-wave running digit counts
+    __shared__ uint32_t tstart[256];          // tile-local start of each digit
+    __shared__ int64_t gshift[256];           // global position - tile position
+    __shared__ uint32_t skey[kRadixTile];
+    __shared__ int64_t sts[kRadixTile];
+    __shared__ uint32_t sact[kRadixTile];
+    __shared__ uint32_t tmp[kRB / kWave + 1];
+
+    const int32_t case_min = info->case_min;
+    const int64_t ts_min = info->ts_min;
+    const int w = threadIdx.x / kWave;
+    const int64_t tile0 = (int64_t)blockIdx.x * kRadixTile;
+    const int64_t wbase = tile0 + (int64_t)w * (kWave * kRI);
+
+    for (int i = threadIdx.x; i < kRW * 256; i += kRB) cnt[i] = 0;
+
+    uint32_t key[kRI], act[kRI], dg[kRI], rk[kRI];
+    int64_t tv[kRI];
+#pragma unroll
+    for (int k = 0; k < kRI; ++k) {
+        const int64_t i = wbase + k * kWave + lane();
+        if (i < n) {
+            key[k] = load_key<FIRST>(in.key, i, case_min);
+            tv[k] = in.ts[i];
+            act[k] = in.act[i];
+        } else {
+            key[k] = 0;
+            tv[k] = ts_min;
+            act[k] = 0;
+        }
+        dg[k] = digit_of<SRC>(key[k], tv[k], shift, ts_min);
+    }
+    __syncthreads();
+
+    // Stable ranks within the wave's contiguous chunk, in (item, lane) order.
+#pragma unroll
+    for (int k = 0; k < kRI; ++k) {
+        const int64_t i = wbase + k * kWave + lane();
+        const bool valid = i < n;
+        const uint64_t active = __ballot(valid);
+        const uint64_t peers = match_digit8(dg[k], active);
+        const uint32_t below = __popcll(peers & lanes_below());
+        uint32_t c = 0;
+        if (valid) c = cnt[w * 256 + dg[k]];
+        rk[k] = c + below;
+        if (valid && below == 0) cnt[w * 256 + dg[k]] = c + __popcll(peers);
+    }
+    __syncthreads();
+
+    // Per digit: exclusive offsets of the waves, the tile's digit totals.
+    uint32_t tot = 0;
+    if (threadIdx.x < 256) {
+        const int d = threadIdx.x;
+        uint32_t run = 0;
+        for (int ww = 0; ww < kRW; ++ww) {
+            const uint32_t x = cnt[ww * 256 + d];
+            cnt[ww * 256 + d] = run;
+            run += x;
+        }
+        tot = run;
+    }
+    uint32_t all;
+    const uint32_t ts_excl = block_excl_sum<kRB>(tot, tmp, &all);
+    const uint32_t rs = threadIdx.x < 256 ? rowsum[threadIdx.x] : 0u;
+    const uint32_t digit_base = block_excl_sum<kRB>(rs, tmp, &all);
+    if (threadIdx.x < 256) {
+        const int d = threadIdx.x;
+        tstart[d] = ts_excl;
+        gshift[d] = (int64_t)digit_base + (int64_t)hist[(int64_t)d * nb + blockIdx.x] - (int64_t)ts_excl;
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int k = 0; k < kRI; ++k) {
+        const int64_t i = wbase + k * kWave + lane();
+        if (i < n) {
+            const uint32_t pos = tstart[dg[k]] + cnt[w * 256 + dg[k]] + rk[k];
+            skey[pos] = key[k];
+            sts[pos] = tv[k];
+            sact[pos] = act[k];
+        }
+    }
+    __syncthreads();
+
+    const int64_t valid_count = (n - tile0) < kRadixTile ? (n - tile0) : kRadixTile;
+    for (int i = threadIdx.x; i < valid_count; i += kRB) {
+        const uint32_t k = skey[i];
+        const int64_t t = sts[i];
+        const uint32_t d = digit_of<SRC>(k, t, shift, ts_min);
+        const int64_t g = gshift[d] + i;
+        out.key[g] = k;
+        out.ts[g] = t;
+        out.act[g] = sact[i];
+    }
+}
+
+template <int SRC, bool FIRST>
+static void run_pass(SortBufs in, SortBufs out, int64_t n, int shift, const RangeInfo* info,
+                     uint32_t* hist, uint32_t* rowsum, hipStream_t s) {
+    const int64_t nb = radix_blocks(n);
+    k_radix_hist<SRC, FIRST><<<(unsigned)nb, kRB, 0, s>>>(in, n, shift, info, hist, nb);
+    k_radix_scan<<<256, 256, 0, s>>>(hist, nb, rowsum);
+    k_radix_scatter<SRC, FIRST><<<(unsigned)nb, kRB, 0, s>>>(in, out, n, shift, info, hist, rowsum, nb);
+}
+
+hipError_t launch_radix_pass(SortBufs in, SortBufs out, int64_t n, int digit_src, int shift,
+                             bool first, const RangeInfo* info, uint32_t* hist, uint32_t* rowsum,
+                             hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (digit_src == 0) {
+        if (first) run_pass<0, true>(in, out, n, shift, info, hist, rowsum, s);
+        else run_pass<0, false>(in, out, n, shift, info, hist, rowsum, s);
+    } else {
+        if (first) run_pass<1, true>(in, out, n, shift, info, hist, rowsum, s);
+        else run_pass<1, false>(in, out, n, shift, info, hist, rowsum, s);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pm4g

@@ -1,0 +1,111 @@
+// Range scan of a raw log: case-id and timestamp extremes (they fix the
+// radix key widths), activity validation, and the order check for a log
+// that claims to be presorted (Sec. 3: (case, timestamp, row) order).
+//
+// Streaming pass, HBM-bound: 8 bytes/event (case, activity), 16 with the
+// timestamp.  Per-wave reductions, then one atomic per wave per extreme.
+#include "common.hpp"
+#include "internal.hpp"
+#include "../../include/pm4g.h"
+
+namespace pm4g {
+
+__global__ void k_range_init(RangeInfo* info) {
+    info->case_min = INT32_MAX;
+    info->case_max = INT32_MIN;
+    info->status = 0;
+    info->long_case = 0;
+    info->ts_min = INT64_MAX;
+    info->ts_max = INT64_MIN;
+}
+
+template <bool PRESORTED, bool WANT_TS>
+__global__ __launch_bounds__(256) void k_range_scan(const int32_t* __restrict__ case_id,
+                                                    const int32_t* __restrict__ act,
+                                                    const int64_t* __restrict__ ts, int64_t n,
+                                                    int32_t A, RangeInfo* info) {
+    int32_t cmin = INT32_MAX, cmax = INT32_MIN;
+    int64_t tmin = INT64_MAX, tmax = INT64_MIN;
+    bool bad_act = false, unsorted = false;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int32_t c = case_id[i];
+        const int32_t a = act[i];
+        bad_act |= (uint32_t)a >= (uint32_t)A;
+        cmin = c < cmin ? c : cmin;
+        cmax = c > cmax ? c : cmax;
+        if (WANT_TS || PRESORTED) {
+            const int64_t t = ts[i];
+            tmin = t < tmin ? t : tmin;
+            tmax = t > tmax ? t : tmax;
+            if (PRESORTED && i > 0) {
+                const int32_t c0 = case_id[i - 1];
+                const int64_t t0 = ts[i - 1];
+                unsorted |= (c0 > c) || (c0 == c && t0 > t);
+            }
+        }
+    }
+    cmin = wave_min(cmin);
+    cmax = wave_max(cmax);
+    if (WANT_TS || PRESORTED) {
+        tmin = wave_min(tmin);
+        tmax = wave_max(tmax);
+    }
+    const bool any_bad = __ballot(bad_act) != 0;
+    const bool any_unsorted = __ballot(unsorted) != 0;
+    if (lane() == 0) {
+        atomicMin(&info->case_min, cmin);
+        atomicMax(&info->case_max, cmax);
+        if (WANT_TS || PRESORTED) {
+            __hip_atomic_fetch_min(&info->ts_min, tmin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_max(&info->ts_max, tmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (any_bad) set_status(&info->status, PM4G_E_RANGE);
+        if (any_unsorted) set_status(&info->status, PM4G_E_NOT_SORTED);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ts_range(const int64_t* __restrict__ ts, int64_t n,
+                                                  RangeInfo* info) {
+    int64_t tmin = INT64_MAX, tmax = INT64_MIN;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int64_t t = ts[i];
+        tmin = t < tmin ? t : tmin;
+        tmax = t > tmax ? t : tmax;
+    }
+    tmin = wave_min(tmin);
+    tmax = wave_max(tmax);
+    if (lane() == 0) {
+        __hip_atomic_fetch_min(&info->ts_min, tmin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_max(&info->ts_max, tmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+static int range_grid(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    return g < 1 ? 1 : (int)g;
+}
+
+hipError_t launch_range_scan(const int32_t* case_id, const int32_t* act, const int64_t* ts, int64_t n,
+                             int32_t A, bool presorted, bool want_ts, RangeInfo* info, hipStream_t s) {
+    k_range_init<<<1, 1, 0, s>>>(info);
+    if (n > 0) {
+        const int g = range_grid(n);
+        if (presorted)
+            k_range_scan<true, true><<<g, 256, 0, s>>>(case_id, act, ts, n, A, info);
+        else if (want_ts)
+            k_range_scan<false, true><<<g, 256, 0, s>>>(case_id, act, ts, n, A, info);
+        else
+            k_range_scan<false, false><<<g, 256, 0, s>>>(case_id, act, ts, n, A, info);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ts_range(const int64_t* ts, int64_t n, RangeInfo* info, hipStream_t s) {
+    if (n > 0) k_ts_range<<<range_grid(n), 256, 0, s>>>(ts, n, info);
+    return hipGetLastError();
+}
+
+}  // namespace pm4g

@@ -1,0 +1,224 @@
+// Per-case ordering (Sec. 3, first formatting step: within a case, events are
+// ordered by timestamp, then by absolute row index).
+//
+// Input: the radix output, grouped by case, each case's events in row order
+// (the passes are stable).  Block w owns the cases that START inside window
+// [w*2048, (w+1)*2048); their events (at most 2048 + 2048 = 4096 when no case
+// is longer than 2049 events) are staged in LDS.  Each event's rank inside its
+// case is counted against the other events of the case: rank = #{j in case :
+// t_j < t_i or (t_j == t_i and j before i)}.  Lanes of a wave hold adjacent
+// events, so they walk the same case and the LDS reads are broadcasts.
+// A region longer than the LDS window sets RangeInfo::long_case and the
+// host switches to the full-key fallback.
+//
+// Also writes the prepared columns: case id (unbiased), activity, timestamp.
+// Bytes per event: 16 read + 16 write.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace pm4g {
+
+constexpr int kSB = 512;
+constexpr int kSI = kSegCap / kSB;   // 8 items per thread
+
+__device__ __forceinline__ int64_t block_min_i64(int64_t v, int64_t* red) {
+    v = wave_min(v);
+    const int w = threadIdx.x / kWave;
+    if (lane() == 0) red[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t m = red[0];
+        for (int i = 1; i < kSB / kWave; ++i) m = red[i] < m ? red[i] : m;
+        red[kSB / kWave] = m;
+    }
+    __syncthreads();
+    const int64_t r = red[kSB / kWave];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ int32_t wave_incl_max_i32(int32_t v) {
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        int32_t u = __shfl_up(v, o);
+        if (lane() >= o) v = u > v ? u : v;
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeInfo* info,
+                                                 int32_t* __restrict__ case_s,
+                                                 int32_t* __restrict__ act_s,
+                                                 int64_t* __restrict__ ts_s) {
+    __shared__ uint32_t lkey[kSegCap];
+    __shared__ int64_t lts[kSegCap];
+    __shared__ uint16_t lact[kSegCap];
+    __shared__ uint16_t lcs[kSegCap];
+    __shared__ uint16_t lce[kSegCap + 1];
+    __shared__ int64_t red[kSB / kWave + 1];
+    __shared__ int32_t wred[kSB / kWave];
+
+    const uint32_t* __restrict__ key = in.key;
+    const int64_t w0 = (int64_t)blockIdx.x * kSegWindow;
+    const int64_t w1 = (w0 + kSegWindow) < n ? (w0 + kSegWindow) : n;
+
+    // 1. first case start inside the window
+    int64_t cand = INT64_MAX;
+    for (int64_t p = w0 + threadIdx.x; p < w1; p += kSB) {
+        if (p == 0 || key[p] != key[p - 1]) {
+            cand = p;
+            break;
+        }
+    }
+    const int64_t s = block_min_i64(cand, red);
+    if (s == INT64_MAX) return;   // a long case covers the whole window (block-uniform)
+
+    // 2. first case start at or after the window end (n counts as a start)
+    int64_t e = INT64_MAX;
+    for (int64_t base = w1; base <= n && base - s <= kSegCap; base += kSB) {
+        const int64_t p = base + threadIdx.x;
+        int64_t c = INT64_MAX;
+        if (p == n) c = n;
+        else if (p < n && key[p] != key[p - 1]) c = p;
+        const int64_t m = block_min_i64(c, red);
+        if (m != INT64_MAX) {
+            e = m;
+            break;
+        }
+    }
+    if (e == INT64_MAX || e - s > kSegCap) {
+        if (threadIdx.x == 0) atomicOr(&info->long_case, 1);
+        return;
+    }
+    const int R = (int)(e - s);
+
+    // 3. stage the region
+    for (int i = threadIdx.x; i < R; i += kSB) {
+        lkey[i] = key[s + i];
+        lts[i] = in.ts[s + i];
+        lact[i] = (uint16_t)in.act[s + i];
+    }
+    __syncthreads();
+
+    // 4. case start of every event: inclusive max-scan of start positions
+    //    (blocked layout: thread t owns items 8t .. 8t+7)
+    {
+        int32_t loc[kSI];
+        int32_t m = 0;
+#pragma unroll
+        for (int q = 0; q < kSI; ++q) {
+            const int i = threadIdx.x * kSI + q;
+            if (i < R && (i == 0 || lkey[i] != lkey[i - 1])) m = i;
+            loc[q] = m;
+        }
+        const int w = threadIdx.x / kWave;
+        int32_t inc = wave_incl_max_i32(m);
+        if (lane() == kWave - 1) wred[w] = inc;
+        __syncthreads();
+        int32_t before = 0;
+        for (int i = 0; i < w; ++i) before = wred[i] > before ? wred[i] : before;
+        int32_t excl = __shfl_up(inc, 1);
+        if (lane() == 0) excl = 0;
+        excl = excl > before ? excl : before;
+#pragma unroll
+        for (int q = 0; q < kSI; ++q) {
+            const int i = threadIdx.x * kSI + q;
+            if (i < R) lcs[i] = (uint16_t)(loc[q] > excl ? loc[q] : excl);
+        }
+    }
+    __syncthreads();
+    // case end, stored at the case start: the last event of each case writes it
+    for (int i = threadIdx.x; i < R; i += kSB) {
+        if (i == R - 1 || lkey[i + 1] != lkey[i]) lce[lcs[i]] = (uint16_t)(i + 1);
+    }
+    __syncthreads();
+
+    // 5. rank inside the case (striped: a wave holds 64 adjacent events)
+    int32_t pos[kSI];
+    uint32_t kv[kSI];
+    int64_t tv[kSI];
+    uint16_t av[kSI];
+#pragma unroll
+    for (int q = 0; q < kSI; ++q) {
+        const int i = threadIdx.x + q * kSB;
+        pos[q] = -1;
+        if (i < R) {
+            const int cs = lcs[i];
+            const int ce = lce[cs];
+            const int64_t t = lts[i];
+            int r = 0;
+            for (int j = cs; j < ce; ++j) {
+                const int64_t tj = lts[j];
+                r += (tj < t) | ((tj == t) & (j < i));
+            }
+            pos[q] = cs + r;
+            kv[q] = lkey[i];
+            tv[q] = t;
+            av[q] = lact[i];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kSI; ++q) {
+        if (pos[q] >= 0) {
+            lkey[pos[q]] = kv[q];
+            lts[pos[q]] = tv[q];
+            lact[pos[q]] = av[q];
+        }
+    }
+    __syncthreads();
+
+    // 6. write the prepared columns
+    const uint32_t bias = (uint32_t)info->case_min;
+    for (int i = threadIdx.x; i < R; i += kSB) {
+        case_s[s + i] = (int32_t)(lkey[i] + bias);
+        act_s[s + i] = (int32_t)lact[i];
+        ts_s[s + i] = lts[i];
+    }
+}
+
+__global__ void k_unbias_copy(SortBufs in, int64_t n, const RangeInfo* info, int32_t* case_s,
+                              int32_t* act_s, int64_t* ts_s) {
+    const uint32_t bias = (uint32_t)info->case_min;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        case_s[i] = (int32_t)(in.key[i] + bias);
+        act_s[i] = (int32_t)in.act[i];
+        ts_s[i] = in.ts[i];
+    }
+}
+
+__global__ void k_copy_log(const int32_t* c, const int32_t* a, const int64_t* t, int64_t n,
+                           int32_t* case_s, int32_t* act_s, int64_t* ts_s) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        case_s[i] = c[i];
+        act_s[i] = a[i];
+        ts_s[i] = t[i];
+    }
+}
+
+static unsigned copy_grid(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    return (unsigned)(g > 8192 ? 8192 : (g < 1 ? 1 : g));
+}
+
+hipError_t launch_segsort(SortBufs in, int64_t n, RangeInfo* info, int32_t* case_s, int32_t* act_s,
+                          int64_t* ts_s, hipStream_t s) {
+    if (n > 0) k_segsort<<<(unsigned)segsort_blocks(n), kSB, 0, s>>>(in, n, info, case_s, act_s, ts_s);
+    return hipGetLastError();
+}
+
+hipError_t launch_unbias_copy(SortBufs in, int64_t n, const RangeInfo* info, int32_t* case_s,
+                              int32_t* act_s, int64_t* ts_s, hipStream_t s) {
+    if (n > 0) k_unbias_copy<<<copy_grid(n), 256, 0, s>>>(in, n, info, case_s, act_s, ts_s);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_log(const int32_t* c, const int32_t* a, const int64_t* t, int64_t n,
+                           int32_t* case_s, int32_t* act_s, int64_t* ts_s, hipStream_t s) {
+    if (n > 0) k_copy_log<<<copy_grid(n), 256, 0, s>>>(c, a, t, n, case_s, act_s, ts_s);
+    return hipGetLastError();
+}
+
+}  // namespace pm4g

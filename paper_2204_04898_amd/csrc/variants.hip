@@ -1,0 +1,272 @@
+// Trace variants of a prepared log (Sec. 3, variant level: cases grouped by
+// their activity sequence, "a double aggregation"; the cases dataframe holds
+// numeric features that identify each case's variant).
+//
+// Grouping is exact: a 64-bit hash of each case's sequence (the numeric
+// feature) only brings candidates together; every equal-hash neighbour pair
+// is compared element by element, and a run of equal hashes holding more
+// than one sequence is regrouped exactly.  Variant ids follow (count desc,
+// representative asc) with the representative the smallest case id.
+//
+//   k_var_hash       per case: length-seeded FNV-1a over the activities, mixed
+//   radix (64 bits)  cases by hash; stable, so equal hashes keep case order
+//   k_var_verify     neighbour sequences compared exactly -> group starts
+//   k_var_fix        only after a true collision: exact regrouping of a run
+//   scans            group ids; representatives (first member = smallest id)
+//                    enumerated in case order = representative order
+//   radix (count)    stable sort by descending count -> final ids
+//   k_var_emit       counts, lengths, representatives, CSR sequences, ids
+// All sizes (cases, variants) stay on the device; nothing synchronises.
+#include "common.hpp"
+#include "devsort.hpp"
+#include "internal.hpp"
+#include "../../include/pm4g.h"
+
+namespace pm4g {
+
+VarWs var_ws_layout(Bump& b, int64_t n) {
+    VarWs w{};
+    const size_t m = (size_t)(n > 0 ? n : 1);
+    w.hash = b.take<uint64_t>(m);
+    w.hash2 = b.take<uint64_t>(m);
+    w.idx = b.take<uint32_t>(m);
+    w.idx2 = b.take<uint32_t>(m);
+    w.hist = b.take<uint32_t>(256 * (size_t)(dev::tiles(n) + 1));
+    w.rowsum = b.take<uint32_t>(256);
+    w.flag = b.take<uint32_t>(m);
+    w.sid = b.take<uint32_t>(m);
+    w.sstart = b.take<uint32_t>(m + 1);
+    w.repflag = b.take<uint32_t>(m);
+    w.rrank = b.take<uint32_t>(m);
+    w.vcount = b.take<uint32_t>(m);
+    w.vrepcase = b.take<uint32_t>(m);
+    w.cvar = b.take<uint32_t>(m);
+    w.vkey = b.take<uint32_t>(m);
+    w.vkey2 = b.take<uint32_t>(m);
+    w.vidx = b.take<uint32_t>(m);
+    w.vidx2 = b.take<uint32_t>(m);
+    w.fid = b.take<uint32_t>(m);
+    w.lens = b.take<uint32_t>(m);
+    w.part32 = b.take<uint32_t>(dev::kScanGrid);
+    w.part64 = b.take<int64_t>(dev::kScanGrid);
+    w.scal = b.take<int64_t>(8);
+    w.u32scal = b.take<uint32_t>(8);
+    return w;
+}
+
+namespace {
+
+constexpr int kGrid = 2048;
+constexpr int kBlk = 256;
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__device__ bool same_seq(const int32_t* act_s, const int64_t* case_off, uint32_t a, uint32_t b) {
+    const int64_t a0 = case_off[a], a1 = case_off[a + 1];
+    const int64_t b0 = case_off[b], b1 = case_off[b + 1];
+    if (a1 - a0 != b1 - b0) return false;
+    for (int64_t k = 0; k < a1 - a0; ++k)
+        if (act_s[a0 + k] != act_s[b0 + k]) return false;
+    return true;
+}
+
+__global__ void k_var_init(VarWs w, const int64_t* n_cases) {
+    if (threadIdx.x == 0) {
+        w.scal[0] = *n_cases;   // C
+        w.scal[1] = 0;          // V (filled later)
+        w.u32scal[0] = 0;       // collisions
+        w.u32scal[1] = 0;       // V (u32)
+    }
+}
+
+__global__ __launch_bounds__(kBlk) void k_var_hash(const int32_t* __restrict__ act_s,
+                                                   const int64_t* __restrict__ case_off, VarWs w,
+                                                   uint64_t mask) {
+    const int64_t C = w.scal[0];
+    for (int64_t c = (int64_t)blockIdx.x * kBlk + threadIdx.x; c < C; c += (int64_t)gridDim.x * kBlk) {
+        const int64_t o0 = case_off[c], o1 = case_off[c + 1];
+        uint64_t h = 0xcbf29ce484222325ull ^ mix64((uint64_t)(o1 - o0));
+        for (int64_t k = o0; k < o1; ++k) h = (h ^ (uint64_t)(uint32_t)(act_s[k] + 1)) * 0x100000001b3ull;
+        h = mix64(h);
+        if (mask) h &= mask;
+        w.hash[c] = h;
+        w.idx[c] = (uint32_t)c;
+        w.repflag[c] = 0;
+    }
+}
+
+__global__ __launch_bounds__(kBlk) void k_var_verify(const uint64_t* __restrict__ hs,
+                                                     const uint32_t* __restrict__ is,
+                                                     const int32_t* __restrict__ act_s,
+                                                     const int64_t* __restrict__ case_off, VarWs w) {
+    const int64_t C = w.scal[0];
+    for (int64_t p = (int64_t)blockIdx.x * kBlk + threadIdx.x; p < C; p += (int64_t)gridDim.x * kBlk) {
+        uint32_t f = 1;
+        if (p > 0 && hs[p] == hs[p - 1]) {
+            if (same_seq(act_s, case_off, is[p], is[p - 1])) f = 0;
+            else atomicOr(&w.u32scal[0], 1u);
+        }
+        w.flag[p] = f;
+    }
+}
+
+// Exact regrouping of equal-hash runs that hold several sequences.  Only does
+// work after a true hash collision; one thread per affected run.
+__global__ __launch_bounds__(kBlk) void k_var_fix(const uint64_t* __restrict__ hs, uint32_t* is,
+                                                  const int32_t* __restrict__ act_s,
+                                                  const int64_t* __restrict__ case_off, VarWs w) {
+    if (w.u32scal[0] == 0) return;
+    const int64_t C = w.scal[0];
+    uint32_t* out = w.vidx2;     // scratch
+    uint32_t* mark = w.vkey2;    // scratch
+    for (int64_t p = (int64_t)blockIdx.x * kBlk + threadIdx.x; p < C; p += (int64_t)gridDim.x * kBlk) {
+        if (p > 0 && hs[p] == hs[p - 1]) continue;   // not a run start
+        int64_t q = p + 1;
+        bool mixed = false;
+        while (q < C && hs[q] == hs[p]) {
+            mixed |= w.flag[q] != 0;
+            ++q;
+        }
+        if (!mixed) continue;
+        for (int64_t a = p; a < q; ++a) mark[a] = 0;
+        int64_t o = p;
+        for (int64_t a = p; a < q; ++a) {
+            if (mark[a]) continue;
+            const uint32_t lead = is[a];
+            mark[a] = 1;
+            out[o] = lead;
+            w.flag[o] = 1;
+            ++o;
+            for (int64_t b = a + 1; b < q; ++b) {
+                if (!mark[b] && same_seq(act_s, case_off, is[b], lead)) {
+                    mark[b] = 1;
+                    out[o] = is[b];
+                    w.flag[o] = 0;
+                    ++o;
+                }
+            }
+        }
+        for (int64_t a = p; a < q; ++a) is[a] = out[a];
+    }
+}
+
+// sid = inclusive group index (after the exclusive scan of flags + flag - 1).
+__global__ __launch_bounds__(kBlk) void k_var_groups(const uint32_t* __restrict__ is, VarWs w) {
+    const int64_t C = w.scal[0];
+    for (int64_t p = (int64_t)blockIdx.x * kBlk + threadIdx.x; p < C; p += (int64_t)gridDim.x * kBlk) {
+        if (w.flag[p]) {
+            const uint32_t g = w.sid[p];       // exclusive count of starts before p
+            w.sstart[g] = (uint32_t)p;
+            w.repflag[is[p]] = 1;              // first member: smallest case index
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint32_t V = w.u32scal[1];
+        w.sstart[V] = (uint32_t)C;
+        w.scal[1] = V;
+    }
+}
+
+// Per group (hash order): count and representative, stored at the group's
+// representative-order index; per case: its representative-order variant.
+__global__ __launch_bounds__(kBlk) void k_var_segments(const uint32_t* __restrict__ is, VarWs w) {
+    const int64_t C = w.scal[0];
+    const int64_t V = w.scal[1];
+    for (int64_t g = (int64_t)blockIdx.x * kBlk + threadIdx.x; g < V; g += (int64_t)gridDim.x * kBlk) {
+        const uint32_t s0 = w.sstart[g], s1 = w.sstart[g + 1];
+        const uint32_t rep = is[s0];
+        const uint32_t v = w.rrank[rep];
+        w.vcount[v] = s1 - s0;
+        w.vrepcase[v] = rep;
+        w.vkey[v] = (uint32_t)C - (s1 - s0);   // ascending key = descending count
+        w.vidx[v] = v;
+    }
+    for (int64_t p = (int64_t)blockIdx.x * kBlk + threadIdx.x; p < C; p += (int64_t)gridDim.x * kBlk) {
+        // group of p: flags up to p, minus one
+        const uint32_t g = w.sid[p] + w.flag[p] - 1;
+        w.cvar[is[p]] = w.rrank[is[w.sstart[g]]];
+    }
+}
+
+__global__ __launch_bounds__(kBlk) void k_var_ids(const uint32_t* __restrict__ order, VarWs w,
+                                                  const int64_t* __restrict__ case_off,
+                                                  const int32_t* __restrict__ case_code, VarOutDev out) {
+    const int64_t V = w.scal[1];
+    for (int64_t k = (int64_t)blockIdx.x * kBlk + threadIdx.x; k < V; k += (int64_t)gridDim.x * kBlk) {
+        const uint32_t v = order[k];
+        w.fid[v] = (uint32_t)k;
+        const uint32_t r = w.vrepcase[v];
+        const uint32_t L = (uint32_t)(case_off[r + 1] - case_off[r]);
+        out.var_count[k] = w.vcount[v];
+        out.var_rep[k] = case_code[r];
+        out.var_len[k] = (int32_t)L;
+        w.lens[k] = L;
+    }
+}
+
+__global__ __launch_bounds__(kBlk) void k_var_emit(const uint32_t* __restrict__ order,
+                                                   const int32_t* __restrict__ act_s,
+                                                   const int64_t* __restrict__ case_off, VarWs w,
+                                                   const int32_t* status_in, VarOutDev out) {
+    const int64_t C = w.scal[0];
+    const int64_t V = w.scal[1];
+    for (int64_t k = (int64_t)blockIdx.x * kBlk + threadIdx.x; k < V; k += (int64_t)gridDim.x * kBlk) {
+        const uint32_t r = w.vrepcase[order[k]];
+        const int64_t o0 = case_off[r];
+        const int64_t L = case_off[r + 1] - o0;
+        const int64_t d = out.var_off[k];
+        for (int64_t j = 0; j < L; ++j) out.var_acts[d + j] = act_s[o0 + j];
+    }
+    if (out.case_variant) {
+        for (int64_t c = (int64_t)blockIdx.x * kBlk + threadIdx.x; c < C; c += (int64_t)gridDim.x * kBlk)
+            out.case_variant[c] = (int32_t)w.fid[w.cvar[c]];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        out.var_off[V] = w.scal[2];
+        *out.n_variants = V;
+        *out.status = status_in ? *status_in : 0;
+    }
+}
+
+int bits_for(int64_t n) {
+    int b = 0;
+    while (b < 63 && (int64_t(1) << b) <= n) ++b;
+    return b;
+}
+
+}  // namespace
+
+hipError_t launch_variants(const int32_t* act_s, const int64_t* case_off, const int32_t* case_code,
+                           const int64_t* n_cases, const int32_t* status_in, int64_t n, VarWs w,
+                           VarOutDev out, uint32_t debug_hash_bits, hipStream_t s) {
+    const uint64_t mask = (debug_hash_bits == 0 || debug_hash_bits >= 64)
+                              ? 0ull
+                              : ((uint64_t(1) << debug_hash_bits) - 1);
+    k_var_init<<<1, 1, 0, s>>>(w, n_cases);
+    k_var_hash<<<kGrid, kBlk, 0, s>>>(act_s, case_off, w, mask);
+    const bool in2 = dev::sort_pairs<uint64_t>(w.hash, w.idx, w.hash2, w.idx2, &w.scal[0], n, 64, w.hist,
+                                               w.rowsum, s);
+    const uint64_t* hs = in2 ? w.hash2 : w.hash;
+    uint32_t* is = in2 ? w.idx2 : w.idx;
+    k_var_verify<<<kGrid, kBlk, 0, s>>>(hs, is, act_s, case_off, w);
+    k_var_fix<<<kGrid, kBlk, 0, s>>>(hs, is, act_s, case_off, w);
+    // group index of every group start; V
+    dev::excl_scan<uint32_t>(w.flag, &w.scal[0], w.sid, w.part32, &w.u32scal[1], s);
+    k_var_groups<<<kGrid, kBlk, 0, s>>>(is, w);
+    // representative-order index of every representative case
+    dev::excl_scan<uint32_t>(w.repflag, &w.scal[0], w.rrank, w.part32, (uint32_t*)nullptr, s);
+    k_var_segments<<<kGrid, kBlk, 0, s>>>(is, w);
+    const bool o2 = dev::sort_pairs<uint32_t>(w.vkey, w.vidx, w.vkey2, w.vidx2, &w.scal[1], n,
+                                              bits_for(n), w.hist, w.rowsum, s);
+    const uint32_t* order = o2 ? w.vidx2 : w.vidx;
+    k_var_ids<<<kGrid, kBlk, 0, s>>>(order, w, case_off, case_code, out);
+    dev::excl_scan<int64_t>(w.lens, &w.scal[1], out.var_off, w.part64, &w.scal[2], s);
+    k_var_emit<<<kGrid, kBlk, 0, s>>>(order, act_s, case_off, w, status_in, out);
+    return hipGetLastError();
+}
+
+}  // namespace pm4g

@@ -1,0 +1,303 @@
+"""Thin Python binding of libpm4g (the C ABI in include/pm4g.h).
+
+Argument marshalling only: torch tensors supply device memory and the
+current HIP stream; every step of the computation runs in the library's HIP
+kernels.  The library is loaded from this package directory; if it is
+missing, every call raises (there is no fallback path).
+
+Entry points mirror the C names: pm4g_prepare, pm4g_dfg, pm4g_dfg_prepared,
+pm4g_variants, pm4g_variants_prepared, pm4g_dfg_batched.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpm4g.so")
+
+PM4G_OK = 0
+PM4G_E_INVALID = -1
+PM4G_E_RANGE = -2
+PM4G_E_NOT_SORTED = -3
+PM4G_E_CAPACITY = -4
+PM4G_E_WORKSPACE = -5
+PM4G_E_DEVICE = -6
+PM4G_PRESORTED = 1
+PM4G_MAX_ACTIVITIES = 4096
+
+OP_PREPARE, OP_DFG, OP_DFG_PREPARED, OP_VARIANTS, OP_VARIANTS_PREPARED, OP_DFG_BATCHED = 1, 2, 3, 4, 5, 6
+
+_P = ctypes.c_void_p
+
+
+class _Log(ctypes.Structure):
+    _fields_ = [("case_id", _P), ("activity", _P), ("timestamp", _P), ("n_events", ctypes.c_int64),
+                ("n_activities", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class _Prepared(ctypes.Structure):
+    _fields_ = [("case_s", _P), ("act_s", _P), ("ts_s", _P), ("case_off", _P), ("case_code", _P),
+                ("n_cases", _P), ("status", _P), ("n_events", ctypes.c_int64),
+                ("n_activities", ctypes.c_int32)]
+
+
+class _DfgOut(ctypes.Structure):
+    _fields_ = [(k, _P) for k in ("count", "dt_sum", "dt_min", "dt_max", "dt_mean", "start_count",
+                                  "end_count", "act_count", "n_cases", "overflow", "status")]
+
+
+class _VarOut(ctypes.Structure):
+    _fields_ = [(k, _P) for k in ("n_variants", "var_count", "var_len", "var_rep", "var_off",
+                                  "var_acts", "case_variant", "status")]
+
+
+class Pm4gError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pm4g error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load():
+    """Loads libpm4g.so (built in-tree by paper_2204_04898_amd.build)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2204_04898_amd.build`")
+            L = ctypes.CDLL(LIB_PATH)
+            L.pm4g_workspace_bytes.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]
+            L.pm4g_workspace_bytes.restype = ctypes.c_size_t
+            for name, argt in (("pm4g_prepare", [ctypes.POINTER(_Log), ctypes.POINTER(_Prepared)]),
+                               ("pm4g_dfg", [ctypes.POINTER(_Log), ctypes.POINTER(_DfgOut)]),
+                               ("pm4g_dfg_prepared", [ctypes.POINTER(_Prepared), ctypes.POINTER(_DfgOut)]),
+                               ("pm4g_variants", [ctypes.POINTER(_Log), ctypes.POINTER(_VarOut)]),
+                               ("pm4g_variants_prepared", [ctypes.POINTER(_Prepared), ctypes.POINTER(_VarOut)])):
+                f = getattr(L, name)
+                f.argtypes = argt + [_P, ctypes.c_size_t, _P]
+                f.restype = ctypes.c_int
+            L.pm4g_status_string.argtypes = [ctypes.c_int]
+            L.pm4g_status_string.restype = ctypes.c_char_p
+            L.pm4g_last_error.argtypes = []
+            L.pm4g_last_error.restype = ctypes.c_char_p
+            L.pm4g_abi_version.restype = ctypes.c_int
+            if hasattr(L, "pm4g_debug_variant_hash_bits"):
+                L.pm4g_debug_variant_hash_bits.argtypes = [ctypes.c_int]
+                L.pm4g_debug_variant_hash_bits.restype = ctypes.c_int
+            _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != PM4G_OK:
+        L = load()
+        raise Pm4gError(rc, L.pm4g_last_error().decode() or L.pm4g_status_string(rc).decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# One growing workspace per (device, stream): keeps allocation out of repeated calls.
+_ws_cache: dict = {}
+
+
+def workspace(op: int, n_events: int, n_activities: int, device, stream=None, n_views: int = 0):
+    need = int(load().pm4g_workspace_bytes(op, n_events, n_activities, n_views))
+    if need == 0:
+        raise Pm4gError(PM4G_E_INVALID, "invalid sizes for the workspace query")
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    key = (torch.device(device).index, s.cuda_stream)
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < need:
+        buf = torch.empty(need, dtype=torch.uint8, device=device)
+        _ws_cache[key] = buf
+    return buf, need
+
+
+def _cols(case, act, ts):
+    for t, dt in ((case, torch.int32), (act, torch.int32), (ts, torch.int64)):
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous() or t.dim() != 1:
+            raise ValueError("case/act must be contiguous 1-D int32 and ts int64 CUDA tensors")
+    if not (case.numel() == act.numel() == ts.numel()):
+        raise ValueError("case, act and ts differ in length")
+
+
+def _log(case, act, ts, A: int, presorted: bool) -> _Log:
+    _cols(case, act, ts)
+    return _Log(_ptr(case), _ptr(act), _ptr(ts), case.numel(), int(A), PM4G_PRESORTED if presorted else 0)
+
+
+@dataclasses.dataclass
+class Prepared:
+    """A prepared (formatted) log in device memory, Sec. 3 formatting steps."""
+
+    case_s: torch.Tensor
+    act_s: torch.Tensor
+    ts_s: torch.Tensor
+    case_off: torch.Tensor
+    case_code: torch.Tensor
+    n_cases: torch.Tensor     # int64 [1]
+    status: torch.Tensor      # int32 [1]
+    n_activities: int
+
+    @property
+    def n_events(self) -> int:
+        return int(self.case_s.numel())
+
+    def _struct(self) -> _Prepared:
+        return _Prepared(_ptr(self.case_s), _ptr(self.act_s), _ptr(self.ts_s), _ptr(self.case_off),
+                         _ptr(self.case_code), _ptr(self.n_cases), _ptr(self.status), self.n_events,
+                         self.n_activities)
+
+    @staticmethod
+    def empty(n: int, A: int, device) -> "Prepared":
+        m = max(n, 1)
+        return Prepared(case_s=torch.empty(n, dtype=torch.int32, device=device),
+                        act_s=torch.empty(n, dtype=torch.int32, device=device),
+                        ts_s=torch.empty(n, dtype=torch.int64, device=device),
+                        case_off=torch.empty(m + 1, dtype=torch.int64, device=device),
+                        case_code=torch.empty(m, dtype=torch.int32, device=device),
+                        n_cases=torch.zeros(1, dtype=torch.int64, device=device),
+                        status=torch.zeros(1, dtype=torch.int32, device=device), n_activities=A)
+
+
+def pm4g_prepare(case, act, ts, A: int, presorted: bool = False, out: Prepared | None = None,
+                 stream=None) -> Prepared:
+    """Formats a raw log on the GPU (order, per-case table).  Synchronises the stream."""
+    log = _log(case, act, ts, A, presorted)
+    if out is None:
+        out = Prepared.empty(case.numel(), A, case.device)
+    ws, need = workspace(OP_PREPARE, case.numel(), A, case.device, stream)
+    p = out._struct()
+    _check(load().pm4g_prepare(ctypes.byref(log), ctypes.byref(p), _ptr(ws), need, _stream(stream)))
+    return out
+
+
+def _dfg_out(A: int, device) -> dict:
+    cells = A * A
+    o = dict(count=torch.empty(cells, dtype=torch.int64, device=device),
+             dt_sum=torch.empty(cells, dtype=torch.int64, device=device),
+             dt_min=torch.empty(cells, dtype=torch.int64, device=device),
+             dt_max=torch.empty(cells, dtype=torch.int64, device=device),
+             dt_mean=torch.empty(cells, dtype=torch.float64, device=device),
+             start_count=torch.empty(A, dtype=torch.int64, device=device),
+             end_count=torch.empty(A, dtype=torch.int64, device=device),
+             act_count=torch.empty(A, dtype=torch.int64, device=device),
+             n_cases=torch.zeros(1, dtype=torch.int64, device=device),
+             overflow=torch.zeros(1, dtype=torch.int32, device=device),
+             status=torch.zeros(1, dtype=torch.int32, device=device))
+    return o
+
+
+def _dfg_struct(o: dict) -> _DfgOut:
+    return _DfgOut(*[_ptr(o.get(k)) for k in ("count", "dt_sum", "dt_min", "dt_max", "dt_mean",
+                                               "start_count", "end_count", "act_count", "n_cases",
+                                               "overflow", "status")])
+
+
+def pm4g_dfg(case, act, ts, A: int, presorted: bool = False, out: dict | None = None,
+             stream=None) -> dict:
+    """DFG of a raw log (formats it in the workspace first).  Synchronises once or twice."""
+    log = _log(case, act, ts, A, presorted)
+    o = out if out is not None else _dfg_out(A, case.device)
+    ws, need = workspace(OP_DFG, case.numel(), A, case.device, stream)
+    s = _dfg_struct(o)
+    _check(load().pm4g_dfg(ctypes.byref(log), ctypes.byref(s), _ptr(ws), need, _stream(stream)))
+    return o
+
+
+def pm4g_dfg_prepared(prep: Prepared, out: dict | None = None, stream=None) -> dict:
+    """DFG of a prepared log.  Asynchronous on the stream."""
+    o = out if out is not None else _dfg_out(prep.n_activities, prep.case_s.device)
+    ws, need = workspace(OP_DFG_PREPARED, prep.n_events, prep.n_activities, prep.case_s.device, stream)
+    p = prep._struct()
+    s = _dfg_struct(o)
+    _check(load().pm4g_dfg_prepared(ctypes.byref(p), ctypes.byref(s), _ptr(ws), need, _stream(stream)))
+    return o
+
+
+def _var_out(n: int, device, with_cases: bool = True) -> dict:
+    m = max(n, 1)
+    return dict(n_variants=torch.zeros(1, dtype=torch.int64, device=device),
+                var_count=torch.empty(m, dtype=torch.int64, device=device),
+                var_len=torch.empty(m, dtype=torch.int32, device=device),
+                var_rep=torch.empty(m, dtype=torch.int32, device=device),
+                var_off=torch.empty(m + 1, dtype=torch.int64, device=device),
+                var_acts=torch.empty(m, dtype=torch.int32, device=device),
+                case_variant=torch.empty(m, dtype=torch.int32, device=device) if with_cases else None,
+                status=torch.zeros(1, dtype=torch.int32, device=device))
+
+
+def _var_struct(o: dict) -> _VarOut:
+    return _VarOut(*[_ptr(o.get(k)) for k in ("n_variants", "var_count", "var_len", "var_rep",
+                                               "var_off", "var_acts", "case_variant", "status")])
+
+
+def pm4g_variants(case, act, ts, A: int, presorted: bool = False, out: dict | None = None,
+                  stream=None) -> dict:
+    """Trace variants of a raw log.  Synchronises once or twice."""
+    log = _log(case, act, ts, A, presorted)
+    o = out if out is not None else _var_out(case.numel(), case.device)
+    ws, need = workspace(OP_VARIANTS, case.numel(), A, case.device, stream)
+    s = _var_struct(o)
+    _check(load().pm4g_variants(ctypes.byref(log), ctypes.byref(s), _ptr(ws), need, _stream(stream)))
+    return o
+
+
+def pm4g_variants_prepared(prep: Prepared, out: dict | None = None, stream=None) -> dict:
+    """Trace variants of a prepared log.  Asynchronous on the stream."""
+    o = out if out is not None else _var_out(prep.n_events, prep.case_s.device)
+    ws, need = workspace(OP_VARIANTS_PREPARED, prep.n_events, prep.n_activities, prep.case_s.device, stream)
+    p = prep._struct()
+    s = _var_struct(o)
+    _check(load().pm4g_variants_prepared(ctypes.byref(p), ctypes.byref(s), _ptr(ws), need, _stream(stream)))
+    return o
+
+
+def debug_variant_hash_bits(bits: int) -> int:
+    """Test hook: truncate the variant hash of this thread's calls to `bits` bits (0 = full)."""
+    return load().pm4g_debug_variant_hash_bits(int(bits))
+
+
+# ---- host views of results (copies to host; for tests and reporting) ------------
+
+def dfg_to_host(o: dict, A: int) -> dict:
+    h = {k: v.cpu().numpy() for k, v in o.items() if v is not None}
+    for k in ("count", "dt_sum", "dt_min", "dt_max", "dt_mean"):
+        h[k] = h[k].reshape(A, A)
+    for k in ("n_cases", "overflow", "status"):
+        h[k] = int(h[k][0])
+    return h
+
+
+def variants_to_host(o: dict, n_cases: int | None = None) -> dict:
+    V = int(o["n_variants"].item())
+    h = dict(n_variants=V, status=int(o["status"].item()))
+    for k in ("var_count", "var_len", "var_rep"):
+        h[k] = o[k][:V].cpu().numpy()
+    h["var_off"] = o["var_off"][:V + 1].cpu().numpy()
+    h["var_acts"] = o["var_acts"][:int(h["var_off"][V])].cpu().numpy()
+    if o.get("case_variant") is not None and n_cases is not None:
+        h["case_variant"] = o["case_variant"][:n_cases].cpu().numpy()
+    return h
+
+
+def prepared_to_host(p: Prepared) -> dict:
+    C = int(p.n_cases.item())
+    return dict(case_s=p.case_s.cpu().numpy(), act_s=p.act_s.cpu().numpy(), ts_s=p.ts_s.cpu().numpy(),
+                case_off=p.case_off[:C + 1].cpu().numpy(), case_code=p.case_code[:C].cpu().numpy(),
+                n_cases=C, status=int(p.status.item()))

@@ -1,0 +1,95 @@
+"""The C-ABI library on the CPU: it loads, exports what include/pm4g.h
+declares, sizes workspaces, and rejects bad arguments before any device work.
+No call here reaches a HIP runtime function (no GPU is needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2204_04898_amd import pm4g
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pm4g.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(pm4g_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pm4g.load()
+    names = declared_functions()
+    assert "pm4g_dfg" in names and "pm4g_variants" in names and "pm4g_prepare" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert lib.pm4g_abi_version() == 1
+
+
+def test_workspace_sizes():
+    lib = pm4g.load()
+    for op in (pm4g.OP_PREPARE, pm4g.OP_DFG, pm4g.OP_DFG_PREPARED, pm4g.OP_VARIANTS,
+               pm4g.OP_VARIANTS_PREPARED):
+        for n, A in ((0, 1), (1, 16), (100_000, 64), (10_000_000, 512), (1000, 4096)):
+            assert lib.pm4g_workspace_bytes(op, n, A, 0) > 0
+    assert lib.pm4g_workspace_bytes(pm4g.OP_DFG, -1, 16, 0) == 0
+    assert lib.pm4g_workspace_bytes(pm4g.OP_DFG, 10, 0, 0) == 0
+    assert lib.pm4g_workspace_bytes(pm4g.OP_DFG, 10, 4097, 0) == 0
+    assert lib.pm4g_workspace_bytes(pm4g.OP_DFG, 2**31, 16, 0) == 0
+    assert lib.pm4g_workspace_bytes(99, 10, 16, 0) == 0
+    # the raw-log DFG needs the formatted log on top of the aggregation space
+    assert lib.pm4g_workspace_bytes(pm4g.OP_DFG, 10**6, 64, 0) > lib.pm4g_workspace_bytes(
+        pm4g.OP_DFG_PREPARED, 10**6, 64, 0)
+
+
+def _fake(n):   # non-NULL host addresses: validation never dereferences them
+    return ctypes.c_void_p(0x1000)
+
+
+def test_validation_before_any_device_work():
+    lib = pm4g.load()
+    out = pm4g._DfgOut(*[_fake(0)] * 11)
+    ws = ctypes.c_void_p(0x1000)
+    # NULL log
+    assert lib.pm4g_dfg(None, ctypes.byref(out), ws, 1 << 40, None) == pm4g.PM4G_E_INVALID
+    assert b"NULL" in lib.pm4g_last_error()
+    log = pm4g._Log(_fake(0), _fake(0), _fake(0), 10, 0, 0)          # A = 0
+    assert lib.pm4g_dfg(ctypes.byref(log), ctypes.byref(out), ws, 1 << 40, None) == pm4g.PM4G_E_INVALID
+    log = pm4g._Log(_fake(0), _fake(0), _fake(0), 10, 4097, 0)       # A too large
+    assert lib.pm4g_dfg(ctypes.byref(log), ctypes.byref(out), ws, 1 << 40, None) == pm4g.PM4G_E_INVALID
+    log = pm4g._Log(_fake(0), _fake(0), _fake(0), -5, 16, 0)         # n < 0
+    assert lib.pm4g_dfg(ctypes.byref(log), ctypes.byref(out), ws, 1 << 40, None) == pm4g.PM4G_E_INVALID
+    log = pm4g._Log(_fake(0), _fake(0), _fake(0), 10, 16, 0x8)       # unknown flag
+    assert lib.pm4g_dfg(ctypes.byref(log), ctypes.byref(out), ws, 1 << 40, None) == pm4g.PM4G_E_INVALID
+    log = pm4g._Log(None, _fake(0), _fake(0), 10, 16, 0)             # NULL column
+    assert lib.pm4g_dfg(ctypes.byref(log), ctypes.byref(out), ws, 1 << 40, None) == pm4g.PM4G_E_INVALID
+    log = pm4g._Log(_fake(0), _fake(0), _fake(0), 10, 16, 0)
+    assert lib.pm4g_dfg(ctypes.byref(log), ctypes.byref(out), ws, 16, None) == pm4g.PM4G_E_WORKSPACE
+    assert b"workspace" in lib.pm4g_last_error()
+    bad = pm4g._DfgOut(*([_fake(0)] * 10 + [None]))                   # NULL status
+    assert lib.pm4g_dfg(ctypes.byref(log), ctypes.byref(bad), ws, 1 << 40, None) == pm4g.PM4G_E_INVALID
+    vout = pm4g._VarOut(*([None] * 8))
+    assert lib.pm4g_variants(ctypes.byref(log), ctypes.byref(vout), ws, 1 << 40, None) == pm4g.PM4G_E_INVALID
+    prep = pm4g._Prepared(_fake(0), _fake(0), _fake(0), None, None, None, None, 10, 16)
+    vout = pm4g._VarOut(*([_fake(0)] * 8))
+    assert lib.pm4g_variants_prepared(ctypes.byref(prep), ctypes.byref(vout), ws, 1 << 40, None) == pm4g.PM4G_E_INVALID
+    p2 = pm4g._Prepared(_fake(0), _fake(0), _fake(0), _fake(0), _fake(0), _fake(0), _fake(0), 10, 16)
+    assert lib.pm4g_prepare(ctypes.byref(log), ctypes.byref(pm4g._Prepared(*([_fake(0)] * 7), 11, 16)),
+                            ws, 1 << 40, None) == pm4g.PM4G_E_INVALID   # n differs
+    assert p2.n_events == 10
+
+
+def test_status_strings():
+    lib = pm4g.load()
+    for code in range(-6, 1):
+        assert lib.pm4g_status_string(code)
+    assert lib.pm4g_status_string(-99) == b"unknown status"
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    monkeypatch.setattr(pm4g, "_lib", None)
+    monkeypatch.setattr(pm4g, "LIB_PATH", "/nonexistent/libpm4g.so")
+    with pytest.raises(RuntimeError, match="missing"):
+        pm4g.load()
