@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Benchmark of the DFG hot path on one MI355X.
+
+One step is the whole path over one synthetic log already resident in HBM:
+format (range scan, case-key radix passes, per-case LDS ordering, case
+table), the frequency/performance DFG with start/end/activity counts and the
+FP64 mean, and the trace variants.  The default workload is the 100M-event
+log (5M cases, lognormal lengths, 512 Zipf activities, ns timestamps,
+shuffled rows).
+
+Prints one JSON line: events/s for the whole step, the roofline of the
+dominant kernel (algorithmic bytes per launch over its HIP-event-timed
+average duration on the launching stream), and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+
+WORKLOADS = {
+    # name: (config index, description)
+    "dfg-variants-100M": (3, "5M cases, ~99M events, lognormal lengths (median 12, max 2000), "
+                             "512 activities (Zipf 1.1 Markov chain), int64 ns timestamps, shuffled rows"),
+    "dfg-perf-10M": (2, "1M cases, ~10M events, geometric lengths (mean 10), 64 activities "
+                        "(Zipf 1.1 Markov chain), int64 ms timestamps with 5% duplicates, shuffled rows"),
+    "dfg-100k-presorted": (1, "10k cases, ~100k events, 16 activities, ms timestamps, rows presorted"),
+}
+
+
+def log_progress(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_bytes(stage: str, n: int, c: int, A: int, presorted: bool) -> float | None:
+    """Algorithmic HBM bytes one launch of a stage must move (reads + writes)."""
+    e = n - c   # directly-follows pairs
+    model = {
+        "range_scan": 8.0 * n + (8.0 * n if presorted else 0.0),      # case + act (+ ts)
+        "radix_hist": 4.0 * n,                                        # case key
+        "radix_scan": None,
+        "radix_scatter": 32.0 * n,                                    # (key, ts, act) in + out
+        "segsort": 32.0 * n,                                          # (key, ts, act) in, (case, act, ts) out
+        "case_table": 8.0 * n + 12.0 * c,                             # case column twice, offsets + codes
+        "dfg_main": 16.0 * n + (10.0 * e if A > 64 else 0.0),         # prepared log (+ bucketed edges)
+        "dfg_agg": 10.0 * e,                                          # bucketed edges
+        "variant_hash": 4.0 * n + 8.0 * c + 12.0 * c,                 # activities, offsets, hash + index
+    }
+    return model.get(stage)
+
+
+def source_sha(files: list[str]) -> str:
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+STAGE_SOURCES = {
+    "radix_scatter": ["paper_2204_04898_amd/csrc/radix.hip", "paper_2204_04898_amd/csrc/common.hpp"],
+    "radix_hist": ["paper_2204_04898_amd/csrc/radix.hip", "paper_2204_04898_amd/csrc/common.hpp"],
+    "segsort": ["paper_2204_04898_amd/csrc/segsort.hip", "paper_2204_04898_amd/csrc/common.hpp"],
+    "dfg_main": ["paper_2204_04898_amd/csrc/dfg.hip", "paper_2204_04898_amd/csrc/common.hpp"],
+    "dfg_agg": ["paper_2204_04898_amd/csrc/dfg.hip", "paper_2204_04898_amd/csrc/common.hpp"],
+}
+
+
+def measured_traffic(stage: str, workload: str) -> float | None:
+    """HBM bytes per launch from the committed counter summary, if it is current.
+
+    profiles/traffic_<stage>_<workload>.txt holds key=value lines written from
+    two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch) and
+    the copy-kernel calibration factor; it is ignored when the kernel's
+    sources changed since (source_sha mismatch).
+    """
+    path = os.path.join(ROOT, "profiles", f"traffic_{stage}_{workload}.txt")
+    if not os.path.exists(path) or stage not in STAGE_SOURCES:
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha") != source_sha(STAGE_SOURCES[stage]):
+        return None
+    try:
+        return float(kv["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(log, target_events: int) -> dict:
+    """The oracle as it stands, single-threaded, on a bounded sample of the same log.
+
+    The sample is every event of the cases whose code is below a cut-off;
+    codes are a random permutation, so it is a random subset of whole cases.
+    """
+    import numpy as np
+
+    import oracle
+
+    C = int(log.lengths_by_code.shape[0])
+    cum = np.cumsum(log.lengths_by_code)
+    cut = int(np.searchsorted(cum, target_events, side="left")) + 1
+    cut = min(cut, C)
+    keep = log.case < cut
+    case, act, ts = log.case[keep], log.act[keep], log.ts[keep]
+    A = log.n_activities
+    t0 = time.perf_counter()
+    oracle.dfg(case, act, ts, A)
+    oracle.variants(case, act, ts, A)
+    dt = time.perf_counter() - t0
+    return {"value": case.size / dt, "unit": "events/s", "cores": 1, "kind": "oracle",
+            "sample": f"the {cut} cases with the lowest codes of the benchmark log ({case.size} events, "
+                      f"rows in log order): DFG + variants, single thread, {dt:.2f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="dfg-variants-100M", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-sample-events", type=int, default=40_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="time prepare + DFG only")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the design for sharding by case is described in DESIGN.md).", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_2204_04898_amd import pm4g, synth
+
+    k, desc = WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    log = synth.config_log(k)
+    N, A = log.n_events, log.n_activities
+    log_progress(f"generated {args.workload}: {N} events, A={A} in {time.perf_counter() - t0:.1f} s")
+
+    dev = torch.device("cuda:0")
+    c = torch.from_numpy(log.case).to(dev)
+    a = torch.from_numpy(log.act).to(dev)
+    t = torch.from_numpy(log.ts).to(dev)
+    prep = pm4g.Prepared.empty(N, A, dev)
+    dout = pm4g._dfg_out(A, dev)
+    vout = pm4g._var_out(N, dev)
+
+    def step():
+        pm4g.pm4g_prepare(c, a, t, A, presorted=log.presorted, out=prep)
+        pm4g.pm4g_dfg_prepared(prep, out=dout)
+        if not args.no_variants:
+            pm4g.pm4g_variants_prepared(prep, out=vout)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log_progress(f"warmup done ({args.warmup} steps)")
+
+    pm4g.profile_enable(True)
+    pm4g.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = pm4g.profile_read()
+    pm4g.profile_enable(False)
+    log_progress(f"timed {args.steps} steps in {t1 - t0:.3f} s")
+
+    C = int(prep.n_cases.item())
+    # validity of the last step: directly-follows pairs = events - cases, one start per case
+    assert int(dout["count"].sum().item()) == N - C, "DFG invariant failed"
+    assert int(dout["start_count"].sum().item()) == C, "start counts invariant failed"
+    if not args.no_variants:
+        assert int(vout["var_count"][: int(vout["n_variants"].item())].sum().item()) == C
+
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    value = N * args.steps / (t1 - t0)
+
+    stages = {name: {"ms_per_step": tot / args.steps, "launches_per_step": cnt / args.steps}
+              for name, (tot, cnt) in prof.items() if cnt}
+    dominant = max(((n, v) for n, v in prof.items() if kernel_bytes(n, N, C, A, log.presorted)),
+                   key=lambda kv: kv[1][0])
+    dname, (dms, dcnt) = dominant
+    per_launch_ms = dms / dcnt
+    algo = kernel_bytes(dname, N, C, A, log.presorted)
+    achieved = algo / (per_launch_ms * 1e-3) / 1e9
+    traffic = measured_traffic(dname, args.workload)
+
+    out = {
+        "metric": "DFG events/sec on 1 MI355X + % HBM roofline",
+        "value": value,
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "n_events": N, "n_cases": C,
+                   "n_activities": A, "step": "prepare + dfg" + ("" if args.no_variants else " + variants")},
+        "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": algo, "avg_launch_ms": per_launch_ms},
+        "stages": stages,
+    }
+    if not args.no_cpu_baseline:
+        log_progress("timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(log, args.cpu_sample_events)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

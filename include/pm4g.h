@@ -218,6 +218,19 @@ const char *pm4g_last_error(void);
  */
 int pm4g_debug_variant_hash_bits(int bits);
 
+/*
+ * Stage timing for measurement: while enabled (process-wide), every stage of
+ * the library records a pair of HIP events on the stream it launches on.
+ * pm4g_profile_read() waits for the recorded events, writes per-stage total
+ * milliseconds and launch counts for stages 0..n_stages-1 (host arrays, may
+ * be NULL) and clears the record.  Stage names: pm4g_profile_stage_name().
+ * Timing adds event records between launches; it is off by default.
+ */
+int pm4g_profile_enable(int on);
+int pm4g_profile_read(double *total_ms, int64_t *launches, int n_stages);
+const char *pm4g_profile_stage_name(int stage);
+int pm4g_profile_stage_count(void);
+
 /* PM4G_ABI_VERSION of the loaded library. */
 int pm4g_abi_version(void);
 

@@ -9,6 +9,7 @@
 // Bytes per event: 4 + 4 read (the column is read twice).
 #include "common.hpp"
 #include "internal.hpp"
+#include "prof.hpp"
 
 namespace pm4g {
 
@@ -79,6 +80,7 @@ __global__ __launch_bounds__(kCB) void k_case_emit(const int32_t* __restrict__ c
 
 hipError_t launch_case_table(const int32_t* case_s, int64_t n, uint32_t* blockcnt, int64_t* case_off,
                              int32_t* case_code, int64_t* n_cases, hipStream_t s) {
+    ProfScope p(P_CASE_TABLE, s);
     const int64_t nb = case_blocks(n);
     if (nb > 0) k_case_count<<<(unsigned)nb, kCB, 0, s>>>(case_s, n, blockcnt);
     k_case_scan<<<1, 1024, 0, s>>>(blockcnt, nb, n, case_off, n_cases);

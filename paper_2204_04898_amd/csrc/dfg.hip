@@ -22,6 +22,7 @@
 
 #include "common.hpp"
 #include "internal.hpp"
+#include "prof.hpp"
 #include "../../include/pm4g.h"
 
 namespace pm4g {
@@ -471,17 +472,31 @@ hipError_t launch_dfg(const int32_t* case_s, const int32_t* act_s, const int64_t
     k_status_init<<<1, 1, 0, s>>>(out.status);
     const int64_t cells = (int64_t)A * A;
     if (A <= kDfgLdsMaxA) {
-        k_dfg_lds<<<kDfgLdsBlocks, kLB, 0, s>>>(case_s, act_s, ts_s, n, A, ws, out.status);
+        {
+            ProfScope p(P_DFG_MAIN, s);
+            k_dfg_lds<<<kDfgLdsBlocks, kLB, 0, s>>>(case_s, act_s, ts_s, n, A, ws, out.status);
+        }
+        ProfScope p(P_DFG_REDUCE, s);
         k_dfg_reduce<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(A, kDfgLdsBlocks, ws, out);
         launch_acts(A, kDfgLdsBlocks, ws, status_in, out, s);
     } else {
         const int64_t nbt = dfg_tiles(n);
         const int64_t nbk = n_buckets(A);
-        k_dfg_part<<<(unsigned)ws.n_act_blocks, kPB, 0, s>>>(case_s, act_s, ts_s, n, A, nbt, nbk, ws,
-                                                             out.status);
-        k_dfg_bucket_scan<<<(unsigned)nbk, 256, 0, s>>>(nbt, ws);
-        k_dfg_plan<<<1, 1024, 0, s>>>(nbk, ws);
-        k_dfg_agg<<<(unsigned)ws.n_slots_max, kAB, 0, s>>>(nbt, ws);
+        {
+            ProfScope p(P_DFG_MAIN, s);
+            k_dfg_part<<<(unsigned)ws.n_act_blocks, kPB, 0, s>>>(case_s, act_s, ts_s, n, A, nbt, nbk,
+                                                                 ws, out.status);
+        }
+        {
+            ProfScope p(P_DFG_PLAN, s);
+            k_dfg_bucket_scan<<<(unsigned)nbk, 256, 0, s>>>(nbt, ws);
+            k_dfg_plan<<<1, 1024, 0, s>>>(nbk, ws);
+        }
+        {
+            ProfScope p(P_DFG_AGG, s);
+            k_dfg_agg<<<(unsigned)ws.n_slots_max, kAB, 0, s>>>(nbt, ws);
+        }
+        ProfScope p(P_DFG_REDUCE, s);
         k_dfg_reduce<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(A, 0, ws, out);
         launch_acts(A, ws.n_act_blocks, ws, status_in, out, s);
     }

@@ -13,6 +13,7 @@
 // Bytes per event per pass: 4 (hist) + 16 read + 16 write.
 #include "common.hpp"
 #include "internal.hpp"
+#include "prof.hpp"
 
 namespace pm4g {
 
@@ -188,8 +189,15 @@ template <int SRC, bool FIRST>
 static void run_pass(SortBufs in, SortBufs out, int64_t n, int shift, const RangeInfo* info,
                      uint32_t* hist, uint32_t* rowsum, hipStream_t s) {
     const int64_t nb = radix_blocks(n);
-    k_radix_hist<SRC, FIRST><<<(unsigned)nb, kRB, 0, s>>>(in, n, shift, info, hist, nb);
-    k_radix_scan<<<256, 256, 0, s>>>(hist, nb, rowsum);
+    {
+        ProfScope p(P_RADIX_HIST, s);
+        k_radix_hist<SRC, FIRST><<<(unsigned)nb, kRB, 0, s>>>(in, n, shift, info, hist, nb);
+    }
+    {
+        ProfScope p(P_RADIX_SCAN, s);
+        k_radix_scan<<<256, 256, 0, s>>>(hist, nb, rowsum);
+    }
+    ProfScope p(P_RADIX_SCATTER, s);
     k_radix_scatter<SRC, FIRST><<<(unsigned)nb, kRB, 0, s>>>(in, out, n, shift, info, hist, rowsum, nb);
 }
 

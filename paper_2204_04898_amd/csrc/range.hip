@@ -6,6 +6,7 @@
 // timestamp.  Per-wave reductions, then one atomic per wave per extreme.
 #include "common.hpp"
 #include "internal.hpp"
+#include "prof.hpp"
 #include "../../include/pm4g.h"
 
 namespace pm4g {
@@ -90,6 +91,7 @@ static int range_grid(int64_t n) {
 
 hipError_t launch_range_scan(const int32_t* case_id, const int32_t* act, const int64_t* ts, int64_t n,
                              int32_t A, bool presorted, bool want_ts, RangeInfo* info, hipStream_t s) {
+    ProfScope p(P_RANGE, s);
     k_range_init<<<1, 1, 0, s>>>(info);
     if (n > 0) {
         const int g = range_grid(n);

@@ -15,6 +15,7 @@
 // Bytes per event: 16 read + 16 write.
 #include "common.hpp"
 #include "internal.hpp"
+#include "prof.hpp"
 
 namespace pm4g {
 
@@ -205,6 +206,7 @@ static unsigned copy_grid(int64_t n) {
 
 hipError_t launch_segsort(SortBufs in, int64_t n, RangeInfo* info, int32_t* case_s, int32_t* act_s,
                           int64_t* ts_s, hipStream_t s) {
+    ProfScope p(P_SEGSORT, s);
     if (n > 0) k_segsort<<<(unsigned)segsort_blocks(n), kSB, 0, s>>>(in, n, info, case_s, act_s, ts_s);
     return hipGetLastError();
 }

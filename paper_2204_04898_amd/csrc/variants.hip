@@ -20,6 +20,7 @@
 #include "common.hpp"
 #include "devsort.hpp"
 #include "internal.hpp"
+#include "prof.hpp"
 #include "../../include/pm4g.h"
 
 namespace pm4g {
@@ -247,22 +248,37 @@ hipError_t launch_variants(const int32_t* act_s, const int64_t* case_off, const 
                               ? 0ull
                               : ((uint64_t(1) << debug_hash_bits) - 1);
     k_var_init<<<1, 1, 0, s>>>(w, n_cases);
-    k_var_hash<<<kGrid, kBlk, 0, s>>>(act_s, case_off, w, mask);
-    const bool in2 = dev::sort_pairs<uint64_t>(w.hash, w.idx, w.hash2, w.idx2, &w.scal[0], n, 64, w.hist,
-                                               w.rowsum, s);
+    {
+        ProfScope p(P_VAR_HASH, s);
+        k_var_hash<<<kGrid, kBlk, 0, s>>>(act_s, case_off, w, mask);
+    }
+    bool in2;
+    {
+        ProfScope p(P_VAR_SORT, s);
+        in2 = dev::sort_pairs<uint64_t>(w.hash, w.idx, w.hash2, w.idx2, &w.scal[0], n, 64, w.hist,
+                                        w.rowsum, s);
+    }
     const uint64_t* hs = in2 ? w.hash2 : w.hash;
     uint32_t* is = in2 ? w.idx2 : w.idx;
-    k_var_verify<<<kGrid, kBlk, 0, s>>>(hs, is, act_s, case_off, w);
-    k_var_fix<<<kGrid, kBlk, 0, s>>>(hs, is, act_s, case_off, w);
-    // group index of every group start; V
-    dev::excl_scan<uint32_t>(w.flag, &w.scal[0], w.sid, w.part32, &w.u32scal[1], s);
-    k_var_groups<<<kGrid, kBlk, 0, s>>>(is, w);
-    // representative-order index of every representative case
-    dev::excl_scan<uint32_t>(w.repflag, &w.scal[0], w.rrank, w.part32, (uint32_t*)nullptr, s);
-    k_var_segments<<<kGrid, kBlk, 0, s>>>(is, w);
-    const bool o2 = dev::sort_pairs<uint32_t>(w.vkey, w.vidx, w.vkey2, w.vidx2, &w.scal[1], n,
-                                              bits_for(n), w.hist, w.rowsum, s);
+    {
+        ProfScope p(P_VAR_GROUP, s);
+        k_var_verify<<<kGrid, kBlk, 0, s>>>(hs, is, act_s, case_off, w);
+        k_var_fix<<<kGrid, kBlk, 0, s>>>(hs, is, act_s, case_off, w);
+        // group index of every group start; V
+        dev::excl_scan<uint32_t>(w.flag, &w.scal[0], w.sid, w.part32, &w.u32scal[1], s);
+        k_var_groups<<<kGrid, kBlk, 0, s>>>(is, w);
+        // representative-order index of every representative case
+        dev::excl_scan<uint32_t>(w.repflag, &w.scal[0], w.rrank, w.part32, (uint32_t*)nullptr, s);
+        k_var_segments<<<kGrid, kBlk, 0, s>>>(is, w);
+    }
+    bool o2;
+    {
+        ProfScope p(P_VAR_ORDER, s);
+        o2 = dev::sort_pairs<uint32_t>(w.vkey, w.vidx, w.vkey2, w.vidx2, &w.scal[1], n, bits_for(n),
+                                       w.hist, w.rowsum, s);
+    }
     const uint32_t* order = o2 ? w.vidx2 : w.vidx;
+    ProfScope p(P_VAR_EMIT, s);
     k_var_ids<<<kGrid, kBlk, 0, s>>>(order, w, case_off, case_code, out);
     dev::excl_scan<int64_t>(w.lens, &w.scal[1], out.var_off, w.part64, &w.scal[2], s);
     k_var_emit<<<kGrid, kBlk, 0, s>>>(order, act_s, case_off, w, status_in, out);

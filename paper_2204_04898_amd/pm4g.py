@@ -89,6 +89,13 @@ def load():
             L.pm4g_last_error.argtypes = []
             L.pm4g_last_error.restype = ctypes.c_char_p
             L.pm4g_abi_version.restype = ctypes.c_int
+            L.pm4g_profile_enable.argtypes = [ctypes.c_int]
+            L.pm4g_profile_enable.restype = ctypes.c_int
+            L.pm4g_profile_read.argtypes = [_P, _P, ctypes.c_int]
+            L.pm4g_profile_read.restype = ctypes.c_int
+            L.pm4g_profile_stage_name.argtypes = [ctypes.c_int]
+            L.pm4g_profile_stage_name.restype = ctypes.c_char_p
+            L.pm4g_profile_stage_count.restype = ctypes.c_int
             if hasattr(L, "pm4g_debug_variant_hash_bits"):
                 L.pm4g_debug_variant_hash_bits.argtypes = [ctypes.c_int]
                 L.pm4g_debug_variant_hash_bits.restype = ctypes.c_int
@@ -271,6 +278,21 @@ def pm4g_variants_prepared(prep: Prepared, out: dict | None = None, stream=None)
 def debug_variant_hash_bits(bits: int) -> int:
     """Test hook: truncate the variant hash of this thread's calls to `bits` bits (0 = full)."""
     return load().pm4g_debug_variant_hash_bits(int(bits))
+
+
+def profile_enable(on: bool) -> bool:
+    """Turns the library's per-stage HIP-event timing on or off."""
+    return bool(load().pm4g_profile_enable(1 if on else 0))
+
+
+def profile_read() -> dict:
+    """{stage name: (total ms, launches)} since the last read; waits for the events."""
+    L = load()
+    n = L.pm4g_profile_stage_count()
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    _check(L.pm4g_profile_read(ctypes.cast(ms, _P), ctypes.cast(cnt, _P), n))
+    return {L.pm4g_profile_stage_name(i).decode(): (ms[i], cnt[i]) for i in range(n)}
 
 
 # ---- host views of results (copies to host; for tests and reporting) ------------

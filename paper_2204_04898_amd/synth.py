@@ -63,46 +63,69 @@ def markov_chain(A: int, law: str, rng: np.random.Generator):
     return pi0, P
 
 
-def _sample_rows(cum_flat: np.ndarray, A: int, prev: np.ndarray, u: np.ndarray) -> np.ndarray:
-    # cum_flat holds row r's cumulative distribution shifted by r, so one
-    # searchsorted samples every row at once (inverse-CDF sampling).
-    idx = np.searchsorted(cum_flat, prev.astype(np.float64) + u, side="right")
-    nxt = idx - prev.astype(np.int64) * A
-    return np.clip(nxt, 0, A - 1).astype(np.int32)
+def alias_table(p: np.ndarray):
+    """Walker/Vose alias table of one distribution: (prob, alias)."""
+    A = p.shape[0]
+    scaled = p * A
+    prob = np.ones(A)
+    alias = np.arange(A)
+    small = [i for i in range(A) if scaled[i] < 1.0]
+    large = [i for i in range(A) if scaled[i] >= 1.0]
+    while small and large:
+        s_, l_ = small.pop(), large.pop()
+        prob[s_] = scaled[s_]
+        alias[s_] = l_
+        scaled[l_] -= 1.0 - scaled[s_]
+        (small if scaled[l_] < 1.0 else large).append(l_)
+    return prob, alias
+
+
+def _sample_alias(prob: np.ndarray, alias: np.ndarray, rows: np.ndarray, u: np.ndarray) -> np.ndarray:
+    # one uniform: its integer part picks a column, its fraction accepts it or its alias
+    A = prob.shape[1]
+    x = u * A
+    j = np.minimum(x.astype(np.int64), A - 1)
+    keep = (x - j) < prob[rows, j]
+    return np.where(keep, j, alias[rows, j]).astype(np.int32)
 
 
 def markov_sequences(lengths: np.ndarray, pi0: np.ndarray, P: np.ndarray,
                      rng: np.random.Generator) -> np.ndarray:
-    """Activities of every case, case-major: case k occupies off[k]..off[k]+L_k."""
+    """Activities of every case, case-major: case k occupies off[k]..off[k]+L_k.
+
+    The chain is advanced position by position over the cases still running
+    (longest first), stored position-major so each step reads and writes one
+    contiguous block; one gather then lays the sequences out case by case.
+    """
     A = P.shape[0]
     C = lengths.shape[0]
     N = int(lengths.sum())
+    if N == 0:
+        return np.zeros(0, np.int32)
+    order = np.argsort(-lengths, kind="stable")   # longest cases first
+    rank = np.empty(C, np.int64)
+    rank[order] = np.arange(C)
+    sorted_len = lengths[order]
+    max_len = int(sorted_len[0])
+    # n_k = cases with L > k, for k = 0 .. max_len-1
+    n_k = np.searchsorted(-sorted_len, -np.arange(max_len), side="left")
+    block = np.zeros(max_len + 1, np.int64)
+    np.cumsum(n_k, out=block[1:])
+    tables = [alias_table(P[r]) for r in range(A)]
+    prob = np.stack([t[0] for t in tables])
+    alias = np.stack([t[1] for t in tables])
+    p0, a0 = alias_table(pi0)
+    pm = np.empty(N, np.int32)
+    n0 = int(n_k[0])
+    pm[:n0] = _sample_alias(p0[None, :], a0[None, :], np.zeros(n0, np.int64), rng.random(n0))
+    for k in range(1, max_len):
+        n = int(n_k[k])
+        prev = pm[block[k - 1]:block[k - 1] + n]
+        pm[block[k]:block[k] + n] = _sample_alias(prob, alias, prev, rng.random(n))
     off = np.zeros(C + 1, dtype=np.int64)
     np.cumsum(lengths, out=off[1:])
-    acts = np.empty(N, dtype=np.int32)
-    order = np.argsort(-lengths, kind="stable")   # longest cases first
-    sorted_len = lengths[order]
-    starts = off[:-1][order]
-    cum0 = np.cumsum(pi0)
-    cum0[-1] = 1.0
-    cum = np.cumsum(P, axis=1)
-    cum[:, -1] = 1.0
-    cum_flat = (cum + np.arange(A, dtype=np.float64)[:, None]).ravel()
-    n_active = int(np.count_nonzero(sorted_len > 0))
-    if n_active:
-        u = rng.random(n_active)
-        first = np.searchsorted(cum0, u, side="right")
-        acts[starts[:n_active]] = np.clip(first, 0, A - 1).astype(np.int32)
-    k = 1
-    while True:
-        n_active = int(np.searchsorted(-sorted_len, -k, side="left"))  # cases with L > k
-        if n_active == 0:
-            break
-        pos = starts[:n_active] + k
-        prev = acts[pos - 1]
-        acts[pos] = _sample_rows(cum_flat, A, prev, rng.random(n_active))
-        k += 1
-    return acts
+    within = np.arange(N, dtype=np.int64) - np.repeat(off[:-1], lengths)
+    return pm[block[within] + np.repeat(rank, lengths)]
 
 
 def make_log(*, n_cases: int, length_law: str, A: int, act_law: str, unit: str,

@@ -420,3 +420,32 @@ def test_generators_are_seeded_and_shaped():
     assert int(c.lengths_by_code.max()) <= 2000
     one = synth.config_log(1, 1.0)
     assert 95_000 < one.n_events < 105_000 and one.presorted
+
+
+def test_generator_markov_chain_frequencies():
+    """The sampled sequences follow pi0 and P (alias sampling), within 5 sigma."""
+    rng = np.random.default_rng(123)
+    A = 6
+    pi0, P = synth.markov_chain(A, "zipf", rng)
+    lengths = rng.geometric(0.2, size=60_000).astype(np.int64)
+    acts = synth.markov_sequences(lengths, pi0, P, rng)
+    off = np.zeros(lengths.size + 1, np.int64)
+    np.cumsum(lengths, out=off[1:])
+    first = acts[off[:-1]]
+    f0 = np.bincount(first, minlength=A) / first.size
+    assert np.all(np.abs(f0 - pi0) < 5 * np.sqrt(pi0 * (1 - pi0) / first.size) + 1e-9)
+    nonfirst = np.ones(acts.size, bool)
+    nonfirst[off[:-1]] = False
+    idx = np.flatnonzero(nonfirst)
+    prev, nxt = acts[idx - 1], acts[idx]
+    T = np.zeros((A, A))
+    np.add.at(T, (prev, nxt), 1)
+    rows = T.sum(axis=1, keepdims=True)
+    emp = T / rows
+    sd = np.sqrt(P * (1 - P) / rows)
+    assert np.all(np.abs(emp - P) < 5 * sd + 1e-9)
+    for r in range(A):
+        pr, al = synth.alias_table(P[r])
+        q = pr / A
+        np.add.at(q, al, (1 - pr) / A)
+        assert np.allclose(q, P[r], atol=1e-12)
