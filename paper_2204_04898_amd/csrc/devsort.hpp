@@ -18,28 +18,38 @@ constexpr int kW = kB / kWave;
 
 inline int64_t tiles(int64_t nmax) { return (nmax + kTile - 1) / kTile; }
 
+constexpr int kMaxGrid = 2048;   // persistent blocks; tiles are visited grid-stride
+
+inline unsigned grid_for(int64_t nb) { return (unsigned)(nb < kMaxGrid ? (nb < 1 ? 1 : nb) : kMaxGrid); }
+
+// hist is digit-major with row stride nb (an upper bound); only the first
+// ceil(n/kTile) tiles of each row are written and scanned.
 template <typename K>
 __global__ __launch_bounds__(kB) void k_hist(const K* __restrict__ key, const int64_t* n_dev, int shift,
                                              uint32_t* hist, int64_t nb) {
     __shared__ uint32_t h[256];
-    if (threadIdx.x < 256) h[threadIdx.x] = 0;
-    __syncthreads();
     const int64_t n = *n_dev;
-    const int64_t base = (int64_t)blockIdx.x * kTile;
-    if (base < n) {
+    const int64_t tiles_n = (n + kTile - 1) / kTile;
+    for (int64_t tile = blockIdx.x; tile < tiles_n; tile += gridDim.x) {
+        if (threadIdx.x < 256) h[threadIdx.x] = 0;
+        __syncthreads();
+        const int64_t base = tile * kTile;
 #pragma unroll
         for (int k = 0; k < kI; ++k) {
             const int64_t i = base + k * kB + threadIdx.x;
             if (i < n) atomicAdd(&h[(uint32_t)(key[i] >> shift) & 255u], 1u);
         }
+        __syncthreads();
+        if (threadIdx.x < 256) hist[(int64_t)threadIdx.x * nb + tile] = h[threadIdx.x];
+        __syncthreads();
     }
-    __syncthreads();
-    if (threadIdx.x < 256) hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
-__global__ __launch_bounds__(256) void k_hist_scan(uint32_t* hist, int64_t nb, uint32_t* rowsum) {
+__global__ __launch_bounds__(256) void k_hist_scan(uint32_t* hist, const int64_t* n_dev, int64_t nb_stride,
+                                                   uint32_t* rowsum) {
     __shared__ uint32_t tmp[256 / kWave + 1];
-    uint32_t* row = hist + (int64_t)blockIdx.x * nb;
+    const int64_t nb = (*n_dev + kTile - 1) / kTile;
+    uint32_t* row = hist + (int64_t)blockIdx.x * nb_stride;
     uint32_t run = 0;
     for (int64_t c0 = 0; c0 < nb; c0 += 256 * 4) {
         uint32_t v[4];
@@ -76,71 +86,75 @@ __global__ __launch_bounds__(kB) void k_scatter(const K* __restrict__ kin, const
     __shared__ uint32_t tmp[kB / kWave + 1];
 
     const int64_t n = *n_dev;
-    const int64_t tile0 = (int64_t)blockIdx.x * kTile;
-    if (tile0 >= n) return;   // block-uniform
+    const int64_t tiles_n = (n + kTile - 1) / kTile;
     const int w = threadIdx.x / kWave;
-    const int64_t wbase = tile0 + (int64_t)w * (kWave * kI);
-    for (int i = threadIdx.x; i < kW * 256; i += kB) cnt[i] = 0;
-
-    K key[kI];
-    uint32_t val[kI], dg[kI], rk[kI];
-#pragma unroll
-    for (int k = 0; k < kI; ++k) {
-        const int64_t i = wbase + k * kWave + lane();
-        key[k] = i < n ? kin[i] : K(0);
-        val[k] = i < n ? vin[i] : 0u;
-        dg[k] = (uint32_t)(key[k] >> shift) & 255u;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kI; ++k) {
-        const int64_t i = wbase + k * kWave + lane();
-        const bool valid = i < n;
-        const uint64_t active = __ballot(valid);
-        const uint64_t peers = match_digit8(dg[k], active);
-        const uint32_t below = __popcll(peers & lanes_below());
-        uint32_t c = 0;
-        if (valid) c = cnt[w * 256 + dg[k]];
-        rk[k] = c + below;
-        if (valid && below == 0) cnt[w * 256 + dg[k]] = c + __popcll(peers);
-    }
-    __syncthreads();
-    uint32_t tot = 0;
-    if (threadIdx.x < 256) {
-        uint32_t run = 0;
-        for (int ww = 0; ww < kW; ++ww) {
-            const uint32_t x = cnt[ww * 256 + threadIdx.x];
-            cnt[ww * 256 + threadIdx.x] = run;
-            run += x;
-        }
-        tot = run;
-    }
     uint32_t all;
-    const uint32_t ts_excl = block_excl_sum<kB>(tot, tmp, &all);
     const uint32_t rs = threadIdx.x < 256 ? rowsum[threadIdx.x] : 0u;
     const uint32_t digit_base = block_excl_sum<kB>(rs, tmp, &all);
-    if (threadIdx.x < 256) {
-        tstart[threadIdx.x] = ts_excl;
-        gshift[threadIdx.x] =
-            (int64_t)digit_base + (int64_t)hist[(int64_t)threadIdx.x * nb + blockIdx.x] - (int64_t)ts_excl;
-    }
-    __syncthreads();
+
+    for (int64_t tile = blockIdx.x; tile < tiles_n; tile += gridDim.x) {
+        const int64_t tile0 = tile * kTile;
+        const int64_t wbase = tile0 + (int64_t)w * (kWave * kI);
+        for (int i = threadIdx.x; i < kW * 256; i += kB) cnt[i] = 0;
+
+        K key[kI];
+        uint32_t val[kI], dg[kI], rk[kI];
 #pragma unroll
-    for (int k = 0; k < kI; ++k) {
-        const int64_t i = wbase + k * kWave + lane();
-        if (i < n) {
-            const uint32_t pos = tstart[dg[k]] + cnt[w * 256 + dg[k]] + rk[k];
-            skey[pos] = key[k];
-            sval[pos] = val[k];
+        for (int k = 0; k < kI; ++k) {
+            const int64_t i = wbase + k * kWave + lane();
+            key[k] = i < n ? kin[i] : K(0);
+            val[k] = i < n ? vin[i] : 0u;
+            dg[k] = (uint32_t)(key[k] >> shift) & 255u;
         }
-    }
-    __syncthreads();
-    const int64_t vc = (n - tile0) < kTile ? (n - tile0) : kTile;
-    for (int i = threadIdx.x; i < vc; i += kB) {
-        const K k = skey[i];
-        const int64_t g = gshift[(uint32_t)(k >> shift) & 255u] + i;
-        kout[g] = k;
-        vout[g] = sval[i];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kI; ++k) {
+            const int64_t i = wbase + k * kWave + lane();
+            const bool valid = i < n;
+            const uint64_t active = __ballot(valid);
+            const uint64_t peers = match_digit8(dg[k], active);
+            const uint32_t below = __popcll(peers & lanes_below());
+            uint32_t c = 0;
+            if (valid) c = cnt[w * 256 + dg[k]];
+            rk[k] = c + below;
+            if (valid && below == 0) cnt[w * 256 + dg[k]] = c + __popcll(peers);
+        }
+        __syncthreads();
+        uint32_t tot = 0;
+        if (threadIdx.x < 256) {
+            uint32_t run = 0;
+            for (int ww = 0; ww < kW; ++ww) {
+                const uint32_t x = cnt[ww * 256 + threadIdx.x];
+                cnt[ww * 256 + threadIdx.x] = run;
+                run += x;
+            }
+            tot = run;
+        }
+        const uint32_t ts_excl = block_excl_sum<kB>(tot, tmp, &all);
+        if (threadIdx.x < 256) {
+            tstart[threadIdx.x] = ts_excl;
+            gshift[threadIdx.x] =
+                (int64_t)digit_base + (int64_t)hist[(int64_t)threadIdx.x * nb + tile] - (int64_t)ts_excl;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kI; ++k) {
+            const int64_t i = wbase + k * kWave + lane();
+            if (i < n) {
+                const uint32_t pos = tstart[dg[k]] + cnt[w * 256 + dg[k]] + rk[k];
+                skey[pos] = key[k];
+                sval[pos] = val[k];
+            }
+        }
+        __syncthreads();
+        const int64_t vc = (n - tile0) < kTile ? (n - tile0) : kTile;
+        for (int i = threadIdx.x; i < vc; i += kB) {
+            const K k = skey[i];
+            const int64_t g = gshift[(uint32_t)(k >> shift) & 255u] + i;
+            kout[g] = k;
+            vout[g] = sval[i];
+        }
+        __syncthreads();
     }
 }
 
@@ -157,9 +171,9 @@ inline bool sort_pairs(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const int64_t* 
         uint32_t* vi = flip ? v1 : v0;
         K* ko = flip ? k0 : k1;
         uint32_t* vo = flip ? v0 : v1;
-        k_hist<K><<<(unsigned)nb, kB, 0, s>>>(ki, n_dev, shift, hist, nb);
-        k_hist_scan<<<256, 256, 0, s>>>(hist, nb, rowsum);
-        k_scatter<K><<<(unsigned)nb, kB, 0, s>>>(ki, vi, ko, vo, n_dev, shift, hist, rowsum, nb);
+        k_hist<K><<<grid_for(nb), kB, 0, s>>>(ki, n_dev, shift, hist, nb);
+        k_hist_scan<<<256, 256, 0, s>>>(hist, n_dev, nb, rowsum);
+        k_scatter<K><<<grid_for(nb), kB, 0, s>>>(ki, vi, ko, vo, n_dev, shift, hist, rowsum, nb);
         flip = !flip;
     }
     return flip;

@@ -54,8 +54,8 @@ hipError_t launch_radix_pass(SortBufs in, SortBufs out, int64_t n, int digit_src
                              hipStream_t s);
 
 // ---- per-case ordering of a case-grouped sequence (segsort.hip) ----
-constexpr int kSegWindow = 2048;
-constexpr int kSegCap = 4096;
+constexpr int kSegWindow = 1024;
+constexpr int kSegCap = 3072;   // window + the longest case kept on the fast path (2049) - 1
 inline int64_t segsort_blocks(int64_t n) { return (n + kSegWindow - 1) / kSegWindow; }
 hipError_t launch_segsort(SortBufs in, int64_t n, RangeInfo* info, int32_t* case_s, int32_t* act_s,
                           int64_t* ts_s, hipStream_t s);

@@ -3,11 +3,15 @@
 //
 // Input: the radix output, grouped by case, each case's events in row order
 // (the passes are stable).  Block w owns the cases that START inside window
-// [w*2048, (w+1)*2048); their events (at most 2048 + 2048 = 4096 when no case
-// is longer than 2049 events) are staged in LDS.  Each event's rank inside its
-// case is counted against the other events of the case: rank = #{j in case :
-// t_j < t_i or (t_j == t_i and j before i)}.  Lanes of a wave hold adjacent
-// events, so they walk the same case and the LDS reads are broadcasts.
+// [w*1024, (w+1)*1024); their events (at most 1023 + 2049 = 3072 when no case
+// is longer than 2049 events) are staged in LDS.  The staged region is cut
+// into 64-event chunks; each wave sorts its chunks in registers with a
+// bitonic network on (case, timestamp, staging position) -- the staging
+// position is the row order inside a case.  A case that fits in one chunk is
+// then ordered; a case spanning k chunks has k sorted portions, and an event's
+// rank in its case is its rank in its own portion plus, for each other
+// portion, the number of smaller events found by binary search:
+// O(L/64 * log 64) comparisons per event instead of O(L).
 // A region longer than the LDS window sets RangeInfo::long_case and the
 // host switches to the full-key fallback.
 //
@@ -20,7 +24,7 @@
 namespace pm4g {
 
 constexpr int kSB = 512;
-constexpr int kSI = kSegCap / kSB;   // 8 items per thread
+constexpr int kSI = kSegCap / kSB;   // 6 items per thread
 
 __device__ __forceinline__ int64_t block_min_i64(int64_t v, int64_t* red) {
     v = wave_min(v);
@@ -54,6 +58,7 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
     __shared__ uint32_t lkey[kSegCap];
     __shared__ int64_t lts[kSegCap];
     __shared__ uint16_t lact[kSegCap];
+    __shared__ uint16_t lidx[kSegCap];   // staging position of the event now at i
     __shared__ uint16_t lcs[kSegCap];
     __shared__ uint16_t lce[kSegCap + 1];
     __shared__ int64_t red[kSB / kWave + 1];
@@ -134,7 +139,45 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
     }
     __syncthreads();
 
-    // 5. rank inside the case (striped: a wave holds 64 adjacent events)
+    // 5. sort every 64-event chunk in registers by (case, ts, staging position)
+    {
+        const int w = threadIdx.x / kWave;
+        const int l = lane();
+        for (int ch = w; ch * kWave < R; ch += kSB / kWave) {
+            const int i = ch * kWave + l;
+            uint32_t k = 0xFFFFFFFFu, id = 0x10000u + (uint32_t)l;   // padding sorts last
+            int64_t t = INT64_MAX;
+            if (i < R) {
+                k = lkey[i];
+                t = lts[i];
+                id = (uint32_t)i;
+            }
+#pragma unroll
+            for (int m = 2; m <= kWave; m <<= 1) {
+#pragma unroll
+                for (int j = m >> 1; j > 0; j >>= 1) {
+                    const uint32_t pk = __shfl_xor(k, j);
+                    const int64_t pt = __shfl_xor(t, j);
+                    const uint32_t pid = __shfl_xor(id, j);
+                    // branch-free compare-exchange: keep the partner iff it belongs here
+                    const bool pless = (pk < k) | ((pk == k) & ((pt < t) | ((pt == t) & (pid < id))));
+                    const bool flip = ((l & m) == 0) != ((l & j) == 0);
+                    const bool take = pless != flip;
+                    k = take ? pk : k;
+                    t = take ? pt : t;
+                    id = take ? pid : id;
+                }
+            }
+            if (i < R) {
+                lkey[i] = k;   // unchanged: the chunk was already grouped by case
+                lts[i] = t;
+                lidx[i] = (uint16_t)id;
+            }
+        }
+    }
+    __syncthreads();
+
+    // 6. rank inside the case: own portion + binary searches in the other portions
     int32_t pos[kSI];
     uint32_t kv[kSI];
     int64_t tv[kSI];
@@ -147,15 +190,26 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
             const int cs = lcs[i];
             const int ce = lce[cs];
             const int64_t t = lts[i];
-            int r = 0;
-            for (int j = cs; j < ce; ++j) {
-                const int64_t tj = lts[j];
-                r += (tj < t) | ((tj == t) & (j < i));
+            const uint32_t id = lidx[i];
+            const int ch = i >> 6;
+            int r = i - (cs > (ch << 6) ? cs : (ch << 6));
+            const int c_last = (ce - 1) >> 6;
+            for (int c2 = cs >> 6; c2 <= c_last; ++c2) {
+                if (c2 == ch) continue;
+                const int p0 = cs > (c2 << 6) ? cs : (c2 << 6);
+                int lo = p0, hi = ce < (c2 << 6) + kWave ? ce : (c2 << 6) + kWave;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    const int64_t tm = lts[mid];
+                    if (tm < t || (tm == t && (uint32_t)lidx[mid] < id)) lo = mid + 1;
+                    else hi = mid;
+                }
+                r += lo - p0;
             }
             pos[q] = cs + r;
             kv[q] = lkey[i];
             tv[q] = t;
-            av[q] = lact[i];
+            av[q] = lact[id];
         }
     }
     __syncthreads();
@@ -169,7 +223,7 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
     }
     __syncthreads();
 
-    // 6. write the prepared columns
+    // 7. write the prepared columns
     const uint32_t bias = (uint32_t)info->case_min;
     for (int i = threadIdx.x; i < R; i += kSB) {
         case_s[s + i] = (int32_t)(lkey[i] + bias);

@@ -8,7 +8,8 @@
 // than one sequence is regrouped exactly.  Variant ids follow (count desc,
 // representative asc) with the representative the smallest case id.
 //
-//   k_var_hash       per case: length-seeded FNV-1a over the activities, mixed
+//   k_var_hash       per case: sum over positions of mix(position, activity), mixed
+//                    with the length (wave-cooperative, coalesced)
 //   radix (64 bits)  cases by hash; stable, so equal hashes keep case order
 //   k_var_verify     neighbour sequences compared exactly -> group starts
 //   k_var_fix        only after a true collision: exact regrouping of a run
@@ -84,19 +85,60 @@ __global__ void k_var_init(VarWs w, const int64_t* n_cases) {
     }
 }
 
+// Wave-cooperative walk over 64 consecutive segments: lane m holds the
+// virtual start of segment m (INT64_MAX if absent); returns the segment that
+// contains virtual position p (the last m with start_m <= p).  Starts are
+// strictly increasing (segments are non-empty) and p >= start_0.  Must be
+// called with all 64 lanes active (the shuffles read every lane).
+__device__ __forceinline__ int seg_of(int64_t vstart, int64_t p) {
+    int lo = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+        const int cand = lo + step;
+        if (__shfl(vstart, cand) <= p) lo = cand;
+    }
+    return lo;
+}
+
+// Sequence hash of every case: a sum over positions of mix(position, activity)
+// (order-sensitive, computable in any order), mixed with the length.  A wave
+// takes 64 consecutive cases and walks their events coalesced.
 __global__ __launch_bounds__(kBlk) void k_var_hash(const int32_t* __restrict__ act_s,
                                                    const int64_t* __restrict__ case_off, VarWs w,
                                                    uint64_t mask) {
+    __shared__ unsigned long long hsum[kBlk / kWave][kWave];
     const int64_t C = w.scal[0];
-    for (int64_t c = (int64_t)blockIdx.x * kBlk + threadIdx.x; c < C; c += (int64_t)gridDim.x * kBlk) {
-        const int64_t o0 = case_off[c], o1 = case_off[c + 1];
-        uint64_t h = 0xcbf29ce484222325ull ^ mix64((uint64_t)(o1 - o0));
-        for (int64_t k = o0; k < o1; ++k) h = (h ^ (uint64_t)(uint32_t)(act_s[k] + 1)) * 0x100000001b3ull;
-        h = mix64(h);
-        if (mask) h &= mask;
-        w.hash[c] = h;
-        w.idx[c] = (uint32_t)c;
-        w.repflag[c] = 0;
+    const int wl = threadIdx.x / kWave;
+    const int64_t wv = ((int64_t)blockIdx.x * kBlk + threadIdx.x) / kWave;
+    const int64_t nw = (int64_t)gridDim.x * kBlk / kWave;
+    for (int64_t c0 = wv * kWave; c0 < C; c0 += nw * kWave) {
+        const int64_t c = c0 + lane();
+        const bool has = c < C;
+        const int64_t st = has ? case_off[c] : INT64_MAX;
+        const int64_t en = has ? case_off[c + 1] : 0;
+        hsum[wl][lane()] = 0;
+        const int last = (C - 1 - c0) < (kWave - 1) ? (int)(C - 1 - c0) : (kWave - 1);
+        const int64_t base = __shfl(st, 0);
+        const int64_t end = __shfl(en, last);
+        // wave-uniform trip count: every lane takes part in the shuffles
+        for (int64_t p0 = base; p0 < end; p0 += kWave) {
+            const int64_t p = p0 + lane();
+            const int m = seg_of(st, p);
+            const int64_t s_m = __shfl(st, m);
+            if (p < end) {
+                const uint64_t pos = (uint64_t)(p - s_m);
+                const uint64_t term =
+                    mix64((pos << 13) + (uint64_t)(uint32_t)act_s[p] + 0x632be59bd9b4e019ull);
+                atomicAdd(&hsum[wl][m], (unsigned long long)term);
+            }
+        }
+        if (has) {
+            uint64_t h = mix64((uint64_t)hsum[wl][lane()] ^ mix64((uint64_t)(en - st) + 0x9e3779b97f4a7c15ull));
+            if (mask) h &= mask;
+            w.hash[c] = h;
+            w.idx[c] = (uint32_t)c;
+            w.repflag[c] = 0;
+        }
     }
 }
 
@@ -209,18 +251,37 @@ __global__ __launch_bounds__(kBlk) void k_var_ids(const uint32_t* __restrict__ o
     }
 }
 
+// Sequences in final order: a wave takes 64 consecutive variants and copies
+// their representatives' activities, writes coalesced over the output range.
 __global__ __launch_bounds__(kBlk) void k_var_emit(const uint32_t* __restrict__ order,
                                                    const int32_t* __restrict__ act_s,
                                                    const int64_t* __restrict__ case_off, VarWs w,
                                                    const int32_t* status_in, VarOutDev out) {
     const int64_t C = w.scal[0];
     const int64_t V = w.scal[1];
-    for (int64_t k = (int64_t)blockIdx.x * kBlk + threadIdx.x; k < V; k += (int64_t)gridDim.x * kBlk) {
-        const uint32_t r = w.vrepcase[order[k]];
-        const int64_t o0 = case_off[r];
-        const int64_t L = case_off[r + 1] - o0;
-        const int64_t d = out.var_off[k];
-        for (int64_t j = 0; j < L; ++j) out.var_acts[d + j] = act_s[o0 + j];
+    const int64_t wv = ((int64_t)blockIdx.x * kBlk + threadIdx.x) / kWave;
+    const int64_t nw = (int64_t)gridDim.x * kBlk / kWave;
+    for (int64_t k0 = wv * kWave; k0 < V; k0 += nw * kWave) {
+        const int64_t k = k0 + lane();
+        const bool has = k < V;
+        int64_t src = 0, dst = INT64_MAX, len = 0;
+        if (has) {
+            const uint32_t r = w.vrepcase[order[k]];
+            src = case_off[r];
+            len = case_off[r + 1] - src;
+            dst = out.var_off[k];
+        }
+        const int last = (V - 1 - k0) < (kWave - 1) ? (int)(V - 1 - k0) : (kWave - 1);
+        const int64_t base = __shfl(dst, 0);
+        const int64_t end = __shfl(dst + len, last);
+        // wave-uniform trip count: every lane takes part in the shuffles
+        for (int64_t p0 = base; p0 < end; p0 += kWave) {
+            const int64_t p = p0 + lane();
+            const int m = seg_of(dst, p);
+            const int64_t s_m = __shfl(src, m);
+            const int64_t d_m = __shfl(dst, m);
+            if (p < end) out.var_acts[p] = act_s[s_m + (p - d_m)];
+        }
     }
     if (out.case_variant) {
         for (int64_t c = (int64_t)blockIdx.x * kBlk + threadIdx.x; c < C; c += (int64_t)gridDim.x * kBlk)
