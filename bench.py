@@ -126,6 +126,73 @@ def cpu_baseline(log, target_events: int) -> dict:
                       f"rows in log order): DFG + variants, single thread, {dt:.2f} s"}
 
 
+def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int) -> dict:
+    """Batched drill-down views over the prepared log: one call for all views,
+    against a loop of one-view calls of the same entry point."""
+    import numpy as np
+    import torch
+
+    from paper_2204_04898_amd import pm4g, synth
+
+    views = synth.make_views(log, n_views, seed=synth.SEED_BASE + 4)
+    visits = int(np.sum([log.lengths_by_code[views.case_lo[v]:views.case_hi[v]].sum() for v in range(n_views)]))
+    vd, md = pm4g.views_to_device(views, prep.case_s.device)
+    t0 = time.perf_counter()
+    out = pm4g.pm4g_dfg_batched(prep, vd, md, n_views)          # sizes the capacities (retries)
+    log_progress(f"views: first call (capacity sizing) {time.perf_counter() - t0:.2f} s")
+    req = [int(x) for x in out["required"].cpu().tolist()]
+    tune = pm4g.BatchedTuning(pair_capacity=int(req[3] * 1.1) + 1024, record_capacity=int(req[1] * 1.1) + 1024,
+                              descriptor_capacity=int(req[2] * 1.1) + 1024, cell_capacity=int(req[4] * 1.1) + 1024)
+    out = pm4g.pm4g_dfg_batched(prep, vd, md, n_views, tuning=tune, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pm4g.pm4g_dfg_batched(prep, vd, md, n_views, tuning=tune, out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    # per-view launches of the same entry point on a sample of the views
+    idx = np.linspace(0, n_views - 1, per_view_sample).astype(int)
+    one_t = pm4g.BatchedTuning(pair_capacity=int(req[3]) + 1024, record_capacity=int(req[1]) + 1024,
+                               descriptor_capacity=int(req[2]) + 1024, cell_capacity=int(req[4]) + 1024)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for v in idx:
+        pm4g.pm4g_dfg_batched(prep, vd[v * 24:(v + 1) * 24], md[v:v + 1], 1, tuning=one_t)
+    torch.cuda.synchronize()
+    per_view_s = (time.perf_counter() - t1) / len(idx)
+    return {"views_per_s": n_views / dt, "ms_per_call": dt * 1e3, "n_views": n_views,
+            "event_view_visits": visits, "output_cells": req[0], "records": req[1],
+            "per_view_launch_views_per_s": 1.0 / per_view_s,
+            "per_view_launch_sample": len(idx),
+            "speedup_vs_per_view_launches": per_view_s * n_views / dt}
+
+
+def bench_serving(logs: dict, preps: dict, seconds: float, rate: float) -> dict:
+    """Open-loop Poisson mix of DFG / variants / filter queries on resident logs."""
+    import copy
+
+    import numpy as np
+
+    from paper_2204_04898_amd import serve
+
+    info = {k: serve.log_info(v) for k, v in logs.items()}
+    A_of = {k: v.n_activities for k, v in logs.items()}
+    reqs = serve.poisson_requests(np.random.default_rng(220404898 + 5), rate, seconds, info, A_of)
+    ex = serve.GpuExecutor(preps)
+    free, _total = __import__("torch").cuda.mem_get_info()
+    budget = int(free * 0.5)
+    # warm the executor's workspaces
+    serve.Scheduler(ex, budget, max_batch=64, workers=2).run(copy.deepcopy(reqs[:16]))
+    sch = serve.Scheduler(ex, budget, max_batch=64, workers=2)
+    res = sch.run(copy.deepcopy(reqs))
+    st = serve.latency_stats(res)
+    st.update(offered_qps=rate, seconds=seconds, n_requests=len(reqs), batches=len(sch.batches))
+    base = serve.Scheduler(ex, budget, max_batch=1, workers=1)
+    bres = base.run(copy.deepcopy(reqs))
+    st["one_request_per_launch"] = serve.latency_stats(bres)
+    return st
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +202,11 @@ def main() -> int:
     ap.add_argument("--cpu-sample-events", type=int, default=40_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="time prepare + DFG only")
+    ap.add_argument("--views", type=int, default=4096, help="batched drill-down views (0: skip)")
+    ap.add_argument("--view-steps", type=int, default=3)
+    ap.add_argument("--per-view-sample", type=int, default=64)
+    ap.add_argument("--serve-seconds", type=float, default=8.0, help="serving run length (0: skip)")
+    ap.add_argument("--serve-qps", type=float, default=200.0)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -224,6 +296,18 @@ def main() -> int:
                      "algorithmic_bytes_per_launch": algo, "avg_launch_ms": per_launch_ms},
         "stages": stages,
     }
+    if args.views > 0 and k == 3:
+        log_progress(f"batched views: {args.views} views")
+        out["batched_views"] = bench_views(log, prep, args.views, args.view_steps, args.per_view_sample)
+    if args.serve_seconds > 0 and k == 3:
+        log_progress("serving: generating the 10M-event log")
+        log2 = synth.config_log(2)
+        c2, a2, t2 = (torch.from_numpy(x).to(dev) for x in (log2.case, log2.act, log2.ts))
+        prep2 = pm4g.pm4g_prepare(c2, a2, t2, log2.n_activities)
+        log_progress(f"serving: {args.serve_seconds} s at {args.serve_qps} queries/s")
+        out["serving"] = bench_serving({"dfg-perf-10M": log2, args.workload: log},
+                                       {"dfg-perf-10M": prep2, args.workload: prep},
+                                       args.serve_seconds, args.serve_qps)
     if not args.no_cpu_baseline:
         log_progress("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(log, args.cpu_sample_events)

@@ -49,6 +49,7 @@ extern "C" {
 
 #define PM4G_ABI_VERSION 1
 #define PM4G_MAX_ACTIVITIES 4096
+#define PM4G_BATCHED_MAX_ACTIVITIES 1024
 
 /* Return and status codes. */
 enum {
@@ -171,6 +172,71 @@ typedef struct {
 } pm4g_variants_out;
 
 /*
+ * A drill-down view (Sec. 1 "smaller views on the dataset"; Sec. 3 event-level
+ * timestamp filter and activity-attribute filter).  Event i is kept iff
+ * case_lo <= case_id_i < case_hi, t_lo <= timestamp_i <= t_hi and bit
+ * activity_i of the view's mask is set; the view's DFG is re-discovered on
+ * the kept events (a kept event is paired with the previous kept event of
+ * its case).  24 bytes, naturally aligned.
+ */
+typedef struct {
+    int32_t case_lo;
+    int32_t case_hi;
+    int64_t t_lo;
+    int64_t t_hi;
+} pm4g_view;
+
+/*
+ * Outputs of pm4g_dfg_batched for n_views views over A activities.
+ *   edge_off[v]..edge_off[v+1]-1   view v's non-empty DFG cells, ordered by
+ *                                  (src, dst): src, dst, count, dt_sum,
+ *                                  dt_min, dt_max, dt_mean (mean may be NULL)
+ *                                  in arrays of cap_edges entries
+ *   start_count, end_count, act_count   [n_views * A], row v for view v
+ *   n_events, n_cases                   [n_views] kept events and cases
+ *   required   device int64[5]: output cells, internal records, internal run
+ *              descriptors, (tile, view) pairs and internal aggregated cells
+ *              the call needed
+ *   status     device status word (PM4G_E_CAPACITY if cap_edges was short)
+ */
+typedef struct {
+    int64_t *edge_off;
+    int32_t *src;
+    int32_t *dst;
+    int64_t *count;
+    int64_t *dt_sum;
+    int64_t *dt_min;
+    int64_t *dt_max;
+    double *dt_mean;
+    int64_t *start_count;
+    int64_t *end_count;
+    int64_t *act_count;
+    int64_t *n_events;
+    int64_t *n_cases;
+    int64_t cap_edges;
+    int64_t *required;
+    int32_t *status;
+} pm4g_batched_out;
+
+/*
+ * Launch shape and internal capacities of pm4g_dfg_batched (NULL or zero
+ * fields: defaults).  tile_events is 2048 or 4096 (events of the log staged
+ * per block); emit_blocks and agg_blocks are grid sizes; the capacities size
+ * the workspace: (tile, view) pairs, records (one per kept event), run
+ * descriptors and aggregated cells (before compaction into the output).
+ */
+typedef struct {
+    int32_t tile_events;
+    int32_t emit_blocks;
+    int32_t agg_blocks;
+    int32_t reserved;
+    int64_t pair_capacity;
+    int64_t record_capacity;
+    int64_t descriptor_capacity;
+    int64_t cell_capacity;
+} pm4g_batched_tuning;
+
+/*
  * Bytes of workspace an operation needs for a log of n_events events and
  * n_activities activities (n_views for PM4G_OP_DFG_BATCHED, else ignored).
  * Returns 0 for invalid arguments.
@@ -202,6 +268,39 @@ int pm4g_variants(const pm4g_log *log, const pm4g_variants_out *out, void *ws, s
 /* Variants of a prepared log.  Does not synchronise. */
 int pm4g_variants_prepared(const pm4g_prepared *log, const pm4g_variants_out *out, void *ws,
                            size_t ws_bytes, void *stream);
+
+/*
+ * DFGs of many drill-down views of one prepared log in one pass over the log
+ * (views: device array of n_views records; act_masks: device array of
+ * n_views * ceil(A/64) words, bit a of word a/64 of row v selects activity a
+ * for view v).  Requires A <= PM4G_BATCHED_MAX_ACTIVITIES.  Synchronises
+ * `stream` twice to check the internal capacities; returns PM4G_E_CAPACITY
+ * (and fills out->required) when a pair, record or descriptor capacity of
+ * `tuning` is too small: call again with larger capacities.  The cell and
+ * output capacities (cell_capacity, cap_edges) are checked on the device and
+ * reported in out->status and out->required.
+ */
+size_t pm4g_batched_workspace_bytes(int64_t n_events, int32_t n_activities, int32_t n_views,
+                                    const pm4g_batched_tuning *tuning);
+int pm4g_dfg_batched(const pm4g_prepared *log, const pm4g_view *views, const uint64_t *act_masks,
+                     int32_t n_views, const pm4g_batched_out *out, const pm4g_batched_tuning *tuning,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * One drill-down view (device record `view`, device mask of ceil(A/64)
+ * words) of a prepared log, materialised as a prepared log of the kept
+ * events, in their (case, timestamp, row) order, with its case table
+ * (Sec. 3 event-level timestamp filter and activity filter on the formatted
+ * log).  out->n_events is the capacity of out's arrays; if the view's case
+ * range holds more events, nothing is kept and out->status is
+ * PM4G_E_CAPACITY.  The kept count is out->case_off[*out->n_cases], on the
+ * device.  The result can be
+ * given to pm4g_variants_prepared (which only reads the case ranges).  Does
+ * not synchronise.
+ */
+size_t pm4g_filter_workspace_bytes(int64_t n_events);
+int pm4g_filter_view(const pm4g_prepared *log, const pm4g_view *view, const uint64_t *act_mask,
+                     const pm4g_prepared *out, void *ws, size_t ws_bytes, void *stream);
 
 /* Text for a status code (static storage). */
 const char *pm4g_status_string(int code);

@@ -42,6 +42,49 @@ void set_err(const char* fmt, ...) {
 constexpr int64_t kMaxEvents = (int64_t(1) << 31) - 1;
 
 __global__ void k_set_status(int32_t* status, int32_t code) { *status = code; }
+__global__ void k_set_required(int64_t* req, int64_t pairs, int64_t records, int64_t descs, int32_t* status) {
+    req[1] = records;
+    req[2] = descs;
+    req[3] = pairs;
+    *status = PM4G_E_CAPACITY;
+}
+
+struct BatchedTune {
+    int tile, emit_blocks, agg_blocks;
+    int64_t pair_cap, rec_cap, desc_cap, cell_cap;
+};
+
+int resolve_tuning(const pm4g_batched_tuning* t, int64_t n, int32_t V, BatchedTune* r) {
+    if (t && t->tile_events != 0 && t->tile_events != 2048 && t->tile_events != 4096) {
+        set_err("tile_events must be 2048 or 4096 (0: default)");
+        return PM4G_E_INVALID;
+    }
+    if (t && (t->emit_blocks < 0 || t->agg_blocks < 0 || t->emit_blocks > 65535 || t->agg_blocks > 65535 ||
+              t->pair_capacity < 0 || t->record_capacity < 0 || t->descriptor_capacity < 0 ||
+              t->cell_capacity < 0)) {
+        set_err("negative or oversized tuning field");
+        return PM4G_E_INVALID;
+    }
+    r->tile = (t && t->tile_events) ? t->tile_events : 4096;
+    r->emit_blocks = (t && t->emit_blocks) ? t->emit_blocks : 512;
+    r->agg_blocks = (t && t->agg_blocks) ? t->agg_blocks : 512;
+    const int64_t tiles = (n + r->tile - 1) / r->tile;
+    r->pair_cap = (t && t->pair_capacity) ? t->pair_capacity : 4 * (tiles + V) + 1024;
+    r->rec_cap = (t && t->record_capacity) ? t->record_capacity : (n > 4096 ? n : 4096);
+    r->desc_cap = (t && t->descriptor_capacity) ? t->descriptor_capacity : 8 * r->pair_cap;
+    r->cell_cap = (t && t->cell_capacity) ? t->cell_capacity : (r->rec_cap / 2 > 4096 ? r->rec_cap / 2 : 4096);
+    if (r->desc_cap > (int64_t)0xFFFFFFF0 || r->pair_cap > (int64_t)0xFFFFFFF0) {
+        set_err("descriptor and pair capacities must stay below 2^32");
+        return PM4G_E_INVALID;
+    }
+    return PM4G_OK;
+}
+
+size_t batched_ws_bytes(int64_t n, int32_t A, int32_t V, const BatchedTune& t) {
+    Bump b(nullptr);
+    view_ws_layout(b, n, A, V, t.tile, t.pair_cap, t.rec_cap, t.desc_cap, t.cell_cap);
+    return b.off + 256;
+}
 
 // Workspace of the formatting step.
 struct PrepWs {
@@ -268,10 +311,97 @@ const char* pm4g_status_string(int code) {
 }
 
 size_t pm4g_workspace_bytes(int op, int64_t n_events, int32_t n_activities, int32_t n_views) {
-    (void)n_views;
     if (n_events < 0 || n_events > kMaxEvents) return 0;
     if (n_activities < 1 || n_activities > PM4G_MAX_ACTIVITIES) return 0;
+    if (op == PM4G_OP_DFG_BATCHED) return pm4g_batched_workspace_bytes(n_events, n_activities, n_views, nullptr);
     return ws_bytes(op, n_events, n_activities);
+}
+
+size_t pm4g_batched_workspace_bytes(int64_t n_events, int32_t n_activities, int32_t n_views,
+                                    const pm4g_batched_tuning* tuning) {
+    if (n_events < 0 || n_events > kMaxEvents || n_views < 0) return 0;
+    if (n_activities < 1 || n_activities > PM4G_BATCHED_MAX_ACTIVITIES) return 0;
+    BatchedTune t;
+    if (resolve_tuning(tuning, n_events, n_views, &t) != PM4G_OK) return 0;
+    return batched_ws_bytes(n_events, n_activities, n_views, t);
+}
+
+size_t pm4g_filter_workspace_bytes(int64_t n_events) {
+    if (n_events < 0 || n_events > kMaxEvents) return 0;
+    Bump b(nullptr);
+    filter_ws_layout(b, n_events);
+    return b.off + 256;
+}
+
+int pm4g_filter_view(const pm4g_prepared* log, const pm4g_view* view, const uint64_t* act_mask,
+                     const pm4g_prepared* out, void* ws, size_t ws_size, void* stream) {
+    if (int rc = check_prepared(log, true)) return rc;
+    PM4G_CHECK(view && act_mask, "view or act_mask is NULL");
+    PM4G_CHECK(out && out->case_off && out->n_cases && out->status &&
+                   (log->n_events == 0 || (out->case_s && out->act_s && out->ts_s && out->case_code)),
+               "a filtered-log output array is NULL");
+    PM4G_CHECK(out->n_events >= 0 && out->n_activities == log->n_activities,
+               "the filtered log needs a capacity >= 0 and the same n_activities");
+    const size_t need = pm4g_filter_workspace_bytes(log->n_events);
+    if (ws_size < need || !ws) {
+        set_err("workspace of %zu bytes, %zu needed", ws_size, need);
+        return PM4G_E_WORKSPACE;
+    }
+    Bump bp(ws);
+    FilterWs w = filter_ws_layout(bp, log->n_events);
+    PM4G_HIP(launch_filter_view(log, view, act_mask, out, w, (hipStream_t)stream));
+    return PM4G_OK;
+}
+
+int pm4g_dfg_batched(const pm4g_prepared* log, const pm4g_view* views, const uint64_t* act_masks,
+                     int32_t n_views, const pm4g_batched_out* out, const pm4g_batched_tuning* tuning,
+                     void* ws, size_t ws_size, void* stream) {
+    if (int rc = check_prepared(log, true)) return rc;
+    PM4G_CHECK(log->n_activities <= PM4G_BATCHED_MAX_ACTIVITIES, "n_activities %d above %d for batched views",
+               log->n_activities, PM4G_BATCHED_MAX_ACTIVITIES);
+    PM4G_CHECK(n_views >= 0, "n_views < 0");
+    PM4G_CHECK(n_views == 0 || (views && act_masks), "views or act_masks is NULL");
+    PM4G_CHECK(out && out->edge_off && out->start_count && out->end_count && out->act_count && out->n_events &&
+                   out->n_cases && out->required && out->status && out->cap_edges >= 0 &&
+                   (out->cap_edges == 0 ||
+                    (out->src && out->dst && out->count && out->dt_sum && out->dt_min && out->dt_max)),
+               "a batched output array is NULL (only dt_mean may be NULL)");
+    BatchedTune t;
+    if (int rc = resolve_tuning(tuning, log->n_events, n_views, &t)) return rc;
+    const size_t need = batched_ws_bytes(log->n_events, log->n_activities, n_views, t);
+    if (ws_size < need || !ws) {
+        set_err("workspace of %zu bytes, %zu needed", ws_size, need);
+        return PM4G_E_WORKSPACE;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    Bump bp(ws);
+    ViewWs w = view_ws_layout(bp, log->n_events, log->n_activities, n_views, t.tile, t.pair_cap, t.rec_cap,
+                              t.desc_cap, t.cell_cap);
+    const BatchedOutDev o{out->edge_off, out->src, out->dst, out->count, out->dt_sum, out->dt_min,
+                          out->dt_max, out->dt_mean, out->start_count, out->end_count, out->act_count,
+                          out->n_events, out->n_cases, out->cap_edges, out->required, out->status};
+    PM4G_HIP(launch_views_plan(log, views, n_views, w, o, s));
+    int64_t sc[8];
+    PM4G_HIP(hipMemcpyAsync(sc, w.scal, sizeof(sc), hipMemcpyDeviceToHost, s));
+    PM4G_HIP(hipStreamSynchronize(s));
+    if (sc[7] > t.pair_cap) {
+        k_set_required<<<1, 1, 0, s>>>(out->required, sc[7], 0, 0, out->status);
+        PM4G_HIP(hipGetLastError());
+        set_err("%lld (tile, view) pairs, pair_capacity %lld", (long long)sc[7], (long long)t.pair_cap);
+        return PM4G_E_CAPACITY;
+    }
+    PM4G_HIP(launch_views_emit(log, views, act_masks, w, t.emit_blocks, s));
+    PM4G_HIP(hipMemcpyAsync(sc, w.scal, sizeof(sc), hipMemcpyDeviceToHost, s));
+    PM4G_HIP(hipStreamSynchronize(s));
+    if (sc[0] > t.rec_cap || sc[1] > t.desc_cap) {
+        k_set_required<<<1, 1, 0, s>>>(out->required, sc[7], sc[0], sc[1], out->status);
+        PM4G_HIP(hipGetLastError());
+        set_err("%lld records (capacity %lld), %lld descriptors (capacity %lld)", (long long)sc[0],
+                (long long)t.rec_cap, (long long)sc[1], (long long)t.desc_cap);
+        return PM4G_E_CAPACITY;
+    }
+    PM4G_HIP(launch_views_reduce(log, n_views, w, o, t.agg_blocks, s));
+    return PM4G_OK;
 }
 
 int pm4g_prepare(const pm4g_log* log, const pm4g_prepared* out, void* ws, size_t ws_size,

@@ -1,6 +1,6 @@
 // Device-sized building blocks: the element count lives in device memory
-// (it is data-dependent, e.g. the number of cases), grids are sized by a
-// host-side upper bound and surplus blocks do no work.
+// (it is data-dependent, e.g. the number of cases); persistent grids visit
+// only the tiles that hold data.
 //   - stable LSD radix sort of (key, u32 value) pairs, 8-bit digits,
 //     ballot ranking in wave64, LDS staging (same scheme as radix.hip);
 //   - exclusive prefix sum, reduce-then-scan over a fixed grid.
@@ -8,8 +8,12 @@
 
 #include "common.hpp"
 
+#pragma clang diagnostic ignored "-Wunneeded-internal-declaration"
+
 namespace pm4g {
 namespace dev {
+// internal linkage: every including file gets its own kernels
+namespace {
 
 constexpr int kB = 512;
 constexpr int kI = 8;
@@ -241,5 +245,6 @@ inline void excl_scan(const uint32_t* in, const int64_t* n_dev, T* out, T* parti
     k_scan_apply<T><<<kScanGrid, 256, 0, s>>>(in, n_dev, partial, out);
 }
 
+}  // namespace
 }  // namespace dev
 }  // namespace pm4g

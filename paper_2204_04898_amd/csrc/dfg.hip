@@ -29,7 +29,7 @@ namespace pm4g {
 
 constexpr int kLB = 1024;   // threads of k_dfg_lds
 constexpr int kPB = 512;    // threads of k_dfg_part
-constexpr int kAB = 512;    // threads of k_dfg_agg
+constexpr int kAB = 1024;   // threads of k_dfg_agg
 
 static int64_t dfg_tiles(int64_t n) { return (n + kDfgTile - 1) / kDfgTile; }
 static int64_t n_buckets(int32_t A) {

@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/pm4g.h"
+
 namespace pm4g {
 
 // Device header written by the range scan and read back by the host.
@@ -165,5 +167,85 @@ struct VarOutDev {
 hipError_t launch_variants(const int32_t* act_s, const int64_t* case_off, const int32_t* case_code,
                            const int64_t* n_cases, const int32_t* status_in, int64_t n, VarWs ws,
                            VarOutDev out, uint32_t debug_hash_bits, hipStream_t s);
+
+// ---- batched views (views.hip) ----
+struct ViewWs {
+    int32_t tile;
+    int32_t n_buckets;
+    int64_t n_tiles;
+    int64_t pair_cap, rec_cap, desc_cap, cell_cap;
+    int64_t* p0;            // [V] event slice of each view
+    int64_t* p1;
+    uint32_t* tcount;       // [tiles + 2] overlapping views per tile
+    uint32_t* toff;         // [tiles + 2]
+    uint32_t* tcursor;      // [tiles + 2]
+    uint32_t* list;         // [pair_cap] views of each tile
+    int64_t* scal;          // cursors and totals
+    uint32_t* part32;
+    int64_t* part64;
+    uint16_t* rec_cell;     // [rec_cap] records: cell within its bucket, gap
+    uint64_t* rec_gap;
+    uint32_t* d_view;       // [desc_cap] run descriptors
+    int64_t* d_off;
+    uint32_t* d_cnt;
+    uint32_t* d_key;        // (view, bucket) sort keys, ping-pong with d_key2
+    uint32_t* d_key2;
+    uint32_t* d_idx;
+    uint32_t* d_idx2;
+    uint32_t* d_hist;
+    uint32_t* d_rowsum;
+    uint32_t* seg_flag;     // segment starts in the sorted descriptors
+    uint32_t* seg_id;
+    uint32_t* seg_start;
+    uint32_t* seg_cells;    // non-empty pair cells per segment
+    int64_t* seg_tmp;       // their place in the temporary cell arrays
+    int64_t* seg_out;       // their place in the output lists
+    uint32_t* view_cells;   // [V] non-empty pair cells per view
+    uint32_t* t_cell;       // [rec_cap] temporary aggregated cells
+    uint32_t* t_count;
+    uint64_t* t_sum;
+    int64_t* t_min;
+    int64_t* t_max;
+};
+int64_t view_buckets(int32_t A);
+ViewWs view_ws_layout(Bump& b, int64_t n, int32_t A, int32_t V, int32_t tile, int64_t pair_cap,
+                      int64_t rec_cap, int64_t desc_cap, int64_t cell_cap);
+struct BatchedOutDev {
+    int64_t* edge_off;
+    int32_t* src;
+    int32_t* dst;
+    int64_t* count;
+    int64_t* dt_sum;
+    int64_t* dt_min;
+    int64_t* dt_max;
+    double* dt_mean;
+    int64_t* start_count;
+    int64_t* end_count;
+    int64_t* act_count;
+    int64_t* n_events;
+    int64_t* n_cases;
+    int64_t cap_edges;
+    int64_t* required;
+    int32_t* status;
+};
+// ---- one view as a prepared log (filter.hip) ----
+constexpr int kFilterTile = 4096;
+struct FilterWs {
+    int64_t* scal;
+    uint32_t* tile_cnt;
+    int64_t* tile_off;
+    int64_t* part64;
+    uint32_t* caseblk;
+};
+FilterWs filter_ws_layout(Bump& b, int64_t n);
+hipError_t launch_filter_view(const pm4g_prepared* p, const pm4g_view* view, const uint64_t* mask,
+                              const pm4g_prepared* out, FilterWs w, hipStream_t s);
+
+hipError_t launch_views_plan(const pm4g_prepared* p, const pm4g_view* views, int32_t V, ViewWs w,
+                             BatchedOutDev out, hipStream_t s);
+hipError_t launch_views_emit(const pm4g_prepared* p, const pm4g_view* views, const uint64_t* masks,
+                             ViewWs w, int grid, hipStream_t s);
+hipError_t launch_views_reduce(const pm4g_prepared* p, int32_t V, ViewWs w, BatchedOutDev out, int agg_grid,
+                               hipStream_t s);
 
 }  // namespace pm4g

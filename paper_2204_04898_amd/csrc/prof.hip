@@ -11,7 +11,9 @@ namespace {
 const char* kNames[P_COUNT] = {
     "range_scan",   "radix_hist", "radix_scan", "radix_scatter", "segsort",
     "case_table",   "dfg_main",   "dfg_plan",   "dfg_agg",       "dfg_reduce",
-    "variant_hash", "variant_sort", "variant_group", "variant_order", "variant_emit"};
+    "variant_hash", "variant_sort", "variant_group", "variant_order", "variant_emit",
+    "view_plan",    "view_emit",  "view_sort",  "view_agg",      "view_out",
+    "view_filter"};
 
 struct Rec {
     int id;

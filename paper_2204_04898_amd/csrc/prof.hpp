@@ -23,6 +23,12 @@ enum ProfId {
     P_VAR_GROUP,
     P_VAR_ORDER,
     P_VAR_EMIT,
+    P_VIEW_PLAN,
+    P_VIEW_EMIT,
+    P_VIEW_SORT,
+    P_VIEW_AGG,
+    P_VIEW_OUT,
+    P_VIEW_FILTER,
     P_COUNT
 };
 

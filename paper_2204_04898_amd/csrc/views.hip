@@ -1,0 +1,686 @@
+// Batched drill-down views over a prepared log (Sec. 1 drill-down: "smaller
+// views on the dataset"; Sec. 3: event-level timestamp filter, attribute
+// filter on the activity, and the DFG re-discovered on what is kept).
+//
+// A view v keeps event i iff case_lo <= c_i < case_hi, t_lo <= t_i <= t_hi and
+// bit a_i of its activity mask is set.  Its DFG pairs each kept event with the
+// previous kept event of the same case.  Every kept event is either the first
+// kept event of its case (a start) or the destination of exactly one pair, and
+// either the last one (an end) or the source of exactly one pair, so
+//   act_count(y) = start(y) + sum_x count(x, y),  end(x) = act_count(x) - sum_y count(x, y).
+//
+// Pipeline (sizes stay on the device; two host synchronisations read the
+// pair and record totals to check capacities):
+//   k_view_slice     case range -> event slice [p0, p1) (binary search in the
+//                    case table); a slice always holds whole cases
+//   k_view_tile_scan per-tile counts of overlapping views, offsets
+//   k_view_fill      per-tile lists of overlapping views
+//   k_view_emit      tile-major: a block stages one tile of the log in LDS;
+//                    each wave takes one overlapping view and walks the tile 64
+//                    events at a time: ballots give the previous kept event of
+//                    the same case, carried across windows and (by a backward
+//                    search) across tiles.  A pair gives a record (cell = x*A+y,
+//                    gap); a start gives (A*A + y, 0).  The walk runs twice:
+//                    count per cell bucket (cell >> 12), reserve, write runs;
+//                    one descriptor per (tile, view, bucket) run.
+//   radix sort       descriptors by (view, bucket)
+//   k_view_agg       one block per (view, bucket) segment: 4096-cell LDS table;
+//                    non-empty pair cells -> temporary sparse records, start
+//                    cells -> start counts
+//   scans, copy      per-view lists ordered by (src, dst), offsets, FP64 mean
+//   k_view_acts      per view: activity and end counts from the start counts
+//                    and the row / column sums
+#include <math.h>
+
+#include "common.hpp"
+#include "devsort.hpp"
+#include "internal.hpp"
+#include "prof.hpp"
+#include "../../include/pm4g.h"
+
+namespace pm4g {
+
+namespace {
+
+constexpr int kVB = 1024;                 // threads per emit block (16 waves)
+constexpr int kVW = kVB / kWave;
+constexpr int kMaxBuckets = 264;          // >= ceil(1024 * 1025 / 4096) = 257
+constexpr int kMaskWords = PM4G_BATCHED_MAX_ACTIVITIES / 64;
+constexpr int kAB2 = 1024;                // threads per aggregation block
+
+__device__ __forceinline__ int hi_bit(uint64_t m) { return 63 - __clzll((long long)m); }
+
+}  // namespace
+
+int64_t view_buckets(int32_t A) {
+    return ((int64_t)A * (A + 1) + kCellsPerTable - 1) / kCellsPerTable;
+}
+
+ViewWs view_ws_layout(Bump& b, int64_t n, int32_t A, int32_t V, int32_t tile, int64_t pair_cap,
+                      int64_t rec_cap, int64_t desc_cap, int64_t cell_cap) {
+    ViewWs w{};
+    const size_t cc = (size_t)(cell_cap > 0 ? cell_cap : 1);
+    w.cell_cap = cell_cap;
+    const int64_t tiles = (n + tile - 1) / tile;
+    const size_t vm = (size_t)(V > 0 ? V : 1);
+    const size_t rc = (size_t)(rec_cap > 0 ? rec_cap : 1);
+    const size_t dc = (size_t)(desc_cap > 0 ? desc_cap : 1);
+    w.tile = tile;
+    w.n_tiles = tiles;
+    w.n_buckets = (int32_t)view_buckets(A);
+    w.pair_cap = pair_cap;
+    w.rec_cap = rec_cap;
+    w.desc_cap = desc_cap;
+    w.p0 = b.take<int64_t>(vm);
+    w.p1 = b.take<int64_t>(vm);
+    w.tcount = b.take<uint32_t>((size_t)tiles + 2);
+    w.toff = b.take<uint32_t>((size_t)tiles + 2);
+    w.tcursor = b.take<uint32_t>((size_t)tiles + 2);
+    w.list = b.take<uint32_t>((size_t)(pair_cap > 0 ? pair_cap : 1));
+    w.scal = b.take<int64_t>(16);
+    w.part32 = b.take<uint32_t>(dev::kScanGrid);
+    w.part64 = b.take<int64_t>(dev::kScanGrid);
+    w.rec_cell = b.take<uint16_t>(rc);
+    w.rec_gap = b.take<uint64_t>(rc);
+    w.d_view = b.take<uint32_t>(dc);
+    w.d_off = b.take<int64_t>(dc);
+    w.d_cnt = b.take<uint32_t>(dc);
+    w.d_key = b.take<uint32_t>(dc);
+    w.d_key2 = b.take<uint32_t>(dc);
+    w.d_idx = b.take<uint32_t>(dc);
+    w.d_idx2 = b.take<uint32_t>(dc);
+    w.d_hist = b.take<uint32_t>(256 * (size_t)(dev::tiles((int64_t)dc) + 1));
+    w.d_rowsum = b.take<uint32_t>(256);
+    w.seg_flag = b.take<uint32_t>(dc);
+    w.seg_id = b.take<uint32_t>(dc);
+    w.seg_start = b.take<uint32_t>(dc + 1);
+    w.seg_cells = b.take<uint32_t>(dc);
+    w.seg_tmp = b.take<int64_t>(dc);
+    w.seg_out = b.take<int64_t>(dc);
+    w.view_cells = b.take<uint32_t>(vm);
+    w.t_cell = b.take<uint32_t>(cc);
+    w.t_count = b.take<uint32_t>(cc);
+    w.t_sum = b.take<uint64_t>(cc);
+    w.t_min = b.take<int64_t>(cc);
+    w.t_max = b.take<int64_t>(cc);
+    return w;
+}
+
+namespace {
+
+// scal: [0] record cursor, [1] descriptor cursor, [2] #segments (u32 total
+// written at [8] as u32 by the scan, copied here), [3] temporary cell cursor,
+// [4] total output cells, [5] descriptors to sort, [6] #views, [7] #pairs
+
+__global__ void k_view_init(ViewWs w, int32_t V, int32_t A, const int32_t* status_in,
+                            BatchedOutDev out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = i0; i < w.n_tiles + 2; i += stride) {
+        w.tcount[i] = 0;
+        w.tcursor[i] = 0;
+    }
+    for (int64_t i = i0; i < V; i += stride) w.view_cells[i] = 0;
+    for (int64_t i = i0; i < (int64_t)V * A; i += stride) out.start_count[i] = 0;
+    if (i0 < 16) w.scal[i0] = 0;
+    if (i0 == 0) {
+        *out.status = (status_in && *status_in) ? *status_in : 0;
+        out.required[0] = 0;
+        out.required[1] = 0;
+        out.required[2] = 0;
+        out.required[3] = 0;
+        out.required[4] = 0;
+    }
+}
+
+__device__ int64_t lower_bound_i32(const int32_t* a, int64_t n, int32_t x) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Event slice of every view (whole cases) and the per-tile overlap differences.
+__global__ void k_view_slice(const pm4g_view* views, int32_t V, const int64_t* case_off,
+                             const int32_t* case_code, const int64_t* n_cases, ViewWs w) {
+    const int64_t C = *n_cases;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const pm4g_view vw = views[v];
+        int64_t p0 = 0, p1 = 0;
+        if (vw.case_lo < vw.case_hi && vw.t_lo <= vw.t_hi) {
+            p0 = case_off[lower_bound_i32(case_code, C, vw.case_lo)];
+            p1 = case_off[lower_bound_i32(case_code, C, vw.case_hi)];
+        }
+        w.p0[v] = p0;
+        w.p1[v] = p1;
+        if (p1 > p0) {
+            atomicAdd(&w.tcount[p0 / w.tile], 1u);
+            atomicAdd(&w.tcount[(p1 - 1) / w.tile + 1], 0xFFFFFFFFu);   // -1
+        }
+    }
+}
+
+// tcount holds differences; one block turns them into counts and offsets.
+__global__ __launch_bounds__(1024) void k_view_tile_scan(ViewWs w) {
+    __shared__ uint32_t tmp[1024 / kWave + 1];
+    uint32_t run_cnt = 0, run_off = 0;
+    const int64_t nt = w.n_tiles;
+    for (int64_t t0 = 0; t0 < nt; t0 += 1024) {
+        const int64_t t = t0 + threadIdx.x;
+        const uint32_t d = t < nt ? w.tcount[t] : 0u;
+        uint32_t total;
+        const uint32_t ex = block_excl_sum<1024>(d, tmp, &total);
+        const uint32_t cnt = run_cnt + ex + d;
+        uint32_t total2;
+        const uint32_t ex2 = block_excl_sum<1024>(t < nt ? cnt : 0u, tmp, &total2);
+        if (t < nt) {
+            w.tcount[t] = cnt;
+            w.toff[t] = run_off + ex2;
+        }
+        run_cnt += total;
+        run_off += total2;
+    }
+    if (threadIdx.x == 0) {
+        w.toff[nt] = run_off;
+        w.scal[7] = run_off;
+    }
+}
+
+__global__ void k_view_fill(int32_t V, ViewWs w) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p0 = w.p0[v], p1 = w.p1[v];
+        if (p1 <= p0) continue;
+        for (int64_t t = p0 / w.tile; t <= (p1 - 1) / w.tile; ++t) {
+            const int64_t at = (int64_t)w.toff[t] + atomicAdd(&w.tcursor[t], 1u);
+            if (at < w.pair_cap) w.list[at] = (uint32_t)v;
+        }
+    }
+}
+
+__device__ __forceinline__ bool kept(int32_t a, int64_t t, int64_t tlo, int64_t thi, const uint64_t* mask) {
+    return t >= tlo && t <= thi && ((mask[a >> 6] >> (a & 63)) & 1ull);
+}
+
+struct WalkState {
+    bool have_cur;   // the position before the window is in the slice
+    int32_t cur;     // ... and its case
+    bool cr_valid;   // a kept event of case `cur` precedes the window
+    int32_t cr_a;
+    int64_t cr_t;
+};
+
+// Initial state for a walk that starts at e0 inside slice [p0, p1): the case at
+// e0 - 1 and, if it continues at e0, its last kept event before e0.
+__device__ WalkState walk_init(const int32_t* case_s, const int32_t* act_s, const int64_t* ts_s,
+                               int64_t e0, int64_t p0, int64_t tlo, int64_t thi, const uint64_t* mask) {
+    WalkState st{false, 0, false, 0, 0};
+    if (e0 <= p0) return st;   // slices start at a case start
+    st.have_cur = true;
+    st.cur = case_s[e0 - 1];
+    if (case_s[e0] != st.cur) return st;
+    for (int64_t hi = e0; hi > p0; hi -= kWave) {
+        const int64_t i = hi - 1 - lane();
+        bool same = false, k = false;
+        int32_t a = 0;
+        int64_t t = 0;
+        if (i >= p0) {
+            same = case_s[i] == st.cur;
+            if (same) {
+                a = act_s[i];
+                t = ts_s[i];
+                k = kept(a, t, tlo, thi, mask);
+            }
+        }
+        const uint64_t kb = __ballot(k);
+        const int l = kb ? (__ffsll((long long)kb) - 1) : 0;   // lowest lane = latest position
+        const int32_t al = __shfl(a, l);
+        const int64_t tl = __shfl(t, l);
+        if (kb) {
+            st.cr_valid = true;
+            st.cr_a = al;
+            st.cr_t = tl;
+            return st;
+        }
+        if (__ballot(i >= p0 && !same) != 0) return st;   // reached the case start
+    }
+    return st;
+}
+
+// One walk over [e0, e1) of the staged tile (T0 = first position of the tile).
+// Every kept event yields one record; WRITE=false counts per bucket in
+// cursor[], WRITE=true takes slots from cursor[] and writes the records.
+template <bool WRITE>
+__device__ void walk(const int32_t* s_case, const int16_t* s_act, const int64_t* s_ts, int64_t T0,
+                     int64_t e0, int64_t e1, WalkState st, int32_t A, int64_t tlo, int64_t thi,
+                     const uint64_t* mask, uint32_t* cursor, int64_t rec_base, bool can_write,
+                     uint16_t* rec_cell, uint64_t* rec_gap) {
+    const int64_t AA = (int64_t)A * A;
+    const uint64_t below = lanes_below();
+    const uint64_t le = below | (uint64_t(1) << lane());
+    for (int64_t b0 = e0; b0 < e1; b0 += kWave) {
+        const int64_t i = b0 + lane();
+        const bool in = i < e1;
+        int32_t c = 0, a = 0;
+        int64_t t = 0;
+        bool k = false;
+        if (in) {
+            const int li = (int)(i - T0);
+            c = s_case[li];
+            a = s_act[li];
+            t = s_ts[li];
+            k = kept(a, t, tlo, thi, mask);
+        }
+        const int32_t cup = __shfl_up(c, 1);
+        bool starts;
+        if (lane() == 0) starts = !st.have_cur || c != st.cur;
+        else starts = c != cup;
+        starts = starts && in;
+        const uint64_t K = __ballot(k);
+        const uint64_t S = __ballot(starts);
+        const uint64_t sle = S & le;
+        const int sl = sle ? hi_bit(sle) : -1;           // -1: the segment began before the window
+        const uint64_t seg = sl < 0 ? below : (below & ~((uint64_t(1) << sl) - 1));
+        const uint64_t pk = K & seg;
+        const int pl = pk ? hi_bit(pk) : 0;
+        const int32_t ap = __shfl(a, pl);
+        const int64_t tp = __shfl(t, pl);
+        if (k) {
+            bool has_prev = pk != 0;
+            int32_t pa = ap;
+            int64_t pt = tp;
+            if (!has_prev && sl < 0 && st.cr_valid) {
+                has_prev = true;
+                pa = st.cr_a;
+                pt = st.cr_t;
+            }
+            const int64_t cell = has_prev ? (int64_t)pa * A + a : AA + a;
+            const uint64_t gap = has_prev ? (uint64_t)t - (uint64_t)pt : 0ull;
+            const uint32_t slot = atomicAdd(&cursor[(uint32_t)(cell >> 12)], 1u);
+            if (WRITE && can_write) {
+                rec_cell[rec_base + slot] = (uint16_t)(cell & (kCellsPerTable - 1));
+                rec_gap[rec_base + slot] = gap;
+            }
+        }
+        // carry to the next window
+        const int lastS = S ? hi_bit(S) : -1;
+        const uint64_t Klast = lastS < 0 ? K : (K & ~((uint64_t(1) << lastS) - 1));
+        const int lk = Klast ? hi_bit(Klast) : 0;
+        const int32_t ak = __shfl(a, lk);
+        const int64_t tk = __shfl(t, lk);
+        if (Klast) {
+            st.cr_valid = true;
+            st.cr_a = ak;
+            st.cr_t = tk;
+        } else if (lastS >= 0) {
+            st.cr_valid = false;
+        }
+        const int lin = hi_bit(__ballot(in));
+        st.cur = __shfl(c, lin);
+        st.have_cur = true;
+    }
+}
+
+template <int TILE>
+__global__ __launch_bounds__(kVB) void k_view_emit(const int32_t* __restrict__ case_s,
+                                                   const int32_t* __restrict__ act_s,
+                                                   const int64_t* __restrict__ ts_s, int64_t n, int32_t A,
+                                                   const pm4g_view* __restrict__ views,
+                                                   const uint64_t* __restrict__ masks, ViewWs w) {
+    __shared__ int32_t s_case[TILE];
+    __shared__ int16_t s_act[TILE];
+    __shared__ int64_t s_ts[TILE];
+    __shared__ uint64_t s_mask[kVW][kMaskWords];
+    __shared__ uint32_t s_cur[kVW][kMaxBuckets];
+
+    const int wv = threadIdx.x / kWave;
+    const int NB = w.n_buckets;
+    const int MW = (A + 63) / 64;
+    uint64_t* mask = s_mask[wv];
+    uint32_t* cur = s_cur[wv];
+    for (int64_t tile = blockIdx.x; tile < w.n_tiles; tile += gridDim.x) {
+        const int64_t T0 = tile * TILE;
+        const int64_t T1 = (T0 + TILE) < n ? (T0 + TILE) : n;
+        for (int64_t i = T0 + threadIdx.x; i < T1; i += kVB) {
+            s_case[i - T0] = case_s[i];
+            s_act[i - T0] = (int16_t)act_s[i];
+            s_ts[i - T0] = ts_s[i];
+        }
+        __syncthreads();
+        const uint32_t cnt = w.tcount[tile];
+        const int64_t off = w.toff[tile];
+        for (uint32_t j = wv; j < cnt; j += kVW) {
+            if (off + j >= w.pair_cap) break;   // wave-uniform; reported by the host
+            const uint32_t v = w.list[off + j];
+            const pm4g_view vw = views[v];
+            const int64_t p0 = w.p0[v], p1 = w.p1[v];
+            for (int q = lane(); q < MW; q += kWave) mask[q] = masks[(size_t)v * MW + q];
+            const int64_t e0 = T0 > p0 ? T0 : p0;
+            const int64_t e1 = T1 < p1 ? T1 : p1;
+            const WalkState st = walk_init(case_s, act_s, ts_s, e0, p0, vw.t_lo, vw.t_hi, mask);
+            for (int q = lane(); q < NB; q += kWave) cur[q] = 0;
+            walk<false>(s_case, s_act, s_ts, T0, e0, e1, st, A, vw.t_lo, vw.t_hi, mask, cur, 0, false,
+                        w.rec_cell, w.rec_gap);
+            // reserve the records and one descriptor per non-empty bucket;
+            // cur[q] becomes the exclusive offset of bucket q (the write cursor)
+            uint32_t run = 0, nne = 0;
+            for (int q0 = 0; q0 < NB; q0 += kWave) {
+                const int q = q0 + lane();
+                const uint32_t c = q < NB ? cur[q] : 0u;
+                const uint32_t ic = wave_incl_sum(c);
+                if (q < NB) cur[q] = run + ic - c;
+                run += __shfl(ic, kWave - 1);
+                nne += (uint32_t)__popcll(__ballot(c != 0));
+            }
+            int64_t rbase = 0, dbase = 0;
+            if (lane() == 0) {
+                rbase = (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(&w.scal[0]),
+                                           (unsigned long long)run);
+                dbase = (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(&w.scal[1]),
+                                           (unsigned long long)nne);
+            }
+            rbase = __shfl(rbase, 0);
+            dbase = __shfl(dbase, 0);
+            const bool ok = rbase + (int64_t)run <= w.rec_cap && dbase + (int64_t)nne <= w.desc_cap;
+            // descriptors: bucket q has count cur[q+1] - cur[q] (cur[NB] = run)
+            uint32_t drun = 0;
+            for (int q0 = 0; q0 < NB; q0 += kWave) {
+                const int q = q0 + lane();
+                uint32_t c = 0, o = 0;
+                if (q < NB) {
+                    o = cur[q];
+                    c = (q + 1 < NB ? cur[q + 1] : run) - o;
+                }
+                const uint64_t nzm = __ballot(c != 0);
+                if (ok && c != 0) {
+                    const int64_t d = dbase + drun + __popcll(nzm & lanes_below());
+                    w.d_view[d] = v;
+                    w.d_key[d] = v * (uint32_t)NB + (uint32_t)q;
+                    w.d_idx[d] = (uint32_t)d;
+                    w.d_off[d] = rbase + o;
+                    w.d_cnt[d] = c;
+                }
+                drun += (uint32_t)__popcll(nzm);
+            }
+            walk<true>(s_case, s_act, s_ts, T0, e0, e1, st, A, vw.t_lo, vw.t_hi, mask, cur, rbase, ok,
+                       w.rec_cell, w.rec_gap);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_view_seg_count(ViewWs w, int32_t V) {
+    w.scal[5] = w.scal[1] < w.desc_cap ? w.scal[1] : w.desc_cap;
+    w.scal[6] = V;
+}
+
+// Segment starts of the sorted descriptor keys.
+__global__ void k_view_seg_flags(const uint32_t* keys, ViewWs w) {
+    const int64_t D = w.scal[5];
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < D;
+         p += (int64_t)gridDim.x * blockDim.x)
+        w.seg_flag[p] = (p == 0 || keys[p] != keys[p - 1]) ? 1u : 0u;
+}
+
+__global__ void k_view_seg_starts(ViewWs w) {
+    const int64_t D = w.scal[5];
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < D;
+         p += (int64_t)gridDim.x * blockDim.x)
+        if (w.seg_flag[p]) w.seg_start[w.seg_id[p]] = (uint32_t)p;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int64_t S = (int64_t)((uint32_t*)&w.scal[8])[0];
+        w.seg_start[S] = (uint32_t)D;
+        w.scal[2] = S;
+    }
+}
+
+// One block per (view, bucket) segment.
+__global__ __launch_bounds__(kAB2) void k_view_agg(const uint32_t* keys, const uint32_t* idx, int32_t A,
+                                                   ViewWs w, BatchedOutDev out) {
+    __shared__ uint32_t scount[kCellsPerTable];
+    __shared__ uint64_t ssum[kCellsPerTable];
+    __shared__ int64_t smin[kCellsPerTable];
+    __shared__ int64_t smax[kCellsPerTable];
+    __shared__ uint32_t tmp[kAB2 / kWave + 1];
+    __shared__ int64_t s_base;
+    const int64_t S = w.scal[2];
+    const int64_t AA = (int64_t)A * A;
+    const int NB = w.n_buckets;
+    for (int64_t g = blockIdx.x; g < S; g += gridDim.x) {
+        const uint32_t d0 = w.seg_start[g], d1 = w.seg_start[g + 1];
+        const uint32_t key = keys[d0];
+        const uint32_t v = key / (uint32_t)NB;
+        const uint32_t bk = key % (uint32_t)NB;
+        for (int c = threadIdx.x; c < kCellsPerTable; c += kAB2) {
+            scount[c] = 0;
+            ssum[c] = 0;
+            smin[c] = INT64_MAX;
+            smax[c] = INT64_MIN;
+        }
+        __syncthreads();
+        const int wv = threadIdx.x / kWave;
+        for (uint32_t d = d0 + wv; d < d1; d += kAB2 / kWave) {
+            const uint32_t di = idx[d];
+            const int64_t r0 = w.d_off[di];
+            const uint32_t rc = w.d_cnt[di];
+            for (uint32_t r = lane(); r < rc; r += kWave) {
+                const uint32_t cell = w.rec_cell[r0 + r];
+                const uint64_t gap = w.rec_gap[r0 + r];
+                const int64_t gg = (int64_t)gap;
+                atomicAdd(&scount[cell], 1u);
+                atomicAdd(reinterpret_cast<unsigned long long*>(&ssum[cell]), (unsigned long long)gap);
+                if (gg < __hip_atomic_load(&smin[cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+                    __hip_atomic_fetch_min(&smin[cell], gg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (gg > __hip_atomic_load(&smax[cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+                    __hip_atomic_fetch_max(&smax[cell], gg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+        __syncthreads();
+        // compaction in cell order; start cells go straight to the start counts
+        constexpr int kPer = kCellsPerTable / kAB2;   // 4 cells per thread, blocked
+        uint32_t flags = 0;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int c = threadIdx.x * kPer + q;
+            const int64_t cell = (int64_t)bk * kCellsPerTable + c;
+            if (scount[c] == 0) continue;
+            if (cell < AA) flags |= 1u << q;
+            else if (cell < AA + A) out.start_count[(size_t)v * A + (cell - AA)] = scount[c];
+        }
+        uint32_t total;
+        uint32_t r = block_excl_sum<kAB2>((uint32_t)__popc(flags), tmp, &total);
+        if (threadIdx.x == 0) {
+            s_base = (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(&w.scal[3]),
+                                        (unsigned long long)total);
+            w.seg_cells[g] = total;
+            w.seg_tmp[g] = s_base;
+            atomicAdd(&w.view_cells[v], total);
+        }
+        __syncthreads();
+        const int64_t base = s_base;
+        if (base + (int64_t)total > w.cell_cap) flags = 0;   // over capacity: counted, not written
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            if (!(flags & (1u << q))) continue;
+            const int c = threadIdx.x * kPer + q;
+            const int64_t at = base + r;
+            w.t_cell[at] = (uint32_t)((int64_t)bk * kCellsPerTable + c);
+            w.t_count[at] = scount[c];
+            w.t_sum[at] = ssum[c];
+            w.t_min[at] = smin[c];
+            w.t_max[at] = smax[c];
+            ++r;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_view_copy(int32_t A, ViewWs w, BatchedOutDev out) {
+    const int64_t S = w.scal[2];
+    const bool fits = w.scal[4] <= out.cap_edges && w.scal[3] <= w.cell_cap;
+    if (!fits) return;
+    const int wv = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int nw = gridDim.x * blockDim.x / kWave;
+    for (int64_t g = wv; g < S; g += nw) {
+        const int64_t src = w.seg_tmp[g], dst = w.seg_out[g];
+        const uint32_t m = w.seg_cells[g];
+        for (uint32_t r = lane(); r < m; r += kWave) {
+            const uint32_t cell = w.t_cell[src + r];
+            const uint32_t cnt = w.t_count[src + r];
+            const uint64_t sum = w.t_sum[src + r];
+            out.src[dst + r] = (int32_t)(cell / (uint32_t)A);
+            out.dst[dst + r] = (int32_t)(cell % (uint32_t)A);
+            out.count[dst + r] = cnt;
+            out.dt_sum[dst + r] = (int64_t)sum;
+            out.dt_min[dst + r] = w.t_min[src + r];
+            out.dt_max[dst + r] = w.t_max[src + r];
+            if (out.dt_mean) out.dt_mean[dst + r] = (double)(int64_t)sum / (double)(int64_t)cnt;
+        }
+    }
+}
+
+// Per view: its segments form a run of the sorted segment list; fold their
+// cells into row and column sums; derive activity and end counts.
+__global__ __launch_bounds__(256) void k_view_acts(const uint32_t* keys, int32_t V, int32_t A, ViewWs w,
+                                                   BatchedOutDev out) {
+    __shared__ unsigned long long rows[PM4G_BATCHED_MAX_ACTIVITIES];
+    __shared__ unsigned long long cols[PM4G_BATCHED_MAX_ACTIVITIES];
+    __shared__ int64_t red[2][256 / kWave];
+    const int64_t S = w.scal[2];
+    const uint32_t NB = (uint32_t)w.n_buckets;
+    if (w.scal[3] > w.cell_cap) return;   // temporary cells were not all written
+    for (int64_t v = blockIdx.x; v < V; v += gridDim.x) {
+        for (int a = threadIdx.x; a < A; a += 256) rows[a] = cols[a] = 0;
+        __syncthreads();
+        // first segment of this view: lower bound of key v*NB over segment keys
+        int64_t lo = 0, hi = S;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (keys[w.seg_start[mid]] < (uint32_t)v * NB) lo = mid + 1;
+            else hi = mid;
+        }
+        for (int64_t g = lo; g < S && keys[w.seg_start[g]] / NB == (uint32_t)v; ++g) {
+            const int64_t src = w.seg_tmp[g];
+            const uint32_t m = w.seg_cells[g];
+            for (uint32_t r = threadIdx.x; r < m; r += 256) {
+                const uint32_t cell = w.t_cell[src + r];
+                const unsigned long long c = w.t_count[src + r];
+                atomicAdd(&rows[cell / (uint32_t)A], c);
+                atomicAdd(&cols[cell % (uint32_t)A], c);
+            }
+        }
+        __syncthreads();
+        int64_t ne = 0, nc = 0;
+        for (int a = threadIdx.x; a < A; a += 256) {
+            const size_t at = (size_t)v * A + a;
+            const int64_t st = out.start_count[at];
+            const int64_t act = st + (int64_t)cols[a];
+            out.act_count[at] = act;
+            out.end_count[at] = act - (int64_t)rows[a];
+            ne += act;
+            nc += st;
+        }
+        ne = wave_sum(ne);
+        nc = wave_sum(nc);
+        if (lane() == 0) {
+            red[0][threadIdx.x / kWave] = ne;
+            red[1][threadIdx.x / kWave] = nc;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t a = 0, b = 0;
+            for (int k = 0; k < 256 / kWave; ++k) {
+                a += red[0][k];
+                b += red[1][k];
+            }
+            out.n_events[v] = a;
+            out.n_cases[v] = b;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_view_finish(int32_t V, ViewWs w, BatchedOutDev out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        out.edge_off[V] = w.scal[4];
+        out.required[0] = w.scal[4];
+        out.required[1] = w.scal[0];
+        out.required[2] = w.scal[1];
+        out.required[3] = w.scal[7];
+        out.required[4] = w.scal[3];
+        if (w.scal[4] > out.cap_edges || w.scal[3] > w.cell_cap) set_status(out.status, PM4G_E_CAPACITY);
+    }
+}
+
+int bits_u32(uint64_t x) {
+    int b = 0;
+    while (b < 32 && (uint64_t(1) << b) <= x) ++b;
+    return b;
+}
+
+}  // namespace
+
+hipError_t launch_views_plan(const pm4g_prepared* p, const pm4g_view* views, int32_t V, ViewWs w,
+                             BatchedOutDev out, hipStream_t s) {
+    ProfScope ps(P_VIEW_PLAN, s);
+    const int32_t A = p->n_activities;
+    k_view_init<<<1024, 256, 0, s>>>(w, V, A, p->status, out);
+    if (V > 0) k_view_slice<<<(unsigned)((V + 255) / 256), 256, 0, s>>>(views, V, p->case_off, p->case_code,
+                                                                          p->n_cases, w);
+    k_view_tile_scan<<<1, 1024, 0, s>>>(w);
+    if (V > 0) k_view_fill<<<(unsigned)((V + 255) / 256), 256, 0, s>>>(V, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_views_emit(const pm4g_prepared* p, const pm4g_view* views, const uint64_t* masks,
+                             ViewWs w, int grid, hipStream_t s) {
+    ProfScope ps(P_VIEW_EMIT, s);
+    const int64_t n = p->n_events;
+    if (w.n_tiles > 0) {
+        const unsigned g = (unsigned)(w.n_tiles < grid ? w.n_tiles : grid);
+        if (w.tile == 2048)
+            k_view_emit<2048><<<g, kVB, 0, s>>>(p->case_s, p->act_s, p->ts_s, n, p->n_activities, views, masks, w);
+        else
+            k_view_emit<4096><<<g, kVB, 0, s>>>(p->case_s, p->act_s, p->ts_s, n, p->n_activities, views, masks, w);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_views_reduce(const pm4g_prepared* p, int32_t V, ViewWs w, BatchedOutDev out, int agg_grid,
+                               hipStream_t s) {
+    const int32_t A = p->n_activities;
+    const uint32_t* keys;
+    const uint32_t* idx;
+    {
+        ProfScope ps(P_VIEW_SORT, s);
+        // descriptors to sort: min(cursor, capacity); the host only comes here if they fit
+        k_view_seg_count<<<1, 1, 0, s>>>(w, V);
+        const int kb = bits_u32((uint64_t)(V > 0 ? V : 1) * (uint64_t)w.n_buckets);
+        const bool flip = dev::sort_pairs<uint32_t>(w.d_key, w.d_idx, w.d_key2, w.d_idx2, &w.scal[5], w.desc_cap,
+                                                    kb, w.d_hist, w.d_rowsum, s);
+        keys = flip ? w.d_key2 : w.d_key;
+        idx = flip ? w.d_idx2 : w.d_idx;
+        k_view_seg_flags<<<2048, 256, 0, s>>>(keys, w);
+        dev::excl_scan<uint32_t>(w.seg_flag, &w.scal[5], w.seg_id, w.part32, (uint32_t*)&w.scal[8], s);
+        k_view_seg_starts<<<2048, 256, 0, s>>>(w);
+    }
+    {
+        ProfScope ps(P_VIEW_AGG, s);
+        k_view_agg<<<(unsigned)agg_grid, kAB2, 0, s>>>(keys, idx, A, w, out);
+    }
+    {
+        ProfScope ps(P_VIEW_OUT, s);
+        dev::excl_scan<int64_t>(w.seg_cells, &w.scal[2], w.seg_out, w.part64, &w.scal[4], s);
+        dev::excl_scan<int64_t>(w.view_cells, &w.scal[6], out.edge_off, w.part64, (int64_t*)nullptr, s);
+        k_view_copy<<<2048, 256, 0, s>>>(A, w, out);
+        k_view_acts<<<2048, 256, 0, s>>>(keys, V, A, w, out);
+        k_view_finish<<<1, 1, 0, s>>>(V, w, out);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pm4g

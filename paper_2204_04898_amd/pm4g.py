@@ -56,6 +56,21 @@ class _VarOut(ctypes.Structure):
                                   "var_acts", "case_variant", "status")]
 
 
+class _BatchedOut(ctypes.Structure):
+    _fields_ = [(k, _P) for k in ("edge_off", "src", "dst", "count", "dt_sum", "dt_min", "dt_max", "dt_mean",
+                                  "start_count", "end_count", "act_count", "n_events", "n_cases")] + \
+               [("cap_edges", ctypes.c_int64), ("required", _P), ("status", _P)]
+
+
+class BatchedTuning(ctypes.Structure):
+    """Launch shape and capacities of pm4g_dfg_batched (zero fields: library defaults)."""
+
+    _fields_ = [("tile_events", ctypes.c_int32), ("emit_blocks", ctypes.c_int32),
+                ("agg_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("pair_capacity", ctypes.c_int64), ("record_capacity", ctypes.c_int64),
+                ("descriptor_capacity", ctypes.c_int64), ("cell_capacity", ctypes.c_int64)]
+
+
 class Pm4gError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"pm4g error {code}: {msg}")
@@ -89,6 +104,18 @@ def load():
             L.pm4g_last_error.argtypes = []
             L.pm4g_last_error.restype = ctypes.c_char_p
             L.pm4g_abi_version.restype = ctypes.c_int
+            L.pm4g_batched_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                                       ctypes.POINTER(BatchedTuning)]
+            L.pm4g_batched_workspace_bytes.restype = ctypes.c_size_t
+            L.pm4g_dfg_batched.argtypes = [ctypes.POINTER(_Prepared), _P, _P, ctypes.c_int32,
+                                           ctypes.POINTER(_BatchedOut), ctypes.POINTER(BatchedTuning),
+                                           _P, ctypes.c_size_t, _P]
+            L.pm4g_dfg_batched.restype = ctypes.c_int
+            L.pm4g_filter_workspace_bytes.argtypes = [ctypes.c_int64]
+            L.pm4g_filter_workspace_bytes.restype = ctypes.c_size_t
+            L.pm4g_filter_view.argtypes = [ctypes.POINTER(_Prepared), _P, _P, ctypes.POINTER(_Prepared), _P,
+                                           ctypes.c_size_t, _P]
+            L.pm4g_filter_view.restype = ctypes.c_int
             L.pm4g_profile_enable.argtypes = [ctypes.c_int]
             L.pm4g_profile_enable.restype = ctypes.c_int
             L.pm4g_profile_read.argtypes = [_P, _P, ctypes.c_int]
@@ -273,6 +300,143 @@ def pm4g_variants_prepared(prep: Prepared, out: dict | None = None, stream=None)
     s = _var_struct(o)
     _check(load().pm4g_variants_prepared(ctypes.byref(p), ctypes.byref(s), _ptr(ws), need, _stream(stream)))
     return o
+
+
+PM4G_BATCHED_MAX_ACTIVITIES = 1024
+
+
+def views_to_device(views, device) -> tuple[torch.Tensor, torch.Tensor]:
+    """Packs synth.Views (or any object with case_lo/case_hi/t_lo/t_hi/masks) for the library."""
+    import numpy as np
+    rec = np.zeros(len(views.case_lo), dtype=np.dtype([("lo", "<i4"), ("hi", "<i4"), ("t_lo", "<i8"),
+                                                        ("t_hi", "<i8")]))
+    rec["lo"], rec["hi"], rec["t_lo"], rec["t_hi"] = views.case_lo, views.case_hi, views.t_lo, views.t_hi
+    v = torch.from_numpy(rec.view(np.uint8).copy()).to(device)
+    m = torch.from_numpy(np.ascontiguousarray(views.masks).view(np.int64).copy()).to(device)
+    return v, m
+
+
+def _batched_out(V: int, A: int, cap_edges: int, device) -> dict:
+    cap = max(int(cap_edges), 1)
+    i64 = dict(dtype=torch.int64, device=device)
+    return dict(edge_off=torch.empty(V + 1, **i64),
+                src=torch.empty(cap, dtype=torch.int32, device=device),
+                dst=torch.empty(cap, dtype=torch.int32, device=device),
+                count=torch.empty(cap, **i64), dt_sum=torch.empty(cap, **i64),
+                dt_min=torch.empty(cap, **i64), dt_max=torch.empty(cap, **i64),
+                dt_mean=torch.empty(cap, dtype=torch.float64, device=device),
+                start_count=torch.empty(max(V * A, 1), **i64), end_count=torch.empty(max(V * A, 1), **i64),
+                act_count=torch.empty(max(V * A, 1), **i64), n_events=torch.empty(max(V, 1), **i64),
+                n_cases=torch.empty(max(V, 1), **i64), required=torch.zeros(5, **i64),
+                status=torch.zeros(1, dtype=torch.int32, device=device), cap_edges=cap)
+
+
+def _batched_struct(o: dict) -> _BatchedOut:
+    return _BatchedOut(*[_ptr(o[k]) for k in ("edge_off", "src", "dst", "count", "dt_sum", "dt_min", "dt_max",
+                                               "dt_mean", "start_count", "end_count", "act_count",
+                                               "n_events", "n_cases")],
+                       o["cap_edges"], _ptr(o["required"]), _ptr(o["status"]))
+
+
+def pm4g_dfg_batched(prep: Prepared, views: torch.Tensor, masks: torch.Tensor, n_views: int,
+                     tuning: BatchedTuning | None = None, cap_edges: int | None = None,
+                     out: dict | None = None, stream=None, retry: bool = True) -> dict:
+    """DFGs of n_views drill-down views in one pass (Sec. 1 drill-down, Sec. 3 filters).
+
+    views: device uint8 tensor of n_views packed pm4g_view records; masks: device
+    int64 tensor [n_views, ceil(A/64)].  Synchronises the stream.  With `retry`,
+    capacities found too small are raised to what the call reported and the
+    call is repeated.
+    """
+    L = load()
+    A = prep.n_activities
+    dev = prep.case_s.device
+    t = BatchedTuning() if tuning is None else BatchedTuning.from_buffer_copy(tuning)
+    cap = int(cap_edges) if cap_edges is not None else max(1024, min(prep.n_events, 1 << 24))
+    o = out if out is not None else _batched_out(n_views, A, cap, dev)
+    for _ in range(6):
+        need = int(L.pm4g_batched_workspace_bytes(prep.n_events, A, n_views, ctypes.byref(t)))
+        if need == 0:
+            raise Pm4gError(PM4G_E_INVALID, "invalid sizes or tuning for the batched workspace")
+        ws = _batched_ws(dev, need, stream)
+        p = prep._struct()
+        s = _batched_struct(o)
+        rc = L.pm4g_dfg_batched(ctypes.byref(p), _ptr(views), _ptr(masks), int(n_views), ctypes.byref(s),
+                                ctypes.byref(t), _ptr(ws), need, _stream(stream))
+        if rc == PM4G_OK:
+            (torch.cuda.current_stream() if stream is None else stream).synchronize()
+            status = int(o["status"].item())
+            if status == PM4G_OK:
+                return o
+            if status != PM4G_E_CAPACITY or not retry:
+                raise Pm4gError(status, L.pm4g_status_string(status).decode())
+        elif rc != PM4G_E_CAPACITY or not retry:
+            _check(rc)
+        req = [int(x) for x in o["required"].cpu().tolist()]
+        grow = lambda cur, r: max(int(cur), int(r * 1.25) + 1024)
+        if req[3] > 0:
+            t.pair_capacity = grow(t.pair_capacity, req[3])
+        if req[1] > 0:
+            t.record_capacity = grow(t.record_capacity, req[1])
+        if req[2] > 0:
+            t.descriptor_capacity = grow(t.descriptor_capacity, req[2])
+        if req[4] > 0:
+            t.cell_capacity = grow(t.cell_capacity, req[4])
+        if req[0] > o["cap_edges"]:
+            o = _batched_out(n_views, A, int(req[0] * 1.1) + 1024, dev)
+    raise Pm4gError(PM4G_E_CAPACITY, "capacities still short after retries")
+
+
+def pm4g_filter_view(prep: Prepared, view: torch.Tensor, mask: torch.Tensor, out: Prepared | None = None,
+                     ws: torch.Tensor | None = None, stream=None) -> Prepared:
+    """The kept events of one view as a prepared log (device record `view`, device `mask` words).
+
+    Asynchronous; out's kept count is out.case_off[out.n_cases] on the device.
+    """
+    L = load()
+    dev = prep.case_s.device
+    o = out if out is not None else Prepared.empty(prep.n_events, prep.n_activities, dev)
+    need = int(L.pm4g_filter_workspace_bytes(prep.n_events))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    p = prep._struct()
+    q = o._struct()
+    _check(L.pm4g_filter_view(ctypes.byref(p), _ptr(view), _ptr(mask), ctypes.byref(q), _ptr(ws), need,
+                              _stream(stream)))
+    return o
+
+
+_bws_cache: dict = {}
+
+
+def _batched_ws(device, need: int, stream=None) -> torch.Tensor:
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    key = (torch.device(device).index, s.cuda_stream)
+    buf = _bws_cache.get(key)
+    if buf is None or buf.numel() < need:
+        _bws_cache.pop(key, None)
+        buf = torch.empty(need, dtype=torch.uint8, device=device)
+        _bws_cache[key] = buf
+    return buf
+
+
+def batched_to_host(o: dict, n_views: int, A: int) -> dict:
+    """Per-view results on the host: list of dicts with sparse cells and counts."""
+    off = o["edge_off"][:n_views + 1].cpu().numpy()
+    E = int(off[-1]) if n_views > 0 else 0
+    cols = {k: o[k][:E].cpu().numpy() for k in ("src", "dst", "count", "dt_sum", "dt_min", "dt_max", "dt_mean")}
+    st = o["start_count"][:n_views * A].cpu().numpy().reshape(n_views, A)
+    en = o["end_count"][:n_views * A].cpu().numpy().reshape(n_views, A)
+    ac = o["act_count"][:n_views * A].cpu().numpy().reshape(n_views, A)
+    ne = o["n_events"][:n_views].cpu().numpy()
+    nc = o["n_cases"][:n_views].cpu().numpy()
+    res = []
+    for v in range(n_views):
+        a, b = int(off[v]), int(off[v + 1])
+        d = {k: c[a:b] for k, c in cols.items()}
+        d.update(start_count=st[v], end_count=en[v], act_count=ac[v], n_events=int(ne[v]), n_cases=int(nc[v]))
+        res.append(d)
+    return res
 
 
 def debug_variant_hash_bits(bits: int) -> int:

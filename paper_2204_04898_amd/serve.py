@@ -1,0 +1,297 @@
+"""Continuous-batching query server over event logs resident in HBM.
+
+The paper names the responsiveness of the tool and drill-down into smaller
+views as what users need (Sec. 1); this module serves DFG, variant and
+filter queries on such views while the prepared logs (Sec. 3 formatting,
+done once) stay on the GPU.
+
+Scheduling (host side, independent of the executor):
+  - requests carry a scheduled arrival time (open loop); latency is measured
+    from it, not from dispatch;
+  - admission by memory: each request has a workspace estimate; a batch is
+    formed from the head of the FIFO queue while the estimates fit in the
+    budget left by the batches in flight; the head never gets skipped, so no
+    request starves; a request larger than the whole budget is rejected;
+  - continuous batching: up to `workers` batches are in flight, each on its
+    own HIP stream, so requests that arrive while a batch runs join the next
+    batch and its work overlaps on the device with the running one.
+
+GpuExecutor runs a batch with the library: all DFG and FILTER views of one
+log in one pm4g_dfg_batched launch, each VARIANTS view as pm4g_filter_view +
+pm4g_variants_prepared.
+"""
+from __future__ import annotations
+
+import dataclasses
+import threading
+import time
+from typing import Callable
+
+import numpy as np
+
+KINDS = ("dfg", "variants", "filter")
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    log: str
+    kind: str                 # "dfg" | "variants" | "filter"
+    case_lo: int
+    case_hi: int
+    t_lo: int
+    t_hi: int
+    mask: np.ndarray          # uint64 words, bit a selects activity a
+    arrival: float            # scheduled arrival, seconds on the server clock
+    est_bytes: int = 0
+    dispatched: float = float("nan")
+    done: float = float("nan")
+    result: dict | None = None
+    error: str | None = None
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class Scheduler:
+    """FIFO admission by memory estimate, up to `workers` batches in flight."""
+
+    def __init__(self, executor, mem_budget: int, max_batch: int = 256, workers: int = 2,
+                 clock: Callable[[], float] = time.monotonic):
+        self.ex = executor
+        self.budget = int(mem_budget)
+        self.max_batch = int(max_batch)
+        self.workers = int(workers)
+        self.clock = clock
+        self._lock = threading.Condition()
+        self._in_flight_bytes = 0
+        self._in_flight = 0
+        self.max_in_flight_bytes = 0
+        self.batches: list[list[int]] = []
+
+    def form_batch(self, queue: list[Request]) -> list[Request]:
+        """Head-of-queue batch that fits the memory left; removes it from `queue`."""
+        batch: list[Request] = []
+        room = self.budget - self._in_flight_bytes
+        while queue and len(batch) < self.max_batch:
+            r = queue[0]
+            if r.est_bytes > room:
+                break
+            room -= r.est_bytes
+            batch.append(queue.pop(0))
+        return batch
+
+    def run(self, requests: list[Request], t0: float | None = None) -> list[Request]:
+        """Serves `requests` (arrival times relative to t0); returns them completed."""
+        pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        for r in pending:
+            r.est_bytes = int(self.ex.estimate(r))
+        t0 = self.clock() if t0 is None else t0
+        queue: list[Request] = []
+        done: list[Request] = []
+        threads: list[threading.Thread] = []
+        i = 0
+        while True:
+            now = self.clock() - t0
+            while i < len(pending) and pending[i].arrival <= now:
+                r = pending[i]
+                i += 1
+                if r.est_bytes > self.budget:
+                    r.error = "request exceeds the memory budget"
+                    r.dispatched = r.done = now
+                    done.append(r)
+                else:
+                    queue.append(r)
+            batch: list[Request] = []
+            with self._lock:
+                if self._in_flight < self.workers:
+                    batch = self.form_batch(queue)
+                if batch:
+                    self._in_flight += 1
+                    self._in_flight_bytes += sum(r.est_bytes for r in batch)
+                    self.max_in_flight_bytes = max(self.max_in_flight_bytes, self._in_flight_bytes)
+                    self.batches.append([r.rid for r in batch])
+                elif i == len(pending) and not queue and self._in_flight == 0:
+                    break
+                else:
+                    # sleep until the next arrival or a completion (notified), at most 5 ms
+                    nxt = pending[i].arrival - now if i < len(pending) else 0.005
+                    self._lock.wait(timeout=min(max(nxt, 0.0), 0.005))
+            if batch:
+                for r in batch:
+                    r.dispatched = now
+                th = threading.Thread(target=self._serve, args=(batch, t0, done), daemon=True)
+                th.start()
+                threads.append(th)
+        for th in threads:
+            th.join()
+        return sorted(done, key=lambda r: r.rid)
+
+    def _serve(self, batch: list[Request], t0: float, done: list[Request]):
+        try:
+            self.ex.run(batch)
+        except Exception as e:  # reported per request; the server keeps going
+            for r in batch:
+                r.error = f"{type(e).__name__}: {e}"
+        end = self.clock() - t0
+        with self._lock:
+            for r in batch:
+                r.done = end
+                done.append(r)
+            self._in_flight -= 1
+            self._in_flight_bytes -= sum(r.est_bytes for r in batch)
+            self._lock.notify_all()
+
+
+def latency_stats(reqs: list[Request]) -> dict:
+    ok = [r for r in reqs if r.error is None]
+    lat = np.array([r.latency for r in ok]) * 1e3
+    if lat.size == 0:
+        return dict(n=0)
+    span = max(r.done for r in ok) - min(r.arrival for r in ok)
+    return dict(n=len(ok), rejected=len(reqs) - len(ok), p50_ms=float(np.percentile(lat, 50)),
+                p99_ms=float(np.percentile(lat, 99)), max_ms=float(lat.max()),
+                qps=len(ok) / span if span > 0 else float("nan"))
+
+
+def log_info(log) -> dict:
+    """What the request generator needs of a synthetic log (a synth.Log)."""
+    cum = np.zeros(log.lengths_by_code.shape[0] + 1, np.int64)
+    np.cumsum(log.lengths_by_code, out=cum[1:])
+    return dict(lengths_by_code=log.lengths_by_code, cum=cum, t_min=int(log.ts.min()), t_max=int(log.ts.max()))
+
+
+def poisson_requests(rng: np.random.Generator, rate: float, seconds: float, logs: dict, A_of: dict,
+                     mix=(("dfg", 0.4), ("variants", 0.3), ("filter", 0.3)),
+                     min_events: float = 1e4, max_events: float = 1e8) -> list[Request]:
+    """Open-loop Poisson arrivals: log chosen uniformly, kind by `mix`, view with
+    a log-uniform slice size in [min_events, max_events] (capped at the log),
+    a time window and an activity subset as in the batched-view workload."""
+    names = sorted(logs)
+    kinds = [k for k, _ in mix]
+    probs = np.array([p for _, p in mix], float)
+    probs /= probs.sum()
+    out = []
+    t = 0.0
+    rid = 0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > seconds:
+            break
+        name = names[int(rng.integers(0, len(names)))]
+        lg = logs[name]
+        lengths = lg["lengths_by_code"]
+        cum = lg["cum"]
+        C = lengths.shape[0]
+        N = int(cum[-1])
+        A = A_of[name]
+        hi_cap = min(max_events, N)
+        lo_cap = min(min_events, hi_cap)
+        S = int(round(np.exp(rng.uniform(np.log(lo_cap), np.log(max(hi_cap, lo_cap))))))
+        p = int(rng.integers(0, C))
+        h = int(np.searchsorted(cum, cum[p] + S, side="left"))
+        h = min(max(h, p + 1), C)
+        if cum[h] - cum[p] < S:
+            p = max(int(np.searchsorted(cum, cum[h] - S, side="right")) - 1, 0)
+        f = rng.uniform(0.05, 1.0)
+        span = lg["t_max"] - lg["t_min"]
+        w = int(f * span)
+        tl = lg["t_min"] + int(rng.integers(0, max(1, span - w + 1)))
+        k = int(rng.integers(min(8, A), A + 1))
+        mask = np.zeros((A + 63) // 64, np.uint64)
+        for a in rng.choice(A, size=k, replace=False):
+            mask[a // 64] |= np.uint64(1) << np.uint64(a % 64)
+        kind = kinds[int(rng.choice(len(kinds), p=probs))]
+        out.append(Request(rid=rid, log=name, kind=kind, case_lo=p, case_hi=h, t_lo=tl, t_hi=tl + w,
+                           mask=mask, arrival=t))
+        rid += 1
+    return out
+
+
+class GpuExecutor:
+    """Runs batches with libpm4g; one HIP stream and workspace per worker thread."""
+
+    def __init__(self, logs: dict, device="cuda:0"):
+        import torch
+
+        from . import pm4g
+        self.torch = torch
+        self.pm4g = pm4g
+        self.device = torch.device(device)
+        self.logs = {}
+        for name, prep in logs.items():
+            C = int(prep.n_cases.item())
+            off = prep.case_off[:C + 1].cpu().numpy()
+            codes = prep.case_code[:C].cpu().numpy()
+            self.logs[name] = dict(prep=prep, off=off, codes=codes)
+        self._local = threading.local()
+
+    def slice_events(self, r: Request) -> int:
+        lg = self.logs[r.log]
+        a = int(np.searchsorted(lg["codes"], r.case_lo, side="left"))
+        b = int(np.searchsorted(lg["codes"], r.case_hi, side="left"))
+        return int(lg["off"][b] - lg["off"][a]) if b > a else 0
+
+    def estimate(self, r: Request) -> int:
+        """Workspace estimate: records and cells of a batched view, or filtered log + variants."""
+        S = self.slice_events(r)
+        if r.kind == "variants":
+            return 2048 + S * 16 + S * 90
+        return 2048 + S * 30
+
+    def _stream(self):
+        s = getattr(self._local, "stream", None)
+        if s is None:
+            s = self.torch.cuda.Stream(device=self.device)
+            self._local.stream = s
+        return s
+
+    def run(self, batch: list[Request]) -> None:
+        torch = self.torch
+        pm4g = self.pm4g
+        s = self._stream()
+        with torch.cuda.stream(s):
+            by_log: dict[str, list[Request]] = {}
+            for r in batch:
+                if r.kind in ("dfg", "filter"):
+                    by_log.setdefault(r.log, []).append(r)
+            for name, rs in by_log.items():
+                prep = self.logs[name]["prep"]
+                A = prep.n_activities
+                rec = np.zeros(len(rs), dtype=np.dtype([("lo", "<i4"), ("hi", "<i4"), ("t_lo", "<i8"),
+                                                       ("t_hi", "<i8")]))
+                rec["lo"] = [r.case_lo for r in rs]
+                rec["hi"] = [r.case_hi for r in rs]
+                rec["t_lo"] = [r.t_lo for r in rs]
+                rec["t_hi"] = [r.t_hi for r in rs]
+                masks = np.stack([r.mask for r in rs]).view(np.int64)
+                vd = torch.from_numpy(rec.view(np.uint8).copy()).to(self.device, non_blocking=False)
+                md = torch.from_numpy(np.ascontiguousarray(masks)).to(self.device)
+                o = pm4g.pm4g_dfg_batched(prep, vd, md, len(rs), stream=s)
+                res = pm4g.batched_to_host(o, len(rs), A)
+                for r, d in zip(rs, res):
+                    if r.kind == "filter":
+                        r.result = dict(n_events=d["n_events"], n_cases=d["n_cases"])
+                    else:
+                        r.result = d
+            for r in batch:
+                if r.kind != "variants":
+                    continue
+                prep = self.logs[r.log]["prep"]
+                rec = np.zeros(1, dtype=np.dtype([("lo", "<i4"), ("hi", "<i4"), ("t_lo", "<i8"),
+                                                  ("t_hi", "<i8")]))
+                rec["lo"], rec["hi"], rec["t_lo"], rec["t_hi"] = r.case_lo, r.case_hi, r.t_lo, r.t_hi
+                vd = torch.from_numpy(rec.view(np.uint8).copy()).to(self.device)
+                md = torch.from_numpy(np.ascontiguousarray(r.mask).view(np.int64).copy()).to(self.device)
+                cap = max(self.slice_events(r), 1)
+                sub = pm4g.pm4g_filter_view(prep, vd, md, stream=s,
+                                            out=pm4g.Prepared.empty(cap, prep.n_activities, self.device))
+                v = pm4g.pm4g_variants_prepared(sub, stream=s)
+                s.synchronize()
+                C = int(sub.n_cases.item())
+                h = pm4g.variants_to_host(v, C)
+                h["n_events"] = int(sub.case_off[C].item())
+                h["n_cases"] = C
+                r.result = h
+        s.synchronize()

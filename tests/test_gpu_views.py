@@ -1,0 +1,110 @@
+"""GPU parity of the batched drill-down views against the oracle's view
+function (filter, then re-discover), view by view, bit-exact."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2204_04898_amd import pm4g, synth
+from tests.gpu_util import cols, note, same_f64
+
+pytestmark = pytest.mark.gpu
+INT64_MIN = np.iinfo(np.int64).min
+INT64_MAX = np.iinfo(np.int64).max
+
+
+def dense_to_sparse(o, A):
+    nz = np.flatnonzero(o["count"].ravel())
+    return dict(src=(nz // A).astype(np.int32), dst=(nz % A).astype(np.int32),
+                count=o["count"].ravel()[nz], dt_sum=o["dt_sum"].ravel()[nz],
+                dt_min=o["dt_min"].ravel()[nz], dt_max=o["dt_max"].ravel()[nz],
+                dt_mean=o["dt_mean"].ravel()[nz])
+
+
+def check_views(log, views, tuning=None, sample=None):
+    A = log.n_activities
+    c, a, t = cols(log.case, log.act, log.ts)
+    prep = pm4g.pm4g_prepare(c, a, t, A, presorted=log.presorted)
+    vd, md = pm4g.views_to_device(views, "cuda:0")
+    V = views.n_views
+    o = pm4g.pm4g_dfg_batched(prep, vd, md, V, tuning=tuning)
+    res = pm4g.batched_to_host(o, V, A)
+    idx = range(V) if sample is None else sample
+    for v in idx:
+        ref = oracle.view(log.case, log.act, log.ts, A, int(views.case_lo[v]), int(views.case_hi[v]),
+                          int(views.t_lo[v]), int(views.t_hi[v]), views.masks[v])
+        sp = dense_to_sparse(ref, A)
+        g = res[v]
+        for k in ("src", "dst", "count", "dt_sum", "dt_min", "dt_max"):
+            assert np.array_equal(g[k], sp[k]), (v, k)
+        assert same_f64(g["dt_mean"], sp["dt_mean"]), v
+        for k in ("start_count", "end_count", "act_count"):
+            assert np.array_equal(g[k], ref[k]), (v, k)
+        assert g["n_events"] == ref["n_events"] and g["n_cases"] == ref["n_cases"], v
+    return res
+
+
+@pytest.mark.parametrize("tile", [2048, 4096])
+def test_views_scaled_workload(tile):
+    log = synth.config_log(3, 0.004)          # ~400k events, 512 activities
+    views = synth.make_views(log, 48, seed=7, min_events=50, max_events=300_000)
+    note(f"views: N={log.n_events} V={views.n_views} tile={tile}")
+    t = pm4g.BatchedTuning(tile_events=tile)
+    check_views(log, views, tuning=t)
+
+
+def test_views_small_activity_set_and_edge_views():
+    log = synth.config_log(2, 0.01)           # ~100k events, 64 activities, 5% tied timestamps
+    A = log.n_activities
+    base = synth.make_views(log, 20, seed=3, min_events=10, max_events=50_000)
+    C = int(log.case.max()) + 1
+    full = np.full((1, 1), np.uint64(0xFFFFFFFFFFFFFFFF))
+    extra_lo = np.array([0, 5, 10, 0, 3, -7], np.int32)
+    extra_hi = np.array([C, 5, 4, C, 4, C + 10], np.int32)       # full, empty, reversed, ...
+    extra_tl = np.array([INT64_MIN, INT64_MIN, INT64_MIN, 0, INT64_MIN, INT64_MIN], np.int64)
+    extra_th = np.array([INT64_MAX, INT64_MAX, INT64_MAX, -1, INT64_MAX, INT64_MAX], np.int64)
+    extra_m = np.repeat(full, 6, axis=0)
+    extra_m[4] = 0                                                # empty activity set
+    extra_m[5] = np.uint64(0x5555555555555555)
+    views = synth.Views(case_lo=np.concatenate([base.case_lo, extra_lo]),
+                        case_hi=np.concatenate([base.case_hi, extra_hi]),
+                        t_lo=np.concatenate([base.t_lo, extra_tl]), t_hi=np.concatenate([base.t_hi, extra_th]),
+                        masks=np.concatenate([base.masks, extra_m]))
+    res = check_views(log, views)
+    # the unfiltered view equals the plain DFG
+    d = oracle.dfg(log.case, log.act, log.ts, A)
+    assert int(res[base.n_views]["count"].sum()) == int(d["count"].sum())
+    assert res[base.n_views + 1]["n_events"] == 0
+
+
+def test_views_long_cases_cross_tiles():
+    """Cases longer than a tile: the previous kept event comes from an earlier tile."""
+    rng = np.random.default_rng(9)
+    lens = [9000, 3, 5000, 1, 2500] + list(rng.integers(1, 40, 400))
+    case = np.repeat(np.arange(len(lens), dtype=np.int32), lens)
+    n = case.size
+    A = 16
+    act = rng.integers(0, A, n).astype(np.int32)
+    ts = rng.integers(0, 10**6, n, dtype=np.int64)
+    perm = rng.permutation(n)
+    log = synth.Log(case=case[perm], act=act[perm], ts=ts[perm], n_activities=A, presorted=False,
+                    lengths_by_code=np.asarray(lens, np.int64))
+    V = 12
+    lo = rng.integers(0, 3, V).astype(np.int32)
+    hi = (lo + rng.integers(1, len(lens), V)).astype(np.int32)
+    tl = rng.integers(0, 300_000, V)
+    th = tl + rng.integers(100_000, 10**6, V)
+    masks = np.zeros((V, 1), np.uint64)
+    for v in range(V):
+        for x in rng.choice(A, rng.integers(1, A + 1), replace=False):
+            masks[v, 0] |= np.uint64(1) << np.uint64(x)
+    views = synth.Views(case_lo=lo, case_hi=hi, t_lo=tl, t_hi=th, masks=masks)
+    check_views(log, views, tuning=pm4g.BatchedTuning(tile_events=2048))
+
+
+def test_views_capacity_retry():
+    """Tiny capacities force the PM4G_E_CAPACITY path; the binding retries with what was required."""
+    log = synth.config_log(3, 0.002)
+    views = synth.make_views(log, 16, seed=11, min_events=100, max_events=100_000)
+    t = pm4g.BatchedTuning(pair_capacity=8, record_capacity=64, descriptor_capacity=16, cell_capacity=16)
+    check_views(log, views, tuning=t)

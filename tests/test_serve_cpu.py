@@ -1,0 +1,93 @@
+"""Scheduler logic of the serving loop on the CPU: a fake executor with
+known memory estimates and service times (no GPU)."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_2204_04898_amd.serve import Request, Scheduler, latency_stats
+
+
+class FakeExecutor:
+    def __init__(self, est, service_s=0.002, fail_rids=()):
+        self.est = est
+        self.service_s = service_s
+        self.fail = set(fail_rids)
+        self.lock = threading.Lock()
+        self.concurrent = 0
+        self.max_concurrent = 0
+        self.batches = []
+
+    def estimate(self, r):
+        return self.est(r)
+
+    def run(self, batch):
+        with self.lock:
+            self.concurrent += 1
+            self.max_concurrent = max(self.max_concurrent, self.concurrent)
+            self.batches.append([r.rid for r in batch])
+        time.sleep(self.service_s)
+        for r in batch:
+            if r.rid in self.fail:
+                raise RuntimeError("executor failure")
+            r.result = {"rid": r.rid}
+        with self.lock:
+            self.concurrent -= 1
+
+
+def reqs(n, gap=0.0005, kind="dfg"):
+    return [Request(rid=i, log="L", kind=kind, case_lo=0, case_hi=1, t_lo=0, t_hi=1,
+                    mask=np.zeros(1, np.uint64), arrival=i * gap) for i in range(n)]
+
+
+def test_every_request_completes_fifo_within_budget():
+    ex = FakeExecutor(est=lambda r: 100 + 10 * (r.rid % 7))
+    sch = Scheduler(ex, mem_budget=600, max_batch=8, workers=2)
+    out = sch.run(reqs(60))
+    assert [r.rid for r in out] == list(range(60))
+    assert all(r.error is None and r.result == {"rid": r.rid} for r in out)
+    assert sch.max_in_flight_bytes <= 600
+    assert ex.max_concurrent <= 2
+    # FIFO: batches are contiguous runs in arrival order
+    flat = [rid for b in sch.batches for rid in b]
+    assert flat == sorted(flat)
+    assert all(len(b) <= 8 for b in sch.batches)
+    # latency is measured from the scheduled arrival
+    assert all(r.done >= r.arrival and r.dispatched >= r.arrival - 1e-9 for r in out)
+
+
+def test_requests_arriving_during_a_batch_join_a_later_batch():
+    ex = FakeExecutor(est=lambda r: 1, service_s=0.02)
+    sch = Scheduler(ex, mem_budget=10**9, max_batch=1000, workers=1)
+    out = sch.run(reqs(20, gap=0.003))
+    assert len(sch.batches) >= 2 and len(sch.batches[0]) < 20
+    assert all(r.error is None for r in out)
+
+
+def test_oversized_request_rejected_others_served():
+    ex = FakeExecutor(est=lambda r: 10**6 if r.rid == 3 else 10)
+    sch = Scheduler(ex, mem_budget=1000, max_batch=4, workers=2)
+    out = sch.run(reqs(10))
+    assert out[3].error == "request exceeds the memory budget" and out[3].result is None
+    assert all(r.error is None for r in out if r.rid != 3)
+    st = latency_stats(out)
+    assert st["n"] == 9 and st["rejected"] == 1
+
+
+def test_head_is_never_skipped():
+    # a big request waits for memory; smaller ones behind it do not overtake it
+    ex = FakeExecutor(est=lambda r: 900 if r.rid == 1 else 200, service_s=0.01)
+    sch = Scheduler(ex, mem_budget=1000, max_batch=10, workers=2)
+    out = sch.run(reqs(6, gap=0.0))
+    order = [rid for b in sch.batches for rid in b]
+    assert order == sorted(order)
+    assert all(r.error is None for r in out)
+
+
+def test_executor_failure_is_reported_per_request():
+    ex = FakeExecutor(est=lambda r: 1, fail_rids={5})
+    sch = Scheduler(ex, mem_budget=100, max_batch=1, workers=2)
+    out = sch.run(reqs(8))
+    assert out[5].error and "executor failure" in out[5].error
+    assert all(r.error is None for r in out if r.rid != 5)
