@@ -193,7 +193,75 @@ def bench_serving(logs: dict, preps: dict, seconds: float, rate: float) -> dict:
     return st
 
 
+def calibrate_copy(gib: float = 1.0, reps: int = 3) -> None:
+    """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+
+    n = int(gib * (1 << 30))
+    x = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "reps": reps}))
+
+
+def _counter_rows(path: str, kernel: str, counter: str) -> list[float]:
+    import csv
+
+    vals = []
+    with open(path) as fh:
+        for row in csv.DictReader(fh):
+            if kernel in row.get("Kernel_Name", "") and row.get("Counter_Name") == counter:
+                vals.append(float(row["Counter_Value"]))
+    return vals
+
+
+def summarize_counters(a) -> None:
+    """Writes profiles/traffic_<stage>_<workload>.txt from two rocprofv3 --pmc runs of the
+    benchmark (FETCH_SIZE, WRITE_SIZE in KiB per dispatch) and of the copy calibration."""
+    fetch = _counter_rows(a.fetch_csv, a.kernel, "FETCH_SIZE")
+    write = _counter_rows(a.write_csv, a.kernel, "WRITE_SIZE")
+    cf = _counter_rows(a.copy_fetch_csv, a.copy_kernel, "FETCH_SIZE")
+    cw = _counter_rows(a.copy_write_csv, a.copy_kernel, "WRITE_SIZE")
+    if not (fetch and write and cf and cw):
+        raise SystemExit("counter rows missing for the kernel or the copy kernel")
+    copy_bytes = float(a.copy_bytes)
+    f_scale = copy_bytes / (sum(cf) / len(cf) * 1024.0)
+    w_scale = copy_bytes / (sum(cw) / len(cw) * 1024.0)
+    fb = sum(fetch) / len(fetch) * 1024.0 * f_scale
+    wb = sum(write) / len(write) * 1024.0 * w_scale
+    path = os.path.join(ROOT, "profiles", f"traffic_{a.stage}_{a.workload}.txt")
+    with open(path, "w") as fh:
+        fh.write(f"# HBM traffic of {a.kernel} (stage {a.stage}) on the {a.workload} workload, per launch\n")
+        fh.write("# from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of:\n")
+        fh.write(f"#   {a.command}\n")
+        fh.write("# scaled by the same counters on a plain copy of copy_bytes bytes "
+                 "(python3 bench.py --calibrate-copy)\n")
+        fh.write(f"kernel = {a.kernel}\nstage = {a.stage}\n")
+        fh.write(f"launches_fetch = {len(fetch)}\nlaunches_write = {len(write)}\n")
+        fh.write(f"fetch_kib_per_launch = {sum(fetch) / len(fetch):.1f}\n")
+        fh.write(f"write_kib_per_launch = {sum(write) / len(write):.1f}\n")
+        fh.write(f"copy_bytes = {int(copy_bytes)}\ncopy_fetch_scale = {f_scale:.4f}\ncopy_write_scale = {w_scale:.4f}\n")
+        fh.write(f"bytes_per_launch = {fb + wb:.0f}\n")
+        fh.write(f"source_sha = {source_sha(STAGE_SOURCES[a.stage])}\n")
+    print(path)
+
+
 def main() -> int:
+    if "--calibrate-copy" in sys.argv:
+        calibrate_copy()
+        return 0
+    if "--summarize-counters" in sys.argv:
+        sp = argparse.ArgumentParser()
+        sp.add_argument("--summarize-counters", action="store_true")
+        for k in ("fetch-csv", "write-csv", "copy-fetch-csv", "copy-write-csv", "kernel", "stage", "workload",
+                  "command"):
+            sp.add_argument("--" + k, required=True)
+        sp.add_argument("--copy-kernel", default="copy")
+        sp.add_argument("--copy-bytes", type=int, default=1 << 30)
+        summarize_counters(sp.parse_args())
+        return 0
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)

@@ -184,17 +184,20 @@ int run_prepare(const pm4g_log* log, const pm4g_prepared* out, bool case_table, 
     } else if (n > 0) {
         const SortBufs raw{(uint32_t*)log->case_id, (int64_t*)log->timestamp, (uint32_t*)log->activity};
         const int case_bits = bits_of((uint64_t)(uint32_t)(h.case_max - h.case_min));
+        const int act_bits = bits_of((uint64_t)(A - 1));
+        // packed keys (activity above the case bits) when both fit in 32 bits
+        const int act_shift = (case_bits > 0 && case_bits < 32 && case_bits + act_bits <= 32) ? case_bits : 0;
         int passes = (case_bits + 7) / 8;
         if (passes == 0) passes = 1;   // a single case: one pass still biases the keys
         SortBufs bufs[2] = {w.a, w.b};
         SortBufs in = raw;
         int cur = 0;
         for (int p = 0; p < passes; ++p) {
-            PM4G_HIP(launch_radix_pass(in, bufs[cur], n, 0, 8 * p, p == 0, w.info, w.hist, w.rowsum, s));
+            PM4G_HIP(launch_radix_pass(in, bufs[cur], n, 0, 8 * p, p == 0, w.info, w.hist, w.rowsum, act_shift, s));
             in = bufs[cur];
             cur ^= 1;
         }
-        PM4G_HIP(launch_segsort(in, n, w.info, out->case_s, out->act_s, out->ts_s, s));
+        PM4G_HIP(launch_segsort(in, n, w.info, out->case_s, out->act_s, out->ts_s, act_shift, s));
         PM4G_HIP(hipMemcpyAsync(&h, w.info, sizeof(h), hipMemcpyDeviceToHost, s));
         PM4G_HIP(hipStreamSynchronize(s));
         if (h.long_case) {
@@ -208,16 +211,18 @@ int run_prepare(const pm4g_log* log, const pm4g_prepared* out, bool case_table, 
             cur = 0;
             bool first = true;
             for (int p = 0; p < ts_passes; ++p, first = false) {
-                PM4G_HIP(launch_radix_pass(in, bufs[cur], n, 1, 8 * p, first, w.info, w.hist, w.rowsum, s));
+                PM4G_HIP(launch_radix_pass(in, bufs[cur], n, 1, 8 * p, first, w.info, w.hist, w.rowsum,
+                                           act_shift, s));
                 in = bufs[cur];
                 cur ^= 1;
             }
             for (int p = 0; p < passes; ++p, first = false) {
-                PM4G_HIP(launch_radix_pass(in, bufs[cur], n, 0, 8 * p, first, w.info, w.hist, w.rowsum, s));
+                PM4G_HIP(launch_radix_pass(in, bufs[cur], n, 0, 8 * p, first, w.info, w.hist, w.rowsum,
+                                           act_shift, s));
                 in = bufs[cur];
                 cur ^= 1;
             }
-            PM4G_HIP(launch_unbias_copy(in, n, w.info, out->case_s, out->act_s, out->ts_s, s));
+            PM4G_HIP(launch_unbias_copy(in, n, w.info, out->case_s, out->act_s, out->ts_s, act_shift, s));
         }
     }
     if (case_table)

@@ -52,28 +52,41 @@ __global__ __launch_bounds__(1024) void k_case_scan(uint32_t* blockcnt, int64_t 
 __global__ __launch_bounds__(kCB) void k_case_emit(const int32_t* __restrict__ case_s, int64_t n,
                                                    const uint32_t* blockoff, int64_t* case_off,
                                                    int32_t* case_code) {
+    // striped layout (coalesced loads): item k of thread t is position base + k*256 + t,
+    // so position order is (k, wave, lane) order; ranks from ballots + one small scan
+    constexpr int kNW = kCB / kWave;
+    __shared__ uint32_t wcnt[kCI * kNW];
     __shared__ uint32_t tmp[kCB / kWave + 1];
-    // blocked layout so that ranks follow positions
-    const int64_t base = (int64_t)blockIdx.x * kCaseTile + (int64_t)threadIdx.x * kCI;
-    uint32_t flags = 0;
+    const int64_t base = (int64_t)blockIdx.x * kCaseTile;
+    const int w = threadIdx.x / kWave;
+    uint64_t masks[kCI];
     int32_t cv[kCI];
 #pragma unroll
-    for (int q = 0; q < kCI; ++q) {
-        const int64_t i = base + q;
-        cv[q] = 0;
+    for (int k = 0; k < kCI; ++k) {
+        const int64_t i = base + k * kCB + threadIdx.x;
+        bool f = false;
+        cv[k] = 0;
         if (i < n) {
-            cv[q] = case_s[i];
-            if (i == 0 || cv[q] != case_s[i - 1]) flags |= 1u << q;
+            cv[k] = case_s[i];
+            f = (i == 0) || cv[k] != case_s[i - 1];
         }
+        masks[k] = __ballot(f);
+        if (lane() == 0) wcnt[k * kNW + w] = (uint32_t)__popcll(masks[k]);
     }
+    __syncthreads();
+    // exclusive scan of the kCI * kNW (k-major) wave counts; kCI * kNW = 64 <= kCB
     uint32_t total;
-    uint32_t r = block_excl_sum<kCB>((uint32_t)__popc(flags), tmp, &total) + blockoff[blockIdx.x];
+    const uint32_t v = threadIdx.x < kCI * kNW ? wcnt[threadIdx.x] : 0u;
+    const uint32_t ex = block_excl_sum<kCB>(v, tmp, &total);
+    if (threadIdx.x < kCI * kNW) wcnt[threadIdx.x] = ex;
+    __syncthreads();
+    const uint32_t b0 = blockoff[blockIdx.x];
 #pragma unroll
-    for (int q = 0; q < kCI; ++q) {
-        if (flags & (1u << q)) {
-            case_off[r] = base + q;
-            case_code[r] = cv[q];
-            ++r;
+    for (int k = 0; k < kCI; ++k) {
+        if ((masks[k] >> lane()) & 1ull) {
+            const uint32_t r = b0 + wcnt[k * kNW + w] + (uint32_t)__popcll(masks[k] & lanes_below());
+            case_off[r] = base + k * kCB + threadIdx.x;
+            case_code[r] = cv[k];
         }
     }
 }

@@ -48,22 +48,25 @@ struct SortBufs {
 };
 constexpr int kRadixTile = 4096;
 inline int64_t radix_blocks(int64_t n) { return (n + kRadixTile - 1) / kRadixTile; }
-// One stable pass on an 8-bit digit.  digit_src 0: (key >> shift) & 255;
+// One stable pass on an 8-bit digit.  digit_src 0: ((key & case bits) >> shift) & 255;
 // digit_src 1: ((ts - ts_min) >> shift) & 255.  With `first`, the input is
 // the raw log (in.key is the int32 case id, biased by case_min on the fly).
+// act_shift > 0 selects the packed layout: key = case | act << act_shift and
+// no activity column (act_shift = number of case bits, case bits + activity
+// bits <= 32); act_shift = 0: separate activity column.
 hipError_t launch_radix_pass(SortBufs in, SortBufs out, int64_t n, int digit_src, int shift,
                              bool first, const RangeInfo* info, uint32_t* hist, uint32_t* rowsum,
-                             hipStream_t s);
+                             int act_shift, hipStream_t s);
 
 // ---- per-case ordering of a case-grouped sequence (segsort.hip) ----
 constexpr int kSegWindow = 1024;
 constexpr int kSegCap = 3072;   // window + the longest case kept on the fast path (2049) - 1
 inline int64_t segsort_blocks(int64_t n) { return (n + kSegWindow - 1) / kSegWindow; }
 hipError_t launch_segsort(SortBufs in, int64_t n, RangeInfo* info, int32_t* case_s, int32_t* act_s,
-                          int64_t* ts_s, hipStream_t s);
+                          int64_t* ts_s, int act_shift, hipStream_t s);
 // Copies fully sorted buffers (fallback path) into the prepared arrays.
 hipError_t launch_unbias_copy(SortBufs in, int64_t n, const RangeInfo* info, int32_t* case_s,
-                              int32_t* act_s, int64_t* ts_s, hipStream_t s);
+                              int32_t* act_s, int64_t* ts_s, int act_shift, hipStream_t s);
 // Copies a presorted raw log into the prepared arrays.
 hipError_t launch_copy_log(const int32_t* c, const int32_t* a, const int64_t* t, int64_t n,
                            int32_t* case_s, int32_t* act_s, int64_t* ts_s, hipStream_t s);

@@ -10,7 +10,10 @@
 // This is the grouping step of Sec. 3's first formatting step: events of a
 // case become adjacent while keeping their row order (stability); the
 // per-case timestamp order is applied afterwards in LDS (segsort.hip).
-// Bytes per event per pass: 4 (hist) + 16 read + 16 write.
+// Packed layout (PACKED): when the case bits and the activity bits fit in 32,
+// the activity rides in the key above the case bits (key_mask selects the
+// case bits) and no activity column moves: 12 bytes per element.
+// Bytes per event per pass: 4 (hist) + 16 read + 16 write (12 + 12 packed).
 #include "common.hpp"
 #include "internal.hpp"
 #include "prof.hpp"
@@ -22,21 +25,27 @@ constexpr int kRI = kRadixTile / kRB;  // items per thread (8)
 constexpr int kRW = kRB / kWave;       // waves per block (8)
 
 template <int SRC>
-__device__ __forceinline__ uint32_t digit_of(uint32_t key, int64_t ts, int shift, int64_t ts_min) {
-    if (SRC == 0) return (key >> shift) & 255u;
+__device__ __forceinline__ uint32_t digit_of(uint32_t key, int64_t ts, int shift, int64_t ts_min,
+                                             uint32_t key_mask) {
+    if (SRC == 0) return ((key & key_mask) >> shift) & 255u;
     return (uint32_t)(((uint64_t)ts - (uint64_t)ts_min) >> shift) & 255u;
 }
 
-template <bool FIRST>
-__device__ __forceinline__ uint32_t load_key(const uint32_t* key, int64_t i, int32_t case_min) {
-    if (FIRST) return (uint32_t)reinterpret_cast<const int32_t*>(key)[i] - (uint32_t)case_min;
-    return key[i];
+// The first pass reads the raw columns: key = case - case_min (| act << act_shift when packed).
+template <bool FIRST, bool PACKED>
+__device__ __forceinline__ uint32_t load_key(const SortBufs& in, int64_t i, int32_t case_min, int act_shift) {
+    if (FIRST) {
+        uint32_t k = (uint32_t)reinterpret_cast<const int32_t*>(in.key)[i] - (uint32_t)case_min;
+        if (PACKED) k |= (uint32_t)reinterpret_cast<const int32_t*>(in.act)[i] << act_shift;
+        return k;
+    }
+    return in.key[i];
 }
 
 template <int SRC, bool FIRST>
 __global__ __launch_bounds__(kRB) void k_radix_hist(SortBufs in, int64_t n, int shift,
                                                     const RangeInfo* info, uint32_t* hist,
-                                                    int64_t nb) {
+                                                    int64_t nb, uint32_t key_mask) {
     __shared__ uint32_t h[256];
     if (threadIdx.x < 256) h[threadIdx.x] = 0;
     __syncthreads();
@@ -48,8 +57,8 @@ __global__ __launch_bounds__(kRB) void k_radix_hist(SortBufs in, int64_t n, int 
         const int64_t i = base + k * kRB + threadIdx.x;
         if (i < n) {
             uint32_t d;
-            if (SRC == 0) d = digit_of<0>(load_key<FIRST>(in.key, i, case_min), 0, shift, 0);
-            else d = digit_of<1>(0, in.ts[i], shift, ts_min);
+            if (SRC == 0) d = digit_of<0>(load_key<FIRST, false>(in, i, case_min, 0), 0, shift, 0, key_mask);
+            else d = digit_of<1>(0, in.ts[i], shift, ts_min, key_mask);
             atomicAdd(&h[d], 1u);
         }
     }
@@ -85,10 +94,11 @@ __global__ __launch_bounds__(256) void k_radix_scan(uint32_t* hist, int64_t nb, 
     if (threadIdx.x == 0) rowsum[blockIdx.x] = run;
 }
 
-template <int SRC, bool FIRST>
+template <int SRC, bool FIRST, bool PACKED>
 __global__ __launch_bounds__(kRB) void k_radix_scatter(SortBufs in, SortBufs out, int64_t n, int shift,
                                                        const RangeInfo* info, const uint32_t* hist,
-                                                       const uint32_t* rowsum, int64_t nb) {
+                                                       const uint32_t* rowsum, int64_t nb,
+                                                       uint32_t key_mask, int act_shift) {
     __shared__ uint32_t cnt[kRW * 256];       // per-wave running digit counts
     __shared__ uint32_t tstart[256];          // tile-local start of each digit
     __shared__ int64_t gshift[256];           // global position - tile position
@@ -111,15 +121,15 @@ __global__ __launch_bounds__(kRB) void k_radix_scatter(SortBufs in, SortBufs out
     for (int k = 0; k < kRI; ++k) {
         const int64_t i = wbase + k * kWave + lane();
         if (i < n) {
-            key[k] = load_key<FIRST>(in.key, i, case_min);
+            key[k] = load_key<FIRST, PACKED>(in, i, case_min, act_shift);
             tv[k] = in.ts[i];
-            act[k] = in.act[i];
+            act[k] = PACKED ? 0u : in.act[i];
         } else {
             key[k] = 0;
             tv[k] = ts_min;
             act[k] = 0;
         }
-        dg[k] = digit_of<SRC>(key[k], tv[k], shift, ts_min);
+        dg[k] = digit_of<SRC>(key[k], tv[k], shift, ts_min, key_mask);
     }
     __syncthreads();
 
@@ -168,7 +178,7 @@ __global__ __launch_bounds__(kRB) void k_radix_scatter(SortBufs in, SortBufs out
             const uint32_t pos = tstart[dg[k]] + cnt[w * 256 + dg[k]] + rk[k];
             skey[pos] = key[k];
             sts[pos] = tv[k];
-            sact[pos] = act[k];
+            if (!PACKED) sact[pos] = act[k];
         }
     }
     __syncthreads();
@@ -177,41 +187,47 @@ __global__ __launch_bounds__(kRB) void k_radix_scatter(SortBufs in, SortBufs out
     for (int i = threadIdx.x; i < valid_count; i += kRB) {
         const uint32_t k = skey[i];
         const int64_t t = sts[i];
-        const uint32_t d = digit_of<SRC>(k, t, shift, ts_min);
+        const uint32_t d = digit_of<SRC>(k, t, shift, ts_min, key_mask);
         const int64_t g = gshift[d] + i;
         out.key[g] = k;
         out.ts[g] = t;
-        out.act[g] = sact[i];
+        if (!PACKED) out.act[g] = sact[i];
     }
 }
 
-template <int SRC, bool FIRST>
+template <int SRC, bool FIRST, bool PACKED>
 static void run_pass(SortBufs in, SortBufs out, int64_t n, int shift, const RangeInfo* info,
-                     uint32_t* hist, uint32_t* rowsum, hipStream_t s) {
+                     uint32_t* hist, uint32_t* rowsum, uint32_t key_mask, int act_shift, hipStream_t s) {
     const int64_t nb = radix_blocks(n);
     {
         ProfScope p(P_RADIX_HIST, s);
-        k_radix_hist<SRC, FIRST><<<(unsigned)nb, kRB, 0, s>>>(in, n, shift, info, hist, nb);
+        k_radix_hist<SRC, FIRST><<<(unsigned)nb, kRB, 0, s>>>(in, n, shift, info, hist, nb, key_mask);
     }
     {
         ProfScope p(P_RADIX_SCAN, s);
         k_radix_scan<<<256, 256, 0, s>>>(hist, nb, rowsum);
     }
     ProfScope p(P_RADIX_SCATTER, s);
-    k_radix_scatter<SRC, FIRST><<<(unsigned)nb, kRB, 0, s>>>(in, out, n, shift, info, hist, rowsum, nb);
+    k_radix_scatter<SRC, FIRST, PACKED><<<(unsigned)nb, kRB, 0, s>>>(in, out, n, shift, info, hist, rowsum,
+                                                                      nb, key_mask, act_shift);
 }
 
 hipError_t launch_radix_pass(SortBufs in, SortBufs out, int64_t n, int digit_src, int shift,
                              bool first, const RangeInfo* info, uint32_t* hist, uint32_t* rowsum,
-                             hipStream_t s) {
+                             int act_shift, hipStream_t s) {
     if (n <= 0) return hipSuccess;
+    const bool packed = act_shift > 0;
+    const uint32_t key_mask = packed ? ((act_shift >= 32) ? 0xFFFFFFFFu : ((1u << act_shift) - 1u)) : 0xFFFFFFFFu;
+#define PM4G_PASS(SRC, FIRST, PACKED) \
+    run_pass<SRC, FIRST, PACKED>(in, out, n, shift, info, hist, rowsum, key_mask, act_shift, s)
     if (digit_src == 0) {
-        if (first) run_pass<0, true>(in, out, n, shift, info, hist, rowsum, s);
-        else run_pass<0, false>(in, out, n, shift, info, hist, rowsum, s);
+        if (first) { if (packed) PM4G_PASS(0, true, true); else PM4G_PASS(0, true, false); }
+        else { if (packed) PM4G_PASS(0, false, true); else PM4G_PASS(0, false, false); }
     } else {
-        if (first) run_pass<1, true>(in, out, n, shift, info, hist, rowsum, s);
-        else run_pass<1, false>(in, out, n, shift, info, hist, rowsum, s);
+        if (first) { if (packed) PM4G_PASS(1, true, true); else PM4G_PASS(1, true, false); }
+        else { if (packed) PM4G_PASS(1, false, true); else PM4G_PASS(1, false, false); }
     }
+#undef PM4G_PASS
     return hipGetLastError();
 }
 

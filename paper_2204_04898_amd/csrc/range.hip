@@ -28,10 +28,9 @@ __global__ __launch_bounds__(256) void k_range_scan(const int32_t* __restrict__ 
     int32_t cmin = INT32_MAX, cmax = INT32_MIN;
     int64_t tmin = INT64_MAX, tmax = INT64_MIN;
     bool bad_act = false, unsorted = false;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const int32_t c = case_id[i];
-        const int32_t a = act[i];
+    auto visit = [&](int64_t i, int32_t c, int32_t a) {
         bad_act |= (uint32_t)a >= (uint32_t)A;
         cmin = c < cmin ? c : cmin;
         cmax = c > cmax ? c : cmax;
@@ -45,6 +44,25 @@ __global__ __launch_bounds__(256) void k_range_scan(const int32_t* __restrict__ 
                 unsorted |= (c0 > c) || (c0 == c && t0 > t);
             }
         }
+    };
+    if (!WANT_TS && !PRESORTED) {
+        // 16-byte loads of four ids and four activities (the columns are 16-byte aligned
+        // torch/hip allocations; a misaligned start falls back to the scalar loop)
+        const bool aligned = ((reinterpret_cast<uintptr_t>(case_id) | reinterpret_cast<uintptr_t>(act)) & 15) == 0;
+        const int64_t n4 = aligned ? n / 4 : 0;
+        const int4* c4 = reinterpret_cast<const int4*>(case_id);
+        const int4* a4 = reinterpret_cast<const int4*>(act);
+        for (int64_t q = tid; q < n4; q += stride) {
+            const int4 c = c4[q];
+            const int4 a = a4[q];
+            visit(4 * q, c.x, a.x);
+            visit(4 * q + 1, c.y, a.y);
+            visit(4 * q + 2, c.z, a.z);
+            visit(4 * q + 3, c.w, a.w);
+        }
+        for (int64_t i = 4 * n4 + tid; i < n; i += stride) visit(i, case_id[i], act[i]);
+    } else {
+        for (int64_t i = tid; i < n; i += stride) visit(i, case_id[i], act[i]);
     }
     cmin = wave_min(cmin);
     cmax = wave_max(cmax);

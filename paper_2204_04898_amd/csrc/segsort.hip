@@ -51,10 +51,11 @@ __device__ __forceinline__ int32_t wave_incl_max_i32(int32_t v) {
     return v;
 }
 
+// act_shift > 0: packed keys (case bits below act_shift, activity above).
 __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeInfo* info,
                                                  int32_t* __restrict__ case_s,
                                                  int32_t* __restrict__ act_s,
-                                                 int64_t* __restrict__ ts_s) {
+                                                 int64_t* __restrict__ ts_s, int act_shift) {
     __shared__ uint32_t lkey[kSegCap];
     __shared__ int64_t lts[kSegCap];
     __shared__ uint16_t lact[kSegCap];
@@ -65,13 +66,14 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
     __shared__ int32_t wred[kSB / kWave];
 
     const uint32_t* __restrict__ key = in.key;
+    const uint32_t kmask = act_shift > 0 ? ((1u << act_shift) - 1u) : 0xFFFFFFFFu;
     const int64_t w0 = (int64_t)blockIdx.x * kSegWindow;
     const int64_t w1 = (w0 + kSegWindow) < n ? (w0 + kSegWindow) : n;
 
     // 1. first case start inside the window
     int64_t cand = INT64_MAX;
     for (int64_t p = w0 + threadIdx.x; p < w1; p += kSB) {
-        if (p == 0 || key[p] != key[p - 1]) {
+        if (p == 0 || ((key[p] ^ key[p - 1]) & kmask) != 0) {
             cand = p;
             break;
         }
@@ -85,7 +87,7 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
         const int64_t p = base + threadIdx.x;
         int64_t c = INT64_MAX;
         if (p == n) c = n;
-        else if (p < n && key[p] != key[p - 1]) c = p;
+        else if (p < n && ((key[p] ^ key[p - 1]) & kmask) != 0) c = p;
         const int64_t m = block_min_i64(c, red);
         if (m != INT64_MAX) {
             e = m;
@@ -100,9 +102,10 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
 
     // 3. stage the region
     for (int i = threadIdx.x; i < R; i += kSB) {
-        lkey[i] = key[s + i];
+        const uint32_t kr = key[s + i];
+        lkey[i] = kr & kmask;
         lts[i] = in.ts[s + i];
-        lact[i] = (uint16_t)in.act[s + i];
+        lact[i] = (uint16_t)(act_shift > 0 ? (kr >> act_shift) : in.act[s + i]);
     }
     __syncthreads();
 
@@ -233,12 +236,14 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
 }
 
 __global__ void k_unbias_copy(SortBufs in, int64_t n, const RangeInfo* info, int32_t* case_s,
-                              int32_t* act_s, int64_t* ts_s) {
+                              int32_t* act_s, int64_t* ts_s, int act_shift) {
     const uint32_t bias = (uint32_t)info->case_min;
+    const uint32_t kmask = act_shift > 0 ? ((1u << act_shift) - 1u) : 0xFFFFFFFFu;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        case_s[i] = (int32_t)(in.key[i] + bias);
-        act_s[i] = (int32_t)in.act[i];
+        const uint32_t k = in.key[i];
+        case_s[i] = (int32_t)((k & kmask) + bias);
+        act_s[i] = (int32_t)(act_shift > 0 ? (k >> act_shift) : in.act[i]);
         ts_s[i] = in.ts[i];
     }
 }
@@ -259,15 +264,15 @@ static unsigned copy_grid(int64_t n) {
 }
 
 hipError_t launch_segsort(SortBufs in, int64_t n, RangeInfo* info, int32_t* case_s, int32_t* act_s,
-                          int64_t* ts_s, hipStream_t s) {
+                          int64_t* ts_s, int act_shift, hipStream_t s) {
     ProfScope p(P_SEGSORT, s);
-    if (n > 0) k_segsort<<<(unsigned)segsort_blocks(n), kSB, 0, s>>>(in, n, info, case_s, act_s, ts_s);
+    if (n > 0) k_segsort<<<(unsigned)segsort_blocks(n), kSB, 0, s>>>(in, n, info, case_s, act_s, ts_s, act_shift);
     return hipGetLastError();
 }
 
 hipError_t launch_unbias_copy(SortBufs in, int64_t n, const RangeInfo* info, int32_t* case_s,
-                              int32_t* act_s, int64_t* ts_s, hipStream_t s) {
-    if (n > 0) k_unbias_copy<<<copy_grid(n), 256, 0, s>>>(in, n, info, case_s, act_s, ts_s);
+                              int32_t* act_s, int64_t* ts_s, int act_shift, hipStream_t s) {
+    if (n > 0) k_unbias_copy<<<copy_grid(n), 256, 0, s>>>(in, n, info, case_s, act_s, ts_s, act_shift);
     return hipGetLastError();
 }
 

@@ -93,3 +93,35 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(pm4g, "LIB_PATH", "/nonexistent/libpm4g.so")
     with pytest.raises(RuntimeError, match="missing"):
         pm4g.load()
+
+
+def test_batched_and_filter_validation():
+    lib = pm4g.load()
+    ws = ctypes.c_void_p(0x1000)
+    prep = pm4g._Prepared(*([_fake(0)] * 7), 100, 2000)        # A above the batched limit
+    out = pm4g._BatchedOut(*([_fake(0)] * 13), 10, _fake(0), _fake(0))
+    assert lib.pm4g_dfg_batched(ctypes.byref(prep), _fake(0), _fake(0), 4, ctypes.byref(out), None, ws,
+                                1 << 40, None) == pm4g.PM4G_E_INVALID
+    prep = pm4g._Prepared(*([_fake(0)] * 7), 100, 16)
+    assert lib.pm4g_dfg_batched(ctypes.byref(prep), None, None, 4, ctypes.byref(out), None, ws,
+                                1 << 40, None) == pm4g.PM4G_E_INVALID
+    assert lib.pm4g_dfg_batched(ctypes.byref(prep), _fake(0), _fake(0), -1, ctypes.byref(out), None, ws,
+                                1 << 40, None) == pm4g.PM4G_E_INVALID
+    bad_t = pm4g.BatchedTuning(tile_events=1000)
+    assert lib.pm4g_dfg_batched(ctypes.byref(prep), _fake(0), _fake(0), 4, ctypes.byref(out),
+                                ctypes.byref(bad_t), ws, 1 << 40, None) == pm4g.PM4G_E_INVALID
+    assert lib.pm4g_dfg_batched(ctypes.byref(prep), _fake(0), _fake(0), 4, ctypes.byref(out), None, ws,
+                                16, None) == pm4g.PM4G_E_WORKSPACE
+    assert lib.pm4g_batched_workspace_bytes(100, 16, 4, None) > 0
+    assert lib.pm4g_batched_workspace_bytes(100, 2000, 4, None) == 0
+    t = pm4g.BatchedTuning(record_capacity=10**6)
+    assert lib.pm4g_batched_workspace_bytes(100, 16, 4, ctypes.byref(t)) > lib.pm4g_batched_workspace_bytes(
+        100, 16, 4, None)
+    fo = pm4g._Prepared(*([_fake(0)] * 7), 100, 8)                 # A differs
+    assert lib.pm4g_filter_view(ctypes.byref(prep), _fake(0), _fake(0), ctypes.byref(fo), ws, 1 << 40,
+                                None) == pm4g.PM4G_E_INVALID
+    fo = pm4g._Prepared(*([_fake(0)] * 7), 100, 16)
+    assert lib.pm4g_filter_view(ctypes.byref(prep), None, _fake(0), ctypes.byref(fo), ws, 1 << 40,
+                                None) == pm4g.PM4G_E_INVALID
+    assert lib.pm4g_filter_view(ctypes.byref(prep), _fake(0), _fake(0), ctypes.byref(fo), ws, 8,
+                                None) == pm4g.PM4G_E_WORKSPACE
