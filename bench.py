@@ -126,13 +126,14 @@ def cpu_baseline(log, target_events: int) -> dict:
                       f"rows in log order): DFG + variants, single thread, {dt:.2f} s"}
 
 
-def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int) -> dict:
+def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int, autotune: bool = True) -> dict:
     """Batched drill-down views over the prepared log: one call for all views,
     against a loop of one-view calls of the same entry point."""
     import numpy as np
     import torch
 
     from paper_2204_04898_amd import pm4g, synth
+    from paper_2204_04898_amd import tune as tuner
 
     views = synth.make_views(log, n_views, seed=synth.SEED_BASE + 4)
     visits = int(np.sum([log.lengths_by_code[views.case_lo[v]:views.case_hi[v]].sum() for v in range(n_views)]))
@@ -141,8 +142,19 @@ def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int) -> di
     out = pm4g.pm4g_dfg_batched(prep, vd, md, n_views)          # sizes the capacities (retries)
     log_progress(f"views: first call (capacity sizing) {time.perf_counter() - t0:.2f} s")
     req = [int(x) for x in out["required"].cpu().tolist()]
-    tune = pm4g.BatchedTuning(pair_capacity=int(req[3] * 1.1) + 1024, record_capacity=int(req[1] * 1.1) + 1024,
-                              descriptor_capacity=int(req[2] * 1.1) + 1024, cell_capacity=int(req[4] * 1.1) + 1024)
+    tuned = None
+    if autotune:
+        t0 = time.perf_counter()
+        res = tuner.tune_batched(prep, vd, md, n_views, reps=2, log=log_progress)
+        log_progress(f"views: autotune sweep {time.perf_counter() - t0:.1f} s")
+        tune = res["tuning"]
+        tuned = {k: res["best"][k] for k in ("tile_events", "emit_blocks", "agg_blocks")}
+        tuned["sweep"] = len(res["table"])
+    else:
+        tune = pm4g.BatchedTuning(pair_capacity=int(req[3] * 1.1) + 1024,
+                                  record_capacity=int(req[1] * 1.1) + 1024,
+                                  descriptor_capacity=int(req[2] * 1.1) + 1024,
+                                  cell_capacity=int(req[4] * 1.1) + 1024)
     out = pm4g.pm4g_dfg_batched(prep, vd, md, n_views, tuning=tune, out=out)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -164,7 +176,10 @@ def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int) -> di
             "event_view_visits": visits, "output_cells": req[0], "records": req[1],
             "per_view_launch_views_per_s": 1.0 / per_view_s,
             "per_view_launch_sample": len(idx),
-            "speedup_vs_per_view_launches": per_view_s * n_views / dt}
+            "speedup_vs_per_view_launches": per_view_s * n_views / dt,
+            "tuning": tuned if tuned is not None else {"tile_events": tune.tile_events or 4096,
+                                                       "emit_blocks": tune.emit_blocks or 512,
+                                                       "agg_blocks": tune.agg_blocks or 512}}
 
 
 def bench_serving(logs: dict, preps: dict, seconds: float, rate: float) -> dict:
@@ -273,6 +288,8 @@ def main() -> int:
     ap.add_argument("--views", type=int, default=4096, help="batched drill-down views (0: skip)")
     ap.add_argument("--view-steps", type=int, default=3)
     ap.add_argument("--per-view-sample", type=int, default=64)
+    ap.add_argument("--no-autotune", action="store_true", help="batched views with the library's default shape")
+    ap.add_argument("--tune-cache", default=None, help="autotune cache file (default: the package's)")
     ap.add_argument("--serve-seconds", type=float, default=8.0, help="serving run length (0: skip)")
     ap.add_argument("--serve-qps", type=float, default=200.0)
     args = ap.parse_args()
@@ -366,7 +383,10 @@ def main() -> int:
     }
     if args.views > 0 and k == 3:
         log_progress(f"batched views: {args.views} views")
-        out["batched_views"] = bench_views(log, prep, args.views, args.view_steps, args.per_view_sample)
+        if args.tune_cache:
+            os.environ["PM4G_TUNE_CACHE"] = args.tune_cache
+        out["batched_views"] = bench_views(log, prep, args.views, args.view_steps, args.per_view_sample,
+                                           autotune=not args.no_autotune)
     if args.serve_seconds > 0 and k == 3:
         log_progress("serving: generating the 10M-event log")
         log2 = synth.config_log(2)

@@ -3,7 +3,7 @@
 //
 // Input: the radix output, grouped by case, each case's events in row order
 // (the passes are stable).  Block w owns the cases that START inside window
-// [w*1024, (w+1)*1024); their events (at most 1023 + 2049 = 3072 when no case
+// [w*W, (w+1)*W); their events (at most W - 1 + 2049 = kSegCap when no case
 // is longer than 2049 events) are staged in LDS.  The staged region is cut
 // into 64-event chunks; each wave sorts its chunks in registers with a
 // bitonic network on (case, timestamp, staging position) -- the staging
@@ -12,11 +12,24 @@
 // rank in its case is its rank in its own portion plus, for each other
 // portion, the number of smaller events found by binary search:
 // O(L/64 * log 64) comparisons per event instead of O(L).
+//
+// Sort key.  When every staged event lies within 2^51 time units of its
+// case's first staged event (block-uniform check; ns timestamps: 26 days per
+// case), the three fields fold into one u64 per event:
+//   [63:58] case slot in the chunk (count of case starts before it)
+//   [57:6]  timestamp - case base + 2^51
+//   [5:0]   lane (= staging order inside the chunk)
+// and the network moves 2 dwords per stage with one 64-bit compare; the lane
+// bits name the event, the timestamp is rebuilt from the base.  Otherwise the
+// network compares (case start, timestamp, staging position) field by field.
+// Lane exchanges: quad permutes and a row rotate (DPP) for distances 1, 2, 8,
+// swizzles for 4 and 16, a permute for 32.
+//
 // A region longer than the LDS window sets RangeInfo::long_case and the
 // host switches to the full-key fallback.
 //
 // Also writes the prepared columns: case id (unbiased), activity, timestamp.
-// Bytes per event: 16 read + 16 write.
+// Bytes per event: 16 read + 16 write (12 + 16 packed).
 #include "common.hpp"
 #include "internal.hpp"
 #include "prof.hpp"
@@ -24,22 +37,38 @@
 namespace pm4g {
 
 constexpr int kSB = 512;
-constexpr int kSI = kSegCap / kSB;   // 6 items per thread
+constexpr int kSW = kSB / kWave;     // waves per block
+constexpr int kSI = kSegCap / kSB;   // items per thread = chunks per wave
+static_assert(kSegCap % kSB == 0, "staging capacity must be a multiple of the block");
 
 __device__ __forceinline__ int64_t block_min_i64(int64_t v, int64_t* red) {
     v = wave_min(v);
-    const int w = threadIdx.x / kWave;
-    if (lane() == 0) red[w] = v;
+    if (lane() == 0) red[threadIdx.x / kWave] = v;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t m = red[0];
-        for (int i = 1; i < kSB / kWave; ++i) m = red[i] < m ? red[i] : m;
-        red[kSB / kWave] = m;
+    int64_t m = red[0];
+#pragma unroll
+    for (int i = 1; i < kSW; ++i) m = red[i] < m ? red[i] : m;
+    __syncthreads();
+    return m;
+}
+
+// Block minimum of two values at once (one barrier pair).
+__device__ __forceinline__ void block_min2_i64(int64_t& a, int64_t& b, int64_t* red) {
+    a = wave_min(a);
+    b = wave_min(b);
+    if (lane() == 0) {
+        red[threadIdx.x / kWave] = a;
+        red[kSW + threadIdx.x / kWave] = b;
     }
     __syncthreads();
-    const int64_t r = red[kSB / kWave];
+    a = red[0];
+    b = red[kSW];
+#pragma unroll
+    for (int i = 1; i < kSW; ++i) {
+        a = red[i] < a ? red[i] : a;
+        b = red[kSW + i] < b ? red[kSW + i] : b;
+    }
     __syncthreads();
-    return r;
 }
 
 __device__ __forceinline__ int32_t wave_incl_max_i32(int32_t v) {
@@ -51,48 +80,112 @@ __device__ __forceinline__ int32_t wave_incl_max_i32(int32_t v) {
     return v;
 }
 
+// Value of lane (lane ^ J); every lane of the wave must be active.
+template <int J>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
+    if constexpr (J == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);   // quad [1,0,3,2]
+    else if constexpr (J == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // quad [2,3,0,1]
+    else if constexpr (J == 8) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false); // row rotate 8
+    else if constexpr (J == 4 || J == 16) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (J << 10) | 0x1F);
+    else return (uint32_t)__shfl_xor((int)v, J);
+}
+
+template <int J>
+__device__ __forceinline__ uint64_t xor_lane64(uint64_t v) {
+    const uint32_t lo = xor_lane<J>((uint32_t)v);
+    const uint32_t hi = xor_lane<J>((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// One bitonic merge level (block size M) on one u64 key per lane, ascending.
+template <int M, int J>
+__device__ __forceinline__ void merge_u64(uint64_t& k, int l) {
+    if constexpr (J > 0) {
+        const uint64_t p = xor_lane64<J>(k);
+        const bool flip = ((l & M) == 0) != ((l & J) == 0);
+        k = ((p < k) != flip) ? p : k;
+        merge_u64<M, J / 2>(k, l);
+    }
+}
+
+__device__ __forceinline__ void bitonic64_u64(uint64_t& k, int l) {
+    merge_u64<2, 1>(k, l);
+    merge_u64<4, 2>(k, l);
+    merge_u64<8, 4>(k, l);
+    merge_u64<16, 8>(k, l);
+    merge_u64<32, 16>(k, l);
+    merge_u64<64, 32>(k, l);
+}
+
+// Field-by-field network: (case start c, timestamp t, staging position id).
+template <int M, int J>
+__device__ __forceinline__ void merge_3(uint32_t& c, int64_t& t, uint32_t& id, int l) {
+    if constexpr (J > 0) {
+        const uint32_t pc = xor_lane<J>(c);
+        const int64_t pt = (int64_t)xor_lane64<J>((uint64_t)t);
+        const uint32_t pid = xor_lane<J>(id);
+        const bool pless = (pc < c) | ((pc == c) & ((pt < t) | ((pt == t) & (pid < id))));
+        const bool flip = ((l & M) == 0) != ((l & J) == 0);
+        const bool take = pless != flip;
+        c = take ? pc : c;
+        t = take ? pt : t;
+        id = take ? pid : id;
+        merge_3<M, J / 2>(c, t, id, l);
+    }
+}
+
+__device__ __forceinline__ void bitonic64_3(uint32_t& c, int64_t& t, uint32_t& id, int l) {
+    merge_3<2, 1>(c, t, id, l);
+    merge_3<4, 2>(c, t, id, l);
+    merge_3<8, 4>(c, t, id, l);
+    merge_3<16, 8>(c, t, id, l);
+    merge_3<32, 16>(c, t, id, l);
+    merge_3<64, 32>(c, t, id, l);
+}
+
+constexpr uint64_t kOffBias = 1ull << 51;
+constexpr uint64_t kOffMask = (1ull << 52) - 1;
+
 // act_shift > 0: packed keys (case bits below act_shift, activity above).
 __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeInfo* info,
                                                  int32_t* __restrict__ case_s,
                                                  int32_t* __restrict__ act_s,
                                                  int64_t* __restrict__ ts_s, int act_shift) {
-    __shared__ uint32_t lkey[kSegCap];
     __shared__ int64_t lts[kSegCap];
     __shared__ uint16_t lact[kSegCap];
     __shared__ uint16_t lidx[kSegCap];   // staging position of the event now at i
-    __shared__ uint16_t lcs[kSegCap];
-    __shared__ uint16_t lce[kSegCap + 1];
-    __shared__ int64_t red[kSB / kWave + 1];
-    __shared__ int32_t wred[kSB / kWave];
+    __shared__ uint16_t lcs[kSegCap];    // case start of position i
+    __shared__ uint16_t lce[kSegCap];    // case end, stored at the case start
+    __shared__ int64_t red[2 * kSW];
+    __shared__ int32_t wred[kSW];
 
     const uint32_t* __restrict__ key = in.key;
     const uint32_t kmask = act_shift > 0 ? ((1u << act_shift) - 1u) : 0xFFFFFFFFu;
     const int64_t w0 = (int64_t)blockIdx.x * kSegWindow;
     const int64_t w1 = (w0 + kSegWindow) < n ? (w0 + kSegWindow) : n;
+    auto is_start = [&](int64_t p) { return p == 0 || ((key[p] ^ key[p - 1]) & kmask) != 0; };
 
-    // 1. first case start inside the window
-    int64_t cand = INT64_MAX;
+    // 1. first case start inside the window, first at or after its end (n counts)
+    int64_t s = INT64_MAX, e = INT64_MAX;
     for (int64_t p = w0 + threadIdx.x; p < w1; p += kSB) {
-        if (p == 0 || ((key[p] ^ key[p - 1]) & kmask) != 0) {
-            cand = p;
+        if (is_start(p)) {
+            s = p;
             break;
         }
     }
-    const int64_t s = block_min_i64(cand, red);
+    {
+        const int64_t p = w1 + threadIdx.x;
+        if (p == n) e = n;
+        else if (p < n && is_start(p)) e = p;
+    }
+    block_min2_i64(s, e, red);
     if (s == INT64_MAX) return;   // a long case covers the whole window (block-uniform)
-
-    // 2. first case start at or after the window end (n counts as a start)
-    int64_t e = INT64_MAX;
-    for (int64_t base = w1; base <= n && base - s <= kSegCap; base += kSB) {
+    for (int64_t base = w1 + kSB; e == INT64_MAX && base <= n && base - s <= kSegCap; base += kSB) {
         const int64_t p = base + threadIdx.x;
         int64_t c = INT64_MAX;
         if (p == n) c = n;
-        else if (p < n && ((key[p] ^ key[p - 1]) & kmask) != 0) c = p;
-        const int64_t m = block_min_i64(c, red);
-        if (m != INT64_MAX) {
-            e = m;
-            break;
-        }
+        else if (p < n && is_start(p)) c = p;
+        e = block_min_i64(c, red);
     }
     if (e == INT64_MAX || e - s > kSegCap) {
         if (threadIdx.x == 0) atomicOr(&info->long_case, 1);
@@ -100,28 +193,35 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
     }
     const int R = (int)(e - s);
 
-    // 3. stage the region
-    for (int i = threadIdx.x; i < R; i += kSB) {
-        const uint32_t kr = key[s + i];
-        lkey[i] = kr & kmask;
-        lts[i] = in.ts[s + i];
-        lact[i] = (uint16_t)(act_shift > 0 ? (kr >> act_shift) : in.act[s + i]);
+    // 2. stage the region; case ids stay in registers (same striped mapping as the output)
+    uint32_t ck[kSI];
+#pragma unroll
+    for (int q = 0; q < kSI; ++q) {
+        const int i = threadIdx.x + q * kSB;
+        ck[q] = 0;
+        if (i < R) {
+            const uint32_t kr = key[s + i];
+            ck[q] = kr & kmask;
+            lts[i] = in.ts[s + i];
+            lact[i] = (uint16_t)(act_shift > 0 ? (kr >> act_shift) : in.act[s + i]);
+            lcs[i] = (uint16_t)((i == 0 || ((kr ^ key[s + i - 1]) & kmask) != 0) ? i : 0);
+        }
     }
     __syncthreads();
 
-    // 4. case start of every event: inclusive max-scan of start positions
-    //    (blocked layout: thread t owns items 8t .. 8t+7)
+    // 3. case start of every event: inclusive max-scan of the start positions
+    //    (blocked layout: thread t owns items kSI*t .. kSI*t + kSI - 1)
     {
         int32_t loc[kSI];
         int32_t m = 0;
 #pragma unroll
         for (int q = 0; q < kSI; ++q) {
             const int i = threadIdx.x * kSI + q;
-            if (i < R && (i == 0 || lkey[i] != lkey[i - 1])) m = i;
+            if (i < R) m = (int32_t)lcs[i] > m ? (int32_t)lcs[i] : m;
             loc[q] = m;
         }
         const int w = threadIdx.x / kWave;
-        int32_t inc = wave_incl_max_i32(m);
+        const int32_t inc = wave_incl_max_i32(m);
         if (lane() == kWave - 1) wred[w] = inc;
         __syncthreads();
         int32_t before = 0;
@@ -138,41 +238,69 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
     __syncthreads();
     // case end, stored at the case start: the last event of each case writes it
     for (int i = threadIdx.x; i < R; i += kSB) {
-        if (i == R - 1 || lkey[i + 1] != lkey[i]) lce[lcs[i]] = (uint16_t)(i + 1);
+        if (i == R - 1 || lcs[i + 1] == i + 1) lce[lcs[i]] = (uint16_t)(i + 1);
     }
-    __syncthreads();
 
-    // 5. sort every 64-event chunk in registers by (case, ts, staging position)
-    {
-        const int w = threadIdx.x / kWave;
-        const int l = lane();
-        for (int ch = w; ch * kWave < R; ch += kSB / kWave) {
+    // 4. sort every 64-event chunk in registers (wave w: chunks w, w + kSW, ...)
+    const int w = threadIdx.x / kWave;
+    const int l = lane();
+    uint64_t sk[kSI];
+    int64_t sb[kSI];
+    bool fits = true;
+#pragma unroll
+    for (int q = 0; q < kSI; ++q) {
+        const int ch = w + q * kSW;
+        const int i = ch * kWave + l;
+        sk[q] = ~0ull;   // padding sorts last
+        sb[q] = 0;
+        if (ch * kWave < R) {   // wave-uniform
+            const bool valid = i < R;
+            const int cs = valid ? (int)lcs[i] : 0;
+            const bool first = l == 0 || (valid && cs == i);
+            const uint64_t starts = __ballot(first);
+            const uint32_t slot = (uint32_t)__popcll(starts & lanes_below()) + (first ? 1u : 0u) - 1u;
+            if (valid) {
+                const int64_t base = lts[cs];
+                const int64_t t = lts[i];
+                const bool ok = t >= base ? ((uint64_t)t - (uint64_t)base < kOffBias)
+                                          : ((uint64_t)base - (uint64_t)t <= kOffBias);
+                fits &= ok;
+                sk[q] = ((uint64_t)slot << 58) | ((((uint64_t)t - (uint64_t)base + kOffBias) & kOffMask) << 6) |
+                        (uint64_t)l;
+                sb[q] = base;
+            }
+        }
+    }
+    const bool fast = __syncthreads_and(fits);   // also: every read of step 4 precedes the writes below
+    if (fast) {
+#pragma unroll
+        for (int q = 0; q < kSI; ++q) {
+            const int ch = w + q * kSW;
+            if (ch * kWave >= R) continue;   // wave-uniform
+            uint64_t k = sk[q];
+            bitonic64_u64(k, l);
             const int i = ch * kWave + l;
-            uint32_t k = 0xFFFFFFFFu, id = 0x10000u + (uint32_t)l;   // padding sorts last
+            if (i < R) {
+                // position i holds an event of the same case as staging position i
+                lidx[i] = (uint16_t)(ch * kWave + (int)(k & 63u));
+                lts[i] = (int64_t)((uint64_t)sb[q] + ((k >> 6) & kOffMask) - kOffBias);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < kSI; ++q) {
+            const int ch = w + q * kSW;
+            if (ch * kWave >= R) continue;   // wave-uniform
+            const int i = ch * kWave + l;
+            uint32_t c = 0xFFFFFFFFu, id = 0x10000u + (uint32_t)l;   // padding sorts last
             int64_t t = INT64_MAX;
             if (i < R) {
-                k = lkey[i];
+                c = lcs[i];
                 t = lts[i];
                 id = (uint32_t)i;
             }
-#pragma unroll
-            for (int m = 2; m <= kWave; m <<= 1) {
-#pragma unroll
-                for (int j = m >> 1; j > 0; j >>= 1) {
-                    const uint32_t pk = __shfl_xor(k, j);
-                    const int64_t pt = __shfl_xor(t, j);
-                    const uint32_t pid = __shfl_xor(id, j);
-                    // branch-free compare-exchange: keep the partner iff it belongs here
-                    const bool pless = (pk < k) | ((pk == k) & ((pt < t) | ((pt == t) & (pid < id))));
-                    const bool flip = ((l & m) == 0) != ((l & j) == 0);
-                    const bool take = pless != flip;
-                    k = take ? pk : k;
-                    t = take ? pt : t;
-                    id = take ? pid : id;
-                }
-            }
+            bitonic64_3(c, t, id, l);
             if (i < R) {
-                lkey[i] = k;   // unchanged: the chunk was already grouped by case
                 lts[i] = t;
                 lidx[i] = (uint16_t)id;
             }
@@ -180,9 +308,8 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
     }
     __syncthreads();
 
-    // 6. rank inside the case: own portion + binary searches in the other portions
+    // 5. rank inside the case: own portion + binary searches in the other portions
     int32_t pos[kSI];
-    uint32_t kv[kSI];
     int64_t tv[kSI];
     uint16_t av[kSI];
 #pragma unroll
@@ -210,7 +337,6 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
                 r += lo - p0;
             }
             pos[q] = cs + r;
-            kv[q] = lkey[i];
             tv[q] = t;
             av[q] = lact[id];
         }
@@ -219,19 +345,22 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
 #pragma unroll
     for (int q = 0; q < kSI; ++q) {
         if (pos[q] >= 0) {
-            lkey[pos[q]] = kv[q];
             lts[pos[q]] = tv[q];
             lact[pos[q]] = av[q];
         }
     }
     __syncthreads();
 
-    // 7. write the prepared columns
+    // 6. write the prepared columns (position i keeps the case of staging position i)
     const uint32_t bias = (uint32_t)info->case_min;
-    for (int i = threadIdx.x; i < R; i += kSB) {
-        case_s[s + i] = (int32_t)(lkey[i] + bias);
-        act_s[s + i] = (int32_t)lact[i];
-        ts_s[s + i] = lts[i];
+#pragma unroll
+    for (int q = 0; q < kSI; ++q) {
+        const int i = threadIdx.x + q * kSB;
+        if (i < R) {
+            case_s[s + i] = (int32_t)(ck[q] + bias);
+            act_s[s + i] = (int32_t)lact[i];
+            ts_s[s + i] = lts[i];
+        }
     }
 }
 

@@ -344,14 +344,25 @@ def pm4g_dfg_batched(prep: Prepared, views: torch.Tensor, masks: torch.Tensor, n
     """DFGs of n_views drill-down views in one pass (Sec. 1 drill-down, Sec. 3 filters).
 
     views: device uint8 tensor of n_views packed pm4g_view records; masks: device
-    int64 tensor [n_views, ceil(A/64)].  Synchronises the stream.  With `retry`,
+    int64 tensor [n_views, ceil(A/64)].  With no `tuning`, the launch shape
+    comes from the autotune cache (tune.py).  Synchronises the stream.  With `retry`,
     capacities found too small are raised to what the call reported and the
     call is repeated.
     """
     L = load()
     A = prep.n_activities
     dev = prep.case_s.device
-    t = BatchedTuning() if tuning is None else BatchedTuning.from_buffer_copy(tuning)
+    if tuning is None:
+        # launch shape from the autotune cache (capacities are sized below)
+        from . import tune
+        t = BatchedTuning()
+        hit = tune.default_cache().lookup(A, n_views, prep.n_events)
+        if hit is not None:
+            t.tile_events = int(hit["tile_events"])
+            t.emit_blocks = int(hit["emit_blocks"])
+            t.agg_blocks = int(hit["agg_blocks"])
+    else:
+        t = BatchedTuning.from_buffer_copy(tuning)
     cap = int(cap_edges) if cap_edges is not None else max(1024, min(prep.n_events, 1 << 24))
     o = out if out is not None else _batched_out(n_views, A, cap, dev)
     for _ in range(6):
