@@ -42,16 +42,37 @@ def log_progress(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_bytes(stage: str, n: int, c: int, A: int, presorted: bool) -> float | None:
-    """Algorithmic HBM bytes one launch of a stage must move (reads + writes)."""
+def packed_keys(log) -> bool:
+    """Whether the library carries the activity inside the radix key: case-id
+    bits plus activity bits fit in 32 (the rule of the formatting step)."""
+    span = int(log.case.max()) - int(log.case.min()) if log.case.size else 0
+    case_bits = span.bit_length()
+    act_bits = max(log.n_activities - 1, 0).bit_length()
+    return 0 < case_bits < 32 and case_bits + act_bits <= 32
+
+
+def radix_passes(log) -> int:
+    span = int(log.case.max()) - int(log.case.min()) if log.case.size else 0
+    return max(1, (span.bit_length() + 7) // 8)
+
+
+def kernel_bytes(stage: str, n: int, c: int, A: int, presorted: bool, packed: bool = False,
+                 passes: int = 1) -> float | None:
+    """Algorithmic HBM bytes one launch of a stage must move (reads + writes),
+    averaged over the launches of one step where they differ."""
     e = n - c   # directly-follows pairs
+    # radix scatter: the first pass reads the raw columns (case, act, ts = 16 B),
+    # later passes the previous pass's elements; each writes one element.
+    elem = 12.0 if packed else 16.0
+    scatter_total = (16.0 + elem) * n + (passes - 1) * 2 * elem * n
     model = {
         "range_scan": 8.0 * n + (8.0 * n if presorted else 0.0),      # case + act (+ ts)
         "radix_hist": 4.0 * n,                                        # case key
         "radix_scan": None,
-        "radix_scatter": 32.0 * n,                                    # (key, ts, act) in + out
-        "segsort": 32.0 * n,                                          # (key, ts, act) in, (case, act, ts) out
+        "radix_scatter": scatter_total / passes,
+        "segsort": (elem + 16.0) * n,                                 # sorted elements in, (case, act, ts) out
         "case_table": 8.0 * n + 12.0 * c,                             # case column twice, offsets + codes
+        "dfg_count": 8.0 * n,                                         # case + act (A > 64)
         "dfg_main": 16.0 * n + (10.0 * e if A > 64 else 0.0),         # prepared log (+ bucketed edges)
         "dfg_agg": 10.0 * e,                                          # bucketed edges
         "variant_hash": 4.0 * n + 8.0 * c + 12.0 * c,                 # activities, offsets, hash + index
@@ -71,6 +92,7 @@ STAGE_SOURCES = {
     "radix_scatter": ["paper_2204_04898_amd/csrc/radix.hip", "paper_2204_04898_amd/csrc/common.hpp"],
     "radix_hist": ["paper_2204_04898_amd/csrc/radix.hip", "paper_2204_04898_amd/csrc/common.hpp"],
     "segsort": ["paper_2204_04898_amd/csrc/segsort.hip", "paper_2204_04898_amd/csrc/common.hpp"],
+    "dfg_count": ["paper_2204_04898_amd/csrc/dfg.hip", "paper_2204_04898_amd/csrc/common.hpp"],
     "dfg_main": ["paper_2204_04898_amd/csrc/dfg.hip", "paper_2204_04898_amd/csrc/common.hpp"],
     "dfg_agg": ["paper_2204_04898_amd/csrc/dfg.hip", "paper_2204_04898_amd/csrc/common.hpp"],
 }
@@ -353,11 +375,12 @@ def main() -> int:
 
     stages = {name: {"ms_per_step": tot / args.steps, "launches_per_step": cnt / args.steps}
               for name, (tot, cnt) in prof.items() if cnt}
-    dominant = max(((n, v) for n, v in prof.items() if kernel_bytes(n, N, C, A, log.presorted)),
-                   key=lambda kv: kv[1][0])
+    packed, passes = packed_keys(log), radix_passes(log)
+    kb = lambda name: kernel_bytes(name, N, C, A, log.presorted, packed, passes)
+    dominant = max(((n, v) for n, v in prof.items() if kb(n) and v[1]), key=lambda kv: kv[1][0])
     dname, (dms, dcnt) = dominant
     per_launch_ms = dms / dcnt
-    algo = kernel_bytes(dname, N, C, A, log.presorted)
+    algo = kb(dname)
     achieved = algo / (per_launch_ms * 1e-3) / 1e9
     traffic = measured_traffic(dname, args.workload)
 

@@ -9,18 +9,27 @@
 //   A*A <= 4096  k_dfg_lds: 256 persistent blocks, one privatised LDS table
 //                each (count u32, sum u64, min, max: 112 KB), partial tables
 //                written out and reduced per cell.
-//   A*A >  4096  k_dfg_part: per 4096-event tile, edges are bucketed by
-//                cell >> 12 in LDS and written as runs (u16 cell, u64 gap);
-//                k_dfg_agg: blocks take equal shares of each bucket's edges
-//                (work split by edge counts, so Zipf-heavy buckets get more
-//                blocks), aggregate in a 4096-cell LDS table, write partials.
+//   A*A >  4096  cells are cut into buckets of 4096 (cell >> 12) and the
+//                edges are partitioned bucket-major, so that each bucket's
+//                edges are one contiguous stream:
+//                k_dfg_count    per (bucket, chunk of the log) edge counts,
+//                               and the activity / start / end counts;
+//                scan           first edge index of every (bucket, chunk);
+//                k_dfg_scatter  edges (u16 cell within the bucket, u64 gap)
+//                               written to their place via LDS cursors;
+//                k_dfg_plan     buckets cut into slots of about E/512 edges
+//                               (Zipf-heavy buckets get more slots);
+//                k_dfg_agg      one block per slot streams its edges into a
+//                               4096-cell LDS table, writes a partial table.
 // k_dfg_reduce folds the partial tables, writes the dense outputs and the
 // FP64 mean; k_dfg_acts / k_dfg_final fold the activity counts, n_cases and the
 // overflow flag.
-// Bytes per event: 16 read (+ 10 write + 10 read per edge on the bucketed path).
+// Bytes per event: 16 read (+ 8 read, 10 write and 10 read per edge on the
+// bucketed path).
 #include <math.h>
 
 #include "common.hpp"
+#include "devsort.hpp"
 #include "internal.hpp"
 #include "prof.hpp"
 #include "../../include/pm4g.h"
@@ -28,12 +37,16 @@
 namespace pm4g {
 
 constexpr int kLB = 1024;   // threads of k_dfg_lds
-constexpr int kPB = 512;    // threads of k_dfg_part
 constexpr int kAB = 1024;   // threads of k_dfg_agg
 
-static int64_t dfg_tiles(int64_t n) { return (n + kDfgTile - 1) / kDfgTile; }
 static int64_t n_buckets(int32_t A) {
     return ((int64_t)A * A + kCellsPerTable - 1) / kCellsPerTable;
+}
+// chunk of the log per (bucket, chunk) counter: about 64 buckets per 4096 events
+static int64_t dfg_chunk(int64_t nbk) { return (int64_t)kDfgTile * (nbk <= 64 ? 1 : (nbk + 63) / 64); }
+static int64_t dfg_chunks(int64_t n, int64_t nbk) {
+    const int64_t c = dfg_chunk(nbk);
+    return (n + c - 1) / c;
 }
 
 DfgWs dfg_ws_layout(Bump& b, int64_t n, int32_t A) {
@@ -48,25 +61,29 @@ DfgWs dfg_ws_layout(Bump& b, int64_t n, int32_t A) {
         w.pmax = b.take<int64_t>(slots * kCellsPerTable);
     } else {
         const int64_t nbk = n_buckets(A);
-        const int64_t nbt = dfg_tiles(n);
+        const int64_t nch = dfg_chunks(n, nbk);
         const int64_t slots = nbk + kDfgAggTarget;
         w.n_slots_max = (int32_t)slots;
-        const int64_t g = nbt < kDfgPartBlocks ? (nbt < 1 ? 1 : nbt) : kDfgPartBlocks;
+        const int64_t g = nch < kDfgPartBlocks ? (nch < 1 ? 1 : nch) : kDfgPartBlocks;
         w.n_act_blocks = (int32_t)g;
+        const size_t m = (size_t)(n > 0 ? n : 1);
         w.pcount = b.take<uint32_t>(slots * kCellsPerTable);
         w.psum = b.take<uint64_t>(slots * kCellsPerTable);
         w.pmin = b.take<int64_t>(slots * kCellsPerTable);
         w.pmax = b.take<int64_t>(slots * kCellsPerTable);
-        w.ecell = b.take<uint16_t>((size_t)nbt * kDfgTile);
-        w.egap = b.take<uint64_t>((size_t)nbt * kDfgTile);
-        w.ecnt = b.take<uint32_t>(nbk * nbt);
-        w.ebeg = b.take<uint32_t>(nbk * nbt);
-        w.escan = b.take<uint32_t>(nbk * nbt);
+        w.ecell = b.take<uint16_t>(m);
+        w.egap = b.take<uint64_t>(m);
+        w.ecnt = b.take<uint32_t>((size_t)(nbk * nch) + 1);
+        w.escan = b.take<uint32_t>((size_t)(nbk * nch) + 1);
+        w.bbase = b.take<uint32_t>(nbk);
         w.btotal = b.take<uint32_t>(nbk);
         w.bfirst = b.take<uint32_t>(nbk);
         w.bslots = b.take<uint32_t>(nbk);
         w.plan = b.take<int4>(slots);
         w.nplan = b.take<uint32_t>(1);
+        w.part32 = b.take<uint32_t>(dev::kScanGrid);
+        w.scal = b.take<int64_t>(2);
+        w.utotal = b.take<uint32_t>(1);
     }
     w.pfreq = b.take<uint32_t>((size_t)w.n_act_blocks * A);
     w.pstart = b.take<uint32_t>((size_t)w.n_act_blocks * A);
@@ -157,143 +174,148 @@ __global__ __launch_bounds__(kLB) void k_dfg_lds(const int32_t* __restrict__ cas
 }
 
 // ---------------------------------------------------------------------------
-// A*A > 4096: bucketed edges
+// A*A > 4096: bucket-major edges
 
-__global__ __launch_bounds__(kPB) void k_dfg_part(const int32_t* __restrict__ case_s,
-                                                  const int32_t* __restrict__ act_s,
-                                                  const int64_t* __restrict__ ts_s, int64_t n,
-                                                  int32_t A, int64_t nbt, int64_t nbk, DfgWs ws,
-                                                  int32_t* status) {
-    __shared__ uint32_t sfreq[PM4G_MAX_ACTIVITIES], sstart[PM4G_MAX_ACTIVITIES],
-        send[PM4G_MAX_ACTIVITIES];
-    __shared__ uint32_t bcnt[kCellsPerTable];   // bucket counters (nbk <= 4096)
-    __shared__ uint32_t tmp[kPB / kWave + 1];
-    __shared__ uint64_t sspan[kPB / kWave];
-    constexpr int kPI = kDfgTile / kPB;          // 8 events per thread
+constexpr int kCB = 512;                  // threads of k_dfg_count / k_dfg_scatter
+constexpr int kCI = kDfgTile / kCB;       // events per thread per tile (8)
 
-    for (int a = threadIdx.x; a < A; a += kPB) sfreq[a] = sstart[a] = send[a] = 0;
-    uint64_t span = 0;
+// Per chunk: edge counts per bucket; per block: activity, start and end counts.
+// Dynamic LDS: (3 * A + nbk) u32.
+__global__ __launch_bounds__(kCB) void k_dfg_count(const int32_t* __restrict__ case_s,
+                                                   const int32_t* __restrict__ act_s, int64_t n,
+                                                   int32_t A, int64_t nbk, int64_t nch, int64_t chunk,
+                                                   DfgWs ws, int32_t* status) {
+    extern __shared__ uint32_t dsm[];
+    uint32_t* sfreq = dsm;
+    uint32_t* sstart = dsm + A;
+    uint32_t* send = dsm + 2 * A;
+    uint32_t* bcnt = dsm + 3 * A;
+    for (int a = threadIdx.x; a < 3 * A; a += kCB) dsm[a] = 0;
     bool bad = false;
-
-    for (int64_t t = blockIdx.x; t < nbt; t += gridDim.x) {
-        for (int k = threadIdx.x; k < nbk; k += kPB) bcnt[k] = 0;
+    for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+        for (int64_t k = threadIdx.x; k < nbk; k += kCB) bcnt[k] = 0;
         __syncthreads();
-        uint32_t ecell[kPI], ebk[kPI], eslot[kPI];
-        uint64_t egap[kPI];
-        const int64_t base = t * kDfgTile;
+        const int64_t i1 = (ch + 1) * chunk < n ? (ch + 1) * chunk : n;
+        for (int64_t t0 = ch * chunk; t0 < i1; t0 += kDfgTile) {
+            int32_t c[kCI], cp[kCI], cn[kCI], a[kCI], ap[kCI];
 #pragma unroll
-        for (int q = 0; q < kPI; ++q) {
-            const int64_t i = base + q * kPB + threadIdx.x;
-            ebk[q] = 0xFFFFFFFFu;
-            if (i >= n) continue;
-            const int32_t c = case_s[i];
-            const int32_t a = act_s[i];
-            if ((uint32_t)a >= (uint32_t)A) {
-                bad = true;
-                continue;
+            for (int q = 0; q < kCI; ++q) {
+                const int64_t i = t0 + q * kCB + threadIdx.x;
+                c[q] = cp[q] = cn[q] = a[q] = ap[q] = 0;
+                if (i < i1) {
+                    c[q] = case_s[i];
+                    a[q] = act_s[i];
+                    cp[q] = i > 0 ? case_s[i - 1] : ~c[q];
+                    ap[q] = i > 0 ? act_s[i - 1] : 0;
+                    cn[q] = i + 1 < n ? case_s[i + 1] : ~c[q];
+                }
             }
-            const bool first = (i == 0) || case_s[i - 1] != c;
-            const bool last = (i == n - 1) || case_s[i + 1] != c;
-            atomicAdd(&sfreq[a], 1u);
-            if (first) atomicAdd(&sstart[a], 1u);
-            if (last) atomicAdd(&send[a], 1u);
-            if (!first) {
-                const int32_t p = act_s[i - 1];
-                if ((uint32_t)p >= (uint32_t)A) continue;
-                const uint32_t cell = (uint32_t)p * (uint32_t)A + (uint32_t)a;
-                const uint64_t gap = (uint64_t)ts_s[i] - (uint64_t)ts_s[i - 1];
-                span = sat_add63(span, cap63(gap));
-                ecell[q] = cell & (kCellsPerTable - 1);
-                ebk[q] = cell >> 12;
-                egap[q] = gap;
-                eslot[q] = atomicAdd(&bcnt[ebk[q]], 1u);
-            }
-        }
-        __syncthreads();
-        // exclusive scan of the bucket counts; publish count and start per bucket
-        uint32_t run = 0;
-        for (int64_t k0 = 0; k0 < nbk; k0 += kPB) {
-            const int64_t k = k0 + threadIdx.x;
-            const uint32_t v = k < nbk ? bcnt[k] : 0u;
-            uint32_t total;
-            const uint32_t ex = block_excl_sum<kPB>(v, tmp, &total);
-            if (k < nbk) {
-                ws.ecnt[k * nbt + t] = v;
-                ws.ebeg[k * nbt + t] = run + ex;
-                bcnt[k] = run + ex;
-            }
-            run += total;
-        }
-        __syncthreads();
 #pragma unroll
-        for (int q = 0; q < kPI; ++q) {
-            if (ebk[q] != 0xFFFFFFFFu) {
-                const size_t at = (size_t)base + bcnt[ebk[q]] + eslot[q];
-                ws.ecell[at] = (uint16_t)ecell[q];
-                ws.egap[at] = egap[q];
+            for (int q = 0; q < kCI; ++q) {
+                const int64_t i = t0 + q * kCB + threadIdx.x;
+                if (i >= i1) continue;
+                if ((uint32_t)a[q] >= (uint32_t)A) {
+                    bad = true;
+                    continue;
+                }
+                const bool first = cp[q] != c[q];
+                atomicAdd(&sfreq[a[q]], 1u);
+                if (first) atomicAdd(&sstart[a[q]], 1u);
+                if (cn[q] != c[q]) atomicAdd(&send[a[q]], 1u);
+                if (!first && (uint32_t)ap[q] < (uint32_t)A)
+                    atomicAdd(&bcnt[((uint32_t)ap[q] * (uint32_t)A + (uint32_t)a[q]) >> 12], 1u);
             }
         }
+        __syncthreads();
+        for (int64_t k = threadIdx.x; k < nbk; k += kCB) ws.ecnt[k * nch + ch] = bcnt[k];
         __syncthreads();
     }
     if (__ballot(bad) != 0 && lane() == 0) set_status(status, PM4G_E_RANGE);
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) span = sat_add63(span, __shfl_xor(span, o));
-    if (lane() == 0) sspan[threadIdx.x / kWave] = span;
-    __syncthreads();
     const size_t ab = (size_t)blockIdx.x * A;
-    for (int a = threadIdx.x; a < A; a += kPB) {
+    for (int a = threadIdx.x; a < A; a += kCB) {
         ws.pfreq[ab + a] = sfreq[a];
         ws.pstart[ab + a] = sstart[a];
         ws.pend[ab + a] = send[a];
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) ws.scal[0] = nbk * nch;
+}
+
+// Per chunk: every edge written at its bucket's cursor (LDS, seeded from the
+// scan); order inside a (bucket, chunk) run is free.  Span partial per block.
+// Dynamic LDS: nbk u32.
+__global__ __launch_bounds__(kCB) void k_dfg_scatter(const int32_t* __restrict__ case_s,
+                                                     const int32_t* __restrict__ act_s,
+                                                     const int64_t* __restrict__ ts_s, int64_t n, int32_t A,
+                                                     int64_t nbk, int64_t nch, int64_t chunk, DfgWs ws) {
+    extern __shared__ uint32_t cur[];
+    __shared__ uint64_t sspan[kCB / kWave];
+    uint64_t span = 0;
+    for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+        for (int64_t k = threadIdx.x; k < nbk; k += kCB) cur[k] = ws.escan[k * nch + ch];
+        __syncthreads();
+        const int64_t i1 = (ch + 1) * chunk < n ? (ch + 1) * chunk : n;
+        for (int64_t t0 = ch * chunk; t0 < i1; t0 += kDfgTile) {
+            uint32_t cell[kCI];
+            uint64_t gap[kCI];
+#pragma unroll
+            for (int q = 0; q < kCI; ++q) {
+                const int64_t i = t0 + q * kCB + threadIdx.x;
+                cell[q] = 0xFFFFFFFFu;
+                gap[q] = 0;
+                if (i < i1 && i > 0) {
+                    const int32_t c = case_s[i], cp = case_s[i - 1];
+                    const int32_t a = act_s[i], ap = act_s[i - 1];
+                    if (c == cp && (uint32_t)a < (uint32_t)A && (uint32_t)ap < (uint32_t)A) {
+                        cell[q] = (uint32_t)ap * (uint32_t)A + (uint32_t)a;
+                        gap[q] = (uint64_t)ts_s[i] - (uint64_t)ts_s[i - 1];
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kCI; ++q) {
+                if (cell[q] == 0xFFFFFFFFu) continue;
+                span = sat_add63(span, cap63(gap[q]));
+                const uint32_t pos = atomicAdd(&cur[cell[q] >> 12], 1u);
+                ws.ecell[pos] = (uint16_t)(cell[q] & (kCellsPerTable - 1));
+                ws.egap[pos] = gap[q];
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) span = sat_add63(span, __shfl_xor(span, o));
+    if (lane() == 0) sspan[threadIdx.x / kWave] = span;
+    __syncthreads();
     if (threadIdx.x == 0) {
         uint64_t s = 0;
-        for (int k = 0; k < kPB / kWave; ++k) s = sat_add63(s, sspan[k]);
+        for (int k = 0; k < kCB / kWave; ++k) s = sat_add63(s, sspan[k]);
         ws.pspan[blockIdx.x] = s;
     }
 }
 
-// One block per bucket: exclusive scan over its tiles' counts, bucket total.
-__global__ __launch_bounds__(256) void k_dfg_bucket_scan(int64_t nbt, DfgWs ws) {
-    __shared__ uint32_t tmp[256 / kWave + 1];
-    const int64_t b = blockIdx.x;
-    uint32_t run = 0;
-    for (int64_t t0 = 0; t0 < nbt; t0 += 256) {
-        const int64_t t = t0 + threadIdx.x;
-        const uint32_t v = t < nbt ? ws.ecnt[b * nbt + t] : 0u;
-        uint32_t total;
-        const uint32_t ex = block_excl_sum<256>(v, tmp, &total);
-        if (t < nbt) ws.escan[b * nbt + t] = run + ex;
-        run += total;
-    }
-    if (threadIdx.x == 0) ws.btotal[b] = run;
-}
-
-// Splits every bucket into slots of about total/kDfgAggTarget edges.
-__global__ __launch_bounds__(1024) void k_dfg_plan(int64_t nbk, DfgWs ws) {
-    __shared__ uint64_t red[1024 / kWave];
+// Bucket bases and totals from the scan; every bucket cut into slots of about
+// E/kDfgAggTarget edges.
+__global__ __launch_bounds__(1024) void k_dfg_plan(int64_t nbk, int64_t nch, DfgWs ws) {
     __shared__ uint32_t tmp[1024 / kWave + 1];
-    uint64_t tot = 0;
-    for (int64_t b = threadIdx.x; b < nbk; b += 1024) tot += ws.btotal[b];
-    tot = wave_sum(tot);
-    if (lane() == 0) red[threadIdx.x / kWave] = tot;
-    __syncthreads();
-    uint64_t all = 0;
-    for (int k = 0; k < 1024 / kWave; ++k) all += red[k];
+    const uint64_t all = *ws.utotal;
     uint64_t chunk = (all + kDfgAggTarget - 1) / kDfgAggTarget;
     if (chunk < 1) chunk = 1;
     uint32_t run = 0;
     for (int64_t b0 = 0; b0 < nbk; b0 += 1024) {
         const int64_t b = b0 + threadIdx.x;
-        uint32_t sl = 0, tb = 0;
-        if (b < nbk) {
-            tb = ws.btotal[b];
+        uint32_t sl = 0, tb = 0, base = 0;
+        if (b < nbk && nch > 0) {   // no chunks (empty log): empty buckets
+            base = ws.escan[b * nch];
+            const uint32_t next = b + 1 < nbk ? ws.escan[(b + 1) * nch] : (uint32_t)all;
+            tb = next - base;
             sl = (uint32_t)((tb + chunk - 1) / chunk);
         }
         uint32_t total;
         const uint32_t ex = block_excl_sum<1024>(sl, tmp, &total);
         if (b < nbk) {
             const uint32_t first = run + ex;
+            ws.bbase[b] = base;
+            ws.btotal[b] = tb;
             ws.bfirst[b] = first;
             ws.bslots[b] = sl;
             for (uint32_t s = 0; s < sl; ++s) {
@@ -307,62 +329,50 @@ __global__ __launch_bounds__(1024) void k_dfg_plan(int64_t nbk, DfgWs ws) {
     if (threadIdx.x == 0) *ws.nplan = run;
 }
 
-__global__ __launch_bounds__(kAB) void k_dfg_agg(int64_t nbt, DfgWs ws) {
+__device__ __forceinline__ void agg_edge(uint32_t* scount, uint64_t* ssum, int64_t* smin, int64_t* smax,
+                                         uint32_t cell, uint64_t gap) {
+    const int64_t gg = (int64_t)gap;
+    atomicAdd(&scount[cell], 1u);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&ssum[cell]), (unsigned long long)gap);
+    if (gg < __hip_atomic_load(&smin[cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+        __hip_atomic_fetch_min(&smin[cell], gg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (gg > __hip_atomic_load(&smax[cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+        __hip_atomic_fetch_max(&smax[cell], gg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// One block per slot: its edges are one contiguous range of its bucket.
+__global__ __launch_bounds__(kAB) void k_dfg_agg(DfgWs ws) {
     __shared__ uint32_t scount[kCellsPerTable];
     __shared__ uint64_t ssum[kCellsPerTable];
     __shared__ int64_t smin[kCellsPerTable];
     __shared__ int64_t smax[kCellsPerTable];
-    __shared__ int64_t tfirst;
 
     const uint32_t g = blockIdx.x;
     if (g >= *ws.nplan) return;
     const int4 pl = ws.plan[g];
-    const int64_t b = pl.x;
-    const uint32_t v0 = (uint32_t)pl.y, v1 = (uint32_t)pl.z;
     for (int c = threadIdx.x; c < kCellsPerTable; c += kAB) {
         scount[c] = 0;
         ssum[c] = 0;
         smin[c] = INT64_MAX;
         smax[c] = INT64_MIN;
     }
-    const uint32_t* scan = ws.escan + b * nbt;
-    const uint32_t* cnt = ws.ecnt + b * nbt;
-    const uint32_t* beg = ws.ebeg + b * nbt;
-    if (threadIdx.x == 0) {
-        // last tile whose run starts at or before v0 and is non-empty past it
-        int64_t lo = 0, hi = nbt - 1;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi + 1) / 2;
-            if (scan[mid] <= v0) lo = mid;
-            else hi = mid - 1;
-        }
-        // skip empty runs that end exactly at v0
-        while (lo < nbt && scan[lo] + cnt[lo] <= v0) ++lo;
-        tfirst = lo;
-    }
     __syncthreads();
-    const int w = threadIdx.x / kWave;
-    constexpr int kAW = kAB / kWave;
-    for (int64_t t = tfirst + w; t < nbt; t += kAW) {
-        const uint32_t r0 = scan[t];
-        if (r0 >= v1) break;
-        const uint32_t rl = cnt[t];
-        const uint32_t lo = r0 > v0 ? r0 : v0;
-        const uint32_t hi = (r0 + rl) < v1 ? (r0 + rl) : v1;
-        const size_t at0 = (size_t)t * kDfgTile + beg[t];
-        for (uint32_t v = lo + lane(); v < hi; v += kWave) {
-            const size_t at = at0 + (v - r0);
-            const uint32_t cell = ws.ecell[at];
-            const uint64_t gap = ws.egap[at];
-            const int64_t gg = (int64_t)gap;
-            atomicAdd(&scount[cell], 1u);
-            atomicAdd(reinterpret_cast<unsigned long long*>(&ssum[cell]), (unsigned long long)gap);
-            if (gg < __hip_atomic_load(&smin[cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
-                __hip_atomic_fetch_min(&smin[cell], gg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (gg > __hip_atomic_load(&smax[cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
-                __hip_atomic_fetch_max(&smax[cell], gg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const size_t at0 = (size_t)ws.bbase[pl.x];
+    const int64_t v1 = pl.z;
+    constexpr int kU = 4;   // edges in flight per thread
+    int64_t v = pl.y + threadIdx.x;
+    for (; v + (kU - 1) * kAB < v1; v += kU * kAB) {
+        uint32_t cell[kU];
+        uint64_t gap[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            cell[u] = ws.ecell[at0 + v + u * kAB];
+            gap[u] = ws.egap[at0 + v + u * kAB];
         }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) agg_edge(scount, ssum, smin, smax, cell[u], gap[u]);
     }
+    for (; v < v1; v += kAB) agg_edge(scount, ssum, smin, smax, ws.ecell[at0 + v], ws.egap[at0 + v]);
     __syncthreads();
     const size_t slot = (size_t)g * kCellsPerTable;
     for (int c = threadIdx.x; c < kCellsPerTable; c += kAB) {
@@ -480,21 +490,28 @@ hipError_t launch_dfg(const int32_t* case_s, const int32_t* act_s, const int64_t
         k_dfg_reduce<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(A, kDfgLdsBlocks, ws, out);
         launch_acts(A, kDfgLdsBlocks, ws, status_in, out, s);
     } else {
-        const int64_t nbt = dfg_tiles(n);
         const int64_t nbk = n_buckets(A);
+        const int64_t nch = dfg_chunks(n, nbk);
+        const int64_t chunk = dfg_chunk(nbk);
+        const unsigned g = (unsigned)ws.n_act_blocks;
+        {
+            ProfScope p(P_DFG_COUNT, s);
+            k_dfg_count<<<g, kCB, (size_t)(3 * A + nbk) * sizeof(uint32_t), s>>>(case_s, act_s, n, A, nbk, nch,
+                                                                             chunk, ws, out.status);
+            dev::excl_scan<uint32_t>(ws.ecnt, &ws.scal[0], ws.escan, ws.part32, ws.utotal, s);
+        }
         {
             ProfScope p(P_DFG_MAIN, s);
-            k_dfg_part<<<(unsigned)ws.n_act_blocks, kPB, 0, s>>>(case_s, act_s, ts_s, n, A, nbt, nbk,
-                                                                 ws, out.status);
+            k_dfg_scatter<<<g, kCB, (size_t)nbk * sizeof(uint32_t), s>>>(case_s, act_s, ts_s, n, A, nbk, nch,
+                                                                       chunk, ws);
         }
         {
             ProfScope p(P_DFG_PLAN, s);
-            k_dfg_bucket_scan<<<(unsigned)nbk, 256, 0, s>>>(nbt, ws);
-            k_dfg_plan<<<1, 1024, 0, s>>>(nbk, ws);
+            k_dfg_plan<<<1, 1024, 0, s>>>(nbk, nch, ws);
         }
         {
             ProfScope p(P_DFG_AGG, s);
-            k_dfg_agg<<<(unsigned)ws.n_slots_max, kAB, 0, s>>>(nbt, ws);
+            k_dfg_agg<<<(unsigned)ws.n_slots_max, kAB, 0, s>>>(ws);
         }
         ProfScope p(P_DFG_REDUCE, s);
         k_dfg_reduce<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(A, 0, ws, out);

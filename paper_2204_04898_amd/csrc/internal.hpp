@@ -96,17 +96,20 @@ struct DfgWs {
     uint32_t* pstart;
     uint32_t* pend;
     uint64_t* pspan;
-    // partition path
-    uint16_t* ecell;
-    uint64_t* egap;
-    uint32_t* ecnt;
-    uint32_t* ebeg;
-    uint32_t* escan;
-    uint32_t* btotal;
-    uint32_t* bfirst;
-    uint32_t* bslots;
-    int4* plan;
+    // bucketed path: edges in bucket-major order, each bucket cut by chunks
+    uint16_t* ecell;    // [edges] cell within the bucket
+    uint64_t* egap;     // [edges] timestamp gap
+    uint32_t* ecnt;     // [bucket][chunk] edge counts
+    uint32_t* escan;    // [bucket][chunk] exclusive scan = first edge index
+    uint32_t* bbase;    // [bucket] first edge index
+    uint32_t* btotal;   // [bucket] edges
+    uint32_t* bfirst;   // [bucket] first aggregation slot
+    uint32_t* bslots;   // [bucket] slots
+    int4* plan;         // [slot] (bucket, first, end) edge range within the bucket
     uint32_t* nplan;
+    uint32_t* part32;   // scan partials
+    int64_t* scal;      // [0] bucket x chunk entries, [1] edges (u32 total at utotal)
+    uint32_t* utotal;
     int32_t n_act_blocks;
     int32_t n_slots_max;
 };

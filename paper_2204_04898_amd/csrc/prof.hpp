@@ -29,6 +29,7 @@ enum ProfId {
     P_VIEW_AGG,
     P_VIEW_OUT,
     P_VIEW_FILTER,
+    P_DFG_COUNT,
     P_COUNT
 };
 
