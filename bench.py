@@ -231,14 +231,15 @@ def bench_serving(logs: dict, preps: dict, seconds: float, rate: float) -> dict:
 
 
 def calibrate_copy(gib: float = 1.0, reps: int = 3) -> None:
-    """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    """A plain streaming kernel of known traffic (reads gib GiB, writes gib GiB:
+    an elementwise bitwise-not), for scaling the FETCH_SIZE / WRITE_SIZE counters."""
     import torch
 
     n = int(gib * (1 << 30))
     x = torch.ones(n, dtype=torch.uint8, device="cuda:0")
     y = torch.empty_like(x)
     for _ in range(reps):
-        y.copy_(x)
+        torch.bitwise_not(x, out=y)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": n, "reps": reps}))
 
@@ -295,7 +296,7 @@ def main() -> int:
         for k in ("fetch-csv", "write-csv", "copy-fetch-csv", "copy-write-csv", "kernel", "stage", "workload",
                   "command"):
             sp.add_argument("--" + k, required=True)
-        sp.add_argument("--copy-kernel", default="copy")
+        sp.add_argument("--copy-kernel", default="bitwise_not")
         sp.add_argument("--copy-bytes", type=int, default=1 << 30)
         summarize_counters(sp.parse_args())
         return 0
