@@ -89,6 +89,7 @@ size_t batched_ws_bytes(int64_t n, int32_t A, int32_t V, const BatchedTune& t) {
 // Workspace of the formatting step.
 struct PrepWs {
     RangeInfo* info;
+    RangePart* rpart;
     SortBufs a, b;
     uint32_t* hist;
     uint32_t* rowsum;
@@ -99,6 +100,7 @@ PrepWs prep_ws_layout(Bump& bp, int64_t n) {
     PrepWs w{};
     const size_t m = (size_t)(n > 0 ? n : 1);
     w.info = bp.take<RangeInfo>(1);
+    w.rpart = bp.take<RangePart>(kRangeParts);
     w.a.key = bp.take<uint32_t>(m);
     w.a.ts = bp.take<int64_t>(m);
     w.a.act = bp.take<uint32_t>(m);
@@ -167,7 +169,7 @@ int run_prepare(const pm4g_log* log, const pm4g_prepared* out, bool case_table, 
     PrepWs w = prep_ws_layout(bp, n);
     k_set_status<<<1, 1, 0, s>>>(out->status, 0);
     PM4G_HIP(launch_range_scan(log->case_id, log->activity, log->timestamp, n, A, presorted, false,
-                               w.info, s));
+                               w.info, w.rpart, s));
     RangeInfo h{};
     PM4G_HIP(hipMemcpyAsync(&h, w.info, sizeof(h), hipMemcpyDeviceToHost, s));
     PM4G_HIP(hipStreamSynchronize(s));

@@ -27,6 +27,33 @@ __device__ __forceinline__ uint64_t match_digit8(uint32_t d, uint64_t active) {
     return peers;
 }
 
+// Lanes of this wave whose value agrees with this lane's in the low `bits`
+// bits, among `active`.  Every lane of the wave must execute it (`bits` is
+// wave-uniform).
+__device__ __forceinline__ uint64_t match_bits(uint32_t v, int bits, uint64_t active) {
+    uint64_t peers = active;
+    for (int b = 0; b < bits; ++b) {
+        const bool bit = (v >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+    }
+    return peers;
+}
+
+// Wave-aggregated LDS counter increment: the lanes with `has` set add one to
+// counter[key]; each gets the counter's value before its own increment (one
+// atomic per distinct key).  Every lane of the wave must execute it.
+__device__ __forceinline__ uint32_t wave_bump(uint32_t* counter, uint32_t key, int key_bits, bool has) {
+    const uint64_t active = __ballot(has);
+    const uint64_t peers = match_bits(has ? key : 0u, key_bits, active);
+    const uint32_t rank = (uint32_t)__popcll(peers & lanes_below());
+    const int leader = has ? (int)__ffsll((unsigned long long)peers) - 1 : 0;
+    uint32_t base = 0;
+    if (has && rank == 0) base = atomicAdd(&counter[key], (uint32_t)__popcll(peers));
+    base = (uint32_t)__shfl((int)base, leader);
+    return base + rank;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_incl_sum(T v) {
 #pragma unroll

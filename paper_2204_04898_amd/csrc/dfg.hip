@@ -177,7 +177,65 @@ __global__ __launch_bounds__(kLB) void k_dfg_lds(const int32_t* __restrict__ cas
 // A*A > 4096: bucket-major edges
 
 constexpr int kCB = 512;                  // threads of k_dfg_count / k_dfg_scatter
-constexpr int kCI = kDfgTile / kCB;       // events per thread per tile (8)
+
+
+// Four consecutive events [e0, e0 + 4) of the prepared log in registers,
+// with the event before e0 (and the case after e0 + 3): 16-byte loads when
+// the quad lies inside [.., lim) and the columns are 16-byte aligned, element
+// loads otherwise; neighbours come from the adjacent lanes (the lanes hold
+// consecutive quads), the wave's edge lanes load them.  Every lane of the
+// wave must execute it.  Lanes past `lim` get case ~prev so nothing pairs.
+struct Quad {
+    int32_t c[4], a[4];
+    int64_t t[4];
+    int32_t cp, ap;   // event e0 - 1 (cp = ~c[0] when e0 == 0)
+    int64_t tp;
+    int32_t cn;       // case of event e0 + 4 (~c[3] past the log)
+};
+
+template <bool WANT_TS, bool WANT_NEXT>
+__device__ __forceinline__ Quad load_quad(const int32_t* __restrict__ case_s, const int32_t* __restrict__ act_s,
+                                          const int64_t* __restrict__ ts_s, int64_t e0, int64_t lim, int64_t n,
+                                          bool aligned) {
+    Quad q;
+    if (aligned && e0 + 3 < lim) {
+        const int4 c4 = *reinterpret_cast<const int4*>(case_s + e0);
+        const int4 a4 = *reinterpret_cast<const int4*>(act_s + e0);
+        q.c[0] = c4.x; q.c[1] = c4.y; q.c[2] = c4.z; q.c[3] = c4.w;
+        q.a[0] = a4.x; q.a[1] = a4.y; q.a[2] = a4.z; q.a[3] = a4.w;
+        if (WANT_TS) {
+            const longlong2 t01 = *reinterpret_cast<const longlong2*>(ts_s + e0);
+            const longlong2 t23 = *reinterpret_cast<const longlong2*>(ts_s + e0 + 2);
+            q.t[0] = t01.x; q.t[1] = t01.y; q.t[2] = t23.x; q.t[3] = t23.y;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t i = e0 + j;
+            const bool in = i < lim;
+            q.c[j] = in ? case_s[i] : (j ? ~q.c[j - 1] : 0);
+            q.a[j] = in ? act_s[i] : 0;
+            if (WANT_TS) q.t[j] = in ? ts_s[i] : 0;
+        }
+    }
+    q.cp = __shfl_up(q.c[3], 1);
+    q.ap = __shfl_up(q.a[3], 1);
+    if (WANT_TS) q.tp = __shfl_up(q.t[3], 1);
+    if (lane() == 0) {
+        if (e0 > 0 && e0 - 1 < n) {
+            q.cp = case_s[e0 - 1];
+            q.ap = act_s[e0 - 1];
+            if (WANT_TS) q.tp = ts_s[e0 - 1];
+        } else {
+            q.cp = ~q.c[0];
+        }
+    }
+    if (WANT_NEXT) {
+        q.cn = __shfl_down(q.c[0], 1);
+        if (lane() == kWave - 1) q.cn = e0 + 4 < n ? case_s[e0 + 4] : ~q.c[3];
+    }
+    return q;
+}
 
 // Per chunk: edge counts per bucket; per block: activity, start and end counts.
 // Dynamic LDS: (3 * A + nbk) u32.
@@ -191,45 +249,43 @@ __global__ __launch_bounds__(kCB) void k_dfg_count(const int32_t* __restrict__ c
     uint32_t* send = dsm + 2 * A;
     uint32_t* bcnt = dsm + 3 * A;
     for (int a = threadIdx.x; a < 3 * A; a += kCB) dsm[a] = 0;
+    const bool aligned = ((reinterpret_cast<uintptr_t>(case_s) | reinterpret_cast<uintptr_t>(act_s)) & 15) == 0;
     bool bad = false;
     for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
         for (int64_t k = threadIdx.x; k < nbk; k += kCB) bcnt[k] = 0;
         __syncthreads();
         const int64_t i1 = (ch + 1) * chunk < n ? (ch + 1) * chunk : n;
         for (int64_t t0 = ch * chunk; t0 < i1; t0 += kDfgTile) {
-            int32_t c[kCI], cp[kCI], cn[kCI], a[kCI], ap[kCI];
 #pragma unroll
-            for (int q = 0; q < kCI; ++q) {
-                const int64_t i = t0 + q * kCB + threadIdx.x;
-                c[q] = cp[q] = cn[q] = a[q] = ap[q] = 0;
-                if (i < i1) {
-                    c[q] = case_s[i];
-                    a[q] = act_s[i];
-                    cp[q] = i > 0 ? case_s[i - 1] : ~c[q];
-                    ap[q] = i > 0 ? act_s[i - 1] : 0;
-                    cn[q] = i + 1 < n ? case_s[i + 1] : ~c[q];
-                }
-            }
+            for (int h = 0; h < kDfgTile / (4 * kCB); ++h) {
+                const int64_t e0 = t0 + 4 * (h * kCB + (int64_t)threadIdx.x);
+                if (t0 + 4 * h * kCB >= i1) break;   // block-uniform
+                const Quad qd = load_quad<false, true>(case_s, act_s, nullptr, e0, i1, n, aligned);
 #pragma unroll
-            for (int q = 0; q < kCI; ++q) {
-                const int64_t i = t0 + q * kCB + threadIdx.x;
-                if (i >= i1) continue;
-                if ((uint32_t)a[q] >= (uint32_t)A) {
-                    bad = true;
-                    continue;
+                for (int j = 0; j < 4; ++j) {
+                    if (e0 + j >= i1) break;
+                    const int32_t c = qd.c[j], a = qd.a[j];
+                    if ((uint32_t)a >= (uint32_t)A) {
+                        bad = true;
+                        continue;
+                    }
+                    const int32_t cp = j ? qd.c[j - 1] : qd.cp;
+                    const int32_t ap = j ? qd.a[j - 1] : qd.ap;
+                    const int32_t cn = j < 3 ? qd.c[j + 1] : qd.cn;
+                    const bool first = cp != c;
+                    atomicAdd(&sfreq[a], 1u);
+                    if (first) atomicAdd(&sstart[a], 1u);
+                    if (e0 + j + 1 >= n || cn != c) atomicAdd(&send[a], 1u);
+                    if (!first && (uint32_t)ap < (uint32_t)A)
+                        atomicAdd(&bcnt[((uint32_t)ap * (uint32_t)A + (uint32_t)a) >> 12], 1u);
                 }
-                const bool first = cp[q] != c[q];
-                atomicAdd(&sfreq[a[q]], 1u);
-                if (first) atomicAdd(&sstart[a[q]], 1u);
-                if (cn[q] != c[q]) atomicAdd(&send[a[q]], 1u);
-                if (!first && (uint32_t)ap[q] < (uint32_t)A)
-                    atomicAdd(&bcnt[((uint32_t)ap[q] * (uint32_t)A + (uint32_t)a[q]) >> 12], 1u);
             }
         }
         __syncthreads();
         for (int64_t k = threadIdx.x; k < nbk; k += kCB) ws.ecnt[k * nch + ch] = bcnt[k];
         __syncthreads();
     }
+    __syncthreads();   // (a block without chunks: the zeroing above)
     if (__ballot(bad) != 0 && lane() == 0) set_status(status, PM4G_E_RANGE);
     const size_t ab = (size_t)blockIdx.x * A;
     for (int a = threadIdx.x; a < A; a += kCB) {
@@ -249,35 +305,34 @@ __global__ __launch_bounds__(kCB) void k_dfg_scatter(const int32_t* __restrict__
                                                      int64_t nbk, int64_t nch, int64_t chunk, DfgWs ws) {
     extern __shared__ uint32_t cur[];
     __shared__ uint64_t sspan[kCB / kWave];
+    const bool aligned = ((reinterpret_cast<uintptr_t>(case_s) | reinterpret_cast<uintptr_t>(act_s) |
+                           reinterpret_cast<uintptr_t>(ts_s)) & 15) == 0;
     uint64_t span = 0;
     for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
         for (int64_t k = threadIdx.x; k < nbk; k += kCB) cur[k] = ws.escan[k * nch + ch];
         __syncthreads();
         const int64_t i1 = (ch + 1) * chunk < n ? (ch + 1) * chunk : n;
         for (int64_t t0 = ch * chunk; t0 < i1; t0 += kDfgTile) {
-            uint32_t cell[kCI];
-            uint64_t gap[kCI];
 #pragma unroll
-            for (int q = 0; q < kCI; ++q) {
-                const int64_t i = t0 + q * kCB + threadIdx.x;
-                cell[q] = 0xFFFFFFFFu;
-                gap[q] = 0;
-                if (i < i1 && i > 0) {
-                    const int32_t c = case_s[i], cp = case_s[i - 1];
-                    const int32_t a = act_s[i], ap = act_s[i - 1];
-                    if (c == cp && (uint32_t)a < (uint32_t)A && (uint32_t)ap < (uint32_t)A) {
-                        cell[q] = (uint32_t)ap * (uint32_t)A + (uint32_t)a;
-                        gap[q] = (uint64_t)ts_s[i] - (uint64_t)ts_s[i - 1];
-                    }
+            for (int h = 0; h < kDfgTile / (4 * kCB); ++h) {
+                const int64_t e0 = t0 + 4 * (h * kCB + (int64_t)threadIdx.x);
+                if (t0 + 4 * h * kCB >= i1) break;   // block-uniform
+                const Quad qd = load_quad<true, false>(case_s, act_s, ts_s, e0, i1, n, aligned);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int32_t cp = j ? qd.c[j - 1] : qd.cp;
+                    const int32_t ap = j ? qd.a[j - 1] : qd.ap;
+                    const int64_t tp = j ? qd.t[j - 1] : qd.tp;
+                    if (e0 + j >= i1 || qd.c[j] != cp || (uint32_t)qd.a[j] >= (uint32_t)A ||
+                        (uint32_t)ap >= (uint32_t)A)
+                        continue;
+                    const uint32_t cell = (uint32_t)ap * (uint32_t)A + (uint32_t)qd.a[j];
+                    const uint64_t gap = (uint64_t)qd.t[j] - (uint64_t)tp;
+                    span = sat_add63(span, cap63(gap));
+                    const uint32_t pos = atomicAdd(&cur[cell >> 12], 1u);
+                    ws.ecell[pos] = (uint16_t)(cell & (kCellsPerTable - 1));
+                    ws.egap[pos] = gap;
                 }
-            }
-#pragma unroll
-            for (int q = 0; q < kCI; ++q) {
-                if (cell[q] == 0xFFFFFFFFu) continue;
-                span = sat_add63(span, cap63(gap[q]));
-                const uint32_t pos = atomicAdd(&cur[cell[q] >> 12], 1u);
-                ws.ecell[pos] = (uint16_t)(cell[q] & (kCellsPerTable - 1));
-                ws.egap[pos] = gap[q];
             }
         }
         __syncthreads();

@@ -20,6 +20,14 @@ struct RangeInfo {
     int64_t reserved[4];
 };
 
+// Per-block partial of the range scan.
+struct RangePart {
+    int32_t cmin, cmax;
+    int32_t bad, unsorted;
+    int64_t tmin, tmax;
+};
+constexpr int kRangeParts = 2048;   // blocks of the range scan
+
 // Bump allocator over the caller's workspace.  With base == nullptr it only
 // measures (used by pm4g_workspace_bytes), so the layout has one definition.
 struct Bump {
@@ -37,7 +45,8 @@ struct Bump {
 
 // ---- range scan (range.hip) ----
 hipError_t launch_range_scan(const int32_t* case_id, const int32_t* act, const int64_t* ts, int64_t n,
-                             int32_t A, bool presorted, bool want_ts, RangeInfo* info, hipStream_t s);
+                             int32_t A, bool presorted, bool want_ts, RangeInfo* info, RangePart* part,
+                             hipStream_t s);
 hipError_t launch_ts_range(const int64_t* ts, int64_t n, RangeInfo* info, hipStream_t s);
 
 // ---- LSD radix passes over (case key u32, ts i64, act u32) elements (radix.hip) ----
@@ -145,8 +154,7 @@ struct VarWs {
     uint32_t* sstart;    // [V+1] group start positions
     uint32_t* repflag;   // [C] 1 for representative cases
     uint32_t* rrank;     // [C] representative-order index of representative cases
-    uint32_t* vcount;    // [V] cases per variant (representative order)
-    uint32_t* vrepcase;  // [V] representative case index (representative order)
+    uint2* vcr;          // [V] (cases, representative case index), representative order
     uint32_t* cvar;      // [C] representative-order variant of each case
     uint32_t* vkey;      // [V] ordering keys (ping-pong with vkey2)
     uint32_t* vkey2;

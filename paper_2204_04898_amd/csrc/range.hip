@@ -3,7 +3,8 @@
 // that claims to be presorted (Sec. 3: (case, timestamp, row) order).
 //
 // Streaming pass, HBM-bound: 8 bytes/event (case, activity), 16 with the
-// timestamp.  Per-wave reductions, then one atomic per wave per extreme.
+// timestamp.  Block reductions into per-block partials, folded by one block
+// (no same-address atomics: across the 8 XCDs they serialise).
 #include "common.hpp"
 #include "internal.hpp"
 #include "prof.hpp"
@@ -24,7 +25,8 @@ template <bool PRESORTED, bool WANT_TS>
 __global__ __launch_bounds__(256) void k_range_scan(const int32_t* __restrict__ case_id,
                                                     const int32_t* __restrict__ act,
                                                     const int64_t* __restrict__ ts, int64_t n,
-                                                    int32_t A, RangeInfo* info) {
+                                                    int32_t A, RangePart* part) {
+    __shared__ RangePart red[256 / kWave];
     int32_t cmin = INT32_MAX, cmax = INT32_MIN;
     int64_t tmin = INT64_MAX, tmax = INT64_MIN;
     bool bad_act = false, unsorted = false;
@@ -52,7 +54,20 @@ __global__ __launch_bounds__(256) void k_range_scan(const int32_t* __restrict__ 
         const int64_t n4 = aligned ? n / 4 : 0;
         const int4* c4 = reinterpret_cast<const int4*>(case_id);
         const int4* a4 = reinterpret_cast<const int4*>(act);
-        for (int64_t q = tid; q < n4; q += stride) {
+        int64_t q = tid;
+        for (; q + stride < n4; q += 2 * stride) {   // two loads of each column in flight
+            const int4 c = c4[q], cb = c4[q + stride];
+            const int4 a = a4[q], ab = a4[q + stride];
+            visit(4 * q, c.x, a.x);
+            visit(4 * q + 1, c.y, a.y);
+            visit(4 * q + 2, c.z, a.z);
+            visit(4 * q + 3, c.w, a.w);
+            visit(4 * (q + stride), cb.x, ab.x);
+            visit(4 * (q + stride) + 1, cb.y, ab.y);
+            visit(4 * (q + stride) + 2, cb.z, ab.z);
+            visit(4 * (q + stride) + 3, cb.w, ab.w);
+        }
+        for (; q < n4; q += stride) {
             const int4 c = c4[q];
             const int4 a = a4[q];
             visit(4 * q, c.x, a.x);
@@ -64,23 +79,65 @@ __global__ __launch_bounds__(256) void k_range_scan(const int32_t* __restrict__ 
     } else {
         for (int64_t i = tid; i < n; i += stride) visit(i, case_id[i], act[i]);
     }
-    cmin = wave_min(cmin);
-    cmax = wave_max(cmax);
-    if (WANT_TS || PRESORTED) {
-        tmin = wave_min(tmin);
-        tmax = wave_max(tmax);
-    }
-    const bool any_bad = __ballot(bad_act) != 0;
-    const bool any_unsorted = __ballot(unsorted) != 0;
-    if (lane() == 0) {
-        atomicMin(&info->case_min, cmin);
-        atomicMax(&info->case_max, cmax);
-        if (WANT_TS || PRESORTED) {
-            __hip_atomic_fetch_min(&info->ts_min, tmin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_max(&info->ts_max, tmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    RangePart r;
+    r.cmin = wave_min(cmin);
+    r.cmax = wave_max(cmax);
+    r.tmin = wave_min(tmin);
+    r.tmax = wave_max(tmax);
+    r.bad = __ballot(bad_act) != 0;
+    r.unsorted = __ballot(unsorted) != 0;
+    if (lane() == 0) red[threadIdx.x / kWave] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < 256 / kWave; ++k) {
+            const RangePart& o = red[k];
+            r.cmin = o.cmin < r.cmin ? o.cmin : r.cmin;
+            r.cmax = o.cmax > r.cmax ? o.cmax : r.cmax;
+            r.tmin = o.tmin < r.tmin ? o.tmin : r.tmin;
+            r.tmax = o.tmax > r.tmax ? o.tmax : r.tmax;
+            r.bad |= o.bad;
+            r.unsorted |= o.unsorted;
         }
-        if (any_bad) set_status(&info->status, PM4G_E_RANGE);
-        if (any_unsorted) set_status(&info->status, PM4G_E_NOT_SORTED);
+        part[blockIdx.x] = r;
+    }
+}
+
+// One block folds the per-block partials into the RangeInfo.
+__global__ __launch_bounds__(1024) void k_range_final(const RangePart* part, int nparts, RangeInfo* info) {
+    __shared__ RangePart red[1024 / kWave];
+    RangePart r{INT32_MAX, INT32_MIN, 0, 0, INT64_MAX, INT64_MIN};
+    for (int k = threadIdx.x; k < nparts; k += 1024) {
+        const RangePart o = part[k];
+        r.cmin = o.cmin < r.cmin ? o.cmin : r.cmin;
+        r.cmax = o.cmax > r.cmax ? o.cmax : r.cmax;
+        r.tmin = o.tmin < r.tmin ? o.tmin : r.tmin;
+        r.tmax = o.tmax > r.tmax ? o.tmax : r.tmax;
+        r.bad |= o.bad;
+        r.unsorted |= o.unsorted;
+    }
+    r.cmin = wave_min(r.cmin);
+    r.cmax = wave_max(r.cmax);
+    r.tmin = wave_min(r.tmin);
+    r.tmax = wave_max(r.tmax);
+    r.bad = __ballot(r.bad != 0) != 0;
+    r.unsorted = __ballot(r.unsorted != 0) != 0;
+    if (lane() == 0) red[threadIdx.x / kWave] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < 1024 / kWave; ++k) {
+            const RangePart& o = red[k];
+            r.cmin = o.cmin < r.cmin ? o.cmin : r.cmin;
+            r.cmax = o.cmax > r.cmax ? o.cmax : r.cmax;
+            r.tmin = o.tmin < r.tmin ? o.tmin : r.tmin;
+            r.tmax = o.tmax > r.tmax ? o.tmax : r.tmax;
+            r.bad |= o.bad;
+            r.unsorted |= o.unsorted;
+        }
+        info->case_min = r.cmin;
+        info->case_max = r.cmax;
+        info->ts_min = r.tmin;
+        info->ts_max = r.tmax;
+        info->status = r.bad ? PM4G_E_RANGE : (r.unsorted ? PM4G_E_NOT_SORTED : 0);
     }
 }
 
@@ -103,22 +160,24 @@ __global__ __launch_bounds__(256) void k_ts_range(const int64_t* __restrict__ ts
 
 static int range_grid(int64_t n) {
     int64_t g = (n + 255) / 256;
-    if (g > 4096) g = 4096;
+    if (g > kRangeParts) g = kRangeParts;
     return g < 1 ? 1 : (int)g;
 }
 
 hipError_t launch_range_scan(const int32_t* case_id, const int32_t* act, const int64_t* ts, int64_t n,
-                             int32_t A, bool presorted, bool want_ts, RangeInfo* info, hipStream_t s) {
+                             int32_t A, bool presorted, bool want_ts, RangeInfo* info, RangePart* part,
+                             hipStream_t s) {
     ProfScope p(P_RANGE, s);
     k_range_init<<<1, 1, 0, s>>>(info);
     if (n > 0) {
         const int g = range_grid(n);
         if (presorted)
-            k_range_scan<true, true><<<g, 256, 0, s>>>(case_id, act, ts, n, A, info);
+            k_range_scan<true, true><<<g, 256, 0, s>>>(case_id, act, ts, n, A, part);
         else if (want_ts)
-            k_range_scan<false, true><<<g, 256, 0, s>>>(case_id, act, ts, n, A, info);
+            k_range_scan<false, true><<<g, 256, 0, s>>>(case_id, act, ts, n, A, part);
         else
-            k_range_scan<false, false><<<g, 256, 0, s>>>(case_id, act, ts, n, A, info);
+            k_range_scan<false, false><<<g, 256, 0, s>>>(case_id, act, ts, n, A, part);
+        k_range_final<<<1, 1024, 0, s>>>(part, g, info);
     }
     return hipGetLastError();
 }

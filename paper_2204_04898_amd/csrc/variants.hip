@@ -40,8 +40,7 @@ VarWs var_ws_layout(Bump& b, int64_t n) {
     w.sstart = b.take<uint32_t>(m + 1);
     w.repflag = b.take<uint32_t>(m);
     w.rrank = b.take<uint32_t>(m);
-    w.vcount = b.take<uint32_t>(m);
-    w.vrepcase = b.take<uint32_t>(m);
+    w.vcr = b.take<uint2>(m);
     w.cvar = b.take<uint32_t>(m);
     w.vkey = b.take<uint32_t>(m);
     w.vkey2 = b.take<uint32_t>(m);
@@ -121,15 +120,27 @@ __global__ __launch_bounds__(kBlk) void k_var_hash(const int32_t* __restrict__ a
         const int64_t base = __shfl(st, 0);
         const int64_t end = __shfl(en, last);
         // wave-uniform trip count: every lane takes part in the shuffles
-        for (int64_t p0 = base; p0 < end; p0 += kWave) {
-            const int64_t p = p0 + lane();
-            const int m = seg_of(st, p);
-            const int64_t s_m = __shfl(st, m);
-            if (p < end) {
-                const uint64_t pos = (uint64_t)(p - s_m);
-                const uint64_t term =
-                    mix64((pos << 13) + (uint64_t)(uint32_t)act_s[p] + 0x632be59bd9b4e019ull);
-                atomicAdd(&hsum[wl][m], (unsigned long long)term);
+        // wave-uniform trip count: every lane takes part in the shuffles;
+        // four 64-event steps per trip, their loads issued first
+        constexpr int kU = 4;
+        for (int64_t p0 = base; p0 < end; p0 += kU * kWave) {
+            int32_t av[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int64_t p = p0 + u * kWave + lane();
+                av[u] = p < end ? act_s[p] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int64_t p = p0 + u * kWave + lane();
+                const int m = seg_of(st, p);
+                const int64_t s_m = __shfl(st, m);
+                if (p < end) {
+                    const uint64_t pos = (uint64_t)(p - s_m);
+                    const uint64_t term =
+                        mix64((pos << 13) + (uint64_t)(uint32_t)av[u] + 0x632be59bd9b4e019ull);
+                    atomicAdd(&hsum[wl][m], (unsigned long long)term);
+                }
             }
         }
         if (has) {
@@ -215,23 +226,34 @@ __global__ __launch_bounds__(kBlk) void k_var_groups(const uint32_t* __restrict_
 }
 
 // Per group (hash order): count and representative, stored at the group's
-// representative-order index; per case: its representative-order variant.
+// representative-order index v (one 8-byte scattered write); the group's v
+// is kept in hash order (gv, coalesced) for the per-case pass.
 __global__ __launch_bounds__(kBlk) void k_var_segments(const uint32_t* __restrict__ is, VarWs w) {
-    const int64_t C = w.scal[0];
     const int64_t V = w.scal[1];
+    uint32_t* gv = w.repflag;   // free again after the representative scan
     for (int64_t g = (int64_t)blockIdx.x * kBlk + threadIdx.x; g < V; g += (int64_t)gridDim.x * kBlk) {
         const uint32_t s0 = w.sstart[g], s1 = w.sstart[g + 1];
         const uint32_t rep = is[s0];
         const uint32_t v = w.rrank[rep];
-        w.vcount[v] = s1 - s0;
-        w.vrepcase[v] = rep;
-        w.vkey[v] = (uint32_t)C - (s1 - s0);   // ascending key = descending count
-        w.vidx[v] = v;
+        w.vcr[v] = make_uint2(s1 - s0, rep);
+        gv[g] = v;
+    }
+}
+
+// Sort input of the final order (ascending key = descending count, stable on
+// the representative order), and every case's representative-order variant.
+__global__ __launch_bounds__(kBlk) void k_var_keys(const uint32_t* __restrict__ is, VarWs w) {
+    const int64_t C = w.scal[0];
+    const int64_t V = w.scal[1];
+    const uint32_t* gv = w.repflag;
+    for (int64_t v = (int64_t)blockIdx.x * kBlk + threadIdx.x; v < V; v += (int64_t)gridDim.x * kBlk) {
+        w.vkey[v] = (uint32_t)C - w.vcr[v].x;
+        w.vidx[v] = (uint32_t)v;
     }
     for (int64_t p = (int64_t)blockIdx.x * kBlk + threadIdx.x; p < C; p += (int64_t)gridDim.x * kBlk) {
         // group of p: flags up to p, minus one
         const uint32_t g = w.sid[p] + w.flag[p] - 1;
-        w.cvar[is[p]] = w.rrank[is[w.sstart[g]]];
+        w.cvar[is[p]] = gv[g];
     }
 }
 
@@ -242,9 +264,10 @@ __global__ __launch_bounds__(kBlk) void k_var_ids(const uint32_t* __restrict__ o
     for (int64_t k = (int64_t)blockIdx.x * kBlk + threadIdx.x; k < V; k += (int64_t)gridDim.x * kBlk) {
         const uint32_t v = order[k];
         w.fid[v] = (uint32_t)k;
-        const uint32_t r = w.vrepcase[v];
+        const uint2 cr = w.vcr[v];
+        const uint32_t r = cr.y;
         const uint32_t L = (uint32_t)(case_off[r + 1] - case_off[r]);
-        out.var_count[k] = w.vcount[v];
+        out.var_count[k] = cr.x;
         out.var_rep[k] = case_code[r];
         out.var_len[k] = (int32_t)L;
         w.lens[k] = L;
@@ -266,7 +289,7 @@ __global__ __launch_bounds__(kBlk) void k_var_emit(const uint32_t* __restrict__ 
         const bool has = k < V;
         int64_t src = 0, dst = INT64_MAX, len = 0;
         if (has) {
-            const uint32_t r = w.vrepcase[order[k]];
+            const uint32_t r = w.vcr[order[k]].y;
             src = case_off[r];
             len = case_off[r + 1] - src;
             dst = out.var_off[k];
@@ -274,13 +297,24 @@ __global__ __launch_bounds__(kBlk) void k_var_emit(const uint32_t* __restrict__ 
         const int last = (V - 1 - k0) < (kWave - 1) ? (int)(V - 1 - k0) : (kWave - 1);
         const int64_t base = __shfl(dst, 0);
         const int64_t end = __shfl(dst + len, last);
-        // wave-uniform trip count: every lane takes part in the shuffles
-        for (int64_t p0 = base; p0 < end; p0 += kWave) {
-            const int64_t p = p0 + lane();
-            const int m = seg_of(dst, p);
-            const int64_t s_m = __shfl(src, m);
-            const int64_t d_m = __shfl(dst, m);
-            if (p < end) out.var_acts[p] = act_s[s_m + (p - d_m)];
+        // wave-uniform trip count: every lane takes part in the shuffles;
+        // four 64-element steps per trip, their loads issued first
+        constexpr int kU = 4;
+        for (int64_t p0 = base; p0 < end; p0 += kU * kWave) {
+            int32_t av[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int64_t p = p0 + u * kWave + lane();
+                const int m = seg_of(dst, p);
+                const int64_t s_m = __shfl(src, m);
+                const int64_t d_m = __shfl(dst, m);
+                av[u] = p < end ? act_s[s_m + (p - d_m)] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int64_t p = p0 + u * kWave + lane();
+                if (p < end) out.var_acts[p] = av[u];
+            }
         }
     }
     if (out.case_variant) {
@@ -331,6 +365,7 @@ hipError_t launch_variants(const int32_t* act_s, const int64_t* case_off, const 
         // representative-order index of every representative case
         dev::excl_scan<uint32_t>(w.repflag, &w.scal[0], w.rrank, w.part32, (uint32_t*)nullptr, s);
         k_var_segments<<<kGrid, kBlk, 0, s>>>(is, w);
+        k_var_keys<<<kGrid, kBlk, 0, s>>>(is, w);
     }
     bool o2;
     {
