@@ -179,11 +179,16 @@ def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int, autot
                                   cell_capacity=int(req[4] * 1.1) + 1024)
     out = pm4g.pm4g_dfg_batched(prep, vd, md, n_views, tuning=tune, out=out)
     torch.cuda.synchronize()
+    pm4g.profile_enable(True)
+    pm4g.profile_read()
     t0 = time.perf_counter()
     for _ in range(steps):
         pm4g.pm4g_dfg_batched(prep, vd, md, n_views, tuning=tune, out=out)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
+    vprof = pm4g.profile_read()
+    pm4g.profile_enable(False)
+    view_stages = {name: tot / steps for name, (tot, cnt) in vprof.items() if cnt}
     # per-view launches of the same entry point on a sample of the views
     idx = np.linspace(0, n_views - 1, per_view_sample).astype(int)
     one_t = pm4g.BatchedTuning(pair_capacity=int(req[3]) + 1024, record_capacity=int(req[1]) + 1024,
@@ -199,6 +204,7 @@ def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int, autot
             "per_view_launch_views_per_s": 1.0 / per_view_s,
             "per_view_launch_sample": len(idx),
             "speedup_vs_per_view_launches": per_view_s * n_views / dt,
+            "stages_ms_per_call": view_stages,
             "tuning": tuned if tuned is not None else {"tile_events": tune.tile_events or 4096,
                                                        "emit_blocks": tune.emit_blocks or 512,
                                                        "agg_blocks": tune.agg_blocks or 512}}

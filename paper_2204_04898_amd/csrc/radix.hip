@@ -52,14 +52,29 @@ __global__ __launch_bounds__(kRB) void k_radix_hist(SortBufs in, int64_t n, int 
     const int32_t case_min = info->case_min;
     const int64_t ts_min = info->ts_min;
     const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    const bool vec = SRC == 0 && base + kRadixTile <= n && (reinterpret_cast<uintptr_t>(in.key) & 15) == 0;
+    if (vec) {
+        // full tile: 16-byte loads of four keys
+        const uint4* k4 = reinterpret_cast<const uint4*>(in.key + base);
 #pragma unroll
-    for (int k = 0; k < kRI; ++k) {
-        const int64_t i = base + k * kRB + threadIdx.x;
-        if (i < n) {
-            uint32_t d;
-            if (SRC == 0) d = digit_of<0>(load_key<FIRST, false>(in, i, case_min, 0), 0, shift, 0, key_mask);
-            else d = digit_of<1>(0, in.ts[i], shift, ts_min, key_mask);
-            atomicAdd(&h[d], 1u);
+        for (int q = 0; q < kRI / 4; ++q) {
+            const uint4 v = k4[q * kRB + threadIdx.x];
+            const uint32_t bias = FIRST ? (uint32_t)case_min : 0u;
+            atomicAdd(&h[digit_of<0>(v.x - bias, 0, shift, 0, key_mask)], 1u);
+            atomicAdd(&h[digit_of<0>(v.y - bias, 0, shift, 0, key_mask)], 1u);
+            atomicAdd(&h[digit_of<0>(v.z - bias, 0, shift, 0, key_mask)], 1u);
+            atomicAdd(&h[digit_of<0>(v.w - bias, 0, shift, 0, key_mask)], 1u);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kRI; ++k) {
+            const int64_t i = base + k * kRB + threadIdx.x;
+            if (i < n) {
+                uint32_t d;
+                if (SRC == 0) d = digit_of<0>(load_key<FIRST, false>(in, i, case_min, 0), 0, shift, 0, key_mask);
+                else d = digit_of<1>(0, in.ts[i], shift, ts_min, key_mask);
+                atomicAdd(&h[d], 1u);
+            }
         }
     }
     __syncthreads();

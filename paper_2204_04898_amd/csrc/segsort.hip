@@ -39,7 +39,10 @@ namespace pm4g {
 constexpr int kSB = 512;
 constexpr int kSW = kSB / kWave;     // waves per block
 constexpr int kSI = kSegCap / kSB;   // items per thread = chunks per wave
+constexpr int kPre = 3;              // window + lookahead read in the first load round
 static_assert(kSegCap % kSB == 0, "staging capacity must be a multiple of the block");
+static_assert(kSegCap <= 4096, "cross keys hold the staging position in 12 bits");
+static_assert(kPre * kSB >= kSegWindow, "the first load round covers the window");
 
 __device__ __forceinline__ int64_t block_min_i64(int64_t v, int64_t* red) {
     v = wave_min(v);
@@ -151,9 +154,9 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
                                                  int32_t* __restrict__ case_s,
                                                  int32_t* __restrict__ act_s,
                                                  int64_t* __restrict__ ts_s, int act_shift) {
-    __shared__ int64_t lts[kSegCap];
+    __shared__ int64_t lts[kSegCap];     // timestamps; on the fast path the sorted cross keys
     __shared__ uint16_t lact[kSegCap];
-    __shared__ uint16_t lidx[kSegCap];   // staging position of the event now at i
+    __shared__ uint16_t lidx[kSegCap];   // field-by-field path: staging position of the event now at i
     __shared__ uint16_t lcs[kSegCap];    // case start of position i
     __shared__ uint16_t lce[kSegCap];    // case end, stored at the case start
     __shared__ int64_t red[2 * kSW];
@@ -163,28 +166,40 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
     const uint32_t kmask = act_shift > 0 ? ((1u << act_shift) - 1u) : 0xFFFFFFFFu;
     const int64_t w0 = (int64_t)blockIdx.x * kSegWindow;
     const int64_t w1 = (w0 + kSegWindow) < n ? (w0 + kSegWindow) : n;
-    auto is_start = [&](int64_t p) { return p == 0 || ((key[p] ^ key[p - 1]) & kmask) != 0; };
 
-    // 1. first case start inside the window, first at or after its end (n counts)
+    // 1. one load round: the window and a lookahead are read into registers; the
+    //    first case start inside the window (s) and the first at or after its end
+    //    (e; n counts) come from them
+    uint32_t pk[kPre], pa[kPre];
+    int64_t pt[kPre];
+    bool pst[kPre];
     int64_t s = INT64_MAX, e = INT64_MAX;
-    for (int64_t p = w0 + threadIdx.x; p < w1; p += kSB) {
-        if (is_start(p)) {
-            s = p;
-            break;
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) {
+        const int64_t P = w0 + threadIdx.x + q * kSB;
+        pk[q] = pa[q] = 0;
+        pt[q] = 0;
+        pst[q] = false;
+        if (P < n) {
+            pk[q] = key[P];
+            pt[q] = in.ts[P];
+            pa[q] = act_shift > 0 ? (pk[q] >> act_shift) : in.act[P];
+            pst[q] = P == 0 || ((pk[q] ^ key[P - 1]) & kmask) != 0;
+            if (pst[q]) {
+                if (P < w1) s = P < s ? P : s;
+                else e = P < e ? P : e;
+            }
+        } else if (P == n) {
+            e = n < e ? n : e;
         }
-    }
-    {
-        const int64_t p = w1 + threadIdx.x;
-        if (p == n) e = n;
-        else if (p < n && is_start(p)) e = p;
     }
     block_min2_i64(s, e, red);
     if (s == INT64_MAX) return;   // a long case covers the whole window (block-uniform)
-    for (int64_t base = w1 + kSB; e == INT64_MAX && base <= n && base - s <= kSegCap; base += kSB) {
+    for (int64_t base = w0 + kPre * kSB; e == INT64_MAX && base <= n && base - s <= kSegCap; base += kSB) {
         const int64_t p = base + threadIdx.x;
         int64_t c = INT64_MAX;
         if (p == n) c = n;
-        else if (p < n && is_start(p)) c = p;
+        else if (p < n && ((key[p] ^ key[p - 1]) & kmask) != 0) c = p;
         e = block_min_i64(c, red);
     }
     if (e == INT64_MAX || e - s > kSegCap) {
@@ -193,19 +208,31 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
     }
     const int R = (int)(e - s);
 
-    // 2. stage the region; case ids stay in registers (same striped mapping as the output)
+    // 2. stage the region [s, e): prefetched events, then any beyond the lookahead
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) {
+        const int64_t P = w0 + threadIdx.x + q * kSB;
+        if (P >= s && P < e) {
+            const int i = (int)(P - s);
+            lts[i] = pt[q];
+            lact[i] = (uint16_t)pa[q];
+            lcs[i] = (uint16_t)(pst[q] ? i : 0);
+        }
+    }
+    for (int64_t P = w0 + kPre * kSB + threadIdx.x; P < e; P += kSB) {
+        const int i = (int)(P - s);
+        const uint32_t kr = key[P];
+        lts[i] = in.ts[P];
+        lact[i] = (uint16_t)(act_shift > 0 ? (kr >> act_shift) : in.act[P]);
+        lcs[i] = (uint16_t)((((kr ^ key[P - 1]) & kmask) != 0) ? i : 0);
+    }
+    // case ids of the output positions (striped), in flight during the sort:
+    // position i keeps the case of staging position i
     uint32_t ck[kSI];
 #pragma unroll
     for (int q = 0; q < kSI; ++q) {
         const int i = threadIdx.x + q * kSB;
-        ck[q] = 0;
-        if (i < R) {
-            const uint32_t kr = key[s + i];
-            ck[q] = kr & kmask;
-            lts[i] = in.ts[s + i];
-            lact[i] = (uint16_t)(act_shift > 0 ? (kr >> act_shift) : in.act[s + i]);
-            lcs[i] = (uint16_t)((i == 0 || ((kr ^ key[s + i - 1]) & kmask) != 0) ? i : 0);
-        }
+        ck[q] = i < R ? (key[s + i] & kmask) : 0u;
     }
     __syncthreads();
 
@@ -241,7 +268,8 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
         if (i == R - 1 || lcs[i + 1] == i + 1) lce[lcs[i]] = (uint16_t)(i + 1);
     }
 
-    // 4. sort every 64-event chunk in registers (wave w: chunks w, w + kSW, ...)
+    // 4. sort every 64-event chunk in registers (wave w: chunks w, w + kSW, ...;
+    //    chunk w + q*kSW, lane l is position threadIdx.x + q*kSB, as in step 5)
     const int w = threadIdx.x / kWave;
     const int l = lane();
     uint64_t sk[kSI];
@@ -272,7 +300,12 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
         }
     }
     const bool fast = __syncthreads_and(fits);   // also: every read of step 4 precedes the writes below
+    int32_t pos[kSI];
+    int64_t tv[kSI];
+    uint16_t av[kSI];
     if (fast) {
+        // sorted position i holds cross key (offset << 12 | staging position):
+        // unique, and ordered as (timestamp, row) across the chunks of a case
 #pragma unroll
         for (int q = 0; q < kSI; ++q) {
             const int ch = w + q * kSW;
@@ -280,10 +313,35 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
             uint64_t k = sk[q];
             bitonic64_u64(k, l);
             const int i = ch * kWave + l;
+            if (i < R) lts[i] = (int64_t)((((k >> 6) & kOffMask) << 12) | (uint64_t)(ch * kWave + (int)(k & 63u)));
+        }
+        __syncthreads();
+        // 5. rank inside the case: own portion + binary searches in the other portions
+#pragma unroll
+        for (int q = 0; q < kSI; ++q) {
+            const int i = threadIdx.x + q * kSB;
+            pos[q] = -1;
             if (i < R) {
-                // position i holds an event of the same case as staging position i
-                lidx[i] = (uint16_t)(ch * kWave + (int)(k & 63u));
-                lts[i] = (int64_t)((uint64_t)sb[q] + ((k >> 6) & kOffMask) - kOffBias);
+                const int cs = lcs[i];
+                const int ce = lce[cs];
+                const uint64_t x = (uint64_t)lts[i];
+                const int ch = i >> 6;
+                int r = i - (cs > (ch << 6) ? cs : (ch << 6));
+                const int c_last = (ce - 1) >> 6;
+                for (int c2 = cs >> 6; c2 <= c_last; ++c2) {
+                    if (c2 == ch) continue;
+                    const int p0 = cs > (c2 << 6) ? cs : (c2 << 6);
+                    int lo = p0, hi = ce < (c2 << 6) + kWave ? ce : (c2 << 6) + kWave;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if ((uint64_t)lts[mid] < x) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    r += lo - p0;
+                }
+                pos[q] = cs + r;
+                tv[q] = (int64_t)((uint64_t)sb[q] + (x >> 12) - kOffBias);
+                av[q] = lact[x & 0xFFFu];
             }
         }
     } else {
@@ -305,40 +363,36 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
                 lidx[i] = (uint16_t)id;
             }
         }
-    }
-    __syncthreads();
-
-    // 5. rank inside the case: own portion + binary searches in the other portions
-    int32_t pos[kSI];
-    int64_t tv[kSI];
-    uint16_t av[kSI];
+        __syncthreads();
+        // 5. rank inside the case: own portion + binary searches in the other portions
 #pragma unroll
-    for (int q = 0; q < kSI; ++q) {
-        const int i = threadIdx.x + q * kSB;
-        pos[q] = -1;
-        if (i < R) {
-            const int cs = lcs[i];
-            const int ce = lce[cs];
-            const int64_t t = lts[i];
-            const uint32_t id = lidx[i];
-            const int ch = i >> 6;
-            int r = i - (cs > (ch << 6) ? cs : (ch << 6));
-            const int c_last = (ce - 1) >> 6;
-            for (int c2 = cs >> 6; c2 <= c_last; ++c2) {
-                if (c2 == ch) continue;
-                const int p0 = cs > (c2 << 6) ? cs : (c2 << 6);
-                int lo = p0, hi = ce < (c2 << 6) + kWave ? ce : (c2 << 6) + kWave;
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    const int64_t tm = lts[mid];
-                    if (tm < t || (tm == t && (uint32_t)lidx[mid] < id)) lo = mid + 1;
-                    else hi = mid;
+        for (int q = 0; q < kSI; ++q) {
+            const int i = threadIdx.x + q * kSB;
+            pos[q] = -1;
+            if (i < R) {
+                const int cs = lcs[i];
+                const int ce = lce[cs];
+                const int64_t t = lts[i];
+                const uint32_t id = lidx[i];
+                const int ch = i >> 6;
+                int r = i - (cs > (ch << 6) ? cs : (ch << 6));
+                const int c_last = (ce - 1) >> 6;
+                for (int c2 = cs >> 6; c2 <= c_last; ++c2) {
+                    if (c2 == ch) continue;
+                    const int p0 = cs > (c2 << 6) ? cs : (c2 << 6);
+                    int lo = p0, hi = ce < (c2 << 6) + kWave ? ce : (c2 << 6) + kWave;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        const int64_t tm = lts[mid];
+                        if (tm < t || (tm == t && (uint32_t)lidx[mid] < id)) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    r += lo - p0;
                 }
-                r += lo - p0;
+                pos[q] = cs + r;
+                tv[q] = t;
+                av[q] = lact[id];
             }
-            pos[q] = cs + r;
-            tv[q] = t;
-            av[q] = lact[id];
         }
     }
     __syncthreads();
@@ -351,7 +405,7 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
     }
     __syncthreads();
 
-    // 6. write the prepared columns (position i keeps the case of staging position i)
+    // 6. write the prepared columns
     const uint32_t bias = (uint32_t)info->case_min;
 #pragma unroll
     for (int q = 0; q < kSI; ++q) {

@@ -336,6 +336,8 @@ __global__ __launch_bounds__(kVB) void k_view_emit(const int32_t* __restrict__ c
     __shared__ int64_t s_ts[TILE];
     __shared__ uint64_t s_mask[kVW][kMaskWords];
     __shared__ uint32_t s_cur[kVW][kMaxBuckets];
+    __shared__ uint32_t s_rrun[kVW], s_drun[kVW];
+    __shared__ int64_t s_rbase[kVW], s_dbase[kVW];
 
     const int wv = threadIdx.x / kWave;
     const int NB = w.n_buckets;
@@ -353,61 +355,86 @@ __global__ __launch_bounds__(kVB) void k_view_emit(const int32_t* __restrict__ c
         __syncthreads();
         const uint32_t cnt = w.tcount[tile];
         const int64_t off = w.toff[tile];
-        for (uint32_t j = wv; j < cnt; j += kVW) {
-            if (off + j >= w.pair_cap) break;   // wave-uniform; reported by the host
-            const uint32_t v = w.list[off + j];
-            const pm4g_view vw = views[v];
-            const int64_t p0 = w.p0[v], p1 = w.p1[v];
-            for (int q = lane(); q < MW; q += kWave) mask[q] = masks[(size_t)v * MW + q];
-            const int64_t e0 = T0 > p0 ? T0 : p0;
-            const int64_t e1 = T1 < p1 ? T1 : p1;
-            const WalkState st = walk_init(case_s, act_s, ts_s, e0, p0, vw.t_lo, vw.t_hi, mask);
-            for (int q = lane(); q < NB; q += kWave) cur[q] = 0;
-            walk<false>(s_case, s_act, s_ts, T0, e0, e1, st, A, vw.t_lo, vw.t_hi, mask, cur, 0, false,
-                        w.rec_cell, w.rec_gap);
-            // reserve the records and one descriptor per non-empty bucket;
-            // cur[q] becomes the exclusive offset of bucket q (the write cursor)
+        // rounds of one view per wave: the block reserves the round's records and
+        // descriptors with one atomic each (instead of one per wave and view)
+        for (uint32_t j0 = 0; j0 < cnt; j0 += kVW) {   // block-uniform
+            const uint32_t j = j0 + wv;
+            const bool has = j < cnt && off + j < w.pair_cap;   // pair overflow: reported by the host
+            uint32_t v = 0;
+            pm4g_view vw{};
+            int64_t p0 = 0, p1 = 0, e0 = 0, e1 = 0;
+            WalkState st{false, 0, false, 0, 0};
             uint32_t run = 0, nne = 0;
-            for (int q0 = 0; q0 < NB; q0 += kWave) {
-                const int q = q0 + lane();
-                const uint32_t c = q < NB ? cur[q] : 0u;
-                const uint32_t ic = wave_incl_sum(c);
-                if (q < NB) cur[q] = run + ic - c;
-                run += __shfl(ic, kWave - 1);
-                nne += (uint32_t)__popcll(__ballot(c != 0));
+            if (has) {   // wave-uniform
+                v = w.list[off + j];
+                vw = views[v];
+                p0 = w.p0[v];
+                p1 = w.p1[v];
+                for (int q = lane(); q < MW; q += kWave) mask[q] = masks[(size_t)v * MW + q];
+                e0 = T0 > p0 ? T0 : p0;
+                e1 = T1 < p1 ? T1 : p1;
+                st = walk_init(case_s, act_s, ts_s, e0, p0, vw.t_lo, vw.t_hi, mask);
+                for (int q = lane(); q < NB; q += kWave) cur[q] = 0;
+                walk<false>(s_case, s_act, s_ts, T0, e0, e1, st, A, vw.t_lo, vw.t_hi, mask, cur, 0, false,
+                            w.rec_cell, w.rec_gap);
+                // cur[q] becomes the exclusive offset of bucket q (the write cursor)
+                for (int q0 = 0; q0 < NB; q0 += kWave) {
+                    const int q = q0 + lane();
+                    const uint32_t c = q < NB ? cur[q] : 0u;
+                    const uint32_t ic = wave_incl_sum(c);
+                    if (q < NB) cur[q] = run + ic - c;
+                    run += __shfl(ic, kWave - 1);
+                    nne += (uint32_t)__popcll(__ballot(c != 0));
+                }
             }
-            int64_t rbase = 0, dbase = 0;
             if (lane() == 0) {
-                rbase = (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(&w.scal[0]),
-                                           (unsigned long long)run);
-                dbase = (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(&w.scal[1]),
-                                           (unsigned long long)nne);
+                s_rrun[wv] = run;
+                s_drun[wv] = nne;
             }
-            rbase = __shfl(rbase, 0);
-            dbase = __shfl(dbase, 0);
-            const bool ok = rbase + (int64_t)run <= w.rec_cap && dbase + (int64_t)nne <= w.desc_cap;
-            // descriptors: bucket q has count cur[q+1] - cur[q] (cur[NB] = run)
-            uint32_t drun = 0;
-            for (int q0 = 0; q0 < NB; q0 += kWave) {
-                const int q = q0 + lane();
-                uint32_t c = 0, o = 0;
-                if (q < NB) {
-                    o = cur[q];
-                    c = (q + 1 < NB ? cur[q + 1] : run) - o;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                uint64_t rt = 0, dt = 0;
+                for (int k = 0; k < kVW; ++k) {
+                    rt += s_rrun[k];
+                    dt += s_drun[k];
                 }
-                const uint64_t nzm = __ballot(c != 0);
-                if (ok && c != 0) {
-                    const int64_t d = dbase + drun + __popcll(nzm & lanes_below());
-                    w.d_view[d] = v;
-                    w.d_key[d] = v * (uint32_t)NB + (uint32_t)q;
-                    w.d_idx[d] = (uint32_t)d;
-                    w.d_off[d] = rbase + o;
-                    w.d_cnt[d] = c;
+                uint64_t rb = 0, db = 0;
+                if (rt) rb = atomicAdd(reinterpret_cast<unsigned long long*>(&w.scal[0]), (unsigned long long)rt);
+                if (dt) db = atomicAdd(reinterpret_cast<unsigned long long*>(&w.scal[1]), (unsigned long long)dt);
+                for (int k = 0; k < kVW; ++k) {
+                    s_rbase[k] = (int64_t)rb;
+                    s_dbase[k] = (int64_t)db;
+                    rb += s_rrun[k];
+                    db += s_drun[k];
                 }
-                drun += (uint32_t)__popcll(nzm);
             }
-            walk<true>(s_case, s_act, s_ts, T0, e0, e1, st, A, vw.t_lo, vw.t_hi, mask, cur, rbase, ok,
-                       w.rec_cell, w.rec_gap);
+            __syncthreads();
+            if (has) {   // wave-uniform
+                const int64_t rbase = s_rbase[wv], dbase = s_dbase[wv];
+                const bool ok = rbase + (int64_t)run <= w.rec_cap && dbase + (int64_t)nne <= w.desc_cap;
+                // descriptors: bucket q has count cur[q+1] - cur[q] (cur[NB] = run)
+                uint32_t drun = 0;
+                for (int q0 = 0; q0 < NB; q0 += kWave) {
+                    const int q = q0 + lane();
+                    uint32_t c = 0, o = 0;
+                    if (q < NB) {
+                        o = cur[q];
+                        c = (q + 1 < NB ? cur[q + 1] : run) - o;
+                    }
+                    const uint64_t nzm = __ballot(c != 0);
+                    if (ok && c != 0) {
+                        const int64_t d = dbase + drun + __popcll(nzm & lanes_below());
+                        w.d_view[d] = v;
+                        w.d_key[d] = v * (uint32_t)NB + (uint32_t)q;
+                        w.d_idx[d] = (uint32_t)d;
+                        w.d_off[d] = rbase + o;
+                        w.d_cnt[d] = c;
+                    }
+                    drun += (uint32_t)__popcll(nzm);
+                }
+                walk<true>(s_case, s_act, s_ts, T0, e0, e1, st, A, vw.t_lo, vw.t_hi, mask, cur, rbase, ok,
+                           w.rec_cell, w.rec_gap);
+            }
         }
         __syncthreads();
     }

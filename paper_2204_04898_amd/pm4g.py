@@ -18,7 +18,8 @@ import threading
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpm4g.so")
+# the in-tree build; PM4G_LIBRARY names another build of the same library
+LIB_PATH = os.environ.get("PM4G_LIBRARY") or os.path.join(_HERE, "libpm4g.so")
 
 PM4G_OK = 0
 PM4G_E_INVALID = -1
@@ -363,7 +364,9 @@ def pm4g_dfg_batched(prep: Prepared, views: torch.Tensor, masks: torch.Tensor, n
             t.agg_blocks = int(hit["agg_blocks"])
     else:
         t = BatchedTuning.from_buffer_copy(tuning)
-    cap = int(cap_edges) if cap_edges is not None else max(1024, min(prep.n_events, 1 << 24))
+    # output cells: at most A*A per view and one per kept event
+    cap = int(cap_edges) if cap_edges is not None else \
+        max(1024, min(int(n_views) * A * A, prep.n_events, 1 << 24))
     o = out if out is not None else _batched_out(n_views, A, cap, dev)
     for _ in range(6):
         need = int(L.pm4g_batched_workspace_bytes(prep.n_events, A, n_views, ctypes.byref(t)))
@@ -481,13 +484,17 @@ def dfg_to_host(o: dict, A: int) -> dict:
     return h
 
 
-def variants_to_host(o: dict, n_cases: int | None = None) -> dict:
+def variants_to_host(o: dict, n_cases: int | None = None, top: int | None = None) -> dict:
+    """Variants on the host; with `top`, only the first `top` variants of the
+    order (count desc, representative asc) and their sequences (n_variants
+    still counts all)."""
     V = int(o["n_variants"].item())
     h = dict(n_variants=V, status=int(o["status"].item()))
+    K = V if top is None else min(V, int(top))
     for k in ("var_count", "var_len", "var_rep"):
-        h[k] = o[k][:V].cpu().numpy()
-    h["var_off"] = o["var_off"][:V + 1].cpu().numpy()
-    h["var_acts"] = o["var_acts"][:int(h["var_off"][V])].cpu().numpy()
+        h[k] = o[k][:K].cpu().numpy()
+    h["var_off"] = o["var_off"][:K + 1].cpu().numpy()
+    h["var_acts"] = o["var_acts"][:int(h["var_off"][K])].cpu().numpy()
     if o.get("case_variant") is not None and n_cases is not None:
         h["case_variant"] = o["case_variant"][:n_cases].cpu().numpy()
     return h

@@ -18,7 +18,9 @@ Scheduling (host side, independent of the executor):
 
 GpuExecutor runs a batch with the library: all DFG and FILTER views of one
 log in one pm4g_dfg_batched launch, each VARIANTS view as pm4g_filter_view +
-pm4g_variants_prepared.
+pm4g_variants_prepared; a variants answer carries the variant count and the
+first `variants_top` variants (count desc, representative asc) with their
+sequences.
 """
 from __future__ import annotations
 
@@ -210,21 +212,26 @@ def poisson_requests(rng: np.random.Generator, rate: float, seconds: float, logs
 
 
 class GpuExecutor:
-    """Runs batches with libpm4g; one HIP stream and workspace per worker thread."""
+    """Runs batches with libpm4g; one HIP stream and one set of buffers per
+    worker thread (filtered view and variants outputs sized for the largest
+    log once, so requests allocate nothing large)."""
 
-    def __init__(self, logs: dict, device="cuda:0"):
+    def __init__(self, logs: dict, device="cuda:0", variants_top: int = 1000):
         import torch
 
         from . import pm4g
         self.torch = torch
         self.pm4g = pm4g
         self.device = torch.device(device)
+        self.variants_top = int(variants_top)
         self.logs = {}
         for name, prep in logs.items():
             C = int(prep.n_cases.item())
             off = prep.case_off[:C + 1].cpu().numpy()
             codes = prep.case_code[:C].cpu().numpy()
             self.logs[name] = dict(prep=prep, off=off, codes=codes)
+        self.max_events = max([p.n_events for p in logs.values()] + [1])
+        self.max_A = max([p.n_activities for p in logs.values()] + [1])
         self._local = threading.local()
 
     def slice_events(self, r: Request) -> int:
@@ -240,17 +247,30 @@ class GpuExecutor:
             return 2048 + S * 16 + S * 90
         return 2048 + S * 30
 
-    def _stream(self):
-        s = getattr(self._local, "stream", None)
-        if s is None:
-            s = self.torch.cuda.Stream(device=self.device)
-            self._local.stream = s
-        return s
+    def _state(self):
+        st = getattr(self._local, "state", None)
+        if st is None:
+            torch = self.torch
+            s = torch.cuda.Stream(device=self.device)
+            with torch.cuda.stream(s):
+                sub = self.pm4g.Prepared.empty(self.max_events, self.max_A, self.device)
+                vout = self.pm4g._var_out(self.max_events, self.device, with_cases=False)
+            s.synchronize()
+            st = dict(stream=s, sub=sub, vout=vout)
+            self._local.state = st
+        return st
+
+    def _view_of(self, sub, cap: int, A: int):
+        """The worker's filter buffers as a prepared log of capacity `cap`."""
+        return self.pm4g.Prepared(case_s=sub.case_s[:cap], act_s=sub.act_s[:cap], ts_s=sub.ts_s[:cap],
+                                  case_off=sub.case_off, case_code=sub.case_code, n_cases=sub.n_cases,
+                                  status=sub.status, n_activities=A)
 
     def run(self, batch: list[Request]) -> None:
         torch = self.torch
         pm4g = self.pm4g
-        s = self._stream()
+        st = self._state()
+        s = st["stream"]
         with torch.cuda.stream(s):
             by_log: dict[str, list[Request]] = {}
             for r in batch:
@@ -286,11 +306,11 @@ class GpuExecutor:
                 md = torch.from_numpy(np.ascontiguousarray(r.mask).view(np.int64).copy()).to(self.device)
                 cap = max(self.slice_events(r), 1)
                 sub = pm4g.pm4g_filter_view(prep, vd, md, stream=s,
-                                            out=pm4g.Prepared.empty(cap, prep.n_activities, self.device))
-                v = pm4g.pm4g_variants_prepared(sub, stream=s)
+                                            out=self._view_of(st["sub"], cap, prep.n_activities))
+                v = pm4g.pm4g_variants_prepared(sub, out=st["vout"], stream=s)
                 s.synchronize()
                 C = int(sub.n_cases.item())
-                h = pm4g.variants_to_host(v, C)
+                h = pm4g.variants_to_host(v, top=self.variants_top)
                 h["n_events"] = int(sub.case_off[C].item())
                 h["n_cases"] = C
                 r.result = h
