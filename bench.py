@@ -227,11 +227,13 @@ def bench_serving(logs: dict, preps: dict, seconds: float, rate: float) -> dict:
     # warm the executor's workspaces
     serve.Scheduler(ex, budget, max_batch=64, workers=2).run(copy.deepcopy(reqs[:16]))
     sch = serve.Scheduler(ex, budget, max_batch=64, workers=2)
-    res = sch.run(copy.deepcopy(reqs))
+    res = sch.run(copy.deepcopy(reqs), progress=log_progress)
     st = serve.latency_stats(res)
-    st.update(offered_qps=rate, seconds=seconds, n_requests=len(reqs), batches=len(sch.batches))
+    st.update(offered_qps=rate, seconds=seconds, n_requests=len(reqs), batches=len(sch.batches),
+              variants_answer=f"variant count + first {ex.variants_top} variants")
+    log_progress("serving: one request per launch")
     base = serve.Scheduler(ex, budget, max_batch=1, workers=1)
-    bres = base.run(copy.deepcopy(reqs))
+    bres = base.run(copy.deepcopy(reqs), progress=log_progress)
     st["one_request_per_launch"] = serve.latency_stats(bres)
     return st
 

@@ -92,6 +92,7 @@ struct PrepWs {
     RangePart* rpart;
     SortBufs a, b;
     uint32_t* hist;
+    uint32_t* hist_raw;
     uint32_t* rowsum;
     uint32_t* caseblk;
 };
@@ -100,7 +101,7 @@ PrepWs prep_ws_layout(Bump& bp, int64_t n) {
     PrepWs w{};
     const size_t m = (size_t)(n > 0 ? n : 1);
     w.info = bp.take<RangeInfo>(1);
-    w.rpart = bp.take<RangePart>(kRangeParts);
+    w.rpart = bp.take<RangePart>((size_t)(radix_blocks(n) > kRangeParts ? radix_blocks(n) : kRangeParts));
     w.a.key = bp.take<uint32_t>(m);
     w.a.ts = bp.take<int64_t>(m);
     w.a.act = bp.take<uint32_t>(m);
@@ -108,6 +109,7 @@ PrepWs prep_ws_layout(Bump& bp, int64_t n) {
     w.b.ts = bp.take<int64_t>(m);
     w.b.act = bp.take<uint32_t>(m);
     w.hist = bp.take<uint32_t>(256 * (size_t)(radix_blocks(n) + 1));
+    w.hist_raw = bp.take<uint32_t>(256 * (size_t)(radix_blocks(n) + 1));
     w.rowsum = bp.take<uint32_t>(256);
     w.caseblk = bp.take<uint32_t>((size_t)case_blocks(n) + 1);
     return w;
@@ -169,7 +171,7 @@ int run_prepare(const pm4g_log* log, const pm4g_prepared* out, bool case_table, 
     PrepWs w = prep_ws_layout(bp, n);
     k_set_status<<<1, 1, 0, s>>>(out->status, 0);
     PM4G_HIP(launch_range_scan(log->case_id, log->activity, log->timestamp, n, A, presorted, false,
-                               w.info, w.rpart, s));
+                               w.info, w.rpart, presorted ? nullptr : w.hist_raw, s));
     RangeInfo h{};
     PM4G_HIP(hipMemcpyAsync(&h, w.info, sizeof(h), hipMemcpyDeviceToHost, s));
     PM4G_HIP(hipStreamSynchronize(s));
@@ -195,7 +197,8 @@ int run_prepare(const pm4g_log* log, const pm4g_prepared* out, bool case_table, 
         SortBufs in = raw;
         int cur = 0;
         for (int p = 0; p < passes; ++p) {
-            PM4G_HIP(launch_radix_pass(in, bufs[cur], n, 0, 8 * p, p == 0, w.info, w.hist, w.rowsum, act_shift, s));
+            PM4G_HIP(launch_radix_pass(in, bufs[cur], n, 0, 8 * p, p == 0, w.info, w.hist, w.rowsum, act_shift,
+                                       p == 0 ? w.hist_raw : nullptr, s));
             in = bufs[cur];
             cur ^= 1;
         }
@@ -214,13 +217,13 @@ int run_prepare(const pm4g_log* log, const pm4g_prepared* out, bool case_table, 
             bool first = true;
             for (int p = 0; p < ts_passes; ++p, first = false) {
                 PM4G_HIP(launch_radix_pass(in, bufs[cur], n, 1, 8 * p, first, w.info, w.hist, w.rowsum,
-                                           act_shift, s));
+                                           act_shift, nullptr, s));
                 in = bufs[cur];
                 cur ^= 1;
             }
             for (int p = 0; p < passes; ++p, first = false) {
                 PM4G_HIP(launch_radix_pass(in, bufs[cur], n, 0, 8 * p, first, w.info, w.hist, w.rowsum,
-                                           act_shift, s));
+                                           act_shift, nullptr, s));
                 in = bufs[cur];
                 cur ^= 1;
             }

@@ -26,7 +26,8 @@ struct RangePart {
     int32_t bad, unsorted;
     int64_t tmin, tmax;
 };
-constexpr int kRangeParts = 2048;   // blocks of the range scan
+constexpr int kRangeParts = 2048;   // blocks of the grid-stride range scan
+constexpr int kRangeTileThreads = 512;
 
 // Bump allocator over the caller's workspace.  With base == nullptr it only
 // measures (used by pm4g_workspace_bytes), so the layout has one definition.
@@ -44,9 +45,12 @@ struct Bump {
 };
 
 // ---- range scan (range.hip) ----
+// hist_raw (may be NULL): [256][radix tiles] histograms of the raw case id's
+// low byte, for the first radix pass (raw logs only; the partials then need
+// one entry per radix tile).
 hipError_t launch_range_scan(const int32_t* case_id, const int32_t* act, const int64_t* ts, int64_t n,
                              int32_t A, bool presorted, bool want_ts, RangeInfo* info, RangePart* part,
-                             hipStream_t s);
+                             uint32_t* hist_raw, hipStream_t s);
 hipError_t launch_ts_range(const int64_t* ts, int64_t n, RangeInfo* info, hipStream_t s);
 
 // ---- LSD radix passes over (case key u32, ts i64, act u32) elements (radix.hip) ----
@@ -63,9 +67,11 @@ inline int64_t radix_blocks(int64_t n) { return (n + kRadixTile - 1) / kRadixTil
 // act_shift > 0 selects the packed layout: key = case | act << act_shift and
 // no activity column (act_shift = number of case bits, case bits + activity
 // bits <= 32); act_shift = 0: separate activity column.
+// hist_raw (may be NULL; first case pass only): the range scan's raw-byte
+// histograms, used instead of a histogram kernel.
 hipError_t launch_radix_pass(SortBufs in, SortBufs out, int64_t n, int digit_src, int shift,
                              bool first, const RangeInfo* info, uint32_t* hist, uint32_t* rowsum,
-                             int act_shift, hipStream_t s);
+                             int act_shift, const uint32_t* hist_raw, hipStream_t s);
 
 // ---- per-case ordering of a case-grouped sequence (segsort.hip) ----
 constexpr int kSegWindow = 1024;

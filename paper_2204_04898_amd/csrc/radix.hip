@@ -109,6 +109,38 @@ __global__ __launch_bounds__(256) void k_radix_scan(uint32_t* hist, int64_t nb, 
     if (threadIdx.x == 0) rowsum[blockIdx.x] = run;
 }
 
+// First case pass with the range scan's histograms of the raw low byte u:
+// digit d of case - case_min is u = (d + case_min) & 255, so row d is the
+// scan of raw row (d + case_min) & 255.
+__global__ __launch_bounds__(256) void k_radix_scan_rot(const uint32_t* hist_raw, uint32_t* hist, int64_t nb,
+                                                        uint32_t* rowsum, const RangeInfo* info) {
+    __shared__ uint32_t tmp[256 / kWave + 1];
+    const uint32_t u = (blockIdx.x + (uint32_t)info->case_min) & 255u;
+    const uint32_t* in = hist_raw + (int64_t)u * nb;
+    uint32_t* row = hist + (int64_t)blockIdx.x * nb;
+    uint32_t run = 0;
+    for (int64_t c0 = 0; c0 < nb; c0 += 256 * 4) {
+        uint32_t v[4];
+        uint32_t s = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = c0 + threadIdx.x * 4 + q;
+            v[q] = i < nb ? in[i] : 0u;
+            s += v[q];
+        }
+        uint32_t total;
+        uint32_t r = run + block_excl_sum<256>(s, tmp, &total);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = c0 + threadIdx.x * 4 + q;
+            if (i < nb) row[i] = r;
+            r += v[q];
+        }
+        run += total;
+    }
+    if (threadIdx.x == 0) rowsum[blockIdx.x] = run;
+}
+
 template <int SRC, bool FIRST, bool PACKED>
 __global__ __launch_bounds__(kRB) void k_radix_scatter(SortBufs in, SortBufs out, int64_t n, int shift,
                                                        const RangeInfo* info, const uint32_t* hist,
@@ -212,13 +244,17 @@ __global__ __launch_bounds__(kRB) void k_radix_scatter(SortBufs in, SortBufs out
 
 template <int SRC, bool FIRST, bool PACKED>
 static void run_pass(SortBufs in, SortBufs out, int64_t n, int shift, const RangeInfo* info,
-                     uint32_t* hist, uint32_t* rowsum, uint32_t key_mask, int act_shift, hipStream_t s) {
+                     uint32_t* hist, uint32_t* rowsum, uint32_t key_mask, int act_shift,
+                     const uint32_t* hist_raw, hipStream_t s) {
     const int64_t nb = radix_blocks(n);
-    {
-        ProfScope p(P_RADIX_HIST, s);
-        k_radix_hist<SRC, FIRST><<<(unsigned)nb, kRB, 0, s>>>(in, n, shift, info, hist, nb, key_mask);
-    }
-    {
+    if (hist_raw) {
+        ProfScope p(P_RADIX_SCAN, s);
+        k_radix_scan_rot<<<256, 256, 0, s>>>(hist_raw, hist, nb, rowsum, info);
+    } else {
+        {
+            ProfScope p(P_RADIX_HIST, s);
+            k_radix_hist<SRC, FIRST><<<(unsigned)nb, kRB, 0, s>>>(in, n, shift, info, hist, nb, key_mask);
+        }
         ProfScope p(P_RADIX_SCAN, s);
         k_radix_scan<<<256, 256, 0, s>>>(hist, nb, rowsum);
     }
@@ -229,12 +265,14 @@ static void run_pass(SortBufs in, SortBufs out, int64_t n, int shift, const Rang
 
 hipError_t launch_radix_pass(SortBufs in, SortBufs out, int64_t n, int digit_src, int shift,
                              bool first, const RangeInfo* info, uint32_t* hist, uint32_t* rowsum,
-                             int act_shift, hipStream_t s) {
+                             int act_shift, const uint32_t* hist_raw, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const bool packed = act_shift > 0;
     const uint32_t key_mask = packed ? ((act_shift >= 32) ? 0xFFFFFFFFu : ((1u << act_shift) - 1u)) : 0xFFFFFFFFu;
+    // the raw-byte histograms describe the first case pass only
+    if (!(digit_src == 0 && first && shift == 0)) hist_raw = nullptr;
 #define PM4G_PASS(SRC, FIRST, PACKED) \
-    run_pass<SRC, FIRST, PACKED>(in, out, n, shift, info, hist, rowsum, key_mask, act_shift, s)
+    run_pass<SRC, FIRST, PACKED>(in, out, n, shift, info, hist, rowsum, key_mask, act_shift, hist_raw, s)
     if (digit_src == 0) {
         if (first) { if (packed) PM4G_PASS(0, true, true); else PM4G_PASS(0, true, false); }
         else { if (packed) PM4G_PASS(0, false, true); else PM4G_PASS(0, false, false); }

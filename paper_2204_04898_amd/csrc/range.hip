@@ -102,6 +102,60 @@ __global__ __launch_bounds__(256) void k_range_scan(const int32_t* __restrict__ 
     }
 }
 
+// The formatting step's range scan over radix tiles (kRadixTile events per
+// block, no timestamps): besides the partials, each tile's histogram of the
+// low 8 bits of the raw case id.  The first radix pass digit is the low byte
+// of case - case_min, a rotation of that byte by case_min, so this histogram
+// replaces the first pass's histogram kernel (k_radix_scan_rot rotates it).
+__global__ __launch_bounds__(kRangeTileThreads) void k_range_tiles(const int32_t* __restrict__ case_id,
+                                                                   const int32_t* __restrict__ act, int64_t n,
+                                                                   int32_t A, RangePart* part,
+                                                                   uint32_t* hist_raw, int64_t nb) {
+    __shared__ uint32_t h[256];
+    __shared__ RangePart red[kRangeTileThreads / kWave];
+    constexpr int kT = kRangeTileThreads;
+    if (threadIdx.x < 256) h[threadIdx.x] = 0;
+    __syncthreads();
+    int32_t cmin = INT32_MAX, cmax = INT32_MIN;
+    bool bad = false;
+    auto visit = [&](int32_t c, int32_t a) {
+        bad |= (uint32_t)a >= (uint32_t)A;
+        cmin = c < cmin ? c : cmin;
+        cmax = c > cmax ? c : cmax;
+        atomicAdd(&h[(uint32_t)c & 255u], 1u);
+    };
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    const bool vec = base + kRadixTile <= n &&
+                     ((reinterpret_cast<uintptr_t>(case_id) | reinterpret_cast<uintptr_t>(act)) & 15) == 0;
+    if (vec) {
+        const int4* c4 = reinterpret_cast<const int4*>(case_id + base);
+        const int4* a4 = reinterpret_cast<const int4*>(act + base);
+#pragma unroll
+        for (int q = 0; q < kRadixTile / (4 * kT); ++q) {
+            const int4 c = c4[q * kT + threadIdx.x];
+            const int4 a = a4[q * kT + threadIdx.x];
+            visit(c.x, a.x);
+            visit(c.y, a.y);
+            visit(c.z, a.z);
+            visit(c.w, a.w);
+        }
+    } else {
+        for (int64_t i = base + threadIdx.x; i < n && i < base + kRadixTile; i += kT) visit(case_id[i], act[i]);
+    }
+    RangePart r{wave_min(cmin), wave_max(cmax), __ballot(bad) != 0, 0, INT64_MAX, INT64_MIN};
+    if (lane() == 0) red[threadIdx.x / kWave] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < kT / kWave; ++k) {
+            r.cmin = red[k].cmin < r.cmin ? red[k].cmin : r.cmin;
+            r.cmax = red[k].cmax > r.cmax ? red[k].cmax : r.cmax;
+            r.bad |= red[k].bad;
+        }
+        part[blockIdx.x] = r;
+    }
+    if (threadIdx.x < 256) hist_raw[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
 // One block folds the per-block partials into the RangeInfo.
 __global__ __launch_bounds__(1024) void k_range_final(const RangePart* part, int nparts, RangeInfo* info) {
     __shared__ RangePart red[1024 / kWave];
@@ -166,10 +220,16 @@ static int range_grid(int64_t n) {
 
 hipError_t launch_range_scan(const int32_t* case_id, const int32_t* act, const int64_t* ts, int64_t n,
                              int32_t A, bool presorted, bool want_ts, RangeInfo* info, RangePart* part,
-                             hipStream_t s) {
+                             uint32_t* hist_raw, hipStream_t s) {
     ProfScope p(P_RANGE, s);
     k_range_init<<<1, 1, 0, s>>>(info);
     if (n > 0) {
+        if (hist_raw && !presorted && !want_ts) {
+            const int64_t nb = radix_blocks(n);
+            k_range_tiles<<<(unsigned)nb, kRangeTileThreads, 0, s>>>(case_id, act, n, A, part, hist_raw, nb);
+            k_range_final<<<1, 1024, 0, s>>>(part, (int)nb, info);
+            return hipGetLastError();
+        }
         const int g = range_grid(n);
         if (presorted)
             k_range_scan<true, true><<<g, 256, 0, s>>>(case_id, act, ts, n, A, part);

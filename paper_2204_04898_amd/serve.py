@@ -12,9 +12,10 @@ Scheduling (host side, independent of the executor):
     formed from the head of the FIFO queue while the estimates fit in the
     budget left by the batches in flight; the head never gets skipped, so no
     request starves; a request larger than the whole budget is rejected;
-  - continuous batching: up to `workers` batches are in flight, each on its
-    own HIP stream, so requests that arrive while a batch runs join the next
-    batch and its work overlaps on the device with the running one.
+  - continuous batching: `workers` persistent worker threads, each with its
+    own HIP stream, run up to `workers` batches at once, so requests that
+    arrive while a batch runs join the next batch and its work overlaps on
+    the device with the running one.
 
 GpuExecutor runs a batch with the library: all DFG and FILTER views of one
 log in one pm4g_dfg_batched launch, each VARIANTS view as pm4g_filter_view +
@@ -25,6 +26,7 @@ sequences.
 from __future__ import annotations
 
 import dataclasses
+import queue as _queue
 import threading
 import time
 from typing import Callable
@@ -84,16 +86,33 @@ class Scheduler:
             batch.append(queue.pop(0))
         return batch
 
-    def run(self, requests: list[Request], t0: float | None = None) -> list[Request]:
-        """Serves `requests` (arrival times relative to t0); returns them completed."""
+    def run(self, requests: list[Request], t0: float | None = None,
+            progress: Callable[[str], None] | None = None) -> list[Request]:
+        """Serves `requests` (arrival times relative to t0); returns them completed.
+
+        `workers` persistent threads take the formed batches (each keeps its
+        own stream and buffers in the executor); the calling thread admits
+        arrivals and forms a batch whenever a worker is free."""
         pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
         for r in pending:
             r.est_bytes = int(self.ex.estimate(r))
         t0 = self.clock() if t0 is None else t0
-        queue: list[Request] = []
+        waiting: list[Request] = []
         done: list[Request] = []
-        threads: list[threading.Thread] = []
+        work: _queue.Queue = _queue.Queue()
+
+        def worker():
+            while True:
+                batch = work.get()
+                if batch is None:
+                    return
+                self._serve(batch, t0, done)
+
+        threads = [threading.Thread(target=worker, daemon=True) for _ in range(self.workers)]
+        for th in threads:
+            th.start()
         i = 0
+        last_note = self.clock()
         while True:
             now = self.clock() - t0
             while i < len(pending) and pending[i].arrival <= now:
@@ -102,19 +121,20 @@ class Scheduler:
                 if r.est_bytes > self.budget:
                     r.error = "request exceeds the memory budget"
                     r.dispatched = r.done = now
-                    done.append(r)
+                    with self._lock:
+                        done.append(r)
                 else:
-                    queue.append(r)
+                    waiting.append(r)
             batch: list[Request] = []
             with self._lock:
                 if self._in_flight < self.workers:
-                    batch = self.form_batch(queue)
+                    batch = self.form_batch(waiting)
                 if batch:
                     self._in_flight += 1
                     self._in_flight_bytes += sum(r.est_bytes for r in batch)
                     self.max_in_flight_bytes = max(self.max_in_flight_bytes, self._in_flight_bytes)
                     self.batches.append([r.rid for r in batch])
-                elif i == len(pending) and not queue and self._in_flight == 0:
+                elif i == len(pending) and not waiting and self._in_flight == 0:
                     break
                 else:
                     # sleep until the next arrival or a completion (notified), at most 5 ms
@@ -123,9 +143,12 @@ class Scheduler:
             if batch:
                 for r in batch:
                     r.dispatched = now
-                th = threading.Thread(target=self._serve, args=(batch, t0, done), daemon=True)
-                th.start()
-                threads.append(th)
+                work.put(batch)
+            if progress is not None and self.clock() - last_note > 2.0:
+                last_note = self.clock()
+                progress(f"serving: {len(done)}/{len(pending)} done, {len(waiting)} waiting at t={now:.1f} s")
+        for _ in threads:
+            work.put(None)
         for th in threads:
             th.join()
         return sorted(done, key=lambda r: r.rid)
