@@ -400,9 +400,14 @@ int pm4g_dfg_batched(const pm4g_prepared* log, const pm4g_view* views, const uin
         set_err("%lld (tile, view) pairs, pair_capacity %lld", (long long)sc[7], (long long)t.pair_cap);
         return PM4G_E_CAPACITY;
     }
-    PM4G_HIP(launch_views_emit(log, views, act_masks, w, t.emit_blocks, s));
+    PM4G_HIP(launch_views_count(log, views, act_masks, w, t.emit_blocks, s));
     PM4G_HIP(hipMemcpyAsync(sc, w.scal, sizeof(sc), hipMemcpyDeviceToHost, s));
     PM4G_HIP(hipStreamSynchronize(s));
+    if (sc[0] > (int64_t)0xFFFFFFFF) {
+        set_err("%lld kept (event, view) pairs in one call; at most 2^32 - 1: split the views",
+                (long long)sc[0]);
+        return PM4G_E_INVALID;
+    }
     if (sc[0] > t.rec_cap || sc[1] > t.desc_cap) {
         k_set_required<<<1, 1, 0, s>>>(out->required, sc[7], sc[0], sc[1], out->status);
         PM4G_HIP(hipGetLastError());
@@ -410,7 +415,7 @@ int pm4g_dfg_batched(const pm4g_prepared* log, const pm4g_view* views, const uin
                 (long long)t.rec_cap, (long long)sc[1], (long long)t.desc_cap);
         return PM4G_E_CAPACITY;
     }
-    PM4G_HIP(launch_views_reduce(log, n_views, w, o, t.agg_blocks, s));
+    PM4G_HIP(launch_views_reduce(log, views, act_masks, n_views, w, o, t.emit_blocks, t.agg_blocks, s));
     return PM4G_OK;
 }
 

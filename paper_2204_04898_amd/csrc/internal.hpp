@@ -205,9 +205,14 @@ struct ViewWs {
     int64_t* part64;
     uint16_t* rec_cell;     // [rec_cap] records: cell within its bucket, gap
     uint64_t* rec_gap;
-    uint32_t* d_view;       // [desc_cap] run descriptors
-    int64_t* d_off;
-    uint32_t* d_cnt;
+    uint32_t* pair_dbase;   // [pair_cap] first descriptor of each (tile, view) pair
+    uint32_t* pair_nd;      // [pair_cap] its descriptors (non-empty buckets)
+    uint32_t* d_cnt;        // [desc_cap] run descriptors: records of the run
+    uint16_t* d_q;          //   bucket of the run
+    int64_t* d_pos;         //   first record of the run (segment-contiguous layout)
+    uint32_t* d_cnt_sorted; //   counts in (view, bucket) order
+    int64_t* d_pos_sorted;
+    int64_t* seg_rec;       // [segments + 1] first record of each (view, bucket) segment
     uint32_t* d_key;        // (view, bucket) sort keys, ping-pong with d_key2
     uint32_t* d_key2;
     uint32_t* d_idx;
@@ -263,9 +268,14 @@ hipError_t launch_filter_view(const pm4g_prepared* p, const pm4g_view* view, con
 
 hipError_t launch_views_plan(const pm4g_prepared* p, const pm4g_view* views, int32_t V, ViewWs w,
                              BatchedOutDev out, hipStream_t s);
-hipError_t launch_views_emit(const pm4g_prepared* p, const pm4g_view* views, const uint64_t* masks,
-                             ViewWs w, int grid, hipStream_t s);
-hipError_t launch_views_reduce(const pm4g_prepared* p, int32_t V, ViewWs w, BatchedOutDev out, int agg_grid,
-                               hipStream_t s);
+// Count walk: per (tile, view) pair its records per bucket, one descriptor per
+// non-empty bucket; record and descriptor totals in scal[0], scal[1].
+hipError_t launch_views_count(const pm4g_prepared* p, const pm4g_view* views, const uint64_t* masks,
+                              ViewWs w, int grid, hipStream_t s);
+// After the descriptors are sorted and placed: write walk into runs.
+hipError_t launch_views_write(const pm4g_prepared* p, const pm4g_view* views, const uint64_t* masks,
+                              ViewWs w, int grid, hipStream_t s);
+hipError_t launch_views_reduce(const pm4g_prepared* p, const pm4g_view* views, const uint64_t* masks, int32_t V,
+                               ViewWs w, BatchedOutDev out, int emit_grid, int agg_grid, hipStream_t s);
 
 }  // namespace pm4g

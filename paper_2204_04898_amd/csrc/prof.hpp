@@ -30,6 +30,7 @@ enum ProfId {
     P_VIEW_OUT,
     P_VIEW_FILTER,
     P_DFG_COUNT,
+    P_VIEW_WRITE,
     P_COUNT
 };
 

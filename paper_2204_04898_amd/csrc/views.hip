@@ -82,9 +82,14 @@ ViewWs view_ws_layout(Bump& b, int64_t n, int32_t A, int32_t V, int32_t tile, in
     w.part64 = b.take<int64_t>(dev::kScanGrid);
     w.rec_cell = b.take<uint16_t>(rc);
     w.rec_gap = b.take<uint64_t>(rc);
-    w.d_view = b.take<uint32_t>(dc);
-    w.d_off = b.take<int64_t>(dc);
+    w.pair_dbase = b.take<uint32_t>((size_t)(pair_cap > 0 ? pair_cap : 1));
+    w.pair_nd = b.take<uint32_t>((size_t)(pair_cap > 0 ? pair_cap : 1));
     w.d_cnt = b.take<uint32_t>(dc);
+    w.d_q = b.take<uint16_t>(dc);
+    w.d_pos = b.take<int64_t>(dc);
+    w.d_cnt_sorted = b.take<uint32_t>(dc);
+    w.d_pos_sorted = b.take<int64_t>(dc);
+    w.seg_rec = b.take<int64_t>(dc + 1);
     w.d_key = b.take<uint32_t>(dc);
     w.d_key2 = b.take<uint32_t>(dc);
     w.d_idx = b.take<uint32_t>(dc);
@@ -108,9 +113,10 @@ ViewWs view_ws_layout(Bump& b, int64_t n, int32_t A, int32_t V, int32_t tile, in
 
 namespace {
 
-// scal: [0] record cursor, [1] descriptor cursor, [2] #segments (u32 total
+// scal: [0] records, [1] descriptor cursor, [2] #segments (u32 total
 // written at [8] as u32 by the scan, copied here), [3] temporary cell cursor,
-// [4] total output cells, [5] descriptors to sort, [6] #views, [7] #pairs
+// [4] total output cells, [5] descriptors to sort, [6] #views, [7] #pairs,
+// [9] records placed (scan total)
 
 __global__ void k_view_init(ViewWs w, int32_t V, int32_t A, const int32_t* status_in,
                             BatchedOutDev out) {
@@ -253,12 +259,12 @@ __device__ WalkState walk_init(const int32_t* case_s, const int32_t* act_s, cons
 
 // One walk over [e0, e1) of the staged tile (T0 = first position of the tile).
 // Every kept event yields one record; WRITE=false counts per bucket in
-// cursor[], WRITE=true takes slots from cursor[] and writes the records.
+// cursor[], WRITE=true takes record places from cursor[] (each bucket's
+// cursor starts at its run) and writes the records.
 template <bool WRITE>
 __device__ void walk(const int32_t* s_case, const int16_t* s_act, const int64_t* s_ts, int64_t T0,
                      int64_t e0, int64_t e1, WalkState st, int32_t A, int64_t tlo, int64_t thi,
-                     const uint64_t* mask, uint32_t* cursor, int64_t rec_base, bool can_write,
-                     uint16_t* rec_cell, uint64_t* rec_gap) {
+                     const uint64_t* mask, uint32_t* cursor, uint16_t* rec_cell, uint64_t* rec_gap) {
     const int64_t AA = (int64_t)A * A;
     const uint64_t below = lanes_below();
     const uint64_t le = below | (uint64_t(1) << lane());
@@ -301,9 +307,9 @@ __device__ void walk(const int32_t* s_case, const int16_t* s_act, const int64_t*
             const int64_t cell = has_prev ? (int64_t)pa * A + a : AA + a;
             const uint64_t gap = has_prev ? (uint64_t)t - (uint64_t)pt : 0ull;
             const uint32_t slot = atomicAdd(&cursor[(uint32_t)(cell >> 12)], 1u);
-            if (WRITE && can_write) {
-                rec_cell[rec_base + slot] = (uint16_t)(cell & (kCellsPerTable - 1));
-                rec_gap[rec_base + slot] = gap;
+            if (WRITE) {   // slot: the record's place (the cursor starts at its run)
+                rec_cell[slot] = (uint16_t)(cell & (kCellsPerTable - 1));
+                rec_gap[slot] = gap;
             }
         }
         // carry to the next window
@@ -325,19 +331,21 @@ __device__ void walk(const int32_t* s_case, const int16_t* s_act, const int64_t*
     }
 }
 
+// Count walk.  Rounds of one view per wave: the block reserves the round's
+// descriptors with one atomic (and adds the round's records to the total).
 template <int TILE>
-__global__ __launch_bounds__(kVB) void k_view_emit(const int32_t* __restrict__ case_s,
-                                                   const int32_t* __restrict__ act_s,
-                                                   const int64_t* __restrict__ ts_s, int64_t n, int32_t A,
-                                                   const pm4g_view* __restrict__ views,
-                                                   const uint64_t* __restrict__ masks, ViewWs w) {
+__global__ __launch_bounds__(kVB) void k_view_count(const int32_t* __restrict__ case_s,
+                                                    const int32_t* __restrict__ act_s,
+                                                    const int64_t* __restrict__ ts_s, int64_t n, int32_t A,
+                                                    const pm4g_view* __restrict__ views,
+                                                    const uint64_t* __restrict__ masks, ViewWs w) {
     __shared__ int32_t s_case[TILE];
     __shared__ int16_t s_act[TILE];
     __shared__ int64_t s_ts[TILE];
     __shared__ uint64_t s_mask[kVW][kMaskWords];
     __shared__ uint32_t s_cur[kVW][kMaxBuckets];
     __shared__ uint32_t s_rrun[kVW], s_drun[kVW];
-    __shared__ int64_t s_rbase[kVW], s_dbase[kVW];
+    __shared__ int64_t s_dbase[kVW];
 
     const int wv = threadIdx.x / kWave;
     const int NB = w.n_buckets;
@@ -355,35 +363,25 @@ __global__ __launch_bounds__(kVB) void k_view_emit(const int32_t* __restrict__ c
         __syncthreads();
         const uint32_t cnt = w.tcount[tile];
         const int64_t off = w.toff[tile];
-        // rounds of one view per wave: the block reserves the round's records and
-        // descriptors with one atomic each (instead of one per wave and view)
         for (uint32_t j0 = 0; j0 < cnt; j0 += kVW) {   // block-uniform
             const uint32_t j = j0 + wv;
             const bool has = j < cnt && off + j < w.pair_cap;   // pair overflow: reported by the host
-            uint32_t v = 0;
-            pm4g_view vw{};
-            int64_t p0 = 0, p1 = 0, e0 = 0, e1 = 0;
-            WalkState st{false, 0, false, 0, 0};
-            uint32_t run = 0, nne = 0;
+            uint32_t v = 0, run = 0, nne = 0;
             if (has) {   // wave-uniform
                 v = w.list[off + j];
-                vw = views[v];
-                p0 = w.p0[v];
-                p1 = w.p1[v];
+                const pm4g_view vw = views[v];
+                const int64_t p0 = w.p0[v], p1 = w.p1[v];
                 for (int q = lane(); q < MW; q += kWave) mask[q] = masks[(size_t)v * MW + q];
-                e0 = T0 > p0 ? T0 : p0;
-                e1 = T1 < p1 ? T1 : p1;
-                st = walk_init(case_s, act_s, ts_s, e0, p0, vw.t_lo, vw.t_hi, mask);
+                const int64_t e0 = T0 > p0 ? T0 : p0;
+                const int64_t e1 = T1 < p1 ? T1 : p1;
+                const WalkState st = walk_init(case_s, act_s, ts_s, e0, p0, vw.t_lo, vw.t_hi, mask);
                 for (int q = lane(); q < NB; q += kWave) cur[q] = 0;
-                walk<false>(s_case, s_act, s_ts, T0, e0, e1, st, A, vw.t_lo, vw.t_hi, mask, cur, 0, false,
+                walk<false>(s_case, s_act, s_ts, T0, e0, e1, st, A, vw.t_lo, vw.t_hi, mask, cur,
                             w.rec_cell, w.rec_gap);
-                // cur[q] becomes the exclusive offset of bucket q (the write cursor)
                 for (int q0 = 0; q0 < NB; q0 += kWave) {
                     const int q = q0 + lane();
                     const uint32_t c = q < NB ? cur[q] : 0u;
-                    const uint32_t ic = wave_incl_sum(c);
-                    if (q < NB) cur[q] = run + ic - c;
-                    run += __shfl(ic, kWave - 1);
+                    run += (uint32_t)wave_sum((uint64_t)c);
                     nne += (uint32_t)__popcll(__ballot(c != 0));
                 }
             }
@@ -398,43 +396,87 @@ __global__ __launch_bounds__(kVB) void k_view_emit(const int32_t* __restrict__ c
                     rt += s_rrun[k];
                     dt += s_drun[k];
                 }
-                uint64_t rb = 0, db = 0;
-                if (rt) rb = atomicAdd(reinterpret_cast<unsigned long long*>(&w.scal[0]), (unsigned long long)rt);
+                if (rt) atomicAdd(reinterpret_cast<unsigned long long*>(&w.scal[0]), (unsigned long long)rt);
+                uint64_t db = 0;
                 if (dt) db = atomicAdd(reinterpret_cast<unsigned long long*>(&w.scal[1]), (unsigned long long)dt);
                 for (int k = 0; k < kVW; ++k) {
-                    s_rbase[k] = (int64_t)rb;
                     s_dbase[k] = (int64_t)db;
-                    rb += s_rrun[k];
                     db += s_drun[k];
                 }
             }
             __syncthreads();
             if (has) {   // wave-uniform
-                const int64_t rbase = s_rbase[wv], dbase = s_dbase[wv];
-                const bool ok = rbase + (int64_t)run <= w.rec_cap && dbase + (int64_t)nne <= w.desc_cap;
-                // descriptors: bucket q has count cur[q+1] - cur[q] (cur[NB] = run)
+                const int64_t dbase = s_dbase[wv];
+                const bool ok = dbase + (int64_t)nne <= w.desc_cap;
+                if (lane() == 0) {
+                    w.pair_dbase[off + j] = (uint32_t)dbase;
+                    w.pair_nd[off + j] = ok ? nne : 0u;
+                }
                 uint32_t drun = 0;
                 for (int q0 = 0; q0 < NB; q0 += kWave) {
                     const int q = q0 + lane();
-                    uint32_t c = 0, o = 0;
-                    if (q < NB) {
-                        o = cur[q];
-                        c = (q + 1 < NB ? cur[q + 1] : run) - o;
-                    }
+                    const uint32_t c = q < NB ? cur[q] : 0u;
                     const uint64_t nzm = __ballot(c != 0);
                     if (ok && c != 0) {
                         const int64_t d = dbase + drun + __popcll(nzm & lanes_below());
-                        w.d_view[d] = v;
                         w.d_key[d] = v * (uint32_t)NB + (uint32_t)q;
                         w.d_idx[d] = (uint32_t)d;
-                        w.d_off[d] = rbase + o;
                         w.d_cnt[d] = c;
+                        w.d_q[d] = (uint16_t)q;
                     }
                     drun += (uint32_t)__popcll(nzm);
                 }
-                walk<true>(s_case, s_act, s_ts, T0, e0, e1, st, A, vw.t_lo, vw.t_hi, mask, cur, rbase, ok,
-                           w.rec_cell, w.rec_gap);
             }
+        }
+        __syncthreads();
+    }
+}
+
+// Write walk: each (tile, view) pair's buckets start at their runs' places in
+// the segment-contiguous record layout.
+template <int TILE>
+__global__ __launch_bounds__(kVB) void k_view_write(const int32_t* __restrict__ case_s,
+                                                    const int32_t* __restrict__ act_s,
+                                                    const int64_t* __restrict__ ts_s, int64_t n, int32_t A,
+                                                    const pm4g_view* __restrict__ views,
+                                                    const uint64_t* __restrict__ masks, ViewWs w) {
+    __shared__ int32_t s_case[TILE];
+    __shared__ int16_t s_act[TILE];
+    __shared__ int64_t s_ts[TILE];
+    __shared__ uint64_t s_mask[kVW][kMaskWords];
+    __shared__ uint32_t s_cur[kVW][kMaxBuckets];
+
+    const int wv = threadIdx.x / kWave;
+    const int MW = (A + 63) / 64;
+    uint64_t* mask = s_mask[wv];
+    uint32_t* cur = s_cur[wv];
+    for (int64_t tile = blockIdx.x; tile < w.n_tiles; tile += gridDim.x) {
+        const int64_t T0 = tile * TILE;
+        const int64_t T1 = (T0 + TILE) < n ? (T0 + TILE) : n;
+        for (int64_t i = T0 + threadIdx.x; i < T1; i += kVB) {
+            s_case[i - T0] = case_s[i];
+            s_act[i - T0] = (int16_t)act_s[i];
+            s_ts[i - T0] = ts_s[i];
+        }
+        __syncthreads();
+        const uint32_t cnt = w.tcount[tile];
+        const int64_t off = w.toff[tile];
+        for (uint32_t j = wv; j < cnt; j += kVW) {
+            if (off + j >= w.pair_cap) break;   // wave-uniform (the host has checked)
+            const uint32_t nd = w.pair_nd[off + j];
+            if (nd == 0) continue;   // no kept event
+            const uint32_t v = w.list[off + j];
+            const pm4g_view vw = views[v];
+            const int64_t p0 = w.p0[v], p1 = w.p1[v];
+            for (int q = lane(); q < MW; q += kWave) mask[q] = masks[(size_t)v * MW + q];
+            const int64_t e0 = T0 > p0 ? T0 : p0;
+            const int64_t e1 = T1 < p1 ? T1 : p1;
+            const WalkState st = walk_init(case_s, act_s, ts_s, e0, p0, vw.t_lo, vw.t_hi, mask);
+            // cursors: the runs' first records (buckets without a run get no event)
+            const uint32_t db = w.pair_dbase[off + j];
+            for (uint32_t k = lane(); k < nd; k += kWave) cur[w.d_q[db + k]] = (uint32_t)w.d_pos[db + k];
+            walk<true>(s_case, s_act, s_ts, T0, e0, e1, st, A, vw.t_lo, vw.t_hi, mask, cur,
+                       w.rec_cell, w.rec_gap);
         }
         __syncthreads();
     }
@@ -465,9 +507,42 @@ __global__ void k_view_seg_starts(ViewWs w) {
     }
 }
 
-// One block per (view, bucket) segment.
-__global__ __launch_bounds__(kAB2) void k_view_agg(const uint32_t* keys, const uint32_t* idx, int32_t A,
-                                                   ViewWs w, BatchedOutDev out) {
+// Run places: descriptor counts in (view, bucket) order, their exclusive scan,
+// back to the descriptors; each segment's first record.
+__global__ void k_view_gather_cnt(const uint32_t* idx, ViewWs w) {
+    const int64_t D = w.scal[5];
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < D;
+         p += (int64_t)gridDim.x * blockDim.x)
+        w.d_cnt_sorted[p] = w.d_cnt[idx[p]];
+}
+
+__global__ void k_view_place(const uint32_t* idx, ViewWs w) {
+    const int64_t D = w.scal[5];
+    const int64_t S = w.scal[2];
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < D;
+         p += (int64_t)gridDim.x * blockDim.x)
+        w.d_pos[idx[p]] = w.d_pos_sorted[p];
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g <= S;
+         g += (int64_t)gridDim.x * blockDim.x)
+        w.seg_rec[g] = g < S ? w.d_pos_sorted[w.seg_start[g]] : w.scal[9];
+}
+
+__device__ __forceinline__ void view_agg_rec(uint32_t* scount, uint64_t* ssum, int64_t* smin, int64_t* smax,
+                                             uint32_t cell, uint64_t gap) {
+    const int64_t gg = (int64_t)gap;
+    atomicAdd(&scount[cell], 1u);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&ssum[cell]), (unsigned long long)gap);
+    if (gg < __hip_atomic_load(&smin[cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+        __hip_atomic_fetch_min(&smin[cell], gg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (gg > __hip_atomic_load(&smax[cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+        __hip_atomic_fetch_max(&smax[cell], gg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// One block per (view, bucket) segment: its records are one contiguous range,
+// streamed into a 4096-cell LDS table; after compaction only the touched
+// cells are reset, so the table is cleared once per block.
+__global__ __launch_bounds__(kAB2) void k_view_agg(const uint32_t* keys, int32_t A, ViewWs w,
+                                                   BatchedOutDev out) {
     __shared__ uint32_t scount[kCellsPerTable];
     __shared__ uint64_t ssum[kCellsPerTable];
     __shared__ int64_t smin[kCellsPerTable];
@@ -477,49 +552,47 @@ __global__ __launch_bounds__(kAB2) void k_view_agg(const uint32_t* keys, const u
     const int64_t S = w.scal[2];
     const int64_t AA = (int64_t)A * A;
     const int NB = w.n_buckets;
+    for (int c = threadIdx.x; c < kCellsPerTable; c += kAB2) {
+        scount[c] = 0;
+        ssum[c] = 0;
+        smin[c] = INT64_MAX;
+        smax[c] = INT64_MIN;
+    }
+    __syncthreads();
     for (int64_t g = blockIdx.x; g < S; g += gridDim.x) {
-        const uint32_t d0 = w.seg_start[g], d1 = w.seg_start[g + 1];
-        const uint32_t key = keys[d0];
+        const uint32_t key = keys[w.seg_start[g]];
         const uint32_t v = key / (uint32_t)NB;
         const uint32_t bk = key % (uint32_t)NB;
-        for (int c = threadIdx.x; c < kCellsPerTable; c += kAB2) {
-            scount[c] = 0;
-            ssum[c] = 0;
-            smin[c] = INT64_MAX;
-            smax[c] = INT64_MIN;
-        }
-        __syncthreads();
-        const int wv = threadIdx.x / kWave;
-        for (uint32_t d = d0 + wv; d < d1; d += kAB2 / kWave) {
-            const uint32_t di = idx[d];
-            const int64_t r0 = w.d_off[di];
-            const uint32_t rc = w.d_cnt[di];
-            for (uint32_t r = lane(); r < rc; r += kWave) {
-                const uint32_t cell = w.rec_cell[r0 + r];
-                const uint64_t gap = w.rec_gap[r0 + r];
-                const int64_t gg = (int64_t)gap;
-                atomicAdd(&scount[cell], 1u);
-                atomicAdd(reinterpret_cast<unsigned long long*>(&ssum[cell]), (unsigned long long)gap);
-                if (gg < __hip_atomic_load(&smin[cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
-                    __hip_atomic_fetch_min(&smin[cell], gg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (gg > __hip_atomic_load(&smax[cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
-                    __hip_atomic_fetch_max(&smax[cell], gg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int64_t r1 = w.seg_rec[g + 1];
+        constexpr int kU = 4;   // records in flight per thread
+        int64_t r = w.seg_rec[g] + threadIdx.x;
+        for (; r + (kU - 1) * kAB2 < r1; r += kU * kAB2) {
+            uint32_t cell[kU];
+            uint64_t gap[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                cell[u] = w.rec_cell[r + u * kAB2];
+                gap[u] = w.rec_gap[r + u * kAB2];
             }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) view_agg_rec(scount, ssum, smin, smax, cell[u], gap[u]);
         }
+        for (; r < r1; r += kAB2) view_agg_rec(scount, ssum, smin, smax, w.rec_cell[r], w.rec_gap[r]);
         __syncthreads();
         // compaction in cell order; start cells go straight to the start counts
         constexpr int kPer = kCellsPerTable / kAB2;   // 4 cells per thread, blocked
-        uint32_t flags = 0;
+        uint32_t flags = 0, touched = 0;
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
             const int c = threadIdx.x * kPer + q;
             const int64_t cell = (int64_t)bk * kCellsPerTable + c;
             if (scount[c] == 0) continue;
+            touched |= 1u << q;
             if (cell < AA) flags |= 1u << q;
             else if (cell < AA + A) out.start_count[(size_t)v * A + (cell - AA)] = scount[c];
         }
         uint32_t total;
-        uint32_t r = block_excl_sum<kAB2>((uint32_t)__popc(flags), tmp, &total);
+        uint32_t rr = block_excl_sum<kAB2>((uint32_t)__popc(flags), tmp, &total);
         if (threadIdx.x == 0) {
             s_base = (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(&w.scal[3]),
                                         (unsigned long long)total);
@@ -532,15 +605,21 @@ __global__ __launch_bounds__(kAB2) void k_view_agg(const uint32_t* keys, const u
         if (base + (int64_t)total > w.cell_cap) flags = 0;   // over capacity: counted, not written
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
-            if (!(flags & (1u << q))) continue;
+            if (!(touched & (1u << q))) continue;
             const int c = threadIdx.x * kPer + q;
-            const int64_t at = base + r;
-            w.t_cell[at] = (uint32_t)((int64_t)bk * kCellsPerTable + c);
-            w.t_count[at] = scount[c];
-            w.t_sum[at] = ssum[c];
-            w.t_min[at] = smin[c];
-            w.t_max[at] = smax[c];
-            ++r;
+            if (flags & (1u << q)) {
+                const int64_t at = base + rr;
+                w.t_cell[at] = (uint32_t)((int64_t)bk * kCellsPerTable + c);
+                w.t_count[at] = scount[c];
+                w.t_sum[at] = ssum[c];
+                w.t_min[at] = smin[c];
+                w.t_max[at] = smax[c];
+                ++rr;
+            }
+            scount[c] = 0;   // reset for the next segment
+            ssum[c] = 0;
+            smin[c] = INT64_MAX;
+            smax[c] = INT64_MIN;
         }
         __syncthreads();
     }
@@ -663,25 +742,40 @@ hipError_t launch_views_plan(const pm4g_prepared* p, const pm4g_view* views, int
     return hipGetLastError();
 }
 
-hipError_t launch_views_emit(const pm4g_prepared* p, const pm4g_view* views, const uint64_t* masks,
-                             ViewWs w, int grid, hipStream_t s) {
+hipError_t launch_views_count(const pm4g_prepared* p, const pm4g_view* views, const uint64_t* masks,
+                              ViewWs w, int grid, hipStream_t s) {
     ProfScope ps(P_VIEW_EMIT, s);
     const int64_t n = p->n_events;
     if (w.n_tiles > 0) {
         const unsigned g = (unsigned)(w.n_tiles < grid ? w.n_tiles : grid);
         if (w.tile == 2048)
-            k_view_emit<2048><<<g, kVB, 0, s>>>(p->case_s, p->act_s, p->ts_s, n, p->n_activities, views, masks, w);
+            k_view_count<2048><<<g, kVB, 0, s>>>(p->case_s, p->act_s, p->ts_s, n, p->n_activities, views, masks, w);
         else
-            k_view_emit<4096><<<g, kVB, 0, s>>>(p->case_s, p->act_s, p->ts_s, n, p->n_activities, views, masks, w);
+            k_view_count<4096><<<g, kVB, 0, s>>>(p->case_s, p->act_s, p->ts_s, n, p->n_activities, views, masks, w);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_views_reduce(const pm4g_prepared* p, int32_t V, ViewWs w, BatchedOutDev out, int agg_grid,
-                               hipStream_t s) {
+hipError_t launch_views_write(const pm4g_prepared* p, const pm4g_view* views, const uint64_t* masks,
+                              ViewWs w, int grid, hipStream_t s) {
+    ProfScope ps(P_VIEW_WRITE, s);
+    const int64_t n = p->n_events;
+    if (w.n_tiles > 0) {
+        const unsigned g = (unsigned)(w.n_tiles < grid ? w.n_tiles : grid);
+        if (w.tile == 2048)
+            k_view_write<2048><<<g, kVB, 0, s>>>(p->case_s, p->act_s, p->ts_s, n, p->n_activities, views, masks, w);
+        else
+            k_view_write<4096><<<g, kVB, 0, s>>>(p->case_s, p->act_s, p->ts_s, n, p->n_activities, views, masks, w);
+    }
+    return hipGetLastError();
+}
+
+// Sorts the descriptors by (view, bucket), places the runs, writes the
+// records (write walk), aggregates per segment.
+hipError_t launch_views_reduce(const pm4g_prepared* p, const pm4g_view* views, const uint64_t* masks, int32_t V,
+                               ViewWs w, BatchedOutDev out, int emit_grid, int agg_grid, hipStream_t s) {
     const int32_t A = p->n_activities;
     const uint32_t* keys;
-    const uint32_t* idx;
     {
         ProfScope ps(P_VIEW_SORT, s);
         // descriptors to sort: min(cursor, capacity); the host only comes here if they fit
@@ -690,14 +784,21 @@ hipError_t launch_views_reduce(const pm4g_prepared* p, int32_t V, ViewWs w, Batc
         const bool flip = dev::sort_pairs<uint32_t>(w.d_key, w.d_idx, w.d_key2, w.d_idx2, &w.scal[5], w.desc_cap,
                                                     kb, w.d_hist, w.d_rowsum, s);
         keys = flip ? w.d_key2 : w.d_key;
-        idx = flip ? w.d_idx2 : w.d_idx;
+        const uint32_t* idx = flip ? w.d_idx2 : w.d_idx;
         k_view_seg_flags<<<2048, 256, 0, s>>>(keys, w);
         dev::excl_scan<uint32_t>(w.seg_flag, &w.scal[5], w.seg_id, w.part32, (uint32_t*)&w.scal[8], s);
         k_view_seg_starts<<<2048, 256, 0, s>>>(w);
+        k_view_gather_cnt<<<2048, 256, 0, s>>>(idx, w);
+        dev::excl_scan<int64_t>(w.d_cnt_sorted, &w.scal[5], w.d_pos_sorted, w.part64, &w.scal[9], s);
+        k_view_place<<<2048, 256, 0, s>>>(idx, w);
+    }
+    {
+        const hipError_t e = launch_views_write(p, views, masks, w, emit_grid, s);
+        if (e != hipSuccess) return e;
     }
     {
         ProfScope ps(P_VIEW_AGG, s);
-        k_view_agg<<<(unsigned)agg_grid, kAB2, 0, s>>>(keys, idx, A, w, out);
+        k_view_agg<<<(unsigned)agg_grid, kAB2, 0, s>>>(keys, A, w, out);
     }
     {
         ProfScope ps(P_VIEW_OUT, s);
