@@ -296,30 +296,47 @@ __global__ __launch_bounds__(kCB) void k_dfg_count(const int32_t* __restrict__ c
     if (blockIdx.x == 0 && threadIdx.x == 0) ws.scal[0] = nbk * nch;
 }
 
-// Per chunk: every edge written at its bucket's cursor (LDS, seeded from the
-// scan); order inside a (bucket, chunk) run is free.  Span partial per block.
-// Dynamic LDS: nbk u32.
+// Per chunk: every edge goes to its bucket's run (cursor seeded from the scan).
+// Per 4096-event tile the edges are first grouped by bucket in LDS, then
+// written out in bucket order, so each bucket's piece is one coalesced run.
+// Span partial per block.  Dynamic LDS: 3 * nbk u32.
 __global__ __launch_bounds__(kCB) void k_dfg_scatter(const int32_t* __restrict__ case_s,
                                                      const int32_t* __restrict__ act_s,
                                                      const int64_t* __restrict__ ts_s, int64_t n, int32_t A,
                                                      int64_t nbk, int64_t nch, int64_t chunk, DfgWs ws) {
-    extern __shared__ uint32_t cur[];
+    extern __shared__ uint32_t dsm[];
+    uint32_t* cur = dsm;              // global cursor of each bucket
+    uint32_t* lcnt = dsm + nbk;       // edges per bucket in this tile
+    uint32_t* lstart = dsm + 2 * nbk; // their start in the staged tile
+    __shared__ uint16_t s_cell[kDfgTile];
+    __shared__ uint64_t s_gap[kDfgTile];
+    __shared__ uint16_t s_bk[kDfgTile];
+    __shared__ uint32_t tmp[kCB / kWave + 1];
     __shared__ uint64_t sspan[kCB / kWave];
+    constexpr int kQ = kDfgTile / (4 * kCB);   // quads per thread per tile (2)
     const bool aligned = ((reinterpret_cast<uintptr_t>(case_s) | reinterpret_cast<uintptr_t>(act_s) |
                            reinterpret_cast<uintptr_t>(ts_s)) & 15) == 0;
     uint64_t span = 0;
     for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
         for (int64_t k = threadIdx.x; k < nbk; k += kCB) cur[k] = ws.escan[k * nch + ch];
-        __syncthreads();
         const int64_t i1 = (ch + 1) * chunk < n ? (ch + 1) * chunk : n;
         for (int64_t t0 = ch * chunk; t0 < i1; t0 += kDfgTile) {
+            for (int64_t k = threadIdx.x; k < nbk; k += kCB) lcnt[k] = 0;
+            __syncthreads();
+            // 1. edges of this thread's quads: bucket, slot in the bucket, cell, gap
+            uint32_t eb[4 * kQ], ec[4 * kQ];
+            uint64_t eg[4 * kQ];
 #pragma unroll
-            for (int h = 0; h < kDfgTile / (4 * kCB); ++h) {
+            for (int h = 0; h < kQ; ++h) {
                 const int64_t e0 = t0 + 4 * (h * kCB + (int64_t)threadIdx.x);
-                if (t0 + 4 * h * kCB >= i1) break;   // block-uniform
-                const Quad qd = load_quad<true, false>(case_s, act_s, ts_s, e0, i1, n, aligned);
+                Quad qd{};
+                if (t0 + 4 * h * kCB < i1)   // block-uniform
+                    qd = load_quad<true, false>(case_s, act_s, ts_s, e0, i1, n, aligned);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
+                    const int u = 4 * h + j;
+                    eb[u] = 0xFFFFFFFFu;
+                    if (t0 + 4 * h * kCB >= i1) continue;
                     const int32_t cp = j ? qd.c[j - 1] : qd.cp;
                     const int32_t ap = j ? qd.a[j - 1] : qd.ap;
                     const int64_t tp = j ? qd.t[j - 1] : qd.tp;
@@ -329,11 +346,45 @@ __global__ __launch_bounds__(kCB) void k_dfg_scatter(const int32_t* __restrict__
                     const uint32_t cell = (uint32_t)ap * (uint32_t)A + (uint32_t)qd.a[j];
                     const uint64_t gap = (uint64_t)qd.t[j] - (uint64_t)tp;
                     span = sat_add63(span, cap63(gap));
-                    const uint32_t pos = atomicAdd(&cur[cell >> 12], 1u);
-                    ws.ecell[pos] = (uint16_t)(cell & (kCellsPerTable - 1));
-                    ws.egap[pos] = gap;
+                    const uint32_t b = cell >> 12;
+                    const uint32_t slot = atomicAdd(&lcnt[b], 1u);
+                    eb[u] = b | (slot << 16);   // nbk <= 4096, slot < 4096
+                    ec[u] = cell & (kCellsPerTable - 1);
+                    eg[u] = gap;
                 }
             }
+            __syncthreads();
+            // 2. bucket starts inside the staged tile
+            uint32_t E = 0;
+            for (int64_t k0 = 0; k0 < nbk; k0 += kCB) {
+                const int64_t k = k0 + threadIdx.x;
+                const uint32_t v = k < nbk ? lcnt[k] : 0u;
+                uint32_t total;
+                const uint32_t ex = block_excl_sum<kCB>(v, tmp, &total);
+                if (k < nbk) lstart[k] = E + ex;
+                E += total;
+            }
+            __syncthreads();
+            // 3. stage in bucket order
+#pragma unroll
+            for (int u = 0; u < 4 * kQ; ++u) {
+                if (eb[u] == 0xFFFFFFFFu) continue;
+                const uint32_t b = eb[u] & 0xFFFFu;
+                const uint32_t at = lstart[b] + (eb[u] >> 16);
+                s_cell[at] = (uint16_t)ec[u];
+                s_gap[at] = eg[u];
+                s_bk[at] = (uint16_t)b;
+            }
+            __syncthreads();
+            // 4. coalesced runs out
+            for (uint32_t i = threadIdx.x; i < E; i += kCB) {
+                const uint32_t b = s_bk[i];
+                const uint32_t g = cur[b] + (i - lstart[b]);
+                ws.ecell[g] = s_cell[i];
+                ws.egap[g] = s_gap[i];
+            }
+            __syncthreads();
+            for (int64_t k = threadIdx.x; k < nbk; k += kCB) cur[k] += lcnt[k];
         }
         __syncthreads();
     }
@@ -557,8 +608,8 @@ hipError_t launch_dfg(const int32_t* case_s, const int32_t* act_s, const int64_t
         }
         {
             ProfScope p(P_DFG_MAIN, s);
-            k_dfg_scatter<<<g, kCB, (size_t)nbk * sizeof(uint32_t), s>>>(case_s, act_s, ts_s, n, A, nbk, nch,
-                                                                       chunk, ws);
+            k_dfg_scatter<<<g, kCB, (size_t)3 * nbk * sizeof(uint32_t), s>>>(case_s, act_s, ts_s, n, A, nbk,
+                                                                           nch, chunk, ws);
         }
         {
             ProfScope p(P_DFG_PLAN, s);

@@ -288,6 +288,12 @@ __device__ void walk(const int32_t* s_case, const int16_t* s_act, const int64_t*
         starts = starts && in;
         const uint64_t K = __ballot(k);
         const uint64_t S = __ballot(starts);
+        if (K == 0) {   // wave-uniform: nothing kept in this step, only the carry moves
+            if (S) st.cr_valid = false;   // the last case began here, nothing of it kept yet
+            st.cur = __shfl(c, hi_bit(__ballot(in)));
+            st.have_cur = true;
+            continue;
+        }
         const uint64_t sle = S & le;
         const int sl = sle ? hi_bit(sle) : -1;           // -1: the segment began before the window
         const uint64_t seg = sl < 0 ? below : (below & ~((uint64_t(1) << sl) - 1));
