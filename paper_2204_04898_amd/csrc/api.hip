@@ -95,6 +95,7 @@ struct PrepWs {
     uint32_t* hist_raw;
     uint32_t* rowsum;
     uint32_t* caseblk;
+    uint32_t* wincnt;
 };
 
 PrepWs prep_ws_layout(Bump& bp, int64_t n) {
@@ -112,6 +113,7 @@ PrepWs prep_ws_layout(Bump& bp, int64_t n) {
     w.hist_raw = bp.take<uint32_t>(256 * (size_t)(radix_blocks(n) + 1));
     w.rowsum = bp.take<uint32_t>(256);
     w.caseblk = bp.take<uint32_t>((size_t)case_blocks(n) + 1);
+    w.wincnt = bp.take<uint32_t>((size_t)segsort_blocks(n) + 1);
     return w;
 }
 
@@ -182,6 +184,7 @@ int run_prepare(const pm4g_log* log, const pm4g_prepared* out, bool case_table, 
                                                : "rows are not in (case, timestamp, row) order");
         return h.status;
     }
+    bool have_wincnt = false;   // the per-case sort counted the cases of each window
     if (presorted) {
         PM4G_HIP(launch_copy_log(log->case_id, log->activity, log->timestamp, n, out->case_s,
                                  out->act_s, out->ts_s, s));
@@ -202,9 +205,10 @@ int run_prepare(const pm4g_log* log, const pm4g_prepared* out, bool case_table, 
             in = bufs[cur];
             cur ^= 1;
         }
-        PM4G_HIP(launch_segsort(in, n, w.info, out->case_s, out->act_s, out->ts_s, act_shift, s));
+        PM4G_HIP(launch_segsort(in, n, w.info, out->case_s, out->act_s, out->ts_s, act_shift, w.wincnt, s));
         PM4G_HIP(hipMemcpyAsync(&h, w.info, sizeof(h), hipMemcpyDeviceToHost, s));
         PM4G_HIP(hipStreamSynchronize(s));
+        have_wincnt = !h.long_case;
         if (h.long_case) {
             // Full-key fallback: stable passes on the timestamp bits, then the case bits.
             PM4G_HIP(launch_ts_range(log->timestamp, n, w.info, s));
@@ -232,7 +236,7 @@ int run_prepare(const pm4g_log* log, const pm4g_prepared* out, bool case_table, 
     }
     if (case_table)
         PM4G_HIP(launch_case_table(out->case_s, n, w.caseblk, out->case_off, out->case_code,
-                                   out->n_cases, s));
+                                   out->n_cases, have_wincnt ? w.wincnt : nullptr, s));
     return PM4G_OK;
 }
 

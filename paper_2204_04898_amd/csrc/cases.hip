@@ -3,7 +3,8 @@
 // distinct case id in order and case_off[j] the position of its first event.
 // Reduce-then-scan compaction of the boundary flags
 // flag(i) = (i == 0) || case_s[i] != case_s[i-1]:
-//   k_case_count  per-tile flag counts
+//   k_case_count  per-tile flag counts (or k_case_tiles: from the per-window
+//                 case counts the per-case sort already produced)
 //   k_case_scan   exclusive scan of the tile counts, n_cases, case_off[C] = N
 //   k_case_emit   per-tile ranks -> case_off / case_code
 // Bytes per event: 4 + 4 read (the column is read twice).
@@ -46,6 +47,22 @@ __global__ __launch_bounds__(1024) void k_case_scan(uint32_t* blockcnt, int64_t 
     if (threadIdx.x == 0) {
         *n_cases = run;
         case_off[run] = n;
+    }
+}
+
+// Tile counts from per-window counts (kCaseTile / kSegWindow windows per tile),
+// written by the per-case sort.
+__global__ __launch_bounds__(1024) void k_case_tiles(const uint32_t* wincnt, int64_t nwin, uint32_t* blockcnt,
+                                                     int64_t nb) {
+    constexpr int kPerTile = kCaseTile / kSegWindow;
+    for (int64_t t = (int64_t)blockIdx.x * 1024 + threadIdx.x; t < nb; t += (int64_t)gridDim.x * 1024) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int k = 0; k < kPerTile; ++k) {
+            const int64_t w = t * kPerTile + k;
+            if (w < nwin) c += wincnt[w];
+        }
+        blockcnt[t] = c;
     }
 }
 
@@ -92,10 +109,18 @@ __global__ __launch_bounds__(kCB) void k_case_emit(const int32_t* __restrict__ c
 }
 
 hipError_t launch_case_table(const int32_t* case_s, int64_t n, uint32_t* blockcnt, int64_t* case_off,
-                             int32_t* case_code, int64_t* n_cases, hipStream_t s) {
+                             int32_t* case_code, int64_t* n_cases, const uint32_t* wincnt, hipStream_t s) {
+    static_assert(kCaseTile % kSegWindow == 0, "case tiles hold whole sort windows");
     ProfScope p(P_CASE_TABLE, s);
     const int64_t nb = case_blocks(n);
-    if (nb > 0) k_case_count<<<(unsigned)nb, kCB, 0, s>>>(case_s, n, blockcnt);
+    if (nb > 0) {
+        if (wincnt) {
+            const int64_t g = (nb + 1023) / 1024;
+            k_case_tiles<<<(unsigned)(g < 1024 ? g : 1024), 1024, 0, s>>>(wincnt, segsort_blocks(n), blockcnt, nb);
+        } else {
+            k_case_count<<<(unsigned)nb, kCB, 0, s>>>(case_s, n, blockcnt);
+        }
+    }
     k_case_scan<<<1, 1024, 0, s>>>(blockcnt, nb, n, case_off, n_cases);
     if (nb > 0) k_case_emit<<<(unsigned)nb, kCB, 0, s>>>(case_s, n, blockcnt, case_off, case_code);
     return hipGetLastError();

@@ -77,8 +77,9 @@ hipError_t launch_radix_pass(SortBufs in, SortBufs out, int64_t n, int digit_src
 constexpr int kSegWindow = 1024;
 constexpr int kSegCap = 3072;   // window + the longest case kept on the fast path (2049) - 1
 inline int64_t segsort_blocks(int64_t n) { return (n + kSegWindow - 1) / kSegWindow; }
+// wincnt: [segsort_blocks(n)] cases starting in each window (valid unless long_case).
 hipError_t launch_segsort(SortBufs in, int64_t n, RangeInfo* info, int32_t* case_s, int32_t* act_s,
-                          int64_t* ts_s, int act_shift, hipStream_t s);
+                          int64_t* ts_s, int act_shift, uint32_t* wincnt, hipStream_t s);
 // Copies fully sorted buffers (fallback path) into the prepared arrays.
 hipError_t launch_unbias_copy(SortBufs in, int64_t n, const RangeInfo* info, int32_t* case_s,
                               int32_t* act_s, int64_t* ts_s, int act_shift, hipStream_t s);
@@ -89,8 +90,9 @@ hipError_t launch_copy_log(const int32_t* c, const int32_t* a, const int64_t* t,
 // ---- case table (cases.hip) ----
 constexpr int kCaseTile = 4096;
 inline int64_t case_blocks(int64_t n) { return (n + kCaseTile - 1) / kCaseTile; }
+// wincnt (may be NULL): cases starting in each kSegWindow window, from k_segsort.
 hipError_t launch_case_table(const int32_t* case_s, int64_t n, uint32_t* blockcnt, int64_t* case_off,
-                             int32_t* case_code, int64_t* n_cases, hipStream_t s);
+                             int32_t* case_code, int64_t* n_cases, const uint32_t* wincnt, hipStream_t s);
 
 // ---- DFG aggregation (dfg.hip) ----
 constexpr int kCellsPerTable = 4096;     // one LDS table of cells

@@ -153,7 +153,8 @@ constexpr uint64_t kOffMask = (1ull << 52) - 1;
 __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeInfo* info,
                                                  int32_t* __restrict__ case_s,
                                                  int32_t* __restrict__ act_s,
-                                                 int64_t* __restrict__ ts_s, int act_shift) {
+                                                 int64_t* __restrict__ ts_s, int act_shift,
+                                                 uint32_t* __restrict__ wincnt) {
     __shared__ int64_t lts[kSegCap];     // timestamps; on the fast path the sorted cross keys
     __shared__ uint16_t lact[kSegCap];
     __shared__ uint16_t lidx[kSegCap];   // field-by-field path: staging position of the event now at i
@@ -161,6 +162,7 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
     __shared__ uint16_t lce[kSegCap];    // case end, stored at the case start
     __shared__ int64_t red[2 * kSW];
     __shared__ int32_t wred[kSW];
+    __shared__ int32_t wst[kSW];
 
     const uint32_t* __restrict__ key = in.key;
     const uint32_t kmask = act_shift > 0 ? ((1u << act_shift) - 1u) : 0xFFFFFFFFu;
@@ -194,7 +196,10 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
         }
     }
     block_min2_i64(s, e, red);
-    if (s == INT64_MAX) return;   // a long case covers the whole window (block-uniform)
+    if (s == INT64_MAX) {   // a long case covers the whole window (block-uniform): no case starts here
+        if (threadIdx.x == 0) wincnt[blockIdx.x] = 0;
+        return;
+    }
     for (int64_t base = w0 + kPre * kSB; e == INT64_MAX && base <= n && base - s <= kSegCap; base += kSB) {
         const int64_t p = base + threadIdx.x;
         int64_t c = INT64_MAX;
@@ -240,17 +245,27 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
     //    (blocked layout: thread t owns items kSI*t .. kSI*t + kSI - 1)
     {
         int32_t loc[kSI];
-        int32_t m = 0;
+        int32_t m = 0, nst = 0;
 #pragma unroll
         for (int q = 0; q < kSI; ++q) {
             const int i = threadIdx.x * kSI + q;
-            if (i < R) m = (int32_t)lcs[i] > m ? (int32_t)lcs[i] : m;
+            if (i < R) {
+                m = (int32_t)lcs[i] > m ? (int32_t)lcs[i] : m;
+                nst += (int32_t)lcs[i] == i;   // a case starts at i
+            }
             loc[q] = m;
         }
         const int w = threadIdx.x / kWave;
         const int32_t inc = wave_incl_max_i32(m);
+        nst = wave_sum(nst);
         if (lane() == kWave - 1) wred[w] = inc;
+        if (lane() == 0) wst[w] = nst;
         __syncthreads();
+        if (threadIdx.x == 0) {   // the region's cases are the cases starting in the window
+            int32_t t = 0;
+            for (int k = 0; k < kSW; ++k) t += wst[k];
+            wincnt[blockIdx.x] = (uint32_t)t;
+        }
         int32_t before = 0;
         for (int i = 0; i < w; ++i) before = wred[i] > before ? wred[i] : before;
         int32_t excl = __shfl_up(inc, 1);
@@ -447,9 +462,10 @@ static unsigned copy_grid(int64_t n) {
 }
 
 hipError_t launch_segsort(SortBufs in, int64_t n, RangeInfo* info, int32_t* case_s, int32_t* act_s,
-                          int64_t* ts_s, int act_shift, hipStream_t s) {
+                          int64_t* ts_s, int act_shift, uint32_t* wincnt, hipStream_t s) {
     ProfScope p(P_SEGSORT, s);
-    if (n > 0) k_segsort<<<(unsigned)segsort_blocks(n), kSB, 0, s>>>(in, n, info, case_s, act_s, ts_s, act_shift);
+    if (n > 0)
+        k_segsort<<<(unsigned)segsort_blocks(n), kSB, 0, s>>>(in, n, info, case_s, act_s, ts_s, act_shift, wincnt);
     return hipGetLastError();
 }
 

@@ -101,47 +101,70 @@ __device__ __forceinline__ int seg_of(int64_t vstart, int64_t p) {
 
 // Sequence hash of every case: a sum over positions of mix(position, activity)
 // (order-sensitive, computable in any order), mixed with the length.  A wave
-// takes 64 consecutive cases and walks their events coalesced.
+// takes 64 consecutive cases; their events are read in 1024-event windows
+// with coalesced 16-byte loads into LDS, then each lane sums 16 consecutive
+// events, adding a case's partial sum to its LDS total when it leaves the case
+// (so a case costs one or two LDS additions, not one per event).
+constexpr int kHashWin = 1024;
 __global__ __launch_bounds__(kBlk) void k_var_hash(const int32_t* __restrict__ act_s,
                                                    const int64_t* __restrict__ case_off, VarWs w,
-                                                   uint64_t mask) {
+                                                   uint64_t mask, int64_t n) {
     __shared__ unsigned long long hsum[kBlk / kWave][kWave];
+    __shared__ int64_t sst[kBlk / kWave][kWave + 1];
+    __shared__ int32_t sact[kBlk / kWave][kHashWin];
     const int64_t C = w.scal[0];
     const int wl = threadIdx.x / kWave;
     const int64_t wv = ((int64_t)blockIdx.x * kBlk + threadIdx.x) / kWave;
     const int64_t nw = (int64_t)gridDim.x * kBlk / kWave;
+    const bool aligned = (reinterpret_cast<uintptr_t>(act_s) & 15) == 0;
+    constexpr int kPer = kHashWin / kWave;   // 16 events per lane and window
     for (int64_t c0 = wv * kWave; c0 < C; c0 += nw * kWave) {
         const int64_t c = c0 + lane();
         const bool has = c < C;
         const int64_t st = has ? case_off[c] : INT64_MAX;
         const int64_t en = has ? case_off[c + 1] : 0;
         hsum[wl][lane()] = 0;
+        sst[wl][lane()] = st;
+        if (lane() == 0) sst[wl][kWave] = INT64_MAX;
         const int last = (C - 1 - c0) < (kWave - 1) ? (int)(C - 1 - c0) : (kWave - 1);
         const int64_t base = __shfl(st, 0);
         const int64_t end = __shfl(en, last);
-        // wave-uniform trip count: every lane takes part in the shuffles
-        // wave-uniform trip count: every lane takes part in the shuffles;
-        // four 64-event steps per trip, their loads issued first
-        constexpr int kU = 4;
-        for (int64_t p0 = base; p0 < end; p0 += kU * kWave) {
-            int32_t av[kU];
+        for (int64_t w0 = base & ~(int64_t)3; w0 < end; w0 += kHashWin) {   // wave-uniform
+            // stage the window's activities (positions outside [base, end) are not used)
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const int64_t p = p0 + u * kWave + lane();
-                av[u] = p < end ? act_s[p] : 0;
-            }
+            for (int k = 0; k < kHashWin / (4 * kWave); ++k) {
+                const int o = 4 * (k * kWave + lane());
+                const int64_t p = w0 + o;
+                if (aligned && p + 3 < n) {
+                    const int4 v = *reinterpret_cast<const int4*>(act_s + p);
+                    sact[wl][o] = v.x;
+                    sact[wl][o + 1] = v.y;
+                    sact[wl][o + 2] = v.z;
+                    sact[wl][o + 3] = v.w;
+                } else {
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const int64_t p = p0 + u * kWave + lane();
-                const int m = seg_of(st, p);
-                const int64_t s_m = __shfl(st, m);
-                if (p < end) {
-                    const uint64_t pos = (uint64_t)(p - s_m);
-                    const uint64_t term =
-                        mix64((pos << 13) + (uint64_t)(uint32_t)av[u] + 0x632be59bd9b4e019ull);
-                    atomicAdd(&hsum[wl][m], (unsigned long long)term);
+                    for (int j = 0; j < 4; ++j) sact[wl][o + j] = p + j < n ? act_s[p + j] : 0;
                 }
             }
+            // lane-contiguous sums
+            const int64_t q0 = w0 + (int64_t)kPer * lane();
+            const int64_t lo = q0 > base ? q0 : base;
+            const int64_t hi = (q0 + kPer) < end ? (q0 + kPer) : end;
+            int m = seg_of(st, lo < end ? lo : end - 1);   // all lanes active
+            int64_t s_m = sst[wl][m], nxt = sst[wl][m + 1];
+            uint64_t acc = 0;
+            for (int64_t p = lo; p < hi; ++p) {
+                if (p >= nxt) {   // cases are non-empty: one step at a time
+                    atomicAdd(&hsum[wl][m], (unsigned long long)acc);
+                    acc = 0;
+                    ++m;
+                    s_m = nxt;
+                    nxt = sst[wl][m + 1];
+                }
+                acc += mix64(((uint64_t)(p - s_m) << 13) + (uint64_t)(uint32_t)sact[wl][p - w0] +
+                             0x632be59bd9b4e019ull);
+            }
+            if (lo < hi) atomicAdd(&hsum[wl][m], (unsigned long long)acc);
         }
         if (has) {
             uint64_t h = mix64((uint64_t)hsum[wl][lane()] ^ mix64((uint64_t)(en - st) + 0x9e3779b97f4a7c15ull));
@@ -345,7 +368,7 @@ hipError_t launch_variants(const int32_t* act_s, const int64_t* case_off, const 
     k_var_init<<<1, 1, 0, s>>>(w, n_cases);
     {
         ProfScope p(P_VAR_HASH, s);
-        k_var_hash<<<kGrid, kBlk, 0, s>>>(act_s, case_off, w, mask);
+        k_var_hash<<<kGrid, kBlk, 0, s>>>(act_s, case_off, w, mask, n);
     }
     bool in2;
     {
