@@ -210,7 +210,8 @@ def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int, autot
                                                        "agg_blocks": tune.agg_blocks or 512}}
 
 
-def bench_serving(logs: dict, preps: dict, seconds: float, rate: float) -> dict:
+def bench_serving(logs: dict, preps: dict, seconds: float, rate: float, workers: int = 4,
+                  batch_work: int = 20_000_000) -> dict:
     """Open-loop Poisson mix of DFG / variants / filter queries on resident logs."""
     import copy
 
@@ -225,11 +226,12 @@ def bench_serving(logs: dict, preps: dict, seconds: float, rate: float) -> dict:
     free, _total = __import__("torch").cuda.mem_get_info()
     budget = int(free * 0.5)
     # warm the executor's workspaces
-    serve.Scheduler(ex, budget, max_batch=64, workers=2).run(copy.deepcopy(reqs[:16]))
-    sch = serve.Scheduler(ex, budget, max_batch=64, workers=2)
+    serve.Scheduler(ex, budget, max_batch=64, workers=workers).run(copy.deepcopy(reqs[:16]))
+    sch = serve.Scheduler(ex, budget, max_batch=64, workers=workers, max_batch_work=batch_work)
     res = sch.run(copy.deepcopy(reqs), progress=log_progress)
     st = serve.latency_stats(res)
     st.update(offered_qps=rate, seconds=seconds, n_requests=len(reqs), batches=len(sch.batches),
+              workers=workers, max_batch_work=batch_work,
               variants_answer=f"variant count + first {ex.variants_top} variants")
     log_progress("serving: one request per launch")
     base = serve.Scheduler(ex, budget, max_batch=1, workers=1)
@@ -323,6 +325,9 @@ def main() -> int:
     ap.add_argument("--tune-cache", default=None, help="autotune cache file (default: the package's)")
     ap.add_argument("--serve-seconds", type=float, default=8.0, help="serving run length (0: skip)")
     ap.add_argument("--serve-qps", type=float, default=200.0)
+    ap.add_argument("--serve-workers", type=int, default=4, help="batches in flight (HIP streams)")
+    ap.add_argument("--serve-batch-work", type=int, default=20_000_000,
+                    help="events a batch may scan before it closes (a larger request runs alone)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -427,7 +432,8 @@ def main() -> int:
         log_progress(f"serving: {args.serve_seconds} s at {args.serve_qps} queries/s")
         out["serving"] = bench_serving({"dfg-perf-10M": log2, args.workload: log},
                                        {"dfg-perf-10M": prep2, args.workload: prep},
-                                       args.serve_seconds, args.serve_qps)
+                                       args.serve_seconds, args.serve_qps, args.serve_workers,
+                                       args.serve_batch_work)
     if not args.no_cpu_baseline:
         log_progress("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(log, args.cpu_sample_events)

@@ -12,6 +12,8 @@ Scheduling (host side, independent of the executor):
     formed from the head of the FIFO queue while the estimates fit in the
     budget left by the batches in flight; the head never gets skipped, so no
     request starves; a request larger than the whole budget is rejected;
+  - a batch also stops at a work cap (events to scan), so a large request
+    runs alone instead of holding small ones back;
   - continuous batching: `workers` persistent worker threads, each with its
     own HIP stream, run up to `workers` batches at once, so requests that
     arrive while a batch runs join the next batch and its work overlaps on
@@ -48,6 +50,7 @@ class Request:
     mask: np.ndarray          # uint64 words, bit a selects activity a
     arrival: float            # scheduled arrival, seconds on the server clock
     est_bytes: int = 0
+    est_work: int = 0
     dispatched: float = float("nan")
     done: float = float("nan")
     result: dict | None = None
@@ -62,11 +65,15 @@ class Scheduler:
     """FIFO admission by memory estimate, up to `workers` batches in flight."""
 
     def __init__(self, executor, mem_budget: int, max_batch: int = 256, workers: int = 2,
-                 clock: Callable[[], float] = time.monotonic):
+                 clock: Callable[[], float] = time.monotonic, max_batch_work: int | None = None):
         self.ex = executor
         self.budget = int(mem_budget)
         self.max_batch = int(max_batch)
         self.workers = int(workers)
+        # work cap of one batch (the executor's work units, e.g. events scanned);
+        # a request above it runs in a batch of its own, so small requests do not
+        # wait behind it
+        self.max_batch_work = max_batch_work
         self.clock = clock
         self._lock = threading.Condition()
         self._in_flight_bytes = 0
@@ -78,11 +85,16 @@ class Scheduler:
         """Head-of-queue batch that fits the memory left; removes it from `queue`."""
         batch: list[Request] = []
         room = self.budget - self._in_flight_bytes
+        work = 0
+        cap = self.max_batch_work
         while queue and len(batch) < self.max_batch:
             r = queue[0]
             if r.est_bytes > room:
                 break
+            if cap is not None and batch and work + r.est_work > cap:
+                break
             room -= r.est_bytes
+            work += r.est_work
             batch.append(queue.pop(0))
         return batch
 
@@ -96,6 +108,7 @@ class Scheduler:
         pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
         for r in pending:
             r.est_bytes = int(self.ex.estimate(r))
+            r.est_work = int(self.ex.work(r)) if hasattr(self.ex, "work") else 0
         t0 = self.clock() if t0 is None else t0
         waiting: list[Request] = []
         done: list[Request] = []
@@ -262,6 +275,12 @@ class GpuExecutor:
         a = int(np.searchsorted(lg["codes"], r.case_lo, side="left"))
         b = int(np.searchsorted(lg["codes"], r.case_hi, side="left"))
         return int(lg["off"][b] - lg["off"][a]) if b > a else 0
+
+    def work(self, r: Request) -> int:
+        """Work estimate: events of the view's case slice (variants cost about
+        four passes over them)."""
+        S = self.slice_events(r)
+        return 4 * S if r.kind == "variants" else S
 
     def estimate(self, r: Request) -> int:
         """Workspace estimate: records and cells of a batched view, or filtered log + variants."""

@@ -91,3 +91,24 @@ def test_executor_failure_is_reported_per_request():
     out = sch.run(reqs(8))
     assert out[5].error and "executor failure" in out[5].error
     assert all(r.error is None for r in out if r.rid != 5)
+
+
+def test_work_cap_closes_batches_and_large_requests_run_alone():
+    class WorkExecutor(FakeExecutor):
+        def work(self, r):
+            return 1000 if r.rid % 10 == 3 else 10
+
+    ex = WorkExecutor(est=lambda r: 1, service_s=0.002)
+    sch = Scheduler(ex, mem_budget=10**6, max_batch=64, workers=1, max_batch_work=100)
+    out = sch.run(reqs(40, gap=0.0))   # all arrive at once
+    assert all(r.error is None for r in out)
+    for b in sch.batches:
+        big = [rid for rid in b if rid % 10 == 3]
+        if big:
+            # a request above the cap forms a batch only when it heads the queue, and alone
+            assert b == big
+        else:
+            assert 10 * len(b) <= 100
+    # FIFO order is kept
+    flat = [rid for b in sch.batches for rid in b]
+    assert flat == sorted(flat)
