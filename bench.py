@@ -332,8 +332,8 @@ def main() -> int:
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the design for sharding by case is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (it would shard the log "
+              "by case, each GPU running the whole path on its cases).", file=sys.stderr)
         return 2
 
     import torch
