@@ -41,7 +41,9 @@ def _load():
         L.orc_variants.argtypes = [i64, P, P, P, i32, P, P, P, P, P, P, P, P, P]
         L.orc_view.argtypes = [i64, P, P, P, i32, i32, i32, i64, i64, P,
                                P, P, P, P, P, P, P, P, P, P, P]
-        for f in (L.orc_prepare, L.orc_dfg, L.orc_variants, L.orc_view):
+        L.orc_cases.argtypes = [i64, P, P, P, i32, P, P, P, P]
+        L.orc_filter_cases.argtypes = [i64, P, P, P, i32, i64, i64, i64, i64, P, P, i32, P, P, P, P, P]
+        for f in (L.orc_prepare, L.orc_dfg, L.orc_variants, L.orc_view, L.orc_cases, L.orc_filter_cases):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -173,3 +175,43 @@ def view(case, act, ts, A: int, case_lo: int, case_hi: int, t_lo: int, t_hi: int
     o["overflow"] = int(ov[0])
     o["n_events"] = int(ne[0])
     return o
+
+
+def cases(case, act, ts, A: int) -> dict:
+    """The cases dataframe: per case (ascending code) its events and throughput time."""
+    case, act, ts = _cols(case, act, ts)
+    n = case.shape[0]
+    m = max(n, 1)
+    out = dict(case_code=np.empty(m, np.int32), n_events=np.empty(m, np.int64),
+               throughput=np.empty(m, np.int64))
+    C = np.zeros(1, np.int64)
+    rc = _load().orc_cases(n, _p(case), _p(act), _p(ts), A, _p(out["case_code"]), _p(out["n_events"]),
+                           _p(out["throughput"]), _p(C))
+    if rc:
+        raise OracleError(rc)
+    c = int(C[0])
+    return {k: v[:c] for k, v in out.items()} | {"n_cases": c}
+
+
+I64_MIN, I64_MAX = -(1 << 63), (1 << 63) - 1
+
+
+def filter_cases(case, act, ts, A: int, min_events: int = 0, max_events: int = I64_MAX,
+                 min_thr: int = I64_MIN, max_thr: int = I64_MAX, act_mask=None, path_mask=None,
+                 path_keep: bool = True) -> dict:
+    """Events (in order) of the cases passing the case-level filters."""
+    case, act, ts = _cols(case, act, ts)
+    n = case.shape[0]
+    m = max(n, 1)
+    out = dict(case_s=np.empty(m, np.int32), act_s=np.empty(m, np.int32), ts_s=np.empty(m, np.int64))
+    no, nc = np.zeros(1, np.int64), np.zeros(1, np.int64)
+    am = None if act_mask is None else np.ascontiguousarray(act_mask, dtype=np.uint64)
+    pm = None if path_mask is None else np.ascontiguousarray(path_mask, dtype=np.uint64)
+    rc = _load().orc_filter_cases(n, _p(case), _p(act), _p(ts), A, int(min_events), int(max_events),
+                                  int(min_thr), int(max_thr), None if am is None else _p(am),
+                                  None if pm is None else _p(pm), 1 if path_keep else 0,
+                                  _p(out["case_s"]), _p(out["act_s"]), _p(out["ts_s"]), _p(no), _p(nc))
+    if rc:
+        raise OracleError(rc)
+    k = int(no[0])
+    return {key: v[:k] for key, v in out.items()} | {"n_events": k, "n_cases": int(nc[0])}

@@ -26,6 +26,8 @@
  *              timestamp filter on events and attribute (activity) filter,
  *              composed as a conjunction; the DFG is re-discovered on the
  *              retained events.
+ *   cases      Sec. 3 cases dataframe (events and throughput time per case)
+ *              and the case-level filters on it, with paths filtering.
  *
  * Readings where the paper is silent (each is listed in the design notes):
  *   - the row tie-break is the 0-based row index in the caller's arrays;
@@ -37,7 +39,11 @@
  *   - variants are exact sequence classes, numbered by (count desc,
  *     representative asc) where the representative is the smallest case code;
  *   - a view keeps event i iff case_lo <= c_i < case_hi, t_lo <= t_i <= t_hi
- *     and the activity bit of a_i is set in the mask.
+ *     and the activity bit of a_i is set in the mask;
+ *   - throughput time = timestamp of the case's last event minus its first;
+ *   - paths filtering keeps (or drops) the whole cases that contain a
+ *     directly-follows pair of the given set; the case-level predicates
+ *     combine as a conjunction.
  *
  * Status codes: 0 ok, -1 invalid argument, -2 activity out of [0, A).
  */
@@ -363,5 +369,109 @@ int orc_view(int64_t n, const int32_t *case_id, const int32_t *act, const int64_
     free(rc_);
     free(ra);
     free(rt);
+    return r;
+}
+
+/* ---- cases dataframe and case-level filters -------------------------- */
+
+/*
+ * orc_cases: the cases dataframe (Sec. 3: third formatting step and the
+ * cases-dataframe module).  For the j-th case in ascending case order: its
+ * code, its number of events, and its throughput time, the timestamp of its
+ * last event minus that of its first in the (case, timestamp, row) order
+ * (computed modulo 2^64 and read as int64, like every gap here).  Any output
+ * may be NULL.
+ */
+int orc_cases(int64_t n, const int32_t *case_id, const int32_t *act, const int64_t *ts, int32_t A,
+              int32_t *case_code, int64_t *n_events, int64_t *throughput, int64_t *n_cases)
+{
+    if (n < 0 || A < 1) return ORC_E_INVALID;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    int64_t *ts_s = (int64_t *)malloc(nn * sizeof(int64_t));
+    int64_t *off = (int64_t *)malloc((nn + 1) * sizeof(int64_t));
+    int32_t *code = (int32_t *)malloc(nn * sizeof(int32_t));
+    int64_t C = 0;
+    int r = orc_prepare(n, case_id, act, ts, A, NULL, NULL, NULL, ts_s, off, code, &C);
+    if (r == ORC_OK) {
+        for (int64_t j = 0; j < C; j++) {
+            int64_t first = off[j], last = off[j + 1] - 1;
+            if (case_code) case_code[j] = code[j];
+            if (n_events) n_events[j] = off[j + 1] - off[j];
+            if (throughput) throughput[j] = (int64_t)((uint64_t)ts_s[last] - (uint64_t)ts_s[first]);
+        }
+        if (n_cases) *n_cases = C;
+    }
+    free(ts_s);
+    free(off);
+    free(code);
+    return r;
+}
+
+/*
+ * orc_filter_cases: case-level filtering (Sec. 3: aggregations / filtering at
+ * the case level; the cases-dataframe module's filters on the number of
+ * events and the throughput time; the DFG module's paths filtering).  A case
+ * is kept iff every predicate holds:
+ *   min_events <= its number of events <= max_events;
+ *   min_thr <= its throughput time <= max_thr;
+ *   act_mask (ceil(A/64) words, may be NULL): one of its events has an
+ *     activity of the set;
+ *   path_mask (ceil(A*A/64) words, bit src*A+dst, may be NULL): one of its
+ *     directly-follows pairs is in the set (path_keep != 0), or none is
+ *     (path_keep == 0).
+ * The kept cases' events are written in (case, timestamp, row) order; n_out
+ * receives their number and n_cases_out the number of kept cases.
+ */
+int orc_filter_cases(int64_t n, const int32_t *case_id, const int32_t *act, const int64_t *ts, int32_t A,
+                     int64_t min_events, int64_t max_events, int64_t min_thr, int64_t max_thr,
+                     const uint64_t *act_mask, const uint64_t *path_mask, int32_t path_keep,
+                     int32_t *case_out, int32_t *act_out, int64_t *ts_out, int64_t *n_out,
+                     int64_t *n_cases_out)
+{
+    if (n < 0 || A < 1) return ORC_E_INVALID;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    int32_t *case_s = (int32_t *)malloc(nn * sizeof(int32_t));
+    int32_t *act_s = (int32_t *)malloc(nn * sizeof(int32_t));
+    int64_t *ts_s = (int64_t *)malloc(nn * sizeof(int64_t));
+    int64_t *off = (int64_t *)malloc((nn + 1) * sizeof(int64_t));
+    int64_t C = 0;
+    int r = orc_prepare(n, case_id, act, ts, A, NULL, case_s, act_s, ts_s, off, NULL, &C);
+    int64_t m = 0, kc = 0;
+    if (r == ORC_OK) {
+        for (int64_t j = 0; j < C; j++) {
+            int64_t first = off[j], end = off[j + 1];
+            int64_t events = end - first;
+            int64_t thr = (int64_t)((uint64_t)ts_s[end - 1] - (uint64_t)ts_s[first]);
+            int keep = events >= min_events && events <= max_events && thr >= min_thr && thr <= max_thr;
+            if (keep && act_mask) {
+                int has = 0;
+                for (int64_t k = first; k < end; k++)
+                    if ((act_mask[act_s[k] / 64] >> (act_s[k] % 64)) & 1u) has = 1;
+                keep = has;
+            }
+            if (keep && path_mask) {
+                int has = 0;
+                for (int64_t k = first + 1; k < end; k++) {
+                    int64_t cell = (int64_t)act_s[k - 1] * A + act_s[k];
+                    if ((path_mask[cell / 64] >> (cell % 64)) & 1u) has = 1;
+                }
+                keep = path_keep ? has : !has;
+            }
+            if (!keep) continue;
+            for (int64_t k = first; k < end; k++) {
+                if (case_out) case_out[m] = case_s[k];
+                if (act_out) act_out[m] = act_s[k];
+                if (ts_out) ts_out[m] = ts_s[k];
+                m++;
+            }
+            kc++;
+        }
+    }
+    if (n_out) *n_out = m;
+    if (n_cases_out) *n_cases_out = kc;
+    free(case_s);
+    free(act_s);
+    free(ts_s);
+    free(off);
     return r;
 }

@@ -120,3 +120,53 @@ def view(c, a, t, A, case_lo, case_hi, t_lo, t_hi, members_of_subset):
     out = dfg([c[i] for i in keep], [a[i] for i in keep], [t[i] for i in keep], A)
     out["n_events"] = len(keep)
     return out
+
+
+def ordered_members(c, t, members):
+    """Events of one case, taking the earliest remaining event each time."""
+    rest = list(members)
+    out = []
+    while rest:
+        first = rest[0]
+        for k in rest[1:]:
+            if precedes(c, t, k, first):
+                first = k
+        out.append(first)
+        rest.remove(first)
+    return out
+
+
+def cases(c, a, t):
+    """Cases dataframe by definition: for each distinct case (ascending), its
+    number of events and the time from its earliest to its latest event."""
+    groups = _by_case(c)
+    codes = sorted(groups)
+    out = {"case_code": codes, "n_events": [], "throughput": []}
+    for code in codes:
+        ev = ordered_members(c, t, groups[code])
+        out["n_events"].append(len(ev))
+        out["throughput"].append(to_i64(t[ev[-1]] - t[ev[0]]))
+    return out
+
+
+def filter_cases(c, a, t, min_events, max_events, min_thr, max_thr, act_set=None, path_set=None,
+                 path_keep=True):
+    """Events (case, act, ts) of the kept cases, cases ascending, events in order;
+    a case's paths are the (a_i, a_j) of its directly-follows pairs (i, j)."""
+    groups = _by_case(c)
+    pairs = directly_follows_pairs(c, t)
+    kept_events = []
+    n_cases = 0
+    for code in sorted(groups):
+        ev = ordered_members(c, t, groups[code])
+        thr = to_i64(t[ev[-1]] - t[ev[0]])
+        keep = min_events <= len(ev) <= max_events and min_thr <= thr <= max_thr
+        if keep and act_set is not None:
+            keep = any(a[i] in act_set for i in ev)
+        if keep and path_set is not None:
+            has = any((a[i], a[j]) in path_set for (i, j) in pairs if c[i] == code)
+            keep = has if path_keep else not has
+        if keep:
+            n_cases += 1
+            kept_events += [(c[i], a[i], t[i]) for i in ev]
+    return kept_events, n_cases

@@ -449,3 +449,85 @@ def test_generator_markov_chain_frequencies():
         q = pr / A
         np.add.at(q, al, (1 - pr) / A)
         assert np.allclose(q, P[r], atol=1e-12)
+
+
+# ---- cases dataframe and case-level filters --------------------------------
+
+def _mask(bits, nbits):
+    m = np.zeros((nbits + 63) // 64, np.uint64)
+    for b in bits:
+        m[b // 64] |= np.uint64(1) << np.uint64(b % 64)
+    return m
+
+
+def test_cases_golden():
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_road_fines.json")))
+    r, A = g["rows"], g["A"]
+    o = oracle.cases(r["case"], r["act"], r["ts"], A)
+    for k, v in g["cases"]["expected"].items():
+        assert o[k].tolist() == v, k
+    for f in g["cases"]["filters"]:
+        kw = {k: f[k] for k in ("min_events", "max_events", "min_thr", "max_thr") if k in f}
+        if "activities" in f:
+            kw["act_mask"] = _mask(f["activities"], A)
+        if "paths" in f:
+            kw["path_mask"] = _mask([x * A + y for x, y in f["paths"]], A * A)
+            kw["path_keep"] = f["path_keep"]
+        o = oracle.filter_cases(r["case"], r["act"], r["ts"], A, **kw)
+        got = list(zip(o["case_s"].tolist(), o["act_s"].tolist(), o["ts_s"].tolist()))
+        assert got == [tuple(e) for e in f["events"]], f["name"]
+        assert o["n_cases"] == len(f["kept_cases"]), f["name"]
+        assert sorted(set(o["case_s"].tolist())) == f["kept_cases"], f["name"]
+
+
+@settings(max_examples=200, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(tiny_logs())
+def test_cases_match_bruteforce(log):
+    case, act, ts, A = log
+    o = oracle.cases(case, act, ts, A)
+    b = bf.cases(case, act, ts)
+    assert o["case_code"].tolist() == b["case_code"]
+    assert o["n_events"].tolist() == b["n_events"]
+    assert o["throughput"].tolist() == b["throughput"]
+
+
+@settings(max_examples=250, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(tiny_logs(), st.data())
+def test_filter_cases_match_bruteforce(log, data):
+    case, act, ts, A = log
+    lo_e = data.draw(st.integers(0, 4))
+    hi_e = data.draw(st.integers(lo_e, 30))
+    lo_t = data.draw(st.sampled_from([oracle.I64_MIN, -5, 0, 1, 2**40]))
+    hi_t = data.draw(st.sampled_from([oracle.I64_MAX, 0, 3, 2**61]))
+    acts = data.draw(st.none() | st.sets(st.integers(0, A - 1)))
+    paths = data.draw(st.none() | st.sets(st.tuples(st.integers(0, A - 1), st.integers(0, A - 1))))
+    keep = data.draw(st.booleans())
+    kw = dict(min_events=lo_e, max_events=hi_e, min_thr=lo_t, max_thr=hi_t, path_keep=keep)
+    if acts is not None:
+        kw["act_mask"] = _mask(acts, A)
+    if paths is not None:
+        kw["path_mask"] = _mask([x * A + y for x, y in paths], A * A)
+    o = oracle.filter_cases(case, act, ts, A, **kw)
+    ev, nc = bf.filter_cases(case, act, ts, lo_e, hi_e, lo_t, hi_t, acts, paths, keep)
+    got = list(zip(o["case_s"].tolist(), o["act_s"].tolist(), o["ts_s"].tolist()))
+    assert got == ev
+    assert o["n_cases"] == nc and o["n_events"] == len(ev)
+
+
+def test_cases_invariants_on_workload():
+    log = synth.config_log(2, 0.01)
+    o = oracle.cases(log.case, log.act, log.ts, log.n_activities)
+    assert o["n_events"].sum() == log.n_events
+    assert (o["throughput"] >= 0).all()                    # timestamps ordered inside a case
+    d = oracle.dfg(log.case, log.act, log.ts, log.n_activities)
+    assert o["n_cases"] == d["n_cases"]
+    # the whole log passes an unrestricted filter; a path set of every cell keeps the cases
+    # with at least two events, and its complement keeps the single-event ones
+    A = log.n_activities
+    allp = _mask(range(A * A), A * A)
+    f = oracle.filter_cases(log.case, log.act, log.ts, A)
+    assert f["n_events"] == log.n_events and f["n_cases"] == o["n_cases"]
+    k = oracle.filter_cases(log.case, log.act, log.ts, A, path_mask=allp, path_keep=True)
+    d2 = oracle.filter_cases(log.case, log.act, log.ts, A, path_mask=allp, path_keep=False)
+    assert k["n_cases"] == int((o["n_events"] >= 2).sum()) and d2["n_cases"] == int((o["n_events"] == 1).sum())
+    assert k["n_events"] + d2["n_events"] == log.n_events
