@@ -302,6 +302,53 @@ size_t pm4g_filter_workspace_bytes(int64_t n_events);
 int pm4g_filter_view(const pm4g_prepared *log, const pm4g_view *view, const uint64_t *act_mask,
                      const pm4g_prepared *out, void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * Cases dataframe (Sec. 3: one row per case with its number of events and its
+ * throughput time, the cases-dataframe module).  For the j-th case of a
+ * prepared log (its case-table order: ascending case id), n_events_out[j] is
+ * its number of events and throughput_out[j] the timestamp of its last event
+ * minus that of its first (computed modulo 2^64, read as int64).  Both device
+ * arrays (either may be NULL) hold at least log->n_events entries (an upper
+ * bound of the case count, which stays on the device).  No workspace; does
+ * not synchronise.
+ */
+int pm4g_cases(const pm4g_prepared *log, int64_t *n_events_out, int64_t *throughput_out, void *stream);
+
+/*
+ * Case-level filter (Sec. 3: filtering at the case level on the number of
+ * events and the throughput time; cases containing an activity; the DFG
+ * module's paths filtering).  A case is kept iff every predicate holds:
+ *   min_events <= its events <= max_events (inclusive);
+ *   min_throughput <= its throughput time <= max_throughput (inclusive);
+ *   act_mask (device, ceil(A/64) words; NULL: no predicate): one of its
+ *     events has an activity whose bit is set;
+ *   path_mask (device, ceil(A*A/64) words, bit src*A + dst; NULL: no
+ *     predicate): one of its directly-follows pairs has its bit set
+ *     (path_keep = 1), or none has (path_keep = 0).
+ * The struct itself is read on the host.
+ */
+typedef struct {
+    int64_t min_events;
+    int64_t max_events;
+    int64_t min_throughput;
+    int64_t max_throughput;
+    const uint64_t *act_mask;
+    const uint64_t *path_mask;
+    int32_t path_keep;
+    int32_t reserved;
+} pm4g_case_filter;
+
+/*
+ * The events of the kept cases, as a prepared log of their own (order and
+ * case table as in the input; whole cases).  out->n_events is the capacity
+ * of out's arrays; if the kept events exceed it, nothing is written and
+ * out->status is PM4G_E_CAPACITY.  The kept count is
+ * out->case_off[*out->n_cases], on the device.  Does not synchronise.
+ */
+size_t pm4g_filter_cases_workspace_bytes(int64_t n_events);
+int pm4g_filter_cases(const pm4g_prepared *log, const pm4g_case_filter *filter, const pm4g_prepared *out,
+                      void *ws, size_t ws_bytes, void *stream);
+
 /* Text for a status code (static storage). */
 const char *pm4g_status_string(int code);
 

@@ -367,6 +367,40 @@ int pm4g_filter_view(const pm4g_prepared* log, const pm4g_view* view, const uint
     return PM4G_OK;
 }
 
+int pm4g_cases(const pm4g_prepared* log, int64_t* n_events_out, int64_t* throughput_out, void* stream) {
+    if (int rc = check_prepared(log, true)) return rc;
+    PM4G_HIP(launch_cases_df(log, n_events_out, throughput_out, (hipStream_t)stream));
+    return PM4G_OK;
+}
+
+size_t pm4g_filter_cases_workspace_bytes(int64_t n_events) {
+    if (n_events < 0 || n_events > kMaxEvents) return 0;
+    Bump b(nullptr);
+    case_filter_ws_layout(b, n_events);
+    return b.off + 256;
+}
+
+int pm4g_filter_cases(const pm4g_prepared* log, const pm4g_case_filter* filter, const pm4g_prepared* out,
+                      void* ws, size_t ws_size, void* stream) {
+    if (int rc = check_prepared(log, true)) return rc;
+    PM4G_CHECK(filter != nullptr, "filter is NULL");
+    PM4G_CHECK(filter->path_keep == 0 || filter->path_keep == 1, "path_keep must be 0 or 1");
+    PM4G_CHECK(out && out->case_off && out->n_cases && out->status &&
+                   (log->n_events == 0 || (out->case_s && out->act_s && out->ts_s && out->case_code)),
+               "a filtered-log output array is NULL");
+    PM4G_CHECK(out->n_events >= 0 && out->n_activities == log->n_activities,
+               "the filtered log needs a capacity >= 0 and the same n_activities");
+    const size_t need = pm4g_filter_cases_workspace_bytes(log->n_events);
+    if (ws_size < need || !ws) {
+        set_err("workspace of %zu bytes, %zu needed", ws_size, need);
+        return PM4G_E_WORKSPACE;
+    }
+    Bump bp(ws);
+    CaseFilterWs w = case_filter_ws_layout(bp, log->n_events);
+    PM4G_HIP(launch_filter_cases(log, filter, out, w, (hipStream_t)stream));
+    return PM4G_OK;
+}
+
 int pm4g_dfg_batched(const pm4g_prepared* log, const pm4g_view* views, const uint64_t* act_masks,
                      int32_t n_views, const pm4g_batched_out* out, const pm4g_batched_tuning* tuning,
                      void* ws, size_t ws_size, void* stream) {

@@ -268,6 +268,23 @@ FilterWs filter_ws_layout(Bump& b, int64_t n);
 hipError_t launch_filter_view(const pm4g_prepared* p, const pm4g_view* view, const uint64_t* mask,
                               const pm4g_prepared* out, FilterWs w, hipStream_t s);
 
+// Cases dataframe and case-level filters (casefilter.hip).
+struct CaseFilterWs {
+    uint32_t* flags;   // [cases] containment bits
+    uint32_t* cnt;     // [cases] kept events
+    uint32_t* kept;    // [cases] kept flag
+    int64_t* eoff;     // [cases] first output event
+    uint32_t* koff;    // [cases] output case-table row
+    uint32_t* part32;
+    int64_t* part64;
+    int64_t* scal;
+    uint32_t* uscal;
+};
+CaseFilterWs case_filter_ws_layout(Bump& b, int64_t n);
+hipError_t launch_cases_df(const pm4g_prepared* p, int64_t* n_events, int64_t* thr, hipStream_t s);
+hipError_t launch_filter_cases(const pm4g_prepared* p, const pm4g_case_filter* f, const pm4g_prepared* out,
+                               CaseFilterWs w, hipStream_t s);
+
 hipError_t launch_views_plan(const pm4g_prepared* p, const pm4g_view* views, int32_t V, ViewWs w,
                              BatchedOutDev out, hipStream_t s);
 // Count walk: per (tile, view) pair its records per bucket, one descriptor per

@@ -31,6 +31,8 @@ enum ProfId {
     P_VIEW_FILTER,
     P_DFG_COUNT,
     P_VIEW_WRITE,
+    P_CASES,
+    P_CASE_FILTER,
     P_COUNT
 };
 

@@ -72,6 +72,15 @@ class BatchedTuning(ctypes.Structure):
                 ("descriptor_capacity", ctypes.c_int64), ("cell_capacity", ctypes.c_int64)]
 
 
+class CaseFilter(ctypes.Structure):
+    """Case-level filter (host struct; the masks are device pointers)."""
+
+    _fields_ = [("min_events", ctypes.c_int64), ("max_events", ctypes.c_int64),
+                ("min_throughput", ctypes.c_int64), ("max_throughput", ctypes.c_int64),
+                ("act_mask", _P), ("path_mask", _P), ("path_keep", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 class Pm4gError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"pm4g error {code}: {msg}")
@@ -117,6 +126,13 @@ def load():
             L.pm4g_filter_view.argtypes = [ctypes.POINTER(_Prepared), _P, _P, ctypes.POINTER(_Prepared), _P,
                                            ctypes.c_size_t, _P]
             L.pm4g_filter_view.restype = ctypes.c_int
+            L.pm4g_cases.argtypes = [ctypes.POINTER(_Prepared), _P, _P, _P]
+            L.pm4g_cases.restype = ctypes.c_int
+            L.pm4g_filter_cases_workspace_bytes.argtypes = [ctypes.c_int64]
+            L.pm4g_filter_cases_workspace_bytes.restype = ctypes.c_size_t
+            L.pm4g_filter_cases.argtypes = [ctypes.POINTER(_Prepared), ctypes.POINTER(CaseFilter),
+                                            ctypes.POINTER(_Prepared), _P, ctypes.c_size_t, _P]
+            L.pm4g_filter_cases.restype = ctypes.c_int
             L.pm4g_profile_enable.argtypes = [ctypes.c_int]
             L.pm4g_profile_enable.restype = ctypes.c_int
             L.pm4g_profile_read.argtypes = [_P, _P, ctypes.c_int]
@@ -417,6 +433,49 @@ def pm4g_filter_view(prep: Prepared, view: torch.Tensor, mask: torch.Tensor, out
     q = o._struct()
     _check(L.pm4g_filter_view(ctypes.byref(p), _ptr(view), _ptr(mask), ctypes.byref(q), _ptr(ws), need,
                               _stream(stream)))
+    return o
+
+
+I64_MIN, I64_MAX = -(1 << 63), (1 << 63) - 1
+
+
+def pm4g_cases(prep: Prepared, stream=None) -> dict:
+    """Cases dataframe: per case (case-table order) its events and throughput time.
+
+    Device int64 tensors of prep.n_events entries; the first *prep.n_cases are set.
+    Asynchronous on the stream."""
+    dev = prep.case_s.device
+    m = max(prep.n_events, 1)
+    o = dict(n_events=torch.empty(m, dtype=torch.int64, device=dev),
+             throughput=torch.empty(m, dtype=torch.int64, device=dev))
+    p = prep._struct()
+    _check(load().pm4g_cases(ctypes.byref(p), _ptr(o["n_events"]), _ptr(o["throughput"]), _stream(stream)))
+    return o
+
+
+def pm4g_filter_cases(prep: Prepared, min_events: int = 0, max_events: int = I64_MAX,
+                      min_throughput: int = I64_MIN, max_throughput: int = I64_MAX,
+                      act_mask: torch.Tensor | None = None, path_mask: torch.Tensor | None = None,
+                      path_keep: bool = True, out: Prepared | None = None, ws: torch.Tensor | None = None,
+                      stream=None) -> Prepared:
+    """Events of the cases passing the case-level filters, as a prepared log.
+
+    act_mask: device int64 tensor of ceil(A/64) words; path_mask: ceil(A*A/64)
+    words with bit src*A + dst.  Asynchronous; the kept count is
+    out.case_off[out.n_cases] on the device."""
+    L = load()
+    dev = prep.case_s.device
+    o = out if out is not None else Prepared.empty(prep.n_events, prep.n_activities, dev)
+    need = int(L.pm4g_filter_cases_workspace_bytes(prep.n_events))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    f = CaseFilter(int(min_events), int(max_events), int(min_throughput), int(max_throughput),
+                   _ptr(act_mask) if act_mask is not None else None,
+                   _ptr(path_mask) if path_mask is not None else None, 1 if path_keep else 0, 0)
+    p = prep._struct()
+    q = o._struct()
+    _check(L.pm4g_filter_cases(ctypes.byref(p), ctypes.byref(f), ctypes.byref(q), _ptr(ws), need,
+                               _stream(stream)))
     return o
 
 
