@@ -210,6 +210,42 @@ def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int, autot
                                                        "agg_blocks": tune.agg_blocks or 512}}
 
 
+def bench_cases(log, prep, steps: int = 5) -> dict:
+    """Cases dataframe and case-level filters on the prepared log (whole-log calls)."""
+    import numpy as np
+    import torch
+
+    from paper_2204_04898_amd import pm4g
+
+    A = log.n_activities
+    rng = np.random.default_rng(220404898 + 6)
+    pm = np.zeros((A * A + 63) // 64, np.uint64)
+    for b in rng.choice(A * A, A, replace=False):
+        pm[b // 64] |= np.uint64(1) << np.uint64(b % 64)
+    pmd = torch.from_numpy(pm.view(np.int64)).to(prep.case_s.device)
+    out = pm4g.Prepared.empty(prep.n_events, A, prep.case_s.device)
+    res = {}
+    for name, call in (("cases_dataframe", lambda: pm4g.pm4g_cases(prep)),
+                       ("filter_events_5_40", lambda: pm4g.pm4g_filter_cases(prep, min_events=5, max_events=40,
+                                                                             out=out)),
+                       ("filter_drop_paths", lambda: pm4g.pm4g_filter_cases(prep, path_mask=pmd, path_keep=False,
+                                                                            out=out))):
+        call()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            call()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        r = {"ms_per_call": dt * 1e3, "events_per_s": prep.n_events / dt}
+        if name != "cases_dataframe":
+            K = int(out.n_cases.item())
+            r["kept_events"] = int(out.case_off[K].item())
+            r["kept_cases"] = K
+        res[name] = r
+    return res
+
+
 def bench_serving(logs: dict, preps: dict, seconds: float, rate: float, workers: int = 4,
                   batch_work: int = 20_000_000) -> dict:
     """Open-loop Poisson mix of DFG / variants / filter queries on resident logs."""
@@ -323,6 +359,7 @@ def main() -> int:
     ap.add_argument("--per-view-sample", type=int, default=64)
     ap.add_argument("--no-autotune", action="store_true", help="batched views with the library's default shape")
     ap.add_argument("--tune-cache", default=None, help="autotune cache file (default: the package's)")
+    ap.add_argument("--no-cases", action="store_true", help="skip the cases-dataframe and case-filter timing")
     ap.add_argument("--serve-seconds", type=float, default=8.0, help="serving run length (0: skip)")
     ap.add_argument("--serve-qps", type=float, default=200.0)
     ap.add_argument("--serve-workers", type=int, default=4, help="batches in flight (HIP streams)")
@@ -424,6 +461,9 @@ def main() -> int:
             os.environ["PM4G_TUNE_CACHE"] = args.tune_cache
         out["batched_views"] = bench_views(log, prep, args.views, args.view_steps, args.per_view_sample,
                                            autotune=not args.no_autotune)
+    if k == 3 and not args.no_cases:
+        log_progress("cases dataframe and case filters")
+        out["cases"] = bench_cases(log, prep)
     if args.serve_seconds > 0 and k == 3:
         log_progress("serving: generating the 10M-event log")
         log2 = synth.config_log(2)
