@@ -42,7 +42,7 @@ def _load():
         L.orc_view.argtypes = [i64, P, P, P, i32, i32, i32, i64, i64, P,
                                P, P, P, P, P, P, P, P, P, P, P]
         L.orc_cases.argtypes = [i64, P, P, P, i32, P, P, P, P]
-        L.orc_filter_cases.argtypes = [i64, P, P, P, i32, i64, i64, i64, i64, P, P, i32, P, P, P, P, P]
+        L.orc_filter_cases.argtypes = [i64, P, P, P, i32, P, P, P, i32, P, P, P, i64, i32, P, P, P, P, P]
         for f in (L.orc_prepare, L.orc_dfg, L.orc_variants, L.orc_view, L.orc_cases, L.orc_filter_cases):
             f.restype = ctypes.c_int
         _lib = L
@@ -198,19 +198,24 @@ I64_MIN, I64_MAX = -(1 << 63), (1 << 63) - 1
 
 def filter_cases(case, act, ts, A: int, min_events: int = 0, max_events: int = I64_MAX,
                  min_thr: int = I64_MIN, max_thr: int = I64_MAX, act_mask=None, path_mask=None,
-                 path_keep: bool = True) -> dict:
+                 path_keep: bool = True, contain_lo: int = I64_MIN, contain_hi: int = I64_MAX,
+                 meet_lo: int = I64_MIN, meet_hi: int = I64_MAX, start_mask=None, end_mask=None,
+                 variant_mask=None, n_variant_bits: int = 0, variant_keep: bool = True) -> dict:
     """Events (in order) of the cases passing the case-level filters."""
     case, act, ts = _cols(case, act, ts)
     n = case.shape[0]
     m = max(n, 1)
     out = dict(case_s=np.empty(m, np.int32), act_s=np.empty(m, np.int32), ts_s=np.empty(m, np.int64))
     no, nc = np.zeros(1, np.int64), np.zeros(1, np.int64)
-    am = None if act_mask is None else np.ascontiguousarray(act_mask, dtype=np.uint64)
-    pm = None if path_mask is None else np.ascontiguousarray(path_mask, dtype=np.uint64)
-    rc = _load().orc_filter_cases(n, _p(case), _p(act), _p(ts), A, int(min_events), int(max_events),
-                                  int(min_thr), int(max_thr), None if am is None else _p(am),
-                                  None if pm is None else _p(pm), 1 if path_keep else 0,
-                                  _p(out["case_s"]), _p(out["act_s"]), _p(out["ts_s"]), _p(no), _p(nc))
+    bounds = np.array([min_events, max_events, min_thr, max_thr, contain_lo, contain_hi, meet_lo, meet_hi],
+                      dtype=np.int64)
+    masks = [None if x is None else np.ascontiguousarray(x, dtype=np.uint64)
+             for x in (act_mask, path_mask, start_mask, end_mask, variant_mask)]
+    ptr = [None if x is None else _p(x) for x in masks]
+    rc = _load().orc_filter_cases(n, _p(case), _p(act), _p(ts), A, _p(bounds), ptr[0], ptr[1],
+                                  1 if path_keep else 0, ptr[2], ptr[3], ptr[4], int(n_variant_bits),
+                                  1 if variant_keep else 0, _p(out["case_s"]), _p(out["act_s"]),
+                                  _p(out["ts_s"]), _p(no), _p(nc))
     if rc:
         raise OracleError(rc)
     k = int(no[0])

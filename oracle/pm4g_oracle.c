@@ -43,7 +43,10 @@
  *   - throughput time = timestamp of the case's last event minus its first;
  *   - paths filtering keeps (or drops) the whole cases that contain a
  *     directly-follows pair of the given set; the case-level predicates
- *     combine as a conjunction.
+ *     combine as a conjunction, bounds inclusive;
+ *   - a case is contained in a time window when its first and last events
+ *     are inside it, and intersects it when its [first, last] span overlaps
+ *     it; start/end filters look at the first/last event of the case.
  *
  * Status codes: 0 ok, -1 invalid argument, -2 activity out of [0, A).
  */
@@ -410,39 +413,71 @@ int orc_cases(int64_t n, const int32_t *case_id, const int32_t *act, const int64
 /*
  * orc_filter_cases: case-level filtering (Sec. 3: aggregations / filtering at
  * the case level; the cases-dataframe module's filters on the number of
- * events and the throughput time; the DFG module's paths filtering).  A case
- * is kept iff every predicate holds:
+ * events and the throughput time; the DFG module's paths filtering; the
+ * timestamp filters on whole cases; the start/end-activity and variant
+ * filters).  bounds[8] = {min_events, max_events, min_thr, max_thr,
+ * contain_lo, contain_hi, meet_lo, meet_hi}; with first/last = the case's
+ * first and last event in the (case, timestamp, row) order, a case is kept
+ * iff every predicate holds:
  *   min_events <= its number of events <= max_events;
  *   min_thr <= its throughput time <= max_thr;
+ *   contained in the window: ts(first) >= contain_lo and ts(last) <= contain_hi;
+ *   intersecting the window: ts(first) <= meet_hi and ts(last) >= meet_lo;
  *   act_mask (ceil(A/64) words, may be NULL): one of its events has an
  *     activity of the set;
  *   path_mask (ceil(A*A/64) words, bit src*A+dst, may be NULL): one of its
  *     directly-follows pairs is in the set (path_keep != 0), or none is
- *     (path_keep == 0).
+ *     (path_keep == 0);
+ *   start_mask / end_mask (ceil(A/64) words, may be NULL): the activity of
+ *     its first / last event is in the set;
+ *   variant_mask (may be NULL; n_variant_bits bits over the variant ids of
+ *     orc_variants): its variant is in the set (variant_keep != 0), or is not
+ *     (variant_keep == 0).
  * The kept cases' events are written in (case, timestamp, row) order; n_out
  * receives their number and n_cases_out the number of kept cases.
  */
 int orc_filter_cases(int64_t n, const int32_t *case_id, const int32_t *act, const int64_t *ts, int32_t A,
-                     int64_t min_events, int64_t max_events, int64_t min_thr, int64_t max_thr,
-                     const uint64_t *act_mask, const uint64_t *path_mask, int32_t path_keep,
+                     const int64_t *bounds, const uint64_t *act_mask, const uint64_t *path_mask,
+                     int32_t path_keep, const uint64_t *start_mask, const uint64_t *end_mask,
+                     const uint64_t *variant_mask, int64_t n_variant_bits, int32_t variant_keep,
                      int32_t *case_out, int32_t *act_out, int64_t *ts_out, int64_t *n_out,
                      int64_t *n_cases_out)
 {
-    if (n < 0 || A < 1) return ORC_E_INVALID;
+    if (n < 0 || A < 1 || !bounds) return ORC_E_INVALID;
     size_t nn = (size_t)(n > 0 ? n : 1);
     int32_t *case_s = (int32_t *)malloc(nn * sizeof(int32_t));
     int32_t *act_s = (int32_t *)malloc(nn * sizeof(int32_t));
     int64_t *ts_s = (int64_t *)malloc(nn * sizeof(int64_t));
     int64_t *off = (int64_t *)malloc((nn + 1) * sizeof(int64_t));
+    int32_t *cvar = NULL;
     int64_t C = 0;
     int r = orc_prepare(n, case_id, act, ts, A, NULL, case_s, act_s, ts_s, off, NULL, &C);
+    if (r == ORC_OK && variant_mask) {
+        cvar = (int32_t *)malloc(nn * sizeof(int32_t));
+        int64_t *vc = (int64_t *)malloc(nn * sizeof(int64_t));
+        int32_t *vl = (int32_t *)malloc(nn * sizeof(int32_t));
+        int32_t *vr = (int32_t *)malloc(nn * sizeof(int32_t));
+        int64_t *vo = (int64_t *)malloc((nn + 1) * sizeof(int64_t));
+        int32_t *va = (int32_t *)malloc(nn * sizeof(int32_t));
+        int32_t *cc = (int32_t *)malloc(nn * sizeof(int32_t));
+        int64_t V = 0, C2 = 0;
+        r = orc_variants(n, case_id, act, ts, A, &V, vc, vl, vr, vo, va, cc, cvar, &C2);
+        free(vc);
+        free(vl);
+        free(vr);
+        free(vo);
+        free(va);
+        free(cc);
+    }
     int64_t m = 0, kc = 0;
     if (r == ORC_OK) {
         for (int64_t j = 0; j < C; j++) {
             int64_t first = off[j], end = off[j + 1];
             int64_t events = end - first;
-            int64_t thr = (int64_t)((uint64_t)ts_s[end - 1] - (uint64_t)ts_s[first]);
-            int keep = events >= min_events && events <= max_events && thr >= min_thr && thr <= max_thr;
+            int64_t t0 = ts_s[first], t1 = ts_s[end - 1];
+            int64_t thr = (int64_t)((uint64_t)t1 - (uint64_t)t0);
+            int keep = events >= bounds[0] && events <= bounds[1] && thr >= bounds[2] && thr <= bounds[3] &&
+                       t0 >= bounds[4] && t1 <= bounds[5] && t0 <= bounds[7] && t1 >= bounds[6];
             if (keep && act_mask) {
                 int has = 0;
                 for (int64_t k = first; k < end; k++)
@@ -456,6 +491,13 @@ int orc_filter_cases(int64_t n, const int32_t *case_id, const int32_t *act, cons
                     if ((path_mask[cell / 64] >> (cell % 64)) & 1u) has = 1;
                 }
                 keep = path_keep ? has : !has;
+            }
+            if (keep && start_mask) keep = (start_mask[act_s[first] / 64] >> (act_s[first] % 64)) & 1u;
+            if (keep && end_mask) keep = (end_mask[act_s[end - 1] / 64] >> (act_s[end - 1] % 64)) & 1u;
+            if (keep && variant_mask) {
+                int64_t v = cvar[j];
+                int in = v < n_variant_bits && ((variant_mask[v / 64] >> (v % 64)) & 1u);
+                keep = variant_keep ? in : !in;
             }
             if (!keep) continue;
             for (int64_t k = first; k < end; k++) {
@@ -473,5 +515,6 @@ int orc_filter_cases(int64_t n, const int32_t *case_id, const int32_t *act, cons
     free(act_s);
     free(ts_s);
     free(off);
+    free(cvar);
     return r;
 }

@@ -150,22 +150,40 @@ def cases(c, a, t):
 
 
 def filter_cases(c, a, t, min_events, max_events, min_thr, max_thr, act_set=None, path_set=None,
-                 path_keep=True):
+                 path_keep=True, contain=None, meet=None, start_set=None, end_set=None, variant_set=None,
+                 variant_keep=True):
     """Events (case, act, ts) of the kept cases, cases ascending, events in order;
-    a case's paths are the (a_i, a_j) of its directly-follows pairs (i, j)."""
+    a case's paths are the (a_i, a_j) of its directly-follows pairs (i, j);
+    contain / meet are inclusive (lo, hi) windows the case's first and last
+    timestamps must lie in / its [first, last] span must overlap."""
     groups = _by_case(c)
     pairs = directly_follows_pairs(c, t)
+    var_of = {}
+    if variant_set is not None:
+        v = variants(c, a, t)
+        var_of = dict(zip(v["case_code"], v["case_variant"]))
     kept_events = []
     n_cases = 0
     for code in sorted(groups):
         ev = ordered_members(c, t, groups[code])
-        thr = to_i64(t[ev[-1]] - t[ev[0]])
+        first, last = t[ev[0]], t[ev[-1]]
+        thr = to_i64(last - first)
         keep = min_events <= len(ev) <= max_events and min_thr <= thr <= max_thr
+        if keep and contain is not None:
+            keep = contain[0] <= first and last <= contain[1]
+        if keep and meet is not None:
+            keep = first <= meet[1] and last >= meet[0]
         if keep and act_set is not None:
             keep = any(a[i] in act_set for i in ev)
         if keep and path_set is not None:
             has = any((a[i], a[j]) in path_set for (i, j) in pairs if c[i] == code)
             keep = has if path_keep else not has
+        if keep and start_set is not None:
+            keep = a[ev[0]] in start_set
+        if keep and end_set is not None:
+            keep = a[ev[-1]] in end_set
+        if keep and variant_set is not None:
+            keep = (var_of[code] in variant_set) == bool(variant_keep)
         if keep:
             n_cases += 1
             kept_events += [(c[i], a[i], t[i]) for i in ev]

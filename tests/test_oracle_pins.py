@@ -460,6 +460,25 @@ def _mask(bits, nbits):
     return m
 
 
+def _golden_window_kw(f, A, n_variants):
+    """Keywords of the time-window, start/end activity and variant filters of a
+    golden filter entry."""
+    kw = {}
+    if "contain" in f:
+        kw["contain_lo"], kw["contain_hi"] = f["contain"]
+    if "meet" in f:
+        kw["meet_lo"], kw["meet_hi"] = f["meet"]
+    if "start_acts" in f:
+        kw["start_mask"] = _mask(f["start_acts"], A)
+    if "end_acts" in f:
+        kw["end_mask"] = _mask(f["end_acts"], A)
+    if "variants" in f:
+        kw["variant_mask"] = _mask(f["variants"], n_variants)
+        kw["n_variant_bits"] = n_variants
+        kw["variant_keep"] = f["variant_keep"]
+    return kw
+
+
 def test_cases_golden():
     g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_road_fines.json")))
     r, A = g["rows"], g["A"]
@@ -473,6 +492,7 @@ def test_cases_golden():
         if "paths" in f:
             kw["path_mask"] = _mask([x * A + y for x, y in f["paths"]], A * A)
             kw["path_keep"] = f["path_keep"]
+        kw.update(_golden_window_kw(f, A, len(g["expected"]["variants"]["var_count"])))
         o = oracle.filter_cases(r["case"], r["act"], r["ts"], A, **kw)
         got = list(zip(o["case_s"].tolist(), o["act_s"].tolist(), o["ts_s"].tolist()))
         assert got == [tuple(e) for e in f["events"]], f["name"]
@@ -514,6 +534,41 @@ def test_filter_cases_match_bruteforce(log, data):
     assert o["n_cases"] == nc and o["n_events"] == len(ev)
 
 
+@settings(max_examples=250, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(tiny_logs(), st.data())
+def test_window_start_end_variant_filters_match_bruteforce(log, data):
+    case, act, ts, A = log
+    tv = sorted(set(int(x) for x in ts)) or [0]
+    bound = st.sampled_from(tv) | st.integers(-2**62, 2**62)
+    contain = data.draw(st.none() | st.tuples(bound, bound))
+    meet = data.draw(st.none() | st.tuples(bound, bound))
+    starts = data.draw(st.none() | st.sets(st.integers(0, A - 1)))
+    ends = data.draw(st.none() | st.sets(st.integers(0, A - 1)))
+    nv = oracle.variants(case, act, ts, A)["n_variants"]
+    vbits = data.draw(st.integers(0, nv + 2))                # ids at or above it are outside the set
+    vset = data.draw(st.none() | st.sets(st.integers(0, max(vbits - 1, 0))))
+    if vset is not None:
+        vset = {v for v in vset if v < vbits}
+    vkeep = data.draw(st.booleans())
+    kw = {}
+    if contain is not None:
+        kw["contain_lo"], kw["contain_hi"] = contain
+    if meet is not None:
+        kw["meet_lo"], kw["meet_hi"] = meet
+    if starts is not None:
+        kw["start_mask"] = _mask(starts, A)
+    if ends is not None:
+        kw["end_mask"] = _mask(ends, A)
+    if vset is not None:
+        kw.update(variant_mask=_mask(vset, max(vbits, 1)), n_variant_bits=vbits, variant_keep=vkeep)
+    o = oracle.filter_cases(case, act, ts, A, **kw)
+    ev, nc = bf.filter_cases(case, act, ts, 0, oracle.I64_MAX, oracle.I64_MIN, oracle.I64_MAX, contain=contain,
+                             meet=meet, start_set=starts, end_set=ends, variant_set=vset, variant_keep=vkeep)
+    got = list(zip(o["case_s"].tolist(), o["act_s"].tolist(), o["ts_s"].tolist()))
+    assert got == ev
+    assert o["n_cases"] == nc and o["n_events"] == len(ev)
+
+
 def test_cases_invariants_on_workload():
     log = synth.config_log(2, 0.01)
     o = oracle.cases(log.case, log.act, log.ts, log.n_activities)
@@ -531,3 +586,23 @@ def test_cases_invariants_on_workload():
     d2 = oracle.filter_cases(log.case, log.act, log.ts, A, path_mask=allp, path_keep=False)
     assert k["n_cases"] == int((o["n_events"] >= 2).sum()) and d2["n_cases"] == int((o["n_events"] == 1).sum())
     assert k["n_events"] + d2["n_events"] == log.n_events
+
+    # a variant set and its complement split the cases; keeping every variant keeps all
+    v = oracle.variants(log.case, log.act, log.ts, A)
+    nv = v["n_variants"]
+    half = _mask(range(0, nv, 2), nv)
+    kv = oracle.filter_cases(log.case, log.act, log.ts, A, variant_mask=half, n_variant_bits=nv, variant_keep=True)
+    dv = oracle.filter_cases(log.case, log.act, log.ts, A, variant_mask=half, n_variant_bits=nv, variant_keep=False)
+    assert kv["n_cases"] == int(v["var_count"][0::2].sum()) and kv["n_cases"] + dv["n_cases"] == o["n_cases"]
+    assert kv["n_events"] == int((v["var_count"] * v["var_len"])[0::2].sum())
+    # every case is contained in [min ts, max ts]; the start sets of all activities keep everything
+    every = _mask(range(A), A)
+    w = oracle.filter_cases(log.case, log.act, log.ts, A, contain_lo=int(log.ts.min()), contain_hi=int(log.ts.max()),
+                            start_mask=every, end_mask=every)
+    assert w["n_events"] == log.n_events
+    # a case intersects a window iff it is not wholly before or wholly after it
+    lo, hi = np.percentile(log.ts, [40, 60]).astype(np.int64).tolist()
+    m = oracle.filter_cases(log.case, log.act, log.ts, A, meet_lo=lo, meet_hi=hi)
+    before = oracle.filter_cases(log.case, log.act, log.ts, A, contain_hi=lo - 1)
+    after = oracle.filter_cases(log.case, log.act, log.ts, A, contain_lo=hi + 1)
+    assert m["n_cases"] + before["n_cases"] + after["n_cases"] == o["n_cases"]
