@@ -224,12 +224,28 @@ def bench_cases(log, prep, steps: int = 5) -> dict:
         pm[b // 64] |= np.uint64(1) << np.uint64(b % 64)
     pmd = torch.from_numpy(pm.view(np.int64)).to(prep.case_s.device)
     out = pm4g.Prepared.empty(prep.n_events, A, prep.case_s.device)
+    # per-case variant ids of the same log (untimed), and the ten most frequent variants
+    vo = pm4g.pm4g_variants_prepared(prep)
+    torch.cuda.synchronize()
+    nv = int(vo["n_variants"].item())
+    vm = np.zeros((nv + 63) // 64 or 1, np.uint64)
+    for b in range(min(nv, 10)):
+        vm[b // 64] |= np.uint64(1) << np.uint64(b % 64)
+    vmd = torch.from_numpy(vm.view(np.int64)).to(prep.case_s.device)
+    t_lo, t_hi = (int(x) for x in torch.quantile(prep.ts_s[::max(prep.n_events // 1000000, 1)].double(),
+                                                  torch.tensor([0.3, 0.7], dtype=torch.float64,
+                                                               device=prep.case_s.device)).cpu())
     res = {}
     for name, call in (("cases_dataframe", lambda: pm4g.pm4g_cases(prep)),
                        ("filter_events_5_40", lambda: pm4g.pm4g_filter_cases(prep, min_events=5, max_events=40,
                                                                              out=out)),
                        ("filter_drop_paths", lambda: pm4g.pm4g_filter_cases(prep, path_mask=pmd, path_keep=False,
-                                                                            out=out))):
+                                                                            out=out)),
+                       ("filter_contained_30_70pct", lambda: pm4g.pm4g_filter_cases(prep, contain_lo=t_lo,
+                                                                                    contain_hi=t_hi, out=out)),
+                       ("filter_top10_variants", lambda: pm4g.pm4g_filter_cases(
+                           prep, case_variant=vo["case_variant"], variant_mask=vmd, n_variant_bits=nv,
+                           variant_keep=True, out=out))):
         call()
         torch.cuda.synchronize()
         t0 = time.perf_counter()

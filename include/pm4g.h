@@ -317,15 +317,29 @@ int pm4g_cases(const pm4g_prepared *log, int64_t *n_events_out, int64_t *through
 /*
  * Case-level filter (Sec. 3: filtering at the case level on the number of
  * events and the throughput time; cases containing an activity; the DFG
- * module's paths filtering).  A case is kept iff every predicate holds:
- *   min_events <= its events <= max_events (inclusive);
- *   min_throughput <= its throughput time <= max_throughput (inclusive);
+ * module's paths filtering; timestamp filters on whole cases; start and end
+ * activity filters; variant filtering).  With first/last the case's first
+ * and last event in the (case, timestamp, row) order, a case is kept iff
+ * every predicate holds (bounds inclusive):
+ *   min_events <= its events <= max_events;
+ *   min_throughput <= its throughput time <= max_throughput;
+ *   contained in a window: ts(first) >= contain_lo and ts(last) <= contain_hi;
+ *   intersecting a window: ts(first) <= meet_hi and ts(last) >= meet_lo
+ *     (INT64_MIN / INT64_MAX leave a bound open);
  *   act_mask (device, ceil(A/64) words; NULL: no predicate): one of its
  *     events has an activity whose bit is set;
  *   path_mask (device, ceil(A*A/64) words, bit src*A + dst; NULL: no
  *     predicate): one of its directly-follows pairs has its bit set
- *     (path_keep = 1), or none has (path_keep = 0).
- * The struct itself is read on the host.
+ *     (path_keep = 1), or none has (path_keep = 0);
+ *   start_mask / end_mask (device, ceil(A/64) words; NULL: no predicate): the
+ *     activity of its first / last event has its bit set;
+ *   variant_mask (device, ceil(n_variant_bits/64) words; NULL: no
+ *     predicate): with v = case_variant[j] for the log's j-th case (device,
+ *     as pm4g_variants writes it for the same prepared log), v <
+ *     n_variant_bits and bit v is set (variant_keep = 1), or not
+ *     (variant_keep = 0).  case_variant must be given with variant_mask.
+ * path_keep and variant_keep are 0 or 1, else PM4G_E_INVALID.  The struct
+ * itself is read on the host.
  */
 typedef struct {
     int64_t min_events;
@@ -335,7 +349,16 @@ typedef struct {
     const uint64_t *act_mask;
     const uint64_t *path_mask;
     int32_t path_keep;
-    int32_t reserved;
+    int32_t variant_keep;
+    int64_t contain_lo;
+    int64_t contain_hi;
+    int64_t meet_lo;
+    int64_t meet_hi;
+    const uint64_t *start_mask;
+    const uint64_t *end_mask;
+    const int32_t *case_variant;
+    const uint64_t *variant_mask;
+    int64_t n_variant_bits;
 } pm4g_case_filter;
 
 /*

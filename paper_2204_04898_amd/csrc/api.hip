@@ -385,6 +385,9 @@ int pm4g_filter_cases(const pm4g_prepared* log, const pm4g_case_filter* filter, 
     if (int rc = check_prepared(log, true)) return rc;
     PM4G_CHECK(filter != nullptr, "filter is NULL");
     PM4G_CHECK(filter->path_keep == 0 || filter->path_keep == 1, "path_keep must be 0 or 1");
+    PM4G_CHECK(filter->variant_keep == 0 || filter->variant_keep == 1, "variant_keep must be 0 or 1");
+    PM4G_CHECK(!filter->variant_mask || (filter->case_variant && filter->n_variant_bits >= 0),
+               "variant_mask needs case_variant and n_variant_bits >= 0");
     PM4G_CHECK(out && out->case_off && out->n_cases && out->status &&
                    (log->n_events == 0 || (out->case_s && out->act_s && out->ts_s && out->case_code)),
                "a filtered-log output array is NULL");

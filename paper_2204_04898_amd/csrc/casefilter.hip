@@ -1,7 +1,8 @@
 // Cases dataframe and case-level filters of a prepared log (Sec. 3: the cases
 // dataframe holds, per case, its number of events and its throughput time;
 // case-level filtering on them; the DFG module's paths filtering, which keeps
-// or drops the cases that contain given directly-follows pairs).
+// or drops the cases that contain given directly-follows pairs; timestamp
+// filters on whole cases; start/end activity and variant filters).
 //
 //   k_cases_df      per case: events = case_off[c+1] - case_off[c], throughput
 //                   = ts of its last event - ts of its first (mod 2^64)
@@ -10,6 +11,9 @@
 //                   (or whose pair with the previous event of its case) is in
 //                   the set marks its case in LDS
 //   k_cf_decide     per case: all predicates -> kept; kept events, kept flag
+//                   (range, time-window, start/end activity and variant
+//                   predicates read the case's first and last event and its
+//                   variant id)
 //   scans           output position of each kept case's events and of its row
 //                   in the output case table
 //   k_cf_emit       kept cases' events copied in order (a wave per 64 cases,
@@ -109,7 +113,8 @@ __global__ __launch_bounds__(kCB) void k_cf_contains(const int32_t* __restrict__
     }
 }
 
-__global__ __launch_bounds__(kCB) void k_cf_decide(const int64_t* __restrict__ case_off,
+__global__ __launch_bounds__(kCB) void k_cf_decide(const int32_t* __restrict__ act_s,
+                                                   const int64_t* __restrict__ case_off,
                                                    const int64_t* __restrict__ ts_s, const int64_t* n_cases,
                                                    pm4g_case_filter f, CaseFilterWs w) {
     const int64_t C = *n_cases;
@@ -117,13 +122,22 @@ __global__ __launch_bounds__(kCB) void k_cf_decide(const int64_t* __restrict__ c
     for (int64_t c = (int64_t)blockIdx.x * kCB + threadIdx.x; c < C; c += (int64_t)gridDim.x * kCB) {
         const int64_t a = case_off[c], b = case_off[c + 1];
         const int64_t ev = b - a;
-        const int64_t thr = (int64_t)((uint64_t)ts_s[b - 1] - (uint64_t)ts_s[a]);
+        const int64_t t0 = ts_s[a], t1 = ts_s[b - 1];
+        const int64_t thr = (int64_t)((uint64_t)t1 - (uint64_t)t0);
         bool keep = ev >= f.min_events && ev <= f.max_events && thr >= f.min_throughput &&
-                    thr <= f.max_throughput;
+                    thr <= f.max_throughput && t0 >= f.contain_lo && t1 <= f.contain_hi && t0 <= f.meet_hi &&
+                    t1 >= f.meet_lo;
         if (use_act || use_path) {
             const uint32_t fl = w.flags[c];
             if (use_act) keep = keep && (fl & 1u);
             if (use_path) keep = keep && (((fl >> 1) & 1u) == (f.path_keep ? 1u : 0u));
+        }
+        if (f.start_mask) keep = keep && bit_of(f.start_mask, act_s[a]);
+        if (f.end_mask) keep = keep && bit_of(f.end_mask, act_s[b - 1]);
+        if (f.variant_mask) {
+            const int64_t v = f.case_variant[c];
+            const bool in = v >= 0 && v < f.n_variant_bits && bit_of(f.variant_mask, v);
+            keep = keep && (in == (f.variant_keep != 0));
         }
         w.cnt[c] = keep ? (uint32_t)ev : 0u;
         w.kept[c] = keep ? 1u : 0u;
@@ -207,7 +221,7 @@ hipError_t launch_filter_cases(const pm4g_prepared* p, const pm4g_case_filter* f
     if (fv.act_mask || fv.path_mask)
         k_cf_contains<<<kCGrid, kCB, 0, s>>>(p->act_s, p->case_off, p->n_cases, p->n_activities, fv.act_mask,
                                              fv.path_mask, w.flags);
-    k_cf_decide<<<kCGrid, kCB, 0, s>>>(p->case_off, p->ts_s, p->n_cases, fv, w);
+    k_cf_decide<<<kCGrid, kCB, 0, s>>>(p->act_s, p->case_off, p->ts_s, p->n_cases, fv, w);
     dev::excl_scan<int64_t>(w.cnt, p->n_cases, w.eoff, w.part64, &w.scal[1], s);
     dev::excl_scan<uint32_t>(w.kept, p->n_cases, w.koff, w.part32, &w.uscal[0], s);
     k_cf_check<<<1, 1, 0, s>>>(w, out->n_events);

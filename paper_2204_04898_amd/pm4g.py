@@ -78,7 +78,10 @@ class CaseFilter(ctypes.Structure):
     _fields_ = [("min_events", ctypes.c_int64), ("max_events", ctypes.c_int64),
                 ("min_throughput", ctypes.c_int64), ("max_throughput", ctypes.c_int64),
                 ("act_mask", _P), ("path_mask", _P), ("path_keep", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("variant_keep", ctypes.c_int32), ("contain_lo", ctypes.c_int64), ("contain_hi", ctypes.c_int64),
+                ("meet_lo", ctypes.c_int64), ("meet_hi", ctypes.c_int64), ("start_mask", _P),
+                ("end_mask", _P), ("case_variant", _P), ("variant_mask", _P),
+                ("n_variant_bits", ctypes.c_int64)]
 
 
 class Pm4gError(RuntimeError):
@@ -456,22 +459,33 @@ def pm4g_cases(prep: Prepared, stream=None) -> dict:
 def pm4g_filter_cases(prep: Prepared, min_events: int = 0, max_events: int = I64_MAX,
                       min_throughput: int = I64_MIN, max_throughput: int = I64_MAX,
                       act_mask: torch.Tensor | None = None, path_mask: torch.Tensor | None = None,
-                      path_keep: bool = True, out: Prepared | None = None, ws: torch.Tensor | None = None,
+                      path_keep: bool = True, contain_lo: int = I64_MIN, contain_hi: int = I64_MAX,
+                      meet_lo: int = I64_MIN, meet_hi: int = I64_MAX, start_mask: torch.Tensor | None = None,
+                      end_mask: torch.Tensor | None = None, case_variant: torch.Tensor | None = None,
+                      variant_mask: torch.Tensor | None = None, n_variant_bits: int = 0,
+                      variant_keep: bool = True, out: Prepared | None = None, ws: torch.Tensor | None = None,
                       stream=None) -> Prepared:
     """Events of the cases passing the case-level filters, as a prepared log.
 
-    act_mask: device int64 tensor of ceil(A/64) words; path_mask: ceil(A*A/64)
-    words with bit src*A + dst.  Asynchronous; the kept count is
-    out.case_off[out.n_cases] on the device."""
+    act_mask / start_mask / end_mask: device int64 tensors of ceil(A/64)
+    words; path_mask: ceil(A*A/64) words with bit src*A + dst; variant_mask:
+    ceil(n_variant_bits/64) words over the ids in case_variant (the int32
+    per-case variant ids pm4g_variants_prepared writes for the same log).
+    Asynchronous; the kept count is out.case_off[out.n_cases] on the device."""
     L = load()
     dev = prep.case_s.device
     o = out if out is not None else Prepared.empty(prep.n_events, prep.n_activities, dev)
     need = int(L.pm4g_filter_cases_workspace_bytes(prep.n_events))
     if ws is None or ws.numel() < need:
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
-    f = CaseFilter(int(min_events), int(max_events), int(min_throughput), int(max_throughput),
-                   _ptr(act_mask) if act_mask is not None else None,
-                   _ptr(path_mask) if path_mask is not None else None, 1 if path_keep else 0, 0)
+
+    def opt(t):
+        return _ptr(t) if t is not None else None
+
+    f = CaseFilter(int(min_events), int(max_events), int(min_throughput), int(max_throughput), opt(act_mask),
+                   opt(path_mask), 1 if path_keep else 0, 1 if variant_keep else 0, int(contain_lo),
+                   int(contain_hi), int(meet_lo), int(meet_hi), opt(start_mask), opt(end_mask), opt(case_variant),
+                   opt(variant_mask), int(n_variant_bits))
     p = prep._struct()
     q = o._struct()
     _check(L.pm4g_filter_cases(ctypes.byref(p), ctypes.byref(f), ctypes.byref(q), _ptr(ws), need,

@@ -1,6 +1,7 @@
 """Cases dataframe and case-level filters on the GPU against the oracle:
 events and throughput per case, and the kept cases' events (order and case
-table) for range, activity and path predicates, bit-exact."""
+table) for range, activity, path, time-window, start/end activity and variant
+predicates, bit-exact."""
 import json
 import os
 
@@ -38,12 +39,22 @@ def _gpu_cases(p):
     return {k: v[:C].cpu().numpy() for k, v in o.items()}, p.case_code[:C].cpu().numpy()
 
 
-def _gpu_filter(p, **kw):
+MASKS = ("act_mask", "path_mask", "start_mask", "end_mask", "variant_mask")
+
+
+def _case_variant(p):
+    v = pm4g.pm4g_variants_prepared(p)
+    torch.cuda.synchronize()
+    return v["case_variant"], int(v["n_variants"].item())
+
+
+def _gpu_filter(p, case_variant=None, **kw):
     A = p.n_activities
-    if "act_mask" in kw:
-        kw["act_mask"] = dev(kw["act_mask"].view(np.int64), np.int64)
-    if "path_mask" in kw:
-        kw["path_mask"] = dev(kw["path_mask"].view(np.int64), np.int64)
+    for k in MASKS:
+        if k in kw:
+            kw[k] = dev(kw[k].view(np.int64), np.int64)
+    if "variant_mask" in kw:
+        kw["case_variant"] = case_variant
     f = pm4g.pm4g_filter_cases(p, **kw)
     torch.cuda.synchronize()
     assert int(f.status.item()) == 0
@@ -55,10 +66,10 @@ def _gpu_filter(p, **kw):
                 n_cases=K, n_events=m), A
 
 
-def _check_filter(case, act, ts, A, p, **kw):
+def _check_filter(case, act, ts, A, p, case_variant=None, **kw):
     """GPU filter with the binding's keywords against the oracle (its names for
     the throughput bounds), plus the output case table's consistency."""
-    g, _ = _gpu_filter(p, **dict(kw))
+    g, _ = _gpu_filter(p, case_variant, **dict(kw))
     okw = {k: v for k, v in kw.items() if k not in ("min_throughput", "max_throughput")}
     if "min_throughput" in kw:
         okw["min_thr"] = kw["min_throughput"]
@@ -85,6 +96,8 @@ def test_golden_road_fines():
     assert codes.tolist() == exp["case_code"]
     assert c["n_events"].tolist() == exp["n_events"]
     assert c["throughput"].tolist() == exp["throughput"]
+    cv, nv = _case_variant(p)
+    assert cv[:4].cpu().tolist() == gd["expected"]["variants"]["case_variant"]
     for f in gd["cases"]["filters"]:
         kw = {k: f[k] for k in ("min_events", "max_events") if k in f}
         if "min_thr" in f:
@@ -94,7 +107,18 @@ def test_golden_road_fines():
         if "paths" in f:
             kw["path_mask"] = _mask([x * A + y for x, y in f["paths"]], A * A)
             kw["path_keep"] = f["path_keep"]
-        g, _ = _gpu_filter(p, **kw)
+        if "contain" in f:
+            kw["contain_lo"], kw["contain_hi"] = f["contain"]
+        if "meet" in f:
+            kw["meet_lo"], kw["meet_hi"] = f["meet"]
+        if "start_acts" in f:
+            kw["start_mask"] = _mask(f["start_acts"], A)
+        if "end_acts" in f:
+            kw["end_mask"] = _mask(f["end_acts"], A)
+        if "variants" in f:
+            kw["variant_mask"] = _mask(f["variants"], nv)
+            kw["n_variant_bits"], kw["variant_keep"] = nv, f["variant_keep"]
+        g, _ = _gpu_filter(p, cv, **kw)
         got = list(zip(g["case_s"].tolist(), g["act_s"].tolist(), g["ts_s"].tolist()))
         assert got == [tuple(e) for e in f["events"]], f["name"]
         assert g["case_code"].tolist() == f["kept_cases"], f["name"]
@@ -125,6 +149,48 @@ def test_workloads(k, scale):
     ]
     for f in filters:
         _check_filter(log.case, log.act, log.ts, A, p, **f)
+
+
+@pytest.mark.parametrize("k,scale", [(2, 0.02), (3, 0.005)])
+def test_window_start_end_variant_filters(k, scale):
+    log = synth.config_log(k, scale)
+    A = log.n_activities
+    note(f"window/start/end/variant filters: config {k} scale {scale}: N={log.n_events}")
+    p = _prep(log.case, log.act, log.ts, A)
+    cv, nv = _case_variant(p)
+    rng = np.random.default_rng(200 + k)
+    lo, mid, hi = (int(x) for x in np.percentile(log.ts, [30, 50, 70]))
+    top = list(range(min(nv, 5)))
+    filters = [
+        dict(contain_lo=lo, contain_hi=hi),
+        dict(meet_lo=mid, meet_hi=mid),                             # cases running at one instant
+        dict(meet_lo=lo, meet_hi=hi, min_events=3),
+        dict(contain_hi=lo),                                        # wholly before a time
+        dict(start_mask=_mask(rng.choice(A, 2, replace=False).tolist(), A)),
+        dict(end_mask=_mask(rng.choice(A, 3, replace=False).tolist(), A),
+             start_mask=_mask(range(A // 2), A)),
+        dict(variant_mask=_mask(top, nv), n_variant_bits=nv, variant_keep=True),
+        dict(variant_mask=_mask(top, nv), n_variant_bits=nv, variant_keep=False),
+        dict(variant_mask=_mask(range(1, nv, 3), nv), n_variant_bits=nv, variant_keep=True,
+             contain_lo=lo),
+        # a set narrower than the ids: the ids at or above n_variant_bits are outside it
+        dict(variant_mask=_mask([0], 1), n_variant_bits=1, variant_keep=False),
+        dict(contain_lo=hi, contain_hi=lo),                         # empty window: nothing kept
+    ]
+    for f in filters:
+        _check_filter(log.case, log.act, log.ts, A, p, case_variant=cv, **f)
+
+
+def test_variant_filter_invalid_arguments():
+    log = synth.config_log(2, 0.002)
+    A = log.n_activities
+    p = _prep(log.case, log.act, log.ts, A)
+    vm = dev(_mask([0], 1).view(np.int64), np.int64)
+    with pytest.raises(pm4g.Pm4gError):
+        pm4g.pm4g_filter_cases(p, variant_mask=vm, n_variant_bits=1)    # no case_variant
+    cv, _ = _case_variant(p)
+    with pytest.raises(pm4g.Pm4gError):
+        pm4g.pm4g_filter_cases(p, variant_mask=vm, case_variant=cv, n_variant_bits=-1)
 
 
 def test_filtered_log_composes_with_dfg_and_variants():
