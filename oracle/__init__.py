@@ -43,7 +43,9 @@ def _load():
                                P, P, P, P, P, P, P, P, P, P, P]
         L.orc_cases.argtypes = [i64, P, P, P, i32, P, P, P, P]
         L.orc_filter_cases.argtypes = [i64, P, P, P, i32, P, P, P, i32, P, P, P, i64, i32, P, P, P, P, P]
-        for f in (L.orc_prepare, L.orc_dfg, L.orc_variants, L.orc_view, L.orc_cases, L.orc_filter_cases):
+        L.orc_filter_df_events.argtypes = [i64, P, P, P, i32, P, i32, i32, P, P, P, P, P]
+        for f in (L.orc_prepare, L.orc_dfg, L.orc_variants, L.orc_view, L.orc_cases, L.orc_filter_cases,
+                  L.orc_filter_df_events):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -216,6 +218,23 @@ def filter_cases(case, act, ts, A: int, min_events: int = 0, max_events: int = I
                                   1 if path_keep else 0, ptr[2], ptr[3], ptr[4], int(n_variant_bits),
                                   1 if variant_keep else 0, _p(out["case_s"]), _p(out["act_s"]),
                                   _p(out["ts_s"]), _p(no), _p(nc))
+    if rc:
+        raise OracleError(rc)
+    k = int(no[0])
+    return {key: v[:k] for key, v in out.items()} | {"n_events": k, "n_cases": int(nc[0])}
+
+
+def filter_df_events(case, act, ts, A: int, path_mask, side: int = 0, keep: bool = True) -> dict:
+    """Events kept by the directly-follows-level filter: side 0 pairs an event
+    with the previous event of its case, side 1 with the next one."""
+    case, act, ts = _cols(case, act, ts)
+    n = case.shape[0]
+    m = max(n, 1)
+    out = dict(case_s=np.empty(m, np.int32), act_s=np.empty(m, np.int32), ts_s=np.empty(m, np.int64))
+    no, nc = np.zeros(1, np.int64), np.zeros(1, np.int64)
+    pm = np.ascontiguousarray(path_mask, dtype=np.uint64)
+    rc = _load().orc_filter_df_events(n, _p(case), _p(act), _p(ts), A, _p(pm), int(side), 1 if keep else 0,
+                                      _p(out["case_s"]), _p(out["act_s"]), _p(out["ts_s"]), _p(no), _p(nc))
     if rc:
         raise OracleError(rc)
     k = int(no[0])

@@ -28,6 +28,9 @@
  *              retained events.
  *   cases      Sec. 3 cases dataframe (events and throughput time per case)
  *              and the case-level filters on it, with paths filtering.
+ *   df events  Sec. 3, "directly-follows level" filtering: events kept or
+ *              dropped by the pair they form with the previous (or next)
+ *              event of their case.
  *
  * Readings where the paper is silent (each is listed in the design notes):
  *   - the row tie-break is the 0-based row index in the caller's arrays;
@@ -46,7 +49,11 @@
  *     combine as a conjunction, bounds inclusive;
  *   - a case is contained in a time window when its first and last events
  *     are inside it, and intersects it when its [first, last] span overlaps
- *     it; start/end filters look at the first/last event of the case.
+ *     it; start/end filters look at the first/last event of the case;
+ *   - the event-level directly-follows filter matches an event on the pair
+ *     with its previous (or next) event in the (case, timestamp, row)
+ *     order; the first (last) event of a case has no such pair and never
+ *     matches.
  *
  * Status codes: 0 ok, -1 invalid argument, -2 activity out of [0, A).
  */
@@ -516,5 +523,58 @@ int orc_filter_cases(int64_t n, const int32_t *case_id, const int32_t *act, cons
     free(ts_s);
     free(off);
     free(cvar);
+    return r;
+}
+
+/*
+ * orc_filter_df_events: filtering at the directly-follows level (Sec. 3: an
+ * event is kept or dropped on its own activity together with that of the
+ * previous, or the next, event of its case).  For each event in the (case,
+ * timestamp, row) order, its partner is the previous event of its case
+ * (side == 0, pair (partner, event)) or the next one (side == 1, pair
+ * (event, partner)).  The event matches iff it has a partner and bit
+ * src*A + dst of path_mask (ceil(A*A/64) words) is set for the pair.  keep
+ * != 0 keeps the matching events, keep == 0 keeps the others (events with no
+ * partner among them).  The kept events are written in that order; n_out
+ * receives their number and n_cases_out the number of distinct cases among
+ * them.
+ */
+int orc_filter_df_events(int64_t n, const int32_t *case_id, const int32_t *act, const int64_t *ts, int32_t A,
+                         const uint64_t *path_mask, int32_t side, int32_t keep, int32_t *case_out,
+                         int32_t *act_out, int64_t *ts_out, int64_t *n_out, int64_t *n_cases_out)
+{
+    if (n < 0 || A < 1 || !path_mask || (side != 0 && side != 1)) return ORC_E_INVALID;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    int32_t *case_s = (int32_t *)malloc(nn * sizeof(int32_t));
+    int32_t *act_s = (int32_t *)malloc(nn * sizeof(int32_t));
+    int64_t *ts_s = (int64_t *)malloc(nn * sizeof(int64_t));
+    int64_t C = 0;
+    int r = orc_prepare(n, case_id, act, ts, A, NULL, case_s, act_s, ts_s, NULL, NULL, &C);
+    int64_t m = 0, kc = 0, last = -1;   /* last: sorted position of the previous kept event */
+    if (r == ORC_OK) {
+        for (int64_t k = 0; k < n; k++) {
+            int match = 0;
+            if (side == 0 && k > 0 && case_s[k - 1] == case_s[k]) {
+                int64_t cell = (int64_t)act_s[k - 1] * A + act_s[k];
+                match = (int)((path_mask[cell / 64] >> (cell % 64)) & 1u);
+            }
+            if (side == 1 && k + 1 < n && case_s[k + 1] == case_s[k]) {
+                int64_t cell = (int64_t)act_s[k] * A + act_s[k + 1];
+                match = (int)((path_mask[cell / 64] >> (cell % 64)) & 1u);
+            }
+            if (keep ? !match : match) continue;
+            if (last < 0 || case_s[last] != case_s[k]) kc++;
+            last = k;
+            if (case_out) case_out[m] = case_s[k];
+            if (act_out) act_out[m] = act_s[k];
+            if (ts_out) ts_out[m] = ts_s[k];
+            m++;
+        }
+    }
+    if (n_out) *n_out = m;
+    if (n_cases_out) *n_cases_out = kc;
+    free(case_s);
+    free(act_s);
+    free(ts_s);
     return r;
 }

@@ -188,3 +188,20 @@ def filter_cases(c, a, t, min_events, max_events, min_thr, max_thr, act_set=None
             n_cases += 1
             kept_events += [(c[i], a[i], t[i]) for i in ev]
     return kept_events, n_cases
+
+
+def filter_df_events(c, a, t, pair_set, side, keep):
+    """Events (case, act, ts) kept by the directly-follows-level filter, in
+    (case, timestamp, row) order: an event matches when it is the target
+    (side 0) or the source (side 1) of a directly-follows pair whose
+    activities are in pair_set."""
+    matched = set()
+    for i, j in directly_follows_pairs(c, t):
+        if (a[i], a[j]) in pair_set:
+            matched.add(j if side == 0 else i)
+    kept = []
+    for code, members in sorted(_by_case(c).items()):
+        for i in ordered_members(c, t, members):
+            if (i in matched) == bool(keep):
+                kept.append((c[i], a[i], t[i]))
+    return kept, len({e[0] for e in kept})

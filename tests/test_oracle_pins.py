@@ -606,3 +606,58 @@ def test_cases_invariants_on_workload():
     before = oracle.filter_cases(log.case, log.act, log.ts, A, contain_hi=lo - 1)
     after = oracle.filter_cases(log.case, log.act, log.ts, A, contain_lo=hi + 1)
     assert m["n_cases"] + before["n_cases"] + after["n_cases"] == o["n_cases"]
+
+
+# ---- directly-follows-level event filter ---------------------------------------
+
+def _pairs_of(spec, A):
+    return [(x, y) for x in range(A) for y in range(A)] if spec == "all" else [tuple(p) for p in spec]
+
+
+def test_df_events_golden():
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_road_fines.json")))
+    r, A = g["rows"], g["A"]
+    for f in g["df_events"]["filters"]:
+        pm = _mask([x * A + y for x, y in _pairs_of(f["pairs"], A)], A * A)
+        o = oracle.filter_df_events(r["case"], r["act"], r["ts"], A, pm, f["side"], f["keep"])
+        got = list(zip(o["case_s"].tolist(), o["act_s"].tolist(), o["ts_s"].tolist()))
+        assert got == [tuple(e) for e in f["events"]], f["name"]
+        assert o["n_cases"] == f["n_cases"], f["name"]
+
+
+@settings(max_examples=250, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(tiny_logs(), st.data())
+def test_df_events_match_bruteforce(log, data):
+    case, act, ts, A = log
+    pairs = data.draw(st.sets(st.tuples(st.integers(0, A - 1), st.integers(0, A - 1))))
+    side = data.draw(st.sampled_from([0, 1]))
+    keep = data.draw(st.booleans())
+    o = oracle.filter_df_events(case, act, ts, A, _mask([x * A + y for x, y in pairs], A * A), side, keep)
+    ev, nc = bf.filter_df_events(case, act, ts, pairs, side, keep)
+    got = list(zip(o["case_s"].tolist(), o["act_s"].tolist(), o["ts_s"].tolist()))
+    assert got == ev
+    assert o["n_events"] == len(ev) and o["n_cases"] == nc
+
+
+def test_df_events_invariants_on_workload():
+    log = synth.config_log(2, 0.01)
+    A = log.n_activities
+    d = oracle.dfg(log.case, log.act, log.ts, A)
+    rng = np.random.default_rng(7)
+    cells = rng.choice(A * A, A, replace=False)
+    pm = _mask(cells, A * A)
+    # the events matched on either side number the DFG counts of the chosen cells
+    expect = int(d["count"].reshape(-1)[cells].sum())
+    for side in (0, 1):
+        k = oracle.filter_df_events(log.case, log.act, log.ts, A, pm, side, True)
+        dr = oracle.filter_df_events(log.case, log.act, log.ts, A, pm, side, False)
+        assert k["n_events"] == expect
+        assert k["n_events"] + dr["n_events"] == log.n_events
+    # with every pair chosen, side 0 drops all but each case's first event and side 1
+    # all but its last: the start and end activity counts
+    allp = _mask(range(A * A), A * A)
+    first = oracle.filter_df_events(log.case, log.act, log.ts, A, allp, 0, False)
+    last = oracle.filter_df_events(log.case, log.act, log.ts, A, allp, 1, False)
+    assert np.array_equal(np.bincount(first["act_s"], minlength=A), d["start_count"])
+    assert np.array_equal(np.bincount(last["act_s"], minlength=A), d["end_count"])
+    assert first["n_cases"] == last["n_cases"] == d["n_cases"]
