@@ -211,7 +211,8 @@ def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int, autot
 
 
 def bench_cases(log, prep, steps: int = 5) -> dict:
-    """Cases dataframe and case-level filters on the prepared log (whole-log calls)."""
+    """Cases dataframe, case-level and directly-follows-level filters on the
+    prepared log (whole-log calls)."""
     import numpy as np
     import torch
 
@@ -245,7 +246,10 @@ def bench_cases(log, prep, steps: int = 5) -> dict:
                                                                                     contain_hi=t_hi, out=out)),
                        ("filter_top10_variants", lambda: pm4g.pm4g_filter_cases(
                            prep, case_variant=vo["case_variant"], variant_mask=vmd, n_variant_bits=nv,
-                           variant_keep=True, out=out))):
+                           variant_keep=True, out=out)),
+                       ("df_events_keep_prev_pairs", lambda: pm4g.pm4g_filter_df_events(prep, pmd, 0, True, out=out)),
+                       ("df_events_drop_prev_pairs", lambda: pm4g.pm4g_filter_df_events(prep, pmd, 0, False,
+                                                                                       out=out))):
         call()
         torch.cuda.synchronize()
         t0 = time.perf_counter()

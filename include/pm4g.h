@@ -303,6 +303,27 @@ int pm4g_filter_view(const pm4g_prepared *log, const pm4g_view *view, const uint
                      const pm4g_prepared *out, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Filter at the directly-follows level (Sec. 3: events kept or dropped on
+ * their activity and that of the previous, or next, event of their case;
+ * the paper's example keeps the Insert Fine Notification events whose
+ * previous event is Send Fine).  In the log's (case, timestamp, row) order,
+ * an event's partner is the previous event of its case (side = 0, pair
+ * (partner, event)) or the next one (side = 1, pair (event, partner)); the
+ * event matches iff it has a partner and bit src*A + dst of pair_mask
+ * (device, ceil(A*A/64) words) is set.  keep = 1 keeps the matching events,
+ * keep = 0 the others (events without a partner among them).  The kept
+ * events form a prepared log in out (same order, a case table over the
+ * cases that keep at least one event); the DFG of out pairs each kept event
+ * with the previous kept event of its case.  out->n_events is the capacity:
+ * if the kept events exceed it, nothing is written, the output log is empty
+ * and out->status is PM4G_E_CAPACITY.  side and keep are 0 or 1, else
+ * PM4G_E_INVALID.  Workspace: pm4g_filter_workspace_bytes(log->n_events).
+ * Does not synchronise.
+ */
+int pm4g_filter_df_events(const pm4g_prepared *log, const uint64_t *pair_mask, int32_t side, int32_t keep,
+                          const pm4g_prepared *out, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * Cases dataframe (Sec. 3: one row per case with its number of events and its
  * throughput time, the cases-dataframe module).  For the j-th case of a
  * prepared log (its case-table order: ascending case id), n_events_out[j] is

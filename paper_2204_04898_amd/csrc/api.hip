@@ -367,6 +367,28 @@ int pm4g_filter_view(const pm4g_prepared* log, const pm4g_view* view, const uint
     return PM4G_OK;
 }
 
+int pm4g_filter_df_events(const pm4g_prepared* log, const uint64_t* pair_mask, int32_t side, int32_t keep,
+                          const pm4g_prepared* out, void* ws, size_t ws_size, void* stream) {
+    if (int rc = check_prepared(log, true)) return rc;
+    PM4G_CHECK(pair_mask != nullptr, "pair_mask is NULL");
+    PM4G_CHECK(side == 0 || side == 1, "side must be 0 (previous event) or 1 (next event)");
+    PM4G_CHECK(keep == 0 || keep == 1, "keep must be 0 or 1");
+    PM4G_CHECK(out && out->case_off && out->n_cases && out->status &&
+                   (log->n_events == 0 || (out->case_s && out->act_s && out->ts_s && out->case_code)),
+               "a filtered-log output array is NULL");
+    PM4G_CHECK(out->n_events >= 0 && out->n_activities == log->n_activities,
+               "the filtered log needs a capacity >= 0 and the same n_activities");
+    const size_t need = pm4g_filter_workspace_bytes(log->n_events);
+    if (ws_size < need || !ws) {
+        set_err("workspace of %zu bytes, %zu needed", ws_size, need);
+        return PM4G_E_WORKSPACE;
+    }
+    Bump bp(ws);
+    FilterWs w = filter_ws_layout(bp, log->n_events);
+    PM4G_HIP(launch_filter_df_events(log, pair_mask, side, keep, out, w, (hipStream_t)stream));
+    return PM4G_OK;
+}
+
 int pm4g_cases(const pm4g_prepared* log, int64_t* n_events_out, int64_t* throughput_out, void* stream) {
     if (int rc = check_prepared(log, true)) return rc;
     PM4G_HIP(launch_cases_df(log, n_events_out, throughput_out, (hipStream_t)stream));

@@ -267,6 +267,8 @@ struct FilterWs {
 FilterWs filter_ws_layout(Bump& b, int64_t n);
 hipError_t launch_filter_view(const pm4g_prepared* p, const pm4g_view* view, const uint64_t* mask,
                               const pm4g_prepared* out, FilterWs w, hipStream_t s);
+hipError_t launch_filter_df_events(const pm4g_prepared* p, const uint64_t* pairs, int32_t side, int32_t keep,
+                                   const pm4g_prepared* out, FilterWs w, hipStream_t s);
 
 // Cases dataframe and case-level filters (casefilter.hip).
 struct CaseFilterWs {

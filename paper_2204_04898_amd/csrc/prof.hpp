@@ -33,6 +33,7 @@ enum ProfId {
     P_VIEW_WRITE,
     P_CASES,
     P_CASE_FILTER,
+    P_DF_FILTER,
     P_COUNT
 };
 

@@ -129,6 +129,9 @@ def load():
             L.pm4g_filter_view.argtypes = [ctypes.POINTER(_Prepared), _P, _P, ctypes.POINTER(_Prepared), _P,
                                            ctypes.c_size_t, _P]
             L.pm4g_filter_view.restype = ctypes.c_int
+            L.pm4g_filter_df_events.argtypes = [ctypes.POINTER(_Prepared), _P, ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.POINTER(_Prepared), _P, ctypes.c_size_t, _P]
+            L.pm4g_filter_df_events.restype = ctypes.c_int
             L.pm4g_cases.argtypes = [ctypes.POINTER(_Prepared), _P, _P, _P]
             L.pm4g_cases.restype = ctypes.c_int
             L.pm4g_filter_cases_workspace_bytes.argtypes = [ctypes.c_int64]
@@ -436,6 +439,26 @@ def pm4g_filter_view(prep: Prepared, view: torch.Tensor, mask: torch.Tensor, out
     q = o._struct()
     _check(L.pm4g_filter_view(ctypes.byref(p), _ptr(view), _ptr(mask), ctypes.byref(q), _ptr(ws), need,
                               _stream(stream)))
+    return o
+
+
+def pm4g_filter_df_events(prep: Prepared, pair_mask: torch.Tensor, side: int = 0, keep: bool = True,
+                          out: Prepared | None = None, ws: torch.Tensor | None = None, stream=None) -> Prepared:
+    """Events kept by the directly-follows-level filter, as a prepared log.
+
+    pair_mask: device int64 tensor of ceil(A*A/64) words, bit src*A + dst;
+    side 0 pairs an event with the previous event of its case, side 1 with the
+    next one.  Asynchronous; the kept count is out.case_off[out.n_cases]."""
+    L = load()
+    dev = prep.case_s.device
+    o = out if out is not None else Prepared.empty(prep.n_events, prep.n_activities, dev)
+    need = int(L.pm4g_filter_workspace_bytes(prep.n_events))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    p = prep._struct()
+    q = o._struct()
+    _check(L.pm4g_filter_df_events(ctypes.byref(p), _ptr(pair_mask), int(side), 1 if keep else 0,
+                                   ctypes.byref(q), _ptr(ws), need, _stream(stream)))
     return o
 
 
