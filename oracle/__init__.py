@@ -44,8 +44,9 @@ def _load():
         L.orc_cases.argtypes = [i64, P, P, P, i32, P, P, P, P]
         L.orc_filter_cases.argtypes = [i64, P, P, P, i32, P, P, P, i32, P, P, P, i64, i32, P, P, P, P, P]
         L.orc_filter_df_events.argtypes = [i64, P, P, P, i32, P, i32, i32, P, P, P, P, P]
+        L.orc_efg.argtypes = [i64, P, P, P, i32, P, P, P, P, P, P, P, P]
         for f in (L.orc_prepare, L.orc_dfg, L.orc_variants, L.orc_view, L.orc_cases, L.orc_filter_cases,
-                  L.orc_filter_df_events):
+                  L.orc_filter_df_events, L.orc_efg):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -239,3 +240,23 @@ def filter_df_events(case, act, ts, A: int, path_mask, side: int = 0, keep: bool
         raise OracleError(rc)
     k = int(no[0])
     return {key: v[:k] for key, v in out.items()} | {"n_events": k, "n_cases": int(nc[0])}
+
+
+def efg(case, act, ts, A: int) -> dict:
+    """Eventually-follows graph and temporal profile, [A, A] arrays: count,
+    the exact 128-bit gap sum and squared-gap sum as (lo, hi) uint64 words,
+    mean and sample std (FP64); n_pairs."""
+    case, act, ts = _cols(case, act, ts)
+    n = case.shape[0]
+    cells = A * A
+    out = dict(count=np.empty(cells, np.int64), sum_lo=np.empty(cells, np.uint64), sum_hi=np.empty(cells, np.uint64),
+               sq_lo=np.empty(cells, np.uint64), sq_hi=np.empty(cells, np.uint64), mean=np.empty(cells, np.float64),
+               std=np.empty(cells, np.float64))
+    npairs = np.zeros(1, np.int64)
+    rc = _load().orc_efg(n, _p(case), _p(act), _p(ts), A, _p(out["count"]), _p(out["sum_lo"]), _p(out["sum_hi"]),
+                         _p(out["sq_lo"]), _p(out["sq_hi"]), _p(out["mean"]), _p(out["std"]), _p(npairs))
+    if rc:
+        raise OracleError(rc)
+    out = {k: v.reshape(A, A) for k, v in out.items()}
+    out["n_pairs"] = int(npairs[0])
+    return out

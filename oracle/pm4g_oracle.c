@@ -31,6 +31,8 @@
  *   df events  Sec. 3, "directly-follows level" filtering: events kept or
  *              dropped by the pair they form with the previous (or next)
  *              event of their case.
+ *   EFG        Sec. 3, eventually-follows graph and temporal profile: every
+ *              ordered pair of events of a case, with its gap statistics.
  *
  * Readings where the paper is silent (each is listed in the design notes):
  *   - the row tie-break is the 0-based row index in the caller's arrays;
@@ -53,7 +55,11 @@
  *   - the event-level directly-follows filter matches an event on the pair
  *     with its previous (or next) event in the (case, timestamp, row)
  *     order; the first (last) event of a case has no such pair and never
- *     matches.
+ *     matches;
+ *   - the eventually-follows pairs of a case are all (i, j) with i before j
+ *     in that order; the temporal profile of a pair of activities is the
+ *     mean and the sample standard deviation of their gaps, from exact
+ *     integer sums (see orc_efg).
  *
  * Status codes: 0 ok, -1 invalid argument, -2 activity out of [0, A).
  */
@@ -576,5 +582,136 @@ int orc_filter_df_events(int64_t n, const int32_t *case_id, const int32_t *act, 
     free(case_s);
     free(act_s);
     free(ts_s);
+    return r;
+}
+
+/* ---- eventually-follows graph and temporal profile ----------------------- */
+
+typedef unsigned __int128 orc_u128;
+
+/* A 256-bit unsigned integer as four 64-bit limbs, least significant first. */
+typedef struct {
+    uint64_t w[4];
+} orc_u256;
+
+static orc_u256 u256_mul_128_128(orc_u128 a, orc_u128 b)
+{
+    /* schoolbook product of the two 64-bit halves */
+    uint64_t a0 = (uint64_t)a, a1 = (uint64_t)(a >> 64), b0 = (uint64_t)b, b1 = (uint64_t)(b >> 64);
+    orc_u128 p00 = (orc_u128)a0 * b0, p01 = (orc_u128)a0 * b1, p10 = (orc_u128)a1 * b0, p11 = (orc_u128)a1 * b1;
+    orc_u256 r;
+    orc_u128 mid = (p00 >> 64) + (uint64_t)p01 + (uint64_t)p10;
+    r.w[0] = (uint64_t)p00;
+    r.w[1] = (uint64_t)mid;
+    orc_u128 hi = (mid >> 64) + (p01 >> 64) + (p10 >> 64) + (uint64_t)p11;
+    r.w[2] = (uint64_t)hi;
+    r.w[3] = (uint64_t)((hi >> 64) + (p11 >> 64));
+    return r;
+}
+
+static orc_u256 u256_sub(orc_u256 a, orc_u256 b)
+{
+    orc_u256 r;
+    uint64_t borrow = 0;
+    for (int k = 0; k < 4; k++) {
+        orc_u128 d = (orc_u128)a.w[k] - b.w[k] - borrow;
+        r.w[k] = (uint64_t)d;
+        borrow = (uint64_t)(d >> 64) ? 1 : 0;
+    }
+    return r;
+}
+
+/* Fixed rounding sequence: Horner over the limbs, most significant first. */
+static double u256_to_double(orc_u256 a)
+{
+    const double two64 = 18446744073709551616.0;
+    double x = (double)a.w[3];
+    x = x * two64 + (double)a.w[2];
+    x = x * two64 + (double)a.w[1];
+    x = x * two64 + (double)a.w[0];
+    return x;
+}
+
+static double u128_to_double(orc_u128 a)
+{
+    const double two64 = 18446744073709551616.0;
+    return (double)(uint64_t)(a >> 64) * two64 + (double)(uint64_t)a;
+}
+
+/*
+ * orc_efg: eventually-follows graph and temporal profile (Sec. 3, EFG /
+ * temporal-profile module; the paper names them without a definition).  For
+ * every case and every two of its events i, j with i before j in the (case,
+ * timestamp, row) order, cell a_i*A + a_j counts the pair and accumulates the
+ * gap d = t_j - t_i (>= 0 in that order, taken as an exact unsigned 64-bit
+ * value).  Per cell:
+ *   count             number of pairs;
+ *   sum_lo, sum_hi    the exact sum of the gaps as a 128-bit integer;
+ *   sq_lo, sq_hi      the sum of the squared gaps modulo 2^128 (exact below);
+ *   mean              S / n in FP64, S converted as hi * 2^64 + lo; NaN when
+ *                     the cell is empty;
+ *   std               sample standard deviation sqrt(D / n / (n - 1)) with
+ *                     D = n*Q - S*S evaluated exactly in 256 bits and
+ *                     converted by the fixed sequence above; 0 for one pair,
+ *                     NaN for none.
+ * mean and std may be NULL.  n_pairs receives the total number of pairs.
+ */
+int orc_efg(int64_t n, const int32_t *case_id, const int32_t *act, const int64_t *ts, int32_t A,
+            int64_t *count, uint64_t *sum_lo, uint64_t *sum_hi, uint64_t *sq_lo, uint64_t *sq_hi,
+            double *mean, double *std_out, int64_t *n_pairs)
+{
+    if (n < 0 || A < 1 || !count || !sum_lo || !sum_hi || !sq_lo || !sq_hi) return ORC_E_INVALID;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    size_t cells = (size_t)A * (size_t)A;
+    int32_t *case_s = (int32_t *)malloc(nn * sizeof(int32_t));
+    int32_t *act_s = (int32_t *)malloc(nn * sizeof(int32_t));
+    int64_t *ts_s = (int64_t *)malloc(nn * sizeof(int64_t));
+    int64_t *off = (int64_t *)malloc((nn + 1) * sizeof(int64_t));
+    orc_u128 *S = (orc_u128 *)calloc(cells, sizeof(orc_u128));
+    orc_u128 *Q = (orc_u128 *)calloc(cells, sizeof(orc_u128));
+    int64_t C = 0, pairs = 0;
+    int r = orc_prepare(n, case_id, act, ts, A, NULL, case_s, act_s, ts_s, off, NULL, &C);
+    for (size_t k = 0; k < cells; k++) count[k] = 0;
+    if (r == ORC_OK) {
+        for (int64_t c = 0; c < C; c++) {
+            for (int64_t i = off[c]; i < off[c + 1]; i++) {
+                for (int64_t j = i + 1; j < off[c + 1]; j++) {
+                    size_t cell = (size_t)act_s[i] * (size_t)A + (size_t)act_s[j];
+                    uint64_t d = (uint64_t)ts_s[j] - (uint64_t)ts_s[i];
+                    count[cell] += 1;
+                    S[cell] += d;
+                    Q[cell] += (orc_u128)d * d;
+                    pairs++;
+                }
+            }
+        }
+    }
+    for (size_t k = 0; k < cells; k++) {
+        sum_lo[k] = (uint64_t)S[k];
+        sum_hi[k] = (uint64_t)(S[k] >> 64);
+        sq_lo[k] = (uint64_t)Q[k];
+        sq_hi[k] = (uint64_t)(Q[k] >> 64);
+        int64_t m = count[k];
+        if (mean) mean[k] = m > 0 ? u128_to_double(S[k]) / (double)m : NAN;
+        if (std_out) {
+            if (m == 0) {
+                std_out[k] = NAN;
+            } else if (m == 1) {
+                std_out[k] = 0.0;
+            } else {
+                orc_u256 nq = u256_mul_128_128((orc_u128)(uint64_t)m, Q[k]);
+                orc_u256 ss = u256_mul_128_128(S[k], S[k]);
+                double D = u256_to_double(u256_sub(nq, ss));
+                std_out[k] = sqrt(D / (double)m / (double)(m - 1));
+            }
+        }
+    }
+    if (n_pairs) *n_pairs = pairs;
+    free(case_s);
+    free(act_s);
+    free(ts_s);
+    free(off);
+    free(S);
+    free(Q);
     return r;
 }

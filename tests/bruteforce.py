@@ -205,3 +205,23 @@ def filter_df_events(c, a, t, pair_set, side, keep):
             if (i in matched) == bool(keep):
                 kept.append((c[i], a[i], t[i]))
     return kept, len({e[0] for e in kept})
+
+
+def efg(c, a, t, A):
+    """Eventually-follows pairs by enumeration with Python integers: per cell
+    the count, the exact gap sum S and squared-gap sum Q; n_pairs."""
+    count = [[0] * A for _ in range(A)]
+    S = [[0] * A for _ in range(A)]
+    Q = [[0] * A for _ in range(A)]
+    pairs = 0
+    for code, members in _by_case(c).items():
+        ev = ordered_members(c, t, members)
+        for x in range(len(ev)):
+            for y in range(x + 1, len(ev)):
+                i, j = ev[x], ev[y]
+                d = t[j] - t[i]
+                count[a[i]][a[j]] += 1
+                S[a[i]][a[j]] += d
+                Q[a[i]][a[j]] += d * d
+                pairs += 1
+    return dict(count=count, S=S, Q=Q, n_pairs=pairs)

@@ -661,3 +661,121 @@ def test_df_events_invariants_on_workload():
     assert np.array_equal(np.bincount(first["act_s"], minlength=A), d["start_count"])
     assert np.array_equal(np.bincount(last["act_s"], minlength=A), d["end_count"])
     assert first["n_cases"] == last["n_cases"] == d["n_cases"]
+
+
+# ---- eventually-follows graph and temporal profile -----------------------------
+
+def _u128(lo, hi):
+    return int(lo) + (int(hi) << 64)
+
+
+def _efg_exact_stats(n, S, Q):
+    """Mean and sample std of a cell from its exact sums, by exact rationals."""
+    from fractions import Fraction
+    if n == 0:
+        return math.nan, math.nan
+    mean = float(Fraction(S, n))
+    if n == 1:
+        return mean, 0.0
+    return mean, math.sqrt(float(Fraction(n * Q - S * S, n * (n - 1))))
+
+
+def _check_efg_stats(o, n, S, Q, x, y):
+    em, es = _efg_exact_stats(n, S, Q)
+    m, sd = float(o["mean"][x, y]), float(o["std"][x, y])
+    if n == 0:
+        assert math.isnan(m) and math.isnan(sd)
+        return
+    assert math.isclose(m, em, rel_tol=1e-15, abs_tol=0.0), (x, y, m, em)
+    assert math.isclose(sd, es, rel_tol=1e-13, abs_tol=1e-300), (x, y, sd, es)
+
+
+def test_efg_golden():
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_road_fines.json")))
+    r, A, e = g["rows"], g["A"], g["efg"]
+    o = oracle.efg(r["case"], r["act"], r["ts"], A)
+    assert o["n_pairs"] == e["n_pairs"]
+    want = {(x, y): (n, s, q) for x, y, n, s, q in e["cells"]}
+    for x in range(A):
+        for y in range(A):
+            n, s, q = want.get((x, y), (0, 0, 0))
+            assert int(o["count"][x, y]) == n, (x, y)
+            assert _u128(o["sum_lo"][x, y], o["sum_hi"][x, y]) == s, (x, y)
+            assert _u128(o["sq_lo"][x, y], o["sq_hi"][x, y]) == q, (x, y)
+            _check_efg_stats(o, n, s, q, x, y)
+    cf = e["create_fine_to_payment"]
+    assert math.isclose(o["mean"][0, 4], cf["mean"], rel_tol=1e-15)
+    assert math.isclose(o["std"][0, 4], cf["std"], rel_tol=1e-15)
+
+
+@settings(max_examples=250, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(tiny_logs())
+def test_efg_match_bruteforce(log):
+    case, act, ts, A = log
+    o = oracle.efg(case, act, ts, A)
+    b = bf.efg(case, act, ts, A)
+    assert o["n_pairs"] == b["n_pairs"]
+    for x in range(A):
+        for y in range(A):
+            n, S, Q = b["count"][x][y], b["S"][x][y], b["Q"][x][y]
+            assert int(o["count"][x, y]) == n
+            assert _u128(o["sum_lo"][x, y], o["sum_hi"][x, y]) == S
+            assert _u128(o["sq_lo"][x, y], o["sq_hi"][x, y]) == Q % 2**128     # kept modulo 2^128
+            if Q < 2**128:
+                _check_efg_stats(o, n, S, Q, x, y)
+
+
+@pytest.mark.parametrize("L,k", [(2, 1), (7, 3), (40, 1000), (200, 10**9)])
+def test_efg_closed_form_one_activity(L, k):
+    """One case of L events of one activity at 0, k, 2k, ...: the gap g*k occurs
+    L - g times, so n = L(L-1)/2, S = k L(L^2-1)/6, Q = k^2 L^2(L^2-1)/12 and
+    the mean is k(L+1)/3."""
+    o = oracle.efg([5] * L, [0] * L, [k * i for i in range(L)], 1)
+    n, S, Q = L * (L - 1) // 2, k * L * (L * L - 1) // 6, k * k * L * L * (L * L - 1) // 12
+    assert int(o["count"][0, 0]) == n and o["n_pairs"] == n
+    assert _u128(o["sum_lo"][0, 0], o["sum_hi"][0, 0]) == S
+    assert _u128(o["sq_lo"][0, 0], o["sq_hi"][0, 0]) == Q
+    assert math.isclose(o["mean"][0, 0], k * (L + 1) / 3, rel_tol=1e-15)
+    _check_efg_stats(o, n, S, Q, 0, 0)
+
+
+def test_efg_wide_gaps_carry_into_high_words():
+    # gaps near 2^62: the gap sum passes 2^64 and every square needs 128 bits
+    t = [-(2**62), 0, 2**62 - 1, 2**62]
+    o = oracle.efg([1] * 4, [0, 0, 0, 0], t, 1)
+    gaps = [t[j] - t[i] for i in range(4) for j in range(i + 1, 4)]
+    assert _u128(o["sum_lo"][0, 0], o["sum_hi"][0, 0]) == sum(gaps) > 2**64
+    assert _u128(o["sq_lo"][0, 0], o["sq_hi"][0, 0]) == sum(d * d for d in gaps)
+    _check_efg_stats(o, 6, sum(gaps), sum(d * d for d in gaps), 0, 0)
+
+
+def test_efg_invariants_on_workload():
+    log = synth.config_log(2, 0.005)
+    A = log.n_activities
+    o = oracle.efg(log.case, log.act, log.ts, A)
+    d = oracle.dfg(log.case, log.act, log.ts, A)
+    L = log.lengths_by_code.astype(np.int64)
+    assert o["n_pairs"] == int(o["count"].sum()) == int((L * (L - 1) // 2).sum())
+    assert (o["count"] >= d["count"]).all()               # every directly-follows pair is one
+    # cases of exactly two events: the EFG is their DFG
+    codes = np.flatnonzero(L == 2)
+    keep = np.isin(log.case, codes)
+    two = oracle.efg(log.case[keep], log.act[keep], log.ts[keep], A)
+    d2 = oracle.dfg(log.case[keep], log.act[keep], log.ts[keep], A)
+    assert np.array_equal(two["count"], d2["count"])
+    assert np.array_equal(two["sum_lo"].view(np.int64), d2["dt_sum"])
+    # replicating every case (new case ids) doubles the counts and sums, keeps the mean,
+    # and scales the sample variance by 2(n-1)/(2n-1)
+    off = int(log.case.max()) + 1
+    rc = np.concatenate([log.case, log.case + off])
+    ra, rt = np.concatenate([log.act, log.act]), np.concatenate([log.ts, log.ts])
+    o2 = oracle.efg(rc, ra, rt, A)
+    assert np.array_equal(o2["count"], 2 * o["count"])
+    S1 = [_u128(a, b) for a, b in zip(o["sum_lo"].ravel(), o["sum_hi"].ravel())]
+    S2 = [_u128(a, b) for a, b in zip(o2["sum_lo"].ravel(), o2["sum_hi"].ravel())]
+    assert S2 == [2 * x for x in S1]
+    nz = o["count"] > 0
+    assert np.allclose(o2["mean"][nz], o["mean"][nz], rtol=1e-15, atol=0)
+    m = o["count"] > 1
+    n = o["count"][m].astype(np.float64)
+    assert np.allclose(o2["std"][m] ** 2 * (2 * n - 1), o["std"][m] ** 2 * 2 * (n - 1), rtol=1e-12, atol=0)
