@@ -266,6 +266,40 @@ def bench_cases(log, prep, steps: int = 5) -> dict:
     return res
 
 
+def bench_efg(log, prep, steps: int = 3, oracle_events: int = 1_000_000) -> dict:
+    """Eventually-follows graph and temporal profile of a prepared log (whole-log
+    calls), with the oracle timed on the cases of a bounded sample beside it."""
+    import numpy as np
+    import torch
+
+    from paper_2204_04898_amd import pm4g
+
+    o = pm4g.pm4g_efg(prep)
+    torch.cuda.synchronize()
+    ws = torch.empty(int(pm4g.load().pm4g_efg_workspace_bytes(prep.n_events, prep.n_activities)),
+                     dtype=torch.uint8, device=prep.case_s.device)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pm4g.pm4g_efg(prep, out=o, ws=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    pairs = int(o["n_pairs"].item())
+    res = {"ms_per_call": dt * 1e3, "pairs": pairs, "pairs_per_s": pairs / dt, "events_per_s": prep.n_events / dt,
+           "n_activities": prep.n_activities}
+    import oracle
+
+    cum = np.cumsum(log.lengths_by_code)
+    cut = min(int(np.searchsorted(cum, oracle_events, side="left")) + 1, int(cum.shape[0]))
+    keep = log.case < cut
+    t1 = time.perf_counter()
+    ob = oracle.efg(log.case[keep], log.act[keep], log.ts[keep], log.n_activities)
+    odt = time.perf_counter() - t1
+    res["cpu_oracle"] = {"pairs_per_s": ob["n_pairs"] / odt, "cores": 1,
+                         "sample": f"the {cut} cases with the lowest codes ({int(keep.sum())} events, "
+                                   f"{ob['n_pairs']} pairs), single thread, {odt:.2f} s"}
+    return res
+
+
 def bench_serving(logs: dict, preps: dict, seconds: float, rate: float, workers: int = 4,
                   batch_work: int = 20_000_000) -> dict:
     """Open-loop Poisson mix of DFG / variants / filter queries on resident logs."""
@@ -380,6 +414,7 @@ def main() -> int:
     ap.add_argument("--no-autotune", action="store_true", help="batched views with the library's default shape")
     ap.add_argument("--tune-cache", default=None, help="autotune cache file (default: the package's)")
     ap.add_argument("--no-cases", action="store_true", help="skip the cases-dataframe and case-filter timing")
+    ap.add_argument("--no-efg", action="store_true", help="skip the eventually-follows graph timing")
     ap.add_argument("--serve-seconds", type=float, default=8.0, help="serving run length (0: skip)")
     ap.add_argument("--serve-qps", type=float, default=200.0)
     ap.add_argument("--serve-workers", type=int, default=4, help="batches in flight (HIP streams)")
@@ -484,11 +519,19 @@ def main() -> int:
     if k == 3 and not args.no_cases:
         log_progress("cases dataframe and case filters")
         out["cases"] = bench_cases(log, prep)
-    if args.serve_seconds > 0 and k == 3:
-        log_progress("serving: generating the 10M-event log")
+    if k == 3 and not args.no_efg:
+        log_progress("eventually-follows graph and temporal profile")
+        out["efg"] = {args.workload: bench_efg(log, prep)}
+    log2 = prep2 = None
+    if k == 3 and (args.serve_seconds > 0 or not args.no_efg):
+        log_progress("generating the 10M-event log")
         log2 = synth.config_log(2)
         c2, a2, t2 = (torch.from_numpy(x).to(dev) for x in (log2.case, log2.act, log2.ts))
         prep2 = pm4g.pm4g_prepare(c2, a2, t2, log2.n_activities)
+    if k == 3 and not args.no_efg:
+        log_progress("eventually-follows graph of the 10M-event log")
+        out["efg"]["dfg-perf-10M"] = bench_efg(log2, prep2)
+    if args.serve_seconds > 0 and k == 3:
         log_progress(f"serving: {args.serve_seconds} s at {args.serve_qps} queries/s")
         out["serving"] = bench_serving({"dfg-perf-10M": log2, args.workload: log},
                                        {"dfg-perf-10M": prep2, args.workload: prep},

@@ -393,6 +393,45 @@ size_t pm4g_filter_cases_workspace_bytes(int64_t n_events);
 int pm4g_filter_cases(const pm4g_prepared *log, const pm4g_case_filter *filter, const pm4g_prepared *out,
                       void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * Eventually-follows graph and temporal profile (Sec. 3: the EFG /
+ * temporal-profile module, named there without a definition).  For every case
+ * and every two of its events i, j with i before j in the (case, timestamp,
+ * row) order, cell a_i*A + a_j of the [A*A] device arrays counts the pair and
+ * accumulates its gap d = t_j - t_i (an exact unsigned 64-bit value, >= 0 in
+ * that order):
+ *   count                 number of pairs (the eventually-follows graph);
+ *   sum_lo, sum_hi        the exact sum of the gaps, 128-bit (lo, hi words);
+ *   sq_lo, sq_hi          the sum of the squared gaps modulo 2^128;
+ *   mean (may be NULL)    S / n in FP64 with S converted as hi * 2^64 + lo,
+ *                         NaN for an empty cell;
+ *   std (may be NULL)     sample standard deviation sqrt(D / n / (n - 1)),
+ *                         D = n*Q - S*S evaluated exactly in 256 bits and
+ *                         converted to FP64 limb by limb, most significant
+ *                         first (x = x * 2^64 + limb); 0 for one pair, NaN
+ *                         for none (the temporal profile is (mean, std));
+ *   n_pairs               device int64[1]: all pairs, sum of L(L-1)/2;
+ *   status                device int32[1]: the input log's status, else 0.
+ * mean and std are meaningful while the square sums stay below 2^128.
+ * Requires n_activities <= PM4G_EFG_MAX_ACTIVITIES.  The work grows with the
+ * number of pairs, not of events.  Does not synchronise.
+ */
+#define PM4G_EFG_MAX_ACTIVITIES 4096
+typedef struct {
+    int64_t *count;
+    uint64_t *sum_lo;
+    uint64_t *sum_hi;
+    uint64_t *sq_lo;
+    uint64_t *sq_hi;
+    double *mean;
+    double *std;
+    int64_t *n_pairs;
+    int32_t *status;
+} pm4g_efg_out;
+
+size_t pm4g_efg_workspace_bytes(int64_t n_events, int32_t n_activities);
+int pm4g_efg(const pm4g_prepared *log, const pm4g_efg_out *out, void *ws, size_t ws_bytes, void *stream);
+
 /* Text for a status code (static storage). */
 const char *pm4g_status_string(int code);
 
@@ -407,6 +446,16 @@ const char *pm4g_last_error(void);
  * depend on it.  Returns the previous setting.
  */
 int pm4g_debug_variant_hash_bits(int bits);
+
+/*
+ * Test hook for the eventually-follows aggregation: the calling thread's later
+ * pm4g_efg calls sum at most `pairs` pairs per pass of a block's LDS table
+ * before adding the table into the block's partial slot (0: the full 2^31,
+ * which keeps the table's 32-bit counters exact).  Small values exercise the
+ * multi-pass accumulation on small logs; results do not depend on it.
+ * Returns the previous setting.
+ */
+int64_t pm4g_debug_efg_pass_pairs(int64_t pairs);
 
 /*
  * Stage timing for measurement: while enabled (process-wide), every stage of

@@ -14,6 +14,7 @@ namespace {
 
 thread_local char g_err[512] = "";
 thread_local int g_variant_hash_bits = 0;   // test hook, 0 = full 64-bit hash
+thread_local int64_t g_efg_pass_pairs = 0;  // test hook, 0 = the EFG's full LDS pass length
 
 void set_err(const char* fmt, ...) {
     va_list ap;
@@ -311,6 +312,12 @@ int pm4g_debug_variant_hash_bits(int bits) {
     return old;
 }
 
+int64_t pm4g_debug_efg_pass_pairs(int64_t pairs) {
+    const int64_t old = g_efg_pass_pairs;
+    g_efg_pass_pairs = pairs > 0 ? pairs : 0;
+    return old;
+}
+
 const char* pm4g_status_string(int code) {
     switch (code) {
         case PM4G_OK: return "ok";
@@ -386,6 +393,34 @@ int pm4g_filter_df_events(const pm4g_prepared* log, const uint64_t* pair_mask, i
     Bump bp(ws);
     FilterWs w = filter_ws_layout(bp, log->n_events);
     PM4G_HIP(launch_filter_df_events(log, pair_mask, side, keep, out, w, (hipStream_t)stream));
+    return PM4G_OK;
+}
+
+size_t pm4g_efg_workspace_bytes(int64_t n_events, int32_t n_activities) {
+    if (n_events < 0 || n_events > kMaxEvents || n_activities < 1 || n_activities > PM4G_EFG_MAX_ACTIVITIES)
+        return 0;
+    Bump b(nullptr);
+    efg_ws_layout(b, n_events, n_activities);
+    return b.off + 256;
+}
+
+int pm4g_efg(const pm4g_prepared* log, const pm4g_efg_out* out, void* ws, size_t ws_size, void* stream) {
+    if (int rc = check_prepared(log, true)) return rc;
+    PM4G_CHECK(log->n_activities <= PM4G_EFG_MAX_ACTIVITIES, "n_activities %d above %d for the EFG",
+               log->n_activities, PM4G_EFG_MAX_ACTIVITIES);
+    PM4G_CHECK(out && out->count && out->sum_lo && out->sum_hi && out->sq_lo && out->sq_hi && out->n_pairs &&
+                   out->status,
+               "an EFG output array is NULL (only mean and std may be NULL)");
+    const size_t need = pm4g_efg_workspace_bytes(log->n_events, log->n_activities);
+    if (ws_size < need || !ws) {
+        set_err("workspace of %zu bytes, %zu needed", ws_size, need);
+        return PM4G_E_WORKSPACE;
+    }
+    Bump bp(ws);
+    EfgWs w = efg_ws_layout(bp, log->n_events, log->n_activities);
+    const EfgOutDev o{out->count, out->sum_lo, out->sum_hi, out->sq_lo, out->sq_hi,
+                      out->mean, out->std, out->n_pairs, out->status};
+    PM4G_HIP(launch_efg(log, w, o, g_efg_pass_pairs, (hipStream_t)stream));
     return PM4G_OK;
 }
 

@@ -61,19 +61,6 @@ __global__ __launch_bounds__(kCB) void k_cases_df(const int64_t* __restrict__ ca
     }
 }
 
-// Segment of virtual position p among 64 consecutive segments (lane m holds
-// the start of segment m, INT64_MAX if absent; p >= start of segment 0): the
-// last m whose start is <= p.  Every lane of the wave must execute it.
-__device__ __forceinline__ int seg_at(int64_t vstart, int64_t p) {
-    int lo = 0;
-#pragma unroll
-    for (int step = 32; step > 0; step >>= 1) {
-        const int cand = lo + step;
-        if (__shfl(vstart, cand) <= p) lo = cand;
-    }
-    return lo;
-}
-
 __device__ __forceinline__ bool bit_of(const uint64_t* m, int64_t b) { return (m[b >> 6] >> (b & 63)) & 1ull; }
 
 // flags[c]: bit 0 = the case has an activity of act_mask, bit 1 = it has a

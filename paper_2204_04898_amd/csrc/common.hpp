@@ -54,6 +54,19 @@ __device__ __forceinline__ uint32_t wave_bump(uint32_t* counter, uint32_t key, i
     return base + rank;
 }
 
+// Segment of position p among 64 consecutive segments (lane m holds the start
+// of segment m, INT64_MAX if absent; p >= start of segment 0): the last m
+// whose start is <= p.  Every lane of the wave must execute it.
+__device__ __forceinline__ int seg_at(int64_t vstart, int64_t p) {
+    int lo = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+        const int cand = lo + step;
+        if (__shfl(vstart, cand) <= p) lo = cand;
+    }
+    return lo;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_incl_sum(T v) {
 #pragma unroll

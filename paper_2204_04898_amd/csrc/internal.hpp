@@ -299,4 +299,42 @@ hipError_t launch_views_write(const pm4g_prepared* p, const pm4g_view* views, co
 hipError_t launch_views_reduce(const pm4g_prepared* p, const pm4g_view* views, const uint64_t* masks, int32_t V,
                                ViewWs w, BatchedOutDev out, int emit_grid, int agg_grid, hipStream_t s);
 
+
+// ---- eventually-follows graph and temporal profile (efg.hip) ----
+struct EfgEntry {
+    int64_t q0, q1;     // pair range [q0, q1) of the flattened list
+    int64_t klo, khi;   // its bucket's list range
+    int32_t b, pad;     // bucket
+};
+struct EfgWs {
+    uint32_t* tail;     // [n] later events of the event's case
+    int64_t* poff;      // [list + 1] pair offsets
+    uint32_t* list;     // [n] bucketed source events (bucketed only)
+    uint32_t* tl;       // [n] their tails
+    uint32_t* bcnt;     // [buckets * chunks]
+    int64_t* boff;      // [buckets * chunks]
+    int64_t* part64;
+    int64_t* scal;
+    int64_t* bfirst;    // [buckets] first plan entry
+    int64_t* bnum;      // [buckets] plan entries
+    EfgEntry* plan;     // [plan blocks + buckets]
+    uint64_t* part;     // [plan blocks + buckets][5][4096] partial tables
+};
+struct EfgOutDev {
+    int64_t* count;
+    uint64_t* sum_lo;
+    uint64_t* sum_hi;
+    uint64_t* sq_lo;
+    uint64_t* sq_hi;
+    double* mean;
+    double* std;
+    int64_t* n_pairs;
+    int32_t* status;
+};
+int efg_rows(int32_t A);
+int64_t efg_buckets(int32_t A);
+EfgWs efg_ws_layout(Bump& b, int64_t n, int32_t A);
+// pass_pairs: pairs per LDS pass (0: the full 2^31; smaller values are a test hook)
+hipError_t launch_efg(const pm4g_prepared* p, EfgWs w, const EfgOutDev& o, int64_t pass_pairs, hipStream_t s);
+
 }  // namespace pm4g

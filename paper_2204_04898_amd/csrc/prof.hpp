@@ -34,6 +34,7 @@ enum ProfId {
     P_CASES,
     P_CASE_FILTER,
     P_DF_FILTER,
+    P_EFG,
     P_COUNT
 };
 

@@ -84,6 +84,11 @@ class CaseFilter(ctypes.Structure):
                 ("n_variant_bits", ctypes.c_int64)]
 
 
+class _EfgOut(ctypes.Structure):
+    _fields_ = [(k, _P) for k in ("count", "sum_lo", "sum_hi", "sq_lo", "sq_hi", "mean", "std", "n_pairs",
+                                  "status")]
+
+
 class Pm4gError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"pm4g error {code}: {msg}")
@@ -132,6 +137,10 @@ def load():
             L.pm4g_filter_df_events.argtypes = [ctypes.POINTER(_Prepared), _P, ctypes.c_int32, ctypes.c_int32,
                                                 ctypes.POINTER(_Prepared), _P, ctypes.c_size_t, _P]
             L.pm4g_filter_df_events.restype = ctypes.c_int
+            L.pm4g_efg_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32]
+            L.pm4g_efg_workspace_bytes.restype = ctypes.c_size_t
+            L.pm4g_efg.argtypes = [ctypes.POINTER(_Prepared), ctypes.POINTER(_EfgOut), _P, ctypes.c_size_t, _P]
+            L.pm4g_efg.restype = ctypes.c_int
             L.pm4g_cases.argtypes = [ctypes.POINTER(_Prepared), _P, _P, _P]
             L.pm4g_cases.restype = ctypes.c_int
             L.pm4g_filter_cases_workspace_bytes.argtypes = [ctypes.c_int64]
@@ -146,6 +155,8 @@ def load():
             L.pm4g_profile_stage_name.argtypes = [ctypes.c_int]
             L.pm4g_profile_stage_name.restype = ctypes.c_char_p
             L.pm4g_profile_stage_count.restype = ctypes.c_int
+            L.pm4g_debug_efg_pass_pairs.argtypes = [ctypes.c_int64]
+            L.pm4g_debug_efg_pass_pairs.restype = ctypes.c_int64
             if hasattr(L, "pm4g_debug_variant_hash_bits"):
                 L.pm4g_debug_variant_hash_bits.argtypes = [ctypes.c_int]
                 L.pm4g_debug_variant_hash_bits.restype = ctypes.c_int
@@ -460,6 +471,51 @@ def pm4g_filter_df_events(prep: Prepared, pair_mask: torch.Tensor, side: int = 0
     _check(L.pm4g_filter_df_events(ctypes.byref(p), _ptr(pair_mask), int(side), 1 if keep else 0,
                                    ctypes.byref(q), _ptr(ws), need, _stream(stream)))
     return o
+
+
+PM4G_EFG_MAX_ACTIVITIES = 4096
+
+
+def pm4g_efg(prep: Prepared, out: dict | None = None, ws: torch.Tensor | None = None, stream=None) -> dict:
+    """Eventually-follows graph and temporal profile of a prepared log: device
+    [A*A] count (int64), sum_lo/sum_hi and sq_lo/sq_hi (exact gap sums as
+    int64-typed uint64 words), mean and std (float64); n_pairs, status.
+    Asynchronous."""
+    L = load()
+    dev = prep.case_s.device
+    A = prep.n_activities
+    cells = A * A
+    if out is None:
+        i64 = dict(dtype=torch.int64, device=dev)
+        out = dict(count=torch.empty(cells, **i64), sum_lo=torch.empty(cells, **i64), sum_hi=torch.empty(cells, **i64),
+                   sq_lo=torch.empty(cells, **i64), sq_hi=torch.empty(cells, **i64),
+                   mean=torch.empty(cells, dtype=torch.float64, device=dev),
+                   std=torch.empty(cells, dtype=torch.float64, device=dev), n_pairs=torch.zeros(1, **i64),
+                   status=torch.zeros(1, dtype=torch.int32, device=dev))
+    need = int(L.pm4g_efg_workspace_bytes(prep.n_events, A))
+    if need == 0:
+        raise Pm4gError(PM4G_E_INVALID, f"no EFG workspace size for n={prep.n_events}, A={A}")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    s = _EfgOut(*[_ptr(out.get(k)) for k in ("count", "sum_lo", "sum_hi", "sq_lo", "sq_hi", "mean", "std",
+                                              "n_pairs", "status")])
+    p = prep._struct()
+    _check(L.pm4g_efg(ctypes.byref(p), ctypes.byref(s), _ptr(ws), need, _stream(stream)))
+    return out
+
+
+def efg_to_host(o: dict, A: int) -> dict:
+    """The EFG outputs as [A, A] numpy arrays (sum/sq words as uint64)."""
+    import numpy as np
+    h = {}
+    for k in ("count", "sum_lo", "sum_hi", "sq_lo", "sq_hi", "mean", "std"):
+        v = o[k].cpu().numpy()
+        if k in ("sum_lo", "sum_hi", "sq_lo", "sq_hi"):
+            v = v.view(np.uint64)
+        h[k] = v.reshape(A, A)
+    h["n_pairs"] = int(o["n_pairs"].item())
+    h["status"] = int(o["status"].item())
+    return h
 
 
 I64_MIN, I64_MAX = -(1 << 63), (1 << 63) - 1

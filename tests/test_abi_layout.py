@@ -21,6 +21,7 @@ STRUCTS = {
     "pm4g_batched_out": pm4g._BatchedOut,
     "pm4g_batched_tuning": pm4g.BatchedTuning,
     "pm4g_case_filter": pm4g.CaseFilter,
+    "pm4g_efg_out": pm4g._EfgOut,
 }
 VIEW_FIELDS = ("case_lo", "case_hi", "t_lo", "t_hi")
 
