@@ -131,22 +131,50 @@ __global__ __launch_bounds__(256) void k_efg_bcount(const int32_t* __restrict__ 
     }
 }
 
+// The chunk's events go to LDS in bucket order first (wave-aggregated cursors),
+// then out as one contiguous run per bucket, so the stores coalesce.
 __global__ __launch_bounds__(256) void k_efg_bscatter(const int32_t* __restrict__ act_s,
                                                       const uint32_t* __restrict__ tail, int64_t n, int32_t R,
                                                       int64_t nbk, int32_t kbits, int64_t nch, EfgWs w) {
-    __shared__ uint32_t cur[kEfgCells];
+    __shared__ uint32_t cur[kEfgCells];      // staging cursor, then the global offset - local start
+    __shared__ uint32_t lstart[kEfgCells];   // bucket's first staging slot
+    __shared__ uint32_t st_p[kEfgChunk];
+    __shared__ uint32_t st_t[kEfgChunk];
+    __shared__ uint16_t st_b[kEfgChunk];
+    __shared__ uint32_t tmp[256 / kWave + 1];
     for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
-        for (int64_t b = threadIdx.x; b < nbk; b += 256) cur[b] = (uint32_t)w.boff[b * nch + ch];
+        uint32_t run = 0;
+        for (int64_t b0 = 0; b0 < nbk; b0 += 256) {
+            const int64_t b = b0 + threadIdx.x;
+            const uint32_t v = b < nbk ? w.bcnt[b * nch + ch] : 0u;
+            uint32_t tot;
+            const uint32_t ex = run + block_excl_sum<256>(v, tmp, &tot);
+            if (b < nbk) {
+                lstart[b] = ex;
+                cur[b] = ex;
+            }
+            run += tot;
+        }
         __syncthreads();
         for (int q = 0; q < kEfgChunk / 256; ++q) {
             const int64_t p = ch * kEfgChunk + q * 256 + threadIdx.x;
             const uint32_t t = p < n ? tail[p] : 0u;
             const bool has = t > 0;
-            const uint32_t k = wave_bump(cur, has ? (uint32_t)(act_s[p] / R) : 0u, kbits, has);
+            const uint32_t bk = has ? (uint32_t)(act_s[p] / R) : 0u;
+            const uint32_t x = wave_bump(cur, bk, kbits, has);
             if (has) {
-                w.list[k] = (uint32_t)p;
-                w.tl[k] = t;
+                st_p[x] = (uint32_t)p;
+                st_t[x] = t;
+                st_b[x] = (uint16_t)bk;
             }
+        }
+        __syncthreads();
+        for (int64_t b = threadIdx.x; b < nbk; b += 256) cur[b] = (uint32_t)w.boff[b * nch + ch] - lstart[b];
+        __syncthreads();
+        for (uint32_t x = threadIdx.x; x < run; x += 256) {
+            const uint32_t k = cur[st_b[x]] + x;
+            w.list[k] = st_p[x];
+            w.tl[k] = st_t[x];
         }
         __syncthreads();
     }
