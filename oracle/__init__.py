@@ -45,8 +45,11 @@ def _load():
         L.orc_filter_cases.argtypes = [i64, P, P, P, i32, P, P, P, i32, P, P, P, i64, i32, P, P, P, P, P]
         L.orc_filter_df_events.argtypes = [i64, P, P, P, i32, P, i32, i32, P, P, P, P, P]
         L.orc_efg.argtypes = [i64, P, P, P, i32, P, P, P, P, P, P, P, P]
+        L.orc_sample.argtypes = [i64, P, P, P, i32, i64, ctypes.c_uint64, i32, P, P, P, P, P]
+        L.orc_splitmix.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.orc_splitmix.restype = ctypes.c_uint64
         for f in (L.orc_prepare, L.orc_dfg, L.orc_variants, L.orc_view, L.orc_cases, L.orc_filter_cases,
-                  L.orc_filter_df_events, L.orc_efg):
+                  L.orc_filter_df_events, L.orc_efg, L.orc_sample):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -260,3 +263,23 @@ def efg(case, act, ts, A: int) -> dict:
     out = {k: v.reshape(A, A) for k, v in out.items()}
     out["n_pairs"] = int(npairs[0])
     return out
+
+
+def splitmix(seed: int, x: int) -> int:
+    """The x-th output of SplitMix64 started from state seed."""
+    return int(_load().orc_splitmix(seed & (2**64 - 1), x & (2**64 - 1)))
+
+
+def sample(case, act, ts, A: int, k: int, seed: int, by_events: bool = False) -> dict:
+    """A sample of k cases (whole) or k events of the formatted log, in order."""
+    case, act, ts = _cols(case, act, ts)
+    n = case.shape[0]
+    m = max(n, 1)
+    out = dict(case_s=np.empty(m, np.int32), act_s=np.empty(m, np.int32), ts_s=np.empty(m, np.int64))
+    no, nc = np.zeros(1, np.int64), np.zeros(1, np.int64)
+    rc = _load().orc_sample(n, _p(case), _p(act), _p(ts), A, int(k), seed & (2**64 - 1), 1 if by_events else 0,
+                            _p(out["case_s"]), _p(out["act_s"]), _p(out["ts_s"]), _p(no), _p(nc))
+    if rc:
+        raise OracleError(rc)
+    kk = int(no[0])
+    return {key: v[:kk] for key, v in out.items()} | {"n_events": kk, "n_cases": int(nc[0])}

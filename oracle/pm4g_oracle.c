@@ -33,6 +33,7 @@
  *              event of their case.
  *   EFG        Sec. 3, eventually-follows graph and temporal profile: every
  *              ordered pair of events of a case, with its gap statistics.
+ *   sampling   Sec. 3, sampling module: a sample of k cases or k events.
  *
  * Readings where the paper is silent (each is listed in the design notes):
  *   - the row tie-break is the 0-based row index in the caller's arrays;
@@ -59,7 +60,11 @@
  *   - the eventually-follows pairs of a case are all (i, j) with i before j
  *     in that order; the temporal profile of a pair of activities is the
  *     mean and the sample standard deviation of their gaps, from exact
- *     integer sums (see orc_efg).
+ *     integer sums (see orc_efg);
+ *   - a sample of k cases (events) keeps those with the k smallest SplitMix64
+ *     keys of (seed, case id) ((seed, position in the formatted log)); the
+ *     keys are distinct, so the sample is unique, and a smaller k gives a
+ *     subset of a larger one.
  *
  * Status codes: 0 ok, -1 invalid argument, -2 activity out of [0, A).
  */
@@ -713,5 +718,95 @@ int orc_efg(int64_t n, const int32_t *case_id, const int32_t *act, const int64_t
     free(off);
     free(S);
     free(Q);
+    return r;
+}
+
+/* ---- sampling -------------------------------------------------------------- */
+
+/*
+ * orc_splitmix: the x-th output (x = 0, 1, ...) of the SplitMix64 generator
+ * (Steele, Lea and Flood, OOPSLA 2014) started from state `seed`: the state
+ * advances by the odd constant 0x9E3779B97F4A7C15 per output and each output
+ * is the state passed through the published variant-13 mixer.  Distinct x
+ * give distinct outputs (every step is a bijection of 64-bit words).
+ */
+uint64_t orc_splitmix(uint64_t seed, uint64_t x)
+{
+    uint64_t z = seed + (x + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+typedef struct {
+    uint64_t key;
+    int64_t idx;
+} orc_keyed;
+
+static int cmp_keyed(const void *pa, const void *pb)
+{
+    const orc_keyed *a = (const orc_keyed *)pa, *b = (const orc_keyed *)pb;
+    if (a->key != b->key) return a->key < b->key ? -1 : 1;
+    return (a->idx > b->idx) - (a->idx < b->idx);
+}
+
+/*
+ * orc_sample: the sampling module (Sec. 3: a sample of the log by a number
+ * of cases or of events).  by_events == 0: the k cases whose key
+ * orc_splitmix(seed, case id as a 32-bit pattern) is smallest (all cases
+ * when k >= their number), with all their events; by_events != 0: the k
+ * events whose key orc_splitmix(seed, position) is smallest, the position
+ * being the event's index in the (case, timestamp, row) order.  The kept
+ * events are written in that order; n_out and n_cases_out receive their
+ * number and the number of distinct cases among them.
+ */
+int orc_sample(int64_t n, const int32_t *case_id, const int32_t *act, const int64_t *ts, int32_t A, int64_t k,
+               uint64_t seed, int32_t by_events, int32_t *case_out, int32_t *act_out, int64_t *ts_out,
+               int64_t *n_out, int64_t *n_cases_out)
+{
+    if (n < 0 || A < 1 || k < 0) return ORC_E_INVALID;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    int32_t *case_s = (int32_t *)malloc(nn * sizeof(int32_t));
+    int32_t *act_s = (int32_t *)malloc(nn * sizeof(int32_t));
+    int64_t *ts_s = (int64_t *)malloc(nn * sizeof(int64_t));
+    int64_t *off = (int64_t *)malloc((nn + 1) * sizeof(int64_t));
+    int32_t *code = (int32_t *)malloc(nn * sizeof(int32_t));
+    orc_keyed *kv = (orc_keyed *)malloc(nn * sizeof(orc_keyed));
+    unsigned char *keep = (unsigned char *)calloc(nn, 1);
+    int64_t C = 0, m = 0, kc = 0;
+    int r = orc_prepare(n, case_id, act, ts, A, NULL, case_s, act_s, ts_s, off, code, &C);
+    if (r == ORC_OK) {
+        int64_t units = by_events ? n : C;
+        for (int64_t u = 0; u < units; u++) {
+            uint64_t x = by_events ? (uint64_t)u : (uint64_t)(uint32_t)code[u];
+            kv[u].key = orc_splitmix(seed, x);
+            kv[u].idx = u;
+        }
+        qsort(kv, (size_t)units, sizeof(orc_keyed), cmp_keyed);
+        for (int64_t u = 0; u < units && u < k; u++) keep[kv[u].idx] = 1;
+        int64_t last_case = -1;
+        for (int64_t c = 0; c < C; c++) {
+            for (int64_t e = off[c]; e < off[c + 1]; e++) {
+                if (!(by_events ? keep[e] : keep[c])) continue;
+                if (last_case != c) {
+                    kc++;
+                    last_case = c;
+                }
+                if (case_out) case_out[m] = case_s[e];
+                if (act_out) act_out[m] = act_s[e];
+                if (ts_out) ts_out[m] = ts_s[e];
+                m++;
+            }
+        }
+    }
+    if (n_out) *n_out = m;
+    if (n_cases_out) *n_cases_out = kc;
+    free(case_s);
+    free(act_s);
+    free(ts_s);
+    free(off);
+    free(code);
+    free(kv);
+    free(keep);
     return r;
 }

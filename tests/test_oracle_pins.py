@@ -779,3 +779,62 @@ def test_efg_invariants_on_workload():
     m = o["count"] > 1
     n = o["count"][m].astype(np.float64)
     assert np.allclose(o2["std"][m] ** 2 * (2 * n - 1), o["std"][m] ** 2 * 2 * (n - 1), rtol=1e-12, atol=0)
+
+
+# ---- sampling ------------------------------------------------------------------
+
+def test_splitmix_published_sequence():
+    # the first outputs of SplitMix64 from state 0, as its reference implementation prints them
+    want = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F, 0xF88BB8A8724C81EC]
+    assert [oracle.splitmix(0, x) for x in range(4)] == want
+
+
+def _sample_triples(o):
+    return list(zip(o["case_s"].tolist(), o["act_s"].tolist(), o["ts_s"].tolist()))
+
+
+@settings(max_examples=200, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(tiny_logs(), st.integers(0, 30), st.integers(0, 2**64 - 1), st.booleans())
+def test_sample_match_bruteforce(log, k, seed, by_events):
+    case, act, ts, A = log
+    o = oracle.sample(case, act, ts, A, k, seed, by_events)
+    f = oracle.prepare(case, act, ts, A)
+    if by_events:
+        n = len(case)
+        keep = set(sorted(range(n), key=lambda u: oracle.splitmix(seed, u))[:k])
+        want = [(f["case_s"][u], f["act_s"][u], f["ts_s"][u]) for u in range(n) if u in keep]
+    else:
+        codes = sorted(set(case))
+        chosen = set(sorted(codes, key=lambda c: oracle.splitmix(seed, c & 0xFFFFFFFF))[:k])
+        want = [(c, a, t) for c, a, t in zip(f["case_s"], f["act_s"], f["ts_s"]) if c in chosen]
+    assert _sample_triples(o) == [tuple(int(x) for x in w) for w in want]
+    assert o["n_cases"] == len({w[0] for w in want})
+
+
+def test_sample_sizes_nesting_and_uniformity():
+    from collections import Counter
+
+    log = synth.config_log(2, 0.002)
+    A = log.n_activities
+    C = int(np.unique(log.case).size)
+    for by_events, total in ((False, C), (True, log.n_events)):
+        assert oracle.sample(log.case, log.act, log.ts, A, 0, 7, by_events)["n_events"] == 0
+        whole = oracle.sample(log.case, log.act, log.ts, A, total + 5, 7, by_events)
+        assert whole["n_events"] == log.n_events
+        prev = Counter()
+        for k in (1, 10, 100, total // 2):
+            o = oracle.sample(log.case, log.act, log.ts, A, k, 7, by_events)
+            if by_events:
+                assert o["n_events"] == k
+            else:
+                assert o["n_cases"] == k == len(set(o["case_s"].tolist()))
+            units = Counter(_sample_triples(o))
+            assert not (prev - units)                       # a smaller sample is a sub-multiset
+            prev = units
+    # one case out of four, many seeds: each case about equally often
+    case, act, ts = np.array([1, 2, 3, 4]), np.zeros(4, np.int64), np.zeros(4, np.int64)
+    hits = np.zeros(5, np.int64)
+    for seed in range(4000):
+        hits[int(oracle.sample(case, act, ts, 1, 1, seed)["case_s"][0])] += 1
+    chi2 = float((((hits[1:] - 1000) ** 2) / 1000).sum())
+    assert chi2 < 16.3                                      # chi-square, 3 dof, p = 0.001
