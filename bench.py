@@ -211,8 +211,8 @@ def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int, autot
 
 
 def bench_cases(log, prep, steps: int = 5) -> dict:
-    """Cases dataframe, case-level and directly-follows-level filters on the
-    prepared log (whole-log calls)."""
+    """Cases dataframe, case-level and directly-follows-level filters and
+    sampling on the prepared log (whole-log calls)."""
     import numpy as np
     import torch
 
@@ -236,6 +236,7 @@ def bench_cases(log, prep, steps: int = 5) -> dict:
     t_lo, t_hi = (int(x) for x in torch.quantile(prep.ts_s[::max(prep.n_events // 1000000, 1)].double(),
                                                   torch.tensor([0.3, 0.7], dtype=torch.float64,
                                                                device=prep.case_s.device)).cpu())
+    C_all = int(prep.n_cases.item())
     res = {}
     for name, call in (("cases_dataframe", lambda: pm4g.pm4g_cases(prep)),
                        ("filter_events_5_40", lambda: pm4g.pm4g_filter_cases(prep, min_events=5, max_events=40,
@@ -247,6 +248,9 @@ def bench_cases(log, prep, steps: int = 5) -> dict:
                        ("filter_top10_variants", lambda: pm4g.pm4g_filter_cases(
                            prep, case_variant=vo["case_variant"], variant_mask=vmd, n_variant_bits=nv,
                            variant_keep=True, out=out)),
+                       ("sample_10pct_cases", lambda: pm4g.pm4g_sample(prep, C_all // 10, 7, False, out=out)),
+                       ("sample_10pct_events", lambda: pm4g.pm4g_sample(prep, prep.n_events // 10, 7, True,
+                                                                        out=out)),
                        ("df_events_keep_prev_pairs", lambda: pm4g.pm4g_filter_df_events(prep, pmd, 0, True, out=out)),
                        ("df_events_drop_prev_pairs", lambda: pm4g.pm4g_filter_df_events(prep, pmd, 0, False,
                                                                                        out=out))):

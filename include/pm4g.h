@@ -432,6 +432,26 @@ typedef struct {
 size_t pm4g_efg_workspace_bytes(int64_t n_events, int32_t n_activities);
 int pm4g_efg(const pm4g_prepared *log, const pm4g_efg_out *out, void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * Sampling (Sec. 3: the sampling module, a sample of the log by a number of
+ * cases or of events).  by_events = 0: the k cases (all when k >= their
+ * number) whose key SplitMix64(seed, case id) is smallest, with all their
+ * events; by_events = 1: the k events whose key SplitMix64(seed, position)
+ * is smallest, the position being the event's index in the log's (case,
+ * timestamp, row) order.  SplitMix64(seed, x) is the x-th output (x = 0, 1,
+ * ...) of the SplitMix64 generator (Steele, Lea and Flood, 2014) started
+ * from state seed, the case id taken as its 32-bit pattern; the keys of
+ * distinct inputs differ, so the sample is unique and a smaller k gives a
+ * subset of a larger one.  The kept events form a prepared log in out (same
+ * order, a case table over the cases they belong to).  out->n_events is the
+ * capacity: if the kept events exceed it, nothing is written, the output log
+ * is empty and out->status is PM4G_E_CAPACITY.  k < 0 or by_events outside
+ * {0, 1}: PM4G_E_INVALID.  Does not synchronise.
+ */
+size_t pm4g_sample_workspace_bytes(int64_t n_events);
+int pm4g_sample(const pm4g_prepared *log, int64_t k, uint64_t seed, int32_t by_events, const pm4g_prepared *out,
+                void *ws, size_t ws_bytes, void *stream);
+
 /* Text for a status code (static storage). */
 const char *pm4g_status_string(int code);
 

@@ -7,6 +7,7 @@
 
 #include "../../include/pm4g.h"
 #include "internal.hpp"
+#include "prof.hpp"
 
 using namespace pm4g;
 
@@ -421,6 +422,47 @@ int pm4g_efg(const pm4g_prepared* log, const pm4g_efg_out* out, void* ws, size_t
     const EfgOutDev o{out->count, out->sum_lo, out->sum_hi, out->sq_lo, out->sq_hi,
                       out->mean, out->std, out->n_pairs, out->status};
     PM4G_HIP(launch_efg(log, w, o, g_efg_pass_pairs, (hipStream_t)stream));
+    return PM4G_OK;
+}
+
+size_t pm4g_sample_workspace_bytes(int64_t n_events) {
+    if (n_events < 0 || n_events > kMaxEvents) return 0;
+    Bump a(nullptr);
+    a.take<SelState>(1);
+    filter_ws_layout(a, n_events);
+    Bump b(nullptr);
+    b.take<SelState>(1);
+    case_filter_ws_layout(b, n_events);
+    return (a.off > b.off ? a.off : b.off) + 256;
+}
+
+int pm4g_sample(const pm4g_prepared* log, int64_t k, uint64_t seed, int32_t by_events, const pm4g_prepared* out,
+                void* ws, size_t ws_size, void* stream) {
+    if (int rc = check_prepared(log, true)) return rc;
+    PM4G_CHECK(k >= 0, "k < 0");
+    PM4G_CHECK(by_events == 0 || by_events == 1, "by_events must be 0 or 1");
+    PM4G_CHECK(out && out->case_off && out->n_cases && out->status &&
+                   (log->n_events == 0 || (out->case_s && out->act_s && out->ts_s && out->case_code)),
+               "a sampled-log output array is NULL");
+    PM4G_CHECK(out->n_events >= 0 && out->n_activities == log->n_activities,
+               "the sampled log needs a capacity >= 0 and the same n_activities");
+    const size_t need = pm4g_sample_workspace_bytes(log->n_events);
+    if (ws_size < need || !ws) {
+        set_err("workspace of %zu bytes, %zu needed", ws_size, need);
+        return PM4G_E_WORKSPACE;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    ProfScope ps(P_SAMPLE, s);
+    Bump bp(ws);
+    SelState* sel = bp.take<SelState>(1);
+    PM4G_HIP(launch_sample_select(log, k, seed, by_events != 0, sel, s));
+    if (by_events) {
+        FilterWs w = filter_ws_layout(bp, log->n_events);
+        PM4G_HIP(launch_sample_events(log, seed, sel, out, w, s));
+    } else {
+        CaseFilterWs w = case_filter_ws_layout(bp, log->n_events);
+        PM4G_HIP(launch_sample_cases(log, seed, sel, out, w, s));
+    }
     return PM4G_OK;
 }
 

@@ -201,6 +201,35 @@ hipError_t launch_cases_df(const pm4g_prepared* p, int64_t* n_events, int64_t* t
     return hipGetLastError();
 }
 
+namespace {
+
+// Sampling by cases: a case is kept iff its id's SplitMix64 key is at most the
+// selected threshold.
+__global__ __launch_bounds__(kCB) void k_cf_sample(const int64_t* __restrict__ case_off,
+                                                   const int32_t* __restrict__ case_code, const int64_t* n_cases,
+                                                   uint64_t seed, const SelState* sel, CaseFilterWs w) {
+    const int64_t C = *n_cases;
+    const uint64_t T = sel->T;
+    const bool none = sel->none != 0, all = sel->all != 0;
+    for (int64_t c = (int64_t)blockIdx.x * kCB + threadIdx.x; c < C; c += (int64_t)gridDim.x * kCB) {
+        const bool keep = !none && (all || splitmix64(seed, (uint64_t)(uint32_t)case_code[c]) <= T);
+        w.cnt[c] = keep ? (uint32_t)(case_off[c + 1] - case_off[c]) : 0u;
+        w.kept[c] = keep ? 1u : 0u;
+    }
+}
+
+// The kept cases (w.cnt, w.kept) copied into out.
+void materialise_cases(const pm4g_prepared* p, const pm4g_prepared* out, CaseFilterWs w, hipStream_t s) {
+    dev::excl_scan<int64_t>(w.cnt, p->n_cases, w.eoff, w.part64, &w.scal[1], s);
+    dev::excl_scan<uint32_t>(w.kept, p->n_cases, w.koff, w.part32, &w.uscal[0], s);
+    k_cf_check<<<1, 1, 0, s>>>(w, out->n_events);
+    k_cf_emit<<<kCGrid, kCB, 0, s>>>(p->case_s, p->act_s, p->ts_s, p->case_off, p->case_code, p->n_cases, w,
+                                     out->case_s, out->act_s, out->ts_s, out->case_off, out->case_code);
+    k_cf_finish<<<1, 1, 0, s>>>(w, out->case_off, out->n_cases, out->status, p->status);
+}
+
+}  // namespace
+
 hipError_t launch_filter_cases(const pm4g_prepared* p, const pm4g_case_filter* f, const pm4g_prepared* out,
                                CaseFilterWs w, hipStream_t s) {
     ProfScope ps(P_CASE_FILTER, s);
@@ -209,12 +238,14 @@ hipError_t launch_filter_cases(const pm4g_prepared* p, const pm4g_case_filter* f
         k_cf_contains<<<kCGrid, kCB, 0, s>>>(p->act_s, p->case_off, p->n_cases, p->n_activities, fv.act_mask,
                                              fv.path_mask, w.flags);
     k_cf_decide<<<kCGrid, kCB, 0, s>>>(p->act_s, p->case_off, p->ts_s, p->n_cases, fv, w);
-    dev::excl_scan<int64_t>(w.cnt, p->n_cases, w.eoff, w.part64, &w.scal[1], s);
-    dev::excl_scan<uint32_t>(w.kept, p->n_cases, w.koff, w.part32, &w.uscal[0], s);
-    k_cf_check<<<1, 1, 0, s>>>(w, out->n_events);
-    k_cf_emit<<<kCGrid, kCB, 0, s>>>(p->case_s, p->act_s, p->ts_s, p->case_off, p->case_code, p->n_cases, w,
-                                     out->case_s, out->act_s, out->ts_s, out->case_off, out->case_code);
-    k_cf_finish<<<1, 1, 0, s>>>(w, out->case_off, out->n_cases, out->status, p->status);
+    materialise_cases(p, out, w, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_cases(const pm4g_prepared* p, uint64_t seed, const SelState* sel,
+                               const pm4g_prepared* out, CaseFilterWs w, hipStream_t s) {
+    k_cf_sample<<<kCGrid, kCB, 0, s>>>(p->case_off, p->case_code, p->n_cases, seed, sel, w);
+    materialise_cases(p, out, w, s);
     return hipGetLastError();
 }
 

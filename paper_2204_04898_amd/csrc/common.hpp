@@ -54,6 +54,16 @@ __device__ __forceinline__ uint32_t wave_bump(uint32_t* counter, uint32_t key, i
     return base + rank;
 }
 
+// SplitMix64 (Steele, Lea and Flood, 2014): the x-th output (x = 0, 1, ...)
+// of the generator started from state `seed`.  A bijection of x for a fixed
+// seed, so distinct inputs never share a key.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t x) {
+    uint64_t z = seed + (x + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
 // Segment of position p among 64 consecutive segments (lane m holds the start
 // of segment m, INT64_MAX if absent; p >= start of segment 0): the last m
 // whose start is <= p.  Every lane of the wave must execute it.

@@ -4,7 +4,9 @@
 //     filter), over the view's slice [p0, p1) of whole cases;
 //   - the directly-follows level filter (Sec. 3: an event kept or dropped on
 //     the pair it forms with the previous, or next, event of its case), over
-//     the whole log.
+//     the whole log;
+//   - a sample of events (Sec. 3 sampling module): the positions whose
+//     SplitMix64 key is at most the selected threshold.
 // Stream compaction with the predicate as a template parameter:
 //   k_filter_slice / k_filter_whole   p0, p1 on the device
 //   k_filter_count   per-tile kept counts (persistent grid over the slice)
@@ -129,6 +131,21 @@ struct PairPred {
         }
         return in && (keep ? match : !match);
     }
+};
+
+// Sampling by events: a position is kept iff its SplitMix64 key is at most
+// the selected threshold.
+struct SamplePred {
+    uint64_t seed;
+    const SelState* sel;
+    struct Ready {
+        uint64_t seed, T;
+        int32_t none, all;
+        __device__ __forceinline__ bool operator()(int64_t i, bool in) const {
+            return in && !none && (all || splitmix64(seed, (uint64_t)i) <= T);
+        }
+    };
+    __device__ __forceinline__ Ready ready() const { return Ready{seed, sel->T, sel->none, sel->all}; }
 };
 
 template <class Pred>
@@ -309,6 +326,13 @@ hipError_t launch_filter_view(const pm4g_prepared* p, const pm4g_view* view, con
     ProfScope ps(P_VIEW_FILTER, s);
     k_filter_slice<<<1, 1, 0, s>>>(view, p->case_off, p->case_code, p->n_cases, out->n_events, w);
     filter_compact(p, ViewPred{view, mask, p->act_s, p->ts_s}, out, w, false, filter_grid(p->n_events), s);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_events(const pm4g_prepared* p, uint64_t seed, const SelState* sel,
+                                const pm4g_prepared* out, FilterWs w, hipStream_t s) {
+    k_filter_whole<<<1, 1, 0, s>>>(p->n_events, w);
+    filter_compact(p, SamplePred{seed, sel}, out, w, true, filter_grid(p->n_events), s);
     return hipGetLastError();
 }
 

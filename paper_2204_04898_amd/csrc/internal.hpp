@@ -337,4 +337,25 @@ EfgWs efg_ws_layout(Bump& b, int64_t n, int32_t A);
 // pass_pairs: pairs per LDS pass (0: the full 2^31; smaller values are a test hook)
 hipError_t launch_efg(const pm4g_prepared* p, EfgWs w, const EfgOutDev& o, int64_t pass_pairs, hipStream_t s);
 
+
+// ---- sampling (sample.hip; the kept units' materialisation in filter.hip and
+// casefilter.hip) ----
+// Radix select of the k-th smallest SplitMix64 key over the units (events by
+// position, or cases by id): after the passes, a unit is kept iff none == 0
+// and (all != 0 or its key <= T).
+struct SelState {
+    uint64_t prefix;
+    int64_t krem;
+    uint64_t T;
+    int32_t none;
+    int32_t all;
+    uint32_t hist[256];
+};
+hipError_t launch_sample_select(const pm4g_prepared* p, int64_t k, uint64_t seed, bool by_events, SelState* sel,
+                                hipStream_t s);
+hipError_t launch_sample_events(const pm4g_prepared* p, uint64_t seed, const SelState* sel,
+                                const pm4g_prepared* out, FilterWs w, hipStream_t s);
+hipError_t launch_sample_cases(const pm4g_prepared* p, uint64_t seed, const SelState* sel,
+                               const pm4g_prepared* out, CaseFilterWs w, hipStream_t s);
+
 }  // namespace pm4g

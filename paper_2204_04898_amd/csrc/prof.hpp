@@ -35,6 +35,7 @@ enum ProfId {
     P_CASE_FILTER,
     P_DF_FILTER,
     P_EFG,
+    P_SAMPLE,
     P_COUNT
 };
 

@@ -141,6 +141,11 @@ def load():
             L.pm4g_efg_workspace_bytes.restype = ctypes.c_size_t
             L.pm4g_efg.argtypes = [ctypes.POINTER(_Prepared), ctypes.POINTER(_EfgOut), _P, ctypes.c_size_t, _P]
             L.pm4g_efg.restype = ctypes.c_int
+            L.pm4g_sample_workspace_bytes.argtypes = [ctypes.c_int64]
+            L.pm4g_sample_workspace_bytes.restype = ctypes.c_size_t
+            L.pm4g_sample.argtypes = [ctypes.POINTER(_Prepared), ctypes.c_int64, ctypes.c_uint64, ctypes.c_int32,
+                                      ctypes.POINTER(_Prepared), _P, ctypes.c_size_t, _P]
+            L.pm4g_sample.restype = ctypes.c_int
             L.pm4g_cases.argtypes = [ctypes.POINTER(_Prepared), _P, _P, _P]
             L.pm4g_cases.restype = ctypes.c_int
             L.pm4g_filter_cases_workspace_bytes.argtypes = [ctypes.c_int64]
@@ -470,6 +475,23 @@ def pm4g_filter_df_events(prep: Prepared, pair_mask: torch.Tensor, side: int = 0
     q = o._struct()
     _check(L.pm4g_filter_df_events(ctypes.byref(p), _ptr(pair_mask), int(side), 1 if keep else 0,
                                    ctypes.byref(q), _ptr(ws), need, _stream(stream)))
+    return o
+
+
+def pm4g_sample(prep: Prepared, k: int, seed: int, by_events: bool = False, out: Prepared | None = None,
+                ws: torch.Tensor | None = None, stream=None) -> Prepared:
+    """A sample of k cases (whole) or k events of a prepared log, as a
+    prepared log.  Asynchronous; the kept count is out.case_off[out.n_cases]."""
+    L = load()
+    dev = prep.case_s.device
+    o = out if out is not None else Prepared.empty(prep.n_events, prep.n_activities, dev)
+    need = int(L.pm4g_sample_workspace_bytes(prep.n_events))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    p = prep._struct()
+    q = o._struct()
+    _check(L.pm4g_sample(ctypes.byref(p), int(k), int(seed) & (2**64 - 1), 1 if by_events else 0,
+                         ctypes.byref(q), _ptr(ws), need, _stream(stream)))
     return o
 
 
