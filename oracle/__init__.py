@@ -46,10 +46,12 @@ def _load():
         L.orc_filter_df_events.argtypes = [i64, P, P, P, i32, P, i32, i32, P, P, P, P, P]
         L.orc_efg.argtypes = [i64, P, P, P, i32, P, P, P, P, P, P, P, P]
         L.orc_sample.argtypes = [i64, P, P, P, i32, i64, ctypes.c_uint64, i32, P, P, P, P, P]
+        L.orc_ingest_csv.argtypes = [ctypes.c_char_p, i64, i32, i32, i32, ctypes.c_char, i32, i32, i32, i64,
+                                     P, P, P, P, P, P, P, P, P, P, P]
         L.orc_splitmix.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         L.orc_splitmix.restype = ctypes.c_uint64
         for f in (L.orc_prepare, L.orc_dfg, L.orc_variants, L.orc_view, L.orc_cases, L.orc_filter_cases,
-                  L.orc_filter_df_events, L.orc_efg, L.orc_sample):
+                  L.orc_filter_df_events, L.orc_efg, L.orc_sample, L.orc_ingest_csv):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -283,3 +285,55 @@ def sample(case, act, ts, A: int, k: int, seed: int, by_events: bool = False) ->
         raise OracleError(rc)
     kk = int(no[0])
     return {key: v[:kk] for key, v in out.items()} | {"n_events": kk, "n_cases": int(nc[0])}
+
+
+class CsvParseError(OracleError):
+    def __init__(self, row: int):
+        RuntimeError.__init__(self, f"CSV parse error at data row {row}")
+        self.code = -3
+        self.row = row
+
+
+def ingest_csv(text: bytes, case_col: int, act_col: int, ts_col: int, sep: bytes = b",", has_header: bool = True,
+               ts_iso: bool = False, ts_scale: int = 3, max_rows: int | None = None) -> dict:
+    """Columns of a CSV text: case and activity codes (first-appearance order),
+    timestamps, and per code the raw byte range of its first field."""
+    n = len(text)
+    cap = max_rows if max_rows is not None else n + 1
+    m = max(cap, 1)
+    out = dict(case=np.empty(m, np.int32), act=np.empty(m, np.int32), ts=np.empty(m, np.int64),
+               case_off=np.empty(m, np.int64), case_len=np.empty(m, np.int32), act_off=np.empty(m, np.int64),
+               act_len=np.empty(m, np.int32))
+    nr, nc, na, bad = (np.zeros(1, np.int64) for _ in range(4))
+    rc = _load().orc_ingest_csv(text, n, case_col, act_col, ts_col, sep, 1 if has_header else 0, 1 if ts_iso else 0,
+                                ts_scale, cap, _p(out["case"]), _p(out["act"]), _p(out["ts"]), _p(nr),
+                                _p(out["case_off"]), _p(out["case_len"]), _p(nc), _p(out["act_off"]),
+                                _p(out["act_len"]), _p(na), _p(bad))
+    if rc == -3:
+        raise CsvParseError(int(bad[0]))
+    if rc:
+        raise OracleError(rc)
+    r, c, a = int(nr[0]), int(nc[0]), int(na[0])
+    res = {k: out[k][:r] for k in ("case", "act", "ts")}
+    res.update(case_off=out["case_off"][:c], case_len=out["case_len"][:c], act_off=out["act_off"][:a],
+               act_len=out["act_len"][:a], n_rows=r, n_cases=c, n_acts=a)
+    return res
+
+
+def csv_value(raw: bytes) -> bytes:
+    """The value of a raw CSV field (quoted runs unwrapped, doubled quotes single)."""
+    out = bytearray()
+    inq = False
+    i = 0
+    while i < len(raw):
+        ch = raw[i:i + 1]
+        if ch == b'"':
+            if inq and raw[i + 1:i + 2] == b'"':
+                out += b'"'
+                i += 1
+            else:
+                inq = not inq
+        else:
+            out += ch
+        i += 1
+    return bytes(out)

@@ -34,6 +34,7 @@
  *   EFG        Sec. 3, eventually-follows graph and temporal profile: every
  *              ordered pair of events of a case, with its gap statistics.
  *   sampling   Sec. 3, sampling module: a sample of k cases or k events.
+ *   CSV        Sec. 2.2, ingestion of a CSV text into the columns of a log.
  *
  * Readings where the paper is silent (each is listed in the design notes):
  *   - the row tie-break is the 0-based row index in the caller's arrays;
@@ -66,7 +67,8 @@
  *     keys are distinct, so the sample is unique, and a smaller k gives a
  *     subset of a larger one.
  *
- * Status codes: 0 ok, -1 invalid argument, -2 activity out of [0, A).
+ * Status codes: 0 ok, -1 invalid argument, -2 activity out of [0, A),
+ * -3 parse error (CSV ingestion).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -809,4 +811,330 @@ int orc_sample(int64_t n, const int32_t *case_id, const int32_t *act, const int6
     free(kv);
     free(keep);
     return r;
+}
+
+/* ---- CSV ingestion ------------------------------------------------------------ */
+
+#define ORC_E_PARSE -3
+
+/* Days from 1970-01-01 to y-m-d in the proleptic Gregorian calendar: count the
+ * days of whole 400-year eras since 0000-03-01, the years of the current era
+ * (each from March, so the leap day ends a year) and the days of the current
+ * year, then shift the origin. */
+static int64_t civil_days(int64_t y, int64_t m, int64_t d)
+{
+    y -= m <= 2;
+    int64_t era = (y >= 0 ? y : y - 399) / 400;
+    int64_t yoe = y - era * 400;                              /* 0..399 */
+    int64_t doy = (153 * (m + (m > 2 ? -3 : 9)) + 2) / 5 + d - 1; /* 0..365, from March 1 */
+    int64_t doe = yoe * 365 + yoe / 4 - yoe / 100 + doy;       /* 0..146096 */
+    return era * 146097 + doe - 719468;
+}
+
+static int days_in_month(int64_t y, int64_t m)
+{
+    static const int dm[12] = {31, 28, 31, 30, 31, 30, 31, 31, 30, 31, 30, 31};
+    int leap = (y % 4 == 0 && y % 100 != 0) || y % 400 == 0;
+    return m == 2 ? 28 + leap : dm[m - 1];
+}
+
+static int read_fixed(const char *s, int64_t n, int64_t *i, int width, int64_t *out)
+{
+    int64_t v = 0;
+    for (int k = 0; k < width; k++) {
+        if (*i >= n || s[*i] < '0' || s[*i] > '9') return 0;
+        v = v * 10 + (s[*i] - '0');
+        (*i)++;
+    }
+    *out = v;
+    return 1;
+}
+
+/* ISO-8601 date-time: YYYY-MM-DD, optionally [T or space]HH:MM[:SS[(.|,)F]]
+ * with 1-9 fraction digits, optionally Z or +-HH[[:]MM].  The value counts
+ * units of 10^-scale s since 1970-01-01T00:00Z; fraction digits beyond the
+ * unit are dropped.  Returns 1 and writes *out, or 0. */
+static int parse_iso(const char *s, int64_t n, int scale, int64_t *out)
+{
+    int64_t i = 0, y, mo, d, h = 0, mi = 0, se = 0, frac = 0, tz = 0;
+    int fdig = 0;
+    if (!read_fixed(s, n, &i, 4, &y) || i >= n || s[i++] != '-' || !read_fixed(s, n, &i, 2, &mo) || i >= n ||
+        s[i++] != '-' || !read_fixed(s, n, &i, 2, &d))
+        return 0;
+    if (mo < 1 || mo > 12 || d < 1 || d > days_in_month(y, mo)) return 0;
+    if (i < n && (s[i] == 'T' || s[i] == ' ')) {
+        i++;
+        if (!read_fixed(s, n, &i, 2, &h) || i >= n || s[i++] != ':' || !read_fixed(s, n, &i, 2, &mi)) return 0;
+        if (i < n && s[i] == ':') {
+            i++;
+            if (!read_fixed(s, n, &i, 2, &se)) return 0;
+            if (i < n && (s[i] == '.' || s[i] == ',')) {
+                i++;
+                while (i < n && s[i] >= '0' && s[i] <= '9') {
+                    if (fdig < 9) {
+                        if (fdig < scale) frac = frac * 10 + (s[i] - '0');
+                        fdig++;
+                    } else {
+                        return 0;
+                    }
+                    i++;
+                }
+                if (fdig == 0) return 0;
+            }
+        }
+        if (h > 23 || mi > 59 || se > 59) return 0;
+        if (i < n && s[i] == 'Z') {
+            i++;
+        } else if (i < n && (s[i] == '+' || s[i] == '-')) {
+            int64_t sign = s[i] == '-' ? -1 : 1, th, tm = 0;
+            i++;
+            if (!read_fixed(s, n, &i, 2, &th)) return 0;
+            if (i < n && s[i] == ':') i++;
+            if (i < n && !read_fixed(s, n, &i, 2, &tm)) return 0;
+            if (th > 23 || tm > 59) return 0;
+            tz = sign * (th * 3600 + tm * 60);
+        }
+    }
+    if (i != n) return 0;
+    for (int k = fdig < scale ? fdig : scale; k < scale; k++) frac *= 10;
+    __int128 secs = (__int128)civil_days(y, mo, d) * 86400 + h * 3600 + mi * 60 + se - tz;
+    __int128 p10 = 1;
+    for (int k = 0; k < scale; k++) p10 *= 10;
+    __int128 v = secs * p10 + frac;
+    if (v > (__int128)INT64_MAX || v < (__int128)INT64_MIN) return 0;
+    *out = (int64_t)v;
+    return 1;
+}
+
+/* Optional sign, then 1 or more decimal digits, within int64. */
+static int parse_int(const char *s, int64_t n, int64_t *out)
+{
+    int64_t i = 0;
+    int neg = 0;
+    if (i < n && (s[i] == '+' || s[i] == '-')) neg = s[i++] == '-';
+    if (i >= n) return 0;
+    __int128 v = 0;
+    for (; i < n; i++) {
+        if (s[i] < '0' || s[i] > '9') return 0;
+        v = v * 10 + (s[i] - '0');
+        if (v > (__int128)INT64_MAX + 1) return 0;
+    }
+    if (neg) v = -v;
+    if (v > (__int128)INT64_MAX || v < (__int128)INT64_MIN) return 0;
+    *out = (int64_t)v;
+    return 1;
+}
+
+/* Field value: quote characters open and close quoted runs wherever they
+ * stand, a doubled quote inside a run is one literal quote, and the run's
+ * delimiting quotes are dropped.  Writes the value into buf; returns its
+ * length. */
+static int64_t unquote(const char *s, int64_t n, char *buf)
+{
+    int64_t m = 0;
+    int in = 0;
+    for (int64_t i = 0; i < n; i++) {
+        if (s[i] == '"') {
+            if (in && i + 1 < n && s[i + 1] == '"') {
+                buf[m++] = '"';
+                i++;
+            } else {
+                in = !in;
+            }
+        } else {
+            buf[m++] = s[i];
+        }
+    }
+    return m;
+}
+
+typedef struct {
+    const char *p;
+    int64_t len;
+    int64_t row;
+} orc_str;
+
+static int cmp_str_row(const void *pa, const void *pb)
+{
+    const orc_str *a = (const orc_str *)pa, *b = (const orc_str *)pb;
+    int64_t m = a->len < b->len ? a->len : b->len;
+    int c = memcmp(a->p, b->p, (size_t)m);
+    if (c) return c;
+    if (a->len != b->len) return a->len < b->len ? -1 : 1;
+    return (a->row > b->row) - (a->row < b->row);
+}
+
+/* Codes in order of first appearance: sort (value, row), take each value's
+ * first row, rank the values by it. */
+static int64_t factorize(orc_str *v, int64_t rows, int32_t *code, int64_t *first_of_code)
+{
+    orc_str *srt = (orc_str *)malloc((size_t)(rows > 0 ? rows : 1) * sizeof(orc_str));
+    int64_t *grp_first = (int64_t *)malloc((size_t)(rows > 0 ? rows : 1) * sizeof(int64_t));
+    int64_t *grp_of_row = (int64_t *)malloc((size_t)(rows > 0 ? rows : 1) * sizeof(int64_t));
+    memcpy(srt, v, (size_t)rows * sizeof(orc_str));
+    qsort(srt, (size_t)rows, sizeof(orc_str), cmp_str_row);
+    int64_t G = 0;
+    for (int64_t k = 0; k < rows; k++) {
+        if (k == 0 || srt[k].len != srt[k - 1].len || memcmp(srt[k].p, srt[k - 1].p, (size_t)srt[k].len) != 0)
+            grp_first[G++] = srt[k].row;
+        grp_of_row[srt[k].row] = G - 1;
+    }
+    /* the groups' first rows are distinct; the code of a group is the number of
+       groups whose first row comes earlier */
+    int64_t *mark = (int64_t *)malloc((size_t)(rows > 0 ? rows : 1) * sizeof(int64_t));
+    for (int64_t r = 0; r < rows; r++) mark[r] = -1;
+    for (int64_t g = 0; g < G; g++) mark[grp_first[g]] = g;
+    int64_t *code_of_grp = (int64_t *)malloc((size_t)(G > 0 ? G : 1) * sizeof(int64_t));
+    int64_t next = 0;
+    for (int64_t r = 0; r < rows; r++)
+        if (mark[r] >= 0) {
+            code_of_grp[mark[r]] = next;
+            first_of_code[next] = r;
+            next++;
+        }
+    for (int64_t r = 0; r < rows; r++) code[r] = (int32_t)code_of_grp[grp_of_row[r]];
+    free(srt);
+    free(grp_first);
+    free(grp_of_row);
+    free(mark);
+    free(code_of_grp);
+    return G;
+}
+
+/*
+ * orc_ingest_csv: a CSV text (Sec. 2.2: a header row and data rows of values
+ * separated by a separator character) into the columns of an event log.
+ *   lines     a line ends at a newline outside quoted runs (quote characters
+ *             toggle the quoted state wherever they stand), or at the end of
+ *             the text; a trailing carriage return is not part of the line;
+ *             empty lines are skipped; with has_header the first non-empty
+ *             line is the header.
+ *   fields    split at separators outside quoted runs; values as in unquote.
+ *   columns   case_col, act_col, ts_col (0-based); case and activity values
+ *             are coded 0, 1, ... in order of first appearance (byte-exact
+ *             comparison); timestamps are integers (ts_iso == 0) or ISO-8601
+ *             date-times in units of 10^-ts_scale s (ts_iso != 0).
+ * For each code, *_first_off / *_first_len give the byte range of the raw
+ * field (quotes included) in the row of its first appearance.  A data row
+ * with too few fields or a bad timestamp, or an open quoted run at the end of
+ * the text (reported at the last row), is a parse error: the function
+ * returns ORC_E_PARSE with *bad_row the first such data row (0-based).  More
+ * data rows than max_rows: ORC_E_INVALID.
+ */
+int orc_ingest_csv(const char *text, int64_t n_bytes, int32_t case_col, int32_t act_col, int32_t ts_col,
+                   char sep, int32_t has_header, int32_t ts_iso, int32_t ts_scale, int64_t max_rows,
+                   int32_t *case_code, int32_t *act_code, int64_t *ts, int64_t *n_rows,
+                   int64_t *case_first_off, int32_t *case_first_len, int64_t *n_cases,
+                   int64_t *act_first_off, int32_t *act_first_len, int64_t *n_acts, int64_t *bad_row)
+{
+    if (n_bytes < 0 || case_col < 0 || act_col < 0 || ts_col < 0 || ts_scale < 0 || ts_scale > 9 || max_rows < 0)
+        return ORC_E_INVALID;
+    /* lines */
+    int64_t cap_lines = n_bytes / 1 + 1;
+    int64_t *ls = (int64_t *)malloc((size_t)cap_lines * sizeof(int64_t));
+    int64_t *le = (int64_t *)malloc((size_t)cap_lines * sizeof(int64_t));
+    int64_t L = 0, start = 0;
+    int in = 0;
+    for (int64_t i = 0; i <= n_bytes; i++) {
+        int at_end = i == n_bytes;
+        if (!at_end && text[i] == '"') in = !in;
+        if (at_end || (text[i] == '\n' && !in)) {
+            int64_t e = i;
+            if (e > start && text[e - 1] == '\r') e--;
+            if (e > start) {
+                ls[L] = start;
+                le[L] = e;
+                L++;
+            }
+            start = i + 1;
+        }
+    }
+    int open_at_end = in;
+    int64_t first = (has_header && L > 0) ? 1 : 0;
+    int64_t rows = L - first;
+    int rc = ORC_OK;
+    *bad_row = -1;
+    if (rows > max_rows) {
+        free(ls);
+        free(le);
+        return ORC_E_INVALID;
+    }
+    orc_str *cv = (orc_str *)malloc((size_t)(rows > 0 ? rows : 1) * sizeof(orc_str));
+    orc_str *av = (orc_str *)malloc((size_t)(rows > 0 ? rows : 1) * sizeof(orc_str));
+    int64_t *craw = (int64_t *)malloc((size_t)(rows > 0 ? rows : 1) * 2 * sizeof(int64_t));
+    int64_t *araw = (int64_t *)malloc((size_t)(rows > 0 ? rows : 1) * 2 * sizeof(int64_t));
+    char *store = (char *)malloc((size_t)(n_bytes > 0 ? n_bytes : 1) * 2 + 16);
+    int64_t used = 0;
+    int32_t need = case_col;
+    if (act_col > need) need = act_col;
+    if (ts_col > need) need = ts_col;
+    for (int64_t r = 0; r < rows && rc == ORC_OK; r++) {
+        int64_t a = ls[first + r], b = le[first + r];
+        int64_t fb[3] = {-1, -1, -1}, fe[3] = {-1, -1, -1};
+        int32_t f = 0;
+        int q = 0;
+        int64_t fs = a;
+        for (int64_t i = a; i <= b; i++) {
+            if (i < b && text[i] == '"') q = !q;
+            if (i == b || (text[i] == sep && !q)) {
+                if (f == case_col) { fb[0] = fs; fe[0] = i; }
+                if (f == act_col) { fb[1] = fs; fe[1] = i; }
+                if (f == ts_col) { fb[2] = fs; fe[2] = i; }
+                f++;
+                fs = i + 1;
+            }
+        }
+        if (f <= need) {
+            rc = ORC_E_PARSE;
+            *bad_row = r;
+            break;
+        }
+        int64_t k;
+        k = unquote(text + fb[0], fe[0] - fb[0], store + used);
+        cv[r].p = store + used; cv[r].len = k; cv[r].row = r; used += k;
+        craw[2 * r] = fb[0]; craw[2 * r + 1] = fe[0] - fb[0];
+        k = unquote(text + fb[1], fe[1] - fb[1], store + used);
+        av[r].p = store + used; av[r].len = k; av[r].row = r; used += k;
+        araw[2 * r] = fb[1]; araw[2 * r + 1] = fe[1] - fb[1];
+        char tbuf[96];
+        int64_t tl = fe[2] - fb[2];
+        int ok = tl <= 64;
+        if (ok) {
+            k = unquote(text + fb[2], tl, tbuf);
+            ok = ts_iso ? parse_iso(tbuf, k, ts_scale, &ts[r]) : parse_int(tbuf, k, &ts[r]);
+        }
+        if (!ok) {
+            rc = ORC_E_PARSE;
+            *bad_row = r;
+        }
+    }
+    if (rc == ORC_OK && open_at_end && rows > 0) {
+        rc = ORC_E_PARSE;
+        *bad_row = rows - 1;
+    }
+    *n_rows = rows;
+    *n_cases = 0;
+    *n_acts = 0;
+    if (rc == ORC_OK) {
+        int64_t *firsts = (int64_t *)malloc((size_t)(rows > 0 ? rows : 1) * sizeof(int64_t));
+        *n_cases = factorize(cv, rows, case_code, firsts);
+        for (int64_t c = 0; c < *n_cases; c++) {
+            case_first_off[c] = craw[2 * firsts[c]];
+            case_first_len[c] = (int32_t)craw[2 * firsts[c] + 1];
+        }
+        *n_acts = factorize(av, rows, act_code, firsts);
+        for (int64_t c = 0; c < *n_acts; c++) {
+            act_first_off[c] = araw[2 * firsts[c]];
+            act_first_len[c] = (int32_t)araw[2 * firsts[c] + 1];
+        }
+        free(firsts);
+    }
+    free(ls);
+    free(le);
+    free(cv);
+    free(av);
+    free(craw);
+    free(araw);
+    free(store);
+    return rc;
 }

@@ -838,3 +838,139 @@ def test_sample_sizes_nesting_and_uniformity():
         hits[int(oracle.sample(case, act, ts, 1, 1, seed)["case_s"][0])] += 1
     chi2 = float((((hits[1:] - 1000) ** 2) / 1000).sum())
     assert chi2 < 16.3                                      # chi-square, 3 dof, p = 0.001
+
+
+# ---- CSV ingestion ---------------------------------------------------------------
+
+GOLDEN_DIR = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _csv_values(text, offs, lens):
+    return [oracle.csv_value(text[o:o + n]).decode() for o, n in zip(offs, lens)]
+
+
+def test_csv_golden_road_fines():
+    g = json.load(open(os.path.join(GOLDEN_DIR, "worked_road_fines.json")))["csv"]
+    text = open(os.path.join(GOLDEN_DIR, g["file"]), "rb").read()
+    o = oracle.ingest_csv(text, g["case_col"], g["act_col"], g["ts_col"])
+    assert o["n_rows"] == g["n_rows"]
+    assert o["case"].tolist() == g["case"] and o["act"].tolist() == g["act"] and o["ts"].tolist() == g["ts"]
+    assert _csv_values(text, o["case_off"], o["case_len"]) == g["case_values"]
+    assert _csv_values(text, o["act_off"], o["act_len"]) == g["act_values"]
+
+
+_FIELD_CHARS = st.sampled_from(list("ab Z,\"'\t;") + ["é", "中"])
+
+
+def _iso(draw, aware):
+    """An ISO-8601 date-time; aware ones always carry a time and an offset
+    (pandas reads a naive value after an offset one with that offset)."""
+    y = draw(st.integers(1700, 2250))
+    mo = draw(st.integers(1, 12))
+    import calendar
+    d = draw(st.integers(1, calendar.monthrange(y, mo)[1]))
+    s = f"{y:04d}-{mo:02d}-{d:02d}"
+    if aware or draw(st.booleans()):
+        s += draw(st.sampled_from(["T", " "])) + f"{draw(st.integers(0, 23)):02d}:{draw(st.integers(0, 59)):02d}"
+        if draw(st.booleans()):
+            s += f":{draw(st.integers(0, 59)):02d}"
+            if draw(st.booleans()):
+                s += "." + "".join(str(draw(st.integers(0, 9))) for _ in range(draw(st.integers(1, 9))))
+        if aware:
+            s += draw(st.sampled_from(["Z", "+01:00", "-05:30", "+0200", "-03"]))
+    return s
+
+
+@st.composite
+def csv_tables(draw):
+    rows = draw(st.integers(0, 12))
+    ncol = draw(st.integers(3, 5))
+    cols = draw(st.permutations(range(ncol)))[:3]
+    iso = draw(st.booleans())
+    aware = draw(st.booleans())
+    pool_c = draw(st.lists(st.text(_FIELD_CHARS, min_size=1, max_size=6), min_size=1, max_size=4))
+    pool_a = draw(st.lists(st.text(_FIELD_CHARS, min_size=1, max_size=6), min_size=1, max_size=4))
+    table = []
+    for _ in range(rows):
+        row = [draw(st.text(_FIELD_CHARS, max_size=4)) for _ in range(ncol)]
+        row[cols[0]] = draw(st.sampled_from(pool_c))
+        row[cols[1]] = draw(st.sampled_from(pool_a))
+        row[cols[2]] = _iso(draw, aware) if iso else str(draw(st.integers(-(2**62), 2**62)))
+        table.append(row)
+    crlf = draw(st.booleans())
+    blank = draw(st.booleans())
+    return table, cols, iso, crlf, blank, ncol
+
+
+def _to_csv(table, ncol, crlf, blank, quote_all):
+    nl = "\r\n" if crlf else "\n"
+
+    def q(v):
+        if quote_all or any(ch in v for ch in ",\"\r\n") or v == "":
+            return '"' + v.replace('"', '""') + '"'
+        return v
+    lines = [",".join(f"h{k}" for k in range(ncol))]
+    for i, r in enumerate(table):
+        lines.append(",".join(q(v) for v in r))
+        if blank and i == 0:
+            lines.append("")
+    return (nl.join(lines) + nl).encode()
+
+
+@settings(max_examples=200, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(csv_tables(), st.booleans(), st.sampled_from([3, 6, 9]))
+def test_csv_matches_pandas(tab, quote_all, scale):
+    import io
+
+    import pandas as pd
+    table, cols, iso, crlf, blank, ncol = tab
+    text = _to_csv(table, ncol, crlf, blank, quote_all)
+    o = oracle.ingest_csv(text, cols[0], cols[1], cols[2], ts_iso=iso, ts_scale=scale)
+    df = pd.read_csv(io.BytesIO(text), dtype=str, keep_default_na=False, skip_blank_lines=True, encoding="utf-8")
+    assert o["n_rows"] == len(table) == len(df)
+    if not table:
+        return
+    for col, key, off, ln in ((cols[0], "case", "case_off", "case_len"), (cols[1], "act", "act_off", "act_len")):
+        codes, uniques = pd.factorize(df.iloc[:, col], sort=False)
+        assert o[key].tolist() == codes.tolist()
+        assert [v.encode() for v in uniques] == [oracle.csv_value(text[a:a + n]) for a, n in zip(o[off], o[ln])]
+    tcol = df.iloc[:, cols[2]]
+    if iso:
+        ns = pd.to_datetime(tcol, format="ISO8601", utc=True).astype("int64")
+        want = [int(v) // 10 ** (9 - scale) for v in ns]
+    else:
+        want = [int(v) for v in tcol]
+    assert o["ts"].tolist() == want
+
+
+def test_csv_timestamps_against_datetime():
+    import datetime as dt
+    rng = np.random.default_rng(11)
+    epoch = dt.datetime(1970, 1, 1, tzinfo=dt.timezone.utc)
+    lines = ["c,a,t"]
+    want = []
+    for _ in range(2000):
+        x = epoch + dt.timedelta(microseconds=int(rng.integers(-(2**52), 2**52)))
+        off = int(rng.integers(-14 * 60, 14 * 60 + 1))
+        tz = dt.timezone(dt.timedelta(minutes=off))
+        loc = x.astimezone(tz)
+        s = loc.strftime("%Y-%m-%dT%H:%M:%S.%f") + ("+" if off >= 0 else "-") + f"{abs(off) // 60:02d}:{abs(off) % 60:02d}"
+        lines.append(f"1,a,{s}")
+        want.append((x - epoch) // dt.timedelta(microseconds=1))
+    o = oracle.ingest_csv(("\n".join(lines) + "\n").encode(), 0, 1, 2, ts_iso=True, ts_scale=6)
+    assert o["ts"].tolist() == want
+
+
+@pytest.mark.parametrize("text,iso,row", [
+    (b"c,a,t\n1,x,5\n2,y\n3,z,7\n", False, 1),                      # too few fields
+    (b"c,a,t\n1,x,2006-02-28\n2,y,2006-02-30\n", True, 1),          # no such day
+    (b"c,a,t\n1,x,2006-01-01 24:00\n", True, 0),                     # hour out of range
+    (b"c,a,t\n1,x,2006-01-01T10:00+01:00x\n", True, 0),              # trailing bytes
+    (b"c,a,t\n1,x,12a\n", False, 0),                                 # not an integer
+    (b"c,a,t\n1,x,9223372036854775808\n", False, 0),                 # beyond int64
+    (b"c,a,t\n1,x,5\n2,\"y,6\n", False, 1),                         # quoted run open at the end
+])
+def test_csv_parse_errors(text, iso, row):
+    with pytest.raises(oracle.CsvParseError) as e:
+        oracle.ingest_csv(text, 0, 1, 2, ts_iso=iso)
+    assert e.value.row == row
