@@ -59,7 +59,8 @@ enum {
     PM4G_E_NOT_SORTED = -3,  /* PM4G_PRESORTED given but rows are not in (case, ts, row) order */
     PM4G_E_CAPACITY = -4,    /* an output arena is too small; the required size is reported */
     PM4G_E_WORKSPACE = -5,   /* ws_bytes < pm4g_workspace_bytes(...) */
-    PM4G_E_DEVICE = -6       /* a HIP runtime call failed */
+    PM4G_E_DEVICE = -6,      /* a HIP runtime call failed */
+    PM4G_E_PARSE = -7        /* CSV ingestion: a data row could not be parsed */
 };
 
 /* pm4g_log.flags */
@@ -452,6 +453,69 @@ size_t pm4g_sample_workspace_bytes(int64_t n_events);
 int pm4g_sample(const pm4g_prepared *log, int64_t k, uint64_t seed, int32_t by_events, const pm4g_prepared *out,
                 void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * CSV ingestion (Sec. 2.2: a CSV text of a header row and data rows of values
+ * separated by a separator character, parsed by many GPU threads at once into
+ * columns).  text: device bytes of the whole file.  Lines end at newlines
+ * outside quoted runs (quote characters '"' open and close runs wherever they
+ * stand) or at the end of the text; a trailing carriage return is dropped;
+ * empty lines are skipped; with has_header the first non-empty line is the
+ * header.  Fields are split at `sep` outside quoted runs; a field's value
+ * drops the delimiting quotes of its runs and reads a doubled quote inside a
+ * run as one quote.  From every data row:
+ *   case_code, act_code   the case and activity values (columns case_col,
+ *                         act_col, 0-based) coded 0, 1, ... in order of first
+ *                         appearance, byte-exact; per code, *_dict_off and
+ *                         *_dict_len give the byte range of the raw field
+ *                         (quotes included) where the value first appears;
+ *   ts                    column ts_col: an integer (optional sign, within
+ *                         int64) when ts_iso = 0, else an ISO-8601 date-time
+ *                         YYYY-MM-DD[(T| )HH:MM[:SS[(.|,)F]]][Z|+-HH[[:]MM]]
+ *                         (F: 1-9 digits; no offset: UTC) in units of
+ *                         10^-ts_scale s since 1970-01-01T00:00Z, fraction
+ *                         digits below the unit dropped.
+ * The counts (n_rows, n_cases, n_acts) and status / bad_row are device
+ * int64/int32 words.  A data row with fewer fields than the columns need or a
+ * bad timestamp, or a quoted run still open at the end (reported at the last
+ * row), returns PM4G_E_PARSE with *bad_row the first such data row (0-based);
+ * more data rows than out->capacity returns PM4G_E_CAPACITY; nothing else is
+ * valid then.  The case and activity arrays and dictionaries hold
+ * out->capacity entries.  sep must not be '"', '\n' or '\r'.  Values are
+ * matched through a 64-bit hash and then compared byte by byte; if two
+ * different values share a hash, the call repeats with another hash seed.
+ * Synchronises the stream (the counts decide the work).
+ */
+typedef struct {
+    int32_t case_col;
+    int32_t act_col;
+    int32_t ts_col;
+    int32_t has_header;
+    int32_t ts_iso;
+    int32_t ts_scale;
+    char sep;
+    char reserved[7];
+} pm4g_csv_schema;
+
+typedef struct {
+    int32_t *case_code;
+    int32_t *act_code;
+    int64_t *ts;
+    int64_t capacity;
+    int64_t *n_rows;
+    int64_t *case_dict_off;
+    int32_t *case_dict_len;
+    int64_t *n_cases;
+    int64_t *act_dict_off;
+    int32_t *act_dict_len;
+    int64_t *n_acts;
+    int32_t *status;
+    int64_t *bad_row;
+} pm4g_csv_out;
+
+size_t pm4g_ingest_csv_workspace_bytes(int64_t n_bytes, int64_t capacity);
+int pm4g_ingest_csv(const uint8_t *text, int64_t n_bytes, const pm4g_csv_schema *schema, const pm4g_csv_out *out,
+                    void *ws, size_t ws_bytes, void *stream);
+
 /* Text for a status code (static storage). */
 const char *pm4g_status_string(int code);
 
@@ -476,6 +540,15 @@ int pm4g_debug_variant_hash_bits(int bits);
  * Returns the previous setting.
  */
 int64_t pm4g_debug_efg_pass_pairs(int64_t pairs);
+
+/*
+ * Test hook for CSV ingestion: the calling thread's later pm4g_ingest_csv
+ * calls truncate the value hashes of their first matching attempt to `bits`
+ * bits (0 or >= 64: all 64), so that hash collisions, which the byte-by-byte
+ * check detects and a repeat with another seed resolves, can be forced on
+ * small texts.  Results do not depend on it.  Returns the previous setting.
+ */
+int pm4g_debug_csv_hash_bits(int bits);
 
 /*
  * Stage timing for measurement: while enabled (process-wide), every stage of

@@ -16,6 +16,7 @@ namespace {
 thread_local char g_err[512] = "";
 thread_local int g_variant_hash_bits = 0;   // test hook, 0 = full 64-bit hash
 thread_local int64_t g_efg_pass_pairs = 0;  // test hook, 0 = the EFG's full LDS pass length
+thread_local int g_csv_hash_bits = 0;       // test hook, 0 = full 64-bit value hashes
 
 void set_err(const char* fmt, ...) {
     va_list ap;
@@ -313,6 +314,12 @@ int pm4g_debug_variant_hash_bits(int bits) {
     return old;
 }
 
+int pm4g_debug_csv_hash_bits(int bits) {
+    const int old = g_csv_hash_bits;
+    g_csv_hash_bits = (bits < 0 || bits >= 64) ? 0 : bits;
+    return old;
+}
+
 int64_t pm4g_debug_efg_pass_pairs(int64_t pairs) {
     const int64_t old = g_efg_pass_pairs;
     g_efg_pass_pairs = pairs > 0 ? pairs : 0;
@@ -328,6 +335,7 @@ const char* pm4g_status_string(int code) {
         case PM4G_E_CAPACITY: return "output capacity exceeded";
         case PM4G_E_WORKSPACE: return "workspace too small";
         case PM4G_E_DEVICE: return "HIP runtime error";
+        case PM4G_E_PARSE: return "CSV parse error";
         default: return "unknown status";
     }
 }
@@ -462,6 +470,61 @@ int pm4g_sample(const pm4g_prepared* log, int64_t k, uint64_t seed, int32_t by_e
     } else {
         CaseFilterWs w = case_filter_ws_layout(bp, log->n_events);
         PM4G_HIP(launch_sample_cases(log, seed, sel, out, w, s));
+    }
+    return PM4G_OK;
+}
+
+size_t pm4g_ingest_csv_workspace_bytes(int64_t n_bytes, int64_t capacity) {
+    if (n_bytes < 0 || capacity < 0 || capacity > kMaxEvents) return 0;
+    Bump b(nullptr);
+    csv_ws_layout(b, n_bytes, capacity);
+    return b.off + 256;
+}
+
+int pm4g_ingest_csv(const uint8_t* text, int64_t n_bytes, const pm4g_csv_schema* sc, const pm4g_csv_out* out,
+                    void* ws, size_t ws_size, void* stream) {
+    PM4G_CHECK(n_bytes >= 0 && (n_bytes == 0 || text), "text is NULL or n_bytes < 0");
+    PM4G_CHECK(sc != nullptr && out != nullptr, "schema or out is NULL");
+    PM4G_CHECK(sc->case_col >= 0 && sc->act_col >= 0 && sc->ts_col >= 0, "a column index is negative");
+    PM4G_CHECK(sc->ts_iso == 0 || sc->ts_iso == 1, "ts_iso must be 0 or 1");
+    PM4G_CHECK(sc->ts_scale >= 0 && sc->ts_scale <= 9, "ts_scale outside [0, 9]");
+    PM4G_CHECK(sc->sep != '"' && sc->sep != '\n' && sc->sep != '\r', "the separator cannot be a quote or a line end");
+    PM4G_CHECK(out->capacity >= 0 && out->capacity <= kMaxEvents, "capacity outside [0, 2^31)");
+    PM4G_CHECK(out->n_rows && out->n_cases && out->n_acts && out->status && out->bad_row &&
+                   (out->capacity == 0 || (out->case_code && out->act_code && out->ts && out->case_dict_off &&
+                                           out->case_dict_len && out->act_dict_off && out->act_dict_len)),
+               "a CSV output array is NULL");
+    const size_t need = pm4g_ingest_csv_workspace_bytes(n_bytes, out->capacity);
+    if (ws_size < need || !ws) {
+        set_err("workspace of %zu bytes, %zu needed", ws_size, need);
+        return PM4G_E_WORKSPACE;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    ProfScope ps(P_CSV, s);
+    Bump bp(ws);
+    CsvWs w = csv_ws_layout(bp, n_bytes, out->capacity);
+    PM4G_HIP(launch_csv_lines(text, n_bytes, sc->has_header, out->capacity, w, s));
+    int64_t sc_host[16];
+    // values are matched by 64-bit hash, then checked byte by byte; a collision
+    // (two values, one hash) repeats the matching with the next seed
+    for (uint64_t attempt = 0;; ++attempt) {
+        PM4G_HIP(launch_csv_parse(text, *sc, 0x5851F42D4C957F2Dull * (attempt + 1), attempt == 0 ? g_csv_hash_bits : 0,
+                                  out->capacity, w, *out, s));
+        PM4G_HIP(hipMemcpyAsync(sc_host, w.scal, sizeof(sc_host), hipMemcpyDeviceToHost, s));
+        PM4G_HIP(hipStreamSynchronize(s));
+        if (sc_host[6] || sc_host[3] != INT64_MAX || !sc_host[4]) break;
+        PM4G_CHECK(attempt < 8, "value hashes kept colliding");
+    }
+    if (!sc_host[6] && sc_host[3] == INT64_MAX) PM4G_HIP(launch_csv_codes(w, out->capacity, *out, s));
+    PM4G_HIP(launch_csv_finish(w, *out, s));
+    PM4G_HIP(hipStreamSynchronize(s));
+    if (sc_host[6]) {
+        set_err("more than %lld data rows", (long long)out->capacity);
+        return PM4G_E_CAPACITY;
+    }
+    if (sc_host[3] != INT64_MAX) {
+        set_err("CSV parse error at data row %lld", (long long)sc_host[3]);
+        return PM4G_E_PARSE;
     }
     return PM4G_OK;
 }

@@ -1,0 +1,569 @@
+// CSV ingestion into the columns of an event log (Sec. 2.2: a CSV holds a
+// header row and data rows of separator-delimited values; the GPU parses
+// different parts of the text at once).
+//
+//   lines     quote characters toggle a quoted state wherever they stand; a
+//             line ends at a newline outside quotes (or at the end of the
+//             text), without a trailing carriage return; empty lines are
+//             skipped; with a header the first non-empty line is skipped.
+//   values    fields split at separators outside quotes; a field's value
+//             drops the delimiting quotes of its quoted runs and reads a
+//             doubled quote inside a run as one quote.
+//   columns   case and activity values coded 0, 1, ... in order of first
+//             appearance (byte-exact); timestamps integers or ISO-8601
+//             date-times in units of 10^-scale s.
+//
+// Kernels:
+//   k_csv_quotes     per 4096-byte tile: the parity of its quote characters
+//   scan             quote parity at each tile's start
+//   k_csv_lines      per tile: ends of non-empty lines (newlines at even
+//                    parity), counted, then written in order after a scan
+//   k_csv_close      the unterminated last line, row count, capacity
+//   k_csv_parse      a thread per data row: field ranges, value hashes, the
+//                    timestamp; values enter open-addressing tables keyed by
+//                    64-bit hash, each slot keeping its first row
+//   k_csv_verify     every row's value against its slot's first row, byte by
+//                    byte (a hash collision is detected, and the call is
+//                    repeated with another hash seed)
+//   codes            the used slots sorted by first row: the code is the rank
+//   k_csv_emit       codes per row
+// Bytes: the text is read three times by the tile passes and once more by the
+// row pass (plus the first rows' values once); 16 B/row written.
+#include "common.hpp"
+#include "devsort.hpp"
+#include "internal.hpp"
+#include "prof.hpp"
+#include "../../include/pm4g.h"
+
+namespace pm4g {
+
+namespace {
+
+constexpr int kCT = 4096;              // bytes per tile
+constexpr int kCTB = 256;              // threads per tile block
+constexpr int kCPer = kCT / kCTB;      // 16 bytes per thread
+constexpr int kTsMax = 64;             // longest timestamp value
+
+int64_t pow2_at_least(int64_t x) {
+    int64_t p = 1024;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+CsvWs csv_ws_layout(Bump& b, int64_t n_bytes, int64_t max_rows) {
+    CsvWs w{};
+    const int64_t tiles = (n_bytes + kCT - 1) / kCT;
+    const size_t t1 = (size_t)(tiles > 0 ? tiles : 1) + 1;
+    const size_t rows = (size_t)(max_rows > 0 ? max_rows : 1);
+    w.tsize = pow2_at_least(2 * (max_rows > 0 ? max_rows : 1));
+    w.qpar = b.take<uint32_t>(t1);
+    w.qpre = b.take<uint32_t>(t1);
+    w.lcnt = b.take<uint32_t>(t1);
+    w.loff = b.take<int64_t>(t1);
+    w.line_end = b.take<int64_t>(rows + 2);
+    w.foff = b.take<int64_t>(2 * rows);
+    w.flen = b.take<int32_t>(2 * rows);
+    w.slot = b.take<uint32_t>(2 * rows);
+    w.table = b.take<CsvSlot>((size_t)(2 * w.tsize));
+    w.used = b.take<uint32_t>((size_t)w.tsize);
+    w.pos = b.take<uint32_t>((size_t)w.tsize);
+    w.k0 = b.take<uint32_t>(rows);
+    w.v0 = b.take<uint32_t>(rows);
+    w.k1 = b.take<uint32_t>(rows);
+    w.v1 = b.take<uint32_t>(rows);
+    w.hist = b.take<uint32_t>((size_t)256 * (size_t)dev::tiles((int64_t)rows));
+    w.rowsum = b.take<uint32_t>(256);
+    w.part32 = b.take<uint32_t>(dev::kScanGrid);
+    w.part64 = b.take<int64_t>(dev::kScanGrid);
+    w.scal = b.take<int64_t>(16);
+    return w;
+}
+
+namespace {
+
+// scal: [0] tiles, [1] lines found by the tile pass, [2] data rows, [3] first
+// bad row (INT64_MAX: none), [4] hash collision seen, [5] distinct values (case
+// table, then activity table), [6] rows over capacity, [7] quote parity at
+// the end, [8] table slots, [9] line capacity
+__global__ void k_csv_init(CsvWs w, int64_t n_bytes, int64_t max_lines) {
+    w.scal[0] = (n_bytes + kCT - 1) / kCT;
+    w.scal[1] = 0;
+    w.scal[2] = 0;
+    w.scal[3] = INT64_MAX;
+    w.scal[4] = 0;
+    w.scal[5] = 0;
+    w.scal[6] = 0;
+    w.scal[7] = 0;
+    w.scal[8] = w.tsize;
+    w.scal[9] = max_lines;
+}
+
+__global__ __launch_bounds__(256) void k_csv_clear(CsvWs w) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) w.scal[4] = 0;   // collision flag of this attempt
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < 2 * w.tsize; i += (int64_t)gridDim.x * 256) {
+        w.table[i].hash = 0;
+        w.table[i].first = 0xffffffffu;
+        w.table[i].code = 0;
+    }
+}
+
+// The 16 bytes of thread t of a tile (zero past the end).
+__device__ __forceinline__ void load16(const uint8_t* __restrict__ text, int64_t n, int64_t p, uint8_t* b) {
+    if (p + kCPer <= n && ((reinterpret_cast<uintptr_t>(text + p) & 15) == 0)) {
+        const uint4 v = *reinterpret_cast<const uint4*>(text + p);
+        const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 16; ++k) b[k] = (uint8_t)(u[k >> 2] >> (8 * (k & 3)));
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) b[k] = (p + k < n) ? text[p + k] : 0;
+    }
+}
+
+__global__ __launch_bounds__(kCTB) void k_csv_quotes(const uint8_t* __restrict__ text, int64_t n, CsvWs w) {
+    __shared__ uint32_t red[kCTB / kWave];
+    const int64_t tiles = w.scal[0];
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        uint8_t b[16];
+        load16(text, n, t * kCT + (int64_t)threadIdx.x * kCPer, b);
+        uint32_t q = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) q += b[k] == '"';
+        q = wave_sum(q);
+        if (lane() == 0) red[threadIdx.x / kWave] = q;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t s = 0;
+            for (int k = 0; k < kCTB / kWave; ++k) s += red[k];
+            w.qpar[t] = s & 1u;
+        }
+        __syncthreads();
+    }
+}
+
+// Non-empty line ends of each tile: count (write == 0) or positions.
+__global__ __launch_bounds__(kCTB) void k_csv_lines(const uint8_t* __restrict__ text, int64_t n, CsvWs w,
+                                                    int write) {
+    __shared__ uint32_t tmp[kCTB / kWave + 1];
+    const int64_t tiles = w.scal[0];
+    const int64_t cap = w.scal[9];
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const int64_t p0 = t * kCT + (int64_t)threadIdx.x * kCPer;
+        uint8_t b[16];
+        load16(text, n, p0, b);
+        uint32_t q = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) q += b[k] == '"';
+        uint32_t qt;
+        const uint32_t qx = block_excl_sum<kCTB>(q, tmp, &qt);
+        uint32_t par = (w.qpre[t] + qx) & 1u;
+        uint32_t ends = 0;   // bit k: byte k ends a non-empty line
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int64_t p = p0 + k;
+            if (p < n) {
+                if (b[k] == '"') {
+                    par ^= 1u;
+                } else if (b[k] == '\n' && par == 0) {
+                    // empty when the line is "" or "\r" after a line end (newlines
+                    // and carriage returns are not quotes: same parity)
+                    const uint8_t c1 = p >= 1 ? (k >= 1 ? b[k - 1] : text[p - 1]) : '\n';
+                    const uint8_t c2 = p >= 2 ? (k >= 2 ? b[k - 2] : text[p - 2]) : '\n';
+                    const bool empty = p == 0 || c1 == '\n' || (c1 == '\r' && (p == 1 || c2 == '\n'));
+                    if (!empty) ends |= 1u << k;
+                }
+            }
+        }
+        uint32_t lt;
+        const uint32_t lx = block_excl_sum<kCTB>((uint32_t)__popc(ends), tmp, &lt);
+        if (!write) {
+            if (threadIdx.x == 0) w.lcnt[t] = lt;
+        } else {
+            int64_t r = w.loff[t] + lx;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                if ((ends >> k) & 1u) {
+                    if (r < cap) w.line_end[r] = p0 + k;
+                    ++r;
+                }
+            }
+        }
+    }
+}
+
+// The last line when the text does not end with a line end, the data rows,
+// capacity, and an open quoted run at the end (an error on the last row).
+__global__ void k_csv_close(const uint8_t* __restrict__ text, int64_t n, CsvWs w, int has_header,
+                            int64_t max_rows) {
+    int64_t L = w.scal[1];
+    const uint32_t par_end = w.scal[7] & 1;
+    if (n > 0) {
+        const uint8_t c1 = text[n - 1];
+        const bool ends_on_newline = c1 == '\n' && par_end == 0;
+        const bool only_cr = c1 == '\r' && (n == 1 || text[n - 2] == '\n') && par_end == 0;
+        if (!ends_on_newline && !only_cr) {
+            if (L < w.scal[9]) w.line_end[L] = n;
+            ++L;
+        }
+    }
+    const int64_t rows = L - ((has_header && L > 0) ? 1 : 0);
+    w.scal[1] = L;
+    w.scal[2] = rows;
+    if (rows > max_rows) {
+        w.scal[6] = 1;
+        w.scal[2] = 0;   // nothing parsed
+    } else if (par_end && rows > 0) {
+        w.scal[3] = rows - 1;
+    }
+}
+
+// ---- values ----
+
+// Iterates the value bytes of a raw field (quoted runs unwrapped).
+struct Unquote {
+    const uint8_t* s;
+    int64_t i, e;
+    bool in;
+    __device__ __forceinline__ Unquote(const uint8_t* text, int64_t b, int64_t end) : s(text), i(b), e(end), in(false) {}
+    // next value byte into *c; false at the end
+    __device__ __forceinline__ bool next(uint8_t* c) {
+        while (i < e) {
+            const uint8_t x = s[i++];
+            if (x != '"') {
+                *c = x;
+                return true;
+            }
+            if (in && i < e && s[i] == '"') {
+                ++i;
+                *c = '"';
+                return true;
+            }
+            in = !in;
+        }
+        return false;
+    }
+};
+
+__device__ __forceinline__ uint64_t value_hash(const uint8_t* text, int64_t b, int64_t e, uint64_t seed,
+                                               uint64_t mask) {
+    // FNV-1a over the value bytes from a seeded basis, then a SplitMix64 finish
+    uint64_t h = 0xcbf29ce484222325ull ^ seed;
+    Unquote u(text, b, e);
+    uint8_t c;
+    while (u.next(&c)) {
+        h ^= c;
+        h *= 0x100000001b3ull;
+    }
+    h = splitmix64(seed, h) & mask;
+    return h ? h : 1;
+}
+
+__device__ bool same_value(const uint8_t* text, int64_t b1, int64_t e1, int64_t b2, int64_t e2) {
+    Unquote u1(text, b1, e1), u2(text, b2, e2);
+    uint8_t c1, c2;
+    for (;;) {
+        const bool m1 = u1.next(&c1), m2 = u2.next(&c2);
+        if (m1 != m2) return false;
+        if (!m1) return true;
+        if (c1 != c2) return false;
+    }
+}
+
+// ---- timestamps ----
+
+// Days between 1970-01-01 and y-m-d (proleptic Gregorian): years counted from
+// March so that February's leap day closes a year, 400-year eras of 146097
+// days.
+__device__ __forceinline__ int64_t days_since_epoch(int64_t y, int64_t m, int64_t d) {
+    const int64_t yy = m <= 2 ? y - 1 : y;
+    const int64_t era = (yy >= 0 ? yy : yy - 399) / 400;
+    const int64_t yoe = yy - era * 400;
+    const int64_t mp = m > 2 ? m - 3 : m + 9;                  // months since March
+    const int64_t doy = (153 * mp + 2) / 5 + d - 1;
+    const int64_t doe = 365 * yoe + yoe / 4 - yoe / 100 + doy;
+    return era * 146097 + doe - 719468;
+}
+
+__device__ __forceinline__ bool leap(int64_t y) { return (y % 4 == 0 && y % 100 != 0) || y % 400 == 0; }
+
+__device__ __forceinline__ int month_days(int64_t y, int64_t m) {
+    if (m == 2) return leap(y) ? 29 : 28;
+    return (m == 4 || m == 6 || m == 9 || m == 11) ? 30 : 31;
+}
+
+struct Cursor {
+    const uint8_t* v;
+    int n, i;
+    __device__ __forceinline__ bool digits(int k, int64_t* out) {
+        int64_t x = 0;
+        for (int j = 0; j < k; ++j) {
+            if (i >= n || v[i] < '0' || v[i] > '9') return false;
+            x = x * 10 + (v[i++] - '0');
+        }
+        *out = x;
+        return true;
+    }
+    __device__ __forceinline__ bool is(uint8_t c) const { return i < n && v[i] == c; }
+    __device__ __forceinline__ bool take(uint8_t c) {
+        if (!is(c)) return false;
+        ++i;
+        return true;
+    }
+};
+
+__device__ bool iso_value(const uint8_t* v, int n, int scale, int64_t* out) {
+    Cursor c{v, n, 0};
+    int64_t y, mo, d, hh = 0, mi = 0, ss = 0, frac = 0, off = 0;
+    if (!c.digits(4, &y) || !c.take('-') || !c.digits(2, &mo) || !c.take('-') || !c.digits(2, &d)) return false;
+    if (mo < 1 || mo > 12 || d < 1 || d > month_days(y, mo)) return false;
+    int nf = 0;
+    if (c.is('T') || c.is(' ')) {
+        ++c.i;
+        if (!c.digits(2, &hh) || !c.take(':') || !c.digits(2, &mi)) return false;
+        if (c.take(':')) {
+            if (!c.digits(2, &ss)) return false;
+            if (c.is('.') || c.is(',')) {
+                ++c.i;
+                while (c.i < n && v[c.i] >= '0' && v[c.i] <= '9') {
+                    if (nf == 9) return false;
+                    if (nf < scale) frac = frac * 10 + (v[c.i] - '0');
+                    ++nf;
+                    ++c.i;
+                }
+                if (nf == 0) return false;
+            }
+        }
+        if (hh > 23 || mi > 59 || ss > 59) return false;
+        if (c.take('Z')) {
+        } else if (c.is('+') || c.is('-')) {
+            const int64_t sg = v[c.i] == '-' ? -1 : 1;
+            ++c.i;
+            int64_t oh, om = 0;
+            if (!c.digits(2, &oh)) return false;
+            c.take(':');
+            if (c.i < n && !c.digits(2, &om)) return false;
+            if (oh > 23 || om > 59) return false;
+            off = sg * (oh * 3600 + om * 60);
+        }
+    }
+    if (c.i != n) return false;
+    for (int k = nf < scale ? nf : scale; k < scale; ++k) frac *= 10;
+    const int64_t secs = days_since_epoch(y, mo, d) * 86400 + hh * 3600 + mi * 60 + ss - off;
+    __int128 p10 = 1;
+    for (int k = 0; k < scale; ++k) p10 *= 10;
+    const __int128 x = (__int128)secs * p10 + frac;   // must stay in int64
+    if (x > (__int128)INT64_MAX || x < (__int128)INT64_MIN) return false;
+    *out = (int64_t)x;
+    return true;
+}
+
+__device__ bool int_value(const uint8_t* v, int n, int64_t* out) {
+    int i = 0;
+    bool neg = false;
+    if (i < n && (v[i] == '+' || v[i] == '-')) neg = v[i++] == '-';
+    if (i >= n) return false;
+    uint64_t x = 0;
+    const uint64_t lim = neg ? (uint64_t)INT64_MAX + 1 : (uint64_t)INT64_MAX;
+    for (; i < n; ++i) {
+        if (v[i] < '0' || v[i] > '9') return false;
+        const uint64_t dgt = (uint64_t)(v[i] - '0');
+        if (x > (lim - dgt) / 10) return false;
+        x = x * 10 + dgt;
+    }
+    *out = neg ? (int64_t)(0 - x) : (int64_t)x;
+    return true;
+}
+
+__device__ __forceinline__ void flag_bad(CsvWs& w, int64_t r) {
+    atomicMin(reinterpret_cast<unsigned long long*>(&w.scal[3]), (unsigned long long)r);
+}
+
+// Slot of value hash h in table `tab` (linear probing); the slot keeps the
+// smallest row that holds the value.
+__device__ __forceinline__ uint32_t insert(CsvSlot* tab, int64_t tsize, uint64_t h, uint32_t r) {
+    uint64_t i = h & (uint64_t)(tsize - 1);
+    for (;;) {   // the table has more slots than rows: an empty or equal slot exists
+        const unsigned long long cur =
+            atomicCAS(reinterpret_cast<unsigned long long*>(&tab[i].hash), 0ull, (unsigned long long)h);
+        if (cur == 0 || cur == h) {
+            atomicMin(&tab[i].first, r);
+            return (uint32_t)i;
+        }
+        i = (i + 1) & (uint64_t)(tsize - 1);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_csv_parse(const uint8_t* __restrict__ text, CsvWs w,
+                                                   pm4g_csv_schema sc, uint64_t seed, uint64_t mask,
+                                                   int64_t* __restrict__ ts_out) {
+    const int64_t rows = w.scal[2];
+    const int64_t hdr = (sc.has_header && w.scal[1] > 0) ? 1 : 0;
+    const int32_t need = sc.case_col > sc.act_col ? (sc.case_col > sc.ts_col ? sc.case_col : sc.ts_col)
+                                                   : (sc.act_col > sc.ts_col ? sc.act_col : sc.ts_col);
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < rows; r += (int64_t)gridDim.x * 256) {
+        const int64_t li = r + hdr;
+        int64_t a = li == 0 ? 0 : w.line_end[li - 1] + 1;
+        int64_t e = w.line_end[li];
+        // skip the empty lines in between ("\n" or "\r\n" each)
+        while (a < e && (text[a] == '\n' || (text[a] == '\r' && a + 1 < e && text[a + 1] == '\n'))) ++a;
+        if (e > a && text[e - 1] == '\r') --e;
+        int64_t fb[3] = {-1, -1, -1}, fe[3] = {-1, -1, -1};
+        int32_t f = 0;
+        bool q = false;
+        int64_t fs = a;
+        for (int64_t i = a; i <= e; ++i) {
+            const uint8_t c = i < e ? text[i] : (uint8_t)sc.sep;
+            if (i < e && c == '"') q = !q;
+            if (i == e || (c == (uint8_t)sc.sep && !q)) {
+                if (f == sc.case_col) { fb[0] = fs; fe[0] = i; }
+                if (f == sc.act_col) { fb[1] = fs; fe[1] = i; }
+                if (f == sc.ts_col) { fb[2] = fs; fe[2] = i; }
+                ++f;
+                fs = i + 1;
+            }
+        }
+        if (f <= need) {
+            flag_bad(w, r);
+            w.slot[2 * r] = w.slot[2 * r + 1] = 0;
+            continue;
+        }
+        for (int k = 0; k < 2; ++k) {
+            w.foff[2 * r + k] = fb[k];
+            w.flen[2 * r + k] = (int32_t)(fe[k] - fb[k]);
+            const uint64_t h = value_hash(text, fb[k], fe[k], seed, mask);
+            w.slot[2 * r + k] = insert(w.table + k * w.tsize, w.tsize, h, (uint32_t)r);
+        }
+        uint8_t tv[kTsMax];
+        int tn = 0;
+        bool ok = fe[2] - fb[2] <= kTsMax;
+        if (ok) {
+            Unquote u(text, fb[2], fe[2]);
+            uint8_t c;
+            while (u.next(&c)) tv[tn++] = c;
+            int64_t t;
+            ok = sc.ts_iso ? iso_value(tv, tn, sc.ts_scale, &t) : int_value(tv, tn, &t);
+            if (ok) ts_out[r] = t;
+        }
+        if (!ok) flag_bad(w, r);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_csv_verify(const uint8_t* __restrict__ text, CsvWs w) {
+    const int64_t rows = w.scal[2];
+    if (w.scal[3] != INT64_MAX) return;   // a parse error ends the call
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < rows; r += (int64_t)gridDim.x * 256) {
+        for (int k = 0; k < 2; ++k) {
+            const uint32_t first = w.table[k * w.tsize + w.slot[2 * r + k]].first;
+            if (first == (uint32_t)r) continue;
+            const int64_t b1 = w.foff[2 * r + k], e1 = b1 + w.flen[2 * r + k];
+            const int64_t b2 = w.foff[2 * (int64_t)first + k], e2 = b2 + w.flen[2 * (int64_t)first + k];
+            if (!same_value(text, b1, e1, b2, e2)) w.scal[4] = 1;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_csv_used(CsvWs w, int k) {
+    const CsvSlot* tab = w.table + k * w.tsize;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < w.tsize; i += (int64_t)gridDim.x * 256)
+        w.used[i] = tab[i].hash != 0 ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_csv_list(CsvWs w, int k, const uint32_t* __restrict__ pos) {
+    const CsvSlot* tab = w.table + k * w.tsize;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < w.tsize; i += (int64_t)gridDim.x * 256)
+        if (w.used[i]) {
+            w.k0[pos[i]] = tab[i].first;
+            w.v0[pos[i]] = (uint32_t)i;
+        }
+}
+
+// Sorted by first row: the code of a slot is its rank.
+__global__ __launch_bounds__(256) void k_csv_codes(CsvWs w, int k, const uint32_t* __restrict__ key,
+                                                   const uint32_t* __restrict__ val, int64_t* __restrict__ dict_off,
+                                                   int32_t* __restrict__ dict_len, int64_t* n_dict) {
+    CsvSlot* tab = w.table + k * w.tsize;
+    const int64_t D = w.scal[5];
+    for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < D; d += (int64_t)gridDim.x * 256) {
+        tab[val[d]].code = (uint32_t)d;
+        const int64_t r = key[d];
+        dict_off[d] = w.foff[2 * r + k];
+        dict_len[d] = w.flen[2 * r + k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *n_dict = D;
+}
+
+__global__ __launch_bounds__(256) void k_csv_emit(CsvWs w, int32_t* __restrict__ case_code,
+                                                  int32_t* __restrict__ act_code) {
+    const int64_t rows = w.scal[2];
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < rows; r += (int64_t)gridDim.x * 256) {
+        case_code[r] = (int32_t)w.table[w.slot[2 * r]].code;
+        act_code[r] = (int32_t)w.table[w.tsize + w.slot[2 * r + 1]].code;
+    }
+}
+
+__global__ void k_csv_finish(CsvWs w, int64_t* n_rows, int32_t* status, int64_t* bad_row) {
+    const bool over = w.scal[6] != 0, bad = w.scal[3] != INT64_MAX;
+    *n_rows = (over || bad) ? 0 : w.scal[2];
+    *bad_row = bad ? w.scal[3] : -1;
+    *status = over ? PM4G_E_CAPACITY : (bad ? PM4G_E_PARSE : 0);
+}
+
+unsigned grid_rows(int64_t rows) {
+    const int64_t g = (rows + 255) / 256;
+    return (unsigned)(g < 2048 ? (g < 1 ? 1 : g) : 2048);
+}
+
+}  // namespace
+
+hipError_t launch_csv_lines(const uint8_t* text, int64_t n_bytes, int has_header, int64_t max_rows, CsvWs w,
+                            hipStream_t s) {
+    const int64_t tiles = (n_bytes + kCT - 1) / kCT;
+    const unsigned gt = (unsigned)(tiles < 2048 ? (tiles < 1 ? 1 : tiles) : 2048);
+    k_csv_init<<<1, 1, 0, s>>>(w, n_bytes, max_rows + 1);
+    k_csv_quotes<<<gt, kCTB, 0, s>>>(text, n_bytes, w);
+    dev::excl_scan<uint32_t>(w.qpar, &w.scal[0], w.qpre, w.part32, reinterpret_cast<uint32_t*>(&w.scal[7]), s);
+    k_csv_lines<<<gt, kCTB, 0, s>>>(text, n_bytes, w, 0);
+    dev::excl_scan<int64_t>(w.lcnt, &w.scal[0], w.loff, w.part64, &w.scal[1], s);
+    k_csv_lines<<<gt, kCTB, 0, s>>>(text, n_bytes, w, 1);
+    k_csv_close<<<1, 1, 0, s>>>(text, n_bytes, w, has_header, max_rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_csv_parse(const uint8_t* text, const pm4g_csv_schema& sc, uint64_t seed, int hash_bits,
+                            int64_t max_rows, CsvWs w, const pm4g_csv_out& o, hipStream_t s) {
+    const uint64_t mask = (hash_bits <= 0 || hash_bits >= 64) ? ~0ull : ((1ull << hash_bits) - 1);
+    const unsigned gr = grid_rows(max_rows);
+    k_csv_clear<<<2048, 256, 0, s>>>(w);
+    k_csv_parse<<<gr, 256, 0, s>>>(text, w, sc, seed, mask, o.ts);
+    k_csv_verify<<<gr, 256, 0, s>>>(text, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_csv_codes(CsvWs w, int64_t max_rows, const pm4g_csv_out& o, hipStream_t s) {
+    const int64_t ts = w.tsize;
+    const unsigned gs = (unsigned)((ts + 255) / 256 < 2048 ? (ts + 255) / 256 : 2048);
+    for (int k = 0; k < 2; ++k) {
+        k_csv_used<<<gs, 256, 0, s>>>(w, k);
+        // positions of the used slots (one per table slot); their number -> scal[5]
+        dev::excl_scan<uint32_t>(w.used, &w.scal[8], w.pos, w.part32, reinterpret_cast<uint32_t*>(&w.scal[5]), s);
+        k_csv_list<<<gs, 256, 0, s>>>(w, k, w.pos);
+        const bool flip = dev::sort_pairs<uint32_t>(w.k0, w.v0, w.k1, w.v1, &w.scal[5], max_rows, 32, w.hist,
+                                                    w.rowsum, s);
+        const uint32_t* key = flip ? w.k1 : w.k0;
+        const uint32_t* val = flip ? w.v1 : w.v0;
+        k_csv_codes<<<grid_rows(max_rows), 256, 0, s>>>(w, k, key, val, k == 0 ? o.case_dict_off : o.act_dict_off,
+                                                        k == 0 ? o.case_dict_len : o.act_dict_len,
+                                                        k == 0 ? o.n_cases : o.n_acts);
+    }
+    k_csv_emit<<<grid_rows(max_rows), 256, 0, s>>>(w, o.case_code, o.act_code);
+    return hipGetLastError();
+}
+
+hipError_t launch_csv_finish(CsvWs w, const pm4g_csv_out& o, hipStream_t s) {
+    k_csv_finish<<<1, 1, 0, s>>>(w, o.n_rows, o.status, o.bad_row);
+    return hipGetLastError();
+}
+
+}  // namespace pm4g

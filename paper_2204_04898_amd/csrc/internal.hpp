@@ -358,4 +358,40 @@ hipError_t launch_sample_events(const pm4g_prepared* p, uint64_t seed, const Sel
 hipError_t launch_sample_cases(const pm4g_prepared* p, uint64_t seed, const SelState* sel,
                                const pm4g_prepared* out, CaseFilterWs w, hipStream_t s);
 
+
+// ---- CSV ingestion (csv.hip) ----
+struct CsvSlot {
+    uint64_t hash;    // 0: empty
+    uint32_t first;   // first row holding the value
+    uint32_t code;
+};
+struct CsvWs {
+    int64_t tsize;        // slots per table (power of two, at least twice the rows)
+    uint32_t* qpar;       // [tiles] quote parity
+    uint32_t* qpre;       // [tiles] parity before the tile
+    uint32_t* lcnt;       // [tiles] line ends
+    int64_t* loff;        // [tiles]
+    int64_t* line_end;    // [rows + 2]
+    int64_t* foff;        // [rows][2] raw field start (case, activity)
+    int32_t* flen;        // [rows][2] raw field length
+    uint32_t* slot;       // [rows][2] table slot
+    CsvSlot* table;       // [2][tsize] case table, activity table
+    uint32_t* used;       // [tsize] slot holds a value
+    uint32_t* pos;        // [tsize] its rank among the used slots
+    uint32_t *k0, *v0, *k1, *v1;   // [rows] (first row, slot) pairs to sort
+    uint32_t* hist;
+    uint32_t* rowsum;
+    uint32_t* part32;
+    int64_t* part64;
+    int64_t* scal;
+};
+CsvWs csv_ws_layout(Bump& b, int64_t n_bytes, int64_t max_rows);
+hipError_t launch_csv_lines(const uint8_t* text, int64_t n_bytes, int has_header, int64_t max_rows, CsvWs w,
+                            hipStream_t s);
+// hash_bits: value hashes truncated to that many bits (0: all 64; a test hook)
+hipError_t launch_csv_parse(const uint8_t* text, const pm4g_csv_schema& sc, uint64_t seed, int hash_bits,
+                            int64_t max_rows, CsvWs w, const pm4g_csv_out& o, hipStream_t s);
+hipError_t launch_csv_codes(CsvWs w, int64_t max_rows, const pm4g_csv_out& o, hipStream_t s);
+hipError_t launch_csv_finish(CsvWs w, const pm4g_csv_out& o, hipStream_t s);
+
 }  // namespace pm4g

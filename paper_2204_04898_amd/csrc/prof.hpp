@@ -36,6 +36,7 @@ enum ProfId {
     P_DF_FILTER,
     P_EFG,
     P_SAMPLE,
+    P_CSV,
     P_COUNT
 };
 

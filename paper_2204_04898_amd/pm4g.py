@@ -28,6 +28,7 @@ PM4G_E_NOT_SORTED = -3
 PM4G_E_CAPACITY = -4
 PM4G_E_WORKSPACE = -5
 PM4G_E_DEVICE = -6
+PM4G_E_PARSE = -7
 PM4G_PRESORTED = 1
 PM4G_MAX_ACTIVITIES = 4096
 
@@ -89,6 +90,18 @@ class _EfgOut(ctypes.Structure):
                                   "status")]
 
 
+class CsvSchema(ctypes.Structure):
+    _fields_ = [("case_col", ctypes.c_int32), ("act_col", ctypes.c_int32), ("ts_col", ctypes.c_int32),
+                ("has_header", ctypes.c_int32), ("ts_iso", ctypes.c_int32), ("ts_scale", ctypes.c_int32),
+                ("sep", ctypes.c_char), ("reserved", ctypes.c_char * 7)]
+
+
+class _CsvOut(ctypes.Structure):
+    _fields_ = [("case_code", _P), ("act_code", _P), ("ts", _P), ("capacity", ctypes.c_int64), ("n_rows", _P),
+                ("case_dict_off", _P), ("case_dict_len", _P), ("n_cases", _P), ("act_dict_off", _P),
+                ("act_dict_len", _P), ("n_acts", _P), ("status", _P), ("bad_row", _P)]
+
+
 class Pm4gError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"pm4g error {code}: {msg}")
@@ -146,6 +159,11 @@ def load():
             L.pm4g_sample.argtypes = [ctypes.POINTER(_Prepared), ctypes.c_int64, ctypes.c_uint64, ctypes.c_int32,
                                       ctypes.POINTER(_Prepared), _P, ctypes.c_size_t, _P]
             L.pm4g_sample.restype = ctypes.c_int
+            L.pm4g_ingest_csv_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64]
+            L.pm4g_ingest_csv_workspace_bytes.restype = ctypes.c_size_t
+            L.pm4g_ingest_csv.argtypes = [_P, ctypes.c_int64, ctypes.POINTER(CsvSchema), ctypes.POINTER(_CsvOut), _P,
+                                          ctypes.c_size_t, _P]
+            L.pm4g_ingest_csv.restype = ctypes.c_int
             L.pm4g_cases.argtypes = [ctypes.POINTER(_Prepared), _P, _P, _P]
             L.pm4g_cases.restype = ctypes.c_int
             L.pm4g_filter_cases_workspace_bytes.argtypes = [ctypes.c_int64]
@@ -160,6 +178,8 @@ def load():
             L.pm4g_profile_stage_name.argtypes = [ctypes.c_int]
             L.pm4g_profile_stage_name.restype = ctypes.c_char_p
             L.pm4g_profile_stage_count.restype = ctypes.c_int
+            L.pm4g_debug_csv_hash_bits.argtypes = [ctypes.c_int]
+            L.pm4g_debug_csv_hash_bits.restype = ctypes.c_int
             L.pm4g_debug_efg_pass_pairs.argtypes = [ctypes.c_int64]
             L.pm4g_debug_efg_pass_pairs.restype = ctypes.c_int64
             if hasattr(L, "pm4g_debug_variant_hash_bits"):
@@ -493,6 +513,42 @@ def pm4g_sample(prep: Prepared, k: int, seed: int, by_events: bool = False, out:
     _check(L.pm4g_sample(ctypes.byref(p), int(k), int(seed) & (2**64 - 1), 1 if by_events else 0,
                          ctypes.byref(q), _ptr(ws), need, _stream(stream)))
     return o
+
+
+def pm4g_ingest_csv(text: torch.Tensor, case_col: int, act_col: int, ts_col: int, sep: bytes = b",",
+                    has_header: bool = True, ts_iso: bool = False, ts_scale: int = 3, capacity: int | None = None,
+                    stream=None) -> dict:
+    """Columns of a CSV text held in a device uint8 tensor: case_code and
+    act_code (int32, first-appearance order), ts (int64), and per code the raw
+    byte range of its first field; counts as host ints.  Raises Pm4gError on a
+    parse error (its message names the row) or when the rows exceed capacity
+    (default: an upper bound from the text's newlines)."""
+    L = load()
+    dev = text.device
+    n = int(text.numel())
+    if capacity is None:
+        capacity = int((text == 10).sum().item()) + 1
+    cap = max(int(capacity), 1)
+    i32 = dict(dtype=torch.int32, device=dev)
+    i64 = dict(dtype=torch.int64, device=dev)
+    o = dict(case_code=torch.empty(cap, **i32), act_code=torch.empty(cap, **i32), ts=torch.empty(cap, **i64),
+             n_rows=torch.zeros(1, **i64), case_dict_off=torch.empty(cap, **i64), case_dict_len=torch.empty(cap, **i32),
+             n_cases=torch.zeros(1, **i64), act_dict_off=torch.empty(cap, **i64), act_dict_len=torch.empty(cap, **i32),
+             n_acts=torch.zeros(1, **i64), status=torch.zeros(1, **i32), bad_row=torch.zeros(1, **i64))
+    need = int(L.pm4g_ingest_csv_workspace_bytes(n, int(capacity)))
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    sc = CsvSchema(int(case_col), int(act_col), int(ts_col), 1 if has_header else 0, 1 if ts_iso else 0,
+                   int(ts_scale), sep, b"\0" * 7)
+    q = _CsvOut(_ptr(o["case_code"]), _ptr(o["act_code"]), _ptr(o["ts"]), int(capacity), _ptr(o["n_rows"]),
+                _ptr(o["case_dict_off"]), _ptr(o["case_dict_len"]), _ptr(o["n_cases"]), _ptr(o["act_dict_off"]),
+                _ptr(o["act_dict_len"]), _ptr(o["n_acts"]), _ptr(o["status"]), _ptr(o["bad_row"]))
+    _check(L.pm4g_ingest_csv(_ptr(text), n, ctypes.byref(sc), ctypes.byref(q), _ptr(ws), need, _stream(stream)))
+    r, c, a = int(o["n_rows"].item()), int(o["n_cases"].item()), int(o["n_acts"].item())
+    res = {k: o[k][:r] for k in ("case_code", "act_code", "ts")}
+    res.update(case_dict_off=o["case_dict_off"][:c], case_dict_len=o["case_dict_len"][:c],
+               act_dict_off=o["act_dict_off"][:a], act_dict_len=o["act_dict_len"][:a], n_rows=r, n_cases=c,
+               n_acts=a)
+    return res
 
 
 PM4G_EFG_MAX_ACTIVITIES = 4096

@@ -271,3 +271,40 @@ def make_views(log: Log, n_views: int, seed: int, min_events: float = 1e3,
         for a in sub:
             masks[v, a // 64] |= np.uint64(1) << np.uint64(a % 64)
     return Views(case_lo=lo, case_hi=hi, t_lo=tl, t_hi=th, masks=masks)
+
+
+def _digits(x: np.ndarray, width: int) -> np.ndarray:
+    """[n, width] ASCII decimal digits of non-negative x, zero-padded."""
+    out = np.empty((x.shape[0], width), dtype=np.uint8)
+    v = x.astype(np.int64).copy()
+    for k in range(width - 1, -1, -1):
+        out[:, k] = (v % 10).astype(np.uint8) + ord("0")
+        v //= 10
+    return out
+
+
+def log_csv(log: Log, unit: str = "ms", iso: bool = True) -> bytes:
+    """The log as CSV text (header "case,activity,timestamp", LF line ends,
+    rows in the log's row order): case "c" + 10 digits of the case id plus
+    2^31, activity "Activity " + 4 digits, timestamp ISO-8601 UTC with 3 (ms)
+    or 9 (ns) fraction digits, or the integer itself.  Fixed-width fields,
+    built column by column with numpy."""
+    n = log.n_events
+    case_f = np.concatenate([np.full((n, 1), ord("c"), np.uint8),
+                             _digits(log.case.astype(np.int64) + 2**31, 10)], axis=1)
+    act_f = np.concatenate([np.frombuffer(b"Activity ", np.uint8)[None, :].repeat(n, axis=0),
+                            _digits(log.act, 4)], axis=1)
+    if iso:
+        dt = log.ts.astype("datetime64[ms]" if unit == "ms" else "datetime64[ns]")
+        s = np.datetime_as_string(dt, unit="ms" if unit == "ms" else "ns", timezone="UTC")
+        w = len(s[0]) if n else 0
+        ts_f = np.frombuffer(s.astype(f"S{w}").tobytes(), np.uint8).reshape(n, w)
+    else:
+        neg = log.ts < 0
+        mag = np.where(neg, -log.ts, log.ts)
+        ts_f = np.concatenate([np.where(neg, ord("-"), ord("+")).astype(np.uint8)[:, None], _digits(mag, 19)],
+                              axis=1)
+    comma = np.full((n, 1), ord(","), np.uint8)
+    nl = np.full((n, 1), ord("\n"), np.uint8)
+    body = np.concatenate([case_f, comma, act_f, comma, ts_f, nl], axis=1)
+    return b"case,activity,timestamp\n" + body.tobytes()

@@ -22,6 +22,8 @@ STRUCTS = {
     "pm4g_batched_tuning": pm4g.BatchedTuning,
     "pm4g_case_filter": pm4g.CaseFilter,
     "pm4g_efg_out": pm4g._EfgOut,
+    "pm4g_csv_schema": pm4g.CsvSchema,
+    "pm4g_csv_out": pm4g._CsvOut,
 }
 VIEW_FIELDS = ("case_lo", "case_hi", "t_lo", "t_hi")
 
