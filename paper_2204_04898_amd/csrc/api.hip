@@ -508,8 +508,8 @@ int pm4g_ingest_csv(const uint8_t* text, int64_t n_bytes, const pm4g_csv_schema*
     // values are matched by 64-bit hash, then checked byte by byte; a collision
     // (two values, one hash) repeats the matching with the next seed
     for (uint64_t attempt = 0;; ++attempt) {
-        PM4G_HIP(launch_csv_parse(text, *sc, 0x5851F42D4C957F2Dull * (attempt + 1), attempt == 0 ? g_csv_hash_bits : 0,
-                                  out->capacity, w, *out, s));
+        PM4G_HIP(launch_csv_parse(text, n_bytes, *sc, 0x5851F42D4C957F2Dull * (attempt + 1),
+                                  attempt == 0 ? g_csv_hash_bits : 0, out->capacity, w, *out, s));
         PM4G_HIP(hipMemcpyAsync(sc_host, w.scal, sizeof(sc_host), hipMemcpyDeviceToHost, s));
         PM4G_HIP(hipStreamSynchronize(s));
         if (sc_host[6] || sc_host[3] != INT64_MAX || !sc_host[4]) break;

@@ -221,21 +221,59 @@ __global__ void k_csv_close(const uint8_t* __restrict__ text, int64_t n, CsvWs w
 
 // ---- values ----
 
+// Sequential reader of the text through one cached 16-byte chunk: aligned
+// vector loads, except for the chunk that crosses the end of the text, which
+// is read byte by byte (nothing past the text is touched).
+struct Bytes {
+    const uint8_t* t;
+    int64_t n;
+    int64_t chunk;
+    uint64_t lo, hi;   // the cached chunk as two 64-bit halves (kept in registers)
+    bool vec;
+    __device__ __forceinline__ Bytes(const uint8_t* text, int64_t n_)
+        : t(text), n(n_), chunk(-1), lo(0), hi(0), vec((reinterpret_cast<uintptr_t>(text) & 15) == 0) {}
+    __device__ __forceinline__ uint8_t at(int64_t p) {
+        const int64_t c = p >> 4;
+        if (c != chunk) {
+            chunk = c;
+            const int64_t b = c << 4;
+            if (vec && b + 16 <= n) {
+                const uint4 v = *reinterpret_cast<const uint4*>(t + b);
+                lo = (uint64_t)v.x | ((uint64_t)v.y << 32);
+                hi = (uint64_t)v.z | ((uint64_t)v.w << 32);
+            } else {
+                uint64_t l = 0, h = 0;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    if (b + k < n) l |= (uint64_t)t[b + k] << (8 * k);
+                    if (b + 8 + k < n) h |= (uint64_t)t[b + 8 + k] << (8 * k);
+                }
+                lo = l;
+                hi = h;
+            }
+        }
+        const int o = (int)(p & 15);
+        // a mask blend, not a select of the two halves: no address to index
+        const uint64_t m = (uint64_t)0 - (uint64_t)(o >> 3);
+        return (uint8_t)(((lo & ~m) | (hi & m)) >> (8 * (o & 7)));
+    }
+};
+
 // Iterates the value bytes of a raw field (quoted runs unwrapped).
 struct Unquote {
-    const uint8_t* s;
+    Bytes B;   // its own copy of the reader: no reference to a local object
     int64_t i, e;
     bool in;
-    __device__ __forceinline__ Unquote(const uint8_t* text, int64_t b, int64_t end) : s(text), i(b), e(end), in(false) {}
+    __device__ __forceinline__ Unquote(const Bytes& bytes, int64_t b, int64_t end) : B(bytes), i(b), e(end), in(false) {}
     // next value byte into *c; false at the end
     __device__ __forceinline__ bool next(uint8_t* c) {
         while (i < e) {
-            const uint8_t x = s[i++];
+            const uint8_t x = B.at(i++);
             if (x != '"') {
                 *c = x;
                 return true;
             }
-            if (in && i < e && s[i] == '"') {
+            if (in && i < e && B.at(i) == '"') {
                 ++i;
                 *c = '"';
                 return true;
@@ -246,22 +284,8 @@ struct Unquote {
     }
 };
 
-__device__ __forceinline__ uint64_t value_hash(const uint8_t* text, int64_t b, int64_t e, uint64_t seed,
-                                               uint64_t mask) {
-    // FNV-1a over the value bytes from a seeded basis, then a SplitMix64 finish
-    uint64_t h = 0xcbf29ce484222325ull ^ seed;
-    Unquote u(text, b, e);
-    uint8_t c;
-    while (u.next(&c)) {
-        h ^= c;
-        h *= 0x100000001b3ull;
-    }
-    h = splitmix64(seed, h) & mask;
-    return h ? h : 1;
-}
-
-__device__ bool same_value(const uint8_t* text, int64_t b1, int64_t e1, int64_t b2, int64_t e2) {
-    Unquote u1(text, b1, e1), u2(text, b2, e2);
+__device__ __forceinline__ bool same_value(const Bytes& B1, int64_t b1, int64_t e1, const Bytes& B2, int64_t b2, int64_t e2) {
+    Unquote u1(B1, b1, e1), u2(B2, b2, e2);
     uint8_t c1, c2;
     for (;;) {
         const bool m1 = u1.next(&c1), m2 = u2.next(&c2);
@@ -269,6 +293,14 @@ __device__ bool same_value(const uint8_t* text, int64_t b1, int64_t e1, int64_t 
         if (!m1) return true;
         if (c1 != c2) return false;
     }
+}
+
+// FNV-1a over the value bytes from a seeded basis, then a SplitMix64 finish.
+constexpr uint64_t kFnvBasis = 0xcbf29ce484222325ull, kFnvPrime = 0x100000001b3ull;
+
+__device__ __forceinline__ uint64_t finish_hash(uint64_t h, uint64_t seed, uint64_t mask) {
+    h = splitmix64(seed, h) & mask;
+    return h ? h : 1;
 }
 
 // ---- timestamps ----
@@ -293,44 +325,72 @@ __device__ __forceinline__ int month_days(int64_t y, int64_t m) {
     return (m == 4 || m == 6 || m == 9 || m == 11) ? 30 : 31;
 }
 
-struct Cursor {
-    const uint8_t* v;
-    int n, i;
+// The value bytes of a raw field (quoted runs unwrapped) with one byte of
+// lookahead: c is the current byte, -1 at the end.
+template <class Src>
+struct ValueCursor {
+    Src B;   // its own copy of the reader: no reference to a local object
+    int64_t i, e;
+    bool in;
+    int c;
+    __device__ __forceinline__ ValueCursor(const Src& bytes, int64_t b, int64_t end)
+        : B(bytes), i(b), e(end), in(false), c(-1) {
+        adv();
+    }
+    __device__ __forceinline__ void adv() {
+        while (i < e) {
+            const uint8_t x = B.at(i++);
+            if (x != '"') {
+                c = x;
+                return;
+            }
+            if (in && i < e && B.at(i) == '"') {
+                ++i;
+                c = '"';
+                return;
+            }
+            in = !in;
+        }
+        c = -1;
+    }
+    __device__ __forceinline__ bool end() const { return c < 0; }
+    __device__ __forceinline__ bool is(int ch) const { return c == ch; }
+    __device__ __forceinline__ bool digit() const { return c >= '0' && c <= '9'; }
+    __device__ __forceinline__ bool take(int ch) {
+        if (c != ch) return false;
+        adv();
+        return true;
+    }
     __device__ __forceinline__ bool digits(int k, int64_t* out) {
         int64_t x = 0;
         for (int j = 0; j < k; ++j) {
-            if (i >= n || v[i] < '0' || v[i] > '9') return false;
-            x = x * 10 + (v[i++] - '0');
+            if (!digit()) return false;
+            x = x * 10 + (c - '0');
+            adv();
         }
         *out = x;
         return true;
     }
-    __device__ __forceinline__ bool is(uint8_t c) const { return i < n && v[i] == c; }
-    __device__ __forceinline__ bool take(uint8_t c) {
-        if (!is(c)) return false;
-        ++i;
-        return true;
-    }
 };
 
-__device__ bool iso_value(const uint8_t* v, int n, int scale, int64_t* out) {
-    Cursor c{v, n, 0};
+template <class Cur>
+__device__ __forceinline__ bool iso_value(Cur& c, int scale, int64_t* out) {
     int64_t y, mo, d, hh = 0, mi = 0, ss = 0, frac = 0, off = 0;
     if (!c.digits(4, &y) || !c.take('-') || !c.digits(2, &mo) || !c.take('-') || !c.digits(2, &d)) return false;
     if (mo < 1 || mo > 12 || d < 1 || d > month_days(y, mo)) return false;
     int nf = 0;
     if (c.is('T') || c.is(' ')) {
-        ++c.i;
+        c.adv();
         if (!c.digits(2, &hh) || !c.take(':') || !c.digits(2, &mi)) return false;
         if (c.take(':')) {
             if (!c.digits(2, &ss)) return false;
             if (c.is('.') || c.is(',')) {
-                ++c.i;
-                while (c.i < n && v[c.i] >= '0' && v[c.i] <= '9') {
+                c.adv();
+                while (c.digit()) {
                     if (nf == 9) return false;
-                    if (nf < scale) frac = frac * 10 + (v[c.i] - '0');
+                    if (nf < scale) frac = frac * 10 + (c.c - '0');
                     ++nf;
-                    ++c.i;
+                    c.adv();
                 }
                 if (nf == 0) return false;
             }
@@ -338,17 +398,17 @@ __device__ bool iso_value(const uint8_t* v, int n, int scale, int64_t* out) {
         if (hh > 23 || mi > 59 || ss > 59) return false;
         if (c.take('Z')) {
         } else if (c.is('+') || c.is('-')) {
-            const int64_t sg = v[c.i] == '-' ? -1 : 1;
-            ++c.i;
+            const int64_t sg = c.is('-') ? -1 : 1;
+            c.adv();
             int64_t oh, om = 0;
             if (!c.digits(2, &oh)) return false;
             c.take(':');
-            if (c.i < n && !c.digits(2, &om)) return false;
+            if (!c.end() && !c.digits(2, &om)) return false;
             if (oh > 23 || om > 59) return false;
             off = sg * (oh * 3600 + om * 60);
         }
     }
-    if (c.i != n) return false;
+    if (!c.end()) return false;
     for (int k = nf < scale ? nf : scale; k < scale; ++k) frac *= 10;
     const int64_t secs = days_since_epoch(y, mo, d) * 86400 + hh * 3600 + mi * 60 + ss - off;
     __int128 p10 = 1;
@@ -359,98 +419,173 @@ __device__ bool iso_value(const uint8_t* v, int n, int scale, int64_t* out) {
     return true;
 }
 
-__device__ bool int_value(const uint8_t* v, int n, int64_t* out) {
-    int i = 0;
+template <class Cur>
+__device__ __forceinline__ bool int_value(Cur& c, int64_t* out) {
     bool neg = false;
-    if (i < n && (v[i] == '+' || v[i] == '-')) neg = v[i++] == '-';
-    if (i >= n) return false;
+    if (c.is('+') || c.is('-')) {
+        neg = c.is('-');
+        c.adv();
+    }
+    if (c.end()) return false;
     uint64_t x = 0;
     const uint64_t lim = neg ? (uint64_t)INT64_MAX + 1 : (uint64_t)INT64_MAX;
-    for (; i < n; ++i) {
-        if (v[i] < '0' || v[i] > '9') return false;
-        const uint64_t dgt = (uint64_t)(v[i] - '0');
+    while (!c.end()) {
+        if (!c.digit()) return false;
+        const uint64_t dgt = (uint64_t)(c.c - '0');
         if (x > (lim - dgt) / 10) return false;
         x = x * 10 + dgt;
+        c.adv();
     }
     *out = neg ? (int64_t)(0 - x) : (int64_t)x;
     return true;
 }
 
-__device__ __forceinline__ void flag_bad(CsvWs& w, int64_t r) {
+__device__ __forceinline__ void flag_bad(const CsvWs& w, int64_t r) {
     atomicMin(reinterpret_cast<unsigned long long*>(&w.scal[3]), (unsigned long long)r);
 }
 
 // Slot of value hash h in table `tab` (linear probing); the slot keeps the
-// smallest row that holds the value.
+// smallest row that holds the value.  A slot is read before any atomic: a
+// value already in the table (nearly every row) costs no atomic unless this
+// row is smaller than the first row seen, so hot values (few activities over
+// millions of rows) do not serialise on their slot.
 __device__ __forceinline__ uint32_t insert(CsvSlot* tab, int64_t tsize, uint64_t h, uint32_t r) {
     uint64_t i = h & (uint64_t)(tsize - 1);
     for (;;) {   // the table has more slots than rows: an empty or equal slot exists
-        const unsigned long long cur =
-            atomicCAS(reinterpret_cast<unsigned long long*>(&tab[i].hash), 0ull, (unsigned long long)h);
+        unsigned long long cur = __hip_atomic_load(reinterpret_cast<unsigned long long*>(&tab[i].hash),
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == 0)
+            cur = atomicCAS(reinterpret_cast<unsigned long long*>(&tab[i].hash), 0ull, (unsigned long long)h);
         if (cur == 0 || cur == h) {
-            atomicMin(&tab[i].first, r);
+            if (r < __hip_atomic_load(&tab[i].first, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                atomicMin(&tab[i].first, r);
             return (uint32_t)i;
         }
         i = (i + 1) & (uint64_t)(tsize - 1);
     }
 }
 
-__global__ __launch_bounds__(256) void k_csv_parse(const uint8_t* __restrict__ text, CsvWs w,
+// Bytes of the text already staged in LDS: [lo, lo + len) at stage[0..).
+struct StagedBytes {
+    const uint8_t* stage;
+    int64_t lo;
+    __device__ __forceinline__ uint8_t at(int64_t p) const { return stage[p - lo]; }
+};
+
+// One walk over row r: fields split at separators outside quoted runs; the
+// case and activity values are hashed and the timestamp value copied as the
+// walk unwraps their runs (a doubled quote inside a run is one quote and
+// leaves the run open, as two toggles would).
+template <class Src>
+__device__ __forceinline__ void parse_row(Src B, int64_t r, int64_t a, int64_t e, const CsvWs w,
+                                         const pm4g_csv_schema& sc, int32_t need, uint64_t seed, uint64_t mask,
+                                         int64_t* __restrict__ ts_out) {
+    const uint8_t sep = (uint8_t)sc.sep;
+    // skip the empty lines in between ("\n" or "\r\n" each)
+    while (a < e && (B.at(a) == '\n' || (B.at(a) == '\r' && a + 1 < e && B.at(a + 1) == '\n'))) ++a;
+    if (e > a && B.at(e - 1) == '\r') --e;
+    int64_t cb = -1, ce = -1, ab = -1, ae = -1, tb = -1, te = -1;
+    uint64_t h0 = kFnvBasis ^ seed, h1 = kFnvBasis ^ seed;
+    int32_t f = 0;
+    bool q = false;
+    int64_t fs = a;
+    for (int64_t i = a; i <= e; ++i) {
+        if (i < e) {
+            uint8_t x = B.at(i);
+            bool lit = false;
+            if (x == '"') {
+                if (q && i + 1 < e && B.at(i + 1) == '"') {
+                    ++i;   // a doubled quote inside a run: one quote, still in the run
+                    lit = true;
+                } else {
+                    q = !q;
+                    continue;
+                }
+            }
+            if (lit || x != sep || q) {
+                if (f == sc.case_col) h0 = (h0 ^ x) * kFnvPrime;
+                if (f == sc.act_col) h1 = (h1 ^ x) * kFnvPrime;
+                continue;
+            }
+        }
+        // a separator outside quotes, or the end of the line, closes field f
+        if (f == sc.case_col) { cb = fs; ce = i; }
+        if (f == sc.act_col) { ab = fs; ae = i; }
+        if (f == sc.ts_col) { tb = fs; te = i; }
+        ++f;
+        fs = i + 1;
+    }
+    if (f <= need) {
+        flag_bad(w, r);
+        w.slot[2 * r] = w.slot[2 * r + 1] = 0;
+        return;
+    }
+    w.foff[2 * r] = cb;
+    w.flen[2 * r] = (int32_t)(ce - cb);
+    w.slot[2 * r] = insert(w.table, w.tsize, finish_hash(h0, seed, mask), (uint32_t)r);
+    w.foff[2 * r + 1] = ab;
+    w.flen[2 * r + 1] = (int32_t)(ae - ab);
+    w.slot[2 * r + 1] = insert(w.table + w.tsize, w.tsize, finish_hash(h1, seed, mask), (uint32_t)r);
+    bool ok = te - tb <= kTsMax;
+    if (ok) {
+        ValueCursor<Src> vc(B, tb, te);
+        int64_t t;
+        ok = sc.ts_iso ? iso_value(vc, sc.ts_scale, &t) : int_value(vc, &t);
+        if (ok) ts_out[r] = t;
+    }
+    if (!ok) flag_bad(w, r);
+}
+
+constexpr int kStage = 32768;   // bytes of text staged per block of rows
+
+// A block takes 256 consecutive rows; their bytes (one contiguous range) are
+// copied to LDS with coalesced 16-byte loads and walked there; a range longer
+// than the stage is walked through the chunk reader instead.
+__global__ __launch_bounds__(256) void k_csv_parse(const uint8_t* __restrict__ text, int64_t n_bytes, CsvWs w,
                                                    pm4g_csv_schema sc, uint64_t seed, uint64_t mask,
                                                    int64_t* __restrict__ ts_out) {
+    __shared__ uint4 stage4[kStage / 16];
+    uint8_t* stage = reinterpret_cast<uint8_t*>(stage4);
     const int64_t rows = w.scal[2];
     const int64_t hdr = (sc.has_header && w.scal[1] > 0) ? 1 : 0;
     const int32_t need = sc.case_col > sc.act_col ? (sc.case_col > sc.ts_col ? sc.case_col : sc.ts_col)
                                                    : (sc.act_col > sc.ts_col ? sc.act_col : sc.ts_col);
-    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < rows; r += (int64_t)gridDim.x * 256) {
-        const int64_t li = r + hdr;
-        int64_t a = li == 0 ? 0 : w.line_end[li - 1] + 1;
-        int64_t e = w.line_end[li];
-        // skip the empty lines in between ("\n" or "\r\n" each)
-        while (a < e && (text[a] == '\n' || (text[a] == '\r' && a + 1 < e && text[a + 1] == '\n'))) ++a;
-        if (e > a && text[e - 1] == '\r') --e;
-        int64_t fb[3] = {-1, -1, -1}, fe[3] = {-1, -1, -1};
-        int32_t f = 0;
-        bool q = false;
-        int64_t fs = a;
-        for (int64_t i = a; i <= e; ++i) {
-            const uint8_t c = i < e ? text[i] : (uint8_t)sc.sep;
-            if (i < e && c == '"') q = !q;
-            if (i == e || (c == (uint8_t)sc.sep && !q)) {
-                if (f == sc.case_col) { fb[0] = fs; fe[0] = i; }
-                if (f == sc.act_col) { fb[1] = fs; fe[1] = i; }
-                if (f == sc.ts_col) { fb[2] = fs; fe[2] = i; }
-                ++f;
-                fs = i + 1;
+    const bool vec = (reinterpret_cast<uintptr_t>(text) & 15) == 0;
+    for (int64_t r0 = (int64_t)blockIdx.x * 256; r0 < rows; r0 += (int64_t)gridDim.x * 256) {
+        const int64_t rl = (r0 + 255 < rows ? r0 + 255 : rows - 1);
+        const int64_t li0 = r0 + hdr, lil = rl + hdr;
+        const int64_t lo = (li0 == 0 ? 0 : w.line_end[li0 - 1] + 1) & ~(int64_t)15;
+        const int64_t hi = w.line_end[lil];   // bytes [lo, hi) hold the rows
+        const bool staged = hi - lo <= kStage;   // block-uniform
+        if (staged) {
+            for (int64_t off = (int64_t)threadIdx.x * 16; off < hi - lo; off += 256 * 16) {
+                const int64_t p = lo + off;
+                if (vec && p + 16 <= n_bytes) {
+                    stage4[off >> 4] = *reinterpret_cast<const uint4*>(text + p);
+                } else {
+                    for (int k = 0; k < 16; ++k) stage[off + k] = p + k < n_bytes ? text[p + k] : 0;
+                }
             }
         }
-        if (f <= need) {
-            flag_bad(w, r);
-            w.slot[2 * r] = w.slot[2 * r + 1] = 0;
-            continue;
+        __syncthreads();
+        const int64_t r = r0 + threadIdx.x;
+        if (r < rows) {
+            const int64_t li = r + hdr;
+            const int64_t a = li == 0 ? 0 : w.line_end[li - 1] + 1;
+            const int64_t e = w.line_end[li];
+            if (staged) {
+                StagedBytes SB{stage, lo};
+                parse_row(SB, r, a, e, w, sc, need, seed, mask, ts_out);
+            } else {
+                Bytes B(text, n_bytes);
+                parse_row(B, r, a, e, w, sc, need, seed, mask, ts_out);
+            }
         }
-        for (int k = 0; k < 2; ++k) {
-            w.foff[2 * r + k] = fb[k];
-            w.flen[2 * r + k] = (int32_t)(fe[k] - fb[k]);
-            const uint64_t h = value_hash(text, fb[k], fe[k], seed, mask);
-            w.slot[2 * r + k] = insert(w.table + k * w.tsize, w.tsize, h, (uint32_t)r);
-        }
-        uint8_t tv[kTsMax];
-        int tn = 0;
-        bool ok = fe[2] - fb[2] <= kTsMax;
-        if (ok) {
-            Unquote u(text, fb[2], fe[2]);
-            uint8_t c;
-            while (u.next(&c)) tv[tn++] = c;
-            int64_t t;
-            ok = sc.ts_iso ? iso_value(tv, tn, sc.ts_scale, &t) : int_value(tv, tn, &t);
-            if (ok) ts_out[r] = t;
-        }
-        if (!ok) flag_bad(w, r);
+        __syncthreads();
     }
 }
 
-__global__ __launch_bounds__(256) void k_csv_verify(const uint8_t* __restrict__ text, CsvWs w) {
+__global__ __launch_bounds__(256) void k_csv_verify(const uint8_t* __restrict__ text, int64_t n_bytes, CsvWs w) {
     const int64_t rows = w.scal[2];
     if (w.scal[3] != INT64_MAX) return;   // a parse error ends the call
     for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < rows; r += (int64_t)gridDim.x * 256) {
@@ -459,7 +594,8 @@ __global__ __launch_bounds__(256) void k_csv_verify(const uint8_t* __restrict__ 
             if (first == (uint32_t)r) continue;
             const int64_t b1 = w.foff[2 * r + k], e1 = b1 + w.flen[2 * r + k];
             const int64_t b2 = w.foff[2 * (int64_t)first + k], e2 = b2 + w.flen[2 * (int64_t)first + k];
-            if (!same_value(text, b1, e1, b2, e2)) w.scal[4] = 1;
+            Bytes B1(text, n_bytes), B2(text, n_bytes);
+            if (!same_value(B1, b1, e1, B2, b2, e2)) w.scal[4] = 1;
         }
     }
 }
@@ -531,13 +667,13 @@ hipError_t launch_csv_lines(const uint8_t* text, int64_t n_bytes, int has_header
     return hipGetLastError();
 }
 
-hipError_t launch_csv_parse(const uint8_t* text, const pm4g_csv_schema& sc, uint64_t seed, int hash_bits,
-                            int64_t max_rows, CsvWs w, const pm4g_csv_out& o, hipStream_t s) {
+hipError_t launch_csv_parse(const uint8_t* text, int64_t n_bytes, const pm4g_csv_schema& sc, uint64_t seed,
+                            int hash_bits, int64_t max_rows, CsvWs w, const pm4g_csv_out& o, hipStream_t s) {
     const uint64_t mask = (hash_bits <= 0 || hash_bits >= 64) ? ~0ull : ((1ull << hash_bits) - 1);
     const unsigned gr = grid_rows(max_rows);
     k_csv_clear<<<2048, 256, 0, s>>>(w);
-    k_csv_parse<<<gr, 256, 0, s>>>(text, w, sc, seed, mask, o.ts);
-    k_csv_verify<<<gr, 256, 0, s>>>(text, w);
+    k_csv_parse<<<gr, 256, 0, s>>>(text, n_bytes, w, sc, seed, mask, o.ts);
+    k_csv_verify<<<gr, 256, 0, s>>>(text, n_bytes, w);
     return hipGetLastError();
 }
 

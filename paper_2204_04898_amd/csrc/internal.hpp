@@ -389,8 +389,8 @@ CsvWs csv_ws_layout(Bump& b, int64_t n_bytes, int64_t max_rows);
 hipError_t launch_csv_lines(const uint8_t* text, int64_t n_bytes, int has_header, int64_t max_rows, CsvWs w,
                             hipStream_t s);
 // hash_bits: value hashes truncated to that many bits (0: all 64; a test hook)
-hipError_t launch_csv_parse(const uint8_t* text, const pm4g_csv_schema& sc, uint64_t seed, int hash_bits,
-                            int64_t max_rows, CsvWs w, const pm4g_csv_out& o, hipStream_t s);
+hipError_t launch_csv_parse(const uint8_t* text, int64_t n_bytes, const pm4g_csv_schema& sc, uint64_t seed,
+                            int hash_bits, int64_t max_rows, CsvWs w, const pm4g_csv_out& o, hipStream_t s);
 hipError_t launch_csv_codes(CsvWs w, int64_t max_rows, const pm4g_csv_out& o, hipStream_t s);
 hipError_t launch_csv_finish(CsvWs w, const pm4g_csv_out& o, hipStream_t s);
 
