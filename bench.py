@@ -98,6 +98,30 @@ STAGE_SOURCES = {
 }
 
 
+# every source whose kernels run in one step of the DFG + variants path
+STEP_SOURCES = ["paper_2204_04898_amd/csrc/" + f for f in (
+    "range.hip", "radix.hip", "segsort.hip", "cases.hip", "dfg.hip", "variants.hip", "common.hpp", "devsort.hpp")]
+
+
+def measured_step_traffic(workload: str) -> float | None:
+    """HBM bytes of one whole step (all kernels) from the committed counter
+    summary profiles/traffic_step_<workload>.txt, if its sources are current."""
+    path = os.path.join(ROOT, "profiles", f"traffic_step_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha") != source_sha(STEP_SOURCES):
+        return None
+    try:
+        return float(kv["bytes_per_step"])
+    except (KeyError, ValueError):
+        return None
+
+
 def measured_traffic(stage: str, workload: str) -> float | None:
     """HBM bytes per launch from the committed counter summary, if it is current.
 
@@ -391,16 +415,43 @@ def _counter_rows(path: str, kernel: str, counter: str) -> list[float]:
 
 def summarize_counters(a) -> None:
     """Writes profiles/traffic_<stage>_<workload>.txt from two rocprofv3 --pmc runs of the
-    benchmark (FETCH_SIZE, WRITE_SIZE in KiB per dispatch) and of the copy calibration."""
-    fetch = _counter_rows(a.fetch_csv, a.kernel, "FETCH_SIZE")
-    write = _counter_rows(a.write_csv, a.kernel, "WRITE_SIZE")
+    benchmark (FETCH_SIZE, WRITE_SIZE in KiB per dispatch) and of the copy calibration;
+    with --stage step, the sum over every library kernel divided by the steps run
+    (counted by the range-scan launches), into profiles/traffic_step_<workload>.txt."""
     cf = _counter_rows(a.copy_fetch_csv, a.copy_kernel, "FETCH_SIZE")
     cw = _counter_rows(a.copy_write_csv, a.copy_kernel, "WRITE_SIZE")
-    if not (fetch and write and cf and cw):
-        raise SystemExit("counter rows missing for the kernel or the copy kernel")
     copy_bytes = float(a.copy_bytes)
+    if not (cf and cw):
+        raise SystemExit("counter rows missing for the copy kernel")
     f_scale = copy_bytes / (sum(cf) / len(cf) * 1024.0)
     w_scale = copy_bytes / (sum(cw) / len(cw) * 1024.0)
+    if a.stage == "step":
+        fetch = _counter_rows(a.fetch_csv, "pm4g::", "FETCH_SIZE")
+        write = _counter_rows(a.write_csv, "pm4g::", "WRITE_SIZE")
+        steps = len(_counter_rows(a.fetch_csv, "k_range_", "FETCH_SIZE"))
+        if not (fetch and write and steps):
+            raise SystemExit("counter rows missing for the step's kernels")
+        fb = sum(fetch) * 1024.0 * f_scale / steps
+        wb = sum(write) * 1024.0 * w_scale / steps
+        path = os.path.join(ROOT, "profiles", f"traffic_step_{a.workload}.txt")
+        with open(path, "w") as fh:
+            fh.write(f"# HBM traffic of one whole step (every pm4g kernel) on the {a.workload} workload\n")
+            fh.write("# from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of:\n")
+            fh.write(f"#   {a.command}\n")
+            fh.write("# scaled by the same counters on a plain copy of copy_bytes bytes "
+                     "(python3 bench.py --calibrate-copy)\n")
+            fh.write(f"steps = {steps}\nkernel_dispatches = {len(fetch)}\n")
+            fh.write(f"fetch_bytes_per_step = {fb:.0f}\nwrite_bytes_per_step = {wb:.0f}\n")
+            fh.write(f"copy_bytes = {int(copy_bytes)}\ncopy_fetch_scale = {f_scale:.4f}\n"
+                     f"copy_write_scale = {w_scale:.4f}\n")
+            fh.write(f"bytes_per_step = {fb + wb:.0f}\n")
+            fh.write(f"source_sha = {source_sha(STEP_SOURCES)}\n")
+        print(path)
+        return
+    fetch = _counter_rows(a.fetch_csv, a.kernel, "FETCH_SIZE")
+    write = _counter_rows(a.write_csv, a.kernel, "WRITE_SIZE")
+    if not (fetch and write):
+        raise SystemExit("counter rows missing for the kernel")
     fb = sum(fetch) / len(fetch) * 1024.0 * f_scale
     wb = sum(write) / len(write) * 1024.0 * w_scale
     path = os.path.join(ROOT, "profiles", f"traffic_{a.stage}_{a.workload}.txt")
@@ -545,6 +596,15 @@ def main() -> int:
                      "algorithmic_bytes_per_launch": algo, "avg_launch_ms": per_launch_ms},
         "stages": stages,
     }
+    # the whole step against the HBM peak: measured traffic (all kernels of one
+    # step, from the committed counter summary) and the compulsory floor of
+    # 16 B/event (case, activity, timestamp read once)
+    step_bytes = measured_step_traffic(args.workload)
+    t_step = ms_per_step * 1e-3
+    out["step_hbm"] = {"floor_bytes": 16 * N, "floor_frac": 16 * N / t_step / (HBM_PEAK_GBS * 1e9),
+                       "measured_bytes": step_bytes,
+                       "measured_frac": None if step_bytes is None else step_bytes / t_step / (HBM_PEAK_GBS * 1e9),
+                       "measured_over_floor": None if step_bytes is None else step_bytes / (16 * N)}
     if args.views > 0 and k == 3:
         log_progress(f"batched views: {args.views} views")
         if args.tune_cache:

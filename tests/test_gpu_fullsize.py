@@ -129,3 +129,107 @@ def test_full_4096_views(big):
         for k in ("start_count", "end_count", "act_count"):
             assert np.array_equal(r[k], ref[k]), (v, k)
         assert r["n_events"] == ref["n_events"] and r["n_cases"] == ref["n_cases"], v
+
+
+def _u128(lo, hi):
+    return [int(a) + (int(b) << 64) for a, b in zip(lo.ravel(), hi.ravel())]
+
+
+def test_full_99M_efg_properties(big):
+    """The eventually-follows graph of the 99M-event log (2.6e9 pairs): total
+    pairs, per-activity row and column counts, and per-activity gap sums,
+    each computed on the host from the formatted log."""
+    log, prep = big
+    A = log.n_activities
+    h = pm4g.prepared_to_host(prep)
+    e = pm4g.efg_to_host(pm4g.pm4g_efg(prep), A)
+    L = log.lengths_by_code.astype(np.int64)
+    assert e["status"] == 0 and e["n_pairs"] == int((L * (L - 1) // 2).sum()) == int(e["count"].sum())
+    off, act, ts = h["case_off"], h["act_s"], h["ts_s"]
+    lens = np.diff(off)
+    pos = np.arange(act.size, dtype=np.int64) - np.repeat(off[:-1], lens)     # index within the case
+    tail = np.repeat(lens, lens) - pos - 1                                       # later events of the case
+    assert np.array_equal(e["count"].sum(axis=1), np.bincount(act, weights=tail, minlength=A).astype(np.int64))
+    assert np.array_equal(e["count"].sum(axis=0), np.bincount(act, weights=pos, minlength=A).astype(np.int64))
+    # gap sums: event i contributes sum over later j of (t_j - t_i), from suffix sums of
+    # the times relative to the case start (all within int64)
+    rel = ts - np.repeat(ts[off[:-1]], lens)
+    csum = np.cumsum(rel)
+    case_total = np.add.reduceat(rel, off[:-1]) if rel.size else rel
+    before = csum - np.repeat(csum[off[:-1]] - rel[off[:-1]], lens)             # inclusive prefix within case
+    later = np.repeat(case_total, lens) - before                                 # sum of later rel times
+    contrib = later - tail * rel
+    assert (contrib >= 0).all()
+    assert contrib.max() < 2**60
+    # three 20-bit pieces: each per-activity sum stays below 2^53, so the float bins are exact
+    pieces = [np.bincount(act, weights=((contrib >> (20 * k)) & 0xFFFFF).astype(np.float64), minlength=A)
+              for k in range(3)]
+    assert max(p.max() for p in pieces) < 2**53
+    want = [sum(int(pieces[k][a]) << (20 * k) for k in range(3)) for a in range(A)]
+    S = np.array(_u128(e["sum_lo"], e["sum_hi"]), dtype=object).reshape(A, A)
+    assert [int(x) for x in S.sum(axis=1)] == want
+    nz = e["count"] > 0
+    assert np.isnan(e["mean"][~nz]).all() and np.isfinite(e["mean"][nz]).all() and (e["std"][nz] >= 0).all()
+
+
+def test_full_99M_filters_and_sampling(big):
+    log, prep = big
+    A = log.n_activities
+    N, C = log.n_events, int(prep.n_cases.item())
+    L = log.lengths_by_code.astype(np.int64)                  # case codes are dense 0..C-1
+    c = pm4g.pm4g_cases(prep)
+    assert np.array_equal(c["n_events"][:C].cpu().numpy(), L)
+
+    def kept(f):
+        torch.cuda.synchronize()
+        K = int(f.n_cases.item())
+        assert int(f.status.item()) == 0
+        return K, int(f.case_off[K].item()), f.case_code[:K].cpu().numpy()
+
+    K, M, codes = kept(pm4g.pm4g_filter_cases(prep, min_events=5, max_events=40))
+    sel = (L >= 5) & (L <= 40)
+    assert K == int(sel.sum()) and M == int(L[sel].sum()) and np.array_equal(codes, np.flatnonzero(sel))
+    # sampling: exactly k cases (whole) or k events; a smaller sample is a subset
+    K1, M1, c1 = kept(pm4g.pm4g_sample(prep, C // 10, 5, False))
+    K2, M2, c2 = kept(pm4g.pm4g_sample(prep, C // 20, 5, False))
+    assert K1 == C // 10 and M1 == int(L[c1].sum()) and K2 == C // 20 and np.isin(c2, c1).all()
+    _, M3, _ = kept(pm4g.pm4g_sample(prep, N // 10, 5, True))
+    assert M3 == N // 10
+    # directly-follows filter: dropping every event that has a previous one keeps each case's first
+    allp = torch.from_numpy(np.full((A * A + 63) // 64, -1, np.int64)).cuda()
+    f = pm4g.pm4g_filter_df_events(prep, allp, 0, False)
+    K4, M4, _ = kept(f)
+    d = pm4g.dfg_to_host(pm4g.pm4g_dfg_prepared(prep), A)
+    assert K4 == C == M4
+    assert np.array_equal(np.bincount(f.act_s[:M4].cpu().numpy(), minlength=A), d["start_count"])
+    # variant filter: the ten most frequent variants keep exactly their cases
+    v = pm4g.pm4g_variants_prepared(prep)
+    torch.cuda.synchronize()
+    nv = int(v["n_variants"].item())
+    vm = np.zeros((nv + 63) // 64, np.uint64)
+    vm[0] = np.uint64((1 << 10) - 1)
+    K5, _, _ = kept(pm4g.pm4g_filter_cases(prep, case_variant=v["case_variant"], n_variant_bits=nv,
+                                           variant_mask=torch.from_numpy(vm.view(np.int64)).cuda()))
+    assert K5 == int(v["var_count"][:10].sum().item())
+
+
+def test_full_10M_csv_roundtrip():
+    """CSV ingestion of the 10M-event log's text (509 MB): the timestamps come back
+    exactly and the codes follow the first appearance of each case and activity."""
+    log = synth.config_log(2)
+    text = synth.log_csv(log, "ms", True)
+    note(f"csv: {len(text)} bytes")
+    t = torch.frombuffer(bytearray(text), dtype=torch.uint8).cuda()
+    r = pm4g.pm4g_ingest_csv(t, 0, 1, 2, ts_iso=True, ts_scale=3, capacity=log.n_events + 1)
+    assert r["n_rows"] == log.n_events
+    assert np.array_equal(r["ts"].cpu().numpy(), log.ts)
+    for col, key, n in ((log.case, "case_code", "n_cases"), (log.act, "act_code", "n_acts")):
+        uniq, first = np.unique(col, return_index=True)
+        rank = np.empty(uniq.size, np.int64)
+        rank[np.argsort(first)] = np.arange(uniq.size)
+        assert r[n] == uniq.size
+        assert np.array_equal(r[key].cpu().numpy(), rank[np.searchsorted(uniq, col)])
+    off, ln = r["case_dict_off"].cpu().numpy(), r["case_dict_len"].cpu().numpy()
+    for code in (0, 1, r["n_cases"] - 1):
+        value = int(text[off[code]:off[code] + ln[code]][1:]) - 2**31
+        assert value == log.case[np.flatnonzero(r["case_code"].cpu().numpy() == code)[0]]
