@@ -417,7 +417,7 @@ def summarize_counters(a) -> None:
     """Writes profiles/traffic_<stage>_<workload>.txt from two rocprofv3 --pmc runs of the
     benchmark (FETCH_SIZE, WRITE_SIZE in KiB per dispatch) and of the copy calibration;
     with --stage step, the sum over every library kernel divided by the steps run
-    (counted by the range-scan launches), into profiles/traffic_step_<workload>.txt."""
+    (counted by the launches of the range scan's first kernel), into profiles/traffic_step_<workload>.txt."""
     cf = _counter_rows(a.copy_fetch_csv, a.copy_kernel, "FETCH_SIZE")
     cw = _counter_rows(a.copy_write_csv, a.copy_kernel, "WRITE_SIZE")
     copy_bytes = float(a.copy_bytes)
@@ -428,7 +428,7 @@ def summarize_counters(a) -> None:
     if a.stage == "step":
         fetch = _counter_rows(a.fetch_csv, "pm4g::", "FETCH_SIZE")
         write = _counter_rows(a.write_csv, "pm4g::", "WRITE_SIZE")
-        steps = len(_counter_rows(a.fetch_csv, "k_range_", "FETCH_SIZE"))
+        steps = len(_counter_rows(a.fetch_csv, "k_range_init", "FETCH_SIZE"))
         if not (fetch and write and steps):
             raise SystemExit("counter rows missing for the step's kernels")
         fb = sum(fetch) * 1024.0 * f_scale / steps
