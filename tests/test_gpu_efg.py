@@ -93,3 +93,16 @@ def test_degenerate_logs():
     L = 50
     g, _ = _check(np.zeros(L, np.int64), np.zeros(L, np.int64), 7 * np.arange(L), 1)
     assert g["count"][0, 0] == L * (L - 1) // 2 and g["sum_lo"][0, 0] == 7 * L * (L * L - 1) // 6
+
+
+def test_wide_gaps_carry_into_high_words():
+    # gaps up to about 2^63: the gap sums pass 2^64 and every square needs 128 bits
+    rng = np.random.default_rng(17)
+    n = 4000
+    case = rng.integers(0, 40, n)
+    act = rng.integers(0, 5, n)
+    ts = rng.integers(-(2**62), 2**62, n)
+    g, o = _check(case, act, ts, 5)
+    assert (o["sum_hi"] > 0).any() and (o["sq_hi"] > 0).any()
+    t = np.array([-(2**62), 0, 2**62 - 1, 2**62])
+    _check(np.ones(4, np.int64), np.zeros(4, np.int64), t, 1)
