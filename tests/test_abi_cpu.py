@@ -125,3 +125,58 @@ def test_batched_and_filter_validation():
                                 None) == pm4g.PM4G_E_INVALID
     assert lib.pm4g_filter_view(ctypes.byref(prep), _fake(0), _fake(0), ctypes.byref(fo), ws, 8,
                                 None) == pm4g.PM4G_E_WORKSPACE
+
+
+def test_later_workspace_sizes_and_limits():
+    lib = pm4g.load()
+    for n in (0, 1, 10**6):
+        assert lib.pm4g_filter_cases_workspace_bytes(n) > 0
+        assert lib.pm4g_sample_workspace_bytes(n) > 0
+        assert lib.pm4g_efg_workspace_bytes(n, 512) > 0
+        assert lib.pm4g_ingest_csv_workspace_bytes(n * 40, n) > 0
+    assert lib.pm4g_efg_workspace_bytes(10, 4096) > 0
+    assert lib.pm4g_efg_workspace_bytes(10, 4097) == 0
+    assert lib.pm4g_efg_workspace_bytes(10, 0) == 0
+    assert lib.pm4g_efg_workspace_bytes(2**31, 16) == 0
+    assert lib.pm4g_sample_workspace_bytes(2**31) == 0
+    assert lib.pm4g_filter_cases_workspace_bytes(-1) == 0
+    assert lib.pm4g_ingest_csv_workspace_bytes(100, 2**31) == 0
+    assert lib.pm4g_ingest_csv_workspace_bytes(-1, 10) == 0
+
+
+def test_later_entry_points_validate_before_any_device_work():
+    lib = pm4g.load()
+    f = _fake(0)
+    ws = ctypes.c_void_p(0x1000)
+    prep = pm4g._Prepared(f, f, f, f, f, f, f, 10, 8)
+    out = pm4g._Prepared(f, f, f, f, f, f, f, 10, 8)
+    # sampling: k < 0, by_events outside {0, 1}
+    assert lib.pm4g_sample(ctypes.byref(prep), -1, 0, 0, ctypes.byref(out), ws, 1 << 40, None) == pm4g.PM4G_E_INVALID
+    assert lib.pm4g_sample(ctypes.byref(prep), 1, 0, 2, ctypes.byref(out), ws, 1 << 40, None) == pm4g.PM4G_E_INVALID
+    # directly-follows filter: side and keep are 0 or 1, the pair set is required
+    assert lib.pm4g_filter_df_events(ctypes.byref(prep), f, 2, 1, ctypes.byref(out), ws, 1 << 40,
+                                     None) == pm4g.PM4G_E_INVALID
+    assert lib.pm4g_filter_df_events(ctypes.byref(prep), None, 0, 1, ctypes.byref(out), ws, 1 << 40,
+                                     None) == pm4g.PM4G_E_INVALID
+    # case filter: path_keep / variant_keep are 0 or 1; a variant set needs case_variant
+    cf = pm4g.CaseFilter(0, pm4g.I64_MAX, pm4g.I64_MIN, pm4g.I64_MAX, None, None, 2, 1, pm4g.I64_MIN,
+                         pm4g.I64_MAX, pm4g.I64_MIN, pm4g.I64_MAX, None, None, None, None, 0)
+    assert lib.pm4g_filter_cases(ctypes.byref(prep), ctypes.byref(cf), ctypes.byref(out), ws, 1 << 40,
+                                 None) == pm4g.PM4G_E_INVALID
+    cf.path_keep = 1
+    cf.variant_mask = f
+    assert lib.pm4g_filter_cases(ctypes.byref(prep), ctypes.byref(cf), ctypes.byref(out), ws, 1 << 40,
+                                 None) == pm4g.PM4G_E_INVALID
+    assert b"case_variant" in lib.pm4g_last_error()
+    # the EFG above its activity limit (the prepared log itself allows 4096)
+    big = pm4g._Prepared(f, f, f, f, f, f, f, 10, 4097)
+    eo = pm4g._EfgOut(*[f] * 9)
+    assert lib.pm4g_efg(ctypes.byref(big), ctypes.byref(eo), ws, 1 << 40, None) == pm4g.PM4G_E_INVALID
+    # CSV: separator, timestamp scale and workspace
+    sc = pm4g.CsvSchema(0, 1, 2, 1, 1, 3, b'"', b"\0" * 7)
+    co = pm4g._CsvOut(f, f, f, 10, f, f, f, f, f, f, f, f, f)
+    assert lib.pm4g_ingest_csv(f, 100, ctypes.byref(sc), ctypes.byref(co), ws, 1 << 40, None) == pm4g.PM4G_E_INVALID
+    sc.sep, sc.ts_scale = b",", 10
+    assert lib.pm4g_ingest_csv(f, 100, ctypes.byref(sc), ctypes.byref(co), ws, 1 << 40, None) == pm4g.PM4G_E_INVALID
+    sc.ts_scale = 3
+    assert lib.pm4g_ingest_csv(f, 100, ctypes.byref(sc), ctypes.byref(co), ws, 16, None) == pm4g.PM4G_E_WORKSPACE
