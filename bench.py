@@ -297,7 +297,36 @@ def bench_cases(log, prep, steps: int = 5) -> dict:
             r["achieved_GBps"] = algo / dt / 1e9
             r["frac_of_hbm_peak"] = algo / dt / 1e9 / HBM_PEAK_GBS
         res[name] = r
+    res["cpu_oracle"] = _cases_oracle_timing(log, pm)
     return res
+
+
+def _cases_oracle_timing(log, path_mask, target_events: int = 2_000_000) -> dict:
+    """The oracle's case filter, directly-follows filter and sampling on the
+    cases with the lowest codes (about target_events events), single thread."""
+    import numpy as np
+
+    import oracle
+
+    cum = np.cumsum(log.lengths_by_code)
+    cut = min(int(np.searchsorted(cum, target_events, side="left")) + 1, int(cum.shape[0]))
+    keep = log.case < cut
+    c, a, t = log.case[keep], log.act[keep], log.ts[keep]
+    A = log.n_activities
+    out = {}
+    for name, call in (("filter_events_5_40", lambda: oracle.filter_cases(c, a, t, A, min_events=5, max_events=40)),
+                       ("filter_drop_paths", lambda: oracle.filter_cases(c, a, t, A, path_mask=path_mask,
+                                                                         path_keep=False)),
+                       ("df_events_drop_prev_pairs", lambda: oracle.filter_df_events(c, a, t, A, path_mask, 0,
+                                                                                     False)),
+                       ("sample_10pct_cases", lambda: oracle.sample(c, a, t, A, cut // 10, 7, False))):
+        t0 = time.perf_counter()
+        call()
+        dt = time.perf_counter() - t0
+        out[name] = {"events_per_s": c.size / dt}
+    out["cores"] = 1
+    out["sample"] = f"the {cut} cases with the lowest codes ({c.size} events), single thread"
+    return out
 
 
 def filter_bytes(name: str, n: int, c: int, kept_e: int, kept_c: int) -> int | None:
