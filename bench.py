@@ -223,7 +223,26 @@ def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int, autot
         pm4g.pm4g_dfg_batched(prep, vd[v * 24:(v + 1) * 24], md[v:v + 1], 1, tuning=one_t)
     torch.cuda.synchronize()
     per_view_s = (time.perf_counter() - t1) / len(idx)
+    # the oracle beside it: a few views whose slices hold 0.2-2M events, each
+    # given only its slice's cases (the view keeps nothing else)
+    import oracle
+
+    sizes = np.array([log.lengths_by_code[views.case_lo[v]:views.case_hi[v]].sum() for v in range(n_views)])
+    pick = np.flatnonzero((sizes >= 200_000) & (sizes <= 2_000_000))[:4]
+    o_visits, o_time = 0, 0.0
+    for v in pick:
+        sel = (log.case >= views.case_lo[v]) & (log.case < views.case_hi[v])
+        c, a, t = log.case[sel], log.act[sel], log.ts[sel]
+        t2 = time.perf_counter()
+        oracle.view(c, a, t, log.n_activities, int(views.case_lo[v]), int(views.case_hi[v]), int(views.t_lo[v]),
+                    int(views.t_hi[v]), views.masks[v])
+        o_time += time.perf_counter() - t2
+        o_visits += int(c.size)
+    cpu_oracle = {"event_view_visits_per_s": o_visits / o_time if o_time else None, "cores": 1,
+                  "sample": f"{len(pick)} views with 0.2-2M-event slices ({o_visits} event-view visits), "
+                            "each on its slice's cases, single thread"}
     return {"views_per_s": n_views / dt, "ms_per_call": dt * 1e3, "n_views": n_views,
+            "event_view_visits_per_s": visits / dt, "cpu_oracle": cpu_oracle,
             "event_view_visits": visits, "output_cells": req[0], "records": req[1],
             "per_view_launch_views_per_s": 1.0 / per_view_s,
             "per_view_launch_sample": len(idx),
