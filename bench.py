@@ -249,7 +249,7 @@ def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int, autot
             "speedup_vs_per_view_launches": per_view_s * n_views / dt,
             "stages_ms_per_call": view_stages,
             "tuning": tuned if tuned is not None else {"tile_events": tune.tile_events or 4096,
-                                                       "emit_blocks": tune.emit_blocks or 512,
+                                                       "emit_blocks": tune.emit_blocks or 2048,
                                                        "agg_blocks": tune.agg_blocks or 512}}
 
 

@@ -69,7 +69,7 @@ int resolve_tuning(const pm4g_batched_tuning* t, int64_t n, int32_t V, BatchedTu
         return PM4G_E_INVALID;
     }
     r->tile = (t && t->tile_events) ? t->tile_events : 4096;
-    r->emit_blocks = (t && t->emit_blocks) ? t->emit_blocks : 512;
+    r->emit_blocks = (t && t->emit_blocks) ? t->emit_blocks : 2048;
     r->agg_blocks = (t && t->agg_blocks) ? t->agg_blocks : 512;
     const int64_t tiles = (n + r->tile - 1) / r->tile;
     r->pair_cap = (t && t->pair_capacity) ? t->pair_capacity : 4 * (tiles + V) + 1024;

@@ -205,8 +205,8 @@ struct ViewWs {
     int64_t* scal;          // cursors and totals
     uint32_t* part32;
     int64_t* part64;
-    uint16_t* rec_cell;     // [rec_cap] records: cell within its bucket, gap
-    uint64_t* rec_gap;
+    uint16_t* rec_cell;     // [rec_cap] records: cell within its bucket (logs with a case of
+    uint64_t* rec_gap;      //   2^52 time units or more), gap; else cell << 52 | gap in rec_gap
     uint32_t* pair_dbase;   // [pair_cap] first descriptor of each (tile, view) pair
     uint32_t* pair_nd;      // [pair_cap] its descriptors (non-empty buckets)
     uint32_t* d_cnt;        // [desc_cap] run descriptors: records of the run

@@ -42,11 +42,12 @@ namespace pm4g {
 
 namespace {
 
-constexpr int kVB = 1024;                 // threads per emit block (16 waves)
+constexpr int kVB = 512;                  // threads per emit block (8 waves)
 constexpr int kVW = kVB / kWave;
 constexpr int kMaxBuckets = 264;          // >= ceil(1024 * 1025 / 4096) = 257
 constexpr int kMaskWords = PM4G_BATCHED_MAX_ACTIVITIES / 64;
 constexpr int kAB2 = 1024;                // threads per aggregation block
+constexpr uint64_t kRecGapLimit = 1ull << 52;   // gaps below it share a u64 with the cell
 
 __device__ __forceinline__ int hi_bit(uint64_t m) { return 63 - __clzll((long long)m); }
 
@@ -116,7 +117,13 @@ namespace {
 // scal: [0] records, [1] descriptor cursor, [2] #segments (u32 total
 // written at [8] as u32 by the scan, copied here), [3] temporary cell cursor,
 // [4] total output cells, [5] descriptors to sort, [6] #views, [7] #pairs,
-// [9] records placed (scan total)
+// [9] records placed (scan total), [10] nonzero when some case lasts 2^52
+// time units or more (records then keep the cell in a separate array)
+//
+// Records.  A record's gap is at most its case's duration, so when every case
+// of the log lasts less than 2^52 units a record is one u64 in rec_gap:
+// cell within its bucket (12 bits) << 52 | gap.  Otherwise the cell goes to
+// rec_cell and the full gap to rec_gap.
 
 __global__ void k_view_init(ViewWs w, int32_t V, int32_t A, const int32_t* status_in,
                             BatchedOutDev out) {
@@ -137,6 +144,20 @@ __global__ void k_view_init(ViewWs w, int32_t V, int32_t A, const int32_t* statu
         out.required[3] = 0;
         out.required[4] = 0;
     }
+}
+
+// Sets scal[10] when a case of the log lasts 2^52 time units or more (its
+// last timestamp minus its first; the prepared log is sorted by (case, ts)).
+__global__ void k_view_span(const int64_t* __restrict__ case_off, const int64_t* __restrict__ ts_s,
+                            const int64_t* n_cases, ViewWs w) {
+    const int64_t C = *n_cases;
+    bool wide = false;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < C;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t d = (uint64_t)ts_s[case_off[c + 1] - 1] - (uint64_t)ts_s[case_off[c]];
+        wide |= d >= kRecGapLimit;
+    }
+    if (__ballot(wide) != 0 && lane() == 0) atomicOr(reinterpret_cast<unsigned long long*>(&w.scal[10]), 1ull);
 }
 
 __device__ int64_t lower_bound_i32(const int32_t* a, int64_t n, int32_t x) {
@@ -264,7 +285,7 @@ __device__ WalkState walk_init(const int32_t* case_s, const int32_t* act_s, cons
 template <bool WRITE>
 __device__ void walk(const int32_t* s_case, const int16_t* s_act, const int64_t* s_ts, int64_t T0,
                      int64_t e0, int64_t e1, WalkState st, int32_t A, int64_t tlo, int64_t thi,
-                     const uint64_t* mask, uint32_t* cursor, uint16_t* rec_cell, uint64_t* rec_gap) {
+                     const uint64_t* mask, uint32_t* cursor, uint16_t* rec_cell, uint64_t* rec_gap, bool wide) {
     const int64_t AA = (int64_t)A * A;
     const uint64_t below = lanes_below();
     const uint64_t le = below | (uint64_t(1) << lane());
@@ -314,8 +335,13 @@ __device__ void walk(const int32_t* s_case, const int16_t* s_act, const int64_t*
             const uint64_t gap = has_prev ? (uint64_t)t - (uint64_t)pt : 0ull;
             const uint32_t slot = atomicAdd(&cursor[(uint32_t)(cell >> 12)], 1u);
             if (WRITE) {   // slot: the record's place (the cursor starts at its run)
-                rec_cell[slot] = (uint16_t)(cell & (kCellsPerTable - 1));
-                rec_gap[slot] = gap;
+                const uint64_t q = (uint64_t)(cell & (kCellsPerTable - 1));
+                if (wide) {
+                    rec_cell[slot] = (uint16_t)q;
+                    rec_gap[slot] = gap;
+                } else {
+                    rec_gap[slot] = (q << 52) | gap;
+                }
             }
         }
         // carry to the next window
@@ -383,7 +409,7 @@ __global__ __launch_bounds__(kVB) void k_view_count(const int32_t* __restrict__ 
                 const WalkState st = walk_init(case_s, act_s, ts_s, e0, p0, vw.t_lo, vw.t_hi, mask);
                 for (int q = lane(); q < NB; q += kWave) cur[q] = 0;
                 walk<false>(s_case, s_act, s_ts, T0, e0, e1, st, A, vw.t_lo, vw.t_hi, mask, cur,
-                            w.rec_cell, w.rec_gap);
+                            w.rec_cell, w.rec_gap, false);
                 for (int q0 = 0; q0 < NB; q0 += kWave) {
                     const int q = q0 + lane();
                     const uint32_t c = q < NB ? cur[q] : 0u;
@@ -454,6 +480,7 @@ __global__ __launch_bounds__(kVB) void k_view_write(const int32_t* __restrict__ 
 
     const int wv = threadIdx.x / kWave;
     const int MW = (A + 63) / 64;
+    const bool wide = w.scal[10] != 0;
     uint64_t* mask = s_mask[wv];
     uint32_t* cur = s_cur[wv];
     for (int64_t tile = blockIdx.x; tile < w.n_tiles; tile += gridDim.x) {
@@ -482,7 +509,7 @@ __global__ __launch_bounds__(kVB) void k_view_write(const int32_t* __restrict__ 
             const uint32_t db = w.pair_dbase[off + j];
             for (uint32_t k = lane(); k < nd; k += kWave) cur[w.d_q[db + k]] = (uint32_t)w.d_pos[db + k];
             walk<true>(s_case, s_act, s_ts, T0, e0, e1, st, A, vw.t_lo, vw.t_hi, mask, cur,
-                       w.rec_cell, w.rec_gap);
+                       w.rec_cell, w.rec_gap, wide);
         }
         __syncthreads();
     }
@@ -544,6 +571,32 @@ __device__ __forceinline__ void view_agg_rec(uint32_t* scount, uint64_t* ssum, i
         __hip_atomic_fetch_max(&smax[cell], gg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Records [r, r1) of a segment, this thread's share (stride kAB2), into the
+// LDS table; WIDE: the cell sits in rec_cell, else in the top 12 bits.
+template <bool WIDE>
+__device__ __forceinline__ void agg_records(const ViewWs& w, int64_t r, int64_t r1, uint32_t* scount,
+                                            uint64_t* ssum, int64_t* smin, int64_t* smax) {
+    constexpr int kU = 4;   // records in flight per thread
+    for (; r + (kU - 1) * kAB2 < r1; r += kU * kAB2) {
+        uint64_t x[kU];
+        uint32_t cell[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            x[u] = w.rec_gap[r + u * kAB2];
+            if (WIDE) cell[u] = w.rec_cell[r + u * kAB2];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            view_agg_rec(scount, ssum, smin, smax, WIDE ? cell[u] : (uint32_t)(x[u] >> 52),
+                         WIDE ? x[u] : (x[u] & (kRecGapLimit - 1)));
+    }
+    for (; r < r1; r += kAB2) {
+        const uint64_t x = w.rec_gap[r];
+        view_agg_rec(scount, ssum, smin, smax, WIDE ? (uint32_t)w.rec_cell[r] : (uint32_t)(x >> 52),
+                     WIDE ? x : (x & (kRecGapLimit - 1)));
+    }
+}
+
 // One block per (view, bucket) segment: its records are one contiguous range,
 // streamed into a 4096-cell LDS table; after compaction only the touched
 // cells are reset, so the table is cleared once per block.
@@ -558,6 +611,7 @@ __global__ __launch_bounds__(kAB2) void k_view_agg(const uint32_t* keys, int32_t
     const int64_t S = w.scal[2];
     const int64_t AA = (int64_t)A * A;
     const int NB = w.n_buckets;
+    const bool wide = w.scal[10] != 0;
     for (int c = threadIdx.x; c < kCellsPerTable; c += kAB2) {
         scount[c] = 0;
         ssum[c] = 0;
@@ -570,20 +624,8 @@ __global__ __launch_bounds__(kAB2) void k_view_agg(const uint32_t* keys, int32_t
         const uint32_t v = key / (uint32_t)NB;
         const uint32_t bk = key % (uint32_t)NB;
         const int64_t r1 = w.seg_rec[g + 1];
-        constexpr int kU = 4;   // records in flight per thread
-        int64_t r = w.seg_rec[g] + threadIdx.x;
-        for (; r + (kU - 1) * kAB2 < r1; r += kU * kAB2) {
-            uint32_t cell[kU];
-            uint64_t gap[kU];
-#pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                cell[u] = w.rec_cell[r + u * kAB2];
-                gap[u] = w.rec_gap[r + u * kAB2];
-            }
-#pragma unroll
-            for (int u = 0; u < kU; ++u) view_agg_rec(scount, ssum, smin, smax, cell[u], gap[u]);
-        }
-        for (; r < r1; r += kAB2) view_agg_rec(scount, ssum, smin, smax, w.rec_cell[r], w.rec_gap[r]);
+        if (wide) agg_records<true>(w, w.seg_rec[g] + threadIdx.x, r1, scount, ssum, smin, smax);
+        else agg_records<false>(w, w.seg_rec[g] + threadIdx.x, r1, scount, ssum, smin, smax);
         __syncthreads();
         // compaction in cell order; start cells go straight to the start counts
         constexpr int kPer = kCellsPerTable / kAB2;   // 4 cells per thread, blocked
@@ -741,6 +783,7 @@ hipError_t launch_views_plan(const pm4g_prepared* p, const pm4g_view* views, int
     ProfScope ps(P_VIEW_PLAN, s);
     const int32_t A = p->n_activities;
     k_view_init<<<1024, 256, 0, s>>>(w, V, A, p->status, out);
+    k_view_span<<<1024, 256, 0, s>>>(p->case_off, p->ts_s, p->n_cases, w);
     if (V > 0) k_view_slice<<<(unsigned)((V + 255) / 256), 256, 0, s>>>(views, V, p->case_off, p->case_code,
                                                                           p->n_cases, w);
     k_view_tile_scan<<<1, 1024, 0, s>>>(w);

@@ -108,3 +108,37 @@ def test_views_capacity_retry():
     views = synth.make_views(log, 16, seed=11, min_events=100, max_events=100_000)
     t = pm4g.BatchedTuning(pair_capacity=8, record_capacity=64, descriptor_capacity=16, cell_capacity=16)
     check_views(log, views, tuning=t)
+
+
+@pytest.mark.parametrize("span", [(1 << 52) - 1, 1 << 52, 1 << 62])
+def test_views_record_layouts(span):
+    """Longest case lasting just under, exactly and far over 2^52 time units:
+    below that every record packs its cell and gap into one word, otherwise the
+    cell is kept apart.  Both layouts give the oracle's tables."""
+    rng = np.random.default_rng(21)
+    lens = [2, 3] + list(rng.integers(1, 30, 600))
+    case = np.repeat(np.arange(len(lens), dtype=np.int32), lens)
+    n = case.size
+    A = 24
+    act = rng.integers(0, A, n).astype(np.int32)
+    ts = rng.integers(-(1 << 40), 1 << 40, n, dtype=np.int64)
+    b = -(1 << 61)
+    ts[0:2] = [b, b + span]                           # case 0 lasts exactly `span`
+    ts[2:5] = [b, b + span // 2, b + span]            # case 1 too, in two gaps
+    perm = rng.permutation(n)
+    log = synth.Log(case=case[perm], act=act[perm], ts=ts[perm], n_activities=A, presorted=False,
+                    lengths_by_code=np.asarray(lens, np.int64))
+    V = 10
+    lo = rng.integers(0, 4, V).astype(np.int32)
+    hi = (lo + rng.integers(1, len(lens), V)).astype(np.int32)
+    tl = np.full(V, INT64_MIN, np.int64)
+    th = np.full(V, INT64_MAX, np.int64)
+    tl[5:] = rng.integers(-(1 << 40), 0, V - 5)
+    th[5:] = tl[5:] + rng.integers(1 << 39, 1 << 41, V - 5)
+    masks = np.full((V, 1), np.uint64((1 << A) - 1))
+    masks[3, 0] = np.uint64(0xAAAAAA)
+    lo[0], hi[0] = 0, len(lens)                        # the whole log
+    views = synth.Views(case_lo=lo, case_hi=hi, t_lo=tl, t_hi=th, masks=masks)
+    note(f"views: record layouts, longest case {span}")
+    res = check_views(log, views)
+    assert int(res[0]["dt_max"].max()) == span
