@@ -196,11 +196,16 @@ def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int, autot
         tune = res["tuning"]
         tuned = {k: res["best"][k] for k in ("tile_events", "emit_blocks", "agg_blocks")}
         tuned["sweep"] = len(res["table"])
-    else:
+    else:   # the cached launch shape (library defaults without a cache entry)
         tune = pm4g.BatchedTuning(pair_capacity=int(req[3] * 1.1) + 1024,
                                   record_capacity=int(req[1] * 1.1) + 1024,
                                   descriptor_capacity=int(req[2] * 1.1) + 1024,
                                   cell_capacity=int(req[4] * 1.1) + 1024)
+        hit = tuner.default_cache().lookup(log.n_activities, n_views, prep.n_events)
+        if hit is not None:
+            tune.tile_events = int(hit["tile_events"])
+            tune.emit_blocks = int(hit["emit_blocks"])
+            tune.agg_blocks = int(hit["agg_blocks"])
     out = pm4g.pm4g_dfg_batched(prep, vd, md, n_views, tuning=tune, out=out)
     torch.cuda.synchronize()
     pm4g.profile_enable(True)
@@ -244,6 +249,7 @@ def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int, autot
     return {"views_per_s": n_views / dt, "ms_per_call": dt * 1e3, "n_views": n_views,
             "event_view_visits_per_s": visits / dt, "cpu_oracle": cpu_oracle,
             "event_view_visits": visits, "output_cells": req[0], "records": req[1],
+            "run_descriptors": req[2], "tile_view_pairs": req[3],
             "per_view_launch_views_per_s": 1.0 / per_view_s,
             "per_view_launch_sample": len(idx),
             "speedup_vs_per_view_launches": per_view_s * n_views / dt,
@@ -578,7 +584,7 @@ def main() -> int:
     ap.add_argument("--views", type=int, default=4096, help="batched drill-down views (0: skip)")
     ap.add_argument("--view-steps", type=int, default=3)
     ap.add_argument("--per-view-sample", type=int, default=64)
-    ap.add_argument("--no-autotune", action="store_true", help="batched views with the library's default shape")
+    ap.add_argument("--no-autotune", action="store_true", help="batched views with the cached launch shape (no sweep)")
     ap.add_argument("--tune-cache", default=None, help="autotune cache file (default: the package's)")
     ap.add_argument("--no-cases", action="store_true", help="skip the cases-dataframe and case-filter timing")
     ap.add_argument("--no-efg", action="store_true", help="skip the eventually-follows graph timing")

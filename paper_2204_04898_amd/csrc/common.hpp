@@ -10,6 +10,25 @@ constexpr int kWave = 64;
 
 __device__ __forceinline__ int lane() { return __lane_id(); }
 
+// XCD-contiguous work split.  The dispatcher deals a grid's blocks
+// round-robin to the 8 XCDs (block b runs on XCD b % 8), and each XCD has its
+// own L2.  Items [0, n) are cut into 8 contiguous ranges, one per XCD; the
+// blocks of an XCD stride over its range.  Neighbouring items (whose outputs
+// share cache lines at run boundaries) then meet in the same L2.  A bijection
+// for any grid; grids below 8 blocks keep the plain split.
+struct XcdSplit {
+    int64_t first, end, stride;
+};
+__device__ __forceinline__ XcdSplit xcd_split(int64_t n) {
+    const int64_t G = gridDim.x, b = blockIdx.x;
+    if (G < 8) return XcdSplit{b, n, G};
+    const int64_t x = b % 8, j = b / 8;
+    const int64_t blocks = G / 8 + (x < G % 8 ? 1 : 0);   // blocks on XCD x
+    const int64_t q = n / 8, r = n % 8;
+    const int64_t begin = x * q + (x < r ? x : r);
+    return XcdSplit{begin + j, begin + q + (x < r ? 1 : 0), blocks};
+}
+
 // Mask of the lanes below this one.
 __device__ __forceinline__ uint64_t lanes_below() {
     return (uint64_t(1) << lane()) - uint64_t(1);

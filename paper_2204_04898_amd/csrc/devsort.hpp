@@ -96,7 +96,8 @@ __global__ __launch_bounds__(kB) void k_scatter(const K* __restrict__ kin, const
     const uint32_t rs = threadIdx.x < 256 ? rowsum[threadIdx.x] : 0u;
     const uint32_t digit_base = block_excl_sum<kB>(rs, tmp, &all);
 
-    for (int64_t tile = blockIdx.x; tile < tiles_n; tile += gridDim.x) {
+    const XcdSplit xs = xcd_split(tiles_n);   // neighbouring tiles' digit runs meet in one L2
+    for (int64_t tile = xs.first; tile < xs.end; tile += xs.stride) {
         const int64_t tile0 = tile * kTile;
         const int64_t wbase = tile0 + (int64_t)w * (kWave * kI);
         for (int i = threadIdx.x; i < kW * 256; i += kB) cnt[i] = 0;

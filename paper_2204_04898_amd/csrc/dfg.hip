@@ -317,7 +317,10 @@ __global__ __launch_bounds__(kCB) void k_dfg_scatter(const int32_t* __restrict__
     const bool aligned = ((reinterpret_cast<uintptr_t>(case_s) | reinterpret_cast<uintptr_t>(act_s) |
                            reinterpret_cast<uintptr_t>(ts_s)) & 15) == 0;
     uint64_t span = 0;
-    for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+    // chunks XCD-contiguous: a bucket's runs from neighbouring chunks are
+    // neighbours in the output and meet in the same L2
+    const XcdSplit xs = xcd_split(nch);
+    for (int64_t ch = xs.first; ch < xs.end; ch += xs.stride) {
         for (int64_t k = threadIdx.x; k < nbk; k += kCB) cur[k] = ws.escan[k * nch + ch];
         const int64_t i1 = (ch + 1) * chunk < n ? (ch + 1) * chunk : n;
         for (int64_t t0 = ch * chunk; t0 < i1; t0 += kDfgTile) {

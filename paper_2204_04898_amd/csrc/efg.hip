@@ -142,7 +142,8 @@ __global__ __launch_bounds__(256) void k_efg_bscatter(const int32_t* __restrict_
     __shared__ uint32_t st_t[kEfgChunk];
     __shared__ uint16_t st_b[kEfgChunk];
     __shared__ uint32_t tmp[256 / kWave + 1];
-    for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+    const XcdSplit xs = xcd_split(nch);   // a bucket's runs of neighbouring chunks meet in one L2
+    for (int64_t ch = xs.first; ch < xs.end; ch += xs.stride) {
         uint32_t run = 0;
         for (int64_t b0 = 0; b0 < nbk; b0 += 256) {
             const int64_t b = b0 + threadIdx.x;

@@ -3,7 +3,8 @@
 //   k_radix_hist     per-tile digit histograms, digit-major [256][tiles]
 //   k_radix_scan     exclusive scan of each digit row, row totals
 //   k_radix_scatter  wave64 ballot ranking (stable: wave, item, lane order),
-//                    LDS staging in digit order, coalesced-run writes
+//                    LDS staging in digit order, coalesced-run writes; tiles
+//                    laid out XCD-contiguously over the grid
 // The first pass reads the raw log columns directly (case id biased by the
 // case minimum), so the caller's arrays are never copied.
 //
@@ -157,7 +158,10 @@ __global__ __launch_bounds__(kRB) void k_radix_scatter(SortBufs in, SortBufs out
     const int32_t case_min = info->case_min;
     const int64_t ts_min = info->ts_min;
     const int w = threadIdx.x / kWave;
-    const int64_t tile0 = (int64_t)blockIdx.x * kRadixTile;
+    // one tile per block, XCD-contiguous: the runs of neighbouring tiles meet
+    // in the same L2, where their shared boundary lines are completed
+    const int64_t tile = xcd_split(nb).first;
+    const int64_t tile0 = tile * kRadixTile;
     const int64_t wbase = tile0 + (int64_t)w * (kWave * kRI);
 
     for (int i = threadIdx.x; i < kRW * 256; i += kRB) cnt[i] = 0;
@@ -214,7 +218,7 @@ __global__ __launch_bounds__(kRB) void k_radix_scatter(SortBufs in, SortBufs out
     if (threadIdx.x < 256) {
         const int d = threadIdx.x;
         tstart[d] = ts_excl;
-        gshift[d] = (int64_t)digit_base + (int64_t)hist[(int64_t)d * nb + blockIdx.x] - (int64_t)ts_excl;
+        gshift[d] = (int64_t)digit_base + (int64_t)hist[(int64_t)d * nb + tile] - (int64_t)ts_excl;
     }
     __syncthreads();
 

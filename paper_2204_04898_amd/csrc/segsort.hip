@@ -166,7 +166,10 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
 
     const uint32_t* __restrict__ key = in.key;
     const uint32_t kmask = act_shift > 0 ? ((1u << act_shift) - 1u) : 0xFFFFFFFFu;
-    const int64_t w0 = (int64_t)blockIdx.x * kSegWindow;
+    // one window per block, XCD-contiguous: a window's lookahead is the next
+    // window's start, read by the same XCD at about the same time (its L2)
+    const int64_t win = xcd_split(gridDim.x).first;
+    const int64_t w0 = win * kSegWindow;
     const int64_t w1 = (w0 + kSegWindow) < n ? (w0 + kSegWindow) : n;
 
     // 1. one load round: the window and a lookahead are read into registers; the
@@ -197,7 +200,7 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
     }
     block_min2_i64(s, e, red);
     if (s == INT64_MAX) {   // a long case covers the whole window (block-uniform): no case starts here
-        if (threadIdx.x == 0) wincnt[blockIdx.x] = 0;
+        if (threadIdx.x == 0) wincnt[win] = 0;
         return;
     }
     for (int64_t base = w0 + kPre * kSB; e == INT64_MAX && base <= n && base - s <= kSegCap; base += kSB) {
@@ -264,7 +267,7 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
         if (threadIdx.x == 0) {   // the region's cases are the cases starting in the window
             int32_t t = 0;
             for (int k = 0; k < kSW; ++k) t += wst[k];
-            wincnt[blockIdx.x] = (uint32_t)t;
+            wincnt[win] = (uint32_t)t;
         }
         int32_t before = 0;
         for (int i = 0; i < w; ++i) before = wred[i] > before ? wred[i] : before;

@@ -217,12 +217,16 @@ __global__ __launch_bounds__(1024) void k_view_tile_scan(ViewWs w) {
     }
 }
 
+// One wave per view, its lanes over the view's tiles (a view can span
+// thousands of tiles; one thread per view made that a serial atomic chain).
 __global__ void k_view_fill(int32_t V, ViewWs w) {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V;
-         v += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+    for (int64_t v = wv; v < V; v += nw) {
         const int64_t p0 = w.p0[v], p1 = w.p1[v];
         if (p1 <= p0) continue;
-        for (int64_t t = p0 / w.tile; t <= (p1 - 1) / w.tile; ++t) {
+        const int64_t t1 = (p1 - 1) / w.tile;
+        for (int64_t t = p0 / w.tile + lane(); t <= t1; t += kWave) {
             const int64_t at = (int64_t)w.toff[t] + atomicAdd(&w.tcursor[t], 1u);
             if (at < w.pair_cap) w.list[at] = (uint32_t)v;
         }
@@ -483,6 +487,9 @@ __global__ __launch_bounds__(kVB) void k_view_write(const int32_t* __restrict__ 
     const bool wide = w.scal[10] != 0;
     uint64_t* mask = s_mask[wv];
     uint32_t* cur = s_cur[wv];
+    // tiles interleaved over the grid and so over the XCDs (contiguous per-XCD
+    // ranges measured slower here: a tile's work follows the number of views
+    // overlapping it, which varies along the log)
     for (int64_t tile = blockIdx.x; tile < w.n_tiles; tile += gridDim.x) {
         const int64_t T0 = tile * TILE;
         const int64_t T1 = (T0 + TILE) < n ? (T0 + TILE) : n;
@@ -787,7 +794,7 @@ hipError_t launch_views_plan(const pm4g_prepared* p, const pm4g_view* views, int
     if (V > 0) k_view_slice<<<(unsigned)((V + 255) / 256), 256, 0, s>>>(views, V, p->case_off, p->case_code,
                                                                           p->n_cases, w);
     k_view_tile_scan<<<1, 1024, 0, s>>>(w);
-    if (V > 0) k_view_fill<<<(unsigned)((V + 255) / 256), 256, 0, s>>>(V, w);
+    if (V > 0) k_view_fill<<<(unsigned)((V + 3) / 4), 256, 0, s>>>(V, w);
     return hipGetLastError();
 }
 
