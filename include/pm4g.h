@@ -279,7 +279,9 @@ int pm4g_variants_prepared(const pm4g_prepared *log, const pm4g_variants_out *ou
  * (and fills out->required) when a pair, record or descriptor capacity of
  * `tuning` is too small: call again with larger capacities.  The cell and
  * output capacities (cell_capacity, cap_edges) are checked on the device and
- * reported in out->status and out->required.
+ * reported in out->status and out->required.  n_views times the number of
+ * 4096-cell buckets of the A*(A+1) cells, ceil(A*(A+1)/4096), must stay below
+ * 2^32 (else PM4G_E_INVALID, and a workspace size of 0).
  */
 size_t pm4g_batched_workspace_bytes(int64_t n_events, int32_t n_activities, int32_t n_views,
                                     const pm4g_batched_tuning *tuning);

@@ -351,6 +351,7 @@ size_t pm4g_batched_workspace_bytes(int64_t n_events, int32_t n_activities, int3
                                     const pm4g_batched_tuning* tuning) {
     if (n_events < 0 || n_events > kMaxEvents || n_views < 0) return 0;
     if (n_activities < 1 || n_activities > PM4G_BATCHED_MAX_ACTIVITIES) return 0;
+    if ((int64_t)n_views * view_buckets(n_activities) > (int64_t)0xFFFFFFFF) return 0;
     BatchedTune t;
     if (resolve_tuning(tuning, n_events, n_views, &t) != PM4G_OK) return 0;
     return batched_ws_bytes(n_events, n_activities, n_views, t);
@@ -573,6 +574,9 @@ int pm4g_dfg_batched(const pm4g_prepared* log, const pm4g_view* views, const uin
     PM4G_CHECK(log->n_activities <= PM4G_BATCHED_MAX_ACTIVITIES, "n_activities %d above %d for batched views",
                log->n_activities, PM4G_BATCHED_MAX_ACTIVITIES);
     PM4G_CHECK(n_views >= 0, "n_views < 0");
+    PM4G_CHECK((int64_t)n_views * view_buckets(log->n_activities) <= (int64_t)0xFFFFFFFF,
+               "%d views of %d activities: more (view, cell bucket) pairs than 2^32 - 1; split the views",
+               n_views, log->n_activities);
     PM4G_CHECK(n_views == 0 || (views && act_masks), "views or act_masks is NULL");
     PM4G_CHECK(out && out->edge_off && out->start_count && out->end_count && out->act_count && out->n_events &&
                    out->n_cases && out->required && out->status && out->cap_edges >= 0 &&

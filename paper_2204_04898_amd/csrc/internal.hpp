@@ -209,21 +209,15 @@ struct ViewWs {
     uint64_t* rec_gap;      //   2^52 time units or more), gap; else cell << 52 | gap in rec_gap
     uint32_t* pair_dbase;   // [pair_cap] first descriptor of each (tile, view) pair
     uint32_t* pair_nd;      // [pair_cap] its descriptors (non-empty buckets)
-    uint32_t* d_cnt;        // [desc_cap] run descriptors: records of the run
-    uint16_t* d_q;          //   bucket of the run
-    int64_t* d_pos;         //   first record of the run (segment-contiguous layout)
-    uint32_t* d_cnt_sorted; //   counts in (view, bucket) order
-    int64_t* d_pos_sorted;
-    int64_t* seg_rec;       // [segments + 1] first record of each (view, bucket) segment
-    uint32_t* d_key;        // (view, bucket) sort keys, ping-pong with d_key2
-    uint32_t* d_key2;
-    uint32_t* d_idx;
-    uint32_t* d_idx2;
-    uint32_t* d_hist;
-    uint32_t* d_rowsum;
-    uint32_t* seg_flag;     // segment starts in the sorted descriptors
-    uint32_t* seg_id;
-    uint32_t* seg_start;
+    uint16_t* d_q;          // [desc_cap] run descriptors: bucket of the run
+    uint32_t* d_rel;        //   first record of the run within its (view, bucket) segment
+    int64_t n_vb;           // V * n_buckets (view, bucket) pairs
+    uint32_t* vb_cnt;       // [n_vb] records of each (view, bucket)
+    int64_t* vb_base;       // [n_vb] its segment's first record (exclusive scan)
+    uint32_t* vb_flag;      // [n_vb] non-empty
+    uint32_t* vb_seg;       // [n_vb] segment index of a non-empty pair
+    uint32_t* seg_key;      // [segments] view * n_buckets + bucket, increasing
+    int64_t* seg_rec;       // [segments + 1] first record of each segment
     uint32_t* seg_cells;    // non-empty pair cells per segment
     int64_t* seg_tmp;       // their place in the temporary cell arrays
     int64_t* seg_out;       // their place in the output lists

@@ -12,7 +12,7 @@ const char* kNames[P_COUNT] = {
     "range_scan",   "radix_hist", "radix_scan", "radix_scatter", "segsort",
     "case_table",   "dfg_main",   "dfg_plan",   "dfg_agg",       "dfg_reduce",
     "variant_hash", "variant_sort", "variant_group", "variant_order", "variant_emit",
-    "view_plan",    "view_emit",  "view_sort",  "view_agg",      "view_out",
+    "view_plan",    "view_emit",  "view_place",  "view_agg",      "view_out",
     "view_filter",  "dfg_count",  "view_write", "cases",         "case_filter",
     "df_filter",    "efg",        "sample",        "csv"};
 

@@ -25,7 +25,7 @@ enum ProfId {
     P_VAR_EMIT,
     P_VIEW_PLAN,
     P_VIEW_EMIT,
-    P_VIEW_SORT,
+    P_VIEW_PLACE,
     P_VIEW_AGG,
     P_VIEW_OUT,
     P_VIEW_FILTER,

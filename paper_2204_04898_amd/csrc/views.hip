@@ -15,15 +15,17 @@
 //                    case table); a slice always holds whole cases
 //   k_view_tile_scan per-tile counts of overlapping views, offsets
 //   k_view_fill      per-tile lists of overlapping views
-//   k_view_emit      tile-major: a block stages one tile of the log in LDS;
-//                    each wave takes one overlapping view and walks the tile 64
+//   k_view_count /   tile-major: a block stages one tile of the log in LDS;
+//   k_view_write     each wave takes one overlapping view and walks the tile 64
 //                    events at a time: ballots give the previous kept event of
 //                    the same case, carried across windows and (by a backward
 //                    search) across tiles.  A pair gives a record (cell = x*A+y,
 //                    gap); a start gives (A*A + y, 0).  The walk runs twice:
-//                    count per cell bucket (cell >> 12), reserve, write runs;
-//                    one descriptor per (tile, view, bucket) run.
-//   radix sort       descriptors by (view, bucket)
+//                    count per cell bucket (cell >> 12) and take each run's
+//                    place in its (view, bucket) segment with one atomic (one
+//                    descriptor per (tile, view, bucket) run), then write runs
+//   scans            (view, bucket) counters -> segment places; non-empty
+//                    pairs -> the segment list
 //   k_view_agg       one block per (view, bucket) segment: 4096-cell LDS table;
 //                    non-empty pair cells -> temporary sparse records, start
 //                    cells -> start counts
@@ -85,24 +87,19 @@ ViewWs view_ws_layout(Bump& b, int64_t n, int32_t A, int32_t V, int32_t tile, in
     w.rec_gap = b.take<uint64_t>(rc);
     w.pair_dbase = b.take<uint32_t>((size_t)(pair_cap > 0 ? pair_cap : 1));
     w.pair_nd = b.take<uint32_t>((size_t)(pair_cap > 0 ? pair_cap : 1));
-    w.d_cnt = b.take<uint32_t>(dc);
     w.d_q = b.take<uint16_t>(dc);
-    w.d_pos = b.take<int64_t>(dc);
-    w.d_cnt_sorted = b.take<uint32_t>(dc);
-    w.d_pos_sorted = b.take<int64_t>(dc);
-    w.seg_rec = b.take<int64_t>(dc + 1);
-    w.d_key = b.take<uint32_t>(dc);
-    w.d_key2 = b.take<uint32_t>(dc);
-    w.d_idx = b.take<uint32_t>(dc);
-    w.d_idx2 = b.take<uint32_t>(dc);
-    w.d_hist = b.take<uint32_t>(256 * (size_t)(dev::tiles((int64_t)dc) + 1));
-    w.d_rowsum = b.take<uint32_t>(256);
-    w.seg_flag = b.take<uint32_t>(dc);
-    w.seg_id = b.take<uint32_t>(dc);
-    w.seg_start = b.take<uint32_t>(dc + 1);
-    w.seg_cells = b.take<uint32_t>(dc);
-    w.seg_tmp = b.take<int64_t>(dc);
-    w.seg_out = b.take<int64_t>(dc);
+    w.d_rel = b.take<uint32_t>(dc);
+    w.n_vb = (int64_t)(V > 0 ? V : 0) * w.n_buckets;
+    const size_t nvb = (size_t)(w.n_vb > 0 ? w.n_vb : 1);
+    w.vb_cnt = b.take<uint32_t>(nvb);
+    w.vb_base = b.take<int64_t>(nvb);
+    w.vb_flag = b.take<uint32_t>(nvb);
+    w.vb_seg = b.take<uint32_t>(nvb);
+    w.seg_key = b.take<uint32_t>(nvb);
+    w.seg_rec = b.take<int64_t>(nvb + 1);
+    w.seg_cells = b.take<uint32_t>(nvb);
+    w.seg_tmp = b.take<int64_t>(nvb);
+    w.seg_out = b.take<int64_t>(nvb);
     w.view_cells = b.take<uint32_t>(vm);
     w.t_cell = b.take<uint32_t>(cc);
     w.t_count = b.take<uint32_t>(cc);
@@ -116,9 +113,15 @@ namespace {
 
 // scal: [0] records, [1] descriptor cursor, [2] #segments (u32 total
 // written at [8] as u32 by the scan, copied here), [3] temporary cell cursor,
-// [4] total output cells, [5] descriptors to sort, [6] #views, [7] #pairs,
-// [9] records placed (scan total), [10] nonzero when some case lasts 2^52
-// time units or more (records then keep the cell in a separate array)
+// [4] total output cells, [6] #views, [7] #pairs, [9] records placed (scan
+// total), [10] nonzero when some case lasts 2^52 time units or more (records
+// then keep the cell in a separate array), [11] (view, bucket) pairs
+//
+// Record places.  The count walk adds each (tile, view) pair's records per
+// bucket to the (view, bucket) counter with one atomic, whose old value is the
+// run's place inside that (view, bucket) segment; an exclusive scan of the
+// counters in (view, bucket) order gives the segments' places, so every
+// segment's records form one contiguous range in (view, bucket) order.
 //
 // Records.  A record's gap is at most its case's duration, so when every case
 // of the log lasts less than 2^52 units a record is one u64 in rec_gap:
@@ -134,8 +137,9 @@ __global__ void k_view_init(ViewWs w, int32_t V, int32_t A, const int32_t* statu
         w.tcursor[i] = 0;
     }
     for (int64_t i = i0; i < V; i += stride) w.view_cells[i] = 0;
+    for (int64_t i = i0; i < w.n_vb; i += stride) w.vb_cnt[i] = 0;
     for (int64_t i = i0; i < (int64_t)V * A; i += stride) out.start_count[i] = 0;
-    if (i0 < 16) w.scal[i0] = 0;
+    if (i0 < 16) w.scal[i0] = i0 == 11 ? w.n_vb : 0;
     if (i0 == 0) {
         *out.status = (status_in && *status_in) ? *status_in : 0;
         out.required[0] = 0;
@@ -453,12 +457,13 @@ __global__ __launch_bounds__(kVB) void k_view_count(const int32_t* __restrict__ 
                     const int q = q0 + lane();
                     const uint32_t c = q < NB ? cur[q] : 0u;
                     const uint64_t nzm = __ballot(c != 0);
-                    if (ok && c != 0) {
-                        const int64_t d = dbase + drun + __popcll(nzm & lanes_below());
-                        w.d_key[d] = v * (uint32_t)NB + (uint32_t)q;
-                        w.d_idx[d] = (uint32_t)d;
-                        w.d_cnt[d] = c;
-                        w.d_q[d] = (uint16_t)q;
+                    if (c != 0) {
+                        const uint32_t rel = atomicAdd(&w.vb_cnt[(size_t)v * NB + q], c);
+                        if (ok) {
+                            const int64_t d = dbase + drun + __popcll(nzm & lanes_below());
+                            w.d_q[d] = (uint16_t)q;
+                            w.d_rel[d] = rel;
+                        }
                     }
                     drun += (uint32_t)__popcll(nzm);
                 }
@@ -514,7 +519,10 @@ __global__ __launch_bounds__(kVB) void k_view_write(const int32_t* __restrict__ 
             const WalkState st = walk_init(case_s, act_s, ts_s, e0, p0, vw.t_lo, vw.t_hi, mask);
             // cursors: the runs' first records (buckets without a run get no event)
             const uint32_t db = w.pair_dbase[off + j];
-            for (uint32_t k = lane(); k < nd; k += kWave) cur[w.d_q[db + k]] = (uint32_t)w.d_pos[db + k];
+            for (uint32_t k = lane(); k < nd; k += kWave) {
+                const uint32_t q = w.d_q[db + k];
+                cur[q] = (uint32_t)(w.vb_base[(size_t)v * w.n_buckets + q] + w.d_rel[db + k]);
+            }
             walk<true>(s_case, s_act, s_ts, T0, e0, e1, st, A, vw.t_lo, vw.t_hi, mask, cur,
                        w.rec_cell, w.rec_gap, wide);
         }
@@ -522,49 +530,28 @@ __global__ __launch_bounds__(kVB) void k_view_write(const int32_t* __restrict__ 
     }
 }
 
-__global__ void k_view_seg_count(ViewWs w, int32_t V) {
-    w.scal[5] = w.scal[1] < w.desc_cap ? w.scal[1] : w.desc_cap;
-    w.scal[6] = V;
+__global__ void k_view_vb_flags(ViewWs w, int32_t V) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < w.n_vb;
+         i += (int64_t)gridDim.x * blockDim.x)
+        w.vb_flag[i] = w.vb_cnt[i] != 0 ? 1u : 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) w.scal[6] = V;
 }
 
-// Segment starts of the sorted descriptor keys.
-__global__ void k_view_seg_flags(const uint32_t* keys, ViewWs w) {
-    const int64_t D = w.scal[5];
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < D;
-         p += (int64_t)gridDim.x * blockDim.x)
-        w.seg_flag[p] = (p == 0 || keys[p] != keys[p - 1]) ? 1u : 0u;
-}
-
-__global__ void k_view_seg_starts(ViewWs w) {
-    const int64_t D = w.scal[5];
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < D;
-         p += (int64_t)gridDim.x * blockDim.x)
-        if (w.seg_flag[p]) w.seg_start[w.seg_id[p]] = (uint32_t)p;
+// Segments: the non-empty (view, bucket) pairs in increasing order, each with
+// its first record; the records' total closes the list.
+__global__ void k_view_segs(ViewWs w) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < w.n_vb;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (!w.vb_flag[i]) continue;
+        const uint32_t g = w.vb_seg[i];
+        w.seg_key[g] = (uint32_t)i;
+        w.seg_rec[g] = w.vb_base[i];
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const int64_t S = (int64_t)((uint32_t*)&w.scal[8])[0];
-        w.seg_start[S] = (uint32_t)D;
+        w.seg_rec[S] = w.scal[9];
         w.scal[2] = S;
     }
-}
-
-// Run places: descriptor counts in (view, bucket) order, their exclusive scan,
-// back to the descriptors; each segment's first record.
-__global__ void k_view_gather_cnt(const uint32_t* idx, ViewWs w) {
-    const int64_t D = w.scal[5];
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < D;
-         p += (int64_t)gridDim.x * blockDim.x)
-        w.d_cnt_sorted[p] = w.d_cnt[idx[p]];
-}
-
-__global__ void k_view_place(const uint32_t* idx, ViewWs w) {
-    const int64_t D = w.scal[5];
-    const int64_t S = w.scal[2];
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < D;
-         p += (int64_t)gridDim.x * blockDim.x)
-        w.d_pos[idx[p]] = w.d_pos_sorted[p];
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g <= S;
-         g += (int64_t)gridDim.x * blockDim.x)
-        w.seg_rec[g] = g < S ? w.d_pos_sorted[w.seg_start[g]] : w.scal[9];
 }
 
 __device__ __forceinline__ void view_agg_rec(uint32_t* scount, uint64_t* ssum, int64_t* smin, int64_t* smax,
@@ -607,8 +594,7 @@ __device__ __forceinline__ void agg_records(const ViewWs& w, int64_t r, int64_t 
 // One block per (view, bucket) segment: its records are one contiguous range,
 // streamed into a 4096-cell LDS table; after compaction only the touched
 // cells are reset, so the table is cleared once per block.
-__global__ __launch_bounds__(kAB2) void k_view_agg(const uint32_t* keys, int32_t A, ViewWs w,
-                                                   BatchedOutDev out) {
+__global__ __launch_bounds__(kAB2) void k_view_agg(int32_t A, ViewWs w, BatchedOutDev out) {
     __shared__ uint32_t scount[kCellsPerTable];
     __shared__ uint64_t ssum[kCellsPerTable];
     __shared__ int64_t smin[kCellsPerTable];
@@ -627,7 +613,7 @@ __global__ __launch_bounds__(kAB2) void k_view_agg(const uint32_t* keys, int32_t
     }
     __syncthreads();
     for (int64_t g = blockIdx.x; g < S; g += gridDim.x) {
-        const uint32_t key = keys[w.seg_start[g]];
+        const uint32_t key = w.seg_key[g];
         const uint32_t v = key / (uint32_t)NB;
         const uint32_t bk = key % (uint32_t)NB;
         const int64_t r1 = w.seg_rec[g + 1];
@@ -706,7 +692,7 @@ __global__ void k_view_copy(int32_t A, ViewWs w, BatchedOutDev out) {
 
 // Per view: its segments form a run of the sorted segment list; fold their
 // cells into row and column sums; derive activity and end counts.
-__global__ __launch_bounds__(256) void k_view_acts(const uint32_t* keys, int32_t V, int32_t A, ViewWs w,
+__global__ __launch_bounds__(256) void k_view_acts(int32_t V, int32_t A, ViewWs w,
                                                    BatchedOutDev out) {
     __shared__ unsigned long long rows[PM4G_BATCHED_MAX_ACTIVITIES];
     __shared__ unsigned long long cols[PM4G_BATCHED_MAX_ACTIVITIES];
@@ -721,10 +707,10 @@ __global__ __launch_bounds__(256) void k_view_acts(const uint32_t* keys, int32_t
         int64_t lo = 0, hi = S;
         while (lo < hi) {
             const int64_t mid = (lo + hi) >> 1;
-            if (keys[w.seg_start[mid]] < (uint32_t)v * NB) lo = mid + 1;
+            if (w.seg_key[mid] < (uint32_t)v * NB) lo = mid + 1;
             else hi = mid;
         }
-        for (int64_t g = lo; g < S && keys[w.seg_start[g]] / NB == (uint32_t)v; ++g) {
+        for (int64_t g = lo; g < S && w.seg_key[g] / NB == (uint32_t)v; ++g) {
             const int64_t src = w.seg_tmp[g];
             const uint32_t m = w.seg_cells[g];
             for (uint32_t r = threadIdx.x; r < m; r += 256) {
@@ -777,12 +763,6 @@ __global__ void k_view_finish(int32_t V, ViewWs w, BatchedOutDev out) {
     }
 }
 
-int bits_u32(uint64_t x) {
-    int b = 0;
-    while (b < 32 && (uint64_t(1) << b) <= x) ++b;
-    return b;
-}
-
 }  // namespace
 
 hipError_t launch_views_plan(const pm4g_prepared* p, const pm4g_view* views, int32_t V, ViewWs w,
@@ -826,27 +806,17 @@ hipError_t launch_views_write(const pm4g_prepared* p, const pm4g_view* views, co
     return hipGetLastError();
 }
 
-// Sorts the descriptors by (view, bucket), places the runs, writes the
-// records (write walk), aggregates per segment.
+// Places the (view, bucket) segments, writes the records (write walk),
+// aggregates per segment.
 hipError_t launch_views_reduce(const pm4g_prepared* p, const pm4g_view* views, const uint64_t* masks, int32_t V,
                                ViewWs w, BatchedOutDev out, int emit_grid, int agg_grid, hipStream_t s) {
     const int32_t A = p->n_activities;
-    const uint32_t* keys;
     {
-        ProfScope ps(P_VIEW_SORT, s);
-        // descriptors to sort: min(cursor, capacity); the host only comes here if they fit
-        k_view_seg_count<<<1, 1, 0, s>>>(w, V);
-        const int kb = bits_u32((uint64_t)(V > 0 ? V : 1) * (uint64_t)w.n_buckets);
-        const bool flip = dev::sort_pairs<uint32_t>(w.d_key, w.d_idx, w.d_key2, w.d_idx2, &w.scal[5], w.desc_cap,
-                                                    kb, w.d_hist, w.d_rowsum, s);
-        keys = flip ? w.d_key2 : w.d_key;
-        const uint32_t* idx = flip ? w.d_idx2 : w.d_idx;
-        k_view_seg_flags<<<2048, 256, 0, s>>>(keys, w);
-        dev::excl_scan<uint32_t>(w.seg_flag, &w.scal[5], w.seg_id, w.part32, (uint32_t*)&w.scal[8], s);
-        k_view_seg_starts<<<2048, 256, 0, s>>>(w);
-        k_view_gather_cnt<<<2048, 256, 0, s>>>(idx, w);
-        dev::excl_scan<int64_t>(w.d_cnt_sorted, &w.scal[5], w.d_pos_sorted, w.part64, &w.scal[9], s);
-        k_view_place<<<2048, 256, 0, s>>>(idx, w);
+        ProfScope ps(P_VIEW_PLACE, s);
+        k_view_vb_flags<<<1024, 256, 0, s>>>(w, V);
+        dev::excl_scan<int64_t>(w.vb_cnt, &w.scal[11], w.vb_base, w.part64, &w.scal[9], s);
+        dev::excl_scan<uint32_t>(w.vb_flag, &w.scal[11], w.vb_seg, w.part32, (uint32_t*)&w.scal[8], s);
+        k_view_segs<<<1024, 256, 0, s>>>(w);
     }
     {
         const hipError_t e = launch_views_write(p, views, masks, w, emit_grid, s);
@@ -854,14 +824,14 @@ hipError_t launch_views_reduce(const pm4g_prepared* p, const pm4g_view* views, c
     }
     {
         ProfScope ps(P_VIEW_AGG, s);
-        k_view_agg<<<(unsigned)agg_grid, kAB2, 0, s>>>(keys, A, w, out);
+        k_view_agg<<<(unsigned)agg_grid, kAB2, 0, s>>>(A, w, out);
     }
     {
         ProfScope ps(P_VIEW_OUT, s);
         dev::excl_scan<int64_t>(w.seg_cells, &w.scal[2], w.seg_out, w.part64, &w.scal[4], s);
         dev::excl_scan<int64_t>(w.view_cells, &w.scal[6], out.edge_off, w.part64, (int64_t*)nullptr, s);
         k_view_copy<<<2048, 256, 0, s>>>(A, w, out);
-        k_view_acts<<<2048, 256, 0, s>>>(keys, V, A, w, out);
+        k_view_acts<<<2048, 256, 0, s>>>(V, A, w, out);
         k_view_finish<<<1, 1, 0, s>>>(V, w, out);
     }
     return hipGetLastError();
