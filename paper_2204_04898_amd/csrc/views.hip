@@ -53,6 +53,15 @@ constexpr uint64_t kRecGapLimit = 1ull << 52;   // gaps below it share a u64 wit
 
 __device__ __forceinline__ int hi_bit(uint64_t m) { return 63 - __clzll((long long)m); }
 
+// Value of lane l (l the same in every lane: read into a scalar register, no
+// LDS round trip as a shuffle would take).
+__device__ __forceinline__ int32_t lane_i32(int32_t v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ int64_t lane_i64(int64_t v, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 }  // namespace
 
 int64_t view_buckets(int32_t A) {
@@ -310,7 +319,9 @@ __device__ void walk(const int32_t* s_case, const int16_t* s_act, const int64_t*
             t = s_ts[li];
             k = kept(a, t, tlo, thi, mask);
         }
-        const int32_t cup = __shfl_up(c, 1);
+        // lane l - 1's case (DPP wave shift right by one; lane 0 reads 0 and
+        // uses the carry below)
+        const int32_t cup = __builtin_amdgcn_update_dpp(0, c, 0x138, 0xF, 0xF, false);
         bool starts;
         if (lane() == 0) starts = !st.have_cur || c != st.cur;
         else starts = c != cup;
@@ -319,7 +330,7 @@ __device__ void walk(const int32_t* s_case, const int16_t* s_act, const int64_t*
         const uint64_t S = __ballot(starts);
         if (K == 0) {   // wave-uniform: nothing kept in this step, only the carry moves
             if (S) st.cr_valid = false;   // the last case began here, nothing of it kept yet
-            st.cur = __shfl(c, hi_bit(__ballot(in)));
+            st.cur = lane_i32(c, hi_bit(__ballot(in)));
             st.have_cur = true;
             continue;
         }
@@ -356,8 +367,8 @@ __device__ void walk(const int32_t* s_case, const int16_t* s_act, const int64_t*
         const int lastS = S ? hi_bit(S) : -1;
         const uint64_t Klast = lastS < 0 ? K : (K & ~((uint64_t(1) << lastS) - 1));
         const int lk = Klast ? hi_bit(Klast) : 0;
-        const int32_t ak = __shfl(a, lk);
-        const int64_t tk = __shfl(t, lk);
+        const int32_t ak = lane_i32(a, lk);
+        const int64_t tk = lane_i64(t, lk);
         if (Klast) {
             st.cr_valid = true;
             st.cr_a = ak;
@@ -366,7 +377,7 @@ __device__ void walk(const int32_t* s_case, const int16_t* s_act, const int64_t*
             st.cr_valid = false;
         }
         const int lin = hi_bit(__ballot(in));
-        st.cur = __shfl(c, lin);
+        st.cur = lane_i32(c, lin);
         st.have_cur = true;
     }
 }
