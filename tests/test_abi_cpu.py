@@ -114,6 +114,13 @@ def test_batched_and_filter_validation():
                                 16, None) == pm4g.PM4G_E_WORKSPACE
     assert lib.pm4g_batched_workspace_bytes(100, 16, 4, None) > 0
     assert lib.pm4g_batched_workspace_bytes(100, 2000, 4, None) == 0
+    # (view, cell bucket) pairs at and past 2^32: A = 1024 has 257 buckets
+    big = pm4g._Prepared(*([_fake(0)] * 7), 100, 1024)
+    v_ok, v_over = (2**32 - 1) // 257, (2**32 - 1) // 257 + 1
+    assert lib.pm4g_batched_workspace_bytes(100, 1024, v_over, None) == 0
+    assert lib.pm4g_dfg_batched(ctypes.byref(big), _fake(0), _fake(0), v_over, ctypes.byref(out), None, ws,
+                                1 << 40, None) == pm4g.PM4G_E_INVALID
+    assert lib.pm4g_batched_workspace_bytes(100, 1024, v_ok, None) > 0
     t = pm4g.BatchedTuning(record_capacity=10**6)
     assert lib.pm4g_batched_workspace_bytes(100, 16, 4, ctypes.byref(t)) > lib.pm4g_batched_workspace_bytes(
         100, 16, 4, None)
