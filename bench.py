@@ -9,9 +9,10 @@ log (5M cases, lognormal lengths, 512 Zipf activities, ns timestamps,
 shuffled rows).
 
 Prints one JSON line: events/s for the whole step, the roofline of the
-dominant kernel (algorithmic bytes per launch over its HIP-event-timed
-average duration on the launching stream), and the CPU oracle timed on a
-bounded sample of the same workload.
+dominant kernel (the one with the most time per step: algorithmic bytes per
+launch over its HIP-event-timed average duration on the launching stream;
+the next kernel beside it), and the CPU oracle timed on a bounded sample of
+the same workload.
 """
 from __future__ import annotations
 
@@ -120,6 +121,33 @@ def measured_step_traffic(workload: str) -> float | None:
         return float(kv["bytes_per_step"])
     except (KeyError, ValueError):
         return None
+
+
+def valu_issue_frac(stage: str, workload: str, per_launch_ms: float) -> float | None:
+    """VALU instructions per launch (committed rocprofv3 SQ_INSTS_VALU summary)
+    over the launch time, against one wave64 VALU instruction per CU per cycle;
+    None when the stage is not in the summary or its sources changed since."""
+    import re
+
+    path = os.path.join(ROOT, "profiles", "valu_counters_step_views_100M.txt")
+    if workload != "dfg-variants-100M" or stage not in ("segsort", "radix_scatter") or not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(rf"{stage} = ([0-9a-f]+)", text)
+    if not m or m.group(1) != source_sha(STAGE_SOURCES[stage]):
+        return None
+    insts = []
+    for line in text.splitlines():
+        cols = [c.strip() for c in line.split("|")]
+        if len(cols) == 10 and cols[0].startswith("k_" + stage):
+            insts.append((cols[0], float(cols[2])))
+    if not insts:
+        return None
+    if stage == "radix_scatter":   # launches of one step: the first pass once, the others twice
+        per_launch = sum(v * (1 if "true, true" in k else 2) for k, v in insts) / 3.0
+    else:
+        per_launch = insts[0][1]
+    return per_launch / (per_launch_ms * 1e-3) / (256 * 2.4e9)
 
 
 def measured_traffic(stage: str, workload: str) -> float | None:
@@ -657,12 +685,24 @@ def main() -> int:
               for name, (tot, cnt) in prof.items() if cnt}
     packed, passes = packed_keys(log), radix_passes(log)
     kb = lambda name: kernel_bytes(name, N, C, A, log.presorted, packed, passes)
-    dominant = max(((n, v) for n, v in prof.items() if kb(n) and v[1]), key=lambda kv: kv[1][0])
-    dname, (dms, dcnt) = dominant
+    # the kernel with the most time per step, and the next one (the radix
+    # scatter's three launches and the per-case sort's one are close)
+    ranked = sorted(((n, v) for n, v in prof.items() if kb(n) and v[1]), key=lambda kv: -kv[1][0])
+    dname, (dms, dcnt) = ranked[0]
     per_launch_ms = dms / dcnt
     algo = kb(dname)
     achieved = algo / (per_launch_ms * 1e-3) / 1e9
     traffic = measured_traffic(dname, args.workload)
+    runner_up = None
+    if len(ranked) > 1:
+        rname, (rms, rcnt) = ranked[1]
+        r_launch = rms / rcnt
+        r_ach = kb(rname) / (r_launch * 1e-3) / 1e9
+        runner_up = {"kernel": rname, "ms_per_step": rms / args.steps, "achieved": r_ach, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": r_ach / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(rname, args.workload),
+                     "algorithmic_bytes_per_launch": kb(rname), "avg_launch_ms": r_launch,
+                     "valu_issue_frac": valu_issue_frac(rname, args.workload, r_launch)}
 
     out = {
         "metric": "DFG events/sec on 1 MI355X + % HBM roofline",
@@ -681,7 +721,12 @@ def main() -> int:
                    "n_activities": A, "step": "prepare + dfg" + ("" if args.no_variants else " + variants")},
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": algo, "avg_launch_ms": per_launch_ms},
+                     "algorithmic_bytes_per_launch": algo, "avg_launch_ms": per_launch_ms,
+                     "ms_per_step": dms / args.steps,
+                     # instruction-bound kernels: the VALU issue rate reached (one
+                     # wave64 instruction per CU per cycle is the peak)
+                     "valu_issue_frac": valu_issue_frac(dname, args.workload, per_launch_ms),
+                     "runner_up": runner_up},
         "stages": stages,
     }
     # the whole step against the HBM peak: measured traffic (all kernels of one

@@ -35,28 +35,33 @@ __device__ __forceinline__ uint64_t lanes_below() {
 }
 
 // Lanes of this wave whose 8-bit digit equals this lane's, among `active`.
+// Per bit: the lanes agreeing with this lane are ~(ballot ^ s), s this lane's
+// bit spread over the word (0 or all ones), which gfx950 folds with the and
+// into one three-input bit operation per 32-bit half.
 __device__ __forceinline__ uint64_t match_digit8(uint32_t d, uint64_t active) {
-    uint64_t peers = active;
+    uint32_t lo = (uint32_t)active, hi = (uint32_t)(active >> 32);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t m = __ballot(bit);
-        peers &= bit ? m : ~m;
+        const uint32_t s = 0u - ((d >> b) & 1u);
+        const uint64_t m = __ballot(s != 0u);
+        lo &= ~((uint32_t)m ^ s);
+        hi &= ~((uint32_t)(m >> 32) ^ s);
     }
-    return peers;
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // Lanes of this wave whose value agrees with this lane's in the low `bits`
 // bits, among `active`.  Every lane of the wave must execute it (`bits` is
 // wave-uniform).
 __device__ __forceinline__ uint64_t match_bits(uint32_t v, int bits, uint64_t active) {
-    uint64_t peers = active;
+    uint32_t lo = (uint32_t)active, hi = (uint32_t)(active >> 32);
     for (int b = 0; b < bits; ++b) {
-        const bool bit = (v >> b) & 1u;
-        const uint64_t m = __ballot(bit);
-        peers &= bit ? m : ~m;
+        const uint32_t s = 0u - ((v >> b) & 1u);   // as in match_digit8
+        const uint64_t m = __ballot(s != 0u);
+        lo &= ~((uint32_t)m ^ s);
+        hi &= ~((uint32_t)(m >> 32) ^ s);
     }
-    return peers;
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // Wave-aggregated LDS counter increment: the lanes with `has` set add one to
