@@ -40,6 +40,7 @@ constexpr int kSB = 512;
 constexpr int kSW = kSB / kWave;     // waves per block
 constexpr int kSI = kSegCap / kSB;   // items per thread = chunks per wave
 constexpr int kPre = 3;              // window + lookahead read in the first load round
+static_assert(kSI < 8, "a thread's case starts are counted in three bits");
 static_assert(kSegCap % kSB == 0, "staging capacity must be a multiple of the block");
 static_assert(kSegCap <= 4096, "cross keys hold the staging position in 12 bits");
 static_assert(kPre * kSB >= kSegWindow, "the first load round covers the window");
@@ -53,34 +54,6 @@ __device__ __forceinline__ int64_t block_min_i64(int64_t v, int64_t* red) {
     for (int i = 1; i < kSW; ++i) m = red[i] < m ? red[i] : m;
     __syncthreads();
     return m;
-}
-
-// Block minimum of two values at once (one barrier pair).
-__device__ __forceinline__ void block_min2_i64(int64_t& a, int64_t& b, int64_t* red) {
-    a = wave_min(a);
-    b = wave_min(b);
-    if (lane() == 0) {
-        red[threadIdx.x / kWave] = a;
-        red[kSW + threadIdx.x / kWave] = b;
-    }
-    __syncthreads();
-    a = red[0];
-    b = red[kSW];
-#pragma unroll
-    for (int i = 1; i < kSW; ++i) {
-        a = red[i] < a ? red[i] : a;
-        b = red[kSW + i] < b ? red[kSW + i] : b;
-    }
-    __syncthreads();
-}
-
-__device__ __forceinline__ int32_t wave_incl_max_i32(int32_t v) {
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        int32_t u = __shfl_up(v, o);
-        if (lane() >= o) v = u > v ? u : v;
-    }
-    return v;
 }
 
 // Value of lane (lane ^ J); every lane of the wave must be active.
@@ -100,12 +73,23 @@ __device__ __forceinline__ uint64_t xor_lane64(uint64_t v) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Lanes that take the larger of the pair at stage (M, J) of the ascending
+// network: lane l's block of M runs downward, or l is the upper lane of its
+// pair, but not both.  A compile-time lane mask: with inverse_ballot it stays
+// in scalar registers (no per-wave computation of the 21 masks).
+constexpr uint64_t flip_mask(int M, int J) {
+    uint64_t m = 0;
+    for (int l = 0; l < 64; ++l)
+        if (((l & M) == 0) != ((l & J) == 0)) m |= uint64_t(1) << l;
+    return m;
+}
+
 // One bitonic merge level (block size M) on one u64 key per lane, ascending.
 template <int M, int J>
 __device__ __forceinline__ void merge_u64(uint64_t& k, int l) {
     if constexpr (J > 0) {
         const uint64_t p = xor_lane64<J>(k);
-        const bool flip = ((l & M) == 0) != ((l & J) == 0);
+        const bool flip = __builtin_amdgcn_inverse_ballot_w64(flip_mask(M, J));
         k = ((p < k) != flip) ? p : k;
         merge_u64<M, J / 2>(k, l);
     }
@@ -128,7 +112,7 @@ __device__ __forceinline__ void merge_3(uint32_t& c, int64_t& t, uint32_t& id, i
         const int64_t pt = (int64_t)xor_lane64<J>((uint64_t)t);
         const uint32_t pid = xor_lane<J>(id);
         const bool pless = (pc < c) | ((pc == c) & ((pt < t) | ((pt == t) & (pid < id))));
-        const bool flip = ((l & M) == 0) != ((l & J) == 0);
+        const bool flip = __builtin_amdgcn_inverse_ballot_w64(flip_mask(M, J));
         const bool take = pless != flip;
         c = take ? pc : c;
         t = take ? pt : t;
@@ -163,6 +147,7 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
     __shared__ int64_t red[2 * kSW];
     __shared__ int32_t wred[kSW];
     __shared__ int32_t wst[kSW];
+    __shared__ uint32_t wfirst[2][kSW];
 
     const uint32_t* __restrict__ key = in.key;
     const uint32_t kmask = act_shift > 0 ? ((1u << act_shift) - 1u) : 0xFFFFFFFFu;
@@ -174,11 +159,16 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
 
     // 1. one load round: the window and a lookahead are read into registers; the
     //    first case start inside the window (s) and the first at or after its end
-    //    (e; n counts) come from them
+    //    (e; n counts) come from them.  Item q of thread t is position
+    //    w0 + q*kSB + t, so within a wave positions grow with q, then with the
+    //    lane: the first q whose ballot is not empty holds the wave's first
+    //    start (wave-uniform, scalar work); the block takes the smallest over
+    //    its waves.  Offsets from w0 fit in 32 bits.
     uint32_t pk[kPre], pa[kPre];
     int64_t pt[kPre];
     bool pst[kPre];
-    int64_t s = INT64_MAX, e = INT64_MAX;
+    const int wv0 = threadIdx.x / kWave;
+    uint32_t s_off = UINT32_MAX, e_off = UINT32_MAX;
 #pragma unroll
     for (int q = 0; q < kPre; ++q) {
         const int64_t P = w0 + threadIdx.x + q * kSB;
@@ -190,15 +180,25 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
             pt[q] = in.ts[P];
             pa[q] = act_shift > 0 ? (pk[q] >> act_shift) : in.act[P];
             pst[q] = P == 0 || ((pk[q] ^ key[P - 1]) & kmask) != 0;
-            if (pst[q]) {
-                if (P < w1) s = P < s ? P : s;
-                else e = P < e ? P : e;
-            }
-        } else if (P == n) {
-            e = n < e ? n : e;
         }
+        const uint64_t bs = __ballot(pst[q] && P < w1);
+        const uint64_t be = __ballot((pst[q] && P >= w1) || P == n);
+        const uint32_t base = (uint32_t)(q * kSB + wv0 * kWave);
+        if (s_off == UINT32_MAX && bs) s_off = base + (uint32_t)__ffsll((unsigned long long)bs) - 1u;
+        if (e_off == UINT32_MAX && be) e_off = base + (uint32_t)__ffsll((unsigned long long)be) - 1u;
     }
-    block_min2_i64(s, e, red);
+    if (lane() == 0) {
+        wfirst[0][wv0] = s_off;
+        wfirst[1][wv0] = e_off;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSW; ++k) {
+        s_off = wfirst[0][k] < s_off ? wfirst[0][k] : s_off;
+        e_off = wfirst[1][k] < e_off ? wfirst[1][k] : e_off;
+    }
+    int64_t s = s_off == UINT32_MAX ? INT64_MAX : w0 + (int64_t)s_off;
+    int64_t e = e_off == UINT32_MAX ? INT64_MAX : w0 + (int64_t)e_off;
     if (s == INT64_MAX) {   // a long case covers the whole window (block-uniform): no case starts here
         if (threadIdx.x == 0) wincnt[win] = 0;
         return;
@@ -259,10 +259,16 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
             loc[q] = m;
         }
         const int w = threadIdx.x / kWave;
-        const int32_t inc = wave_incl_max_i32(m);
-        nst = wave_sum(nst);
+        // inclusive max over the lanes: where m is not zero it is the last start
+        // among the lane's items, so it grows with the lane; the max is the m of
+        // the highest lane at or below this one with m > 0
+        const uint64_t nz = __ballot(m > 0) & (lanes_below() | (uint64_t(1) << lane()));
+        const int32_t inc = nz ? __shfl(m, 63 - __clzll((long long)nz)) : 0;
+        // the wave's starts: nst < 8, so three ballots of its bits
+        const int32_t wn = __popcll(__ballot(nst & 1)) + 2 * __popcll(__ballot(nst & 2)) +
+                           4 * __popcll(__ballot(nst & 4));
         if (lane() == kWave - 1) wred[w] = inc;
-        if (lane() == 0) wst[w] = nst;
+        if (lane() == 0) wst[w] = wn;
         __syncthreads();
         if (threadIdx.x == 0) {   // the region's cases are the cases starting in the window
             int32_t t = 0;
@@ -271,8 +277,8 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
         }
         int32_t before = 0;
         for (int i = 0; i < w; ++i) before = wred[i] > before ? wred[i] : before;
-        int32_t excl = __shfl_up(inc, 1);
-        if (lane() == 0) excl = 0;
+        // lane l - 1's inclusive max (DPP wave shift right by one; lane 0 reads 0)
+        int32_t excl = __builtin_amdgcn_update_dpp(0, inc, 0x138, 0xF, 0xF, false);
         excl = excl > before ? excl : before;
 #pragma unroll
         for (int q = 0; q < kSI; ++q) {
