@@ -305,7 +305,6 @@ __device__ void walk(const int32_t* s_case, const int16_t* s_act, const int64_t*
                      const uint64_t* mask, uint32_t* cursor, uint16_t* rec_cell, uint64_t* rec_gap, bool wide) {
     const int64_t AA = (int64_t)A * A;
     const uint64_t below = lanes_below();
-    const uint64_t le = below | (uint64_t(1) << lane());
     for (int64_t b0 = e0; b0 < e1; b0 += kWave) {
         const int64_t i = b0 + lane();
         const bool in = i < e1;
@@ -334,21 +333,32 @@ __device__ void walk(const int32_t* s_case, const int16_t* s_act, const int64_t*
             st.have_cur = true;
             continue;
         }
-        const uint64_t sle = S & le;
-        const int sl = sle ? hi_bit(sle) : -1;           // -1: the segment began before the window
-        const uint64_t seg = sl < 0 ? below : (below & ~((uint64_t(1) << sl) - 1));
-        const uint64_t pk = K & seg;
-        const int pl = pk ? hi_bit(pk) : 0;
-        const int32_t ap = __shfl(a, pl);
-        const int64_t tp = __shfl(t, pl);
+        // The nearest lane j below this one that is kept or starts a case: when
+        // this lane starts its case it has no previous kept event; else a kept
+        // lane j is the previous kept event of the case (no start lies between),
+        // a non-kept start j means none is kept before this lane, and with no
+        // such lane the case began before the window (the carry).  Lane j's
+        // activity travels with its kept flag in bit 30 (activities < 2^30).
+        const uint64_t gb = (K | S) & below;
+        const int j = gb ? hi_bit(gb) : -1;
+        const int32_t aj = __shfl(a | (k ? 0x40000000 : 0), j < 0 ? 0 : j);
+        const int64_t tj = __shfl(t, j < 0 ? 0 : j);
         if (k) {
-            bool has_prev = pk != 0;
-            int32_t pa = ap;
-            int64_t pt = tp;
-            if (!has_prev && sl < 0 && st.cr_valid) {
-                has_prev = true;
+            bool has_prev;
+            int32_t pa;
+            int64_t pt;
+            if (starts) {
+                has_prev = false;
+                pa = 0;
+                pt = 0;
+            } else if (j < 0) {
+                has_prev = st.cr_valid;
                 pa = st.cr_a;
                 pt = st.cr_t;
+            } else {
+                has_prev = (aj & 0x40000000) != 0;
+                pa = aj & 0x3FFFFFFF;
+                pt = tj;
             }
             const int64_t cell = has_prev ? (int64_t)pa * A + a : AA + a;
             const uint64_t gap = has_prev ? (uint64_t)t - (uint64_t)pt : 0ull;
