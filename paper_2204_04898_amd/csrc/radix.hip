@@ -168,19 +168,47 @@ __global__ __launch_bounds__(kRB) void k_radix_scatter(SortBufs in, SortBufs out
 
     uint32_t key[kRI], act[kRI], dg[kRI], rk[kRI];
     int64_t tv[kRI];
+    if constexpr (FIRST) {
+        // all loads of the tile first: forming each key from its two raw
+        // columns right after their loads (as the compiler schedules it
+        // otherwise) made every item's loads wait for the previous item's
+        uint32_t rc[kRI], ra[kRI];
 #pragma unroll
-    for (int k = 0; k < kRI; ++k) {
-        const int64_t i = wbase + k * kWave + lane();
-        if (i < n) {
-            key[k] = load_key<FIRST, PACKED>(in, i, case_min, act_shift);
-            tv[k] = in.ts[i];
-            act[k] = PACKED ? 0u : in.act[i];
-        } else {
-            key[k] = 0;
-            tv[k] = ts_min;
-            act[k] = 0;
+        for (int k = 0; k < kRI; ++k) {
+            const int64_t i = wbase + k * kWave + lane();
+            if (i < n) {
+                rc[k] = reinterpret_cast<const uint32_t*>(in.key)[i];
+                ra[k] = in.act[i];
+                tv[k] = in.ts[i];
+            } else {
+                rc[k] = (uint32_t)case_min;
+                ra[k] = 0;
+                tv[k] = ts_min;
+            }
         }
-        dg[k] = digit_of<SRC>(key[k], tv[k], shift, ts_min, key_mask);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < kRI; ++k) {
+            key[k] = rc[k] - (uint32_t)case_min;   // 0 past the end
+            if (PACKED) key[k] |= ra[k] << act_shift;
+            act[k] = PACKED ? 0u : ra[k];
+            dg[k] = digit_of<SRC>(key[k], tv[k], shift, ts_min, key_mask);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kRI; ++k) {
+            const int64_t i = wbase + k * kWave + lane();
+            if (i < n) {
+                key[k] = load_key<FIRST, PACKED>(in, i, case_min, act_shift);
+                tv[k] = in.ts[i];
+                act[k] = PACKED ? 0u : in.act[i];
+            } else {
+                key[k] = 0;
+                tv[k] = ts_min;
+                act[k] = 0;
+            }
+            dg[k] = digit_of<SRC>(key[k], tv[k], shift, ts_min, key_mask);
+        }
     }
     __syncthreads();
 
