@@ -164,7 +164,9 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
     //    lane: the first q whose ballot is not empty holds the wave's first
     //    start (wave-uniform, scalar work); the block takes the smallest over
     //    its waves.  Offsets from w0 fit in 32 bits.
-    uint32_t pk[kPre], pa[kPre];
+    // The loads take clamped (in-bounds) positions with no branch around them
+    // and all are issued before any is used; values past n are never used.
+    uint32_t pk[kPre], pa[kPre], pkm1[kPre];
     int64_t pt[kPre];
     bool pst[kPre];
     const int wv0 = threadIdx.x / kWave;
@@ -172,15 +174,19 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
 #pragma unroll
     for (int q = 0; q < kPre; ++q) {
         const int64_t P = w0 + threadIdx.x + q * kSB;
-        pk[q] = pa[q] = 0;
-        pt[q] = 0;
-        pst[q] = false;
-        if (P < n) {
-            pk[q] = key[P];
-            pt[q] = in.ts[P];
-            pa[q] = act_shift > 0 ? (pk[q] >> act_shift) : in.act[P];
-            pst[q] = P == 0 || ((pk[q] ^ key[P - 1]) & kmask) != 0;
-        }
+        const int64_t Pc = P < n ? P : n - 1;
+        pk[q] = key[Pc];
+        pkm1[q] = key[Pc > 0 ? Pc - 1 : 0];
+        pt[q] = in.ts[Pc];
+        pa[q] = 0;
+        if (act_shift <= 0) pa[q] = in.act[Pc];   // block-uniform: no activity column when packed
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) {
+        const int64_t P = w0 + threadIdx.x + q * kSB;
+        if (act_shift > 0) pa[q] = pk[q] >> act_shift;
+        pst[q] = P < n && (P == 0 || ((pk[q] ^ pkm1[q]) & kmask) != 0);
         const uint64_t bs = __ballot(pst[q] && P < w1);
         const uint64_t be = __ballot((pst[q] && P >= w1) || P == n);
         const uint32_t base = (uint32_t)(q * kSB + wv0 * kWave);
@@ -240,7 +246,7 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
 #pragma unroll
     for (int q = 0; q < kSI; ++q) {
         const int i = threadIdx.x + q * kSB;
-        ck[q] = i < R ? (key[s + i] & kmask) : 0u;
+        ck[q] = key[s + (i < R ? i : R - 1)];   // in bounds, no branch; masked at the write
     }
     __syncthreads();
 
@@ -435,7 +441,7 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
     for (int q = 0; q < kSI; ++q) {
         const int i = threadIdx.x + q * kSB;
         if (i < R) {
-            case_s[s + i] = (int32_t)(ck[q] + bias);
+            case_s[s + i] = (int32_t)((ck[q] & kmask) + bias);
             act_s[s + i] = (int32_t)lact[i];
             ts_s[s + i] = lts[i];
         }
