@@ -21,11 +21,21 @@ __global__ __launch_bounds__(kCB) void k_case_count(const int32_t* __restrict__ 
                                                     uint32_t* blockcnt) {
     __shared__ uint32_t tmp[kCB / kWave + 1];
     const int64_t base = (int64_t)blockIdx.x * kCaseTile;
+    // loads at clamped positions (n >= 1), all issued before any is used
+    int32_t cv[kCI], pv[kCI];
+#pragma unroll
+    for (int k = 0; k < kCI; ++k) {
+        const int64_t i = base + k * kCB + threadIdx.x;
+        const int64_t ic = i < n ? i : n - 1;
+        cv[k] = case_s[ic];
+        pv[k] = case_s[ic > 0 ? ic - 1 : 0];
+    }
+    __builtin_amdgcn_sched_barrier(0);
     uint32_t c = 0;
 #pragma unroll
     for (int k = 0; k < kCI; ++k) {
         const int64_t i = base + k * kCB + threadIdx.x;
-        if (i < n && (i == 0 || case_s[i] != case_s[i - 1])) ++c;
+        if (i < n && (i == 0 || cv[k] != pv[k])) ++c;
     }
     uint32_t total;
     block_excl_sum<kCB>(c, tmp, &total);
@@ -77,16 +87,20 @@ __global__ __launch_bounds__(kCB) void k_case_emit(const int32_t* __restrict__ c
     const int64_t base = (int64_t)blockIdx.x * kCaseTile;
     const int w = threadIdx.x / kWave;
     uint64_t masks[kCI];
-    int32_t cv[kCI];
+    // loads at clamped positions (n >= 1), all issued before any is used
+    int32_t cv[kCI], pv[kCI];
 #pragma unroll
     for (int k = 0; k < kCI; ++k) {
         const int64_t i = base + k * kCB + threadIdx.x;
-        bool f = false;
-        cv[k] = 0;
-        if (i < n) {
-            cv[k] = case_s[i];
-            f = (i == 0) || cv[k] != case_s[i - 1];
-        }
+        const int64_t ic = i < n ? i : n - 1;
+        cv[k] = case_s[ic];
+        pv[k] = case_s[ic > 0 ? ic - 1 : 0];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < kCI; ++k) {
+        const int64_t i = base + k * kCB + threadIdx.x;
+        const bool f = i < n && (i == 0 || cv[k] != pv[k]);
         masks[k] = __ballot(f);
         if (lane() == 0) wcnt[k * kNW + w] = (uint32_t)__popcll(masks[k]);
     }

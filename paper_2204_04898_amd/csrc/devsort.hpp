@@ -38,10 +38,18 @@ __global__ __launch_bounds__(kB) void k_hist(const K* __restrict__ key, const in
         if (threadIdx.x < 256) h[threadIdx.x] = 0;
         __syncthreads();
         const int64_t base = tile * kTile;
+        // keys at clamped positions (n >= 1 here), all loaded before the first atomic
+        K kv[kI];
 #pragma unroll
         for (int k = 0; k < kI; ++k) {
             const int64_t i = base + k * kB + threadIdx.x;
-            if (i < n) atomicAdd(&h[(uint32_t)(key[i] >> shift) & 255u], 1u);
+            kv[k] = key[i < n ? i : n - 1];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < kI; ++k) {
+            const int64_t i = base + k * kB + threadIdx.x;
+            if (i < n) atomicAdd(&h[(uint32_t)(kv[k] >> shift) & 255u], 1u);
         }
         __syncthreads();
         if (threadIdx.x < 256) hist[(int64_t)threadIdx.x * nb + tile] = h[threadIdx.x];

@@ -130,17 +130,29 @@ __global__ __launch_bounds__(kBlk) void k_var_hash(const int32_t* __restrict__ a
         const int64_t base = __shfl(st, 0);
         const int64_t end = __shfl(en, last);
         for (int64_t w0 = base & ~(int64_t)3; w0 < end; w0 += kHashWin) {   // wave-uniform
-            // stage the window's activities (positions outside [base, end) are not used)
+            // stage the window's activities (positions outside [base, end) are not used);
+            // the 16-byte loads take in-bounds positions with no branch around them
+            // and are all issued before the first store (a quad past n - 4 re-reads
+            // the last aligned quad and is replaced below)
+            constexpr int kQ = kHashWin / (4 * kWave);
+            int4 v[kQ];
+            const bool vec = aligned && n >= 4;
+            const int64_t plast = (n - 4) & ~(int64_t)3;
 #pragma unroll
-            for (int k = 0; k < kHashWin / (4 * kWave); ++k) {
+            for (int k = 0; k < kQ; ++k) {
+                const int64_t p = w0 + 4 * (k * kWave + lane());
+                if (vec) v[k] = *reinterpret_cast<const int4*>(act_s + (p + 3 < n ? p : plast));
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int k = 0; k < kQ; ++k) {
                 const int o = 4 * (k * kWave + lane());
                 const int64_t p = w0 + o;
-                if (aligned && p + 3 < n) {
-                    const int4 v = *reinterpret_cast<const int4*>(act_s + p);
-                    sact[wl][o] = v.x;
-                    sact[wl][o + 1] = v.y;
-                    sact[wl][o + 2] = v.z;
-                    sact[wl][o + 3] = v.w;
+                if (vec && p + 3 < n) {
+                    sact[wl][o] = v[k].x;
+                    sact[wl][o + 1] = v[k].y;
+                    sact[wl][o + 2] = v[k].z;
+                    sact[wl][o + 3] = v[k].w;
                 } else {
 #pragma unroll
                     for (int j = 0; j < 4; ++j) sact[wl][o + j] = p + j < n ? act_s[p + j] : 0;
