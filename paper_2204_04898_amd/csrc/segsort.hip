@@ -86,27 +86,27 @@ constexpr uint64_t flip_mask(int M, int J) {
 
 // One bitonic merge level (block size M) on one u64 key per lane, ascending.
 template <int M, int J>
-__device__ __forceinline__ void merge_u64(uint64_t& k, int l) {
+__device__ __forceinline__ void merge_u64(uint64_t& k) {
     if constexpr (J > 0) {
         const uint64_t p = xor_lane64<J>(k);
         const bool flip = __builtin_amdgcn_inverse_ballot_w64(flip_mask(M, J));
         k = ((p < k) != flip) ? p : k;
-        merge_u64<M, J / 2>(k, l);
+        merge_u64<M, J / 2>(k);
     }
 }
 
-__device__ __forceinline__ void bitonic64_u64(uint64_t& k, int l) {
-    merge_u64<2, 1>(k, l);
-    merge_u64<4, 2>(k, l);
-    merge_u64<8, 4>(k, l);
-    merge_u64<16, 8>(k, l);
-    merge_u64<32, 16>(k, l);
-    merge_u64<64, 32>(k, l);
+__device__ __forceinline__ void bitonic64_u64(uint64_t& k) {
+    merge_u64<2, 1>(k);
+    merge_u64<4, 2>(k);
+    merge_u64<8, 4>(k);
+    merge_u64<16, 8>(k);
+    merge_u64<32, 16>(k);
+    merge_u64<64, 32>(k);
 }
 
 // Field-by-field network: (case start c, timestamp t, staging position id).
 template <int M, int J>
-__device__ __forceinline__ void merge_3(uint32_t& c, int64_t& t, uint32_t& id, int l) {
+__device__ __forceinline__ void merge_3(uint32_t& c, int64_t& t, uint32_t& id) {
     if constexpr (J > 0) {
         const uint32_t pc = xor_lane<J>(c);
         const int64_t pt = (int64_t)xor_lane64<J>((uint64_t)t);
@@ -117,17 +117,17 @@ __device__ __forceinline__ void merge_3(uint32_t& c, int64_t& t, uint32_t& id, i
         c = take ? pc : c;
         t = take ? pt : t;
         id = take ? pid : id;
-        merge_3<M, J / 2>(c, t, id, l);
+        merge_3<M, J / 2>(c, t, id);
     }
 }
 
-__device__ __forceinline__ void bitonic64_3(uint32_t& c, int64_t& t, uint32_t& id, int l) {
-    merge_3<2, 1>(c, t, id, l);
-    merge_3<4, 2>(c, t, id, l);
-    merge_3<8, 4>(c, t, id, l);
-    merge_3<16, 8>(c, t, id, l);
-    merge_3<32, 16>(c, t, id, l);
-    merge_3<64, 32>(c, t, id, l);
+__device__ __forceinline__ void bitonic64_3(uint32_t& c, int64_t& t, uint32_t& id) {
+    merge_3<2, 1>(c, t, id);
+    merge_3<4, 2>(c, t, id);
+    merge_3<8, 4>(c, t, id);
+    merge_3<16, 8>(c, t, id);
+    merge_3<32, 16>(c, t, id);
+    merge_3<64, 32>(c, t, id);
 }
 
 constexpr uint64_t kOffBias = 1ull << 51;
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
             const int ch = w + q * kSW;
             if (ch * kWave >= R) continue;   // wave-uniform
             uint64_t k = sk[q];
-            bitonic64_u64(k, l);
+            bitonic64_u64(k);
             const int i = ch * kWave + l;
             if (i < R) lts[i] = (int64_t)((((k >> 6) & kOffMask) << 12) | (uint64_t)(ch * kWave + (int)(k & 63u)));
         }
@@ -387,7 +387,7 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
                 t = lts[i];
                 id = (uint32_t)i;
             }
-            bitonic64_3(c, t, id, l);
+            bitonic64_3(c, t, id);
             if (i < R) {
                 lts[i] = t;
                 lidx[i] = (uint16_t)id;
