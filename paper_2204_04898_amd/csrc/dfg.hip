@@ -13,7 +13,9 @@
 //                edges are partitioned bucket-major, so that each bucket's
 //                edges are one contiguous stream:
 //                k_dfg_count    per (bucket, chunk of the log) edge counts,
-//                               and the activity / start / end counts;
+//                               and the start / end counts (an activity's
+//                               count is folded from those and the pair
+//                               counts by k_dfg_acts);
 //                scan           first edge index of every (bucket, chunk);
 //                k_dfg_scatter  edges (u16 cell within the bucket, u64 gap)
 //                               written to their place via LDS cursors;
@@ -237,18 +239,17 @@ __device__ __forceinline__ Quad load_quad(const int32_t* __restrict__ case_s, co
     return q;
 }
 
-// Per chunk: edge counts per bucket; per block: activity, start and end counts.
-// Dynamic LDS: (3 * A + nbk) u32.
+// Per chunk: edge counts per bucket; per block: start and end counts.
+// Dynamic LDS: (2 * A + nbk) u32.
 __global__ __launch_bounds__(kCB) void k_dfg_count(const int32_t* __restrict__ case_s,
                                                    const int32_t* __restrict__ act_s, int64_t n,
                                                    int32_t A, int64_t nbk, int64_t nch, int64_t chunk,
                                                    DfgWs ws, int32_t* status) {
     extern __shared__ uint32_t dsm[];
-    uint32_t* sfreq = dsm;
-    uint32_t* sstart = dsm + A;
-    uint32_t* send = dsm + 2 * A;
-    uint32_t* bcnt = dsm + 3 * A;
-    for (int a = threadIdx.x; a < 3 * A; a += kCB) dsm[a] = 0;
+    uint32_t* sstart = dsm;
+    uint32_t* send = dsm + A;
+    uint32_t* bcnt = dsm + 2 * A;
+    for (int a = threadIdx.x; a < 2 * A; a += kCB) dsm[a] = 0;
     const bool aligned = ((reinterpret_cast<uintptr_t>(case_s) | reinterpret_cast<uintptr_t>(act_s)) & 15) == 0;
     bool bad = false;
     for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
@@ -273,7 +274,6 @@ __global__ __launch_bounds__(kCB) void k_dfg_count(const int32_t* __restrict__ c
                     const int32_t ap = j ? qd.a[j - 1] : qd.ap;
                     const int32_t cn = j < 3 ? qd.c[j + 1] : qd.cn;
                     const bool first = cp != c;
-                    atomicAdd(&sfreq[a], 1u);
                     if (first) atomicAdd(&sstart[a], 1u);
                     if (e0 + j + 1 >= n || cn != c) atomicAdd(&send[a], 1u);
                     if (!first && (uint32_t)ap < (uint32_t)A)
@@ -289,7 +289,6 @@ __global__ __launch_bounds__(kCB) void k_dfg_count(const int32_t* __restrict__ c
     if (__ballot(bad) != 0 && lane() == 0) set_status(status, PM4G_E_RANGE);
     const size_t ab = (size_t)blockIdx.x * A;
     for (int a = threadIdx.x; a < A; a += kCB) {
-        ws.pfreq[ab + a] = sfreq[a];
         ws.pstart[ab + a] = sstart[a];
         ws.pend[ab + a] = send[a];
     }
@@ -535,15 +534,24 @@ __global__ void k_dfg_zero_acts(int32_t A, DfgOutDev out) {
 }
 
 // grid (ceil(A/256), kActRows): block (x, r) folds partial rows r, r+kActRows, ...
+// freq_from_counts: every event of a valid log either starts its case or ends
+// one directly-follows pair, so an activity's frequency is its start count plus
+// its column of the pair counts (out.count, already reduced); rows of that
+// column are folded as the partial rows are.
 constexpr int kActRows = 32;
-__global__ __launch_bounds__(256) void k_dfg_acts(int32_t A, int32_t nblk, DfgWs ws, DfgOutDev out) {
+__global__ __launch_bounds__(256) void k_dfg_acts(int32_t A, int32_t nblk, bool freq_from_counts,
+                                                  DfgWs ws, DfgOutDev out) {
     const int a = blockIdx.x * 256 + threadIdx.x;
     if (a >= A) return;
     uint64_t f = 0, st = 0, en = 0;
     for (int k = blockIdx.y; k < nblk; k += kActRows) {
-        f += ws.pfreq[(size_t)k * A + a];
+        if (!freq_from_counts) f += ws.pfreq[(size_t)k * A + a];
         st += ws.pstart[(size_t)k * A + a];
         en += ws.pend[(size_t)k * A + a];
+    }
+    if (freq_from_counts) {
+        f += st;
+        for (int b = blockIdx.y; b < A; b += kActRows) f += (uint64_t)out.count[(size_t)b * A + a];
     }
     atomicAdd(reinterpret_cast<unsigned long long*>(&out.act_count[a]), (unsigned long long)f);
     atomicAdd(reinterpret_cast<unsigned long long*>(&out.start_count[a]), (unsigned long long)st);
@@ -577,10 +585,10 @@ __global__ __launch_bounds__(1024) void k_dfg_final(int32_t A, int32_t nblk, Dfg
     }
 }
 
-static void launch_acts(int32_t A, int32_t nblk, DfgWs ws, const int32_t* status_in, DfgOutDev out,
-                        hipStream_t s) {
+static void launch_acts(int32_t A, int32_t nblk, bool freq_from_counts, DfgWs ws, const int32_t* status_in,
+                        DfgOutDev out, hipStream_t s) {
     k_dfg_zero_acts<<<(unsigned)((A + 255) / 256), 256, 0, s>>>(A, out);
-    k_dfg_acts<<<dim3((unsigned)((A + 255) / 256), kActRows), 256, 0, s>>>(A, nblk, ws, out);
+    k_dfg_acts<<<dim3((unsigned)((A + 255) / 256), kActRows), 256, 0, s>>>(A, nblk, freq_from_counts, ws, out);
     k_dfg_final<<<1, 1024, 0, s>>>(A, nblk, ws, status_in, out);
 }
 
@@ -597,7 +605,7 @@ hipError_t launch_dfg(const int32_t* case_s, const int32_t* act_s, const int64_t
         }
         ProfScope p(P_DFG_REDUCE, s);
         k_dfg_reduce<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(A, kDfgLdsBlocks, ws, out);
-        launch_acts(A, kDfgLdsBlocks, ws, status_in, out, s);
+        launch_acts(A, kDfgLdsBlocks, false, ws, status_in, out, s);
     } else {
         const int64_t nbk = n_buckets(A);
         const int64_t nch = dfg_chunks(n, nbk);
@@ -605,7 +613,7 @@ hipError_t launch_dfg(const int32_t* case_s, const int32_t* act_s, const int64_t
         const unsigned g = (unsigned)ws.n_act_blocks;
         {
             ProfScope p(P_DFG_COUNT, s);
-            k_dfg_count<<<g, kCB, (size_t)(3 * A + nbk) * sizeof(uint32_t), s>>>(case_s, act_s, n, A, nbk, nch,
+            k_dfg_count<<<g, kCB, (size_t)(2 * A + nbk) * sizeof(uint32_t), s>>>(case_s, act_s, n, A, nbk, nch,
                                                                              chunk, ws, out.status);
             dev::excl_scan<uint32_t>(ws.ecnt, &ws.scal[0], ws.escan, ws.part32, ws.utotal, s);
         }
@@ -624,7 +632,7 @@ hipError_t launch_dfg(const int32_t* case_s, const int32_t* act_s, const int64_t
         }
         ProfScope p(P_DFG_REDUCE, s);
         k_dfg_reduce<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(A, 0, ws, out);
-        launch_acts(A, ws.n_act_blocks, ws, status_in, out, s);
+        launch_acts(A, ws.n_act_blocks, true, ws, status_in, out, s);
     }
     return hipGetLastError();
 }
