@@ -99,6 +99,17 @@ __device__ __forceinline__ int seg_of(int64_t vstart, int64_t p) {
     return lo;
 }
 
+// The same search over 32-bit starts (one lane exchange per step instead of two).
+__device__ __forceinline__ int seg_of32(int32_t vstart, int64_t p) {
+    int lo = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+        const int cand = lo + step;
+        if ((int64_t)__shfl(vstart, cand) <= p) lo = cand;
+    }
+    return lo;
+}
+
 // Sequence hash of every case: a sum over positions of mix(position, activity)
 // (order-sensitive, computable in any order), mixed with the length.  A wave
 // takes 64 consecutive cases; their events are read in 1024-event windows
@@ -332,6 +343,11 @@ __global__ __launch_bounds__(kBlk) void k_var_emit(const uint32_t* __restrict__ 
         const int last = (V - 1 - k0) < (kWave - 1) ? (int)(V - 1 - k0) : (kWave - 1);
         const int64_t base = __shfl(dst, 0);
         const int64_t end = __shfl(dst + len, last);
+        // event positions are below 2^31 (the log's size limit), so output
+        // starts and the source-minus-output shift fit 32 bits: the search and
+        // the shift take one lane exchange each instead of two
+        const int32_t dst32 = has ? (int32_t)dst : INT32_MAX;
+        const int32_t shift = (int32_t)(src - (has ? dst : 0));
         // wave-uniform trip count: every lane takes part in the shuffles;
         // four 64-element steps per trip, their loads issued first
         constexpr int kU = 4;
@@ -340,10 +356,9 @@ __global__ __launch_bounds__(kBlk) void k_var_emit(const uint32_t* __restrict__ 
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 const int64_t p = p0 + u * kWave + lane();
-                const int m = seg_of(dst, p);
-                const int64_t s_m = __shfl(src, m);
-                const int64_t d_m = __shfl(dst, m);
-                av[u] = p < end ? act_s[s_m + (p - d_m)] : 0;
+                const int m = seg_of32(dst32, p);
+                const int32_t sh = __shfl(shift, m);
+                av[u] = p < end ? act_s[p + sh] : 0;
             }
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
