@@ -30,6 +30,20 @@
 
 namespace pm4g {
 
+// Segment of event position p among 64 consecutive segments, as seg_at, with
+// 32-bit starts: event positions stay below 2^31 (the log's size limit), so
+// each search step exchanges one dword instead of two.  INT32_MAX marks an
+// absent lane; every lane of the wave must execute it.
+__device__ __forceinline__ int seg_at32(int32_t vstart, int64_t p) {
+    int lo = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+        const int cand = lo + step;
+        if ((int64_t)__shfl(vstart, cand) <= p) lo = cand;
+    }
+    return lo;
+}
+
 CaseFilterWs case_filter_ws_layout(Bump& b, int64_t n) {
     CaseFilterWs w{};
     const size_t m = (size_t)(n > 0 ? n : 1);
@@ -84,10 +98,11 @@ __global__ __launch_bounds__(kCB) void k_cf_contains(const int32_t* __restrict__
         const int last = (C - 1 - c0) < (kWave - 1) ? (int)(C - 1 - c0) : (kWave - 1);
         const int64_t base = __shfl(st, 0);
         const int64_t end = __shfl(en, last);
+        const int32_t st32 = has ? (int32_t)st : INT32_MAX;
         for (int64_t p0 = base; p0 < end; p0 += kWave) {   // wave-uniform trip count
             const int64_t p = p0 + lane();
-            const int m = seg_at(st, p);
-            const int64_t s_m = __shfl(st, m);
+            const int m = seg_at32(st32, p);
+            const int64_t s_m = __shfl(st32, m);
             if (p < end) {
                 const int32_t a = act_s[p];
                 uint32_t bits = 0;
@@ -164,15 +179,18 @@ __global__ __launch_bounds__(kCB) void k_cf_emit(const int32_t* __restrict__ cas
         const int last = (C - 1 - c0) < (kWave - 1) ? (int)(C - 1 - c0) : (kWave - 1);
         const int64_t base = __shfl(dst, 0);
         const int64_t end = __shfl(dst + len, last);
+        // positions fit 32 bits: output starts and the source-minus-output shift
+        // are exchanged as dwords
+        const int32_t dst32 = has ? (int32_t)dst : INT32_MAX;
+        const int32_t shift = (int32_t)(src - (has ? dst : 0));
         // dropped cases are empty segments: the last segment starting at or before
         // p is the kept case that holds p
         for (int64_t p0 = base; p0 < end; p0 += kWave) {   // wave-uniform trip count
             const int64_t p = p0 + lane();
-            const int m = seg_at(dst, p);
-            const int64_t s_m = __shfl(src, m);
-            const int64_t d_m = __shfl(dst, m);
+            const int m = seg_at32(dst32, p);
+            const int32_t sh = __shfl(shift, m);
             if (p < end) {
-                const int64_t i = s_m + (p - d_m);
+                const int64_t i = p + sh;
                 o_case[p] = case_s[i];
                 o_act[p] = act_s[i];
                 o_ts[p] = ts_s[i];
