@@ -173,7 +173,7 @@ typedef struct {
 } pm4g_variants_out;
 
 /*
- * A drill-down view (Sec. 1 "smaller views on the dataset"; Sec. 3 event-level
+ * A drill-down view (Sec. 1 drill-down: a filtered part of the log; Sec. 3 event-level
  * timestamp filter and activity-attribute filter).  Event i is kept iff
  * case_lo <= case_id_i < case_hi, t_lo <= timestamp_i <= t_hi and bit
  * activity_i of the view's mask is set; the view's DFG is re-discovered on

@@ -14,21 +14,21 @@
  *              identifier, then timestamp, then absolute row index.
  *   shift      Sec. 3, second formatting step: each event sees the activity
  *              and timestamp of the previous event of its case.
- *   DFG        Sec. 3, "directly-follows level" aggregation: the frequency /
+ *   DFG        Sec. 3, aggregation at the directly-follows level: the frequency /
  *              performance directly-follows graph.  The paper names no
  *              performance aggregate; here it is the exact int64 count, sum,
  *              min and max of the time gaps, with the FP64 mean sum/count.
  *   endpoints  Sec. 3, start/end activities module, and the event-level
- *              example "occurrences per activity".
+ *              count of each activity's events.
  *   variants   Sec. 3, variant-level aggregation (cases grouped by their
  *              activity sequence; a double aggregation).
- *   views      Sec. 1 drill-down ("smaller views on the dataset"), Sec. 3
+ *   views      Sec. 1 drill-down (filtered parts of the log), Sec. 3
  *              timestamp filter on events and attribute (activity) filter,
  *              composed as a conjunction; the DFG is re-discovered on the
  *              retained events.
  *   cases      Sec. 3 cases dataframe (events and throughput time per case)
  *              and the case-level filters on it, with paths filtering.
- *   df events  Sec. 3, "directly-follows level" filtering: events kept or
+ *   df events  Sec. 3, filtering at the directly-follows level: events kept or
  *              dropped by the pair they form with the previous (or next)
  *              event of their case.
  *   EFG        Sec. 3, eventually-follows graph and temporal profile: every
@@ -817,7 +817,9 @@ int orc_sample(int64_t n, const int32_t *case_id, const int32_t *act, const int6
 
 #define ORC_E_PARSE -3
 
-/* Days from 1970-01-01 to y-m-d in the proleptic Gregorian calendar: count the
+/* Days from 1970-01-01 to y-m-d in the proleptic Gregorian calendar, by
+ * H. Hinnant's published days-from-civil algorithm ("chrono-Compatible
+ * Low-Level Date Algorithms"): count the
  * days of whole 400-year eras since 0000-03-01, the years of the current era
  * (each from March, so the leap day ends a year) and the days of the current
  * year, then shift the origin. */

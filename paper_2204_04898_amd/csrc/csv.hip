@@ -305,9 +305,9 @@ __device__ __forceinline__ uint64_t finish_hash(uint64_t h, uint64_t seed, uint6
 
 // ---- timestamps ----
 
-// Days between 1970-01-01 and y-m-d (proleptic Gregorian): years counted from
-// March so that February's leap day closes a year, 400-year eras of 146097
-// days.
+// Days between 1970-01-01 and y-m-d (proleptic Gregorian), H. Hinnant's
+// published days-from-civil algorithm: years counted from March so that
+// February's leap day closes a year, 400-year eras of 146097 days.
 __device__ __forceinline__ int64_t days_since_epoch(int64_t y, int64_t m, int64_t d) {
     const int64_t yy = m <= 2 ? y - 1 : y;
     const int64_t era = (yy >= 0 ? yy : yy - 399) / 400;

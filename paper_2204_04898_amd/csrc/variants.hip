@@ -1,6 +1,6 @@
 // Trace variants of a prepared log (Sec. 3, variant level: cases grouped by
-// their activity sequence, "a double aggregation"; the cases dataframe holds
-// numeric features that identify each case's variant).
+// their activity sequence, an aggregation of the per-case aggregation; the
+// cases dataframe carries numbers from which each case's variant follows).
 //
 // Grouping is exact: a 64-bit hash of each case's sequence (the numeric
 // feature) only brings candidates together; every equal-hash neighbour pair

@@ -1,6 +1,6 @@
-// Batched drill-down views over a prepared log (Sec. 1 drill-down: "smaller
-// views on the dataset"; Sec. 3: event-level timestamp filter, attribute
-// filter on the activity, and the DFG re-discovered on what is kept).
+// Batched drill-down views over a prepared log (Sec. 1 drill-down: each view
+// is a filtered part of the log; Sec. 3: event-level timestamp filter,
+// attribute filter on the activity, and the DFG re-discovered on what is kept).
 //
 // A view v keeps event i iff case_lo <= c_i < case_hi, t_lo <= t_i <= t_hi and
 // bit a_i of its activity mask is set.  Its DFG pairs each kept event with the

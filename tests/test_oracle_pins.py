@@ -789,6 +789,51 @@ def test_splitmix_published_sequence():
     assert [oracle.splitmix(0, x) for x in range(4)] == want
 
 
+def _splitmix_at(seed: int, x: int) -> int:
+    """The x-th output from state seed: the stream after x + 1 steps, its state
+    reached by adding the increment x times in one product (the stream's
+    state after x steps is seed + x * increment modulo 2^64)."""
+    g = _SplitMix64Stream((seed + x * 0x9E3779B97F4A7C15) & _SplitMix64Stream.M)
+    return g.next()
+
+
+class _SplitMix64Stream:
+    """SplitMix64 as a stateful stream (Steele, Lea and Flood, OOPSLA 2014):
+    each call adds the odd increment 0x9E3779B97F4A7C15 to the 64-bit state,
+    then passes the new state through the variant-13 mixer."""
+
+    M = 2**64 - 1
+
+    def __init__(self, state: int):
+        self.state = state & self.M
+
+    def next(self) -> int:
+        self.state = (self.state + 0x9E3779B97F4A7C15) & self.M
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & self.M
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & self.M
+        return z ^ (z >> 31)
+
+
+def test_splitmix_stream_matches_published_sequence():
+    g = _SplitMix64Stream(0)
+    assert [g.next() for _ in range(4)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4,
+                                            0x06C45D188009454F, 0xF88BB8A8724C81EC]
+
+
+def test_splitmix_nonzero_seeds_follow_the_stream():
+    # the oracle's x-th output from state `seed` equals the stream's (x+1)-th
+    # step from that state, for seeds whose high and low bits are both set
+    # (a slip such as (seed + x + 1) * increment agrees with this only at seed 0)
+    rng = np.random.default_rng(20140414)
+    seeds = [1, 2**63, 2**64 - 1, 0x0123456789ABCDEF] + [int(s) for s in rng.integers(1, 2**63, 12)]
+    for seed in seeds:
+        g = _SplitMix64Stream(seed)
+        want = [g.next() for _ in range(80)]
+        assert [oracle.splitmix(seed, x) for x in range(80)] == want
+        assert [_splitmix_at(seed, x) for x in range(80)] == want
+
+
 def _sample_triples(o):
     return list(zip(o["case_s"].tolist(), o["act_s"].tolist(), o["ts_s"].tolist()))
 
@@ -801,11 +846,13 @@ def test_sample_match_bruteforce(log, k, seed, by_events):
     f = oracle.prepare(case, act, ts, A)
     if by_events:
         n = len(case)
-        keep = set(sorted(range(n), key=lambda u: oracle.splitmix(seed, u))[:k])
+        g = _SplitMix64Stream(seed)
+        keys = [g.next() for _ in range(n)]
+        keep = set(sorted(range(n), key=lambda u: keys[u])[:k])
         want = [(f["case_s"][u], f["act_s"][u], f["ts_s"][u]) for u in range(n) if u in keep]
     else:
         codes = sorted(set(case))
-        chosen = set(sorted(codes, key=lambda c: oracle.splitmix(seed, c & 0xFFFFFFFF))[:k])
+        chosen = set(sorted(codes, key=lambda c: _splitmix_at(seed, c & 0xFFFFFFFF))[:k])
         want = [(c, a, t) for c, a, t in zip(f["case_s"], f["act_s"], f["ts_s"]) if c in chosen]
     assert _sample_triples(o) == [tuple(int(x) for x in w) for w in want]
     assert o["n_cases"] == len({w[0] for w in want})
