@@ -271,6 +271,28 @@ int pm4g_variants_prepared(const pm4g_prepared *log, const pm4g_variants_out *ou
                            size_t ws_bytes, void *stream);
 
 /*
+ * pm4g_dfg_prepared for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and outputs, with the workspace taken from a
+ * library-owned device array of PM4G_NOALLOC_SCRATCH_BYTES bytes instead of
+ * a caller's buffer.  The library holds one such array per GPU it runs on
+ * until the process ends; the call itself allocates nothing.
+ *   - The array belongs to the current device; a non-NULL `stream` must
+ *     belong to it too (else PM4G_E_INVALID).
+ *   - When pm4g_workspace_bytes(PM4G_OP_DFG_PREPARED, n_events, n_activities,
+ *     0) exceeds PM4G_NOALLOC_SCRATCH_BYTES, PM4G_E_WORKSPACE is returned
+ *     before anything is enqueued (every n_events fits for n_activities <= 64;
+ *     with 512 activities about 6.5 million events fit).
+ *   - Every call on one GPU shares that GPU's array and leaves its contents
+ *     behind (the kernels clear what must start at zero): calls that overlap
+ *     in time on one GPU (other streams or threads) race and must be
+ *     serialised by the caller.
+ * Does not synchronise.
+ */
+#define PM4G_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int pm4g_dfg_prepared_noalloc(const pm4g_prepared *log, const pm4g_dfg_out *out, void *stream);
+
+/*
  * DFGs of many drill-down views of one prepared log in one pass over the log
  * (views: device array of n_views records; act_masks: device array of
  * n_views * ceil(A/64) words, bit a of word a/64 of row v selects activity a

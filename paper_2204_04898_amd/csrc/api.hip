@@ -5,6 +5,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "../../include/pm4g.h"
 #include "internal.hpp"
 #include "prof.hpp"
@@ -240,6 +242,39 @@ int run_prepare(const pm4g_log* log, const pm4g_prepared* out, bool case_table, 
     if (case_table)
         PM4G_HIP(launch_case_table(out->case_s, n, w.caseblk, out->case_off, out->case_code,
                                    out->n_cases, have_wincnt ? w.wincnt : nullptr, s));
+    return PM4G_OK;
+}
+
+// Library-owned workspace of pm4g_dfg_prepared_noalloc: one copy per GPU,
+// held for the life of the process.  Host code never passes the array's name
+// to a kernel (on the host it is a stand-in, not a device address); it uses
+// the per-device address that hipGetSymbolAddress returns.
+static __device__ __align__(256) unsigned char scratch[PM4G_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch array's address on the current device, looked up once per
+// device with that device current.
+int scratch_of_current_device(void** ptr) {
+    int dev = -1;
+    PM4G_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_err("device %d outside [0, %d)", dev, kMaxDevices);
+        return PM4G_E_INVALID;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        PM4G_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            set_err("no device address for the scratch array on device %d", dev);
+            return PM4G_E_DEVICE;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
     return PM4G_OK;
 }
 
@@ -656,6 +691,32 @@ int pm4g_dfg_prepared(const pm4g_prepared* log, const pm4g_dfg_out* out, void* w
     DfgWs w = dfg_ws_layout(bp, log->n_events, log->n_activities);
     PM4G_HIP(launch_dfg(log->case_s, log->act_s, log->ts_s, log->n_events, log->n_activities,
                         log->status, w, dev_out(out), (hipStream_t)stream));
+    return PM4G_OK;
+}
+
+int pm4g_dfg_prepared_noalloc(const pm4g_prepared* log, const pm4g_dfg_out* out, void* stream) {
+    if (int rc = check_prepared(log, false)) return rc;
+    if (int rc = check_dfg_out(out)) return rc;
+    const size_t need = ws_bytes(PM4G_OP_DFG_PREPARED, log->n_events, log->n_activities);
+    if (need > PM4G_NOALLOC_SCRATCH_BYTES) {
+        set_err("%lld events of %d activities need %zu bytes of workspace; the library's scratch holds %zu",
+                (long long)log->n_events, log->n_activities, need, (size_t)PM4G_NOALLOC_SCRATCH_BYTES);
+        return PM4G_E_WORKSPACE;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    void* ptr = nullptr;
+    if (int rc = scratch_of_current_device(&ptr)) return rc;
+    if (s) {
+        int cur = -1;
+        hipDevice_t sdev = -1;
+        PM4G_HIP(hipGetDevice(&cur));
+        PM4G_HIP(hipStreamGetDevice(s, &sdev));
+        PM4G_CHECK(sdev == cur, "the stream belongs to device %d, the current device is %d", (int)sdev, cur);
+    }
+    Bump bp(ptr);
+    DfgWs w = dfg_ws_layout(bp, log->n_events, log->n_activities);
+    PM4G_HIP(launch_dfg(log->case_s, log->act_s, log->ts_s, log->n_events, log->n_activities,
+                        log->status, w, dev_out(out), s));
     return PM4G_OK;
 }
 

@@ -130,6 +130,8 @@ def load():
                 f = getattr(L, name)
                 f.argtypes = argt + [_P, ctypes.c_size_t, _P]
                 f.restype = ctypes.c_int
+            L.pm4g_dfg_prepared_noalloc.argtypes = [ctypes.POINTER(_Prepared), ctypes.POINTER(_DfgOut), _P]
+            L.pm4g_dfg_prepared_noalloc.restype = ctypes.c_int
             L.pm4g_status_string.argtypes = [ctypes.c_int]
             L.pm4g_status_string.restype = ctypes.c_char_p
             L.pm4g_last_error.argtypes = []
@@ -321,6 +323,19 @@ def pm4g_dfg_prepared(prep: Prepared, out: dict | None = None, stream=None) -> d
     s = _dfg_struct(o)
     _check(load().pm4g_dfg_prepared(ctypes.byref(p), ctypes.byref(s), _ptr(ws), need, _stream(stream)))
     return o
+
+
+PM4G_NOALLOC_SCRATCH_BYTES = 128 << 20
+
+
+def pm4g_dfg_prepared_noalloc(prep: Prepared, out: dict, stream=None) -> dict:
+    """DFG of a prepared log into caller-allocated outputs, with the workspace
+    in the library's own per-GPU scratch array: the C call allocates nothing.
+    Calls overlapping in time on one GPU race on that array.  Asynchronous."""
+    p = prep._struct()
+    s = _dfg_struct(out)
+    _check(load().pm4g_dfg_prepared_noalloc(ctypes.byref(p), ctypes.byref(s), _stream(stream)))
+    return out
 
 
 def _var_out(n: int, device, with_cases: bool = True) -> dict:

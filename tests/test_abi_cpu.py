@@ -187,3 +187,20 @@ def test_later_entry_points_validate_before_any_device_work():
     assert lib.pm4g_ingest_csv(f, 100, ctypes.byref(sc), ctypes.byref(co), ws, 1 << 40, None) == pm4g.PM4G_E_INVALID
     sc.ts_scale = 3
     assert lib.pm4g_ingest_csv(f, 100, ctypes.byref(sc), ctypes.byref(co), ws, 16, None) == pm4g.PM4G_E_WORKSPACE
+
+
+def test_noalloc_rejects_oversized_logs_before_device_work():
+    # the size check precedes the scratch lookup, so it runs without a GPU
+    lib = pm4g.load()
+    A, n = 512, 20_000_000
+    assert lib.pm4g_workspace_bytes(pm4g.OP_DFG_PREPARED, n, A, 0) > pm4g.PM4G_NOALLOC_SCRATCH_BYTES
+    p = pm4g._Prepared(_fake(0), _fake(0), _fake(0), _fake(0), _fake(0), _fake(0), _fake(0), n, A)
+    out = pm4g._DfgOut(*[_fake(0)] * 11)
+    assert lib.pm4g_dfg_prepared_noalloc(ctypes.byref(p), ctypes.byref(out), None) == pm4g.PM4G_E_WORKSPACE
+    assert b"scratch" in lib.pm4g_last_error()
+    # every log of at most 64 activities fits
+    for n in (0, 1, 10**6, 2**31 - 1):
+        assert lib.pm4g_workspace_bytes(pm4g.OP_DFG_PREPARED, n, 64, 0) <= pm4g.PM4G_NOALLOC_SCRATCH_BYTES
+    bad = pm4g._Prepared(_fake(0), _fake(0), _fake(0), _fake(0), _fake(0), _fake(0), _fake(0), 10, 0)
+    assert lib.pm4g_dfg_prepared_noalloc(ctypes.byref(bad), ctypes.byref(out), None) == pm4g.PM4G_E_INVALID
+    assert lib.pm4g_dfg_prepared_noalloc(None, ctypes.byref(out), None) == pm4g.PM4G_E_INVALID
