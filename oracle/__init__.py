@@ -41,6 +41,8 @@ def _load():
         L.orc_variants.argtypes = [i64, P, P, P, i32, P, P, P, P, P, P, P, P, P]
         L.orc_view.argtypes = [i64, P, P, P, i32, i32, i32, i64, i64, P,
                                P, P, P, P, P, P, P, P, P, P, P]
+        L.orc_view_formatted.argtypes = [i64, P, P, P, i64, P, P, i32, i32, i32, i64, i64, P,
+                                         P, P, P, P, P, P, P, P, P, P, P]
         L.orc_cases.argtypes = [i64, P, P, P, i32, P, P, P, P]
         L.orc_filter_cases.argtypes = [i64, P, P, P, i32, P, P, P, i32, P, P, P, i64, i32, P, P, P, P, P]
         L.orc_filter_df_events.argtypes = [i64, P, P, P, i32, P, i32, i32, P, P, P, P, P]
@@ -50,7 +52,7 @@ def _load():
                                      P, P, P, P, P, P, P, P, P, P, P]
         L.orc_splitmix.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         L.orc_splitmix.restype = ctypes.c_uint64
-        for f in (L.orc_prepare, L.orc_dfg, L.orc_variants, L.orc_view, L.orc_cases, L.orc_filter_cases,
+        for f in (L.orc_prepare, L.orc_dfg, L.orc_variants, L.orc_view, L.orc_view_formatted, L.orc_cases, L.orc_filter_cases,
                   L.orc_filter_df_events, L.orc_efg, L.orc_sample, L.orc_ingest_csv):
             f.restype = ctypes.c_int
         _lib = L
@@ -184,6 +186,44 @@ def view(case, act, ts, A: int, case_lo: int, case_hi: int, t_lo: int, t_hi: int
     o["n_events"] = int(ne[0])
     return o
 
+
+
+def view_formatted(prep: dict, A: int, case_lo: int, case_hi: int, t_lo: int, t_hi: int, mask) -> dict:
+    """One drill-down view answered by a scan of the formatted log `prep`
+    (the dict prepare() returns): same outputs as view()."""
+    case_s = np.ascontiguousarray(prep["case_s"], dtype=np.int32)
+    act_s = np.ascontiguousarray(prep["act_s"], dtype=np.int32)
+    ts_s = np.ascontiguousarray(prep["ts_s"], dtype=np.int64)
+    off = np.ascontiguousarray(prep["case_off"], dtype=np.int64)
+    code = np.ascontiguousarray(prep["case_code"], dtype=np.int32)
+    n, C = case_s.shape[0], code.shape[0]
+    if off.shape != (C + 1,) or act_s.shape != (n,) or ts_s.shape != (n,):
+        raise ValueError("prep is not a formatted log")
+    W = (A + 63) // 64
+    mask = np.ascontiguousarray(mask, dtype=np.uint64)
+    if mask.shape != (W,):
+        raise ValueError("mask must have ceil(A/64) words")
+    cells = A * A
+    o = dict(count=np.empty(cells, np.int64), dt_sum=np.empty(cells, np.int64),
+             dt_min=np.empty(cells, np.int64), dt_max=np.empty(cells, np.int64),
+             dt_mean=np.empty(cells, np.float64), start_count=np.empty(A, np.int64),
+             end_count=np.empty(A, np.int64), act_count=np.empty(A, np.int64))
+    nc = np.zeros(1, np.int64)
+    ov = np.zeros(1, np.int32)
+    ne = np.zeros(1, np.int64)
+    rc = _load().orc_view_formatted(n, _p(case_s), _p(act_s), _p(ts_s), C, _p(off), _p(code), A,
+                                    int(case_lo), int(case_hi), int(t_lo), int(t_hi), _p(mask),
+                                    _p(o["count"]), _p(o["dt_sum"]), _p(o["dt_min"]), _p(o["dt_max"]),
+                                    _p(o["dt_mean"]), _p(o["start_count"]), _p(o["end_count"]),
+                                    _p(o["act_count"]), _p(nc), _p(ov), _p(ne))
+    if rc:
+        raise OracleError(rc)
+    for k in ("count", "dt_sum", "dt_min", "dt_max", "dt_mean"):
+        o[k] = o[k].reshape(A, A)
+    o["n_cases"] = int(nc[0])
+    o["overflow"] = int(ov[0])
+    o["n_events"] = int(ne[0])
+    return o
 
 def cases(case, act, ts, A: int) -> dict:
     """The cases dataframe: per case (ascending code) its events and throughput time."""

@@ -395,6 +395,87 @@ int orc_view(int64_t n, const int32_t *case_id, const int32_t *act, const int64_
     return r;
 }
 
+/*
+ * orc_view_formatted: the same view, answered from a log already in the
+ * (case, timestamp, row) order (the output of orc_prepare: case_s, act_s, ts_s
+ * of n events, and its case table case_code[C] ascending with case_off[C+1]).
+ * Sec. 3: the log is formatted once and every later operation works on the
+ * formatted log; removing events keeps the others in that order, so the
+ * retained events of the cases in [case_lo, case_hi) are met in order by one
+ * scan of those cases' positions.  Walking them, a retained event directly
+ * follows the previous retained event of the same case.  Same outputs as
+ * orc_view.
+ */
+int orc_view_formatted(int64_t n, const int32_t *case_s, const int32_t *act_s, const int64_t *ts_s,
+                       int64_t C, const int64_t *case_off, const int32_t *case_code, int32_t A,
+                       int32_t case_lo, int32_t case_hi, int64_t t_lo, int64_t t_hi,
+                       const uint64_t *mask, int64_t *count, int64_t *dt_sum, int64_t *dt_min,
+                       int64_t *dt_max, double *dt_mean, int64_t *start_count, int64_t *end_count,
+                       int64_t *act_count, int64_t *n_cases, int32_t *overflow, int64_t *n_events)
+{
+    if (n < 0 || A < 1 || C < 0 || C > n || case_off[0] != 0 || case_off[C] != n) return ORC_E_INVALID;
+    const int64_t cells = (int64_t)A * A;
+    for (int64_t x = 0; x < cells; x++) {
+        count[x] = 0;
+        dt_sum[x] = 0;
+        dt_min[x] = INT64_MAX;
+        dt_max[x] = INT64_MIN;
+    }
+    for (int32_t a = 0; a < A; a++) start_count[a] = end_count[a] = act_count[a] = 0;
+
+    /* first case with code >= case_lo, then the first with code >= case_hi
+       (binary searches over the ascending case codes) */
+    int64_t lo = 0, hi = C;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (case_code[mid] < case_lo) lo = mid + 1; else hi = mid;
+    }
+    int64_t j0 = lo;
+    hi = C;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (case_code[mid] < case_hi) lo = mid + 1; else hi = mid;
+    }
+    int64_t j1 = case_lo < case_hi ? lo : j0;
+
+    int64_t kept = 0, cases_seen = 0;
+    unsigned __int128 total_span = 0;
+    for (int64_t j = j0; j < j1; j++) {
+        int64_t prev = -1, first = -1;      /* positions of retained events of this case */
+        for (int64_t k = case_off[j]; k < case_off[j + 1]; k++) {
+            int32_t a = act_s[k];
+            if (a < 0 || a >= A) return ORC_E_RANGE;     /* only the scanned slice is checked */
+            if (ts_s[k] < t_lo || ts_s[k] > t_hi || !((mask[a / 64] >> (a % 64)) & 1u)) continue;
+            kept++;
+            act_count[a] += 1;
+            if (prev < 0) {
+                first = k;
+                start_count[a] += 1;
+            } else {
+                int64_t cell = (int64_t)act_s[prev] * A + a;
+                uint64_t gap_u = (uint64_t)ts_s[k] - (uint64_t)ts_s[prev];
+                int64_t gap = (int64_t)gap_u;
+                count[cell] += 1;
+                dt_sum[cell] = (int64_t)((uint64_t)dt_sum[cell] + gap_u);
+                if (gap < dt_min[cell]) dt_min[cell] = gap;
+                if (gap > dt_max[cell]) dt_max[cell] = gap;
+            }
+            prev = k;
+        }
+        if (prev >= 0) {
+            end_count[act_s[prev]] += 1;
+            total_span += (unsigned __int128)((uint64_t)ts_s[prev] - (uint64_t)ts_s[first]);
+            cases_seen++;
+        }
+    }
+    for (int64_t x = 0; x < cells; x++)
+        dt_mean[x] = count[x] > 0 ? (double)dt_sum[x] / (double)count[x] : NAN;
+    *n_cases = cases_seen;
+    *overflow = total_span > (unsigned __int128)INT64_MAX ? 1 : 0;
+    *n_events = kept;
+    return ORC_OK;
+}
+
 /* ---- cases dataframe and case-level filters -------------------------- */
 
 /*

@@ -161,12 +161,15 @@ def test_view_matches_bruteforce(log, data):
     mask = np.zeros((A + 63) // 64, np.uint64)
     for a in subset:
         mask[a // 64] |= np.uint64(1) << np.uint64(a % 64)
-    o = oracle.view(case, act, ts, A, lo, hi, t_lo, t_hi, mask)
     b = bf.view(case, act, ts, A, lo, hi, t_lo, t_hi, subset)
-    for k in ("count", "dt_sum", "dt_min", "dt_max", "act_count", "start_count", "end_count"):
-        assert o[k].tolist() == b[k], k
-    assert _same_float(o["dt_mean"], b["dt_mean"])
-    assert o["n_cases"] == b["n_cases"] and o["n_events"] == b["n_events"]
+    prep = oracle.prepare(case, act, ts, A)
+    for o in (oracle.view(case, act, ts, A, lo, hi, t_lo, t_hi, mask),
+              oracle.view_formatted(prep, A, lo, hi, t_lo, t_hi, mask)):
+        for k in ("count", "dt_sum", "dt_min", "dt_max", "act_count", "start_count", "end_count"):
+            assert o[k].tolist() == b[k], k
+        assert _same_float(o["dt_mean"], b["dt_mean"])
+        assert o["n_cases"] == b["n_cases"] and o["n_events"] == b["n_events"]
+        assert o["overflow"] == b["overflow"]
 
 
 @settings(max_examples=100, deadline=None)
@@ -409,6 +412,39 @@ def test_view_unfiltered_equals_plain_and_additivity():
     assert np.array_equal(np.maximum(a["dt_max"], b["dt_max"]), d["dt_max"])
     assert a["n_cases"] + b["n_cases"] == d["n_cases"]
 
+
+
+def test_view_formatted_equals_view_on_workload_views():
+    """The scan of the formatted log gives the same view as filtering the raw
+    log and formatting the kept events from scratch, on workload-shaped views
+    (including empty ranges, a full range and a sign-bit case range)."""
+    log = synth.config_log(3, 0.002)
+    A = log.n_activities
+    prep = oracle.prepare(log.case, log.act, log.ts, A)
+    views = synth.make_views(log, 40, seed=7, min_events=10, max_events=20_000)
+    W = (A + 63) // 64
+    full = np.full(W, np.uint64(0xFFFFFFFFFFFFFFFF))
+    extra = [(0, 0, INT64_MIN, INT64_MAX, full), (5, 3, INT64_MIN, INT64_MAX, full),
+             (-2**31, 2**31 - 1, INT64_MIN, INT64_MAX, full), (-2**31, 100, INT64_MIN, INT64_MAX, full),
+             (int(log.case.max()), 2**31 - 1, INT64_MIN, INT64_MAX, full)]
+    cases = [(int(views.case_lo[v]), int(views.case_hi[v]), int(views.t_lo[v]), int(views.t_hi[v]),
+              views.masks[v]) for v in range(views.n_views)] + extra
+    for lo, hi, t_lo, t_hi, mask in cases:
+        a = oracle.view(log.case, log.act, log.ts, A, lo, hi, t_lo, t_hi, mask)
+        b = oracle.view_formatted(prep, A, lo, hi, t_lo, t_hi, mask)
+        for key in ("count", "dt_sum", "dt_min", "dt_max", "start_count", "end_count", "act_count"):
+            assert np.array_equal(a[key], b[key]), (lo, hi, key)
+        assert _same_float(a["dt_mean"], b["dt_mean"])
+        assert (a["n_events"], a["n_cases"], a["overflow"]) == (b["n_events"], b["n_cases"], b["overflow"])
+    d = oracle.dfg(log.case, log.act, log.ts, A)
+    u = oracle.view_formatted(prep, A, -2**31, 2**31 - 1, INT64_MIN, INT64_MAX, full)
+    for key in ("count", "dt_sum", "dt_min", "dt_max", "start_count", "end_count", "act_count"):
+        assert np.array_equal(u[key], d[key]), key
+    with pytest.raises(oracle.OracleError):
+        bad = dict(prep)
+        bad["act_s"] = prep["act_s"].copy()
+        bad["act_s"][0] = A
+        oracle.view_formatted(bad, A, -2**31, 2**31 - 1, INT64_MIN, INT64_MAX, full)
 
 def test_generators_are_seeded_and_shaped():
     a = synth.config_log(2, 0.01)
