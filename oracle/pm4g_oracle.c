@@ -225,7 +225,9 @@ typedef struct {
     int64_t off, len;  /* its events in the ordered activity array */
 } orc_case;
 
-static const int32_t *g_seq_acts;   /* qsort has no context argument */
+/* qsort has no context argument; one per thread, so that concurrent calls
+   from several host threads do not share it */
+static _Thread_local const int32_t *g_seq_acts;
 
 /* Lexicographic order of activity sequences, a shorter prefix first. */
 static int cmp_case_seq(const void *pa, const void *pb)
@@ -444,6 +446,7 @@ int orc_view_formatted(int64_t n, const int32_t *case_s, const int32_t *act_s, c
         int64_t prev = -1, first = -1;      /* positions of retained events of this case */
         for (int64_t k = case_off[j]; k < case_off[j + 1]; k++) {
             int32_t a = act_s[k];
+            if (case_s[k] != case_code[j]) return ORC_E_INVALID;   /* not the case table of this log */
             if (a < 0 || a >= A) return ORC_E_RANGE;     /* only the scanned slice is checked */
             if (ts_s[k] < t_lo || ts_s[k] > t_hi || !((mask[a / 64] >> (a % 64)) & 1u)) continue;
             kept++;

@@ -446,6 +446,20 @@ def test_view_formatted_equals_view_on_workload_views():
         bad["act_s"][0] = A
         oracle.view_formatted(bad, A, -2**31, 2**31 - 1, INT64_MIN, INT64_MAX, full)
 
+
+def test_oracle_calls_from_concurrent_threads_match_sequential_calls():
+    """The oracle's functions give the same results when several host threads
+    call them at once (the variant sort's comparator context is per thread)."""
+    import concurrent.futures as cf
+    logs = [synth.config_log(3, 0.001 * (k + 1)) for k in range(6)]
+    seq = [oracle.variants(g.case, g.act, g.ts, g.n_activities) for g in logs]
+    with cf.ThreadPoolExecutor(6) as ex:
+        par = list(ex.map(lambda g: oracle.variants(g.case, g.act, g.ts, g.n_activities), logs * 2))
+    for k, p in enumerate(par):
+        s = seq[k % len(logs)]
+        for key in ("var_count", "var_len", "var_rep", "var_off", "var_acts", "case_variant"):
+            assert np.array_equal(p[key], s[key]), (k, key)
+
 def test_generators_are_seeded_and_shaped():
     a = synth.config_log(2, 0.01)
     b = synth.config_log(2, 0.01)
