@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define PM4G_ABI_VERSION 1
+#define PM4G_ABI_VERSION 2
 #define PM4G_MAX_ACTIVITIES 4096
 #define PM4G_BATCHED_MAX_ACTIVITIES 1024
 
@@ -103,6 +103,15 @@ typedef struct {
  *   case_off[j]..case_off[j+1]-1  positions of case j's events
  *   n_cases                       device scalar: number of distinct cases C
  *   status                        device status word of pm4g_prepare
+ *   row                           optional (may be NULL): row[k] is the row, in
+ *                                 the raw log given to pm4g_prepare, of the k-th
+ *                                 event in order -- the permutation of the first
+ *                                 formatting step, by which any other column of
+ *                                 the caller's dataframe follows the formatted
+ *                                 order (other_s[k] = other[row[k]]).  Only
+ *                                 pm4g_prepare writes it, and only when it is not
+ *                                 NULL (the sort then carries 4 more bytes per
+ *                                 event); every other entry point ignores it.
  */
 typedef struct {
     int32_t *case_s;
@@ -114,6 +123,7 @@ typedef struct {
     int32_t *status;
     int64_t n_events;
     int32_t n_activities;
+    int32_t *row;
 } pm4g_prepared;
 
 /*
@@ -296,14 +306,16 @@ int pm4g_dfg_prepared_noalloc(const pm4g_prepared *log, const pm4g_dfg_out *out,
  * DFGs of many drill-down views of one prepared log in one pass over the log
  * (views: device array of n_views records; act_masks: device array of
  * n_views * ceil(A/64) words, bit a of word a/64 of row v selects activity a
- * for view v).  Requires A <= PM4G_BATCHED_MAX_ACTIVITIES.  Synchronises
- * `stream` twice to check the internal capacities; returns PM4G_E_CAPACITY
- * (and fills out->required) when a pair, record or descriptor capacity of
- * `tuning` is too small: call again with larger capacities.  The cell and
- * output capacities (cell_capacity, cap_edges) are checked on the device and
- * reported in out->status and out->required.  n_views times the number of
- * 4096-cell buckets of the A*(A+1) cells, ceil(A*(A+1)/4096), must stay below
- * 2^32 (else PM4G_E_INVALID, and a workspace size of 0).
+ * for view v).  Requires A <= PM4G_BATCHED_MAX_ACTIVITIES.  Does not
+ * synchronise: every capacity is checked on the device.  When one is short
+ * -- the pair, record, descriptor or cell capacity of `tuning`, or cap_edges
+ * -- out->status becomes PM4G_E_CAPACITY and out->required holds the sizes
+ * known at that point (0 for those that are not: the output and cell counts
+ * are known only once the records fit): call again with larger capacities
+ * until the status is PM4G_OK.  More than 2^32 - 1 kept (event, view) pairs in
+ * one call give status PM4G_E_INVALID (split the views).  n_views times the
+ * number of 4096-cell buckets of the A*(A+1) cells, ceil(A*(A+1)/4096), must
+ * stay below 2^32 (else PM4G_E_INVALID, returned, and a workspace size of 0).
  */
 size_t pm4g_batched_workspace_bytes(int64_t n_events, int32_t n_activities, int32_t n_views,
                                     const pm4g_batched_tuning *tuning);

@@ -47,13 +47,6 @@ void set_err(const char* fmt, ...) {
 constexpr int64_t kMaxEvents = (int64_t(1) << 31) - 1;
 
 __global__ void k_set_status(int32_t* status, int32_t code) { *status = code; }
-__global__ void k_set_required(int64_t* req, int64_t pairs, int64_t records, int64_t descs, int32_t* status) {
-    req[1] = records;
-    req[2] = descs;
-    req[3] = pairs;
-    *status = PM4G_E_CAPACITY;
-}
-
 struct BatchedTune {
     int tile, emit_blocks, agg_blocks;
     int64_t pair_cap, rec_cap, desc_cap, cell_cap;
@@ -103,7 +96,10 @@ struct PrepWs {
     uint32_t* wincnt;
 };
 
-PrepWs prep_ws_layout(Bump& bp, int64_t n) {
+// with_rows: room for the original row of each element in both sort buffers
+// (pm4g_prepare's workspace has it; the raw-log DFG and variants calls do not
+// produce the permutation).
+PrepWs prep_ws_layout(Bump& bp, int64_t n, bool with_rows) {
     PrepWs w{};
     const size_t m = (size_t)(n > 0 ? n : 1);
     w.info = bp.take<RangeInfo>(1);
@@ -114,6 +110,8 @@ PrepWs prep_ws_layout(Bump& bp, int64_t n) {
     w.b.key = bp.take<uint32_t>(m);
     w.b.ts = bp.take<int64_t>(m);
     w.b.act = bp.take<uint32_t>(m);
+    w.a.row = with_rows ? bp.take<uint32_t>(m) : nullptr;
+    w.b.row = with_rows ? bp.take<uint32_t>(m) : nullptr;
     w.hist = bp.take<uint32_t>(256 * (size_t)(radix_blocks(n) + 1));
     w.hist_raw = bp.take<uint32_t>(256 * (size_t)(radix_blocks(n) + 1));
     w.rowsum = bp.take<uint32_t>(256);
@@ -169,13 +167,17 @@ int bits_of(uint64_t range) {
     return b;
 }
 
-// Formatting step into `out` (caller's arrays or workspace arrays).
+// Formatting step into `out` (caller's arrays or workspace arrays).  With
+// ws_rows the workspace has room for the row order, and out->row (if not
+// NULL) receives the original row of each position.
 int run_prepare(const pm4g_log* log, const pm4g_prepared* out, bool case_table, Bump& bp,
-                hipStream_t s) {
+                hipStream_t s, bool ws_rows = false) {
     const int64_t n = log->n_events;
     const int32_t A = log->n_activities;
     const bool presorted = (log->flags & PM4G_PRESORTED) != 0;
-    PrepWs w = prep_ws_layout(bp, n);
+    PrepWs w = prep_ws_layout(bp, n, ws_rows);
+    int32_t* const row_s = ws_rows ? out->row : nullptr;
+    if (!row_s) w.a.row = w.b.row = nullptr;   // the row order is carried only when asked for
     k_set_status<<<1, 1, 0, s>>>(out->status, 0);
     PM4G_HIP(launch_range_scan(log->case_id, log->activity, log->timestamp, n, A, presorted, false,
                                w.info, w.rpart, presorted ? nullptr : w.hist_raw, s));
@@ -192,9 +194,9 @@ int run_prepare(const pm4g_log* log, const pm4g_prepared* out, bool case_table, 
     bool have_wincnt = false;   // the per-case sort counted the cases of each window
     if (presorted) {
         PM4G_HIP(launch_copy_log(log->case_id, log->activity, log->timestamp, n, out->case_s,
-                                 out->act_s, out->ts_s, s));
+                                 out->act_s, out->ts_s, row_s, s));
     } else if (n > 0) {
-        const SortBufs raw{(uint32_t*)log->case_id, (int64_t*)log->timestamp, (uint32_t*)log->activity};
+        const SortBufs raw{(uint32_t*)log->case_id, (int64_t*)log->timestamp, (uint32_t*)log->activity, nullptr};
         const int case_bits = bits_of((uint64_t)(uint32_t)(h.case_max - h.case_min));
         const int act_bits = bits_of((uint64_t)(A - 1));
         // packed keys (activity above the case bits) when both fit in 32 bits
@@ -210,7 +212,7 @@ int run_prepare(const pm4g_log* log, const pm4g_prepared* out, bool case_table, 
             in = bufs[cur];
             cur ^= 1;
         }
-        PM4G_HIP(launch_segsort(in, n, w.info, out->case_s, out->act_s, out->ts_s, act_shift, w.wincnt, s));
+        PM4G_HIP(launch_segsort(in, n, w.info, out->case_s, out->act_s, out->ts_s, act_shift, w.wincnt, row_s, s));
         PM4G_HIP(hipMemcpyAsync(&h, w.info, sizeof(h), hipMemcpyDeviceToHost, s));
         PM4G_HIP(hipStreamSynchronize(s));
         have_wincnt = !h.long_case;
@@ -236,7 +238,7 @@ int run_prepare(const pm4g_log* log, const pm4g_prepared* out, bool case_table, 
                 in = bufs[cur];
                 cur ^= 1;
             }
-            PM4G_HIP(launch_unbias_copy(in, n, w.info, out->case_s, out->act_s, out->ts_s, act_shift, s));
+            PM4G_HIP(launch_unbias_copy(in, n, w.info, out->case_s, out->act_s, out->ts_s, act_shift, row_s, s));
         }
     }
     if (case_table)
@@ -303,7 +305,7 @@ size_t ws_bytes(int op, int64_t n, int32_t A) {
     Bump b(nullptr);
     switch (op) {
         case PM4G_OP_PREPARE:
-            prep_ws_layout(b, n);
+            prep_ws_layout(b, n, true);
             break;
         case PM4G_OP_DFG_PREPARED:
             dfg_ws_layout(b, n, A);
@@ -311,7 +313,7 @@ size_t ws_bytes(int op, int64_t n, int32_t A) {
         case PM4G_OP_DFG: {
             prepared_in_ws(b, n, A);
             Bump b2(nullptr);
-            prep_ws_layout(b2, n);
+            prep_ws_layout(b2, n, false);
             Bump b3(nullptr);
             dfg_ws_layout(b3, n, A);
             b.off += (b2.off > b3.off ? b2.off : b3.off) + 256;
@@ -323,7 +325,7 @@ size_t ws_bytes(int op, int64_t n, int32_t A) {
         case PM4G_OP_VARIANTS: {
             prepared_in_ws(b, n, A);
             Bump b2(nullptr);
-            prep_ws_layout(b2, n);
+            prep_ws_layout(b2, n, false);
             Bump b3(nullptr);
             var_ws_layout(b3, n);
             b.off += (b2.off > b3.off ? b2.off : b3.off) + 256;
@@ -633,30 +635,7 @@ int pm4g_dfg_batched(const pm4g_prepared* log, const pm4g_view* views, const uin
                           out->dt_max, out->dt_mean, out->start_count, out->end_count, out->act_count,
                           out->n_events, out->n_cases, out->cap_edges, out->required, out->status};
     PM4G_HIP(launch_views_plan(log, views, n_views, w, o, s));
-    int64_t sc[8];
-    PM4G_HIP(hipMemcpyAsync(sc, w.scal, sizeof(sc), hipMemcpyDeviceToHost, s));
-    PM4G_HIP(hipStreamSynchronize(s));
-    if (sc[7] > t.pair_cap) {
-        k_set_required<<<1, 1, 0, s>>>(out->required, sc[7], 0, 0, out->status);
-        PM4G_HIP(hipGetLastError());
-        set_err("%lld (tile, view) pairs, pair_capacity %lld", (long long)sc[7], (long long)t.pair_cap);
-        return PM4G_E_CAPACITY;
-    }
     PM4G_HIP(launch_views_count(log, views, act_masks, w, t.emit_blocks, s));
-    PM4G_HIP(hipMemcpyAsync(sc, w.scal, sizeof(sc), hipMemcpyDeviceToHost, s));
-    PM4G_HIP(hipStreamSynchronize(s));
-    if (sc[0] > (int64_t)0xFFFFFFFF) {
-        set_err("%lld kept (event, view) pairs in one call; at most 2^32 - 1: split the views",
-                (long long)sc[0]);
-        return PM4G_E_INVALID;
-    }
-    if (sc[0] > t.rec_cap || sc[1] > t.desc_cap) {
-        k_set_required<<<1, 1, 0, s>>>(out->required, sc[7], sc[0], sc[1], out->status);
-        PM4G_HIP(hipGetLastError());
-        set_err("%lld records (capacity %lld), %lld descriptors (capacity %lld)", (long long)sc[0],
-                (long long)t.rec_cap, (long long)sc[1], (long long)t.desc_cap);
-        return PM4G_E_CAPACITY;
-    }
     PM4G_HIP(launch_views_reduce(log, views, act_masks, n_views, w, o, t.emit_blocks, t.agg_blocks, s));
     return PM4G_OK;
 }
@@ -675,7 +654,7 @@ int pm4g_prepare(const pm4g_log* log, const pm4g_prepared* out, void* ws, size_t
         return PM4G_E_WORKSPACE;
     }
     Bump bp(ws);
-    return run_prepare(log, out, true, bp, (hipStream_t)stream);
+    return run_prepare(log, out, true, bp, (hipStream_t)stream, true);
 }
 
 int pm4g_dfg_prepared(const pm4g_prepared* log, const pm4g_dfg_out* out, void* ws, size_t ws_size,

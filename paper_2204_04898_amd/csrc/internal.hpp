@@ -58,6 +58,7 @@ struct SortBufs {
     uint32_t* key;
     int64_t* ts;
     uint32_t* act;
+    uint32_t* row;   // original row of each element; NULL when the row order is not carried
 };
 constexpr int kRadixTile = 4096;
 inline int64_t radix_blocks(int64_t n) { return (n + kRadixTile - 1) / kRadixTile; }
@@ -78,14 +79,15 @@ constexpr int kSegWindow = 1024;
 constexpr int kSegCap = 3072;   // window + the longest case kept on the fast path (2049) - 1
 inline int64_t segsort_blocks(int64_t n) { return (n + kSegWindow - 1) / kSegWindow; }
 // wincnt: [segsort_blocks(n)] cases starting in each window (valid unless long_case).
+// row_s (may be NULL): the original row of each position, from in.row.
 hipError_t launch_segsort(SortBufs in, int64_t n, RangeInfo* info, int32_t* case_s, int32_t* act_s,
-                          int64_t* ts_s, int act_shift, uint32_t* wincnt, hipStream_t s);
+                          int64_t* ts_s, int act_shift, uint32_t* wincnt, int32_t* row_s, hipStream_t s);
 // Copies fully sorted buffers (fallback path) into the prepared arrays.
 hipError_t launch_unbias_copy(SortBufs in, int64_t n, const RangeInfo* info, int32_t* case_s,
-                              int32_t* act_s, int64_t* ts_s, int act_shift, hipStream_t s);
-// Copies a presorted raw log into the prepared arrays.
+                              int32_t* act_s, int64_t* ts_s, int act_shift, int32_t* row_s, hipStream_t s);
+// Copies a presorted raw log into the prepared arrays (row_s, if given: the identity).
 hipError_t launch_copy_log(const int32_t* c, const int32_t* a, const int64_t* t, int64_t n,
-                           int32_t* case_s, int32_t* act_s, int64_t* ts_s, hipStream_t s);
+                           int32_t* case_s, int32_t* act_s, int64_t* ts_s, int32_t* row_s, hipStream_t s);
 
 // ---- case table (cases.hip) ----
 constexpr int kCaseTile = 4096;

@@ -15,6 +15,9 @@
 // the activity rides in the key above the case bits (key_mask selects the
 // case bits) and no activity column moves: 12 bytes per element.
 // Bytes per event per pass: 4 (hist) + 16 read + 16 write (12 + 12 packed).
+// Row order (ROW): when the caller asks for the permutation, each element
+// also carries its original row (the first pass takes it from its position),
+// 4 more bytes read and written per element; otherwise nothing moves for it.
 #include "common.hpp"
 #include "internal.hpp"
 #include "prof.hpp"
@@ -142,7 +145,7 @@ __global__ __launch_bounds__(256) void k_radix_scan_rot(const uint32_t* hist_raw
     if (threadIdx.x == 0) rowsum[blockIdx.x] = run;
 }
 
-template <int SRC, bool FIRST, bool PACKED>
+template <int SRC, bool FIRST, bool PACKED, bool ROW>
 __global__ __launch_bounds__(kRB) void k_radix_scatter(SortBufs in, SortBufs out, int64_t n, int shift,
                                                        const RangeInfo* info, const uint32_t* hist,
                                                        const uint32_t* rowsum, int64_t nb,
@@ -152,7 +155,8 @@ __global__ __launch_bounds__(kRB) void k_radix_scatter(SortBufs in, SortBufs out
     __shared__ int64_t gshift[256];           // global position - tile position
     __shared__ uint32_t skey[kRadixTile];
     __shared__ int64_t sts[kRadixTile];
-    __shared__ uint32_t sact[kRadixTile];
+    __shared__ uint32_t sact[PACKED ? 1 : kRadixTile];
+    __shared__ uint32_t srow[ROW ? kRadixTile : 1];
     __shared__ uint32_t tmp[kRB / kWave + 1];
 
     const int32_t case_min = info->case_min;
@@ -166,7 +170,7 @@ __global__ __launch_bounds__(kRB) void k_radix_scatter(SortBufs in, SortBufs out
 
     for (int i = threadIdx.x; i < kRW * 256; i += kRB) cnt[i] = 0;
 
-    uint32_t key[kRI], act[kRI], dg[kRI], rk[kRI];
+    uint32_t key[kRI], act[kRI], dg[kRI], rk[kRI], rw[kRI];
     int64_t tv[kRI];
     if constexpr (FIRST) {
         // all loads of the tile first: forming each key from its two raw
@@ -185,6 +189,7 @@ __global__ __launch_bounds__(kRB) void k_radix_scatter(SortBufs in, SortBufs out
                 ra[k] = 0;
                 tv[k] = ts_min;
             }
+            rw[k] = (uint32_t)i;
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -202,10 +207,12 @@ __global__ __launch_bounds__(kRB) void k_radix_scatter(SortBufs in, SortBufs out
                 key[k] = load_key<FIRST, PACKED>(in, i, case_min, act_shift);
                 tv[k] = in.ts[i];
                 act[k] = PACKED ? 0u : in.act[i];
+                rw[k] = ROW ? in.row[i] : 0u;
             } else {
                 key[k] = 0;
                 tv[k] = ts_min;
                 act[k] = 0;
+                rw[k] = 0;
             }
             dg[k] = digit_of<SRC>(key[k], tv[k], shift, ts_min, key_mask);
         }
@@ -258,6 +265,7 @@ __global__ __launch_bounds__(kRB) void k_radix_scatter(SortBufs in, SortBufs out
             skey[pos] = key[k];
             sts[pos] = tv[k];
             if (!PACKED) sact[pos] = act[k];
+            if (ROW) srow[pos] = rw[k];
         }
     }
     __syncthreads();
@@ -271,10 +279,11 @@ __global__ __launch_bounds__(kRB) void k_radix_scatter(SortBufs in, SortBufs out
         out.key[g] = k;
         out.ts[g] = t;
         if (!PACKED) out.act[g] = sact[i];
+        if (ROW) out.row[g] = srow[i];
     }
 }
 
-template <int SRC, bool FIRST, bool PACKED>
+template <int SRC, bool FIRST, bool PACKED, bool ROW>
 static void run_pass(SortBufs in, SortBufs out, int64_t n, int shift, const RangeInfo* info,
                      uint32_t* hist, uint32_t* rowsum, uint32_t key_mask, int act_shift,
                      const uint32_t* hist_raw, hipStream_t s) {
@@ -291,7 +300,7 @@ static void run_pass(SortBufs in, SortBufs out, int64_t n, int shift, const Rang
         k_radix_scan<<<256, 256, 0, s>>>(hist, nb, rowsum);
     }
     ProfScope p(P_RADIX_SCATTER, s);
-    k_radix_scatter<SRC, FIRST, PACKED><<<(unsigned)nb, kRB, 0, s>>>(in, out, n, shift, info, hist, rowsum,
+    k_radix_scatter<SRC, FIRST, PACKED, ROW><<<(unsigned)nb, kRB, 0, s>>>(in, out, n, shift, info, hist, rowsum,
                                                                       nb, key_mask, act_shift);
 }
 
@@ -303,8 +312,16 @@ hipError_t launch_radix_pass(SortBufs in, SortBufs out, int64_t n, int digit_src
     const uint32_t key_mask = packed ? ((act_shift >= 32) ? 0xFFFFFFFFu : ((1u << act_shift) - 1u)) : 0xFFFFFFFFu;
     // the raw-byte histograms describe the first case pass only
     if (!(digit_src == 0 && first && shift == 0)) hist_raw = nullptr;
-#define PM4G_PASS(SRC, FIRST, PACKED) \
-    run_pass<SRC, FIRST, PACKED>(in, out, n, shift, info, hist, rowsum, key_mask, act_shift, hist_raw, s)
+    // the row order is carried iff the output has a row array
+#define PM4G_PASS(SRC, FIRST, PACKED)                                                                        \
+    do {                                                                                                    \
+        if (out.row)                                                                                        \
+            run_pass<SRC, FIRST, PACKED, true>(in, out, n, shift, info, hist, rowsum, key_mask, act_shift, \
+                                               hist_raw, s);                                                \
+        else                                                                                                \
+            run_pass<SRC, FIRST, PACKED, false>(in, out, n, shift, info, hist, rowsum, key_mask, act_shift, \
+                                                hist_raw, s);                                               \
+    } while (0)
     if (digit_src == 0) {
         if (first) { if (packed) PM4G_PASS(0, true, true); else PM4G_PASS(0, true, false); }
         else { if (packed) PM4G_PASS(0, false, true); else PM4G_PASS(0, false, false); }

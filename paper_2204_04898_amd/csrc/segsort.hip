@@ -28,8 +28,10 @@
 // A region longer than the LDS window sets RangeInfo::long_case and the
 // host switches to the full-key fallback.
 //
-// Also writes the prepared columns: case id (unbiased), activity, timestamp.
-// Bytes per event: 16 read + 16 write (12 + 16 packed).
+// Also writes the prepared columns: case id (unbiased), activity, timestamp,
+// and, when the caller asks for it (ROW), the original row of each position
+// (read from the row the radix passes carried, at its staging position).
+// Bytes per event: 16 read + 16 write (12 + 16 packed; + 4 + 4 with rows).
 #include "common.hpp"
 #include "internal.hpp"
 #include "prof.hpp"
@@ -134,11 +136,13 @@ constexpr uint64_t kOffBias = 1ull << 51;
 constexpr uint64_t kOffMask = (1ull << 52) - 1;
 
 // act_shift > 0: packed keys (case bits below act_shift, activity above).
+template <bool ROW>
 __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeInfo* info,
                                                  int32_t* __restrict__ case_s,
                                                  int32_t* __restrict__ act_s,
                                                  int64_t* __restrict__ ts_s, int act_shift,
-                                                 uint32_t* __restrict__ wincnt) {
+                                                 uint32_t* __restrict__ wincnt,
+                                                 int32_t* __restrict__ row_s) {
     __shared__ int64_t lts[kSegCap];     // timestamps; on the fast path the sorted cross keys
     __shared__ uint16_t lact[kSegCap];
     __shared__ uint16_t lidx[kSegCap];   // field-by-field path: staging position of the event now at i
@@ -333,6 +337,7 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
     int32_t pos[kSI];
     int64_t tv[kSI];
     uint16_t av[kSI];
+    uint16_t sv[kSI];   // staging position of the event (ROW)
     if (fast) {
         // sorted position i holds cross key (offset << 12 | staging position):
         // unique, and ordered as (timestamp, row) across the chunks of a case
@@ -372,6 +377,7 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
                 pos[q] = cs + r;
                 tv[q] = (int64_t)((uint64_t)sb[q] + (x >> 12) - kOffBias);
                 av[q] = lact[x & 0xFFFu];
+                sv[q] = (uint16_t)(x & 0xFFFu);
             }
         }
     } else {
@@ -422,6 +428,7 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
                 pos[q] = cs + r;
                 tv[q] = t;
                 av[q] = lact[id];
+                sv[q] = (uint16_t)id;
             }
         }
     }
@@ -431,6 +438,7 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
         if (pos[q] >= 0) {
             lts[pos[q]] = tv[q];
             lact[pos[q]] = av[q];
+            if (ROW) lidx[pos[q]] = sv[q];
         }
     }
     __syncthreads();
@@ -444,12 +452,13 @@ __global__ __launch_bounds__(kSB) void k_segsort(SortBufs in, int64_t n, RangeIn
             case_s[s + i] = (int32_t)((ck[q] & kmask) + bias);
             act_s[s + i] = (int32_t)lact[i];
             ts_s[s + i] = lts[i];
+            if (ROW) row_s[s + i] = (int32_t)in.row[s + lidx[i]];
         }
     }
 }
 
 __global__ void k_unbias_copy(SortBufs in, int64_t n, const RangeInfo* info, int32_t* case_s,
-                              int32_t* act_s, int64_t* ts_s, int act_shift) {
+                              int32_t* act_s, int64_t* ts_s, int act_shift, int32_t* row_s) {
     const uint32_t bias = (uint32_t)info->case_min;
     const uint32_t kmask = act_shift > 0 ? ((1u << act_shift) - 1u) : 0xFFFFFFFFu;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -458,16 +467,18 @@ __global__ void k_unbias_copy(SortBufs in, int64_t n, const RangeInfo* info, int
         case_s[i] = (int32_t)((k & kmask) + bias);
         act_s[i] = (int32_t)(act_shift > 0 ? (k >> act_shift) : in.act[i]);
         ts_s[i] = in.ts[i];
+        if (row_s) row_s[i] = (int32_t)in.row[i];
     }
 }
 
 __global__ void k_copy_log(const int32_t* c, const int32_t* a, const int64_t* t, int64_t n,
-                           int32_t* case_s, int32_t* act_s, int64_t* ts_s) {
+                           int32_t* case_s, int32_t* act_s, int64_t* ts_s, int32_t* row_s) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         case_s[i] = c[i];
         act_s[i] = a[i];
         ts_s[i] = t[i];
+        if (row_s) row_s[i] = (int32_t)i;   // presorted: position k is row k
     }
 }
 
@@ -477,22 +488,28 @@ static unsigned copy_grid(int64_t n) {
 }
 
 hipError_t launch_segsort(SortBufs in, int64_t n, RangeInfo* info, int32_t* case_s, int32_t* act_s,
-                          int64_t* ts_s, int act_shift, uint32_t* wincnt, hipStream_t s) {
+                          int64_t* ts_s, int act_shift, uint32_t* wincnt, int32_t* row_s, hipStream_t s) {
     ProfScope p(P_SEGSORT, s);
-    if (n > 0)
-        k_segsort<<<(unsigned)segsort_blocks(n), kSB, 0, s>>>(in, n, info, case_s, act_s, ts_s, act_shift, wincnt);
+    if (n > 0) {
+        if (row_s)
+            k_segsort<true><<<(unsigned)segsort_blocks(n), kSB, 0, s>>>(in, n, info, case_s, act_s, ts_s,
+                                                                         act_shift, wincnt, row_s);
+        else
+            k_segsort<false><<<(unsigned)segsort_blocks(n), kSB, 0, s>>>(in, n, info, case_s, act_s, ts_s,
+                                                                          act_shift, wincnt, nullptr);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_unbias_copy(SortBufs in, int64_t n, const RangeInfo* info, int32_t* case_s,
-                              int32_t* act_s, int64_t* ts_s, int act_shift, hipStream_t s) {
-    if (n > 0) k_unbias_copy<<<copy_grid(n), 256, 0, s>>>(in, n, info, case_s, act_s, ts_s, act_shift);
+                              int32_t* act_s, int64_t* ts_s, int act_shift, int32_t* row_s, hipStream_t s) {
+    if (n > 0) k_unbias_copy<<<copy_grid(n), 256, 0, s>>>(in, n, info, case_s, act_s, ts_s, act_shift, row_s);
     return hipGetLastError();
 }
 
 hipError_t launch_copy_log(const int32_t* c, const int32_t* a, const int64_t* t, int64_t n,
-                           int32_t* case_s, int32_t* act_s, int64_t* ts_s, hipStream_t s) {
-    if (n > 0) k_copy_log<<<copy_grid(n), 256, 0, s>>>(c, a, t, n, case_s, act_s, ts_s);
+                           int32_t* case_s, int32_t* act_s, int64_t* ts_s, int32_t* row_s, hipStream_t s) {
+    if (n > 0) k_copy_log<<<copy_grid(n), 256, 0, s>>>(c, a, t, n, case_s, act_s, ts_s, row_s);
     return hipGetLastError();
 }
 

@@ -59,18 +59,23 @@ def check_dfg(case, act, ts, A, presorted=False):
 
 
 def check_prepare(case, act, ts, A, presorted=False):
+    """The formatted log against the oracle's, without and with the row
+    permutation (the two sort variants), the rows element by element."""
     c, a, t = cols(case, act, ts)
-    p = pm4g.pm4g_prepare(c, a, t, A, presorted=presorted)
-    torch.cuda.synchronize()
-    h = pm4g.prepared_to_host(p)
     o = oracle.prepare(case, act, ts, A)
-    assert h["status"] == 0
-    assert h["n_cases"] == o["n_cases"]
-    assert np.array_equal(h["case_s"], o["case_s"]), "case_s"
-    assert np.array_equal(h["act_s"], o["act_s"]), "act_s"
-    assert np.array_equal(h["ts_s"], o["ts_s"]), "ts_s"
-    assert np.array_equal(h["case_off"], o["case_off"]), "case_off"
-    assert np.array_equal(h["case_code"], o["case_code"]), "case_code"
+    for rows in (False, True):
+        p = pm4g.pm4g_prepare(c, a, t, A, presorted=presorted, rows=rows)
+        torch.cuda.synchronize()
+        h = pm4g.prepared_to_host(p)
+        assert h["status"] == 0
+        assert h["n_cases"] == o["n_cases"]
+        assert np.array_equal(h["case_s"], o["case_s"]), "case_s"
+        assert np.array_equal(h["act_s"], o["act_s"]), "act_s"
+        assert np.array_equal(h["ts_s"], o["ts_s"]), "ts_s"
+        assert np.array_equal(h["case_off"], o["case_off"]), "case_off"
+        assert np.array_equal(h["case_code"], o["case_code"]), "case_code"
+        if rows:
+            assert np.array_equal(h["row"], o["row"]), "row"
     return p
 
 

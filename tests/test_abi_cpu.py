@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
     assert "pm4g_dfg" in names and "pm4g_variants" in names and "pm4g_prepare" in names
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.pm4g_abi_version() == 1
+    assert lib.pm4g_abi_version() == 2
 
 
 def test_workspace_sizes():

@@ -1,18 +1,22 @@
 """Parity at the benchmark's full sizes, in the launch configuration bench.py
-times: the 10M-event workload element by element against the oracle; the
-99M-event workload by invariants that hold at any size plus per-case checks
-on sampled cases (each compared with the oracle on that case's events); the
-4096 batched views by identities on every view plus the oracle on sampled
-views."""
+times, element by element against the oracle: the 10M-event workload; the
+99M-event workload (formatted log, every DFG table, every variants array);
+every one of the 4096 batched views over it (each answered by the oracle's
+scan of its own formatted log).  Invariants that hold at any size are
+checked beside them.  The oracle's independent calls run in host threads
+(its C functions release the interpreter lock)."""
+import concurrent.futures as cf
+
 import numpy as np
 import pytest
 import torch
 
 import oracle
 from paper_2204_04898_amd import pm4g, synth
-from tests.gpu_util import assert_dfg_equal, assert_variants_equal, note
+from tests.gpu_util import assert_dfg_equal, assert_variants_equal, note, same_f64
 
 pytestmark = pytest.mark.gpu
+_ROWS = {}   # the 99M-event log's row permutation from the GPU, until it is checked
 
 
 def _dev(log):
@@ -35,6 +39,9 @@ def test_full_10M_against_oracle():
     h = pm4g.prepared_to_host(prep)
     for k in ("case_s", "act_s", "ts_s", "case_off", "case_code"):
         assert np.array_equal(h[k], p[k]), k
+    hr = pm4g.prepared_to_host(pm4g.pm4g_prepare(c, a, t, A, rows=True))
+    for k in ("row", "case_s", "act_s", "ts_s", "case_off", "case_code"):
+        assert np.array_equal(hr[k], p[k]), ("with rows", k)
 
 
 @pytest.fixture(scope="module")
@@ -43,106 +50,114 @@ def big():
     note(f"99M workload: N={log.n_events}")
     c, a, t = _dev(log)
     prep = pm4g.pm4g_prepare(c, a, t, log.n_activities)
+    # the same log formatted with its row permutation (the sort's other variant)
+    rows = pm4g.pm4g_prepare(c, a, t, log.n_activities, rows=True).row
     del c, a, t
     torch.cuda.synchronize()
+    _ROWS["99M"] = rows
     return log, prep
 
 
-def test_full_99M_invariants_and_sampled_cases(big):
+@pytest.fixture(scope="module")
+def big_oracle(big):
+    """The oracle's formatted log, DFG and variants of the 99M-event log, run concurrently."""
+    log, _ = big
+    A = log.n_activities
+    note("oracle: prepare, dfg, variants and eventually-follows graph of 99M events (four host threads)")
+    with cf.ThreadPoolExecutor(4) as ex:
+        fp = ex.submit(oracle.prepare, log.case, log.act, log.ts, A)
+        fd = ex.submit(oracle.dfg, log.case, log.act, log.ts, A)
+        fv = ex.submit(oracle.variants, log.case, log.act, log.ts, A)
+        fe = ex.submit(oracle.efg, log.case, log.act, log.ts, A)
+        out = dict(prep=fp.result(), dfg=fd.result(), variants=fv.result(), efg=fe.result())
+    note("oracle done")
+    return out
+
+
+def test_full_99M_against_oracle(big, big_oracle):
     log, prep = big
     A = log.n_activities
     N = log.n_events
     d = pm4g.dfg_to_host(pm4g.pm4g_dfg_prepared(prep), A)
     C = int(prep.n_cases.item())
-    assert C == log.lengths_by_code.shape[0] and d["n_cases"] == C and d["status"] == 0
+    v = pm4g.variants_to_host(pm4g.pm4g_variants_prepared(prep), C)
+    h = pm4g.prepared_to_host(prep)
+    o = big_oracle
+    assert h["status"] == 0 and h["n_cases"] == o["prep"]["n_cases"]
+    for k in ("case_s", "act_s", "ts_s", "case_off", "case_code"):
+        assert np.array_equal(h[k], o["prep"][k]), k
+    assert np.array_equal(_ROWS.pop("99M").cpu().numpy(), o["prep"]["row"]), "row"
+    assert_dfg_equal(d, o["dfg"], A)
+    assert_variants_equal(v, o["variants"])
+    # invariants, independent of the oracle
     cnt = d["count"]
-    assert cnt.sum() == N - C
+    assert C == log.lengths_by_code.shape[0] and cnt.sum() == N - C
     assert d["start_count"].sum() == C == d["end_count"].sum()
     assert np.array_equal(cnt.sum(axis=1) + d["end_count"], d["act_count"])
     assert np.array_equal(cnt.sum(axis=0) + d["start_count"], d["act_count"])
     assert np.array_equal(d["act_count"], np.bincount(log.act, minlength=A))
-    nz = cnt > 0
-    assert np.all(d["dt_min"][nz] >= 0) and np.all(d["dt_min"][nz] <= d["dt_max"][nz])
-    assert np.all(d["dt_min"][nz].astype(object) * cnt[nz] <= d["dt_sum"][nz].astype(object))
-    assert np.all(d["dt_sum"][nz].astype(object) <= d["dt_max"][nz].astype(object) * cnt[nz])
     assert d["overflow"] == 0
-    # telescoping: the gap sums add up to the case spans
     first = np.full(C, np.iinfo(np.int64).max)
     last = np.full(C, np.iinfo(np.int64).min)
     np.minimum.at(first, log.case, log.ts)
     np.maximum.at(last, log.case, log.ts)
     assert int(d["dt_sum"].astype(object).sum()) == int((last - first).astype(object).sum())
-    # sampled cases against the oracle on exactly their events
-    rng = np.random.default_rng(99)
-    codes = np.sort(rng.choice(C, 3000, replace=False)).astype(np.int32)
-    keep = np.isin(log.case, codes)
-    o = oracle.prepare(log.case[keep], log.act[keep], log.ts[keep], A)
-    h_off = prep.case_off[:C + 1].cpu().numpy()
-    h_code = prep.case_code[:C].cpu().numpy()
-    act_s = prep.act_s.cpu().numpy()
-    ts_s = prep.ts_s.cpu().numpy()
-    for j, code in enumerate(o["case_code"]):
-        g = int(np.searchsorted(h_code, code))
-        assert h_code[g] == code
-        a0, a1 = h_off[g], h_off[g + 1]
-        b0, b1 = o["case_off"][j], o["case_off"][j + 1]
-        assert np.array_equal(act_s[a0:a1], o["act_s"][b0:b1])
-        assert np.array_equal(ts_s[a0:a1], o["ts_s"][b0:b1])
-    # variants: counts add up; sampled cases carry their own sequence
-    v = pm4g.variants_to_host(pm4g.pm4g_variants_prepared(prep), C)
-    assert v["status"] == 0 and v["var_count"].sum() == C and int((v["var_count"] * v["var_len"]).sum()) == N
-    key = np.stack([-v["var_count"], v["var_rep"].astype(np.int64)])
-    assert np.all(np.diff(key[0]) >= 0) and np.all((np.diff(key[0]) > 0) | (np.diff(key[1]) > 0))
-    for j, code in enumerate(o["case_code"][:500]):
-        vid = v["case_variant"][code]          # codes are dense 0..C-1
-        seq = v["var_acts"][v["var_off"][vid]:v["var_off"][vid + 1]]
-        assert np.array_equal(seq, o["act_s"][o["case_off"][j]:o["case_off"][j + 1]])
-        assert v["var_rep"][vid] <= code
+    assert v["var_count"].sum() == C and int((v["var_count"] * v["var_len"]).sum()) == N
 
 
-def test_full_4096_views(big):
+def test_full_4096_views(big, big_oracle):
+    """All 4096 views of the batched benchmark call, each against the oracle's
+    scan of the case-range slice of its formatted log."""
     log, prep = big
     A = log.n_activities
     views = synth.make_views(log, 4096, seed=synth.SEED_BASE + 4)
     vd, md = pm4g.views_to_device(views, "cuda:0")
     o = pm4g.pm4g_dfg_batched(prep, vd, md, views.n_views)
     res = pm4g.batched_to_host(o, views.n_views, A)
-    for v, r in enumerate(res):
+    oprep = big_oracle["prep"]
+    note("oracle: 4096 views")
+
+    def check(v):
+        r = res[v]
         cols = np.bincount(r["dst"], weights=r["count"], minlength=A).astype(np.int64)
         rows = np.bincount(r["src"], weights=r["count"], minlength=A).astype(np.int64)
         assert np.array_equal(r["act_count"], r["start_count"] + cols), v
         assert np.array_equal(r["end_count"], r["act_count"] - rows), v
-        assert r["n_cases"] == r["start_count"].sum() == r["end_count"].sum(), v
-        assert r["n_events"] == r["act_count"].sum(), v
         assert np.all(np.diff(r["src"].astype(np.int64) * A + r["dst"]) > 0), v
-    # the oracle on sampled views (smallest slices first keeps the CPU time bounded)
-    size = np.array([log.lengths_by_code[views.case_lo[v]:views.case_hi[v]].sum() for v in range(views.n_views)])
-    sample = list(np.argsort(size)[:6]) + list(np.argsort(size)[2000:2003])
-    for v in sample:
-        ref = oracle.view(log.case, log.act, log.ts, A, int(views.case_lo[v]), int(views.case_hi[v]),
-                          int(views.t_lo[v]), int(views.t_hi[v]), views.masks[v])
+        ref = oracle.view_formatted(oprep, A, int(views.case_lo[v]), int(views.case_hi[v]),
+                                    int(views.t_lo[v]), int(views.t_hi[v]), views.masks[v])
         nzc = np.flatnonzero(ref["count"].ravel())
-        r = res[v]
         assert np.array_equal(r["src"].astype(np.int64) * A + r["dst"], nzc), v
         for k in ("count", "dt_sum", "dt_min", "dt_max"):
             assert np.array_equal(r[k], ref[k].ravel()[nzc]), (v, k)
+        assert same_f64(r["dt_mean"], ref["dt_mean"].ravel()[nzc]), v
         for k in ("start_count", "end_count", "act_count"):
             assert np.array_equal(r[k], ref[k]), (v, k)
         assert r["n_events"] == ref["n_events"] and r["n_cases"] == ref["n_cases"], v
+        return ref["n_events"]
+
+    with cf.ThreadPoolExecutor(8) as ex:
+        kept = list(ex.map(check, range(views.n_views)))
+    note(f"4096 views checked: {sum(kept)} kept events")
 
 
 def _u128(lo, hi):
     return [int(a) + (int(b) << 64) for a, b in zip(lo.ravel(), hi.ravel())]
 
 
-def test_full_99M_efg_properties(big):
-    """The eventually-follows graph of the 99M-event log (2.6e9 pairs): total
-    pairs, per-activity row and column counts, and per-activity gap sums,
-    each computed on the host from the formatted log."""
+def test_full_99M_efg(big, big_oracle):
+    """The eventually-follows graph of the 99M-event log (2.6e9 pairs): every
+    cell against the oracle; total pairs, per-activity row and column counts,
+    and per-activity gap sums, each computed on the host from the formatted log."""
     log, prep = big
     A = log.n_activities
     h = pm4g.prepared_to_host(prep)
     e = pm4g.efg_to_host(pm4g.pm4g_efg(prep), A)
+    oe = big_oracle["efg"]
+    for k in ("count", "sum_lo", "sum_hi", "sq_lo", "sq_hi"):
+        assert np.array_equal(e[k], oe[k]), k
+    assert same_f64(e["mean"], oe["mean"]) and same_f64(e["std"], oe["std"])
+    assert e["n_pairs"] == oe["n_pairs"]
     L = log.lengths_by_code.astype(np.int64)
     assert e["status"] == 0 and e["n_pairs"] == int((L * (L - 1) // 2).sum()) == int(e["count"].sum())
     off, act, ts = h["case_off"], h["act_s"], h["ts_s"]
