@@ -9,8 +9,9 @@
 // either the last one (an end) or the source of exactly one pair, so
 //   act_count(y) = start(y) + sum_x count(x, y),  end(x) = act_count(x) - sum_y count(x, y).
 //
-// Pipeline (sizes stay on the device; two host synchronisations read the
-// pair and record totals to check capacities):
+// Pipeline (sizes stay on the device and so do the capacity checks: the call
+// never waits for the device; when a capacity is short, the kernels after the
+// check return at once and the status word and the required sizes say so):
 //   k_view_slice     case range -> event slice [p0, p1) (binary search in the
 //                    case table); a slice always holds whole cases
 //   k_view_tile_scan per-tile counts of overlapping views, offsets
@@ -124,7 +125,8 @@ namespace {
 // written at [8] as u32 by the scan, copied here), [3] temporary cell cursor,
 // [4] total output cells, [6] #views, [7] #pairs, [9] records placed (scan
 // total), [10] nonzero when some case lasts 2^52 time units or more (records
-// then keep the cell in a separate array), [11] (view, bucket) pairs
+// then keep the cell in a separate array), [11] (view, bucket) pairs, [12]
+// the gate after the count walk: 0, or the status that stops the call
 //
 // Record places.  The count walk adds each (tile, view) pair's records per
 // bucket to the (view, bucket) counter with one atomic, whose old value is the
@@ -413,6 +415,7 @@ __global__ __launch_bounds__(kVB) void k_view_count(const int32_t* __restrict__ 
     const int MW = (A + 63) / 64;
     uint64_t* mask = s_mask[wv];
     uint32_t* cur = s_cur[wv];
+    if (w.scal[7] > w.pair_cap) return;   // the tile lists are incomplete: the gate stops the call
     for (int64_t tile = blockIdx.x; tile < w.n_tiles; tile += gridDim.x) {
         const int64_t T0 = tile * TILE;
         const int64_t T1 = (T0 + TILE) < n ? (T0 + TILE) : n;
@@ -426,7 +429,7 @@ __global__ __launch_bounds__(kVB) void k_view_count(const int32_t* __restrict__ 
         const int64_t off = w.toff[tile];
         for (uint32_t j0 = 0; j0 < cnt; j0 += kVW) {   // block-uniform
             const uint32_t j = j0 + wv;
-            const bool has = j < cnt && off + j < w.pair_cap;   // pair overflow: reported by the host
+            const bool has = j < cnt;
             uint32_t v = 0, run = 0, nne = 0;
             if (has) {   // wave-uniform
                 v = w.list[off + j];
@@ -513,6 +516,7 @@ __global__ __launch_bounds__(kVB) void k_view_write(const int32_t* __restrict__ 
     const bool wide = w.scal[10] != 0;
     uint64_t* mask = s_mask[wv];
     uint32_t* cur = s_cur[wv];
+    if (w.scal[12] != 0) return;   // a capacity is short: no record is written
     // tiles interleaved over the grid and so over the XCDs (contiguous per-XCD
     // ranges measured slower here: a tile's work follows the number of views
     // overlapping it, which varies along the log)
@@ -528,7 +532,6 @@ __global__ __launch_bounds__(kVB) void k_view_write(const int32_t* __restrict__ 
         const uint32_t cnt = w.tcount[tile];
         const int64_t off = w.toff[tile];
         for (uint32_t j = wv; j < cnt; j += kVW) {
-            if (off + j >= w.pair_cap) break;   // wave-uniform (the host has checked)
             const uint32_t nd = w.pair_nd[off + j];
             if (nd == 0) continue;   // no kept event
             const uint32_t v = w.list[off + j];
@@ -548,6 +551,18 @@ __global__ __launch_bounds__(kVB) void k_view_write(const int32_t* __restrict__ 
                        w.rec_cell, w.rec_gap, wide);
         }
         __syncthreads();
+    }
+}
+
+// The gate after the count walk: every capacity the later kernels write into
+// is known now; if one is short (or the records exceed 32-bit places) the
+// call stops here, reported by k_view_finish.
+__global__ void k_view_gate(ViewWs w) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int64_t g = 0;
+        if (w.scal[7] > w.pair_cap || w.scal[0] > w.rec_cap || w.scal[1] > w.desc_cap) g = PM4G_E_CAPACITY;
+        if (w.scal[7] <= w.pair_cap && w.scal[0] > (int64_t)0xFFFFFFFF) g = PM4G_E_INVALID;
+        w.scal[12] = g;
     }
 }
 
@@ -622,6 +637,7 @@ __global__ __launch_bounds__(kAB2) void k_view_agg(int32_t A, ViewWs w, BatchedO
     __shared__ int64_t smax[kCellsPerTable];
     __shared__ uint32_t tmp[kAB2 / kWave + 1];
     __shared__ int64_t s_base;
+    if (w.scal[12] != 0) return;
     const int64_t S = w.scal[2];
     const int64_t AA = (int64_t)A * A;
     const int NB = w.n_buckets;
@@ -689,7 +705,7 @@ __global__ __launch_bounds__(kAB2) void k_view_agg(int32_t A, ViewWs w, BatchedO
 
 __global__ void k_view_copy(int32_t A, ViewWs w, BatchedOutDev out) {
     const int64_t S = w.scal[2];
-    const bool fits = w.scal[4] <= out.cap_edges && w.scal[3] <= w.cell_cap;
+    const bool fits = w.scal[12] == 0 && w.scal[4] <= out.cap_edges && w.scal[3] <= w.cell_cap;
     if (!fits) return;
     const int wv = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int nw = gridDim.x * blockDim.x / kWave;
@@ -720,7 +736,7 @@ __global__ __launch_bounds__(256) void k_view_acts(int32_t V, int32_t A, ViewWs 
     __shared__ int64_t red[2][256 / kWave];
     const int64_t S = w.scal[2];
     const uint32_t NB = (uint32_t)w.n_buckets;
-    if (w.scal[3] > w.cell_cap) return;   // temporary cells were not all written
+    if (w.scal[12] != 0 || w.scal[3] > w.cell_cap) return;   // temporary cells were not all written
     for (int64_t v = blockIdx.x; v < V; v += gridDim.x) {
         for (int a = threadIdx.x; a < A; a += 256) rows[a] = cols[a] = 0;
         __syncthreads();
@@ -774,13 +790,16 @@ __global__ __launch_bounds__(256) void k_view_acts(int32_t V, int32_t A, ViewWs 
 
 __global__ void k_view_finish(int32_t V, ViewWs w, BatchedOutDev out) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        out.edge_off[V] = w.scal[4];
-        out.required[0] = w.scal[4];
-        out.required[1] = w.scal[0];
-        out.required[2] = w.scal[1];
+        const int64_t gate = w.scal[12];
+        const bool pairs_short = w.scal[7] > w.pair_cap;   // then the count walk did not run
+        out.edge_off[V] = gate ? 0 : w.scal[4];
+        out.required[0] = gate ? 0 : w.scal[4];             // unknown until the records are placed
+        out.required[1] = pairs_short ? 0 : w.scal[0];
+        out.required[2] = pairs_short ? 0 : w.scal[1];
         out.required[3] = w.scal[7];
-        out.required[4] = w.scal[3];
-        if (w.scal[4] > out.cap_edges || w.scal[3] > w.cell_cap) set_status(out.status, PM4G_E_CAPACITY);
+        out.required[4] = gate ? 0 : w.scal[3];
+        if (gate) set_status(out.status, (int32_t)gate);
+        else if (w.scal[4] > out.cap_edges || w.scal[3] > w.cell_cap) set_status(out.status, PM4G_E_CAPACITY);
     }
 }
 
@@ -834,6 +853,7 @@ hipError_t launch_views_reduce(const pm4g_prepared* p, const pm4g_view* views, c
     const int32_t A = p->n_activities;
     {
         ProfScope ps(P_VIEW_PLACE, s);
+        k_view_gate<<<1, 64, 0, s>>>(w);
         k_view_vb_flags<<<1024, 256, 0, s>>>(w, V);
         dev::excl_scan<int64_t>(w.vb_cnt, &w.scal[11], w.vb_base, w.part64, &w.scal[9], s);
         dev::excl_scan<uint32_t>(w.vb_flag, &w.scal[11], w.vb_seg, w.part32, (uint32_t*)&w.scal[8], s);

@@ -1,5 +1,7 @@
 """GPU parity of the batched drill-down views against the oracle's view
 function (filter, then re-discover), view by view, bit-exact."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -142,3 +144,61 @@ def test_views_record_layouts(span):
     note(f"views: record layouts, longest case {span}")
     res = check_views(log, views)
     assert int(res[0]["dt_max"].max()) == span
+
+
+def test_batched_call_does_not_wait_and_reports_capacity_on_the_device():
+    """The C call enqueues and returns while earlier work on its stream is still
+    running (a bounded spin kernel queued first); a short record capacity then
+    shows up in the device status word with the required sizes, and a second
+    call with those sizes gives the oracle's tables."""
+    log = synth.config_log(3, 0.002)
+    A = log.n_activities
+    c, a, t = cols(log.case, log.act, log.ts)
+    prep = pm4g.pm4g_prepare(c, a, t, A)
+    views = synth.make_views(log, 12, seed=5, min_events=100, max_events=50_000)
+    vd, md = pm4g.views_to_device(views, "cuda:0")
+    V = views.n_views
+    L = pm4g.load()
+    s = torch.cuda.Stream()
+    tun = pm4g.BatchedTuning(record_capacity=64)
+    need = int(L.pm4g_batched_workspace_bytes(prep.n_events, A, V, ctypes.byref(tun)))
+    with torch.cuda.stream(s):
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda:0")
+        o = pm4g._batched_out(V, A, 1 << 20, "cuda:0")
+    s.synchronize()
+    with torch.cuda.stream(s):
+        torch.cuda._sleep(300_000_000)           # about 0.15 s on the stream, bounded
+    p = prep._struct()
+    st = pm4g._batched_struct(o)
+    rc = L.pm4g_dfg_batched(ctypes.byref(p), pm4g._ptr(vd), pm4g._ptr(md), V, ctypes.byref(st),
+                            ctypes.byref(tun), pm4g._ptr(ws), need, ctypes.c_void_p(s.cuda_stream))
+    assert rc == 0
+    assert not s.query(), "the call waited for its stream"
+    s.synchronize()
+    assert int(o["status"].item()) == pm4g.PM4G_E_CAPACITY
+    req = o["required"].cpu().numpy()
+    assert req[1] > 64 and req[3] > 0
+    tun.record_capacity = int(req[1])
+    tun.descriptor_capacity = max(int(req[2]), 1)
+    for _ in range(3):   # the cell counts become known once the records fit
+        need = int(L.pm4g_batched_workspace_bytes(prep.n_events, A, V, ctypes.byref(tun)))
+        with torch.cuda.stream(s):
+            ws = torch.empty(need, dtype=torch.uint8, device="cuda:0")
+        rc = L.pm4g_dfg_batched(ctypes.byref(p), pm4g._ptr(vd), pm4g._ptr(md), V, ctypes.byref(st),
+                                ctypes.byref(tun), pm4g._ptr(ws), need, ctypes.c_void_p(s.cuda_stream))
+        assert rc == 0
+        s.synchronize()
+        if int(o["status"].item()) == 0:
+            break
+        req = o["required"].cpu().numpy()
+        assert int(o["status"].item()) == pm4g.PM4G_E_CAPACITY and req[0] <= (1 << 20) and req[4] > 0
+        tun.cell_capacity = int(req[4])
+    assert int(o["status"].item()) == 0
+    res = pm4g.batched_to_host(o, V, A)
+    for v in range(V):
+        ref = oracle.view(log.case, log.act, log.ts, A, int(views.case_lo[v]), int(views.case_hi[v]),
+                          int(views.t_lo[v]), int(views.t_hi[v]), views.masks[v])
+        sp = dense_to_sparse(ref, A)
+        for k in ("src", "dst", "count", "dt_sum", "dt_min", "dt_max"):
+            assert np.array_equal(res[v][k], sp[k]), (v, k)
+        assert res[v]["n_events"] == ref["n_events"], v
