@@ -174,30 +174,121 @@ def measured_traffic(stage: str, workload: str) -> float | None:
         return None
 
 
-def cpu_baseline(log, target_events: int) -> dict:
-    """The oracle as it stands, single-threaded, on a bounded sample of the same log.
+def _sample_cases(log, target_events: int):
+    """Every event of the cases whose code is below a cut-off (codes are a
+    random permutation, so it is a random subset of whole cases)."""
+    import numpy as np
 
-    The sample is every event of the cases whose code is below a cut-off;
-    codes are a random permutation, so it is a random subset of whole cases.
-    """
+    C = int(log.lengths_by_code.shape[0])
+    cum = np.cumsum(log.lengths_by_code)
+    cut = min(int(np.searchsorted(cum, target_events, side="left")) + 1, C)
+    keep = log.case < cut
+    return cut, log.case[keep], log.act[keep], log.ts[keep]
+
+
+def host_threads() -> int:
+    """Host threads for the all-cores oracle row: the CPUs this process may run
+    on, at most 16 (a GPU's share of its host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def oracle_all_cores(case, act, ts, A: int, threads: int) -> dict:
+    """The oracle's DFG and variants of a log, computed on `threads` host
+    threads: the cases are split into `threads` groups by case id (the
+    directly-follows relation never crosses cases), each group runs the
+    oracle's own functions (its C code releases the interpreter lock), and the
+    groups' results are merged: cell counts and gap sums add (sums modulo
+    2^64), minima and maxima combine, activity counts add; variants merge by
+    exact sequence, counts add, the representative is the smallest, then the
+    (count desc, representative asc) order."""
+    import concurrent.futures as cf
+
     import numpy as np
 
     import oracle
 
-    C = int(log.lengths_by_code.shape[0])
-    cum = np.cumsum(log.lengths_by_code)
-    cut = int(np.searchsorted(cum, target_events, side="left")) + 1
-    cut = min(cut, C)
-    keep = log.case < cut
-    case, act, ts = log.case[keep], log.act[keep], log.ts[keep]
+    lo, hi = int(case.min()), int(case.max()) + 1
+    edges = np.linspace(lo, hi, threads + 1).astype(np.int64)
+    part = np.clip(np.searchsorted(edges, case, side="right") - 1, 0, threads - 1)
+    order = np.argsort(part, kind="stable")
+    bounds = np.searchsorted(part[order], np.arange(threads + 1))
+    groups = [order[bounds[g]:bounds[g + 1]] for g in range(threads)]
+
+    def run(idx):
+        c, a, t = case[idx], act[idx], ts[idx]
+        return oracle.dfg(c, a, t, A), oracle.variants(c, a, t, A)
+
+    with cf.ThreadPoolExecutor(threads) as ex:
+        parts = list(ex.map(run, groups))
+    d = {k: parts[0][0][k].copy() for k in ("count", "dt_sum", "dt_min", "dt_max", "start_count", "end_count",
+                                             "act_count")}
+    for pd, _ in parts[1:]:
+        for k in ("count", "dt_sum", "start_count", "end_count", "act_count"):
+            d[k] += pd[k]
+        np.minimum(d["dt_min"], pd["dt_min"], out=d["dt_min"])
+        np.maximum(d["dt_max"], pd["dt_max"], out=d["dt_max"])
+    with np.errstate(invalid="ignore", divide="ignore"):
+        d["dt_mean"] = np.where(d["count"] > 0, d["dt_sum"].astype(np.float64) / d["count"].astype(np.float64),
+                                np.nan)
+    d["n_cases"] = sum(pd["n_cases"] for pd, _ in parts)
+    classes: dict = {}
+    for _, pv in parts:
+        off, acts = pv["var_off"], pv["var_acts"]
+        for v in range(pv["n_variants"]):
+            key = acts[off[v]:off[v + 1]].tobytes()
+            n, rep = int(pv["var_count"][v]), int(pv["var_rep"][v])
+            if key in classes:
+                m, r = classes[key]
+                classes[key] = (m + n, min(r, rep))
+            else:
+                classes[key] = (n, rep)
+    ranked = sorted(classes.items(), key=lambda kv: (-kv[1][0], kv[1][1]))
+    var = dict(n_variants=len(ranked), var_count=np.array([c for _, (c, _) in ranked], np.int64),
+               var_rep=np.array([r for _, (_, r) in ranked], np.int64))
+    return dict(dfg=d, variants=var)
+
+
+def cpu_baseline(log, target_events: int) -> dict:
+    """The oracle as it stands on a bounded sample of the same log: one host
+    thread (the reported value), and all host threads (split by case, merged)."""
+    import platform
+
+    import oracle
+
+    cut, case, act, ts = _sample_cases(log, target_events)
     A = log.n_activities
     t0 = time.perf_counter()
     oracle.dfg(case, act, ts, A)
     oracle.variants(case, act, ts, A)
     dt = time.perf_counter() - t0
+    threads = host_threads()
+    t1 = time.perf_counter()
+    oracle_all_cores(case, act, ts, A, threads)
+    dt_all = time.perf_counter() - t1
     return {"value": case.size / dt, "unit": "events/s", "cores": 1, "kind": "oracle",
             "sample": f"the {cut} cases with the lowest codes of the benchmark log ({case.size} events, "
-                      f"rows in log order): DFG + variants, single thread, {dt:.2f} s"}
+                      f"rows in log order): DFG + variants, single thread, {dt:.2f} s",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(), "machine": platform.machine(),
+            "all_cores": {"value": case.size / dt_all, "unit": "events/s", "cores": threads,
+                          "how": "the oracle's DFG and variants on the sample's cases split into one group "
+                                 "per host thread by case id, merged (counts and sums added, min/max "
+                                 f"combined, variants merged by exact sequence); {dt_all:.2f} s"}}
+
+
+def cpu_model() -> str | None:
+    """The host CPU's model name (as lscpu prints it)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int, autotune: bool = True) -> dict:
@@ -475,33 +566,96 @@ def bench_ingest(log, steps: int = 3) -> dict:
 
 
 def bench_serving(logs: dict, preps: dict, seconds: float, rate: float, workers: int = 4,
-                  batch_work: int = 20_000_000) -> dict:
-    """Open-loop Poisson mix of DFG / variants / filter queries on resident logs."""
+                  batch_work: int = 20_000_000, warmup_s: float = 5.0, stress_budget: int = 4 << 30,
+                  side_seconds: float = 15.0) -> dict:
+    """Open-loop Poisson mix of DFG / variants / filter queries on resident logs.
+
+    A warm-up run of its own (warmup_s of arrivals, not reported), then the
+    main run (`seconds` of arrivals, memory budget: 90 % of the HBM left free
+    by the resident logs).  On the first side_seconds of the same arrivals: a
+    stress run with a stress_budget-byte budget, where admission queues, and
+    the one-request-per-launch baselines with 1 and with `workers` streams;
+    the main run's figures over the same requests stand beside them."""
     import copy
 
     import numpy as np
+    import torch
 
     from paper_2204_04898_amd import serve
 
     info = {k: serve.log_info(v) for k, v in logs.items()}
     A_of = {k: v.n_activities for k, v in logs.items()}
     reqs = serve.poisson_requests(np.random.default_rng(220404898 + 5), rate, seconds, info, A_of)
+    warm = serve.poisson_requests(np.random.default_rng(220404898 + 6), rate, warmup_s, info, A_of)
     ex = serve.GpuExecutor(preps)
-    free, _total = __import__("torch").cuda.mem_get_info()
-    budget = int(free * 0.5)
-    # warm the executor's workspaces
-    serve.Scheduler(ex, budget, max_batch=64, workers=workers).run(copy.deepcopy(reqs[:16]))
+    torch.cuda.synchronize()
+    free, _total = torch.cuda.mem_get_info()
+    budget = int(free * 0.9)
+    log_progress(f"serving: warm-up, {len(warm)} requests over {warmup_s} s")
+    serve.Scheduler(ex, budget, max_batch=64, workers=workers, max_batch_work=batch_work).run(warm)
+    log_progress(f"serving: main run, {len(reqs)} requests over {seconds} s")
     sch = serve.Scheduler(ex, budget, max_batch=64, workers=workers, max_batch_work=batch_work)
     res = sch.run(copy.deepcopy(reqs), progress=log_progress)
-    st = serve.latency_stats(res)
-    st.update(offered_qps=rate, seconds=seconds, n_requests=len(reqs), batches=len(sch.batches),
-              workers=workers, max_batch_work=batch_work,
-              variants_answer=f"variant count + first {ex.variants_top} variants")
-    log_progress("serving: one request per launch")
-    base = serve.Scheduler(ex, budget, max_batch=1, workers=1)
-    bres = base.run(copy.deepcopy(reqs), progress=log_progress)
-    st["one_request_per_launch"] = serve.latency_stats(bres)
+    st = serve.latency_stats(res, sch)
+    st.update(offered_qps=rate, seconds=seconds, warmup_seconds=warmup_s, n_requests=len(reqs),
+              max_batch_work=batch_work, budget="90% of the HBM free after the logs are resident",
+              variants_answer=f"variant count + first {ex.variants_top} variants",
+              admission="per-request estimate = the library's workspace-size query for the request's "
+                        "capacities + the outputs it allocates")
+    side = [r for r in reqs if r.arrival < side_seconds]
+    ids = {r.rid for r in side}
+    st["main_run_first_part"] = dict(serve.latency_stats([r for r in res if r.rid in ids]),
+                                     seconds=side_seconds, workers=workers, max_batch=64)
+    log_progress(f"serving: stress run, {stress_budget >> 20} MiB budget, {len(side)} requests")
+    stress = serve.Scheduler(ex, stress_budget, max_batch=64, workers=workers, max_batch_work=batch_work)
+    sres = stress.run(copy.deepcopy(side), progress=log_progress)
+    st["stress_budget"] = dict(serve.latency_stats(sres, stress), seconds=side_seconds,
+                               budget_mib=stress_budget >> 20)
+    for nw in sorted({1, workers}):
+        log_progress(f"serving: one request per launch, {nw} stream(s)")
+        base = serve.Scheduler(ex, budget, max_batch=1, workers=nw)
+        bres = base.run(copy.deepcopy(side), progress=log_progress)
+        st[f"one_request_per_launch_{nw}_streams"] = dict(serve.latency_stats(bres, base), seconds=side_seconds,
+                                                         workers=nw, max_batch=1)
     return st
+
+
+def kernel_overlap(trace_csv: str) -> dict:
+    """From a rocprofv3 --kernel-trace CSV: the library's kernels grouped by the
+    stream (queue) they ran on, and the share of their busy time during which
+    kernels of two or more streams ran at once."""
+    import csv
+
+    spans = []
+    with open(trace_csv) as fh:
+        for row in csv.DictReader(fh):
+            name = row.get("Kernel_Name", "")
+            if "pm4g::" not in name:
+                continue
+            q = row.get("Stream_Id") or row.get("Queue_Id") or "0"
+            spans.append((int(row["Start_Timestamp"]), int(row["End_Timestamp"]), q))
+    if not spans:
+        raise SystemExit("no library kernels in the trace")
+    ev = []
+    for a, b, q in spans:
+        ev.append((a, 1, q))
+        ev.append((b, -1, q))
+    ev.sort(key=lambda e: (e[0], e[1]))
+    active: dict = {}
+    busy = multi = 0
+    last = ev[0][0]
+    for t, d, q in ev:
+        if active:
+            busy += t - last
+            if len(active) >= 2:
+                multi += t - last
+        last = t
+        active[q] = active.get(q, 0) + d
+        if active[q] == 0:
+            del active[q]
+    streams = sorted({q for _, _, q in spans})
+    return {"kernels": len(spans), "streams": len(streams), "busy_ms": busy / 1e6,
+            "multi_stream_ms": multi / 1e6, "overlap_frac": multi / busy if busy else 0.0}
 
 
 def calibrate_copy(gib: float = 1.0, reps: int = 3) -> None:
@@ -591,6 +745,11 @@ def main() -> int:
     if "--calibrate-copy" in sys.argv:
         calibrate_copy()
         return 0
+    if "--overlap-from" in sys.argv:
+        sp = argparse.ArgumentParser()
+        sp.add_argument("--overlap-from", required=True)
+        print(json.dumps(kernel_overlap(sp.parse_args().overlap_from)))
+        return 0
     if "--summarize-counters" in sys.argv:
         sp = argparse.ArgumentParser()
         sp.add_argument("--summarize-counters", action="store_true")
@@ -617,7 +776,14 @@ def main() -> int:
     ap.add_argument("--no-cases", action="store_true", help="skip the cases-dataframe and case-filter timing")
     ap.add_argument("--no-efg", action="store_true", help="skip the eventually-follows graph timing")
     ap.add_argument("--no-ingest", action="store_true", help="skip the CSV ingestion timing")
-    ap.add_argument("--serve-seconds", type=float, default=8.0, help="serving run length (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="serving run length (0: skip)")
+    ap.add_argument("--serve-warmup", type=float, default=5.0, help="serving warm-up run length")
+    ap.add_argument("--serve-side-seconds", type=float, default=15.0,
+                    help="arrivals replayed by the stress run and the one-request-per-launch baselines")
+    ap.add_argument("--serve-stress-mib", type=int, default=4096, help="memory budget of the stress run")
+    ap.add_argument("--serve-only", action="store_true", help="only the serving runs (for a kernel trace)")
+    ap.add_argument("--overlap-from", default=None,
+                    help="print the multi-stream overlap of a rocprofv3 kernel-trace CSV and exit")
     ap.add_argument("--serve-qps", type=float, default=200.0)
     ap.add_argument("--serve-workers", type=int, default=4, help="batches in flight (HIP streams)")
     ap.add_argument("--serve-batch-work", type=int, default=20_000_000,
@@ -647,6 +813,19 @@ def main() -> int:
     prep = pm4g.Prepared.empty(N, A, dev)
     dout = pm4g._dfg_out(A, dev)
     vout = pm4g._var_out(N, dev)
+    if args.serve_only:
+        if k != 3:
+            raise SystemExit("--serve-only serves the 99M- and 10M-event logs (the default workload)")
+        pm4g.pm4g_prepare(c, a, t, A, out=prep)
+        log2 = synth.config_log(2)
+        c2, a2, t2 = (torch.from_numpy(x).to(dev) for x in (log2.case, log2.act, log2.ts))
+        prep2 = pm4g.pm4g_prepare(c2, a2, t2, log2.n_activities)
+        del c, a, t, c2, a2, t2, vout
+        st = bench_serving({"dfg-perf-10M": log2, args.workload: log}, {"dfg-perf-10M": prep2, args.workload: prep},
+                           args.serve_seconds, args.serve_qps, args.serve_workers, args.serve_batch_work,
+                           args.serve_warmup, args.serve_stress_mib << 20, args.serve_side_seconds)
+        print(json.dumps({"serving": st}), flush=True)
+        return 0
 
     def step():
         pm4g.pm4g_prepare(c, a, t, A, presorted=log.presorted, out=prep)
@@ -774,7 +953,8 @@ def main() -> int:
         out["serving"] = bench_serving({"dfg-perf-10M": log2, args.workload: log},
                                        {"dfg-perf-10M": prep2, args.workload: prep},
                                        args.serve_seconds, args.serve_qps, args.serve_workers,
-                                       args.serve_batch_work)
+                                       args.serve_batch_work, args.serve_warmup, args.serve_stress_mib << 20,
+                                       args.serve_side_seconds)
     if not args.no_cpu_baseline:
         log_progress("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(log, args.cpu_sample_events)

@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
+import functools
 import os
 import threading
 
@@ -45,7 +46,7 @@ class _Log(ctypes.Structure):
 class _Prepared(ctypes.Structure):
     _fields_ = [("case_s", _P), ("act_s", _P), ("ts_s", _P), ("case_off", _P), ("case_code", _P),
                 ("n_cases", _P), ("status", _P), ("n_events", ctypes.c_int64),
-                ("n_activities", ctypes.c_int32)]
+                ("n_activities", ctypes.c_int32), ("row", _P)]
 
 
 class _DfgOut(ctypes.Structure):
@@ -206,6 +207,22 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _on_stream(fn):
+    """Runs a wrapper with its `stream` argument as torch's current stream, so
+    that every tensor it allocates (outputs, workspaces) belongs to the stream
+    its kernels run on: the caching allocator then never hands that memory to
+    work queued on another stream while the kernels may still use it."""
+
+    @functools.wraps(fn)
+    def wrapped(*args, stream=None, **kw):
+        if stream is None:
+            return fn(*args, **kw)
+        with torch.cuda.stream(stream):
+            return fn(*args, stream=stream, **kw)
+
+    return wrapped
+
+
 # One growing workspace per (device, stream): keeps allocation out of repeated calls.
 _ws_cache: dict = {}
 
@@ -248,6 +265,7 @@ class Prepared:
     n_cases: torch.Tensor     # int64 [1]
     status: torch.Tensor      # int32 [1]
     n_activities: int
+    row: torch.Tensor | None = None   # int32 [n]: raw row of each position (pm4g_prepare with rows)
 
     @property
     def n_events(self) -> int:
@@ -256,10 +274,10 @@ class Prepared:
     def _struct(self) -> _Prepared:
         return _Prepared(_ptr(self.case_s), _ptr(self.act_s), _ptr(self.ts_s), _ptr(self.case_off),
                          _ptr(self.case_code), _ptr(self.n_cases), _ptr(self.status), self.n_events,
-                         self.n_activities)
+                         self.n_activities, _ptr(self.row))
 
     @staticmethod
-    def empty(n: int, A: int, device) -> "Prepared":
+    def empty(n: int, A: int, device, rows: bool = False) -> "Prepared":
         m = max(n, 1)
         return Prepared(case_s=torch.empty(n, dtype=torch.int32, device=device),
                         act_s=torch.empty(n, dtype=torch.int32, device=device),
@@ -267,15 +285,18 @@ class Prepared:
                         case_off=torch.empty(m + 1, dtype=torch.int64, device=device),
                         case_code=torch.empty(m, dtype=torch.int32, device=device),
                         n_cases=torch.zeros(1, dtype=torch.int64, device=device),
-                        status=torch.zeros(1, dtype=torch.int32, device=device), n_activities=A)
+                        status=torch.zeros(1, dtype=torch.int32, device=device), n_activities=A,
+                        row=torch.empty(n, dtype=torch.int32, device=device) if rows else None)
 
 
+@_on_stream
 def pm4g_prepare(case, act, ts, A: int, presorted: bool = False, out: Prepared | None = None,
-                 stream=None) -> Prepared:
-    """Formats a raw log on the GPU (order, per-case table).  Synchronises the stream."""
+                 rows: bool = False, stream=None) -> Prepared:
+    """Formats a raw log on the GPU (order, per-case table; with `rows`, also
+    the raw row of each position).  Synchronises the stream."""
     log = _log(case, act, ts, A, presorted)
     if out is None:
-        out = Prepared.empty(case.numel(), A, case.device)
+        out = Prepared.empty(case.numel(), A, case.device, rows=rows)
     ws, need = workspace(OP_PREPARE, case.numel(), A, case.device, stream)
     p = out._struct()
     _check(load().pm4g_prepare(ctypes.byref(log), ctypes.byref(p), _ptr(ws), need, _stream(stream)))
@@ -304,6 +325,7 @@ def _dfg_struct(o: dict) -> _DfgOut:
                                                "overflow", "status")])
 
 
+@_on_stream
 def pm4g_dfg(case, act, ts, A: int, presorted: bool = False, out: dict | None = None,
              stream=None) -> dict:
     """DFG of a raw log (formats it in the workspace first).  Synchronises once or twice."""
@@ -315,6 +337,7 @@ def pm4g_dfg(case, act, ts, A: int, presorted: bool = False, out: dict | None = 
     return o
 
 
+@_on_stream
 def pm4g_dfg_prepared(prep: Prepared, out: dict | None = None, stream=None) -> dict:
     """DFG of a prepared log.  Asynchronous on the stream."""
     o = out if out is not None else _dfg_out(prep.n_activities, prep.case_s.device)
@@ -328,6 +351,7 @@ def pm4g_dfg_prepared(prep: Prepared, out: dict | None = None, stream=None) -> d
 PM4G_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 
+@_on_stream
 def pm4g_dfg_prepared_noalloc(prep: Prepared, out: dict, stream=None) -> dict:
     """DFG of a prepared log into caller-allocated outputs, with the workspace
     in the library's own per-GPU scratch array: the C call allocates nothing.
@@ -355,6 +379,7 @@ def _var_struct(o: dict) -> _VarOut:
                                                "var_off", "var_acts", "case_variant", "status")])
 
 
+@_on_stream
 def pm4g_variants(case, act, ts, A: int, presorted: bool = False, out: dict | None = None,
                   stream=None) -> dict:
     """Trace variants of a raw log.  Synchronises once or twice."""
@@ -366,14 +391,54 @@ def pm4g_variants(case, act, ts, A: int, presorted: bool = False, out: dict | No
     return o
 
 
-def pm4g_variants_prepared(prep: Prepared, out: dict | None = None, stream=None) -> dict:
-    """Trace variants of a prepared log.  Asynchronous on the stream."""
+@_on_stream
+def pm4g_variants_prepared(prep: Prepared, out: dict | None = None, ws: torch.Tensor | None = None,
+                           stream=None) -> dict:
+    """Trace variants of a prepared log.  Asynchronous on the stream.  `ws`: a
+    workspace of at least variants_workspace_bytes(...) bytes (default: the
+    binding's growing per-stream workspace)."""
     o = out if out is not None else _var_out(prep.n_events, prep.case_s.device)
-    ws, need = workspace(OP_VARIANTS_PREPARED, prep.n_events, prep.n_activities, prep.case_s.device, stream)
+    need = variants_workspace_bytes(prep.n_events, prep.n_activities)
+    if ws is None or ws.numel() < need:
+        ws, need = workspace(OP_VARIANTS_PREPARED, prep.n_events, prep.n_activities, prep.case_s.device, stream)
     p = prep._struct()
     s = _var_struct(o)
     _check(load().pm4g_variants_prepared(ctypes.byref(p), ctypes.byref(s), _ptr(ws), need, _stream(stream)))
     return o
+
+
+def variants_workspace_bytes(n_events: int, A: int) -> int:
+    """Workspace bytes of pm4g_variants_prepared on a prepared log of n_events."""
+    return int(load().pm4g_workspace_bytes(OP_VARIANTS_PREPARED, int(n_events), int(A), 0))
+
+
+def batched_workspace_bytes(n_events: int, A: int, n_views: int, tuning: "BatchedTuning | None" = None) -> int:
+    """Workspace bytes of pm4g_dfg_batched (0: invalid sizes or tuning)."""
+    return int(load().pm4g_batched_workspace_bytes(int(n_events), int(A), int(n_views),
+                                                   ctypes.byref(tuning) if tuning is not None else None))
+
+
+def filter_workspace_bytes(n_events: int) -> int:
+    """Workspace bytes of pm4g_filter_view / pm4g_filter_df_events on a log of n_events."""
+    return int(load().pm4g_filter_workspace_bytes(int(n_events)))
+
+
+def batched_out_bytes(n_views: int, A: int, cap_edges: int) -> int:
+    """Device bytes of the outputs _batched_out allocates."""
+    cap = max(int(cap_edges), 1)
+    return 8 * (n_views + 1) + cap * (4 + 4 + 8 * 5) + 3 * 8 * max(n_views * A, 1) + 2 * 8 * max(n_views, 1) + 44
+
+
+def prepared_bytes(n: int, rows: bool = False) -> int:
+    """Device bytes of Prepared.empty(n, ...)."""
+    m = max(int(n), 1)
+    return int(n) * (4 + 4 + 8 + (4 if rows else 0)) + 8 * (m + 1) + 4 * m + 12
+
+
+def variants_out_bytes(n: int, with_cases: bool = True) -> int:
+    """Device bytes of the variants outputs sized for n events."""
+    m = max(int(n), 1)
+    return 8 + m * (8 + 4 + 4 + 4 + (4 if with_cases else 0)) + 8 * (m + 1) + 4
 
 
 PM4G_BATCHED_MAX_ACTIVITIES = 1024
@@ -412,31 +477,33 @@ def _batched_struct(o: dict) -> _BatchedOut:
                        o["cap_edges"], _ptr(o["required"]), _ptr(o["status"]))
 
 
+@_on_stream
 def pm4g_dfg_batched(prep: Prepared, views: torch.Tensor, masks: torch.Tensor, n_views: int,
                      tuning: BatchedTuning | None = None, cap_edges: int | None = None,
-                     out: dict | None = None, stream=None, retry: bool = True) -> dict:
+                     out: dict | None = None, stream=None, retry: bool = True,
+                     keep_workspace: bool = True) -> dict:
     """DFGs of n_views drill-down views in one pass (Sec. 1 drill-down, Sec. 3 filters).
 
     views: device uint8 tensor of n_views packed pm4g_view records; masks: device
     int64 tensor [n_views, ceil(A/64)].  With no `tuning`, the launch shape
-    comes from the autotune cache (tune.py).  Synchronises the stream.  With `retry`,
-    capacities found too small are raised to what the call reported and the
-    call is repeated.
+    comes from the autotune cache (tune.py).  The library call does not wait;
+    this wrapper synchronises the stream once to read the device status.  With
+    `retry`, capacities found too small are raised to what the call reported
+    and the call is repeated.  keep_workspace=False allocates the workspace for
+    this call only (on the stream) instead of growing the per-stream one.
     """
     L = load()
     A = prep.n_activities
     dev = prep.case_s.device
-    if tuning is None:
-        # launch shape from the autotune cache (capacities are sized below)
+    t = BatchedTuning() if tuning is None else BatchedTuning.from_buffer_copy(tuning)
+    if t.tile_events == 0 and t.emit_blocks == 0 and t.agg_blocks == 0:
+        # launch shape from the autotune cache (capacities: the tuning's or the library's)
         from . import tune
-        t = BatchedTuning()
         hit = tune.default_cache().lookup(A, n_views, prep.n_events)
         if hit is not None:
             t.tile_events = int(hit["tile_events"])
             t.emit_blocks = int(hit["emit_blocks"])
             t.agg_blocks = int(hit["agg_blocks"])
-    else:
-        t = BatchedTuning.from_buffer_copy(tuning)
     # output cells: at most A*A per view and one per kept event
     cap = int(cap_edges) if cap_edges is not None else \
         max(1024, min(int(n_views) * A * A, prep.n_events, 1 << 24))
@@ -445,7 +512,7 @@ def pm4g_dfg_batched(prep: Prepared, views: torch.Tensor, masks: torch.Tensor, n
         need = int(L.pm4g_batched_workspace_bytes(prep.n_events, A, n_views, ctypes.byref(t)))
         if need == 0:
             raise Pm4gError(PM4G_E_INVALID, "invalid sizes or tuning for the batched workspace")
-        ws = _batched_ws(dev, need, stream)
+        ws = _batched_ws(dev, need, stream) if keep_workspace else torch.empty(need, dtype=torch.uint8, device=dev)
         p = prep._struct()
         s = _batched_struct(o)
         rc = L.pm4g_dfg_batched(ctypes.byref(p), _ptr(views), _ptr(masks), int(n_views), ctypes.byref(s),
@@ -474,6 +541,7 @@ def pm4g_dfg_batched(prep: Prepared, views: torch.Tensor, masks: torch.Tensor, n
     raise Pm4gError(PM4G_E_CAPACITY, "capacities still short after retries")
 
 
+@_on_stream
 def pm4g_filter_view(prep: Prepared, view: torch.Tensor, mask: torch.Tensor, out: Prepared | None = None,
                      ws: torch.Tensor | None = None, stream=None) -> Prepared:
     """The kept events of one view as a prepared log (device record `view`, device `mask` words).
@@ -493,6 +561,7 @@ def pm4g_filter_view(prep: Prepared, view: torch.Tensor, mask: torch.Tensor, out
     return o
 
 
+@_on_stream
 def pm4g_filter_df_events(prep: Prepared, pair_mask: torch.Tensor, side: int = 0, keep: bool = True,
                           out: Prepared | None = None, ws: torch.Tensor | None = None, stream=None) -> Prepared:
     """Events kept by the directly-follows-level filter, as a prepared log.
@@ -513,6 +582,7 @@ def pm4g_filter_df_events(prep: Prepared, pair_mask: torch.Tensor, side: int = 0
     return o
 
 
+@_on_stream
 def pm4g_sample(prep: Prepared, k: int, seed: int, by_events: bool = False, out: Prepared | None = None,
                 ws: torch.Tensor | None = None, stream=None) -> Prepared:
     """A sample of k cases (whole) or k events of a prepared log, as a
@@ -530,6 +600,7 @@ def pm4g_sample(prep: Prepared, k: int, seed: int, by_events: bool = False, out:
     return o
 
 
+@_on_stream
 def pm4g_ingest_csv(text: torch.Tensor, case_col: int, act_col: int, ts_col: int, sep: bytes = b",",
                     has_header: bool = True, ts_iso: bool = False, ts_scale: int = 3, capacity: int | None = None,
                     stream=None) -> dict:
@@ -569,6 +640,7 @@ def pm4g_ingest_csv(text: torch.Tensor, case_col: int, act_col: int, ts_col: int
 PM4G_EFG_MAX_ACTIVITIES = 4096
 
 
+@_on_stream
 def pm4g_efg(prep: Prepared, out: dict | None = None, ws: torch.Tensor | None = None, stream=None) -> dict:
     """Eventually-follows graph and temporal profile of a prepared log: device
     [A*A] count (int64), sum_lo/sum_hi and sq_lo/sq_hi (exact gap sums as
@@ -614,6 +686,7 @@ def efg_to_host(o: dict, A: int) -> dict:
 I64_MIN, I64_MAX = -(1 << 63), (1 << 63) - 1
 
 
+@_on_stream
 def pm4g_cases(prep: Prepared, stream=None) -> dict:
     """Cases dataframe: per case (case-table order) its events and throughput time.
 
@@ -628,6 +701,7 @@ def pm4g_cases(prep: Prepared, stream=None) -> dict:
     return o
 
 
+@_on_stream
 def pm4g_filter_cases(prep: Prepared, min_events: int = 0, max_events: int = I64_MAX,
                       min_throughput: int = I64_MIN, max_throughput: int = I64_MAX,
                       act_mask: torch.Tensor | None = None, path_mask: torch.Tensor | None = None,
@@ -747,6 +821,9 @@ def variants_to_host(o: dict, n_cases: int | None = None, top: int | None = None
 
 def prepared_to_host(p: Prepared) -> dict:
     C = int(p.n_cases.item())
-    return dict(case_s=p.case_s.cpu().numpy(), act_s=p.act_s.cpu().numpy(), ts_s=p.ts_s.cpu().numpy(),
-                case_off=p.case_off[:C + 1].cpu().numpy(), case_code=p.case_code[:C].cpu().numpy(),
-                n_cases=C, status=int(p.status.item()))
+    h = dict(case_s=p.case_s.cpu().numpy(), act_s=p.act_s.cpu().numpy(), ts_s=p.ts_s.cpu().numpy(),
+             case_off=p.case_off[:C + 1].cpu().numpy(), case_code=p.case_code[:C].cpu().numpy(),
+             n_cases=C, status=int(p.status.item()))
+    if p.row is not None:
+        h["row"] = p.row.cpu().numpy()
+    return h

@@ -8,10 +8,12 @@ done once) stay on the GPU.
 Scheduling (host side, independent of the executor):
   - requests carry a scheduled arrival time (open loop); latency is measured
     from it, not from dispatch;
-  - admission by memory: each request has a workspace estimate; a batch is
-    formed from the head of the FIFO queue while the estimates fit in the
-    budget left by the batches in flight; the head never gets skipped, so no
-    request starves; a request larger than the whole budget is rejected;
+  - admission by memory: each request has a device-memory estimate (for the
+    GPU executor: the library's own workspace-size queries plus the outputs
+    the request allocates); a batch is formed from the head of the FIFO queue
+    while the estimates fit in the budget left by the batches in flight; the
+    head never gets skipped, so no request starves; a request larger than the
+    whole budget is rejected;
   - a batch also stops at a work cap (events to scan), so a large request
     runs alone instead of holding small ones back;
   - continuous batching: `workers` persistent worker threads, each with its
@@ -23,7 +25,10 @@ GpuExecutor runs a batch with the library: all DFG and FILTER views of one
 log in one pm4g_dfg_batched launch, each VARIANTS view as pm4g_filter_view +
 pm4g_variants_prepared; a variants answer carries the variant count and the
 first `variants_top` variants (count desc, representative asc) with their
-sequences.
+sequences.  Every device buffer a batch uses (workspaces, outputs) is
+allocated for that batch, sized by its requests, on the worker's stream, and
+is what the requests' estimates charge; the executor keeps nothing else but
+the resident logs and one stream per worker.
 """
 from __future__ import annotations
 
@@ -80,6 +85,8 @@ class Scheduler:
         self._in_flight = 0
         self.max_in_flight_bytes = 0
         self.batches: list[list[int]] = []
+        self.max_queue = 0          # longest the waiting queue has been
+        self.memory_blocked = 0     # batch formations that stopped because the head did not fit in memory
 
     def form_batch(self, queue: list[Request]) -> list[Request]:
         """Head-of-queue batch that fits the memory left; removes it from `queue`."""
@@ -90,6 +97,8 @@ class Scheduler:
         while queue and len(batch) < self.max_batch:
             r = queue[0]
             if r.est_bytes > room:
+                if not batch:
+                    self.memory_blocked += 1
                 break
             if cap is not None and batch and work + r.est_work > cap:
                 break
@@ -138,6 +147,7 @@ class Scheduler:
                         done.append(r)
                 else:
                     waiting.append(r)
+            self.max_queue = max(self.max_queue, len(waiting))
             batch: list[Request] = []
             with self._lock:
                 if self._in_flight < self.workers:
@@ -182,15 +192,25 @@ class Scheduler:
             self._lock.notify_all()
 
 
-def latency_stats(reqs: list[Request]) -> dict:
+def latency_stats(reqs: list[Request], sched: "Scheduler | None" = None) -> dict:
+    """Latency (completion - scheduled arrival) percentiles, completed queries
+    per second, and the admission wait (dispatch - arrival); with the
+    scheduler, its queue statistics."""
     ok = [r for r in reqs if r.error is None]
     lat = np.array([r.latency for r in ok]) * 1e3
     if lat.size == 0:
-        return dict(n=0)
+        return dict(n=0, rejected=len(reqs))
+    wait = np.array([r.dispatched - r.arrival for r in ok]) * 1e3
     span = max(r.done for r in ok) - min(r.arrival for r in ok)
-    return dict(n=len(ok), rejected=len(reqs) - len(ok), p50_ms=float(np.percentile(lat, 50)),
-                p99_ms=float(np.percentile(lat, 99)), max_ms=float(lat.max()),
-                qps=len(ok) / span if span > 0 else float("nan"))
+    st = dict(n=len(ok), rejected=len(reqs) - len(ok), p50_ms=float(np.percentile(lat, 50)),
+              p99_ms=float(np.percentile(lat, 99)), max_ms=float(lat.max()),
+              qps=len(ok) / span if span > 0 else float("nan"),
+              wait_p50_ms=float(np.percentile(wait, 50)), wait_p99_ms=float(np.percentile(wait, 99)))
+    if sched is not None:
+        st.update(max_queue=sched.max_queue, memory_blocked=sched.memory_blocked,
+                  max_in_flight_bytes=sched.max_in_flight_bytes, budget_bytes=sched.budget,
+                  batches=len(sched.batches), workers=sched.workers)
+    return st
 
 
 def log_info(log) -> dict:
@@ -248,9 +268,10 @@ def poisson_requests(rng: np.random.Generator, rate: float, seconds: float, logs
 
 
 class GpuExecutor:
-    """Runs batches with libpm4g; one HIP stream and one set of buffers per
-    worker thread (filtered view and variants outputs sized for the largest
-    log once, so requests allocate nothing large)."""
+    """Runs batches with libpm4g, one HIP stream per worker thread.  A batch's
+    device buffers are allocated for it on the worker's stream and sized by
+    its requests; estimate() charges each request what it makes the batch
+    allocate, from the library's size queries."""
 
     def __init__(self, logs: dict, device="cuda:0", variants_top: int = 1000):
         import torch
@@ -266,8 +287,6 @@ class GpuExecutor:
             off = prep.case_off[:C + 1].cpu().numpy()
             codes = prep.case_code[:C].cpu().numpy()
             self.logs[name] = dict(prep=prep, off=off, codes=codes)
-        self.max_events = max([p.n_events for p in logs.values()] + [1])
-        self.max_A = max([p.n_activities for p in logs.values()] + [1])
         self._local = threading.local()
 
     def slice_events(self, r: Request) -> int:
@@ -282,37 +301,53 @@ class GpuExecutor:
         S = self.slice_events(r)
         return 4 * S if r.kind == "variants" else S
 
-    def estimate(self, r: Request) -> int:
-        """Workspace estimate: records and cells of a batched view, or filtered log + variants."""
+    # capacities of one view in a batched call: one record per kept event
+    # (at most the slice's events), the (tile, view) pairs its slice spans,
+    # a descriptor per (tile, view, bucket) run, cells and output cells at
+    # most one per kept event and A*A (+A start cells) per view
+    _TILE = 2048   # the smaller tile: its pair count bounds the larger one's
+
+    def _caps(self, r: Request) -> tuple[int, int, int, int, int]:
+        A = self.logs[r.log]["prep"].n_activities
         S = self.slice_events(r)
+        pairs = S // self._TILE + 2
+        nb = (A * (A + 1) + 4095) // 4096
+        return (S + 1, pairs, pairs * nb, min(S, A * (A + 1)) + 1, min(S, A * A) + 1)
+
+    def _batched_tuning(self, rs: list[Request]):
+        caps = [self._caps(r) for r in rs]
+        t = self.pm4g.BatchedTuning()
+        t.record_capacity = sum(c[0] for c in caps)
+        t.pair_capacity = sum(c[1] for c in caps)
+        t.descriptor_capacity = sum(c[2] for c in caps)
+        t.cell_capacity = sum(c[3] for c in caps)
+        return t, sum(c[4] for c in caps)
+
+    def estimate(self, r: Request) -> int:
+        """Device bytes the request makes its batch allocate: the library's
+        workspace size for the request's capacities plus its outputs."""
+        pm4g = self.pm4g
+        prep = self.logs[r.log]["prep"]
+        A, N = prep.n_activities, prep.n_events
         if r.kind == "variants":
-            return 2048 + S * 16 + S * 90
-        return 2048 + S * 30
+            S = self.slice_events(r)
+            return (pm4g.filter_workspace_bytes(N) + pm4g.prepared_bytes(S)
+                    + pm4g.variants_workspace_bytes(S, A) + pm4g.variants_out_bytes(S, with_cases=False)
+                    + 256 * 4)
+        t, edges = self._batched_tuning([r])
+        return pm4g.batched_workspace_bytes(N, A, 1, t) + pm4g.batched_out_bytes(1, A, edges) + 256 * 2
 
-    def _state(self):
-        st = getattr(self._local, "state", None)
-        if st is None:
-            torch = self.torch
-            s = torch.cuda.Stream(device=self.device)
-            with torch.cuda.stream(s):
-                sub = self.pm4g.Prepared.empty(self.max_events, self.max_A, self.device)
-                vout = self.pm4g._var_out(self.max_events, self.device, with_cases=False)
-            s.synchronize()
-            st = dict(stream=s, sub=sub, vout=vout)
-            self._local.state = st
-        return st
-
-    def _view_of(self, sub, cap: int, A: int):
-        """The worker's filter buffers as a prepared log of capacity `cap`."""
-        return self.pm4g.Prepared(case_s=sub.case_s[:cap], act_s=sub.act_s[:cap], ts_s=sub.ts_s[:cap],
-                                  case_off=sub.case_off, case_code=sub.case_code, n_cases=sub.n_cases,
-                                  status=sub.status, n_activities=A)
+    def _stream(self):
+        s = getattr(self._local, "stream", None)
+        if s is None:
+            s = self.torch.cuda.Stream(device=self.device)
+            self._local.stream = s
+        return s
 
     def run(self, batch: list[Request]) -> None:
         torch = self.torch
         pm4g = self.pm4g
-        st = self._state()
-        s = st["stream"]
+        s = self._stream()
         with torch.cuda.stream(s):
             by_log: dict[str, list[Request]] = {}
             for r in batch:
@@ -330,7 +365,9 @@ class GpuExecutor:
                 masks = np.stack([r.mask for r in rs]).view(np.int64)
                 vd = torch.from_numpy(rec.view(np.uint8).copy()).to(self.device, non_blocking=False)
                 md = torch.from_numpy(np.ascontiguousarray(masks)).to(self.device)
-                o = pm4g.pm4g_dfg_batched(prep, vd, md, len(rs), stream=s)
+                t, edges = self._batched_tuning(rs)
+                o = pm4g.pm4g_dfg_batched(prep, vd, md, len(rs), tuning=t, cap_edges=edges, stream=s,
+                                          keep_workspace=False)
                 res = pm4g.batched_to_host(o, len(rs), A)
                 for r, d in zip(rs, res):
                     if r.kind == "filter":
@@ -341,15 +378,21 @@ class GpuExecutor:
                 if r.kind != "variants":
                     continue
                 prep = self.logs[r.log]["prep"]
+                A = prep.n_activities
                 rec = np.zeros(1, dtype=np.dtype([("lo", "<i4"), ("hi", "<i4"), ("t_lo", "<i8"),
                                                   ("t_hi", "<i8")]))
                 rec["lo"], rec["hi"], rec["t_lo"], rec["t_hi"] = r.case_lo, r.case_hi, r.t_lo, r.t_hi
                 vd = torch.from_numpy(rec.view(np.uint8).copy()).to(self.device)
                 md = torch.from_numpy(np.ascontiguousarray(r.mask).view(np.int64).copy()).to(self.device)
-                cap = max(self.slice_events(r), 1)
-                sub = pm4g.pm4g_filter_view(prep, vd, md, stream=s,
-                                            out=self._view_of(st["sub"], cap, prep.n_activities))
-                v = pm4g.pm4g_variants_prepared(sub, out=st["vout"], stream=s)
+                S = max(self.slice_events(r), 1)
+                fws = torch.empty(max(pm4g.filter_workspace_bytes(prep.n_events), 1), dtype=torch.uint8,
+                                  device=self.device)
+                sub = pm4g.pm4g_filter_view(prep, vd, md, out=pm4g.Prepared.empty(S, A, self.device), ws=fws,
+                                            stream=s)
+                vws = torch.empty(max(pm4g.variants_workspace_bytes(S, A), 1), dtype=torch.uint8,
+                                  device=self.device)
+                v = pm4g.pm4g_variants_prepared(sub, out=pm4g._var_out(S, self.device, with_cases=False),
+                                                ws=vws, stream=s)
                 s.synchronize()
                 C = int(sub.n_cases.item())
                 h = pm4g.variants_to_host(v, top=self.variants_top)

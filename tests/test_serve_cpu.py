@@ -112,3 +112,19 @@ def test_work_cap_closes_batches_and_large_requests_run_alone():
     # FIFO order is kept
     flat = [rid for b in sch.batches for rid in b]
     assert flat == sorted(flat)
+
+
+def test_tight_budget_queues_requests_by_memory():
+    """With a budget that holds two requests at a time and four workers, the
+    third concurrent request waits for memory, not for a worker: the queue
+    builds, admission waits grow, and the bytes in flight never exceed the budget."""
+    ex = FakeExecutor(est=lambda r: 400, service_s=0.02)
+    sch = Scheduler(ex, mem_budget=1000, max_batch=1, workers=4)
+    out = sch.run(reqs(24, gap=0.001))
+    assert all(r.error is None for r in out)
+    assert sch.max_in_flight_bytes <= 1000
+    assert ex.max_concurrent <= 2              # memory, not the four workers, bounds the overlap
+    assert sch.memory_blocked > 0 and sch.max_queue > 2
+    st = latency_stats(out, sch)
+    assert st["wait_p99_ms"] > 20.0 and st["max_queue"] == sch.max_queue
+    assert st["budget_bytes"] == 1000 and st["memory_blocked"] == sch.memory_blocked
