@@ -50,10 +50,11 @@ def _load():
         L.orc_sample.argtypes = [i64, P, P, P, i32, i64, ctypes.c_uint64, i32, P, P, P, P, P]
         L.orc_ingest_csv.argtypes = [ctypes.c_char_p, i64, i32, i32, i32, ctypes.c_char, i32, i32, i32, i64,
                                      P, P, P, P, P, P, P, P, P, P, P]
+        L.orc_ingest_parquet.argtypes = [ctypes.c_char_p, i64, i32, i32, i32, i64, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_splitmix.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         L.orc_splitmix.restype = ctypes.c_uint64
         for f in (L.orc_prepare, L.orc_dfg, L.orc_variants, L.orc_view, L.orc_view_formatted, L.orc_cases, L.orc_filter_cases,
-                  L.orc_filter_df_events, L.orc_efg, L.orc_sample, L.orc_ingest_csv):
+                  L.orc_filter_df_events, L.orc_efg, L.orc_sample, L.orc_ingest_csv, L.orc_ingest_parquet):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -359,6 +360,39 @@ def ingest_csv(text: bytes, case_col: int, act_col: int, ts_col: int, sep: bytes
                act_len=out["act_len"][:a], n_rows=r, n_cases=c, n_acts=a)
     return res
 
+
+
+class ParquetUnsupported(OracleError):
+    def __init__(self):
+        RuntimeError.__init__(self, "Parquet feature outside the covered subset")
+        self.code = -4
+
+
+def ingest_parquet(data: bytes, case_col: int, act_col: int, ts_col: int, max_rows: int | None = None) -> dict:
+    """Columns of a Parquet file (leaf columns case_col, act_col, ts_col): case
+    and activity codes (first-appearance order), timestamps, and per code the
+    byte range of its value at its first row (integer columns: the value, -1)."""
+    n = len(data)
+    cap = max_rows if max_rows is not None else n
+    m = max(cap, 1)
+    out = dict(case=np.empty(m, np.int32), act=np.empty(m, np.int32), ts=np.empty(m, np.int64),
+               case_off=np.empty(m, np.int64), case_len=np.empty(m, np.int32), act_off=np.empty(m, np.int64),
+               act_len=np.empty(m, np.int32))
+    nr, nc, na, bad = (np.zeros(1, np.int64) for _ in range(4))
+    rc = _load().orc_ingest_parquet(data, n, case_col, act_col, ts_col, cap, _p(out["case"]), _p(out["act"]),
+                                    _p(out["ts"]), _p(nr), _p(out["case_off"]), _p(out["case_len"]), _p(nc),
+                                    _p(out["act_off"]), _p(out["act_len"]), _p(na), _p(bad))
+    if rc == -3:
+        raise CsvParseError(int(bad[0]))
+    if rc == -4:
+        raise ParquetUnsupported()
+    if rc:
+        raise OracleError(rc)
+    r, c, a = int(nr[0]), int(nc[0]), int(na[0])
+    res = {k: out[k][:r] for k in ("case", "act", "ts")}
+    res.update(case_off=out["case_off"][:c], case_len=out["case_len"][:c], act_off=out["act_off"][:a],
+               act_len=out["act_len"][:a], n_rows=r, n_cases=c, n_acts=a)
+    return res
 
 def csv_value(raw: bytes) -> bytes:
     """The value of a raw CSV field (quoted runs unwrapped, doubled quotes single)."""

@@ -1224,3 +1224,507 @@ int orc_ingest_csv(const char *text, int64_t n_bytes, int32_t case_col, int32_t 
     free(store);
     return rc;
 }
+
+/* ---- Parquet ingestion ------------------------------------------------ */
+
+/*
+ * Sec. 2.2: the event log may also come as a Parquet file, a columnar format
+ * the GPU dataframe library reads directly.  The format is Apache Parquet's
+ * published specification: the file ends with its metadata (a Thrift
+ * compact-protocol struct), a 4-byte little-endian length and "PAR1"; each
+ * column of each row group is a chunk of pages, each page a Thrift header and
+ * its data.  Covered here: uncompressed chunks, flat schemas (required or
+ * optional columns, no nesting), data pages of version 1 and 2, values PLAIN
+ * or dictionary-coded (PLAIN_DICTIONARY / RLE_DICTIONARY, the dictionary page
+ * PLAIN), definition levels in the RLE / bit-packing hybrid; INT32, INT64 and
+ * BYTE_ARRAY case and activity columns, INT32 and INT64 timestamps.
+ */
+#define ORC_E_UNSUPPORTED -4
+
+typedef struct {
+    const uint8_t *b;
+    int64_t n, p;
+    int bad;
+} orc_tr;   /* a reader of Thrift's compact protocol */
+
+static uint64_t tr_varint(orc_tr *r)
+{
+    uint64_t v = 0;
+    for (int sh = 0; sh < 64; sh += 7) {
+        if (r->p >= r->n) break;
+        uint8_t c = r->b[r->p++];
+        v |= (uint64_t)(c & 0x7f) << sh;
+        if (!(c & 0x80)) return v;
+    }
+    r->bad = 1;
+    return 0;
+}
+
+static int64_t tr_zigzag(orc_tr *r)
+{
+    uint64_t u = tr_varint(r);
+    return (int64_t)(u >> 1) ^ -(int64_t)(u & 1);
+}
+
+static uint8_t tr_byte(orc_tr *r)
+{
+    if (r->p >= r->n) {
+        r->bad = 1;
+        return 0;
+    }
+    return r->b[r->p++];
+}
+
+/* A field header inside a struct: returns its type (0 = end of struct) and the
+   field id, whose delta from the previous id is in the high nibble (0: the id
+   follows as a zigzag varint). */
+static int tr_field(orc_tr *r, int *last_id, int *id)
+{
+    uint8_t h = tr_byte(r);
+    int t = h & 0x0f;
+    if (t == 0 || r->bad) return 0;
+    int d = h >> 4;
+    *id = d ? *last_id + d : (int)tr_zigzag(r);
+    *last_id = *id;
+    return t;
+}
+
+/* Skips one value of compact type t (in_list: booleans take a byte). */
+static void tr_skip(orc_tr *r, int t, int in_list, int depth)
+{
+    if (depth > 64 || r->bad) {
+        r->bad = 1;
+        return;
+    }
+    switch (t) {
+    case 1:
+    case 2:
+        if (in_list) r->p += 1;   /* in a field header the value is the type itself */
+        break;
+    case 3: r->p += 1; break;
+    case 4:
+    case 5:
+    case 6: tr_varint(r); break;
+    case 7: r->p += 8; break;
+    case 8: {
+        uint64_t len = tr_varint(r);
+        if (len > (uint64_t)(r->n - r->p)) r->bad = 1;
+        else r->p += (int64_t)len;
+        break;
+    }
+    case 9:
+    case 10: {
+        uint8_t h = tr_byte(r);
+        uint64_t sz = h >> 4;
+        if (sz == 15) sz = tr_varint(r);
+        for (uint64_t k = 0; k < sz && !r->bad; k++) tr_skip(r, h & 0x0f, 1, depth + 1);
+        break;
+    }
+    case 11: {
+        uint64_t sz = tr_varint(r);
+        if (sz) {
+            uint8_t kv = tr_byte(r);
+            for (uint64_t k = 0; k < sz && !r->bad; k++) {
+                tr_skip(r, kv >> 4, 1, depth + 1);
+                tr_skip(r, kv & 0x0f, 1, depth + 1);
+            }
+        }
+        break;
+    }
+    case 12: {
+        int last = 0, id = 0, ft;
+        while ((ft = tr_field(r, &last, &id)) != 0 && !r->bad) tr_skip(r, ft, 0, depth + 1);
+        break;
+    }
+    default: r->bad = 1;
+    }
+    if (r->p > r->n) r->bad = 1;
+}
+
+/* A list header: element count; *etype the element type. */
+static int64_t tr_list(orc_tr *r, int *etype)
+{
+    uint8_t h = tr_byte(r);
+    uint64_t sz = h >> 4;
+    if (sz == 15) sz = tr_varint(r);
+    *etype = h & 0x0f;
+    if (sz > (uint64_t)r->n) r->bad = 1;
+    return (int64_t)sz;
+}
+
+typedef struct {
+    int32_t type, rep, has_children;
+} orc_pq_leaf;
+
+typedef struct {
+    int32_t type, codec;
+    int64_t num_values, size, data_off, dict_off;
+} orc_pq_chunk;
+
+typedef struct {
+    int32_t type;        /* 1 INT32, 2 INT64, 6 BYTE_ARRAY */
+    int32_t optional;    /* repetition OPTIONAL: definition levels present */
+    /* decoded values, one per row: integers, or byte ranges in the file */
+    int64_t *ival;
+    int64_t *off;
+    int32_t *len;
+} orc_pq_col;
+
+/* Parquet's RLE / bit-packing hybrid: count values of bw bits from b[0..n). */
+static int pq_hybrid(const uint8_t *b, int64_t n, int bw, int64_t count, uint32_t *out)
+{
+    orc_tr r = {b, n, 0, 0};
+    int64_t k = 0;
+    int vb = (bw + 7) / 8;
+    while (k < count) {
+        uint64_t h = tr_varint(&r);
+        if (r.bad) return -1;
+        if (h & 1) {   /* bit-packed: (h >> 1) groups of 8 values, least significant bit first */
+            uint64_t groups = h >> 1;
+            if (groups > (uint64_t)n || (int64_t)(groups * (uint64_t)bw) > n - r.p) return -1;
+            for (int64_t j = 0; j < (int64_t)groups * 8 && k < count; j++) {
+                uint32_t v = 0;
+                for (int i = 0; i < bw; i++) {
+                    int64_t q = j * bw + i;
+                    v |= (uint32_t)((b[r.p + q / 8] >> (q % 8)) & 1u) << i;
+                }
+                out[k++] = v;
+            }
+            r.p += (int64_t)groups * bw;
+        } else {       /* a run of one value in ceil(bw/8) little-endian bytes */
+            uint64_t run = h >> 1;
+            if (vb > n - r.p) return -1;
+            uint32_t v = 0;
+            for (int i = 0; i < vb; i++) v |= (uint32_t)b[r.p + i] << (8 * i);
+            r.p += vb;
+            for (uint64_t j = 0; j < run && k < count; j++) out[k++] = v;
+        }
+    }
+    return 0;
+}
+
+static int64_t rd_le(const uint8_t *p, int bytes)
+{
+    uint64_t v = 0;
+    for (int i = 0; i < bytes; i++) v |= (uint64_t)p[i] << (8 * i);
+    if (bytes == 4) return (int64_t)(int32_t)(uint32_t)v;
+    return (int64_t)v;
+}
+
+/* One PLAIN value at b[p] of n bytes: the integer or the byte range. */
+static int pq_plain(const uint8_t *b, int64_t n, int64_t *p, int32_t type, int64_t base, int64_t *ival,
+                    int64_t *off, int32_t *len)
+{
+    if (type == 1 || type == 2) {
+        int w = type == 1 ? 4 : 8;
+        if (w > n - *p) return -1;
+        *ival = rd_le(b + *p, w);
+        *p += w;
+        return 0;
+    }
+    if (4 > n - *p) return -1;
+    int64_t L = (int64_t)(uint32_t)rd_le(b + *p, 4) & 0xffffffffll;
+    if (L > n - *p - 4) return -1;
+    *off = base + *p + 4;
+    *len = (int32_t)L;
+    *p += 4 + L;
+    return 0;
+}
+
+/* The values of one column chunk into col at rows row0 ..; returns 0, a
+   negative status, or (parse error) sets *bad_row. */
+static int pq_chunk(const uint8_t *f, int64_t fn, const orc_pq_chunk *ch, orc_pq_col *col, int64_t row0,
+                    int64_t *bad_row)
+{
+    if (ch->codec != 0) return ORC_E_UNSUPPORTED;
+    if (ch->type != col->type) return ORC_E_PARSE;
+    if (ch->num_values == 0) return ORC_OK;   /* nothing to read (its pages, if any, hold no value) */
+    int64_t pos = (ch->dict_off > 0 && (ch->dict_off < ch->data_off || ch->data_off <= 0)) ? ch->dict_off
+                                                                                          : ch->data_off;
+    if (pos < 4 || ch->size < 0 || ch->size > fn - pos) return ORC_E_PARSE;
+    int64_t end = pos + ch->size;
+    int64_t done = 0;
+    int64_t dn = -1;   /* dictionary entries, -1 before a dictionary page */
+    int64_t *d_ival = NULL, *d_off = NULL;
+    int32_t *d_len = NULL;
+    int rc = ORC_OK;
+    while (done < ch->num_values && rc == ORC_OK) {
+        orc_tr r = {f, end, pos, 0};
+        int last = 0, id = 0, ft;
+        int32_t ptype = -1, csize = -1, nv = -1, enc = -1, dlen = -1, rlen = -1, v2 = 0;
+        while ((ft = tr_field(&r, &last, &id)) != 0 && !r.bad) {
+            if (id == 1 && ft == 5) ptype = (int32_t)tr_zigzag(&r);
+            else if (id == 3 && ft == 5) csize = (int32_t)tr_zigzag(&r);
+            else if ((id == 5 || id == 7 || id == 8) && ft == 12) {
+                v2 = id == 8;
+                int l2 = 0, i2 = 0, t2;
+                while ((t2 = tr_field(&r, &l2, &i2)) != 0 && !r.bad) {
+                    if (i2 == 1 && t2 == 5) nv = (int32_t)tr_zigzag(&r);
+                    else if (((id != 8 && i2 == 2) || (id == 8 && i2 == 4)) && t2 == 5) enc = (int32_t)tr_zigzag(&r);
+                    else if (id == 8 && i2 == 5 && t2 == 5) dlen = (int32_t)tr_zigzag(&r);
+                    else if (id == 8 && i2 == 6 && t2 == 5) rlen = (int32_t)tr_zigzag(&r);
+                    else tr_skip(&r, t2, 0, 1);
+                }
+            } else tr_skip(&r, ft, 0, 0);
+        }
+        if (r.bad || ptype < 0 || csize < 0 || csize > end - r.p) { rc = ORC_E_PARSE; break; }
+        const uint8_t *pg = f + r.p;
+        int64_t pbase = r.p;
+        pos = r.p + csize;
+        if (ptype == 2) {   /* dictionary page: nv PLAIN values */
+            if (nv < 0 || dn >= 0) { rc = ORC_E_PARSE; break; }
+            if (enc != 0 && enc != 2) { rc = ORC_E_UNSUPPORTED; break; }
+            dn = nv;
+            d_ival = (int64_t *)malloc((size_t)(dn > 0 ? dn : 1) * sizeof(int64_t));
+            d_off = (int64_t *)malloc((size_t)(dn > 0 ? dn : 1) * sizeof(int64_t));
+            d_len = (int32_t *)malloc((size_t)(dn > 0 ? dn : 1) * sizeof(int32_t));
+            int64_t p = 0;
+            for (int64_t k = 0; k < dn; k++)
+                if (pq_plain(pg, csize, &p, col->type, pbase, &d_ival[k], &d_off[k], &d_len[k])) {
+                    rc = ORC_E_PARSE;
+                    break;
+                }
+            continue;
+        }
+        if (ptype != 0 && ptype != 3) continue;   /* index pages carry no values */
+        if (nv < 0 || nv > ch->num_values - done) { rc = ORC_E_PARSE; break; }
+        if (v2 && (dlen < 0 || rlen != 0 || (int64_t)dlen > csize)) { rc = v2 && rlen > 0 ? ORC_E_UNSUPPORTED : ORC_E_PARSE; break; }
+        int64_t p = 0;
+        if (col->optional) {   /* definition levels (bit width 1): 0 is a null */
+            int64_t lb;
+            if (v2) lb = dlen;
+            else {
+                if (csize < 4) { rc = ORC_E_PARSE; break; }
+                lb = (int64_t)(uint32_t)rd_le(pg, 4) & 0xffffffffll;
+                p = 4;
+            }
+            if (lb > csize - p) { rc = ORC_E_PARSE; break; }
+            uint32_t *lev = (uint32_t *)malloc((size_t)(nv > 0 ? nv : 1) * sizeof(uint32_t));
+            if (pq_hybrid(pg + p, lb, 1, nv, lev)) rc = ORC_E_PARSE;
+            for (int64_t k = 0; k < nv && rc == ORC_OK; k++)
+                if (lev[k] == 0) {
+                    rc = ORC_E_PARSE;
+                    *bad_row = row0 + done + k;
+                }
+            free(lev);
+            if (rc != ORC_OK) break;
+            p += lb;
+        } else if (v2 && dlen != 0) {
+            rc = ORC_E_PARSE;
+            break;
+        }
+        if (enc == 0) {
+            for (int64_t k = 0; k < nv; k++) {
+                int64_t row = row0 + done + k;
+                if (pq_plain(pg, csize, &p, col->type, pbase, &col->ival[row], &col->off[row], &col->len[row])) {
+                    rc = ORC_E_PARSE;
+                    break;
+                }
+            }
+        } else if (enc == 2 || enc == 8) {
+            if (dn < 0 || p >= csize) { rc = ORC_E_PARSE; break; }
+            int bw = pg[p++];
+            if (bw > 32) { rc = ORC_E_PARSE; break; }
+            uint32_t *idx = (uint32_t *)malloc((size_t)(nv > 0 ? nv : 1) * sizeof(uint32_t));
+            if (pq_hybrid(pg + p, csize - p, bw, nv, idx)) rc = ORC_E_PARSE;
+            for (int64_t k = 0; k < nv && rc == ORC_OK; k++) {
+                if ((int64_t)idx[k] >= dn) {
+                    rc = ORC_E_PARSE;
+                    break;
+                }
+                int64_t row = row0 + done + k;
+                col->ival[row] = d_ival[idx[k]];
+                col->off[row] = d_off[idx[k]];
+                col->len[row] = d_len[idx[k]];
+            }
+            free(idx);
+        } else {
+            rc = ORC_E_UNSUPPORTED;
+        }
+        done += nv;
+    }
+    free(d_ival);
+    free(d_off);
+    free(d_len);
+    if (rc == ORC_OK && done != ch->num_values) rc = ORC_E_PARSE;
+    return rc;
+}
+
+/*
+ * orc_ingest_parquet: columns case_col, act_col, ts_col (0-based leaf
+ * columns of a flat schema) of a Parquet file held in f[0..n) into the
+ * columns of an event log.  Case and activity values are coded 0, 1, ... in
+ * order of first appearance (integers by value, byte arrays byte-exact); for
+ * each code, *_first_off / *_first_len give the byte range of the value at
+ * its first row (for an integer column: the value itself, and -1).
+ * Timestamps are the INT64 (or INT32) values.  A null in one of the three
+ * columns is a parse error at its row (*bad_row); a malformed file is a parse
+ * error with *bad_row = -1; a valid file outside what is covered (compression,
+ * other encodings or types, nesting) returns ORC_E_UNSUPPORTED.  More rows than
+ * max_rows: ORC_E_INVALID.
+ */
+int orc_ingest_parquet(const uint8_t *f, int64_t n, int32_t case_col, int32_t act_col, int32_t ts_col,
+                       int64_t max_rows, int32_t *case_code, int32_t *act_code, int64_t *ts, int64_t *n_rows,
+                       int64_t *case_first_off, int32_t *case_first_len, int64_t *n_cases,
+                       int64_t *act_first_off, int32_t *act_first_len, int64_t *n_acts, int64_t *bad_row)
+{
+    *bad_row = -1;
+    *n_rows = *n_cases = *n_acts = 0;
+    if (n < 0 || case_col < 0 || act_col < 0 || ts_col < 0 || max_rows < 0) return ORC_E_INVALID;
+    if (n < 12 || memcmp(f, "PAR1", 4) != 0 || memcmp(f + n - 4, "PAR1", 4) != 0) return ORC_E_PARSE;
+    int64_t flen = (int64_t)(uint32_t)rd_le(f + n - 8, 4) & 0xffffffffll;
+    if (flen > n - 12) return ORC_E_PARSE;
+    orc_tr r = {f, n - 8, n - 8 - flen, 0};
+
+    /* FileMetaData: 2 schema, 3 num_rows, 4 row_groups */
+    orc_pq_leaf *leaf = NULL;
+    int64_t n_leaf = 0, num_rows = -1, n_rg = 0;
+    int64_t *rg_rows = NULL;
+    orc_pq_chunk *chunks = NULL;   /* [row group][3] */
+    int want[3] = {case_col, act_col, ts_col};
+    int rc = ORC_OK;
+    int last = 0, id = 0, ft;
+    while ((ft = tr_field(&r, &last, &id)) != 0 && !r.bad && rc == ORC_OK) {
+        if (id == 2 && ft == 9) {
+            int et;
+            int64_t ne = tr_list(&r, &et);
+            if (et != 12 || ne < 1) { rc = ORC_E_PARSE; break; }
+            leaf = (orc_pq_leaf *)calloc((size_t)ne, sizeof(orc_pq_leaf));
+            for (int64_t e = 0; e < ne && !r.bad; e++) {
+                orc_pq_leaf el = {-1, 0, 0};
+                int l2 = 0, i2 = 0, t2;
+                while ((t2 = tr_field(&r, &l2, &i2)) != 0 && !r.bad) {
+                    if (i2 == 1 && t2 == 5) el.type = (int32_t)tr_zigzag(&r);
+                    else if (i2 == 3 && t2 == 5) el.rep = (int32_t)tr_zigzag(&r);
+                    else if (i2 == 5 && t2 == 5) el.has_children = tr_zigzag(&r) > 0;
+                    else tr_skip(&r, t2, 0, 1);
+                }
+                if (e == 0) continue;   /* the root */
+                if (el.has_children) rc = ORC_E_UNSUPPORTED;   /* nested schema */
+                leaf[n_leaf++] = el;
+            }
+        } else if (id == 3 && ft == 6) {
+            num_rows = tr_zigzag(&r);
+        } else if (id == 4 && ft == 9) {
+            int et;
+            n_rg = tr_list(&r, &et);
+            if (et != 12) { rc = ORC_E_PARSE; break; }
+            rg_rows = (int64_t *)calloc((size_t)(n_rg > 0 ? n_rg : 1), sizeof(int64_t));
+            chunks = (orc_pq_chunk *)calloc((size_t)(n_rg > 0 ? n_rg : 1) * 3, sizeof(orc_pq_chunk));
+            for (int64_t g = 0; g < n_rg && !r.bad; g++) {
+                int l2 = 0, i2 = 0, t2;
+                rg_rows[g] = -1;
+                while ((t2 = tr_field(&r, &l2, &i2)) != 0 && !r.bad) {
+                    if (i2 == 3 && t2 == 6) rg_rows[g] = tr_zigzag(&r);
+                    else if (i2 == 1 && t2 == 9) {
+                        int ct;
+                        int64_t nc = tr_list(&r, &ct);
+                        if (ct != 12) { r.bad = 1; break; }
+                        for (int64_t c = 0; c < nc && !r.bad; c++) {
+                            orc_pq_chunk cm = {-1, -1, -1, -1, -1, -1};
+                            int l3 = 0, i3 = 0, t3;
+                            while ((t3 = tr_field(&r, &l3, &i3)) != 0 && !r.bad) {
+                                if (i3 == 1 && t3 == 8) rc = rc ? rc : ORC_E_UNSUPPORTED;   /* chunk in another file */
+                                if (i3 == 3 && t3 == 12) {
+                                    int l4 = 0, i4 = 0, t4;
+                                    while ((t4 = tr_field(&r, &l4, &i4)) != 0 && !r.bad) {
+                                        if (i4 == 1 && t4 == 5) cm.type = (int32_t)tr_zigzag(&r);
+                                        else if (i4 == 4 && t4 == 5) cm.codec = (int32_t)tr_zigzag(&r);
+                                        else if (i4 == 5 && t4 == 6) cm.num_values = tr_zigzag(&r);
+                                        else if (i4 == 7 && t4 == 6) cm.size = tr_zigzag(&r);
+                                        else if (i4 == 9 && t4 == 6) cm.data_off = tr_zigzag(&r);
+                                        else if (i4 == 11 && t4 == 6) cm.dict_off = tr_zigzag(&r);
+                                        else tr_skip(&r, t4, 0, 2);
+                                    }
+                                } else tr_skip(&r, t3, 0, 1);
+                            }
+                            for (int k = 0; k < 3; k++)
+                                if (c == want[k]) chunks[g * 3 + k] = cm;
+                        }
+                    } else tr_skip(&r, t2, 0, 1);
+                }
+            }
+        } else {
+            tr_skip(&r, ft, 0, 0);
+        }
+    }
+    if (rc == ORC_OK && (r.bad || !leaf || num_rows < 0)) rc = ORC_E_PARSE;
+    for (int k = 0; k < 3 && rc == ORC_OK; k++) {
+        if (want[k] >= n_leaf) rc = ORC_E_INVALID;
+        else if (leaf[want[k]].rep == 2) rc = ORC_E_UNSUPPORTED;
+        else if (k < 2 && leaf[want[k]].type != 1 && leaf[want[k]].type != 2 && leaf[want[k]].type != 6) rc = ORC_E_UNSUPPORTED;
+        else if (k == 2 && leaf[want[k]].type != 1 && leaf[want[k]].type != 2) rc = ORC_E_UNSUPPORTED;
+    }
+    int64_t total = 0;
+    for (int64_t g = 0; g < n_rg && rc == ORC_OK; g++) {
+        if (rg_rows[g] < 0) rc = ORC_E_PARSE;
+        for (int k = 0; k < 3 && rc == ORC_OK; k++)
+            if (chunks[g * 3 + k].num_values != rg_rows[g]) rc = chunks[g * 3 + k].type < 0 ? ORC_E_PARSE : ORC_E_UNSUPPORTED;
+        total += rg_rows[g];
+    }
+    if (rc == ORC_OK && total != num_rows) rc = ORC_E_PARSE;
+    if (rc == ORC_OK && total > max_rows) rc = ORC_E_INVALID;
+    orc_pq_col col[3];
+    size_t m = (size_t)(total > 0 ? total : 1);
+    for (int k = 0; k < 3; k++) {
+        col[k].type = (rc == ORC_OK) ? leaf[want[k]].type : 0;
+        col[k].optional = (rc == ORC_OK) ? leaf[want[k]].rep == 1 : 0;
+        col[k].ival = (int64_t *)calloc(m, sizeof(int64_t));
+        col[k].off = (int64_t *)calloc(m, sizeof(int64_t));
+        col[k].len = (int32_t *)calloc(m, sizeof(int32_t));
+    }
+    /* row groups in order; a structural error stops at once; nulls: the
+       smallest row with a null in any of the three columns */
+    int64_t row0 = 0;
+    for (int64_t g = 0; g < n_rg && rc == ORC_OK; g++) {
+        int64_t null_row = -1;
+        for (int k = 0; k < 3 && rc == ORC_OK; k++) {
+            int64_t b = -1;
+            int c = pq_chunk(f, n - 8 - flen, &chunks[g * 3 + k], &col[k], row0, &b);
+            if (c == ORC_E_PARSE && b >= 0) {
+                if (null_row < 0 || b < null_row) null_row = b;
+            } else if (c != ORC_OK) {
+                rc = c;
+            }
+        }
+        if (rc == ORC_OK && null_row >= 0) {
+            rc = ORC_E_PARSE;
+            *bad_row = null_row;
+        }
+        row0 += rg_rows[g];
+    }
+    if (rc == ORC_OK) {
+        *n_rows = total;
+        for (int64_t i = 0; i < total; i++) ts[i] = col[2].ival[i];
+        int32_t *codes[2] = {case_code, act_code};
+        int64_t *fo[2] = {case_first_off, act_first_off};
+        int32_t *fl[2] = {case_first_len, act_first_len};
+        int64_t *nc[2] = {n_cases, n_acts};
+        orc_str *sv = (orc_str *)malloc(m * sizeof(orc_str));
+        int64_t *firsts = (int64_t *)malloc(m * sizeof(int64_t));
+        for (int k = 0; k < 2; k++) {
+            int is_int = col[k].type != 6;
+            for (int64_t i = 0; i < total; i++) {
+                sv[i].p = is_int ? (const char *)&col[k].ival[i] : (const char *)f + col[k].off[i];
+                sv[i].len = is_int ? 8 : col[k].len[i];
+                sv[i].row = i;
+            }
+            *nc[k] = factorize(sv, total, codes[k], firsts);
+            for (int64_t c = 0; c < *nc[k]; c++) {
+                fo[k][c] = is_int ? col[k].ival[firsts[c]] : col[k].off[firsts[c]];
+                fl[k][c] = is_int ? -1 : col[k].len[firsts[c]];
+            }
+        }
+        free(sv);
+        free(firsts);
+    }
+    for (int k = 0; k < 3; k++) {
+        free(col[k].ival);
+        free(col[k].off);
+        free(col[k].len);
+    }
+    free(leaf);
+    free(rg_rows);
+    free(chunks);
+    return rc;
+}
