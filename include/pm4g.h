@@ -60,7 +60,8 @@ enum {
     PM4G_E_CAPACITY = -4,    /* an output arena is too small; the required size is reported */
     PM4G_E_WORKSPACE = -5,   /* ws_bytes < pm4g_workspace_bytes(...) */
     PM4G_E_DEVICE = -6,      /* a HIP runtime call failed */
-    PM4G_E_PARSE = -7        /* CSV ingestion: a data row could not be parsed */
+    PM4G_E_PARSE = -7,       /* CSV / Parquet ingestion: a data row could not be parsed */
+    PM4G_E_UNSUPPORTED = -8  /* Parquet ingestion: a valid file outside the covered subset */
 };
 
 /* pm4g_log.flags */
@@ -551,6 +552,48 @@ typedef struct {
 size_t pm4g_ingest_csv_workspace_bytes(int64_t n_bytes, int64_t capacity);
 int pm4g_ingest_csv(const uint8_t *text, int64_t n_bytes, const pm4g_csv_schema *schema, const pm4g_csv_out *out,
                     void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Parquet ingestion (Sec. 2.2: the log as a columnar file the GPU reads
+ * directly).  `file` holds a whole Apache Parquet file of n_bytes bytes in
+ * device memory; case_col, act_col and ts_col are 0-based columns (leaves) of
+ * its flat schema.  Read: uncompressed column chunks, data pages v1 and v2,
+ * PLAIN and dictionary-coded values (PLAIN_DICTIONARY / RLE_DICTIONARY),
+ * definition levels of optional columns; INT32, INT64 and BYTE_ARRAY case and
+ * activity columns, INT32 and INT64 timestamp columns (timestamps are taken
+ * as they are stored, in the column's unit).
+ * Outputs as pm4g_ingest_csv: the rows' case and activity codes (0, 1, ... in
+ * order of first appearance; integers compared by value, byte arrays byte by
+ * byte), timestamps, and per code *_dict_off / *_dict_len: the byte range in
+ * `file` of the value at the code's first row (integer columns: the value
+ * itself in *_dict_off and -1 in *_dict_len).
+ * Errors:
+ *   - returned before anything runs on the device values: PM4G_E_INVALID
+ *     (arguments, a column beyond the schema), PM4G_E_UNSUPPORTED (codec,
+ *     physical type, nested or repeated columns, chunks in other files; also
+ *     in out->status), PM4G_E_PARSE (a malformed footer), PM4G_E_CAPACITY (more
+ *     rows than out->capacity; also in out->status, with *out->n_rows = 0);
+ *   - found while decoding, in out->status and returned: PM4G_E_PARSE with
+ *     *out->bad_row the smallest row holding a null in one of the three
+ *     columns, or -1 for malformed pages; PM4G_E_UNSUPPORTED for other page
+ *     encodings.
+ * Synchronises the stream (the footer is read on the host; value hashes that
+ * collide repeat the matching with another seed).  pm4g_debug_csv_hash_bits
+ * applies to its value hashes too.
+ */
+typedef struct {
+    int32_t case_col;
+    int32_t act_col;
+    int32_t ts_col;
+    int32_t reserved;
+} pm4g_parquet_schema;
+
+/* Rows of a Parquet file in device memory, from its footer (host int64).
+   Synchronises. */
+int pm4g_parquet_rows(const uint8_t *file, int64_t n_bytes, int64_t *rows, void *stream);
+size_t pm4g_ingest_parquet_workspace_bytes(int64_t n_bytes, int64_t capacity);
+int pm4g_ingest_parquet(const uint8_t *file, int64_t n_bytes, const pm4g_parquet_schema *schema,
+                        const pm4g_csv_out *out, void *ws, size_t ws_bytes, void *stream);
 
 /* Text for a status code (static storage). */
 const char *pm4g_status_string(int code);

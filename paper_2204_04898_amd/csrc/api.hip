@@ -372,7 +372,8 @@ const char* pm4g_status_string(int code) {
         case PM4G_E_CAPACITY: return "output capacity exceeded";
         case PM4G_E_WORKSPACE: return "workspace too small";
         case PM4G_E_DEVICE: return "HIP runtime error";
-        case PM4G_E_PARSE: return "CSV parse error";
+        case PM4G_E_PARSE: return "parse error";
+        case PM4G_E_UNSUPPORTED: return "Parquet feature outside the covered subset";
         default: return "unknown status";
     }
 }
@@ -562,6 +563,123 @@ int pm4g_ingest_csv(const uint8_t* text, int64_t n_bytes, const pm4g_csv_schema*
     }
     if (sc_host[3] != INT64_MAX) {
         set_err("CSV parse error at data row %lld", (long long)sc_host[3]);
+        return PM4G_E_PARSE;
+    }
+    return PM4G_OK;
+}
+
+// The footer of a Parquet file in device memory, copied to the host.
+static int parquet_footer(const uint8_t* file, int64_t n_bytes, hipStream_t s, std::vector<uint8_t>* meta) {
+    PM4G_CHECK(n_bytes >= 0 && (n_bytes == 0 || file), "file is NULL or n_bytes < 0");
+    if (n_bytes < 12) {
+        set_err("%lld bytes: not a Parquet file", (long long)n_bytes);
+        return PM4G_E_PARSE;
+    }
+    uint8_t tail[8], head[4];
+    PM4G_HIP(hipMemcpyAsync(tail, file + n_bytes - 8, 8, hipMemcpyDeviceToHost, s));
+    PM4G_HIP(hipMemcpyAsync(head, file, 4, hipMemcpyDeviceToHost, s));
+    PM4G_HIP(hipStreamSynchronize(s));
+    const int64_t len = (int64_t)((uint32_t)tail[0] | (uint32_t)tail[1] << 8 | (uint32_t)tail[2] << 16 |
+                                  (uint32_t)tail[3] << 24);
+    if (memcmp(tail + 4, "PAR1", 4) != 0 || memcmp(head, "PAR1", 4) != 0 || len > n_bytes - 12) {
+        set_err("not a Parquet file (magic or footer length)");
+        return PM4G_E_PARSE;
+    }
+    meta->resize((size_t)(len > 0 ? len : 1));
+    if (len > 0) {
+        PM4G_HIP(hipMemcpyAsync(meta->data(), file + n_bytes - 8 - len, (size_t)len, hipMemcpyDeviceToHost, s));
+        PM4G_HIP(hipStreamSynchronize(s));
+    }
+    meta->resize((size_t)len);
+    return PM4G_OK;
+}
+
+int pm4g_parquet_rows(const uint8_t* file, int64_t n_bytes, int64_t* rows, void* stream) {
+    PM4G_CHECK(rows != nullptr, "rows is NULL");
+    std::vector<uint8_t> meta;
+    if (int rc = parquet_footer(file, n_bytes, (hipStream_t)stream, &meta)) return rc;
+    std::vector<PqChunk> chunks;
+    const int32_t cols[3] = {0, 0, 0};
+    char msg[256];
+    const int rc = pq_parse_footer(meta.data(), (int64_t)meta.size(), n_bytes, cols, &chunks, rows, msg, sizeof(msg));
+    if (rc == PM4G_E_UNSUPPORTED || rc == PM4G_OK) return PM4G_OK;   // the row count is read either way
+    set_err("%s", msg);
+    return rc;
+}
+
+size_t pm4g_ingest_parquet_workspace_bytes(int64_t n_bytes, int64_t capacity) {
+    if (n_bytes < 0 || capacity < 0 || capacity > kMaxEvents) return 0;
+    Bump b(nullptr);
+    pq_ws_layout(b, capacity);
+    return b.off + 256;
+}
+
+int pm4g_ingest_parquet(const uint8_t* file, int64_t n_bytes, const pm4g_parquet_schema* sc, const pm4g_csv_out* out,
+                        void* ws, size_t ws_size, void* stream) {
+    PM4G_CHECK(sc != nullptr && out != nullptr, "schema or out is NULL");
+    PM4G_CHECK(sc->case_col >= 0 && sc->act_col >= 0 && sc->ts_col >= 0, "a column index is negative");
+    PM4G_CHECK(out->capacity >= 0 && out->capacity <= kMaxEvents, "capacity outside [0, 2^31)");
+    PM4G_CHECK(out->n_rows && out->n_cases && out->n_acts && out->status && out->bad_row &&
+                   (out->capacity == 0 || (out->case_code && out->act_code && out->ts && out->case_dict_off &&
+                                           out->case_dict_len && out->act_dict_off && out->act_dict_len)),
+               "an ingestion output array is NULL");
+    const size_t need = pm4g_ingest_parquet_workspace_bytes(n_bytes, out->capacity);
+    if (ws_size < need || !ws) {
+        set_err("workspace of %zu bytes, %zu needed", ws_size, need);
+        return PM4G_E_WORKSPACE;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    ProfScope ps(P_PARQUET, s);
+    std::vector<uint8_t> meta;
+    if (int rc = parquet_footer(file, n_bytes, s, &meta)) return rc;
+    std::vector<PqChunk> chunks;
+    const int32_t cols[3] = {sc->case_col, sc->act_col, sc->ts_col};
+    int64_t rows = 0;
+    char msg[256];
+    int rc = pq_parse_footer(meta.data(), (int64_t)meta.size(), n_bytes, cols, &chunks, &rows, msg, sizeof(msg));
+    if (rc == PM4G_OK && (int64_t)chunks.size() > kPqMaxChunks) {
+        snprintf(msg, sizeof(msg), "more than %lld row groups", (long long)(kPqMaxChunks / 3));
+        rc = PM4G_E_UNSUPPORTED;
+    }
+    if (rc == PM4G_OK && rows > out->capacity) {
+        snprintf(msg, sizeof(msg), "%lld rows, capacity %lld", (long long)rows, (long long)out->capacity);
+        rc = PM4G_E_CAPACITY;
+    }
+    if (rc != PM4G_OK) {
+        set_err("%s", msg);
+        if (rc == PM4G_E_UNSUPPORTED || rc == PM4G_E_CAPACITY || rc == PM4G_E_PARSE) {
+            k_set_status<<<1, 1, 0, s>>>(out->status, rc);
+            PM4G_HIP(hipGetLastError());
+            PM4G_HIP(hipMemsetAsync(out->n_rows, 0, sizeof(int64_t), s));
+            PM4G_HIP(hipStreamSynchronize(s));
+        }
+        return rc;
+    }
+    Bump bp(ws);
+    PqWs w = pq_ws_layout(bp, out->capacity);
+    w.max_rows = out->capacity > 0 ? out->capacity : 1;
+    if (!chunks.empty())
+        PM4G_HIP(hipMemcpyAsync(w.chunks, chunks.data(), chunks.size() * sizeof(PqChunk), hipMemcpyHostToDevice, s));
+    PM4G_HIP(launch_pq_decode(file, w, (int64_t)chunks.size(), rows, out->ts, s));
+    int64_t sc_host[16];
+    for (uint64_t attempt = 0;; ++attempt) {
+        PM4G_HIP(launch_pq_match(file, w, rows, 0x2545F4914F6CDD1Dull * (attempt + 1),
+                                 attempt == 0 ? g_csv_hash_bits : 0, s));
+        PM4G_HIP(hipMemcpyAsync(sc_host, w.scal, sizeof(sc_host), hipMemcpyDeviceToHost, s));
+        PM4G_HIP(hipStreamSynchronize(s));
+        if (sc_host[0] != 0 || sc_host[1] != INT64_MAX || !sc_host[2]) break;
+        PM4G_CHECK(attempt < 8, "value hashes kept colliding");
+    }
+    if (sc_host[0] == 0 && sc_host[1] == INT64_MAX) PM4G_HIP(launch_pq_codes(w, rows, *out, s));
+    PM4G_HIP(launch_pq_finish(w, *out, s));
+    PM4G_HIP(hipStreamSynchronize(s));
+    if (sc_host[0] != 0) {
+        set_err("%s", sc_host[0] == PM4G_E_UNSUPPORTED ? "a page encoding outside the covered subset"
+                                                       : "malformed Parquet page");
+        return (int)sc_host[0];
+    }
+    if (sc_host[1] != INT64_MAX) {
+        set_err("null value at row %lld", (long long)sc_host[1]);
         return PM4G_E_PARSE;
     }
     return PM4G_OK;

@@ -1,6 +1,8 @@
 // Internal interface between the C-ABI layer (api.hip) and the kernel files.
 #pragma once
 
+#include <vector>
+
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -389,5 +391,50 @@ hipError_t launch_csv_parse(const uint8_t* text, int64_t n_bytes, const pm4g_csv
                             int hash_bits, int64_t max_rows, CsvWs w, const pm4g_csv_out& o, hipStream_t s);
 hipError_t launch_csv_codes(CsvWs w, int64_t max_rows, const pm4g_csv_out& o, hipStream_t s);
 hipError_t launch_csv_finish(CsvWs w, const pm4g_csv_out& o, hipStream_t s);
+
+
+// ---- Parquet ingestion (parquet.hip) ----
+constexpr int64_t kPqMaxChunks = 3 * 65536;   // three columns of at most 65536 row groups
+// One column chunk of the three read (case, activity, timestamp) in one row group.
+struct PqChunk {
+    int64_t start, end;    // file offsets of its pages
+    int64_t num_values;    // = rows of the row group
+    int64_t row0;          // its first row
+    int64_t dict_base;     // its dictionary's entries in dict_a / dict_b
+    int32_t type;          // 1 INT32, 2 INT64, 6 BYTE_ARRAY
+    int32_t optional;      // definition levels present
+    int32_t col;           // 0 case, 1 activity, 2 timestamp
+    int32_t pad;
+};
+struct PqWs {
+    int64_t tsize;         // slots per value table (power of two, at least twice the rows)
+    int64_t max_rows;
+    int64_t* scal;         // [0] error status, [1] first null row, [2] hash collision, [3] rows,
+                           // [5] used slots, [8] tsize
+    PqChunk* chunks;
+    int64_t* dict_a;       // [3 * rows] dictionary entries: integer, or byte offset in the file
+    int32_t* dict_b;       //            -1, or byte length
+    int64_t* val_a;        // [2][rows] case and activity values, the same way
+    int32_t* val_b;
+    uint32_t* slot;        // [2][rows] table slot of each value
+    CsvSlot* table;        // [2][tsize]
+    uint32_t* used;
+    uint32_t* pos;
+    uint32_t *k0, *v0, *k1, *v1;
+    uint32_t* hist;
+    uint32_t* rowsum;
+    uint32_t* part32;
+};
+PqWs pq_ws_layout(Bump& b, int64_t max_rows);
+// Parses the file's metadata (meta: its len bytes, copied to the host) and
+// lists the chunks of columns cols[0..2]; PM4G_OK, or an error code with msg.
+int pq_parse_footer(const uint8_t* meta, int64_t len, int64_t file_bytes, const int32_t cols[3],
+                    std::vector<PqChunk>* chunks, int64_t* rows, char* msg, size_t msg_len);
+hipError_t launch_pq_decode(const uint8_t* file, PqWs w, int64_t n_chunks, int64_t rows, int64_t* ts_out,
+                            hipStream_t s);
+hipError_t launch_pq_match(const uint8_t* file, PqWs w, int64_t rows, uint64_t seed, int hash_bits,
+                           hipStream_t s);
+hipError_t launch_pq_codes(PqWs w, int64_t rows, const pm4g_csv_out& o, hipStream_t s);
+hipError_t launch_pq_finish(PqWs w, const pm4g_csv_out& o, hipStream_t s);
 
 }  // namespace pm4g

@@ -37,6 +37,7 @@ enum ProfId {
     P_EFG,
     P_SAMPLE,
     P_CSV,
+    P_PARQUET,
     P_COUNT
 };
 

@@ -30,6 +30,7 @@ PM4G_E_CAPACITY = -4
 PM4G_E_WORKSPACE = -5
 PM4G_E_DEVICE = -6
 PM4G_E_PARSE = -7
+PM4G_E_UNSUPPORTED = -8
 PM4G_PRESORTED = 1
 PM4G_MAX_ACTIVITIES = 4096
 
@@ -95,6 +96,11 @@ class CsvSchema(ctypes.Structure):
     _fields_ = [("case_col", ctypes.c_int32), ("act_col", ctypes.c_int32), ("ts_col", ctypes.c_int32),
                 ("has_header", ctypes.c_int32), ("ts_iso", ctypes.c_int32), ("ts_scale", ctypes.c_int32),
                 ("sep", ctypes.c_char), ("reserved", ctypes.c_char * 7)]
+
+
+class ParquetSchema(ctypes.Structure):
+    _fields_ = [("case_col", ctypes.c_int32), ("act_col", ctypes.c_int32), ("ts_col", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class _CsvOut(ctypes.Structure):
@@ -167,6 +173,13 @@ def load():
             L.pm4g_ingest_csv.argtypes = [_P, ctypes.c_int64, ctypes.POINTER(CsvSchema), ctypes.POINTER(_CsvOut), _P,
                                           ctypes.c_size_t, _P]
             L.pm4g_ingest_csv.restype = ctypes.c_int
+            L.pm4g_parquet_rows.argtypes = [_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _P]
+            L.pm4g_parquet_rows.restype = ctypes.c_int
+            L.pm4g_ingest_parquet_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64]
+            L.pm4g_ingest_parquet_workspace_bytes.restype = ctypes.c_size_t
+            L.pm4g_ingest_parquet.argtypes = [_P, ctypes.c_int64, ctypes.POINTER(ParquetSchema), ctypes.POINTER(_CsvOut),
+                                              _P, ctypes.c_size_t, _P]
+            L.pm4g_ingest_parquet.restype = ctypes.c_int
             L.pm4g_cases.argtypes = [ctypes.POINTER(_Prepared), _P, _P, _P]
             L.pm4g_cases.restype = ctypes.c_int
             L.pm4g_filter_cases_workspace_bytes.argtypes = [ctypes.c_int64]
@@ -629,6 +642,46 @@ def pm4g_ingest_csv(text: torch.Tensor, case_col: int, act_col: int, ts_col: int
                 _ptr(o["case_dict_off"]), _ptr(o["case_dict_len"]), _ptr(o["n_cases"]), _ptr(o["act_dict_off"]),
                 _ptr(o["act_dict_len"]), _ptr(o["n_acts"]), _ptr(o["status"]), _ptr(o["bad_row"]))
     _check(L.pm4g_ingest_csv(_ptr(text), n, ctypes.byref(sc), ctypes.byref(q), _ptr(ws), need, _stream(stream)))
+    r, c, a = int(o["n_rows"].item()), int(o["n_cases"].item()), int(o["n_acts"].item())
+    res = {k: o[k][:r] for k in ("case_code", "act_code", "ts")}
+    res.update(case_dict_off=o["case_dict_off"][:c], case_dict_len=o["case_dict_len"][:c],
+               act_dict_off=o["act_dict_off"][:a], act_dict_len=o["act_dict_len"][:a], n_rows=r, n_cases=c,
+               n_acts=a)
+    return res
+
+
+@_on_stream
+def pm4g_ingest_parquet(data: torch.Tensor, case_col: int, act_col: int, ts_col: int, capacity: int | None = None,
+                        stream=None) -> dict:
+    """Columns of a Parquet file held in a device uint8 tensor (leaf columns
+    case_col, act_col, ts_col): case_code and act_code (int32, first-appearance
+    order), ts (int64), and per code *_dict_off / *_dict_len (the byte range of
+    the value at the code's first row; for integer columns the value and -1);
+    counts as host ints.  Raises Pm4gError on a parse error (its message names
+    the row of a null), on a feature outside the covered subset, or when the
+    rows exceed capacity (default: the footer's row count)."""
+    L = load()
+    dev = data.device
+    n = int(data.numel())
+    s = _stream(stream)
+    if capacity is None:
+        rows = ctypes.c_int64(0)
+        _check(L.pm4g_parquet_rows(_ptr(data), n, ctypes.byref(rows), s))
+        capacity = int(rows.value)
+    cap = max(int(capacity), 1)
+    i32 = dict(dtype=torch.int32, device=dev)
+    i64 = dict(dtype=torch.int64, device=dev)
+    o = dict(case_code=torch.empty(cap, **i32), act_code=torch.empty(cap, **i32), ts=torch.empty(cap, **i64),
+             n_rows=torch.zeros(1, **i64), case_dict_off=torch.empty(cap, **i64), case_dict_len=torch.empty(cap, **i32),
+             n_cases=torch.zeros(1, **i64), act_dict_off=torch.empty(cap, **i64), act_dict_len=torch.empty(cap, **i32),
+             n_acts=torch.zeros(1, **i64), status=torch.zeros(1, **i32), bad_row=torch.zeros(1, **i64))
+    need = int(L.pm4g_ingest_parquet_workspace_bytes(n, int(capacity)))
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    sc = ParquetSchema(int(case_col), int(act_col), int(ts_col), 0)
+    q = _CsvOut(_ptr(o["case_code"]), _ptr(o["act_code"]), _ptr(o["ts"]), int(capacity), _ptr(o["n_rows"]),
+                _ptr(o["case_dict_off"]), _ptr(o["case_dict_len"]), _ptr(o["n_cases"]), _ptr(o["act_dict_off"]),
+                _ptr(o["act_dict_len"]), _ptr(o["n_acts"]), _ptr(o["status"]), _ptr(o["bad_row"]))
+    _check(L.pm4g_ingest_parquet(_ptr(data), n, ctypes.byref(sc), ctypes.byref(q), _ptr(ws), need, s))
     r, c, a = int(o["n_rows"].item()), int(o["n_cases"].item()), int(o["n_acts"].item())
     res = {k: o[k][:r] for k in ("case_code", "act_code", "ts")}
     res.update(case_dict_off=o["case_dict_off"][:c], case_dict_len=o["case_dict_len"][:c],

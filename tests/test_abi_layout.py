@@ -24,6 +24,7 @@ STRUCTS = {
     "pm4g_efg_out": pm4g._EfgOut,
     "pm4g_csv_schema": pm4g.CsvSchema,
     "pm4g_csv_out": pm4g._CsvOut,
+    "pm4g_parquet_schema": pm4g.ParquetSchema,
 }
 VIEW_FIELDS = ("case_lo", "case_hi", "t_lo", "t_hi")
 
