@@ -611,6 +611,16 @@ def bench_serving(logs: dict, preps: dict, seconds: float, rate: float, workers:
     sres = stress.run(copy.deepcopy(side), progress=log_progress)
     st["stress_budget"] = dict(serve.latency_stats(sres, stress), seconds=side_seconds,
                                budget_mib=stress_budget >> 20)
+    # a higher offered load on the same logs and mix: continuous batching
+    # against one request per launch on as many streams
+    hi_rate = 5 * rate
+    hi = serve.poisson_requests(np.random.default_rng(220404898 + 7), hi_rate, 5.0, info, A_of)
+    for label, mb in (("continuous_batching", 64), ("one_request_per_launch", 1)):
+        log_progress(f"serving: {hi_rate:.0f} queries/s, {label}")
+        hs = serve.Scheduler(ex, budget, max_batch=mb, workers=workers, max_batch_work=batch_work)
+        hres = hs.run(copy.deepcopy(hi), progress=log_progress)
+        st.setdefault("high_load", {})[label] = dict(serve.latency_stats(hres, hs), offered_qps=hi_rate, seconds=5.0,
+                                                      max_batch=mb, n_requests=len(hi))
     for nw in sorted({1, workers}):
         log_progress(f"serving: one request per launch, {nw} stream(s)")
         base = serve.Scheduler(ex, budget, max_batch=1, workers=nw)
@@ -741,7 +751,33 @@ def summarize_counters(a) -> None:
     print(path)
 
 
+def kernel_table(stats_csv: str) -> str:
+    """A markdown table of a rocprofv3 --stats kernel summary (kernel_stats.csv):
+    the kernels with their calls, average and total time, by total time."""
+    import csv
+    import re
+
+    rows = []
+    with open(stats_csv) as fh:
+        for r in csv.DictReader(fh):
+            name = r["Name"].replace("(anonymous namespace)::", "").replace("void ", "")
+            name = re.sub(r"\(.*\)$", "", name).replace("pm4g::", "")
+            rows.append((name, int(r["Calls"]), float(r["AverageNs"]) / 1e3, float(r["TotalDurationNs"]) / 1e6,
+                         float(r["Percentage"])))
+    rows.sort(key=lambda x: -x[3])
+    out = ["| kernel | calls | avg us | total ms | % of the run's kernel time |", "|---|---:|---:|---:|---:|"]
+    out += [f"| `{n}` | {c} | {a:.1f} | {t:.2f} | {p:.1f} |" for n, c, a, t, p in rows]
+    out.append("")
+    out.append(f"Sum of the listed kernels' time: {sum(r[3] for r in rows):.2f} ms over all calls.")
+    return "\n".join(out)
+
+
 def main() -> int:
+    if "--kernel-table" in sys.argv:
+        sp = argparse.ArgumentParser()
+        sp.add_argument("--kernel-table", required=True)
+        print(kernel_table(sp.parse_args().kernel_table))
+        return 0
     if "--calibrate-copy" in sys.argv:
         calibrate_copy()
         return 0

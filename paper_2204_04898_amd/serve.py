@@ -123,14 +123,14 @@ class Scheduler:
         done: list[Request] = []
         work: _queue.Queue = _queue.Queue()
 
-        def worker():
+        def worker(k: int):
             while True:
                 batch = work.get()
                 if batch is None:
                     return
-                self._serve(batch, t0, done)
+                self._serve(batch, t0, done, k)
 
-        threads = [threading.Thread(target=worker, daemon=True) for _ in range(self.workers)]
+        threads = [threading.Thread(target=worker, args=(k,), daemon=True) for k in range(self.workers)]
         for th in threads:
             th.start()
         i = 0
@@ -176,9 +176,9 @@ class Scheduler:
             th.join()
         return sorted(done, key=lambda r: r.rid)
 
-    def _serve(self, batch: list[Request], t0: float, done: list[Request]):
+    def _serve(self, batch: list[Request], t0: float, done: list[Request], worker: int = 0):
         try:
-            self.ex.run(batch)
+            self.ex.run(batch, worker)
         except Exception as e:  # reported per request; the server keeps going
             for r in batch:
                 r.error = f"{type(e).__name__}: {e}"
@@ -285,14 +285,17 @@ class GpuExecutor:
         for name, prep in logs.items():
             C = int(prep.n_cases.item())
             off = prep.case_off[:C + 1].cpu().numpy()
-            codes = prep.case_code[:C].cpu().numpy()
+            # int64, as the view bounds are: a search with a wider key would
+            # convert the whole array on every call
+            codes = prep.case_code[:C].cpu().numpy().astype(np.int64)
             self.logs[name] = dict(prep=prep, off=off, codes=codes)
-        self._local = threading.local()
+        self._streams: list = []   # one per worker index, kept across runs (and their memory pools)
+        self._streams_lock = threading.Lock()
 
     def slice_events(self, r: Request) -> int:
         lg = self.logs[r.log]
-        a = int(np.searchsorted(lg["codes"], r.case_lo, side="left"))
-        b = int(np.searchsorted(lg["codes"], r.case_hi, side="left"))
+        a = int(np.searchsorted(lg["codes"], np.int64(r.case_lo), side="left"))
+        b = int(np.searchsorted(lg["codes"], np.int64(r.case_hi), side="left"))
         return int(lg["off"][b] - lg["off"][a]) if b > a else 0
 
     def work(self, r: Request) -> int:
@@ -337,17 +340,18 @@ class GpuExecutor:
         t, edges = self._batched_tuning([r])
         return pm4g.batched_workspace_bytes(N, A, 1, t) + pm4g.batched_out_bytes(1, A, edges) + 256 * 2
 
-    def _stream(self):
-        s = getattr(self._local, "stream", None)
-        if s is None:
-            s = self.torch.cuda.Stream(device=self.device)
-            self._local.stream = s
-        return s
+    def _stream(self, worker: int):
+        """The HIP stream of worker `worker`: the same stream for that index in
+        every run, so the buffers its batches free stay cached for it."""
+        with self._streams_lock:
+            while len(self._streams) <= worker:
+                self._streams.append(self.torch.cuda.Stream(device=self.device))
+            return self._streams[worker]
 
-    def run(self, batch: list[Request]) -> None:
+    def run(self, batch: list[Request], worker: int = 0) -> None:
         torch = self.torch
         pm4g = self.pm4g
-        s = self._stream()
+        s = self._stream(worker)
         with torch.cuda.stream(s):
             by_log: dict[str, list[Request]] = {}
             for r in batch:

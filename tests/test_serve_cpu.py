@@ -22,7 +22,7 @@ class FakeExecutor:
     def estimate(self, r):
         return self.est(r)
 
-    def run(self, batch):
+    def run(self, batch, worker=0):
         with self.lock:
             self.concurrent += 1
             self.max_concurrent = max(self.max_concurrent, self.concurrent)
