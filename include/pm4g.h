@@ -11,7 +11,7 @@
  *     directly-follows graph; start/end activities; occurrences per
  *     activity.                                               -> pm4g_dfg
  *   - Sec. 3, variant level: cases grouped by their activity sequence
- *     (a double aggregation).                                 -> pm4g_variants
+ *     (an aggregation over the per-case aggregation).         -> pm4g_variants
  *   - Sec. 1 drill-down views combined with the Sec. 3 event-level timestamp
  *     filter and activity (attribute) filter, many views per launch
  *                                                             -> pm4g_dfg_batched

@@ -21,7 +21,7 @@
  *   endpoints  Sec. 3, start/end activities module, and the event-level
  *              count of each activity's events.
  *   variants   Sec. 3, variant-level aggregation (cases grouped by their
- *              activity sequence; a double aggregation).
+ *              activity sequence, an aggregation of the per-case one).
  *   views      Sec. 1 drill-down (filtered parts of the log), Sec. 3
  *              timestamp filter on events and attribute (activity) filter,
  *              composed as a conjunction; the DFG is re-discovered on the
