@@ -565,6 +565,60 @@ def bench_ingest(log, steps: int = 3) -> dict:
     return res
 
 
+def bench_parquet(log, steps: int = 3, oracle_rows: int = 2_000_000) -> dict:
+    """Parquet ingestion of a log written by pyarrow with its defaults
+    (dictionary-coded columns, 1 MiB data pages, no compression; string case
+    and activity names, ms timestamps), the file resident in device memory; the
+    oracle's reader timed on a file of the log's first rows beside it."""
+    import io
+
+    import numpy as np
+    import pyarrow as pa
+    import pyarrow.parquet as pq
+    import torch
+
+    import oracle
+    from paper_2204_04898_amd import pm4g
+
+    def parquet(lo, hi):
+        names = np.array([f"Activity {k:04d}" for k in range(log.n_activities)], dtype=object)
+        cases = np.char.add("case ", log.case[lo:hi].astype(str)).astype(object)
+        t = pa.table({"case:concept:name": pa.array(list(cases)),
+                      "concept:name": pa.array(list(names[log.act[lo:hi]])),
+                      "time:timestamp": pa.array(log.ts[lo:hi], pa.timestamp("ms"))})
+        buf = io.BytesIO()
+        pq.write_table(t, buf, compression="NONE")
+        return buf.getvalue()
+
+    data = parquet(0, log.n_events)
+    d = torch.frombuffer(bytearray(data), dtype=torch.uint8).to("cuda")
+    cap = log.n_events
+    r = pm4g.pm4g_ingest_parquet(d, 0, 1, 2, capacity=cap)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = pm4g.pm4g_ingest_parquet(d, 0, 1, 2, capacity=cap)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    algo = len(data) + 16 * r["n_rows"]   # the file read once, codes and timestamps written
+    res = {"ms_per_call": dt * 1e3, "bytes": len(data), "rows": r["n_rows"], "GB_per_s": len(data) / dt / 1e9,
+           "rows_per_s": r["n_rows"] / dt, "n_cases": r["n_cases"], "n_acts": r["n_acts"],
+           "algorithmic_bytes": algo, "achieved_GBps": algo / dt / 1e9,
+           "frac_of_hbm_peak": algo / dt / 1e9 / HBM_PEAK_GBS,
+           "layout": "pyarrow defaults without compression: dictionary pages (the case column falls back to "
+                     "PLAIN once its dictionary passes 1 MiB), 1 MiB data pages, row groups of 1Mi rows",
+           "note": "file resident in HBM; includes the footer read-back and the workspace allocation of the binding"}
+    m = min(oracle_rows, log.n_events)
+    small = parquet(0, m)
+    t1 = time.perf_counter()
+    o = oracle.ingest_parquet(small, 0, 1, 2)
+    odt = time.perf_counter() - t1
+    res["cpu_oracle"] = {"rows_per_s": o["n_rows"] / odt, "GB_per_s": len(small) / odt / 1e9, "cores": 1,
+                         "sample": f"the log's first {m} rows written the same way ({len(small)} bytes), "
+                                   f"single thread, {odt:.2f} s"}
+    return res
+
+
 def bench_serving(logs: dict, preps: dict, seconds: float, rate: float, workers: int = 4,
                   batch_work: int = 20_000_000, warmup_s: float = 5.0, stress_budget: int = 4 << 30,
                   side_seconds: float = 15.0) -> dict:
@@ -595,8 +649,10 @@ def bench_serving(logs: dict, preps: dict, seconds: float, rate: float, workers:
     serve.Scheduler(ex, budget, max_batch=64, workers=workers, max_batch_work=batch_work).run(warm)
     log_progress(f"serving: main run, {len(reqs)} requests over {seconds} s")
     sch = serve.Scheduler(ex, budget, max_batch=64, workers=workers, max_batch_work=batch_work)
+    ex.start_timeline()
     res = sch.run(copy.deepcopy(reqs), progress=log_progress)
     st = serve.latency_stats(res, sch)
+    st["device_overlap"] = dict(ex.timeline(), how="HIP events on each worker's stream around each batch")
     st.update(offered_qps=rate, seconds=seconds, warmup_seconds=warmup_s, n_requests=len(reqs),
               max_batch_work=batch_work, budget="90% of the HBM free after the logs are resident",
               variants_answer=f"variant count + first {ex.variants_top} variants",
@@ -606,11 +662,12 @@ def bench_serving(logs: dict, preps: dict, seconds: float, rate: float, workers:
     ids = {r.rid for r in side}
     st["main_run_first_part"] = dict(serve.latency_stats([r for r in res if r.rid in ids]),
                                      seconds=side_seconds, workers=workers, max_batch=64)
-    log_progress(f"serving: stress run, {stress_budget >> 20} MiB budget, {len(side)} requests")
-    stress = serve.Scheduler(ex, stress_budget, max_batch=64, workers=workers, max_batch_work=batch_work)
-    sres = stress.run(copy.deepcopy(side), progress=log_progress)
-    st["stress_budget"] = dict(serve.latency_stats(sres, stress), seconds=side_seconds,
-                               budget_mib=stress_budget >> 20)
+    for sb in (stress_budget, stress_budget // 4):
+        log_progress(f"serving: stress run, {sb >> 20} MiB budget, {len(side)} requests")
+        stress = serve.Scheduler(ex, sb, max_batch=64, workers=workers, max_batch_work=batch_work)
+        sres = stress.run(copy.deepcopy(side), progress=log_progress)
+        st.setdefault("stress_budget", {})[f"{sb >> 20}MiB"] = dict(serve.latency_stats(sres, stress),
+                                                                    seconds=side_seconds, budget_mib=sb >> 20)
     # a higher offered load on the same logs and mix: continuous batching
     # against one request per launch on as many streams
     hi_rate = 5 * rate
@@ -618,9 +675,11 @@ def bench_serving(logs: dict, preps: dict, seconds: float, rate: float, workers:
     for label, mb in (("continuous_batching", 64), ("one_request_per_launch", 1)):
         log_progress(f"serving: {hi_rate:.0f} queries/s, {label}")
         hs = serve.Scheduler(ex, budget, max_batch=mb, workers=workers, max_batch_work=batch_work)
+        ex.start_timeline()
         hres = hs.run(copy.deepcopy(hi), progress=log_progress)
         st.setdefault("high_load", {})[label] = dict(serve.latency_stats(hres, hs), offered_qps=hi_rate, seconds=5.0,
-                                                      max_batch=mb, n_requests=len(hi))
+                                                      max_batch=mb, n_requests=len(hi),
+                                                      device_overlap=ex.timeline())
     for nw in sorted({1, workers}):
         log_progress(f"serving: one request per launch, {nw} stream(s)")
         base = serve.Scheduler(ex, budget, max_batch=1, workers=nw)
@@ -751,9 +810,10 @@ def summarize_counters(a) -> None:
     print(path)
 
 
-def kernel_table(stats_csv: str) -> str:
+def kernel_table(stats_csv: str, match: str | None = None) -> str:
     """A markdown table of a rocprofv3 --stats kernel summary (kernel_stats.csv):
-    the kernels with their calls, average and total time, by total time."""
+    the kernels (those whose name matches the regular expression, if given)
+    with their calls, average and total time, by total time."""
     import csv
     import re
 
@@ -762,6 +822,8 @@ def kernel_table(stats_csv: str) -> str:
         for r in csv.DictReader(fh):
             name = r["Name"].replace("(anonymous namespace)::", "").replace("void ", "")
             name = re.sub(r"\(.*\)$", "", name).replace("pm4g::", "")
+            if match and not re.search(match, name):
+                continue
             rows.append((name, int(r["Calls"]), float(r["AverageNs"]) / 1e3, float(r["TotalDurationNs"]) / 1e6,
                          float(r["Percentage"])))
     rows.sort(key=lambda x: -x[3])
@@ -776,7 +838,9 @@ def main() -> int:
     if "--kernel-table" in sys.argv:
         sp = argparse.ArgumentParser()
         sp.add_argument("--kernel-table", required=True)
-        print(kernel_table(sp.parse_args().kernel_table))
+        sp.add_argument("--match", default=None, help="only kernels whose name matches this regular expression")
+        a = sp.parse_args()
+        print(kernel_table(a.kernel_table, a.match))
         return 0
     if "--calibrate-copy" in sys.argv:
         calibrate_copy()
@@ -811,7 +875,7 @@ def main() -> int:
     ap.add_argument("--tune-cache", default=None, help="autotune cache file (default: the package's)")
     ap.add_argument("--no-cases", action="store_true", help="skip the cases-dataframe and case-filter timing")
     ap.add_argument("--no-efg", action="store_true", help="skip the eventually-follows graph timing")
-    ap.add_argument("--no-ingest", action="store_true", help="skip the CSV ingestion timing")
+    ap.add_argument("--no-ingest", action="store_true", help="skip the CSV and Parquet ingestion timings")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="serving run length (0: skip)")
     ap.add_argument("--serve-warmup", type=float, default=5.0, help="serving warm-up run length")
     ap.add_argument("--serve-side-seconds", type=float, default=15.0,
@@ -979,6 +1043,13 @@ def main() -> int:
             log2 = synth.config_log(2)
         log_progress("CSV ingestion of the 10M-event log")
         out["ingest_csv"] = {"dfg-perf-10M": bench_ingest(log2)}
+        try:
+            import pyarrow  # noqa: F401
+        except ImportError:
+            out["ingest_parquet"] = {"skipped": "pyarrow is not importable"}
+        else:
+            log_progress("Parquet ingestion of the 10M-event log")
+            out["ingest_parquet"] = {"dfg-perf-10M": bench_parquet(log2)}
     if args.serve_seconds > 0 and k == 3:
         if prep2 is None:
             if log2 is None:

@@ -225,6 +225,7 @@ __global__ void k_csv_close(const uint8_t* __restrict__ text, int64_t n, CsvWs w
 // vector loads, except for the chunk that crosses the end of the text, which
 // is read byte by byte (nothing past the text is touched).
 struct Bytes {
+    static constexpr bool kStaged = false;
     const uint8_t* t;
     int64_t n;
     int64_t chunk;
@@ -373,6 +374,36 @@ struct ValueCursor {
     }
 };
 
+// The bytes of a staged field that holds no quote character, with one byte
+// of lookahead: the cursor of ValueCursor's interface without its unquoting.
+struct PlainCursor {
+    const uint8_t* s;   // the field's first byte in the stage
+    int64_t i, e;       // offsets from s
+    int c;
+    __device__ __forceinline__ PlainCursor(const uint8_t* first, int64_t len) : s(first), i(0), e(len), c(-1) {
+        adv();
+    }
+    __device__ __forceinline__ void adv() { c = i < e ? (int)s[i++] : -1; }
+    __device__ __forceinline__ bool end() const { return c < 0; }
+    __device__ __forceinline__ bool is(int ch) const { return c == ch; }
+    __device__ __forceinline__ bool digit() const { return c >= '0' && c <= '9'; }
+    __device__ __forceinline__ bool take(int ch) {
+        if (c != ch) return false;
+        adv();
+        return true;
+    }
+    __device__ __forceinline__ bool digits(int k, int64_t* out) {
+        int64_t x = 0;
+        for (int j = 0; j < k; ++j) {
+            if (!digit()) return false;
+            x = x * 10 + (c - '0');
+            adv();
+        }
+        *out = x;
+        return true;
+    }
+};
+
 template <class Cur>
 __device__ __forceinline__ bool iso_value(Cur& c, int scale, int64_t* out) {
     int64_t y, mo, d, hh = 0, mi = 0, ss = 0, frac = 0, off = 0;
@@ -467,15 +498,104 @@ __device__ __forceinline__ uint32_t insert(CsvSlot* tab, int64_t tsize, uint64_t
 
 // Bytes of the text already staged in LDS: [lo, lo + len) at stage[0..).
 struct StagedBytes {
+    static constexpr bool kStaged = true;
     const uint8_t* stage;
     int64_t lo;
     __device__ __forceinline__ uint8_t at(int64_t p) const { return stage[p - lo]; }
 };
 
+// Hash of a value: its bytes packed little-endian into 64-bit words (the last
+// one zero-padded), each folded in by xor and multiply, then the length and a
+// SplitMix64 finish.  Fed a byte at a time (quoted values, unwrapped) or a
+// word at a time (values without quotes): the same bytes give the same hash.
+struct ValueHash {
+    uint64_t h, acc;
+    uint32_t n;
+    __device__ __forceinline__ explicit ValueHash(uint64_t seed) : h(kFnvBasis ^ seed), acc(0), n(0) {}
+    __device__ __forceinline__ void byte(uint8_t x) {
+        acc |= (uint64_t)x << (8 * (n & 7));
+        if ((++n & 7) == 0) {
+            h = (h ^ acc) * kFnvPrime;
+            acc = 0;
+        }
+    }
+    __device__ __forceinline__ void word(uint64_t x) {   // eight bytes; n is a multiple of 8
+        h = (h ^ x) * kFnvPrime;
+        n += 8;
+    }
+    __device__ __forceinline__ uint64_t done(uint64_t seed, uint64_t mask) {
+        if (n & 7) h = (h ^ acc) * kFnvPrime;
+        return finish_hash(h ^ (uint64_t)n, seed, mask);
+    }
+};
+
+// Eight staged bytes from stage offset o: the two aligned words around them,
+// funnel-shifted (the stage keeps 16 bytes of room past its capacity).
+__device__ __forceinline__ uint64_t stage_word(const uint8_t* stage, int64_t o) {
+    const int64_t a = o & ~(int64_t)7;
+    const uint64_t* s64 = reinterpret_cast<const uint64_t*>(stage + a);
+    const int sh = (int)(o - a) * 8;
+    const uint64_t lo = s64[0];
+    return sh ? ((lo >> sh) | (s64[1] << (64 - sh))) : lo;
+}
+
+// 0x80 in each byte of x equal to the byte repeated in c8, 0 elsewhere.
+__device__ __forceinline__ uint64_t eq_bytes(uint64_t x, uint64_t c8) {
+    const uint64_t y = x ^ c8;
+    const uint64_t t = (y & 0x7F7F7F7F7F7F7F7Full) + 0x7F7F7F7F7F7F7F7Full;
+    return ~(t | y | 0x7F7F7F7F7F7F7F7Full);
+}
+
+// A staged row with no quote character, eight bytes at a time: separators
+// from byte masks, the case and activity values hashed a word at a time.
+// Fills the field ranges and hashes the byte walk would; false (nothing
+// written) when the row holds a quote.
+__device__ __forceinline__ bool split_fast(const uint8_t* stage, int64_t lo, int64_t a, int64_t e,
+                                           const pm4g_csv_schema& sc, int32_t need, uint64_t seed, uint64_t mask,
+                                           int64_t* fr, int32_t* nf, uint64_t* hc, uint64_t* ha) {
+    const uint64_t sep8 = 0x0101010101010101ull * (uint8_t)sc.sep;
+    const uint64_t quo8 = 0x0101010101010101ull * (uint8_t)'"';
+    for (int64_t p = a; p < e; p += 8)
+        if (eq_bytes(stage_word(stage, p - lo), quo8) & (e - p >= 8 ? ~0ull : ((1ull << (8 * (e - p))) - 1)))
+            return false;
+    int32_t f = 0;
+    int64_t fs = a;
+    for (int64_t p = a; p < e && f <= need; p += 8) {
+        uint64_t sm = eq_bytes(stage_word(stage, p - lo), sep8) & (e - p >= 8 ? ~0ull : ((1ull << (8 * (e - p))) - 1));
+        while (sm && f <= need) {
+            const int64_t i = p + (__builtin_ctzll(sm) >> 3);
+            if (f == sc.case_col) { fr[0] = fs; fr[1] = i; }
+            if (f == sc.act_col) { fr[2] = fs; fr[3] = i; }
+            if (f == sc.ts_col) { fr[4] = fs; fr[5] = i; }
+            ++f;
+            fs = i + 1;
+            sm &= sm - 1;
+        }
+    }
+    if (f <= need) {   // the end of the line closes the last field
+        if (f == sc.case_col) { fr[0] = fs; fr[1] = e; }
+        if (f == sc.act_col) { fr[2] = fs; fr[3] = e; }
+        if (f == sc.ts_col) { fr[4] = fs; fr[5] = e; }
+        ++f;
+    }
+    *nf = f;
+    if (f <= need) return true;
+    for (int k = 0; k < 2; ++k) {
+        const int64_t b = fr[2 * k], en = fr[2 * k + 1];
+        ValueHash hv(seed);
+        int64_t p = b;
+        for (; p + 8 <= en; p += 8) hv.word(stage_word(stage, p - lo));
+        for (; p < en; ++p) hv.byte(stage[p - lo]);
+        (k == 0 ? *hc : *ha) = hv.done(seed, mask);
+    }
+    return true;
+}
+
 // One walk over row r: fields split at separators outside quoted runs; the
 // case and activity values are hashed and the timestamp value copied as the
 // walk unwraps their runs (a doubled quote inside a run is one quote and
-// leaves the run open, as two toggles would).
+// leaves the run open, as two toggles would).  A staged row without quotes
+// takes split_fast instead of the byte walk.
 template <class Src>
 __device__ __forceinline__ void parse_row(Src B, int64_t r, int64_t a, int64_t e, const CsvWs w,
                                          const pm4g_csv_schema& sc, int32_t need, uint64_t seed, uint64_t mask,
@@ -485,8 +605,18 @@ __device__ __forceinline__ void parse_row(Src B, int64_t r, int64_t a, int64_t e
     while (a < e && (B.at(a) == '\n' || (B.at(a) == '\r' && a + 1 < e && B.at(a + 1) == '\n'))) ++a;
     if (e > a && B.at(e - 1) == '\r') --e;
     int64_t cb = -1, ce = -1, ab = -1, ae = -1, tb = -1, te = -1;
-    uint64_t h0 = kFnvBasis ^ seed, h1 = kFnvBasis ^ seed;
     int32_t f = 0;
+    uint64_t hc = 0, ha = 0;
+    bool fast = false;
+    if constexpr (Src::kStaged) {
+        int64_t fr[6] = {-1, -1, -1, -1, -1, -1};
+        fast = split_fast(B.stage, B.lo, a, e, sc, need, seed, mask, fr, &f, &hc, &ha);
+        if (fast) {
+            cb = fr[0]; ce = fr[1]; ab = fr[2]; ae = fr[3]; tb = fr[4]; te = fr[5];
+        }
+    }
+    if (!fast) {
+    ValueHash h0(seed), h1(seed);
     bool q = false;
     int64_t fs = a;
     for (int64_t i = a; i <= e; ++i) {
@@ -503,8 +633,8 @@ __device__ __forceinline__ void parse_row(Src B, int64_t r, int64_t a, int64_t e
                 }
             }
             if (lit || x != sep || q) {
-                if (f == sc.case_col) h0 = (h0 ^ x) * kFnvPrime;
-                if (f == sc.act_col) h1 = (h1 ^ x) * kFnvPrime;
+                if (f == sc.case_col) h0.byte(x);
+                if (f == sc.act_col) h1.byte(x);
                 continue;
             }
         }
@@ -515,6 +645,9 @@ __device__ __forceinline__ void parse_row(Src B, int64_t r, int64_t a, int64_t e
         ++f;
         fs = i + 1;
     }
+    hc = h0.done(seed, mask);
+    ha = h1.done(seed, mask);
+    }
     if (f <= need) {
         flag_bad(w, r);
         w.slot[2 * r] = w.slot[2 * r + 1] = 0;
@@ -522,15 +655,25 @@ __device__ __forceinline__ void parse_row(Src B, int64_t r, int64_t a, int64_t e
     }
     w.foff[2 * r] = cb;
     w.flen[2 * r] = (int32_t)(ce - cb);
-    w.slot[2 * r] = insert(w.table, w.tsize, finish_hash(h0, seed, mask), (uint32_t)r);
+    w.slot[2 * r] = insert(w.table, w.tsize, hc, (uint32_t)r);
     w.foff[2 * r + 1] = ab;
     w.flen[2 * r + 1] = (int32_t)(ae - ab);
-    w.slot[2 * r + 1] = insert(w.table + w.tsize, w.tsize, finish_hash(h1, seed, mask), (uint32_t)r);
+    w.slot[2 * r + 1] = insert(w.table + w.tsize, w.tsize, ha, (uint32_t)r);
     bool ok = te - tb <= kTsMax;
     if (ok) {
-        ValueCursor<Src> vc(B, tb, te);
         int64_t t;
-        ok = sc.ts_iso ? iso_value(vc, sc.ts_scale, &t) : int_value(vc, &t);
+        if constexpr (Src::kStaged) {
+            if (fast) {   // no quote in the row: the field's bytes are its value
+                PlainCursor pc(B.stage + (tb - B.lo), te - tb);
+                ok = sc.ts_iso ? iso_value(pc, sc.ts_scale, &t) : int_value(pc, &t);
+            } else {
+                ValueCursor<Src> vc(B, tb, te);
+                ok = sc.ts_iso ? iso_value(vc, sc.ts_scale, &t) : int_value(vc, &t);
+            }
+        } else {
+            ValueCursor<Src> vc(B, tb, te);
+            ok = sc.ts_iso ? iso_value(vc, sc.ts_scale, &t) : int_value(vc, &t);
+        }
         if (ok) ts_out[r] = t;
     }
     if (!ok) flag_bad(w, r);
@@ -544,7 +687,7 @@ constexpr int kStage = 32768;   // bytes of text staged per block of rows
 __global__ __launch_bounds__(256) void k_csv_parse(const uint8_t* __restrict__ text, int64_t n_bytes, CsvWs w,
                                                    pm4g_csv_schema sc, uint64_t seed, uint64_t mask,
                                                    int64_t* __restrict__ ts_out) {
-    __shared__ uint4 stage4[kStage / 16];
+    __shared__ uint4 stage4[kStage / 16 + 1];   // + 16 bytes of room for the word reads
     uint8_t* stage = reinterpret_cast<uint8_t*>(stage4);
     const int64_t rows = w.scal[2];
     const int64_t hdr = (sc.has_header && w.scal[1] > 0) ? 1 : 0;
@@ -585,15 +728,43 @@ __global__ __launch_bounds__(256) void k_csv_parse(const uint8_t* __restrict__ t
     }
 }
 
+// Eight bytes of the text from p: the two aligned words around them, funnel-
+// shifted (both words end before p + 16, which the caller keeps <= n).
+__device__ __forceinline__ uint64_t word_at(const uint8_t* __restrict__ text, int64_t p) {
+    const int64_t a = p & ~(int64_t)7;
+    const uint64_t* t64 = reinterpret_cast<const uint64_t*>(text + a);
+    const int sh = (int)(p - a) * 8;
+    const uint64_t lo = t64[0];
+    if (sh == 0) return lo;
+    const uint64_t hi = t64[1];
+    return (lo >> sh) | (hi << (64 - sh));
+}
+
+// Raw fields [b1, b1 + len) and [b2, b2 + len) byte for byte, eight at a time
+// (equal raw bytes are equal values; unequal ones may still be, by quoting).
+__device__ __forceinline__ bool raw_equal(const uint8_t* __restrict__ text, int64_t n, int64_t b1, int64_t b2,
+                                          int64_t len, bool aligned) {
+    int64_t i = 0;
+    if (aligned) {
+        for (; i + 8 <= len && b1 + i + 16 <= n && b2 + i + 16 <= n; i += 8)
+            if (word_at(text, b1 + i) != word_at(text, b2 + i)) return false;
+    }
+    for (; i < len; ++i)
+        if (text[b1 + i] != text[b2 + i]) return false;
+    return true;
+}
+
 __global__ __launch_bounds__(256) void k_csv_verify(const uint8_t* __restrict__ text, int64_t n_bytes, CsvWs w) {
     const int64_t rows = w.scal[2];
     if (w.scal[3] != INT64_MAX) return;   // a parse error ends the call
+    const bool aligned = (reinterpret_cast<uintptr_t>(text) & 7) == 0;
     for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < rows; r += (int64_t)gridDim.x * 256) {
         for (int k = 0; k < 2; ++k) {
             const uint32_t first = w.table[k * w.tsize + w.slot[2 * r + k]].first;
             if (first == (uint32_t)r) continue;
             const int64_t b1 = w.foff[2 * r + k], e1 = b1 + w.flen[2 * r + k];
             const int64_t b2 = w.foff[2 * (int64_t)first + k], e2 = b2 + w.flen[2 * (int64_t)first + k];
+            if (e1 - b1 == e2 - b2 && raw_equal(text, n_bytes, b1, b2, e1 - b1, aligned)) continue;
             Bytes B1(text, n_bytes), B2(text, n_bytes);
             if (!same_value(B1, b1, e1, B2, b2, e2)) w.scal[4] = 1;
         }

@@ -94,6 +94,7 @@ class Scheduler:
         room = self.budget - self._in_flight_bytes
         work = 0
         cap = self.max_batch_work
+        batchable = getattr(self.ex, "batchable", None)
         while queue and len(batch) < self.max_batch:
             r = queue[0]
             if r.est_bytes > room:
@@ -101,6 +102,10 @@ class Scheduler:
                     self.memory_blocked += 1
                 break
             if cap is not None and batch and work + r.est_work > cap:
+                break
+            # a request the executor cannot share a launch with runs in a batch
+            # of its own: it would only lengthen the batch of the others
+            if batchable is not None and batch and not (batchable(r) and batchable(batch[0])):
                 break
             room -= r.est_bytes
             work += r.est_work
@@ -298,6 +303,11 @@ class GpuExecutor:
         b = int(np.searchsorted(lg["codes"], np.int64(r.case_hi), side="left"))
         return int(lg["off"][b] - lg["off"][a]) if b > a else 0
 
+    def batchable(self, r: Request) -> bool:
+        """DFG and FILTER views of a batch share one batched launch; a VARIANTS
+        view runs its own filter and variants calls."""
+        return r.kind != "variants"
+
     def work(self, r: Request) -> int:
         """Work estimate: events of the view's case slice (variants cost about
         four passes over them)."""
@@ -348,10 +358,51 @@ class GpuExecutor:
                 self._streams.append(self.torch.cuda.Stream(device=self.device))
             return self._streams[worker]
 
+    def start_timeline(self) -> None:
+        """Records, from now on, each batch's device-side span: a HIP event on
+        its worker's stream before its first launch and after its last one,
+        against a reference event on the current stream."""
+        torch = self.torch
+        self._ref = torch.cuda.Event(enable_timing=True)
+        self._ref.record()
+        self._spans = []
+
+    def timeline(self) -> dict:
+        """Device-side overlap of the recorded batches: the time during which
+        batches of two or more workers were in progress on the GPU, over the
+        time during which any was."""
+        torch = self.torch
+        torch.cuda.synchronize()
+        ev = []
+        for w, a, b in self._spans:
+            t0, t1 = self._ref.elapsed_time(a), self._ref.elapsed_time(b)
+            ev.append((t0, 1, w))
+            ev.append((t1, -1, w))
+        ev.sort(key=lambda e: (e[0], e[1]))
+        open_: dict = {}
+        busy = multi = 0.0
+        last = ev[0][0] if ev else 0.0
+        for t, d, w in ev:
+            if open_:
+                busy += t - last
+                if len(open_) >= 2:
+                    multi += t - last
+            last = t
+            open_[w] = open_.get(w, 0) + d
+            if open_[w] == 0:
+                del open_[w]
+        self._spans = None
+        return {"batches": len(ev) // 2, "busy_ms": busy, "multi_worker_ms": multi,
+                "overlap_frac": multi / busy if busy else 0.0}
+
     def run(self, batch: list[Request], worker: int = 0) -> None:
         torch = self.torch
         pm4g = self.pm4g
         s = self._stream(worker)
+        spans = getattr(self, "_spans", None)
+        if spans is not None:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
         with torch.cuda.stream(s):
             by_log: dict[str, list[Request]] = {}
             for r in batch:
@@ -403,4 +454,7 @@ class GpuExecutor:
                 h["n_events"] = int(sub.case_off[C].item())
                 h["n_cases"] = C
                 r.result = h
+        if spans is not None:
+            e1.record(s)
+            spans.append((worker, e0, e1))
         s.synchronize()

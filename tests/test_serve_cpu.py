@@ -128,3 +128,22 @@ def test_tight_budget_queues_requests_by_memory():
     st = latency_stats(out, sch)
     assert st["wait_p99_ms"] > 20.0 and st["max_queue"] == sch.max_queue
     assert st["budget_bytes"] == 1000 and st["memory_blocked"] == sch.memory_blocked
+
+
+def test_unbatchable_requests_run_alone():
+    """Requests the executor cannot share a launch with form batches of their own."""
+    class Ex(FakeExecutor):
+        def batchable(self, r):
+            return r.kind != "variants"
+    ex = Ex(est=lambda r: 1, service_s=0.02)
+    rs = reqs(30, gap=0.0)
+    for r in rs[::3]:
+        r.kind = "variants"
+    sch = Scheduler(ex, mem_budget=10**9, max_batch=64, workers=1)
+    out = sch.run(rs)
+    assert all(r.error is None for r in out)
+    kind = {r.rid: r.kind for r in rs}
+    for b in sch.batches:
+        if any(kind[i] == "variants" for i in b):
+            assert len(b) == 1, b
+    assert max(len(b) for b in sch.batches) > 1
