@@ -84,22 +84,11 @@ size_t batched_ws_bytes(int64_t n, int32_t A, int32_t V, const BatchedTune& t) {
     return b.off + 256;
 }
 
-// Workspace of the formatting step.
-struct PrepWs {
-    RangeInfo* info;
-    RangePart* rpart;
-    SortBufs a, b;
-    uint32_t* hist;
-    uint32_t* hist_raw;
-    uint32_t* rowsum;
-    uint32_t* caseblk;
-    uint32_t* wincnt;
-};
+}  // namespace
 
-// with_rows: room for the original row of each element in both sort buffers
-// (pm4g_prepare's workspace has it; the raw-log DFG and variants calls do not
-// produce the permutation).
-PrepWs prep_ws_layout(Bump& bp, int64_t n, bool with_rows) {
+// with_rows: pm4g_prepare's workspace has the row room; the raw-log DFG and
+// variants calls do not produce the permutation.
+PrepWs pm4g::prep_ws_layout(Bump& bp, int64_t n, bool with_rows) {
     PrepWs w{};
     const size_t m = (size_t)(n > 0 ? n : 1);
     w.info = bp.take<RangeInfo>(1);
@@ -119,6 +108,8 @@ PrepWs prep_ws_layout(Bump& bp, int64_t n, bool with_rows) {
     w.wincnt = bp.take<uint32_t>((size_t)segsort_blocks(n) + 1);
     return w;
 }
+
+namespace {
 
 // Prepared-log arrays carved out of a workspace (raw-log entry points).
 pm4g_prepared prepared_in_ws(Bump& bp, int64_t n, int32_t A) {

@@ -61,6 +61,8 @@ CsvWs csv_ws_layout(Bump& b, int64_t n_bytes, int64_t max_rows) {
     w.qpar = b.take<uint32_t>(t1);
     w.qpre = b.take<uint32_t>(t1);
     w.lcnt = b.take<uint32_t>(t1);
+    w.lcnt1 = b.take<uint32_t>(t1);
+    w.emask = b.take<uint32_t>((t1 - 1) * kCTB);
     w.loff = b.take<int64_t>(t1);
     w.line_end = b.take<int64_t>(rows + 2);
     w.foff = b.take<int64_t>(2 * rows);
@@ -109,86 +111,122 @@ __global__ __launch_bounds__(256) void k_csv_clear(CsvWs w) {
     }
 }
 
-// The 16 bytes of thread t of a tile (zero past the end).
-__device__ __forceinline__ void load16(const uint8_t* __restrict__ text, int64_t n, int64_t p, uint8_t* b) {
+// High bit of each byte of x that equals the byte repeated in c8 (exact per
+// byte: the 7-bit add cannot carry into the next byte).
+__device__ __forceinline__ uint64_t eq_bytes(uint64_t x, uint64_t c8) {
+    const uint64_t y = x ^ c8;
+    const uint64_t t = (y & 0x7F7F7F7F7F7F7F7Full) + 0x7F7F7F7F7F7F7F7Full;
+    return ~(t | y | 0x7F7F7F7F7F7F7F7Full);
+}
+
+// The eight byte flags of eq_bytes as bits 0..7: after the shift, byte i's flag
+// is bit 8i; the multiplier's byte j holds 2^(7-j), so the products land on
+// distinct bits 8i + 7j + 7 (no carries) and i + j = 7 puts flag i at bit 56 + i.
+__device__ __forceinline__ uint32_t pack8(uint64_t m) {
+    return (uint32_t)(((m >> 7) * 0x0102040810204080ull) >> 56);
+}
+
+constexpr uint64_t kRep8 = 0x0101010101010101ull;
+
+// Bit k: byte k of the 16 (lo: bytes 0-7, hi: 8-15) equals ch.
+__device__ __forceinline__ uint32_t byte_mask16(uint64_t lo, uint64_t hi, uint8_t ch) {
+    return pack8(eq_bytes(lo, kRep8 * ch)) | (pack8(eq_bytes(hi, kRep8 * ch)) << 8);
+}
+
+// The 16 bytes at p as two little-endian words (zero past the end).
+__device__ __forceinline__ void load16w(const uint8_t* __restrict__ text, int64_t n, int64_t p, uint64_t* lo,
+                                        uint64_t* hi) {
     if (p + kCPer <= n && ((reinterpret_cast<uintptr_t>(text + p) & 15) == 0)) {
         const uint4 v = *reinterpret_cast<const uint4*>(text + p);
-        const uint32_t u[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int k = 0; k < 16; ++k) b[k] = (uint8_t)(u[k >> 2] >> (8 * (k & 3)));
+        *lo = (uint64_t)v.x | ((uint64_t)v.y << 32);
+        *hi = (uint64_t)v.z | ((uint64_t)v.w << 32);
     } else {
+        uint64_t a = 0, b = 0;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) b[k] = (p + k < n) ? text[p + k] : 0;
+        for (int k = 0; k < 8; ++k) {
+            if (p + k < n) a |= (uint64_t)text[p + k] << (8 * k);
+            if (p + 8 + k < n) b |= (uint64_t)text[p + 8 + k] << (8 * k);
+        }
+        *lo = a;
+        *hi = b;
     }
 }
 
-__global__ __launch_bounds__(kCTB) void k_csv_quotes(const uint8_t* __restrict__ text, int64_t n, CsvWs w) {
-    __shared__ uint32_t red[kCTB / kWave];
+// Inclusive prefix XOR of a 16-bit mask: bit k = parity of bits 0..k.
+__device__ __forceinline__ uint32_t prefix_xor16(uint32_t x) {
+    x ^= x << 1;
+    x ^= x << 2;
+    x ^= x << 4;
+    x ^= x << 8;
+    return x & 0xFFFFu;
+}
+
+// One pass over the text, tile by tile (16 bytes per thread): the tile's
+// quote parity, and the non-empty line ends outside quotes for both parities
+// the tile may start with (it is known only after the scan of the parities).
+// A line end is empty when the line is "" or "\r" after a line end; bytes
+// before the text count as line ends.  Writes qpar, lcnt (start outside
+// quotes), lcnt1 (inside) and each thread's two 16-bit end masks.
+__global__ __launch_bounds__(kCTB) void k_csv_scan_text(const uint8_t* __restrict__ text, int64_t n, CsvWs w) {
+    __shared__ uint32_t tmp[kCTB / kWave + 1];
     const int64_t tiles = w.scal[0];
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
-        uint8_t b[16];
-        load16(text, n, t * kCT + (int64_t)threadIdx.x * kCPer, b);
-        uint32_t q = 0;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) q += b[k] == '"';
-        q = wave_sum(q);
-        if (lane() == 0) red[threadIdx.x / kWave] = q;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t s = 0;
-            for (int k = 0; k < kCTB / kWave; ++k) s += red[k];
-            w.qpar[t] = s & 1u;
+        const int64_t p0 = t * kCT + (int64_t)threadIdx.x * kCPer;
+        uint64_t lo, hi;
+        load16w(text, n, p0, &lo, &hi);
+        const uint32_t qm = byte_mask16(lo, hi, '"');
+        const uint32_t nm = byte_mask16(lo, hi, '\n');
+        const uint32_t cm = byte_mask16(lo, hi, '\r');
+        // bytes p0 - 2 and p0 - 1: the top two of the thread below (DPP wave
+        // shift right by one); lane 0 reads them
+        uint32_t prev = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(hi >> 48), 0x138, 0xF, 0xF, false);
+        if (lane() == 0) {
+            prev = 0x0A0Au;   // before the text: line ends
+            if (p0 >= 2 && p0 - 1 < n) prev = (uint32_t)text[p0 - 2] | ((uint32_t)text[p0 - 1] << 8);
         }
-        __syncthreads();
+        const uint32_t pn = ((prev & 0xFFu) == '\n' ? 1u : 0u) | ((prev >> 8) == '\n' ? 2u : 0u);
+        const uint32_t pc = ((prev & 0xFFu) == '\r' ? 1u : 0u) | ((prev >> 8) == '\r' ? 2u : 0u);
+        const uint32_t en = (nm << 2) | pn;   // bit k + 2: byte k is a line end
+        const uint32_t ec = (cm << 2) | pc;
+        const uint32_t empty = ((en >> 1) | ((ec >> 1) & en)) & 0xFFFFu;
+        const uint32_t cand = nm & ~empty;   // bytes past the end are zero: no line ends
+        uint32_t qt;
+        const uint32_t qx = block_excl_sum<kCTB>((uint32_t)__popc(qm), tmp, &qt);
+        const uint32_t inq = ((qx & 1u) ? 0xFFFFu : 0u) ^ prefix_xor16(qm);   // inside quotes, tile starting outside
+        const uint32_t e0 = cand & ~inq, e1 = cand & inq;
+        uint32_t ct;
+        (void)block_excl_sum<kCTB>((uint32_t)__popc(e0) | ((uint32_t)__popc(e1) << 16), tmp, &ct);
+        w.emask[t * kCTB + threadIdx.x] = e0 | (e1 << 16);
+        if (threadIdx.x == 0) {
+            w.qpar[t] = qt & 1u;
+            w.lcnt[t] = ct & 0xFFFFu;
+            w.lcnt1[t] = ct >> 16;
+        }
     }
 }
 
-// Non-empty line ends of each tile: count (write == 0) or positions.
-__global__ __launch_bounds__(kCTB) void k_csv_lines(const uint8_t* __restrict__ text, int64_t n, CsvWs w,
-                                                    int write) {
+// Line ends of each tile for the parity it starts with.
+__global__ void k_csv_pick(CsvWs w) {
+    const int64_t tiles = w.scal[0];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tiles; t += (int64_t)gridDim.x * blockDim.x)
+        if (w.qpre[t] & 1u) w.lcnt[t] = w.lcnt1[t];
+}
+
+// Positions of the line ends, from the end masks.
+__global__ __launch_bounds__(kCTB) void k_csv_lines(CsvWs w) {
     __shared__ uint32_t tmp[kCTB / kWave + 1];
     const int64_t tiles = w.scal[0];
     const int64_t cap = w.scal[9];
     for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
         const int64_t p0 = t * kCT + (int64_t)threadIdx.x * kCPer;
-        uint8_t b[16];
-        load16(text, n, p0, b);
-        uint32_t q = 0;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) q += b[k] == '"';
-        uint32_t qt;
-        const uint32_t qx = block_excl_sum<kCTB>(q, tmp, &qt);
-        uint32_t par = (w.qpre[t] + qx) & 1u;
-        uint32_t ends = 0;   // bit k: byte k ends a non-empty line
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int64_t p = p0 + k;
-            if (p < n) {
-                if (b[k] == '"') {
-                    par ^= 1u;
-                } else if (b[k] == '\n' && par == 0) {
-                    // empty when the line is "" or "\r" after a line end (newlines
-                    // and carriage returns are not quotes: same parity)
-                    const uint8_t c1 = p >= 1 ? (k >= 1 ? b[k - 1] : text[p - 1]) : '\n';
-                    const uint8_t c2 = p >= 2 ? (k >= 2 ? b[k - 2] : text[p - 2]) : '\n';
-                    const bool empty = p == 0 || c1 == '\n' || (c1 == '\r' && (p == 1 || c2 == '\n'));
-                    if (!empty) ends |= 1u << k;
-                }
-            }
-        }
+        const uint32_t m = w.emask[t * kCTB + threadIdx.x];
+        uint32_t ends = (w.qpre[t] & 1u) ? (m >> 16) : (m & 0xFFFFu);
         uint32_t lt;
-        const uint32_t lx = block_excl_sum<kCTB>((uint32_t)__popc(ends), tmp, &lt);
-        if (!write) {
-            if (threadIdx.x == 0) w.lcnt[t] = lt;
-        } else {
-            int64_t r = w.loff[t] + lx;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                if ((ends >> k) & 1u) {
-                    if (r < cap) w.line_end[r] = p0 + k;
-                    ++r;
-                }
-            }
+        int64_t r = w.loff[t] + block_excl_sum<kCTB>((uint32_t)__popc(ends), tmp, &lt);
+        while (ends) {
+            if (r < cap) w.line_end[r] = p0 + __builtin_ctz(ends);
+            ++r;
+            ends &= ends - 1;
         }
     }
 }
@@ -540,11 +578,6 @@ __device__ __forceinline__ uint64_t stage_word(const uint8_t* stage, int64_t o) 
 }
 
 // 0x80 in each byte of x equal to the byte repeated in c8, 0 elsewhere.
-__device__ __forceinline__ uint64_t eq_bytes(uint64_t x, uint64_t c8) {
-    const uint64_t y = x ^ c8;
-    const uint64_t t = (y & 0x7F7F7F7F7F7F7F7Full) + 0x7F7F7F7F7F7F7F7Full;
-    return ~(t | y | 0x7F7F7F7F7F7F7F7Full);
-}
 
 // A staged row with no quote character, eight bytes at a time: separators
 // from byte masks, the case and activity values hashed a word at a time.
@@ -829,11 +862,12 @@ hipError_t launch_csv_lines(const uint8_t* text, int64_t n_bytes, int has_header
     const int64_t tiles = (n_bytes + kCT - 1) / kCT;
     const unsigned gt = (unsigned)(tiles < 2048 ? (tiles < 1 ? 1 : tiles) : 2048);
     k_csv_init<<<1, 1, 0, s>>>(w, n_bytes, max_rows + 1);
-    k_csv_quotes<<<gt, kCTB, 0, s>>>(text, n_bytes, w);
+    k_csv_scan_text<<<gt, kCTB, 0, s>>>(text, n_bytes, w);
     dev::excl_scan<uint32_t>(w.qpar, &w.scal[0], w.qpre, w.part32, reinterpret_cast<uint32_t*>(&w.scal[7]), s);
-    k_csv_lines<<<gt, kCTB, 0, s>>>(text, n_bytes, w, 0);
+    k_csv_pick<<<(unsigned)((tiles + 255) / 256 < 1024 ? ((tiles + 255) / 256 < 1 ? 1 : (tiles + 255) / 256) : 1024),
+                 256, 0, s>>>(w);
     dev::excl_scan<int64_t>(w.lcnt, &w.scal[0], w.loff, w.part64, &w.scal[1], s);
-    k_csv_lines<<<gt, kCTB, 0, s>>>(text, n_bytes, w, 1);
+    k_csv_lines<<<gt, kCTB, 0, s>>>(w);
     k_csv_close<<<1, 1, 0, s>>>(text, n_bytes, w, has_header, max_rows);
     return hipGetLastError();
 }

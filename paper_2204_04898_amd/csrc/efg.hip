@@ -37,13 +37,9 @@ namespace pm4g {
 
 namespace {
 
-constexpr int kEfgCells = 4096;          // cells of one LDS table
-constexpr int kEfgChunk = 4096;          // events per block pass when bucketing
-constexpr int kEfgPlanBlocks = 1024;     // plan entries spread over the pairs
 constexpr int kEfgAggGrid = 256;         // one block per CU (128 KB of LDS each)
 constexpr int kEB = 1024;                // threads of an aggregation block
 constexpr int64_t kEfgSeg = int64_t(1) << 31;   // pairs per LDS pass (u32 counters)
-constexpr int kSlotWords = 5 * kEfgCells;       // cnt, sum lo, sum hi, sq lo, sq hi
 
 }  // namespace
 

@@ -62,6 +62,22 @@ struct SortBufs {
     uint32_t* act;
     uint32_t* row;   // original row of each element; NULL when the row order is not carried
 };
+
+// Workspace of the formatting step (api.hip): range-scan header and partials,
+// the two radix buffers, digit histograms, case-table and window counts.
+struct PrepWs {
+    RangeInfo* info;
+    RangePart* rpart;
+    SortBufs a, b;
+    uint32_t* hist;
+    uint32_t* hist_raw;
+    uint32_t* rowsum;
+    uint32_t* caseblk;
+    uint32_t* wincnt;
+};
+// with_rows: room for the original row of each element in both sort buffers.
+PrepWs prep_ws_layout(Bump& bp, int64_t n, bool with_rows);
+
 constexpr int kRadixTile = 4096;
 inline int64_t radix_blocks(int64_t n) { return (n + kRadixTile - 1) / kRadixTile; }
 // One stable pass on an 8-bit digit.  digit_src 0: ((key & case bits) >> shift) & 255;
@@ -329,6 +345,10 @@ struct EfgOutDev {
     int64_t* n_pairs;
     int32_t* status;
 };
+constexpr int kEfgCells = 4096;          // cells of one LDS table
+constexpr int kEfgChunk = 4096;          // events per block pass when bucketing
+constexpr int kEfgPlanBlocks = 1024;     // plan entries spread over the pairs
+constexpr int kSlotWords = 5 * kEfgCells;   // partial table words: cnt, sum lo, sum hi, sq lo, sq hi
 int efg_rows(int32_t A);
 int64_t efg_buckets(int32_t A);
 EfgWs efg_ws_layout(Bump& b, int64_t n, int32_t A);
@@ -367,7 +387,9 @@ struct CsvWs {
     int64_t tsize;        // slots per table (power of two, at least twice the rows)
     uint32_t* qpar;       // [tiles] quote parity
     uint32_t* qpre;       // [tiles] parity before the tile
-    uint32_t* lcnt;       // [tiles] line ends
+    uint32_t* lcnt;       // [tiles] line ends (for the tile's starting quote parity once picked)
+    uint32_t* lcnt1;      // [tiles] line ends if the tile starts inside quotes
+    uint32_t* emask;      // [tiles][256] per-thread line-end masks: bits 0-15 starting outside quotes, 16-31 inside
     int64_t* loff;        // [tiles]
     int64_t* line_end;    // [rows + 2]
     int64_t* foff;        // [rows][2] raw field start (case, activity)
