@@ -534,20 +534,20 @@ int pm4g_ingest_csv(const uint8_t* text, int64_t n_bytes, const pm4g_csv_schema*
     Bump bp(ws);
     CsvWs w = csv_ws_layout(bp, n_bytes, out->capacity);
     PM4G_HIP(launch_csv_lines(text, n_bytes, sc->has_header, out->capacity, w, s));
+    // values are matched by 64-bit hash, then checked byte by byte; the code
+    // kernels do nothing after a parse or capacity error or a collision (two
+    // values, one hash), and a collision repeats the call with the next seed
     int64_t sc_host[16];
-    // values are matched by 64-bit hash, then checked byte by byte; a collision
-    // (two values, one hash) repeats the matching with the next seed
     for (uint64_t attempt = 0;; ++attempt) {
         PM4G_HIP(launch_csv_parse(text, n_bytes, *sc, 0x5851F42D4C957F2Dull * (attempt + 1),
                                   attempt == 0 ? g_csv_hash_bits : 0, out->capacity, w, *out, s));
+        PM4G_HIP(launch_csv_codes(w, out->capacity, *out, s));
+        PM4G_HIP(launch_csv_finish(w, *out, s));
         PM4G_HIP(hipMemcpyAsync(sc_host, w.scal, sizeof(sc_host), hipMemcpyDeviceToHost, s));
         PM4G_HIP(hipStreamSynchronize(s));
         if (sc_host[6] || sc_host[3] != INT64_MAX || !sc_host[4]) break;
         PM4G_CHECK(attempt < 8, "value hashes kept colliding");
     }
-    if (!sc_host[6] && sc_host[3] == INT64_MAX) PM4G_HIP(launch_csv_codes(w, out->capacity, *out, s));
-    PM4G_HIP(launch_csv_finish(w, *out, s));
-    PM4G_HIP(hipStreamSynchronize(s));
     if (sc_host[6]) {
         set_err("more than %lld data rows", (long long)out->capacity);
         return PM4G_E_CAPACITY;
@@ -652,17 +652,13 @@ int pm4g_ingest_parquet(const uint8_t* file, int64_t n_bytes, const pm4g_parquet
     if (!chunks.empty())
         PM4G_HIP(hipMemcpyAsync(w.chunks, chunks.data(), chunks.size() * sizeof(PqChunk), hipMemcpyHostToDevice, s));
     PM4G_HIP(launch_pq_decode(file, w, (int64_t)chunks.size(), rows, out->ts, s));
-    int64_t sc_host[16];
-    for (uint64_t attempt = 0;; ++attempt) {
-        PM4G_HIP(launch_pq_match(file, w, rows, 0x2545F4914F6CDD1Dull * (attempt + 1),
-                                 attempt == 0 ? g_csv_hash_bits : 0, s));
-        PM4G_HIP(hipMemcpyAsync(sc_host, w.scal, sizeof(sc_host), hipMemcpyDeviceToHost, s));
-        PM4G_HIP(hipStreamSynchronize(s));
-        if (sc_host[0] != 0 || sc_host[1] != INT64_MAX || !sc_host[2]) break;
-        PM4G_CHECK(attempt < 8, "value hashes kept colliding");
-    }
-    if (sc_host[0] == 0 && sc_host[1] == INT64_MAX) PM4G_HIP(launch_pq_codes(w, rows, *out, s));
+    // values matched by hash and compared as they enter the tables; the code
+    // kernels do nothing after a decode error or a null
+    PM4G_HIP(launch_pq_match(file, w, rows, 0x2545F4914F6CDD1Dull, g_csv_hash_bits, s));
+    PM4G_HIP(launch_pq_codes(w, rows, *out, s));
     PM4G_HIP(launch_pq_finish(w, *out, s));
+    int64_t sc_host[16];
+    PM4G_HIP(hipMemcpyAsync(sc_host, w.scal, sizeof(sc_host), hipMemcpyDeviceToHost, s));
     PM4G_HIP(hipStreamSynchronize(s));
     if (sc_host[0] != 0) {
         set_err("%s", sc_host[0] == PM4G_E_UNSUPPORTED ? "a page encoding outside the covered subset"

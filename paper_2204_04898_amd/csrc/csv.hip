@@ -14,21 +14,24 @@
 //             date-times in units of 10^-scale s.
 //
 // Kernels:
-//   k_csv_quotes     per 4096-byte tile: the parity of its quote characters
-//   scan             quote parity at each tile's start
-//   k_csv_lines      per tile: ends of non-empty lines (newlines at even
-//                    parity), counted, then written in order after a scan
+//   k_csv_scan_text  per 4096-byte tile: quote parity, and the ends of
+//                    non-empty lines for both quote states the tile may start
+//                    in (16-bit masks per 16 bytes)
+//   scan             quote parity at each tile's start; line counts of the
+//                    state each tile starts in; their scan
+//   k_csv_lines      line-end positions from the masks
 //   k_csv_close      the unterminated last line, row count, capacity
 //   k_csv_parse      a thread per data row: field ranges, value hashes, the
 //                    timestamp; values enter open-addressing tables keyed by
-//                    64-bit hash, each slot keeping its first row
+//                    64-bit hash, each slot keeping its first row; the slots
+//                    claimed (one per distinct value) are listed per table
 //   k_csv_verify     every row's value against its slot's first row, byte by
 //                    byte (a hash collision is detected, and the call is
 //                    repeated with another hash seed)
-//   codes            the used slots sorted by first row: the code is the rank
+//   codes            the listed slots sorted by first row: the code is the rank
 //   k_csv_emit       codes per row
-// Bytes: the text is read three times by the tile passes and once more by the
-// row pass (plus the first rows' values once); 16 B/row written.
+// Bytes: the text is read once by the tile pass and once more by the row
+// pass (plus the first rows' values once); 16 B/row written.
 #include "common.hpp"
 #include "devsort.hpp"
 #include "internal.hpp"
@@ -69,8 +72,8 @@ CsvWs csv_ws_layout(Bump& b, int64_t n_bytes, int64_t max_rows) {
     w.flen = b.take<int32_t>(2 * rows);
     w.slot = b.take<uint32_t>(2 * rows);
     w.table = b.take<CsvSlot>((size_t)(2 * w.tsize));
-    w.used = b.take<uint32_t>((size_t)w.tsize);
-    w.pos = b.take<uint32_t>((size_t)w.tsize);
+    w.max_rows = (int64_t)rows;
+    w.dlist = b.take<uint32_t>(2 * rows);
     w.k0 = b.take<uint32_t>(rows);
     w.v0 = b.take<uint32_t>(rows);
     w.k1 = b.take<uint32_t>(rows);
@@ -88,7 +91,8 @@ namespace {
 // scal: [0] tiles, [1] lines found by the tile pass, [2] data rows, [3] first
 // bad row (INT64_MAX: none), [4] hash collision seen, [5] distinct values (case
 // table, then activity table), [6] rows over capacity, [7] quote parity at
-// the end, [8] table slots, [9] line capacity
+// the end, [8] table slots, [9] line capacity, [10], [11] slots listed in the
+// case and activity tables
 __global__ void k_csv_init(CsvWs w, int64_t n_bytes, int64_t max_lines) {
     w.scal[0] = (n_bytes + kCT - 1) / kCT;
     w.scal[1] = 0;
@@ -100,10 +104,16 @@ __global__ void k_csv_init(CsvWs w, int64_t n_bytes, int64_t max_lines) {
     w.scal[7] = 0;
     w.scal[8] = w.tsize;
     w.scal[9] = max_lines;
+    w.scal[10] = 0;
+    w.scal[11] = 0;
 }
 
 __global__ __launch_bounds__(256) void k_csv_clear(CsvWs w) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) w.scal[4] = 0;   // collision flag of this attempt
+    if (blockIdx.x == 0 && threadIdx.x == 0) {   // this attempt's retry flag and slot lists
+        w.scal[4] = 0;
+        w.scal[10] = 0;
+        w.scal[11] = 0;
+    }
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < 2 * w.tsize; i += (int64_t)gridDim.x * 256) {
         w.table[i].hash = 0;
         w.table[i].first = 0xffffffffu;
@@ -513,18 +523,47 @@ __device__ __forceinline__ void flag_bad(const CsvWs& w, int64_t r) {
     atomicMin(reinterpret_cast<unsigned long long*>(&w.scal[3]), (unsigned long long)r);
 }
 
+// Eight bytes of the text from p: the two aligned words around them, funnel-
+// shifted (both words end before p + 16, which the caller keeps <= n).
+__device__ __forceinline__ uint64_t word_at(const uint8_t* __restrict__ text, int64_t p) {
+    const int64_t a = p & ~(int64_t)7;
+    const uint64_t* t64 = reinterpret_cast<const uint64_t*>(text + a);
+    const int sh = (int)(p - a) * 8;
+    const uint64_t lo = t64[0];
+    if (sh == 0) return lo;
+    const uint64_t hi = t64[1];
+    return (lo >> sh) | (hi << (64 - sh));
+}
+
+// Raw fields [b1, b1 + len) and [b2, b2 + len) byte for byte, eight at a time
+// (equal raw bytes are equal values; unequal ones may still be, by quoting).
+__device__ __forceinline__ bool raw_equal(const uint8_t* __restrict__ text, int64_t n, int64_t b1, int64_t b2,
+                                          int64_t len, bool aligned) {
+    int64_t i = 0;
+    if (aligned) {
+        for (; i + 8 <= len && b1 + i + 16 <= n && b2 + i + 16 <= n; i += 8)
+            if (word_at(text, b1 + i) != word_at(text, b2 + i)) return false;
+    }
+    for (; i < len; ++i)
+        if (text[b1 + i] != text[b2 + i]) return false;
+    return true;
+}
+
 // Slot of value hash h in table `tab` (linear probing); the slot keeps the
 // smallest row that holds the value.  A slot is read before any atomic: a
 // value already in the table (nearly every row) costs no atomic unless this
 // row is smaller than the first row seen, so hot values (few activities over
-// millions of rows) do not serialise on their slot.
-__device__ __forceinline__ uint32_t insert(CsvSlot* tab, int64_t tsize, uint64_t h, uint32_t r) {
+// millions of rows) do not serialise on their slot.  Sets *claimed when this
+// row's compare-and-swap took an empty slot (the value's first insert).
+__device__ __forceinline__ uint32_t insert(CsvSlot* tab, int64_t tsize, uint64_t h, uint32_t r, bool* claimed) {
     uint64_t i = h & (uint64_t)(tsize - 1);
     for (;;) {   // the table has more slots than rows: an empty or equal slot exists
         unsigned long long cur = __hip_atomic_load(reinterpret_cast<unsigned long long*>(&tab[i].hash),
                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (cur == 0)
+        if (cur == 0) {
             cur = atomicCAS(reinterpret_cast<unsigned long long*>(&tab[i].hash), 0ull, (unsigned long long)h);
+            *claimed = cur == 0;
+        }
         if (cur == 0 || cur == h) {
             if (r < __hip_atomic_load(&tab[i].first, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
                 atomicMin(&tab[i].first, r);
@@ -632,7 +671,7 @@ __device__ __forceinline__ bool split_fast(const uint8_t* stage, int64_t lo, int
 template <class Src>
 __device__ __forceinline__ void parse_row(Src B, int64_t r, int64_t a, int64_t e, const CsvWs w,
                                          const pm4g_csv_schema& sc, int32_t need, uint64_t seed, uint64_t mask,
-                                         int64_t* __restrict__ ts_out) {
+                                         int64_t* __restrict__ ts_out, bool* claimed) {
     const uint8_t sep = (uint8_t)sc.sep;
     // skip the empty lines in between ("\n" or "\r\n" each)
     while (a < e && (B.at(a) == '\n' || (B.at(a) == '\r' && a + 1 < e && B.at(a + 1) == '\n'))) ++a;
@@ -688,10 +727,10 @@ __device__ __forceinline__ void parse_row(Src B, int64_t r, int64_t a, int64_t e
     }
     w.foff[2 * r] = cb;
     w.flen[2 * r] = (int32_t)(ce - cb);
-    w.slot[2 * r] = insert(w.table, w.tsize, hc, (uint32_t)r);
     w.foff[2 * r + 1] = ab;
     w.flen[2 * r + 1] = (int32_t)(ae - ab);
-    w.slot[2 * r + 1] = insert(w.table + w.tsize, w.tsize, ha, (uint32_t)r);
+    w.slot[2 * r] = insert(w.table, w.tsize, hc, (uint32_t)r, &claimed[0]);
+    w.slot[2 * r + 1] = insert(w.table + w.tsize, w.tsize, ha, (uint32_t)r, &claimed[1]);
     bool ok = te - tb <= kTsMax;
     if (ok) {
         int64_t t;
@@ -721,6 +760,9 @@ __global__ __launch_bounds__(256) void k_csv_parse(const uint8_t* __restrict__ t
                                                    pm4g_csv_schema sc, uint64_t seed, uint64_t mask,
                                                    int64_t* __restrict__ ts_out) {
     __shared__ uint4 stage4[kStage / 16 + 1];   // + 16 bytes of room for the word reads
+    __shared__ uint32_t s_new[2][256];   // slots this block's rows claimed, per table
+    __shared__ uint32_t s_cnt[2];
+    __shared__ int64_t s_base[2];
     uint8_t* stage = reinterpret_cast<uint8_t*>(stage4);
     const int64_t rows = w.scal[2];
     const int64_t hdr = (sc.has_header && w.scal[1] > 0) ? 1 : 0;
@@ -728,6 +770,7 @@ __global__ __launch_bounds__(256) void k_csv_parse(const uint8_t* __restrict__ t
                                                    : (sc.act_col > sc.ts_col ? sc.act_col : sc.ts_col);
     const bool vec = (reinterpret_cast<uintptr_t>(text) & 15) == 0;
     for (int64_t r0 = (int64_t)blockIdx.x * 256; r0 < rows; r0 += (int64_t)gridDim.x * 256) {
+        if (threadIdx.x < 2) s_cnt[threadIdx.x] = 0;
         const int64_t rl = (r0 + 255 < rows ? r0 + 255 : rows - 1);
         const int64_t li0 = r0 + hdr, lil = rl + hdr;
         const int64_t lo = (li0 == 0 ? 0 : w.line_end[li0 - 1] + 1) & ~(int64_t)15;
@@ -745,48 +788,37 @@ __global__ __launch_bounds__(256) void k_csv_parse(const uint8_t* __restrict__ t
         }
         __syncthreads();
         const int64_t r = r0 + threadIdx.x;
+        bool claimed[2] = {false, false};
         if (r < rows) {
             const int64_t li = r + hdr;
             const int64_t a = li == 0 ? 0 : w.line_end[li - 1] + 1;
             const int64_t e = w.line_end[li];
             if (staged) {
                 StagedBytes SB{stage, lo};
-                parse_row(SB, r, a, e, w, sc, need, seed, mask, ts_out);
+                parse_row(SB, r, a, e, w, sc, need, seed, mask, ts_out, claimed);
             } else {
                 Bytes B(text, n_bytes);
-                parse_row(B, r, a, e, w, sc, need, seed, mask, ts_out);
+                parse_row(B, r, a, e, w, sc, need, seed, mask, ts_out, claimed);
             }
         }
+        // list the claimed slots: one global reservation per table and block pass
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+            if (claimed[k]) s_new[k][atomicAdd(&s_cnt[k], 1u)] = w.slot[2 * r + k];
+        __syncthreads();
+        if (threadIdx.x < 2)
+            s_base[threadIdx.x] = (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(&w.scal[10 + threadIdx.x]),
+                                                     (unsigned long long)s_cnt[threadIdx.x]);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+            for (uint32_t j = threadIdx.x; j < s_cnt[k]; j += 256) w.dlist[k * w.max_rows + s_base[k] + j] = s_new[k][j];
         __syncthreads();
     }
 }
 
-// Eight bytes of the text from p: the two aligned words around them, funnel-
-// shifted (both words end before p + 16, which the caller keeps <= n).
-__device__ __forceinline__ uint64_t word_at(const uint8_t* __restrict__ text, int64_t p) {
-    const int64_t a = p & ~(int64_t)7;
-    const uint64_t* t64 = reinterpret_cast<const uint64_t*>(text + a);
-    const int sh = (int)(p - a) * 8;
-    const uint64_t lo = t64[0];
-    if (sh == 0) return lo;
-    const uint64_t hi = t64[1];
-    return (lo >> sh) | (hi << (64 - sh));
-}
-
-// Raw fields [b1, b1 + len) and [b2, b2 + len) byte for byte, eight at a time
-// (equal raw bytes are equal values; unequal ones may still be, by quoting).
-__device__ __forceinline__ bool raw_equal(const uint8_t* __restrict__ text, int64_t n, int64_t b1, int64_t b2,
-                                          int64_t len, bool aligned) {
-    int64_t i = 0;
-    if (aligned) {
-        for (; i + 8 <= len && b1 + i + 16 <= n && b2 + i + 16 <= n; i += 8)
-            if (word_at(text, b1 + i) != word_at(text, b2 + i)) return false;
-    }
-    for (; i < len; ++i)
-        if (text[b1 + i] != text[b2 + i]) return false;
-    return true;
-}
-
+// Every row's value against its slot's first row, byte by byte: equal values,
+// or a hash collision (scal[4]: the call is repeated with another seed).
 __global__ __launch_bounds__(256) void k_csv_verify(const uint8_t* __restrict__ text, int64_t n_bytes, CsvWs w) {
     const int64_t rows = w.scal[2];
     if (w.scal[3] != INT64_MAX) return;   // a parse error ends the call
@@ -804,19 +836,19 @@ __global__ __launch_bounds__(256) void k_csv_verify(const uint8_t* __restrict__ 
     }
 }
 
-__global__ __launch_bounds__(256) void k_csv_used(CsvWs w, int k) {
+// The slots listed for table k with their first rows, to sort; their number
+// goes to scal[5] (none after a capacity or parse error or a collision).
+__global__ __launch_bounds__(256) void k_csv_gather(CsvWs w, int k) {
+    const bool failed = w.scal[6] != 0 || w.scal[3] != INT64_MAX || w.scal[4] != 0;
+    const int64_t D = failed ? 0 : w.scal[10 + k];
+    if (blockIdx.x == 0 && threadIdx.x == 0) w.scal[5] = D;
+    const uint32_t* dl = w.dlist + k * w.max_rows;
     const CsvSlot* tab = w.table + k * w.tsize;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < w.tsize; i += (int64_t)gridDim.x * 256)
-        w.used[i] = tab[i].hash != 0 ? 1u : 0u;
-}
-
-__global__ __launch_bounds__(256) void k_csv_list(CsvWs w, int k, const uint32_t* __restrict__ pos) {
-    const CsvSlot* tab = w.table + k * w.tsize;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < w.tsize; i += (int64_t)gridDim.x * 256)
-        if (w.used[i]) {
-            w.k0[pos[i]] = tab[i].first;
-            w.v0[pos[i]] = (uint32_t)i;
-        }
+    for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < D; d += (int64_t)gridDim.x * 256) {
+        const uint32_t i = dl[d];
+        w.k0[d] = tab[i].first;
+        w.v0[d] = i;
+    }
 }
 
 // Sorted by first row: the code of a slot is its rank.
@@ -836,6 +868,7 @@ __global__ __launch_bounds__(256) void k_csv_codes(CsvWs w, int k, const uint32_
 
 __global__ __launch_bounds__(256) void k_csv_emit(CsvWs w, int32_t* __restrict__ case_code,
                                                   int32_t* __restrict__ act_code) {
+    if (w.scal[6] != 0 || w.scal[3] != INT64_MAX || w.scal[4] != 0) return;
     const int64_t rows = w.scal[2];
     for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < rows; r += (int64_t)gridDim.x * 256) {
         case_code[r] = (int32_t)w.table[w.slot[2 * r]].code;
@@ -883,14 +916,11 @@ hipError_t launch_csv_parse(const uint8_t* text, int64_t n_bytes, const pm4g_csv
 }
 
 hipError_t launch_csv_codes(CsvWs w, int64_t max_rows, const pm4g_csv_out& o, hipStream_t s) {
-    const int64_t ts = w.tsize;
-    const unsigned gs = (unsigned)((ts + 255) / 256 < 2048 ? (ts + 255) / 256 : 2048);
+    int bits = 8;   // first rows are below max_rows: sort on that many bits
+    while (bits < 32 && (int64_t(1) << bits) < max_rows) bits += 8;
     for (int k = 0; k < 2; ++k) {
-        k_csv_used<<<gs, 256, 0, s>>>(w, k);
-        // positions of the used slots (one per table slot); their number -> scal[5]
-        dev::excl_scan<uint32_t>(w.used, &w.scal[8], w.pos, w.part32, reinterpret_cast<uint32_t*>(&w.scal[5]), s);
-        k_csv_list<<<gs, 256, 0, s>>>(w, k, w.pos);
-        const bool flip = dev::sort_pairs<uint32_t>(w.k0, w.v0, w.k1, w.v1, &w.scal[5], max_rows, 32, w.hist,
+        k_csv_gather<<<grid_rows(max_rows), 256, 0, s>>>(w, k);
+        const bool flip = dev::sort_pairs<uint32_t>(w.k0, w.v0, w.k1, w.v1, &w.scal[5], max_rows, bits, w.hist,
                                                     w.rowsum, s);
         const uint32_t* key = flip ? w.k1 : w.k0;
         const uint32_t* val = flip ? w.v1 : w.v0;

@@ -379,7 +379,7 @@ hipError_t launch_sample_cases(const pm4g_prepared* p, uint64_t seed, const SelS
 
 // ---- CSV ingestion (csv.hip) ----
 struct CsvSlot {
-    uint64_t hash;    // 0: empty
+    uint64_t hash;    // 0: empty; CSV: the value's 64-bit hash; Parquet: (upper 32 hash bits | 1) << 32 | claiming row
     uint32_t first;   // first row holding the value
     uint32_t code;
 };
@@ -396,8 +396,8 @@ struct CsvWs {
     int32_t* flen;        // [rows][2] raw field length
     uint32_t* slot;       // [rows][2] table slot
     CsvSlot* table;       // [2][tsize] case table, activity table
-    uint32_t* used;       // [tsize] slot holds a value
-    uint32_t* pos;        // [tsize] its rank among the used slots
+    int64_t max_rows;
+    uint32_t* dlist;      // [2][max_rows] slots claimed in each table (the distinct values)
     uint32_t *k0, *v0, *k1, *v1;   // [rows] (first row, slot) pairs to sort
     uint32_t* hist;
     uint32_t* rowsum;
@@ -431,8 +431,8 @@ struct PqChunk {
 struct PqWs {
     int64_t tsize;         // slots per value table (power of two, at least twice the rows)
     int64_t max_rows;
-    int64_t* scal;         // [0] error status, [1] first null row, [2] hash collision, [3] rows,
-                           // [5] used slots, [8] tsize
+    int64_t* scal;         // [0] error status, [1] first null row, [3] rows, [5] slots listed,
+                           // [8] tsize, [10], [11] slots claimed in the case, activity tables
     PqChunk* chunks;
     int64_t* dict_a;       // [3 * rows] dictionary entries: integer, or byte offset in the file
     int32_t* dict_b;       //            -1, or byte length
@@ -440,8 +440,7 @@ struct PqWs {
     int32_t* val_b;
     uint32_t* slot;        // [2][rows] table slot of each value
     CsvSlot* table;        // [2][tsize]
-    uint32_t* used;
-    uint32_t* pos;
+    uint32_t* dlist;       // [2][max_rows] slots claimed in each table (the distinct values)
     uint32_t *k0, *v0, *k1, *v1;
     uint32_t* hist;
     uint32_t* rowsum;

@@ -335,8 +335,7 @@ PqWs pq_ws_layout(Bump& b, int64_t max_rows) {
     w.val_b = b.take<int32_t>(2 * rows);
     w.slot = b.take<uint32_t>(2 * rows);
     w.table = b.take<CsvSlot>((size_t)(2 * w.tsize));
-    w.used = b.take<uint32_t>((size_t)w.tsize);
-    w.pos = b.take<uint32_t>((size_t)w.tsize);
+    w.dlist = b.take<uint32_t>(2 * rows);
     w.k0 = b.take<uint32_t>(rows);
     w.v0 = b.take<uint32_t>(rows);
     w.k1 = b.take<uint32_t>(rows);
@@ -353,6 +352,8 @@ namespace {
 
 constexpr int kPB = 256;        // threads per decode block
 constexpr int kRuns = 256;      // hybrid runs read ahead per round
+constexpr int kHdrStage = 512;  // page-header bytes staged in LDS for the parse
+constexpr int kPageSplit = 64;  // blocks per column chunk, each decoding every 64th data page
 
 __device__ __forceinline__ int64_t le_int(const uint8_t* p, int bytes) {
     uint64_t v = 0;
@@ -403,8 +404,8 @@ struct HdrIn {
         last = d ? last + d : (int)svar();
         return t;
     }
-    // a scalar, binary, or list / set of them (page statistics and friends)
-    __device__ void skip_flat(int t, bool element) {
+    // a scalar or binary (an element of a list when `element`: booleans take a byte)
+    __device__ __forceinline__ void skip_scalar(int t, bool element) {
         switch (t) {
             case 1:
             case 2:
@@ -421,26 +422,58 @@ struct HdrIn {
                 else p += (int64_t)len;
                 break;
             }
-            case 9:
-            case 10: {
-                const uint8_t h = byte();
-                uint64_t n = h >> 4;
-                if (n == 15) n = uvar();
-                if (n > (uint64_t)(end - p)) bad = true;
-                for (uint64_t k = 0; k < n && !bad; ++k) skip_flat(h & 15, true);
-                break;
-            }
-            default: bad = true;   // maps and deeper nesting do not occur in page headers
+            default: bad = true;
         }
         if (p > end) bad = true;
     }
-    // a struct whose fields are flat values or structs of flat values
-    __device__ void skip_struct(int depth) {
+    // a list / set header: element type and count
+    __device__ __forceinline__ int list_head(uint64_t* n) {
+        const uint8_t h = byte();
+        *n = h >> 4;
+        if (*n == 15) *n = uvar();
+        if (*n > (uint64_t)(end - p)) bad = true;
+        return h & 15;
+    }
+    // a scalar, binary, or list / set of them, or of lists of them (page
+    // statistics and friends; maps and deeper nesting do not occur in page
+    // headers).  Written without recursion: a recursive device function
+    // keeps its frames in scratch memory.
+    __device__ __noinline__ void skip_flat(int t, bool element) {
+        if (t != 9 && t != 10) {
+            skip_scalar(t, element);
+            return;
+        }
+        uint64_t n;
+        const int et = list_head(&n);
+        for (uint64_t k = 0; k < n && !bad; ++k) {
+            if (et == 9 || et == 10) {
+                uint64_t m;
+                const int it = list_head(&m);
+                for (uint64_t i = 0; i < m && !bad; ++i) {
+                    if (it == 9 || it == 10) bad = true;
+                    else skip_scalar(it, true);
+                }
+            } else {
+                skip_scalar(et, true);
+            }
+        }
+        if (p > end) bad = true;
+    }
+    // a struct whose fields are flat values (depth 0) or also structs of flat
+    // values (depth 1)
+    __device__ __noinline__ void skip_struct0() {
+        int last = 0, t;
+        while ((t = field(last)) != 0 && !bad) {
+            if (t == 12) bad = true;
+            else skip_flat(t, false);
+        }
+    }
+    __device__ __noinline__ void skip_struct(int depth) {
         int last = 0, t;
         while ((t = field(last)) != 0 && !bad) {
             if (t == 12) {
                 if (depth <= 0) bad = true;
-                else skip_struct(depth - 1);
+                else skip_struct0();
             } else {
                 skip_flat(t, false);
             }
@@ -454,7 +487,7 @@ struct PageHdr {
 };
 
 // Reads the page header at file offset `at` (chunk ends at `end`).
-__device__ PageHdr read_page_header(const uint8_t* f, int64_t at, int64_t end) {
+__device__ PageHdr read_page_header(const uint8_t* f, int64_t at, int64_t end, int64_t data_end) {
     PageHdr h{-1, -1, -1, -1, -1, -1, 0, 0, 0};
     HdrIn r{f, at, end, false};
     int last = 0, t;
@@ -480,7 +513,7 @@ __device__ PageHdr read_page_header(const uint8_t* f, int64_t at, int64_t end) {
         }
     }
     h.data = r.p;
-    h.ok = !r.bad && h.type >= 0 && h.csize >= 0 && h.csize <= end - r.p;
+    h.ok = !r.bad && h.type >= 0 && h.csize >= 0 && h.csize <= data_end - r.p;
     return h;
 }
 
@@ -550,12 +583,228 @@ __device__ __forceinline__ void put(Sink s, int64_t i, int64_t a, int32_t b) {
     if (s.b) s.b[i] = b;
 }
 
+// ---- PLAIN byte arrays: the chain of lengths, walked in parallel ----
+//
+// A PLAIN BYTE_ARRAY page is a chain: each value is a 4-byte length and its
+// bytes, so where value k + 1 starts is known only once value k is read.  A
+// single lane or wave following the chain spends a few hundred cycles per
+// value (each step is a dependent read), so the page is walked in rounds of
+// kRound bytes staged in LDS, cut into kNSeg segments of kSeg bytes:
+//   candidates  for every segment, the walks from each of its first kCand
+//               byte offsets to the first position past the segment (their
+//               exit), with the number of values met and whether a length
+//               ran past the page: one thread per (segment, offset), all in
+//               parallel;
+//   stitch      one thread follows the true chain across the round's
+//               segments through those tables (an entry beyond the first
+//               kCand offsets, after a long value, is walked directly), which
+//               gives each segment's entry and the index of its first value;
+//   output      one thread per segment walks its part of the chain from its
+//               entry and writes the values.
+// The walks, errors and outputs are those of the sequential chain (a
+// length running past the page end is an error only where the chain needs it).
+constexpr int kSeg = 512;
+constexpr int kCand = 64;
+constexpr int kNSeg = 64;
+constexpr int kRound = kSeg * kNSeg;            // 32 KiB of the page per round
+constexpr int kStageQ = (kRound + 32) / 16;     // staged 16-byte groups (alignment, reads across the end)
+
+struct ChainLds {
+    uint32_t st[4 * kStageQ];         // bytes [rb, rb + 16 * kStageQ) of the file (zero past the page)
+    int32_t exit_[kNSeg * kCand];     // candidate walk's exit - rb
+    uint16_t cnt[kNSeg * kCand];      // its values; bit 15: it met a length running past the page;
+                                      // bit 14 (during the walks): it stopped at a later candidate
+    int32_t ent[kNSeg];               // entry of the chain into each segment - rb (-1: none)
+    int64_t rk[kNSeg];                // index of the value starting there
+    int64_t e, rank;                  // the chain's position and values done, after the round
+    int32_t bad;
+};
+
+// Little-endian u32 at byte o of the stage (o + 4 <= the staged bytes).
+__device__ __forceinline__ uint32_t st_u32(const uint32_t* st, uint32_t o) {
+    const uint32_t w = o >> 2, sh = (o & 3) * 8;
+    const uint32_t a = st[w];
+    return sh ? (a >> sh) | (st[w + 1] << (32 - sh)) : a;
+}
+
+// The chain from q up to the first position >= s1: values met, exit, and
+// whether a length ran past pend (the walk stops there).
+__device__ __forceinline__ void chain_walk(const uint32_t* st, int64_t rb, int64_t pend, int64_t s1, int64_t* q,
+                                           uint32_t* cnt, bool* dead) {
+    uint32_t c = 0;
+    int64_t x = *q;
+    bool d = false;
+    while (x < s1) {
+        if (4 > pend - x) {
+            d = true;
+            break;
+        }
+        const uint32_t L = st_u32(st, (uint32_t)(x - rb));
+        if ((int64_t)L > pend - x - 4) {
+            d = true;
+            break;
+        }
+        x += 4 + (int64_t)L;
+        ++c;
+    }
+    *q = x;
+    *cnt = c;
+    *dead = d;
+}
+
+// The nv values of the chain starting at p (page data ends at pend), each
+// written as (file offset of its bytes, length) to out[base ..].  All threads
+// of the block call it; false (the same for every thread) when the chain
+// needs a length that runs past pend.
+__device__ bool walk_byte_arrays(const uint8_t* __restrict__ f, int64_t p, int64_t pend, int64_t nv, Sink out,
+                                 int64_t base) {
+    __shared__ ChainLds S;
+    const int tid = threadIdx.x;
+    const bool aligned = (reinterpret_cast<uintptr_t>(f) & 15) == 0;
+    int64_t e = p, rank = 0;
+    while (rank < nv) {   // block-uniform: e and rank come from LDS
+        if (4 > pend - e) return false;
+        const int64_t R = e, rb = R & ~(int64_t)15;
+        // 1. stage [rb, rb + 16 * kStageQ), zero past pend
+        for (int i = tid; i < kStageQ; i += kPB) {
+            const int64_t q = rb + 16 * (int64_t)i;
+            uint4 v;
+            if (aligned && q + 16 <= pend) {
+                v = *reinterpret_cast<const uint4*>(f + q);
+            } else {
+                uint32_t u[4] = {0, 0, 0, 0};
+                for (int b = 0; b < 16; ++b)
+                    if (q + b < pend) u[b >> 2] |= (uint32_t)f[q + b] << (8 * (b & 3));
+                v = make_uint4(u[0], u[1], u[2], u[3]);
+            }
+            S.st[4 * i] = v.x;
+            S.st[4 * i + 1] = v.y;
+            S.st[4 * i + 2] = v.z;
+            S.st[4 * i + 3] = v.w;
+        }
+        __syncthreads();
+        // 2. candidate walks; reads stay below R + kRound + 4 <= rb + 16 * kStageQ.
+        //    A walk that lands on a later candidate offset stops there with a
+        //    link (bit 14), so each segment's chain is walked once; a lane
+        //    that finishes a walk starts its next candidate at once (no lane
+        //    waits for the longest walk of its wave).
+        {
+            int i = tid;
+            int j = i & (kNSeg - 1), c = i / kNSeg;
+            int64_t s0 = R + (int64_t)j * kSeg, x = s0 + c;
+            uint32_t n = 0;
+            while (i < kNSeg * kCand) {
+                uint32_t flag = 0;
+                bool fin = true;
+                if (x < s0 + kSeg) {   // (a start is always inside its segment)
+                    if (4 > pend - x) {   // no length fits (a start at or past pend included)
+                        flag = 0x8000u;
+                    } else {
+                        const uint32_t L = st_u32(S.st, (uint32_t)(x - rb));
+                        if ((int64_t)L > pend - x - 4) {
+                            flag = 0x8000u;
+                        } else {
+                            x += 4 + (int64_t)L;
+                            ++n;
+                            if (x - s0 < kCand) flag = 0x4000u;   // link to candidate x - s0
+                            else fin = x >= s0 + kSeg;
+                        }
+                    }
+                }
+                if (fin) {
+                    S.exit_[j * kCand + c] = (int32_t)(x - rb);
+                    S.cnt[j * kCand + c] = (uint16_t)(n | flag);
+                    i += kPB;
+                    j = i & (kNSeg - 1);
+                    c = i / kNSeg;
+                    s0 = R + (int64_t)j * kSeg;
+                    x = s0 + c;
+                    n = 0;
+                }
+            }
+        }
+        __syncthreads();
+        // links resolved per segment, from the last candidate down (a link
+        // points to a later offset, already resolved)
+        if (tid < kNSeg) {
+            const int64_t s0 = R + (int64_t)tid * kSeg;
+            for (int c = kCand - 1; c >= 0; --c) {
+                const int at = tid * kCand + c;
+                if (S.cnt[at] & 0x4000u) {
+                    const int to = tid * kCand + (int)(rb + S.exit_[at] - s0);
+                    S.exit_[at] = S.exit_[to];
+                    S.cnt[at] = (uint16_t)((S.cnt[at] & 0x3FFFu) + S.cnt[to]);   // the target's flags carried
+                }
+            }
+        }
+        __syncthreads();
+        // 3. stitch
+        if (tid == 0) {
+            int64_t cur = R, acc = rank;
+            int32_t bad = 0;
+            for (int j = 0; j < kNSeg; ++j) S.ent[j] = -1;
+            for (int j = 0; j < kNSeg && acc < nv; ++j) {
+                const int64_t s0 = R + (int64_t)j * kSeg, s1 = s0 + kSeg;
+                if (cur >= s1) continue;   // a long value spans the segment
+                const int64_t off = cur - s0;
+                int64_t q = cur;
+                uint32_t n;
+                bool dead;
+                if (off < kCand) {
+                    q = rb + S.exit_[j * kCand + off];
+                    n = S.cnt[j * kCand + off] & 0x7FFFu;
+                    dead = (S.cnt[j * kCand + off] & 0x8000u) != 0;
+                } else {
+                    chain_walk(S.st, rb, pend, s1, &q, &n, &dead);
+                }
+                S.ent[j] = (int32_t)(cur - rb);
+                S.rk[j] = acc;
+                if (dead && acc + (int64_t)n < nv) {
+                    bad = 1;
+                    break;
+                }
+                acc += n;
+                cur = q;
+                if (dead) break;   // the values needed all came before
+            }
+            S.e = cur;
+            S.rank = acc < nv ? acc : nv;
+            S.bad = bad;
+        }
+        __syncthreads();
+        if (S.bad) return false;
+        // 4. output: a thread per segment
+        if (tid < kNSeg && S.ent[tid] >= 0) {
+            int64_t q = rb + S.ent[tid], r = S.rk[tid];
+            const int64_t s1 = R + (int64_t)tid * kSeg + kSeg;
+            while (q < s1 && r < nv) {
+                const uint32_t L = st_u32(S.st, (uint32_t)(q - rb));
+                put(out, base + r, q + 4, (int32_t)L);
+                q += 4 + (int64_t)L;
+                ++r;
+            }
+        }
+        e = S.e;
+        rank = S.rank;
+        __syncthreads();   // every thread has read the round's results
+    }
+    return true;
+}
+
+// Column chunk blockIdx.x.  DICT: its dictionary page (the first page, when
+// there is one) and nothing else.  Otherwise its data pages, those whose
+// index is blockIdx.y modulo gridDim.y (every block walks all page headers of
+// the chunk, which are short, for the row offsets); the dictionary entries
+// were written by the DICT launch before.
+template <bool DICT>
 __global__ __launch_bounds__(kPB) void k_pq_decode(const uint8_t* __restrict__ f, PqWs w, int64_t* __restrict__ ts) {
     __shared__ PageHdr sh;
+    __shared__ uint8_t hstage[kHdrStage];
     __shared__ Run runs[kRuns];
     __shared__ int s_nruns, s_null, s_stop;
     __shared__ int64_t s_at, s_done;
     const PqChunk ch = w.chunks[blockIdx.x];
+    int64_t page = 0;   // data pages seen
     const int tid = threadIdx.x;
     const int w_int = ch.type == 1 ? 4 : 8;
     const Sink rows = ch.col == 2 ? Sink{ts, nullptr} : Sink{w.val_a + ch.col * w.max_rows, w.val_b + ch.col * w.max_rows};
@@ -563,8 +812,15 @@ __global__ __launch_bounds__(kPB) void k_pq_decode(const uint8_t* __restrict__ f
     int64_t pos = ch.start, done = 0, dict_n = -1;
     while (done < ch.num_values) {
         __syncthreads();   // every thread has read the previous page's header
+        // the header's first bytes staged in LDS with one coalesced load: its
+        // parse is a chain of dependent byte reads
+        const int64_t wlen = ch.end - pos < kHdrStage ? ch.end - pos : kHdrStage;
+        for (int i = tid; i < kHdrStage; i += kPB) hstage[i] = i < wlen ? f[pos + i] : 0;
+        __syncthreads();
         if (tid == 0) {
-            sh = read_page_header(f, pos, ch.end);
+            sh = read_page_header(hstage, 0, wlen, ch.end - pos);   // offsets from pos
+            if (sh.ok) sh.data += pos;
+            else if (wlen < ch.end - pos) sh = read_page_header(f, pos, ch.end, ch.end);   // longer than the stage
             s_stop = 0;
             if (!sh.ok) {
                 pq_fail(w, PM4G_E_PARSE);
@@ -583,25 +839,20 @@ __global__ __launch_bounds__(kPB) void k_pq_decode(const uint8_t* __restrict__ f
                 return;
             }
             dict_n = h.nv;
-            if (ch.type != 6) {
-                if ((int64_t)h.nv * w_int > h.csize) {
-                    if (tid == 0) pq_fail(w, PM4G_E_PARSE);
-                    return;
-                }
-                for (int64_t k = tid; k < dict_n; k += kPB) put(dict, k, le_int(f + h.data + k * w_int, w_int), -1);
-            } else if (tid == 0) {   // length-prefixed byte arrays: a sequential walk
-                int64_t p = h.data;
-                for (int64_t k = 0; k < dict_n; ++k) {
-                    if (4 > pend - p) { pq_fail(w, PM4G_E_PARSE); break; }
-                    const int64_t L = le_int(f + p, 4) & 0xffffffffll;
-                    if (L > pend - p - 4) { pq_fail(w, PM4G_E_PARSE); break; }
-                    put(dict, k, p + 4, (int32_t)L);
-                    p += 4 + L;
-                }
+            if (ch.type != 6 && (int64_t)h.nv * w_int > h.csize) {
+                if (tid == 0) pq_fail(w, PM4G_E_PARSE);
+                return;
             }
-            __syncthreads();
-            continue;
+            if (!DICT) continue;   // decoded by the DICT launch
+            if (ch.type != 6) {
+                for (int64_t k = tid; k < dict_n; k += kPB) put(dict, k, le_int(f + h.data + k * w_int, w_int), -1);
+            } else {   // length-prefixed byte arrays: the chain, walked by the block
+                const bool ok = walk_byte_arrays(f, h.data, pend, dict_n, dict, 0);
+                if (tid == 0 && !ok) pq_fail(w, PM4G_E_PARSE);
+            }
+            return;
         }
+        if (DICT) return;   // the first page holds values: no dictionary
         if (h.type != 0 && h.type != 3) continue;   // index pages hold no values
         if (h.nv < 0 || h.nv > ch.num_values - done || (h.v2 && (h.dlen < 0 || h.rlen < 0 || h.dlen > h.csize))) {
             if (tid == 0) pq_fail(w, PM4G_E_PARSE);
@@ -610,6 +861,10 @@ __global__ __launch_bounds__(kPB) void k_pq_decode(const uint8_t* __restrict__ f
         if (h.v2 && h.rlen != 0) {   // repetition levels belong to nested schemas
             if (tid == 0) pq_fail(w, PM4G_E_UNSUPPORTED);
             return;
+        }
+        if ((page++) % gridDim.y != blockIdx.y) {   // another block's page
+            done += h.nv;
+            continue;
         }
         const int64_t row_base = ch.row0 + done;
         int64_t p = h.data;
@@ -678,13 +933,11 @@ __global__ __launch_bounds__(kPB) void k_pq_decode(const uint8_t* __restrict__ f
                     return;
                 }
                 for (int64_t k = tid; k < h.nv; k += kPB) put(rows, row_base + k, le_int(f + p + k * w_int, w_int), -1);
-            } else if (tid == 0) {
-                for (int64_t k = 0; k < h.nv; ++k) {
-                    if (4 > pend - p) { pq_fail(w, PM4G_E_PARSE); break; }
-                    const int64_t L = le_int(f + p, 4) & 0xffffffffll;
-                    if (L > pend - p - 4) { pq_fail(w, PM4G_E_PARSE); break; }
-                    put(rows, row_base + k, p + 4, (int32_t)L);
-                    p += 4 + L;
+            } else {   // the chain of lengths, walked by the block
+                const bool ok = walk_byte_arrays(f, p, pend, h.nv, rows, row_base);
+                if (!ok) {
+                    if (tid == 0) pq_fail(w, PM4G_E_PARSE);
+                    return;
                 }
             }
         } else if (h.enc == 2 || h.enc == 8) {   // dictionary indices: bit width, then the hybrid
@@ -734,25 +987,11 @@ __global__ __launch_bounds__(kPB) void k_pq_decode(const uint8_t* __restrict__ f
 
 constexpr uint64_t kFnvBasis = 0xcbf29ce484222325ull, kFnvPrime = 0x100000001b3ull;
 
-// Slot of hash h (linear probing); the slot keeps the smallest row holding it.
-__device__ __forceinline__ uint32_t pq_insert(CsvSlot* tab, int64_t tsize, uint64_t h, uint32_t r) {
-    uint64_t i = h & (uint64_t)(tsize - 1);
-    for (;;) {   // more slots than rows: an empty or equal slot exists
-        unsigned long long cur = __hip_atomic_load(reinterpret_cast<unsigned long long*>(&tab[i].hash),
-                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (cur == 0)
-            cur = atomicCAS(reinterpret_cast<unsigned long long*>(&tab[i].hash), 0ull, (unsigned long long)h);
-        if (cur == 0 || cur == h) {
-            if (r < __hip_atomic_load(&tab[i].first, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                atomicMin(&tab[i].first, r);
-            return (uint32_t)i;
-        }
-        i = (i + 1) & (uint64_t)(tsize - 1);
-    }
-}
-
 __global__ __launch_bounds__(256) void k_pq_clear(PqWs w) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) w.scal[2] = 0;   // no collision seen yet
+    if (blockIdx.x == 0 && threadIdx.x == 0) {   // empty slot lists
+        w.scal[10] = 0;
+        w.scal[11] = 0;
+    }
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < 2 * w.tsize; i += (int64_t)gridDim.x * 256) {
         w.table[i].hash = 0;
         w.table[i].first = 0xFFFFFFFFu;
@@ -778,46 +1017,100 @@ __device__ __forceinline__ uint64_t value_hash(const uint8_t* f, const PqWs& w, 
     return h ? h : 1;
 }
 
+// Values of rows r1 and r2 in column k (decoded by earlier launches): equal
+// integers, or byte arrays of equal bytes.
+__device__ __forceinline__ bool same_pq_value(const uint8_t* __restrict__ f, const PqWs& w, int k, int64_t r1,
+                                              int64_t r2) {
+    const int64_t a1 = w.val_a[k * w.max_rows + r1], a2 = w.val_a[k * w.max_rows + r2];
+    const int32_t b1 = w.val_b[k * w.max_rows + r1], b2 = w.val_b[k * w.max_rows + r2];
+    if (b1 != b2) return false;
+    if (b1 < 0) return a1 == a2;
+    for (int32_t i = 0; i < b1; ++i)
+        if (f[a1 + i] != f[a2 + i]) return false;
+    return true;
+}
+
+// Slot of row r's value in column k (hash h).  A slot's hash word is (the
+// hash's upper 32 bits | 1) << 32 | the row that claimed it: one
+// compare-and-swap claims an empty slot and names its owner.  Probing from h,
+// an empty slot is claimed; at a slot with the same upper hash bits the
+// owner's value is compared with this row's: equal values share the slot,
+// which keeps the smallest row (read first, so hot values take no atomic);
+// different values with one hash probe on.  Sets *claimed for a new slot.
+__device__ __forceinline__ uint32_t pq_insert(const uint8_t* __restrict__ f, const PqWs& w, int k, uint64_t h,
+                                              uint32_t r, bool* claimed) {
+    CsvSlot* tab = w.table + k * w.tsize;
+    const uint64_t m = (uint64_t)(w.tsize - 1);
+    const uint32_t tag = (uint32_t)(h >> 32) | 1u;
+    const unsigned long long mine = ((unsigned long long)tag << 32) | r;
+    uint64_t i = h & m;
+    for (;;) {   // more slots than rows: an empty or equal slot exists
+        unsigned long long* hw = reinterpret_cast<unsigned long long*>(&tab[i].hash);
+        unsigned long long cur = __hip_atomic_load(hw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == 0) {
+            cur = atomicCAS(hw, 0ull, mine);
+            if (cur == 0) {
+                atomicMin(&tab[i].first, r);
+                *claimed = true;
+                return (uint32_t)i;
+            }
+        }
+        if ((uint32_t)(cur >> 32) == tag && same_pq_value(f, w, k, r, (int64_t)(uint32_t)cur)) {
+            if (r < __hip_atomic_load(&tab[i].first, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                atomicMin(&tab[i].first, r);
+            return (uint32_t)i;
+        }
+        i = (i + 1) & m;
+    }
+}
+
+// Every row's case and activity values into their tables; the slots claimed
+// are listed per table (one global reservation per table and block pass).
 __global__ __launch_bounds__(256) void k_pq_insert(const uint8_t* __restrict__ f, PqWs w, uint64_t seed,
                                                    uint64_t mask) {
+    __shared__ uint32_t s_new[2][256];
+    __shared__ uint32_t s_cnt[2];
+    __shared__ int64_t s_base[2];
     const int64_t rows = w.scal[3];
     if (w.scal[0] != 0 || w.scal[1] != INT64_MAX) return;
-    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < rows; r += (int64_t)gridDim.x * 256)
+    for (int64_t r0 = (int64_t)blockIdx.x * 256; r0 < rows; r0 += (int64_t)gridDim.x * 256) {
+        if (threadIdx.x < 2) s_cnt[threadIdx.x] = 0;
+        __syncthreads();
+        const int64_t r = r0 + threadIdx.x;
+        if (r < rows) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                bool claimed = false;
+                const uint32_t slot = pq_insert(f, w, k, value_hash(f, w, k, r, seed, mask), (uint32_t)r, &claimed);
+                w.slot[k * w.max_rows + r] = slot;
+                if (claimed) s_new[k][atomicAdd(&s_cnt[k], 1u)] = slot;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 2)
+            s_base[threadIdx.x] = (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(&w.scal[10 + threadIdx.x]),
+                                                     (unsigned long long)s_cnt[threadIdx.x]);
+        __syncthreads();
+#pragma unroll
         for (int k = 0; k < 2; ++k)
-            w.slot[k * w.max_rows + r] = pq_insert(w.table + k * w.tsize, w.tsize, value_hash(f, w, k, r, seed, mask),
-                                                   (uint32_t)r);
+            for (uint32_t j = threadIdx.x; j < s_cnt[k]; j += 256) w.dlist[k * w.max_rows + s_base[k] + j] = s_new[k][j];
+        __syncthreads();
+    }
 }
 
-// Every row against its slot's first row: equal values, or a hash collision.
-__global__ __launch_bounds__(256) void k_pq_verify(const uint8_t* __restrict__ f, PqWs w) {
-    const int64_t rows = w.scal[3];
-    if (w.scal[0] != 0 || w.scal[1] != INT64_MAX) return;
-    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < rows; r += (int64_t)gridDim.x * 256)
-        for (int k = 0; k < 2; ++k) {
-            const int64_t first = w.table[k * w.tsize + w.slot[k * w.max_rows + r]].first;
-            if (first == r) continue;
-            const int64_t a1 = w.val_a[k * w.max_rows + r], a2 = w.val_a[k * w.max_rows + first];
-            const int32_t b1 = w.val_b[k * w.max_rows + r], b2 = w.val_b[k * w.max_rows + first];
-            bool same = b1 == b2;
-            if (same && b1 < 0) same = a1 == a2;
-            for (int32_t i = 0; same && i < b1; ++i) same = f[a1 + i] == f[a2 + i];
-            if (!same) w.scal[2] = 1;
-        }
-}
-
-__global__ __launch_bounds__(256) void k_pq_used(PqWs w, int k) {
+// The slots listed for table k with their first rows, to sort; their number
+// goes to scal[5] (none after a decode error or a null).
+__global__ __launch_bounds__(256) void k_pq_gather(PqWs w, int k) {
+    const bool failed = w.scal[0] != 0 || w.scal[1] != INT64_MAX;
+    const int64_t D = failed ? 0 : w.scal[10 + k];
+    if (blockIdx.x == 0 && threadIdx.x == 0) w.scal[5] = D;
+    const uint32_t* dl = w.dlist + k * w.max_rows;
     const CsvSlot* tab = w.table + k * w.tsize;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < w.tsize; i += (int64_t)gridDim.x * 256)
-        w.used[i] = tab[i].hash != 0 ? 1u : 0u;
-}
-
-__global__ __launch_bounds__(256) void k_pq_list(PqWs w, int k) {
-    const CsvSlot* tab = w.table + k * w.tsize;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < w.tsize; i += (int64_t)gridDim.x * 256)
-        if (w.used[i]) {
-            w.k0[w.pos[i]] = tab[i].first;
-            w.v0[w.pos[i]] = (uint32_t)i;
-        }
+    for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < D; d += (int64_t)gridDim.x * 256) {
+        const uint32_t i = dl[d];
+        w.k0[d] = tab[i].first;
+        w.v0[d] = i;
+    }
 }
 
 // Sorted by first row: the code of a slot is its rank; the dictionary entry is
@@ -838,6 +1131,7 @@ __global__ __launch_bounds__(256) void k_pq_codes(PqWs w, int k, const uint32_t*
 
 __global__ __launch_bounds__(256) void k_pq_emit(PqWs w, int32_t* __restrict__ case_code,
                                                  int32_t* __restrict__ act_code) {
+    if (w.scal[0] != 0 || w.scal[1] != INT64_MAX) return;
     const int64_t rows = w.scal[3];
     for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < rows; r += (int64_t)gridDim.x * 256) {
         case_code[r] = (int32_t)w.table[w.slot[r]].code;
@@ -873,7 +1167,10 @@ unsigned grid_of(int64_t rows) {
 hipError_t launch_pq_decode(const uint8_t* file, PqWs w, int64_t n_chunks, int64_t rows, int64_t* ts_out,
                             hipStream_t s) {
     k_pq_init<<<1, 64, 0, s>>>(w, rows);
-    if (n_chunks > 0) k_pq_decode<<<(unsigned)n_chunks, kPB, 0, s>>>(file, w, ts_out);
+    if (n_chunks > 0) {
+        k_pq_decode<true><<<(unsigned)n_chunks, kPB, 0, s>>>(file, w, ts_out);
+        k_pq_decode<false><<<dim3((unsigned)n_chunks, kPageSplit), kPB, 0, s>>>(file, w, ts_out);
+    }
     return hipGetLastError();
 }
 
@@ -882,18 +1179,15 @@ hipError_t launch_pq_match(const uint8_t* file, PqWs w, int64_t rows, uint64_t s
     const uint64_t mask = (hash_bits <= 0 || hash_bits >= 64) ? ~0ull : ((1ull << hash_bits) - 1);
     k_pq_clear<<<2048, 256, 0, s>>>(w);
     k_pq_insert<<<grid_of(rows), 256, 0, s>>>(file, w, seed, mask);
-    k_pq_verify<<<grid_of(rows), 256, 0, s>>>(file, w);
     return hipGetLastError();
 }
 
 hipError_t launch_pq_codes(PqWs w, int64_t rows, const pm4g_csv_out& o, hipStream_t s) {
-    const int64_t ts = w.tsize;
-    const unsigned gs = (unsigned)((ts + 255) / 256 < 2048 ? (ts + 255) / 256 : 2048);
+    int bits = 8;   // first rows are below max_rows: sort on that many bits
+    while (bits < 32 && (int64_t(1) << bits) < w.max_rows) bits += 8;
     for (int k = 0; k < 2; ++k) {
-        k_pq_used<<<gs, 256, 0, s>>>(w, k);
-        dev::excl_scan<uint32_t>(w.used, &w.scal[8], w.pos, w.part32, reinterpret_cast<uint32_t*>(&w.scal[5]), s);
-        k_pq_list<<<gs, 256, 0, s>>>(w, k);
-        const bool flip = dev::sort_pairs<uint32_t>(w.k0, w.v0, w.k1, w.v1, &w.scal[5], w.max_rows, 32, w.hist,
+        k_pq_gather<<<grid_of(rows), 256, 0, s>>>(w, k);
+        const bool flip = dev::sort_pairs<uint32_t>(w.k0, w.v0, w.k1, w.v1, &w.scal[5], w.max_rows, bits, w.hist,
                                                     w.rowsum, s);
         k_pq_codes<<<grid_of(rows), 256, 0, s>>>(w, k, flip ? w.k1 : w.k0, flip ? w.v1 : w.v0,
                                                  k == 0 ? o.case_dict_off : o.act_dict_off,

@@ -210,9 +210,9 @@ void efg(int64_t n, int32_t A) {
 // CSV: per 4096-byte tile quote parities, line counts (both starting
 // parities) and their scans, 256 end masks per tile; line ends up to the line
 // capacity max_rows + 1 (header) plus the unterminated last line; two fields
-// per row; two hash tables of tsize slots, the used flags of one table and
-// their scan (one position per SLOT: the scan runs over the table); distinct
-// values (at most the rows) sorted by first row; scal up to [9].
+// per row; two hash tables of tsize slots; the slots claimed in each table
+// (one per distinct value: at most the rows), sorted by first row; scal up
+// to [11].
 void csv(int64_t n_bytes, int64_t max_rows) {
     Bump b(kBase);
     const CsvWs w = csv_ws_layout(b, n_bytes, max_rows);
@@ -220,10 +220,10 @@ void csv(int64_t n_bytes, int64_t max_rows) {
     check(tag("csv", n_bytes, max_rows), b.off,
           {NEED(w, qpar, tiles), NEED(w, qpre, tiles), NEED(w, lcnt, tiles), NEED(w, lcnt1, tiles),
            NEED(w, emask, tiles * 256), NEED(w, loff, tiles), NEED(w, line_end, rows + 2), NEED(w, foff, 2 * rows),
-           NEED(w, flen, 2 * rows), NEED(w, slot, 2 * rows), NEED(w, table, 2 * w.tsize), NEED(w, used, w.tsize),
-           NEED(w, pos, w.tsize), NEED(w, k0, rows), NEED(w, v0, rows), NEED(w, k1, rows), NEED(w, v1, rows),
+           NEED(w, flen, 2 * rows), NEED(w, slot, 2 * rows), NEED(w, table, 2 * w.tsize), NEED(w, dlist, 2 * rows),
+           NEED(w, k0, rows), NEED(w, v0, rows), NEED(w, k1, rows), NEED(w, v1, rows),
            NEED(w, hist, 256 * dev::tiles(rows)), NEED(w, rowsum, 256), NEED(w, part32, dev::kScanGrid),
-           NEED(w, part64, dev::kScanGrid), NEED(w, scal, 10)});
+           NEED(w, part64, dev::kScanGrid), NEED(w, scal, 12)});
     if (w.tsize < 2 * rows) {
         std::printf("FAIL csv(%lld, %lld): %lld table slots for %lld rows\n", (long long)n_bytes, (long long)max_rows,
                     (long long)w.tsize, (long long)rows);
@@ -234,16 +234,16 @@ void csv(int64_t n_bytes, int64_t max_rows) {
 // Parquet: the chunk list (the host rejects more than kPqMaxChunks); each
 // chunk's dictionary holds at most its values (checked per dictionary page),
 // and the chunks of the three columns hold 3 * rows values; two value columns
-// and two slot columns of max_rows; two tables, used flags and positions per
-// slot; distinct values sorted by first row; scal up to [8].
+// and two slot columns of max_rows; two tables; the slots claimed in each
+// (at most the rows), sorted by first row; scal up to [11].
 void parquet(int64_t max_rows) {
     Bump b(kBase);
     const PqWs w = pq_ws_layout(b, max_rows);
     const int64_t rows = at_least1(max_rows);
     check(tag("parquet", max_rows), b.off,
-          {NEED(w, scal, 9), NEED(w, chunks, kPqMaxChunks), NEED(w, dict_a, 3 * rows), NEED(w, dict_b, 3 * rows),
+          {NEED(w, scal, 12), NEED(w, chunks, kPqMaxChunks), NEED(w, dict_a, 3 * rows), NEED(w, dict_b, 3 * rows),
            NEED(w, val_a, 2 * rows), NEED(w, val_b, 2 * rows), NEED(w, slot, 2 * rows), NEED(w, table, 2 * w.tsize),
-           NEED(w, used, w.tsize), NEED(w, pos, w.tsize), NEED(w, k0, rows), NEED(w, v0, rows), NEED(w, k1, rows),
+           NEED(w, dlist, 2 * rows), NEED(w, k0, rows), NEED(w, v0, rows), NEED(w, k1, rows),
            NEED(w, v1, rows), NEED(w, hist, 256 * dev::tiles(rows)), NEED(w, rowsum, 256),
            NEED(w, part32, dev::kScanGrid)});
     if (w.tsize < 2 * rows) {
