@@ -649,6 +649,16 @@ int pm4g_ingest_parquet(const uint8_t* file, int64_t n_bytes, const pm4g_parquet
     Bump bp(ws);
     PqWs w = pq_ws_layout(bp, out->capacity);
     w.max_rows = out->capacity > 0 ? out->capacity : 1;
+    // page-table ranges: a data page of at least 32 values on average fits
+    // (a chunk whose pages do not fit has them found by walking again)
+    int64_t pt_used = 0;
+    for (PqChunk& c : chunks) {
+        const int64_t want = c.num_values / 32 + 4;
+        const int64_t cap = want < w.pt_size - pt_used ? want : w.pt_size - pt_used;
+        c.pt_off = pt_used;
+        c.pt_cap = (int32_t)(cap < INT32_MAX ? cap : INT32_MAX);
+        pt_used += c.pt_cap;
+    }
     if (!chunks.empty())
         PM4G_HIP(hipMemcpyAsync(w.chunks, chunks.data(), chunks.size() * sizeof(PqChunk), hipMemcpyHostToDevice, s));
     PM4G_HIP(launch_pq_decode(file, w, (int64_t)chunks.size(), rows, out->ts, s));

@@ -416,6 +416,9 @@ hipError_t launch_csv_finish(CsvWs w, const pm4g_csv_out& o, hipStream_t s);
 
 
 // ---- Parquet ingestion (parquet.hip) ----
+constexpr int kPqPageBytes = 48;   // a page-table entry
+// page-table entries for max_rows rows: a data page holds 32 values on average or more
+inline int64_t pq_table_entries(int64_t max_rows) { return 3 * (max_rows / 32) + 4096; }
 constexpr int64_t kPqMaxChunks = 3 * 65536;   // three columns of at most 65536 row groups
 // One column chunk of the three read (case, activity, timestamp) in one row group.
 struct PqChunk {
@@ -426,7 +429,8 @@ struct PqChunk {
     int32_t type;          // 1 INT32, 2 INT64, 6 BYTE_ARRAY
     int32_t optional;      // definition levels present
     int32_t col;           // 0 case, 1 activity, 2 timestamp
-    int32_t pad;
+    int32_t pt_cap;        // entries of the page table reserved for its data pages
+    int64_t pt_off;        // the first of them
 };
 struct PqWs {
     int64_t tsize;         // slots per value table (power of two, at least twice the rows)
@@ -434,6 +438,10 @@ struct PqWs {
     int64_t* scal;         // [0] error status, [1] first null row, [3] rows, [5] slots listed,
                            // [8] tsize, [10], [11] slots claimed in the case, activity tables
     PqChunk* chunks;
+    int64_t pt_size;       // page-table entries (chunks get ranges of it on the host)
+    uint8_t* pages;        // [pt_size] page table: kPqPageBytes per data page (header, first row)
+    int64_t* pt_n;         // [chunks] data pages listed (-1: more than reserved, -2: a header error)
+    int64_t* pt_dict;      // [chunks] dictionary entries (-1: none)
     int64_t* dict_a;       // [3 * rows] dictionary entries: integer, or byte offset in the file
     int32_t* dict_b;       //            -1, or byte length
     int64_t* val_a;        // [2][rows] case and activity values, the same way

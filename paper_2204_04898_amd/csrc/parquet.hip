@@ -329,6 +329,10 @@ PqWs pq_ws_layout(Bump& b, int64_t max_rows) {
     w.tsize = t;
     w.scal = b.take<int64_t>(16);
     w.chunks = b.take<PqChunk>((size_t)kPqMaxChunks);
+    w.pt_size = pq_table_entries((int64_t)rows);
+    w.pages = b.take<uint8_t>((size_t)w.pt_size * kPqPageBytes);
+    w.pt_n = b.take<int64_t>((size_t)kPqMaxChunks);
+    w.pt_dict = b.take<int64_t>((size_t)kPqMaxChunks);
     w.dict_a = b.take<int64_t>(3 * rows);
     w.dict_b = b.take<int32_t>(3 * rows);
     w.val_a = b.take<int64_t>(2 * rows);
@@ -350,7 +354,7 @@ PqWs pq_ws_layout(Bump& b, int64_t max_rows) {
 
 namespace {
 
-constexpr int kPB = 256;        // threads per decode block
+constexpr int kPB = 1024;       // threads per decode block
 constexpr int kRuns = 256;      // hybrid runs read ahead per round
 constexpr int kHdrStage = 512;  // page-header bytes staged in LDS for the parse
 constexpr int kPageSplit = 64;  // blocks per column chunk, each decoding every 64th data page
@@ -611,14 +615,15 @@ constexpr int kStageQ = (kRound + 32) / 16;     // staged 16-byte groups (alignm
 
 struct ChainLds {
     uint32_t st[4 * kStageQ];         // bytes [rb, rb + 16 * kStageQ) of the file (zero past the page)
-    int32_t exit_[kNSeg * kCand];     // candidate walk's exit - rb
-    uint16_t cnt[kNSeg * kCand];      // its values; bit 15: it met a length running past the page;
-                                      // bit 14 (during the walks): it stopped at a later candidate
+    uint64_t tab[kNSeg * kCand];      // candidate walk: exit - rb (low 32 bits), values (bits 32-45),
+                                      // bit 46 (during the walks): it stopped at a later candidate,
+                                      // bit 47: it met a length running past the page
     int32_t ent[kNSeg];               // entry of the chain into each segment - rb (-1: none)
     int64_t rk[kNSeg];                // index of the value starting there
     int64_t e, rank;                  // the chain's position and values done, after the round
     int32_t bad;
 };
+constexpr uint64_t kLink = 1ull << 46, kDead = 1ull << 47;
 
 // Little-endian u32 at byte o of the stage (o + 4 <= the staged bytes).
 __device__ __forceinline__ uint32_t st_u32(const uint32_t* st, uint32_t o) {
@@ -685,7 +690,7 @@ __device__ bool walk_byte_arrays(const uint8_t* __restrict__ f, int64_t p, int64
         __syncthreads();
         // 2. candidate walks; reads stay below R + kRound + 4 <= rb + 16 * kStageQ.
         //    A walk that lands on a later candidate offset stops there with a
-        //    link (bit 14), so each segment's chain is walked once; a lane
+        //    link (kLink), so each segment's chain is walked once; a lane
         //    that finishes a walk starts its next candidate at once (no lane
         //    waits for the longest walk of its wave).
         {
@@ -698,7 +703,7 @@ __device__ bool walk_byte_arrays(const uint8_t* __restrict__ f, int64_t p, int64
                 bool fin = true;
                 if (x < s0 + kSeg) {   // (a start is always inside its segment)
                     if (4 > pend - x) {   // no length fits (a start at or past pend included)
-                        flag = 0x8000u;
+                        flag = 0x8000u;   // kDead >> 32
                     } else {
                         const uint32_t L = st_u32(S.st, (uint32_t)(x - rb));
                         if ((int64_t)L > pend - x - 4) {
@@ -706,14 +711,13 @@ __device__ bool walk_byte_arrays(const uint8_t* __restrict__ f, int64_t p, int64
                         } else {
                             x += 4 + (int64_t)L;
                             ++n;
-                            if (x - s0 < kCand) flag = 0x4000u;   // link to candidate x - s0
+                            if (x - s0 < kCand) flag = 0x4000u;   // kLink >> 32: to candidate x - s0
                             else fin = x >= s0 + kSeg;
                         }
                     }
                 }
                 if (fin) {
-                    S.exit_[j * kCand + c] = (int32_t)(x - rb);
-                    S.cnt[j * kCand + c] = (uint16_t)(n | flag);
+                    S.tab[j * kCand + c] = (uint64_t)(uint32_t)(x - rb) | ((uint64_t)(n | flag) << 32);
                     i += kPB;
                     j = i & (kNSeg - 1);
                     c = i / kNSeg;
@@ -730,34 +734,40 @@ __device__ bool walk_byte_arrays(const uint8_t* __restrict__ f, int64_t p, int64
             const int64_t s0 = R + (int64_t)tid * kSeg;
             for (int c = kCand - 1; c >= 0; --c) {
                 const int at = tid * kCand + c;
-                if (S.cnt[at] & 0x4000u) {
-                    const int to = tid * kCand + (int)(rb + S.exit_[at] - s0);
-                    S.exit_[at] = S.exit_[to];
-                    S.cnt[at] = (uint16_t)((S.cnt[at] & 0x3FFFu) + S.cnt[to]);   // the target's flags carried
+                const uint64_t v = S.tab[at];
+                if (v & kLink) {
+                    const uint64_t t = S.tab[tid * kCand + (int)(rb + (int64_t)(uint32_t)v - s0)];
+                    // the target's exit and flags, the two counts added (both < 2^14)
+                    S.tab[at] = (t & 0xFFFFFFFFull) | ((((v >> 32) & 0x3FFFull) + (t >> 32)) << 32);
                 }
             }
         }
         __syncthreads();
-        // 3. stitch
+        // 3. stitch (positions as 32-bit offsets from rb: a page is < 2^31 bytes)
         if (tid == 0) {
-            int64_t cur = R, acc = rank;
+            const int32_t r0 = (int32_t)(R - rb);
+            int32_t cur = r0;
+            int64_t acc = rank;
             int32_t bad = 0;
             for (int j = 0; j < kNSeg; ++j) S.ent[j] = -1;
             for (int j = 0; j < kNSeg && acc < nv; ++j) {
-                const int64_t s0 = R + (int64_t)j * kSeg, s1 = s0 + kSeg;
+                const int32_t s0 = r0 + j * kSeg, s1 = s0 + kSeg;
                 if (cur >= s1) continue;   // a long value spans the segment
-                const int64_t off = cur - s0;
-                int64_t q = cur;
+                const int32_t off = cur - s0;
                 uint32_t n;
                 bool dead;
+                int32_t q;
                 if (off < kCand) {
-                    q = rb + S.exit_[j * kCand + off];
-                    n = S.cnt[j * kCand + off] & 0x7FFFu;
-                    dead = (S.cnt[j * kCand + off] & 0x8000u) != 0;
+                    const uint64_t v = S.tab[j * kCand + off];
+                    q = (int32_t)(uint32_t)v;
+                    n = (uint32_t)(v >> 32) & 0x3FFFu;
+                    dead = (v & kDead) != 0;
                 } else {
-                    chain_walk(S.st, rb, pend, s1, &q, &n, &dead);
+                    int64_t x = rb + cur;
+                    chain_walk(S.st, rb, pend, rb + s1, &x, &n, &dead);
+                    q = (int32_t)(x - rb);
                 }
-                S.ent[j] = (int32_t)(cur - rb);
+                S.ent[j] = cur;
                 S.rk[j] = acc;
                 if (dead && acc + (int64_t)n < nv) {
                     bad = 1;
@@ -767,7 +777,7 @@ __device__ bool walk_byte_arrays(const uint8_t* __restrict__ f, int64_t p, int64
                 cur = q;
                 if (dead) break;   // the values needed all came before
             }
-            S.e = cur;
+            S.e = rb + cur;
             S.rank = acc < nv ? acc : nv;
             S.bad = bad;
         }
@@ -791,49 +801,209 @@ __device__ bool walk_byte_arrays(const uint8_t* __restrict__ f, int64_t p, int64
     return true;
 }
 
-// Column chunk blockIdx.x.  DICT: its dictionary page (the first page, when
-// there is one) and nothing else.  Otherwise its data pages, those whose
-// index is blockIdx.y modulo gridDim.y (every block walks all page headers of
-// the chunk, which are short, for the row offsets); the dictionary entries
-// were written by the DICT launch before.
-template <bool DICT>
-__global__ __launch_bounds__(kPB) void k_pq_decode(const uint8_t* __restrict__ f, PqWs w, int64_t* __restrict__ ts) {
-    __shared__ PageHdr sh;
-    __shared__ uint8_t hstage[kHdrStage];
+// One data page whose header was checked, its first row known; false when
+// the block stops decoding the chunk (an error or a null was reported).
+// Every thread of the block calls it.
+__device__ bool decode_data_page(const uint8_t* __restrict__ f, const PqWs& w, const PqChunk& ch, const PageHdr& h,
+                                 int64_t row_base, int64_t dict_n, Sink rows, Sink dict) {
     __shared__ Run runs[kRuns];
-    __shared__ int s_nruns, s_null, s_stop;
+    __shared__ int s_nruns, s_null;
     __shared__ int64_t s_at, s_done;
-    const PqChunk ch = w.chunks[blockIdx.x];
-    int64_t page = 0;   // data pages seen
     const int tid = threadIdx.x;
     const int w_int = ch.type == 1 ? 4 : 8;
-    const Sink rows = ch.col == 2 ? Sink{ts, nullptr} : Sink{w.val_a + ch.col * w.max_rows, w.val_b + ch.col * w.max_rows};
-    const Sink dict{w.dict_a + ch.dict_base, w.dict_b + ch.dict_base};
-    int64_t pos = ch.start, done = 0, dict_n = -1;
-    while (done < ch.num_values) {
-        __syncthreads();   // every thread has read the previous page's header
-        // the header's first bytes staged in LDS with one coalesced load: its
-        // parse is a chain of dependent byte reads
-        const int64_t wlen = ch.end - pos < kHdrStage ? ch.end - pos : kHdrStage;
-        for (int i = tid; i < kHdrStage; i += kPB) hstage[i] = i < wlen ? f[pos + i] : 0;
-        __syncthreads();
-        if (tid == 0) {
-            sh = read_page_header(hstage, 0, wlen, ch.end - pos);   // offsets from pos
-            if (sh.ok) sh.data += pos;
-            else if (wlen < ch.end - pos) sh = read_page_header(f, pos, ch.end, ch.end);   // longer than the stage
-            s_stop = 0;
-            if (!sh.ok) {
+    const int64_t pend = h.data + h.csize;
+    int64_t p = h.data;
+    // definition levels (width 1): a 0 is a null, the page's first one is reported
+    if (tid == 0) {
+        s_null = 0;
+        s_at = p;
+        if (ch.optional) {
+            int64_t lb = h.dlen, q = p;
+            if (!h.v2) {
+                lb = h.csize >= 4 ? (le_int(f + p, 4) & 0xffffffffll) : -1;
+                q = p + 4;
+            }
+            if (lb < 0 || lb > pend - q) {
                 pq_fail(w, PM4G_E_PARSE);
-                s_stop = 1;
+                s_null = 2;
+            } else {
+                // the level runs one at a time (no null: usually a single RLE run)
+                HdrIn r{f, q, q + lb, false};
+                int64_t k = 0;
+                while (k < h.nv && !r.bad && s_null == 0) {
+                    const uint64_t hh = r.uvar();
+                    if (r.bad) break;
+                    if (hh & 1) {
+                        const int64_t cnt = (int64_t)(hh >> 1) * 8, bytes = (int64_t)(hh >> 1);
+                        if (bytes > q + lb - r.p) { r.bad = true; break; }
+                        for (int64_t j = 0; j < cnt && k + j < h.nv; ++j)
+                            if (((f[r.p + (j >> 3)] >> (j & 7)) & 1) == 0) {
+                                pq_null_at(w, row_base + k + j);
+                                s_null = 1;
+                                break;
+                            }
+                        r.p += bytes;
+                        k += cnt;
+                    } else {
+                        if (1 > q + lb - r.p) { r.bad = true; break; }
+                        const uint8_t v = f[r.p++];
+                        if ((v & 1) == 0 && (hh >> 1) > 0) {
+                            pq_null_at(w, row_base + k);
+                            s_null = 1;
+                        }
+                        k += (int64_t)(hh >> 1);
+                    }
+                }
+                if (r.bad || (s_null == 0 && k < h.nv)) {
+                    pq_fail(w, PM4G_E_PARSE);
+                    s_null = 2;
+                }
+                s_at = q + lb;
+            }
+        } else if (h.v2 && h.dlen != 0) {
+            pq_fail(w, PM4G_E_PARSE);
+            s_null = 2;
+        }
+    }
+    __syncthreads();
+    if (s_null == 2) return false;
+    if (s_null == 1) {   // this chunk's result is an error at its first null; later pages do not matter
+        return false;
+    }
+    p = s_at;
+    if (h.enc == 0) {   // PLAIN
+        if (ch.type != 6) {
+            if ((int64_t)h.nv * w_int > pend - p) {
+                if (tid == 0) pq_fail(w, PM4G_E_PARSE);
+                return false;
+            }
+            for (int64_t k = tid; k < h.nv; k += kPB) put(rows, row_base + k, le_int(f + p + k * w_int, w_int), -1);
+        } else {   // the chain of lengths, walked by the block
+            const bool ok = walk_byte_arrays(f, p, pend, h.nv, rows, row_base);
+            if (!ok) {
+                if (tid == 0) pq_fail(w, PM4G_E_PARSE);
+                return false;
             }
         }
+    } else if (h.enc == 2 || h.enc == 8) {   // dictionary indices: bit width, then the hybrid
+        if (dict_n < 0 || p >= pend || f[p] > 32) {
+            if (tid == 0) pq_fail(w, PM4G_E_PARSE);
+            return false;
+        }
+        const int bw = f[p];
+        if (tid == 0) {
+            s_at = p + 1;
+            s_done = 0;
+        }
         __syncthreads();
-        const PageHdr h = sh;
-        if (s_stop) return;
+        for (;;) {
+            if (tid == 0) {
+                int64_t at = s_at, d = s_done;
+                s_nruns = d < h.nv ? read_runs(f, &at, pend, bw, &d, h.nv, runs) : 0;
+                s_at = at;
+                s_done = d;
+                if (s_nruns < 0) pq_fail(w, PM4G_E_PARSE);
+            }
+            __syncthreads();
+            const int nr = s_nruns;
+            if (nr <= 0) break;
+            for (int q = 0; q < nr; ++q) {
+                const Run u = runs[q];
+                for (int64_t j = tid; j < u.count; j += kPB) {
+                    const uint32_t ix = u.packed ? unpack(f, u.pos, j, bw) : u.value;
+                    if ((int64_t)ix >= dict_n) {
+                        pq_fail(w, PM4G_E_PARSE);
+                        continue;
+                    }
+                    put(rows, row_base + u.first + j, dict.a[ix], dict.b ? dict.b[ix] : -1);
+                }
+            }
+            __syncthreads();
+        }
+        if (s_nruns < 0) return false;
+    } else {
+        if (tid == 0) pq_fail(w, PM4G_E_UNSUPPORTED);
+        return false;
+    }
+    return true;
+}
+
+// The chunk's pages in order (blockIdx.x: the chunk), shared by the two
+// walks below: page headers staged in LDS and parsed by thread 0; false on
+// a malformed header (reported).  Sets *h for every thread.
+__device__ bool next_page_header(const uint8_t* __restrict__ f, const PqWs& w, const PqChunk& ch, int64_t pos,
+                                 PageHdr* h) {
+    __shared__ PageHdr sh;
+    __shared__ uint8_t hstage[kHdrStage];
+    __shared__ int s_stop;
+    const int tid = threadIdx.x;
+    __syncthreads();   // every thread has read the previous header
+    // the header's first bytes staged with one coalesced load: its parse is a
+    // chain of dependent byte reads
+    const int64_t wlen = ch.end - pos < kHdrStage ? ch.end - pos : kHdrStage;
+    for (int i = tid; i < kHdrStage; i += kPB) hstage[i] = i < wlen ? f[pos + i] : 0;
+    __syncthreads();
+    if (tid == 0) {
+        sh = read_page_header(hstage, 0, wlen, ch.end - pos);   // offsets from pos
+        if (sh.ok) sh.data += pos;
+        else if (wlen < ch.end - pos) sh = read_page_header(f, pos, ch.end, ch.end);   // longer than the stage
+        s_stop = 0;
+        if (!sh.ok) {
+            pq_fail(w, PM4G_E_PARSE);
+            s_stop = 1;
+        }
+    }
+    __syncthreads();
+    *h = sh;
+    return !s_stop;
+}
+
+// A data page's header checks, before its values: false (reported) when the
+// block stops.
+__device__ __forceinline__ bool check_data_page(const PqWs& w, const PqChunk& ch, const PageHdr& h, int64_t done) {
+    if (h.nv < 0 || h.nv > ch.num_values - done || (h.v2 && (h.dlen < 0 || h.rlen < 0 || h.dlen > h.csize))) {
+        if (threadIdx.x == 0) pq_fail(w, PM4G_E_PARSE);
+        return false;
+    }
+    if (h.v2 && h.rlen != 0) {   // repetition levels belong to nested schemas
+        if (threadIdx.x == 0) pq_fail(w, PM4G_E_UNSUPPORTED);
+        return false;
+    }
+    return true;
+}
+
+struct PqPage {        // a page-table entry
+    PageHdr h;
+    int64_t row_base;  // the page's first row
+};
+static_assert(sizeof(PqPage) == kPqPageBytes, "page-table entry size");
+
+// Column chunk blockIdx.x, two blocks working at once: blockIdx.y == 0
+// decodes its dictionary page (the chunk's first page, when it has one);
+// blockIdx.y == 1 walks its page headers in order and lists its data pages
+// (header, first row) in its range of the page table (pt_n: their number;
+// -1 when they exceed the range, -2 after an error; pt_dict: the
+// dictionary's entries).  Both check the dictionary page's header.
+__global__ __launch_bounds__(kPB) void k_pq_pages(const uint8_t* __restrict__ f, PqWs w) {
+    const bool decode_dict = blockIdx.y == 0;
+    const PqChunk ch = w.chunks[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int w_int = ch.type == 1 ? 4 : 8;
+    const Sink dict{w.dict_a + ch.dict_base, w.dict_b + ch.dict_base};
+    PqPage* table = reinterpret_cast<PqPage*>(w.pages) + ch.pt_off;
+    if (tid == 0 && !decode_dict) {
+        w.pt_n[blockIdx.x] = -2;   // until the walk completes
+        w.pt_dict[blockIdx.x] = -1;
+    }
+    int64_t pos = ch.start, done = 0, dict_n = -1, n = 0;
+    while (done < ch.num_values) {
+        PageHdr h;
+        if (!next_page_header(f, w, ch, pos, &h)) return;
+        if (decode_dict && h.type != 2) return;   // no dictionary page (it comes first)
         pos = h.data + h.csize;
         const int64_t pend = h.data + h.csize;
         if (h.type == 2) {   // dictionary page: PLAIN values
-            bool bad = h.nv < 0 || dict_n >= 0 || h.nv > ch.num_values || (h.enc != 0 && h.enc != 2);
+            const bool bad = h.nv < 0 || dict_n >= 0 || h.nv > ch.num_values || (h.enc != 0 && h.enc != 2);
             if (bad) {
                 if (tid == 0) pq_fail(w, (h.enc != 0 && h.enc != 2) ? PM4G_E_UNSUPPORTED : PM4G_E_PARSE);
                 return;
@@ -843,145 +1013,53 @@ __global__ __launch_bounds__(kPB) void k_pq_decode(const uint8_t* __restrict__ f
                 if (tid == 0) pq_fail(w, PM4G_E_PARSE);
                 return;
             }
-            if (!DICT) continue;   // decoded by the DICT launch
+            if (!decode_dict) continue;
             if (ch.type != 6) {
                 for (int64_t k = tid; k < dict_n; k += kPB) put(dict, k, le_int(f + h.data + k * w_int, w_int), -1);
-            } else {   // length-prefixed byte arrays: the chain, walked by the block
-                const bool ok = walk_byte_arrays(f, h.data, pend, dict_n, dict, 0);
-                if (tid == 0 && !ok) pq_fail(w, PM4G_E_PARSE);
-            }
-            return;
-        }
-        if (DICT) return;   // the first page holds values: no dictionary
-        if (h.type != 0 && h.type != 3) continue;   // index pages hold no values
-        if (h.nv < 0 || h.nv > ch.num_values - done || (h.v2 && (h.dlen < 0 || h.rlen < 0 || h.dlen > h.csize))) {
-            if (tid == 0) pq_fail(w, PM4G_E_PARSE);
-            return;
-        }
-        if (h.v2 && h.rlen != 0) {   // repetition levels belong to nested schemas
-            if (tid == 0) pq_fail(w, PM4G_E_UNSUPPORTED);
-            return;
-        }
-        if ((page++) % gridDim.y != blockIdx.y) {   // another block's page
-            done += h.nv;
-            continue;
-        }
-        const int64_t row_base = ch.row0 + done;
-        int64_t p = h.data;
-        // definition levels (width 1): a 0 is a null, the page's first one is reported
-        if (tid == 0) {
-            s_null = 0;
-            s_at = p;
-            if (ch.optional) {
-                int64_t lb = h.dlen, q = p;
-                if (!h.v2) {
-                    lb = h.csize >= 4 ? (le_int(f + p, 4) & 0xffffffffll) : -1;
-                    q = p + 4;
-                }
-                if (lb < 0 || lb > pend - q) {
-                    pq_fail(w, PM4G_E_PARSE);
-                    s_null = 2;
-                } else {
-                    // the level runs one at a time (no null: usually a single RLE run)
-                    HdrIn r{f, q, q + lb, false};
-                    int64_t k = 0;
-                    while (k < h.nv && !r.bad && s_null == 0) {
-                        const uint64_t hh = r.uvar();
-                        if (r.bad) break;
-                        if (hh & 1) {
-                            const int64_t cnt = (int64_t)(hh >> 1) * 8, bytes = (int64_t)(hh >> 1);
-                            if (bytes > q + lb - r.p) { r.bad = true; break; }
-                            for (int64_t j = 0; j < cnt && k + j < h.nv; ++j)
-                                if (((f[r.p + (j >> 3)] >> (j & 7)) & 1) == 0) {
-                                    pq_null_at(w, row_base + k + j);
-                                    s_null = 1;
-                                    break;
-                                }
-                            r.p += bytes;
-                            k += cnt;
-                        } else {
-                            if (1 > q + lb - r.p) { r.bad = true; break; }
-                            const uint8_t v = f[r.p++];
-                            if ((v & 1) == 0 && (hh >> 1) > 0) {
-                                pq_null_at(w, row_base + k);
-                                s_null = 1;
-                            }
-                            k += (int64_t)(hh >> 1);
-                        }
-                    }
-                    if (r.bad || (s_null == 0 && k < h.nv)) {
-                        pq_fail(w, PM4G_E_PARSE);
-                        s_null = 2;
-                    }
-                    s_at = q + lb;
-                }
-            } else if (h.v2 && h.dlen != 0) {
-                pq_fail(w, PM4G_E_PARSE);
-                s_null = 2;
-            }
-        }
-        __syncthreads();
-        if (s_null == 2) return;
-        if (s_null == 1) {   // this chunk's result is an error at its first null; later pages do not matter
-            return;
-        }
-        p = s_at;
-        if (h.enc == 0) {   // PLAIN
-            if (ch.type != 6) {
-                if ((int64_t)h.nv * w_int > pend - p) {
-                    if (tid == 0) pq_fail(w, PM4G_E_PARSE);
-                    return;
-                }
-                for (int64_t k = tid; k < h.nv; k += kPB) put(rows, row_base + k, le_int(f + p + k * w_int, w_int), -1);
-            } else {   // the chain of lengths, walked by the block
-                const bool ok = walk_byte_arrays(f, p, pend, h.nv, rows, row_base);
-                if (!ok) {
-                    if (tid == 0) pq_fail(w, PM4G_E_PARSE);
-                    return;
-                }
-            }
-        } else if (h.enc == 2 || h.enc == 8) {   // dictionary indices: bit width, then the hybrid
-            if (dict_n < 0 || p >= pend || f[p] > 32) {
+            } else if (!walk_byte_arrays(f, h.data, pend, dict_n, dict, 0)) {   // the chain, walked by the block
                 if (tid == 0) pq_fail(w, PM4G_E_PARSE);
-                return;
             }
-            const int bw = f[p];
-            if (tid == 0) {
-                s_at = p + 1;
-                s_done = 0;
-            }
-            __syncthreads();
-            for (;;) {
-                if (tid == 0) {
-                    int64_t at = s_at, d = s_done;
-                    s_nruns = d < h.nv ? read_runs(f, &at, pend, bw, &d, h.nv, runs) : 0;
-                    s_at = at;
-                    s_done = d;
-                    if (s_nruns < 0) pq_fail(w, PM4G_E_PARSE);
-                }
-                __syncthreads();
-                const int nr = s_nruns;
-                if (nr <= 0) break;
-                for (int q = 0; q < nr; ++q) {
-                    const Run u = runs[q];
-                    for (int64_t j = tid; j < u.count; j += kPB) {
-                        const uint32_t ix = u.packed ? unpack(f, u.pos, j, bw) : u.value;
-                        if ((int64_t)ix >= dict_n) {
-                            pq_fail(w, PM4G_E_PARSE);
-                            continue;
-                        }
-                        put(rows, row_base + u.first + j, dict.a[ix], dict.b ? dict.b[ix] : -1);
-                    }
-                }
-                __syncthreads();
-            }
-            if (s_nruns < 0) return;
-        } else {
-            if (tid == 0) pq_fail(w, PM4G_E_UNSUPPORTED);
             return;
         }
+        if (h.type != 0 && h.type != 3) continue;   // index pages hold no values
+        if (!check_data_page(w, ch, h, done)) return;
+        if (tid == 0 && n < ch.pt_cap) table[n] = PqPage{h, ch.row0 + done};
+        ++n;
         done += h.nv;
-        __syncthreads();
+    }
+    if (tid == 0) {
+        w.pt_n[blockIdx.x] = n <= ch.pt_cap ? n : -1;
+        w.pt_dict[blockIdx.x] = dict_n;
+    }
+}
+
+// Column chunk blockIdx.x, after k_pq_pages: its data pages whose index is
+// blockIdx.y modulo gridDim.y, looked up in the page table (or, when the
+// chunk's pages did not fit there, found by walking the headers again).
+__global__ __launch_bounds__(kPB) void k_pq_decode(const uint8_t* __restrict__ f, PqWs w, int64_t* __restrict__ ts) {
+    const PqChunk ch = w.chunks[blockIdx.x];
+    const int64_t n = w.pt_n[blockIdx.x], dict_n = w.pt_dict[blockIdx.x];
+    if (n == -2) return;   // an error was reported
+    const Sink rows = ch.col == 2 ? Sink{ts, nullptr} : Sink{w.val_a + ch.col * w.max_rows, w.val_b + ch.col * w.max_rows};
+    const Sink dict{w.dict_a + ch.dict_base, w.dict_b + ch.dict_base};
+    if (n >= 0) {
+        const PqPage* table = reinterpret_cast<const PqPage*>(w.pages) + ch.pt_off;
+        for (int64_t k = blockIdx.y; k < n; k += gridDim.y) {
+            const PqPage pg = table[k];
+            if (!decode_data_page(f, w, ch, pg.h, pg.row_base, dict_n, rows, dict)) return;
+        }
+        return;
+    }
+    int64_t pos = ch.start, done = 0, page = 0;
+    while (done < ch.num_values) {
+        PageHdr h;
+        if (!next_page_header(f, w, ch, pos, &h)) return;
+        pos = h.data + h.csize;
+        if (h.type != 0 && h.type != 3) continue;   // the dictionary page was decoded, index pages hold no values
+        if (!check_data_page(w, ch, h, done)) return;
+        if ((page++) % gridDim.y == blockIdx.y && !decode_data_page(f, w, ch, h, ch.row0 + done, dict_n, rows, dict))
+            return;
+        done += h.nv;
     }
 }
 
@@ -999,37 +1077,56 @@ __global__ __launch_bounds__(256) void k_pq_clear(PqWs w) {
     }
 }
 
-// Hash of row r's value in column k (0 case, 1 activity): integers by value,
-// byte arrays by their bytes; never 0 (the empty slot).
-__device__ __forceinline__ uint64_t value_hash(const uint8_t* f, const PqWs& w, int k, int64_t r, uint64_t seed,
-                                               uint64_t mask) {
-    const int64_t a = w.val_a[k * w.max_rows + r];
-    const int32_t b = w.val_b[k * w.max_rows + r];
+// Word k of byte array [a, a + b) of the file: its bytes a + 8k .. a + 8k + 7,
+// those past the value zero.  Only aligned words holding value bytes are
+// read (a value ends at least 8 bytes before the end of a Parquet file, its
+// footer length and magic, and f is 8-byte aligned).
+__device__ __forceinline__ uint64_t value_word(const uint8_t* __restrict__ f, int64_t a, int32_t b, int32_t k) {
+    const int64_t p = a + 8 * (int64_t)k;
+    const int rem = b - 8 * k < 8 ? b - 8 * k : 8;
+    const int64_t al = p & ~(int64_t)7;
+    const int sh = (int)(p & 7) * 8;
+    uint64_t v = *reinterpret_cast<const uint64_t*>(f + al) >> sh;
+    if (sh && al + 8 < p + rem) v |= *reinterpret_cast<const uint64_t*>(f + al + 8) << (64 - sh);
+    return rem < 8 ? v & ((1ull << (8 * rem)) - 1) : v;
+}
+
+// Hash of a value: integers by value, byte arrays by their bytes eight at a
+// time (a byte at a time if f is not 8-byte aligned); never 0 (the empty slot).
+__device__ __forceinline__ uint64_t value_hash(const uint8_t* __restrict__ f, bool aligned, int64_t a, int32_t b,
+                                               uint64_t seed, uint64_t mask) {
     uint64_t h;
     if (b < 0) {
         h = splitmix64(seed, (uint64_t)a);
     } else {
         h = kFnvBasis ^ seed;
-        for (int32_t i = 0; i < b; ++i) h = (h ^ f[a + i]) * kFnvPrime;
+        if (aligned) {
+            for (int32_t k = 0; 8 * k < b; ++k) h = (h ^ value_word(f, a, b, k)) * kFnvPrime;
+            h ^= (uint64_t)b;
+        } else {
+            for (int32_t i = 0; i < b; ++i) h = (h ^ f[a + i]) * kFnvPrime;
+        }
         h = splitmix64(seed, h);
     }
     h &= mask;
     return h ? h : 1;
 }
 
-// Values of rows r1 and r2 in column k (decoded by earlier launches): equal
-// integers, or byte arrays of equal bytes.
-__device__ __forceinline__ bool same_pq_value(const uint8_t* __restrict__ f, const PqWs& w, int k, int64_t r1,
-                                              int64_t r2) {
-    const int64_t a1 = w.val_a[k * w.max_rows + r1], a2 = w.val_a[k * w.max_rows + r2];
-    const int32_t b1 = w.val_b[k * w.max_rows + r1], b2 = w.val_b[k * w.max_rows + r2];
+// Two values (decoded by earlier launches): equal integers, or byte arrays of
+// equal bytes.
+__device__ __forceinline__ bool same_pq_value(const uint8_t* __restrict__ f, bool aligned, int64_t a1, int32_t b1,
+                                              int64_t a2, int32_t b2) {
     if (b1 != b2) return false;
     if (b1 < 0) return a1 == a2;
+    if (aligned) {
+        for (int32_t k = 0; 8 * k < b1; ++k)
+            if (value_word(f, a1, b1, k) != value_word(f, a2, b2, k)) return false;
+        return true;
+    }
     for (int32_t i = 0; i < b1; ++i)
         if (f[a1 + i] != f[a2 + i]) return false;
     return true;
 }
-
 // Slot of row r's value in column k (hash h).  A slot's hash word is (the
 // hash's upper 32 bits | 1) << 32 | the row that claimed it: one
 // compare-and-swap claims an empty slot and names its owner.  Probing from h,
@@ -1037,8 +1134,8 @@ __device__ __forceinline__ bool same_pq_value(const uint8_t* __restrict__ f, con
 // owner's value is compared with this row's: equal values share the slot,
 // which keeps the smallest row (read first, so hot values take no atomic);
 // different values with one hash probe on.  Sets *claimed for a new slot.
-__device__ __forceinline__ uint32_t pq_insert(const uint8_t* __restrict__ f, const PqWs& w, int k, uint64_t h,
-                                              uint32_t r, bool* claimed) {
+__device__ __forceinline__ uint32_t pq_insert(const uint8_t* __restrict__ f, bool aligned, const PqWs& w, int k,
+                                              uint64_t h, uint32_t r, int64_t a, int32_t b, bool* claimed) {
     CsvSlot* tab = w.table + k * w.tsize;
     const uint64_t m = (uint64_t)(w.tsize - 1);
     const uint32_t tag = (uint32_t)(h >> 32) | 1u;
@@ -1055,7 +1152,9 @@ __device__ __forceinline__ uint32_t pq_insert(const uint8_t* __restrict__ f, con
                 return (uint32_t)i;
             }
         }
-        if ((uint32_t)(cur >> 32) == tag && same_pq_value(f, w, k, r, (int64_t)(uint32_t)cur)) {
+        const int64_t r2 = (int64_t)(uint32_t)cur;
+        if ((uint32_t)(cur >> 32) == tag &&
+            same_pq_value(f, aligned, a, b, w.val_a[k * w.max_rows + r2], w.val_b[k * w.max_rows + r2])) {
             if (r < __hip_atomic_load(&tab[i].first, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
                 atomicMin(&tab[i].first, r);
             return (uint32_t)i;
@@ -1073,6 +1172,7 @@ __global__ __launch_bounds__(256) void k_pq_insert(const uint8_t* __restrict__ f
     __shared__ int64_t s_base[2];
     const int64_t rows = w.scal[3];
     if (w.scal[0] != 0 || w.scal[1] != INT64_MAX) return;
+    const bool aligned = (reinterpret_cast<uintptr_t>(f) & 7) == 0;
     for (int64_t r0 = (int64_t)blockIdx.x * 256; r0 < rows; r0 += (int64_t)gridDim.x * 256) {
         if (threadIdx.x < 2) s_cnt[threadIdx.x] = 0;
         __syncthreads();
@@ -1081,7 +1181,10 @@ __global__ __launch_bounds__(256) void k_pq_insert(const uint8_t* __restrict__ f
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 bool claimed = false;
-                const uint32_t slot = pq_insert(f, w, k, value_hash(f, w, k, r, seed, mask), (uint32_t)r, &claimed);
+                const int64_t a = w.val_a[k * w.max_rows + r];
+                const int32_t b = w.val_b[k * w.max_rows + r];
+                const uint32_t slot =
+                    pq_insert(f, aligned, w, k, value_hash(f, aligned, a, b, seed, mask), (uint32_t)r, a, b, &claimed);
                 w.slot[k * w.max_rows + r] = slot;
                 if (claimed) s_new[k][atomicAdd(&s_cnt[k], 1u)] = slot;
             }
@@ -1168,8 +1271,8 @@ hipError_t launch_pq_decode(const uint8_t* file, PqWs w, int64_t n_chunks, int64
                             hipStream_t s) {
     k_pq_init<<<1, 64, 0, s>>>(w, rows);
     if (n_chunks > 0) {
-        k_pq_decode<true><<<(unsigned)n_chunks, kPB, 0, s>>>(file, w, ts_out);
-        k_pq_decode<false><<<dim3((unsigned)n_chunks, kPageSplit), kPB, 0, s>>>(file, w, ts_out);
+        k_pq_pages<<<dim3((unsigned)n_chunks, 2), kPB, 0, s>>>(file, w);
+        k_pq_decode<<<dim3((unsigned)n_chunks, kPageSplit), kPB, 0, s>>>(file, w, ts_out);
     }
     return hipGetLastError();
 }

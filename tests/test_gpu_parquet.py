@@ -150,3 +150,19 @@ def test_unsupported_and_malformed():
     with pytest.raises(pm4g.Pm4gError) as e:
         pm4g.pm4g_ingest_parquet(_dev(good), 0, 1, 2, capacity=10)
     assert e.value.code == pm4g.PM4G_E_CAPACITY
+
+
+def test_pages_of_few_values_and_long_byte_arrays():
+    """Pages of a few values each (more than the page table reserves, so the
+    decode walks the headers again) and byte arrays longer than the chain
+    walk's candidate window (entries found by walking a segment directly)."""
+    rng = np.random.default_rng(21)
+    t = _table(rng, 3_000, "string", "string", "int64", n_cases=900)
+    _check(_write(t, data_page_size=64, write_batch_size=4))
+    _check(_write(t, data_page_size=64, write_batch_size=4, use_dictionary=False, data_page_version="2.0"))
+    n = 4_000
+    long_case = pa.array(["case " + "y" * int(rng.integers(0, 900)) + str(x) for x in rng.integers(0, 700, n)])
+    t2 = pa.table({"case": long_case, "activity": pa.array([f"a{x}" for x in rng.integers(0, 30, n)]),
+                   "time": pa.array(rng.integers(0, 2**40, n))})
+    _check(_write(t2, use_dictionary=False))
+    _check(_write(t2, dictionary_pagesize_limit=100_000))

@@ -231,7 +231,9 @@ void csv(int64_t n_bytes, int64_t max_rows) {
     }
 }
 
-// Parquet: the chunk list (the host rejects more than kPqMaxChunks); each
+// Parquet: the chunk list (the host rejects more than kPqMaxChunks) and a
+// page count and dictionary size per chunk; the page table (the host hands
+// the chunks ranges of it, never past pt_size entries); each
 // chunk's dictionary holds at most its values (checked per dictionary page),
 // and the chunks of the three columns hold 3 * rows values; two value columns
 // and two slot columns of max_rows; two tables; the slots claimed in each
@@ -241,7 +243,8 @@ void parquet(int64_t max_rows) {
     const PqWs w = pq_ws_layout(b, max_rows);
     const int64_t rows = at_least1(max_rows);
     check(tag("parquet", max_rows), b.off,
-          {NEED(w, scal, 12), NEED(w, chunks, kPqMaxChunks), NEED(w, dict_a, 3 * rows), NEED(w, dict_b, 3 * rows),
+          {NEED(w, scal, 12), NEED(w, chunks, kPqMaxChunks), NEED(w, pages, w.pt_size * kPqPageBytes),
+           NEED(w, pt_n, kPqMaxChunks), NEED(w, pt_dict, kPqMaxChunks), NEED(w, dict_a, 3 * rows), NEED(w, dict_b, 3 * rows),
            NEED(w, val_a, 2 * rows), NEED(w, val_b, 2 * rows), NEED(w, slot, 2 * rows), NEED(w, table, 2 * w.tsize),
            NEED(w, dlist, 2 * rows), NEED(w, k0, rows), NEED(w, v0, rows), NEED(w, k1, rows),
            NEED(w, v1, rows), NEED(w, hist, 256 * dev::tiles(rows)), NEED(w, rowsum, 256),
