@@ -318,7 +318,6 @@ def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int, autot
     else:   # the cached launch shape (library defaults without a cache entry)
         tune = pm4g.BatchedTuning(pair_capacity=int(req[3] * 1.1) + 1024,
                                   record_capacity=int(req[1] * 1.1) + 1024,
-                                  descriptor_capacity=int(req[2] * 1.1) + 1024,
                                   cell_capacity=int(req[4] * 1.1) + 1024)
         hit = tuner.default_cache().lookup(log.n_activities, n_views, prep.n_events)
         if hit is not None:
@@ -340,7 +339,7 @@ def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int, autot
     # per-view launches of the same entry point on a sample of the views
     idx = np.linspace(0, n_views - 1, per_view_sample).astype(int)
     one_t = pm4g.BatchedTuning(pair_capacity=int(req[3]) + 1024, record_capacity=int(req[1]) + 1024,
-                               descriptor_capacity=int(req[2]) + 1024, cell_capacity=int(req[4]) + 1024)
+                               cell_capacity=int(req[4]) + 1024)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for v in idx:
@@ -368,7 +367,7 @@ def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int, autot
     return {"views_per_s": n_views / dt, "ms_per_call": dt * 1e3, "n_views": n_views,
             "event_view_visits_per_s": visits / dt, "cpu_oracle": cpu_oracle,
             "event_view_visits": visits, "output_cells": req[0], "records": req[1],
-            "run_descriptors": req[2], "tile_view_pairs": req[3],
+            "run_places": req[2], "tile_view_pairs": req[3],
             "per_view_launch_views_per_s": 1.0 / per_view_s,
             "per_view_launch_sample": len(idx),
             "speedup_vs_per_view_launches": per_view_s * n_views / dt,

@@ -207,8 +207,8 @@ typedef struct {
  *   start_count, end_count, act_count   [n_views * A], row v for view v
  *   n_events, n_cases                   [n_views] kept events and cases
  *   required   device int64[5]: output cells, internal records, internal run
- *              descriptors, (tile, view) pairs and internal aggregated cells
- *              the call needed
+ *              places ((tile, view) pairs x cell buckets), (tile, view) pairs
+ *              and internal aggregated cells the call needed
  *   status     device status word (PM4G_E_CAPACITY if cap_edges was short)
  */
 typedef struct {
@@ -234,8 +234,10 @@ typedef struct {
  * Launch shape and internal capacities of pm4g_dfg_batched (NULL or zero
  * fields: defaults).  tile_events is 2048 or 4096 (events of the log staged
  * per block); emit_blocks and agg_blocks are grid sizes; the capacities size
- * the workspace: (tile, view) pairs, records (one per kept event), run
- * descriptors and aggregated cells (before compaction into the output).
+ * the workspace: (tile, view) pairs, records (one per kept event) and
+ * aggregated cells (before compaction into the output); each pair also holds
+ * one run place per bucket of 4096 cells.  descriptor_capacity is ignored
+ * (kept for the layout of the struct).
  */
 typedef struct {
     int32_t tile_events;

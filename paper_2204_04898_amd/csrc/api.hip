@@ -49,7 +49,7 @@ constexpr int64_t kMaxEvents = (int64_t(1) << 31) - 1;
 __global__ void k_set_status(int32_t* status, int32_t code) { *status = code; }
 struct BatchedTune {
     int tile, emit_blocks, agg_blocks;
-    int64_t pair_cap, rec_cap, desc_cap, cell_cap;
+    int64_t pair_cap, rec_cap, cell_cap;
 };
 
 int resolve_tuning(const pm4g_batched_tuning* t, int64_t n, int32_t V, BatchedTune* r) {
@@ -69,10 +69,9 @@ int resolve_tuning(const pm4g_batched_tuning* t, int64_t n, int32_t V, BatchedTu
     const int64_t tiles = (n + r->tile - 1) / r->tile;
     r->pair_cap = (t && t->pair_capacity) ? t->pair_capacity : 4 * (tiles + V) + 1024;
     r->rec_cap = (t && t->record_capacity) ? t->record_capacity : (n > 4096 ? n : 4096);
-    r->desc_cap = (t && t->descriptor_capacity) ? t->descriptor_capacity : 8 * r->pair_cap;
     r->cell_cap = (t && t->cell_capacity) ? t->cell_capacity : (r->rec_cap / 2 > 4096 ? r->rec_cap / 2 : 4096);
-    if (r->desc_cap > (int64_t)0xFFFFFFF0 || r->pair_cap > (int64_t)0xFFFFFFF0) {
-        set_err("descriptor and pair capacities must stay below 2^32");
+    if (r->pair_cap > (int64_t)0xFFFFFFF0) {
+        set_err("the pair capacity must stay below 2^32");
         return PM4G_E_INVALID;
     }
     return PM4G_OK;
@@ -80,7 +79,7 @@ int resolve_tuning(const pm4g_batched_tuning* t, int64_t n, int32_t V, BatchedTu
 
 size_t batched_ws_bytes(int64_t n, int32_t A, int32_t V, const BatchedTune& t) {
     Bump b(nullptr);
-    view_ws_layout(b, n, A, V, t.tile, t.pair_cap, t.rec_cap, t.desc_cap, t.cell_cap);
+    view_ws_layout(b, n, A, V, t.tile, t.pair_cap, t.rec_cap, t.cell_cap);
     return b.off + 256;
 }
 
@@ -745,7 +744,7 @@ int pm4g_dfg_batched(const pm4g_prepared* log, const pm4g_view* views, const uin
     hipStream_t s = (hipStream_t)stream;
     Bump bp(ws);
     ViewWs w = view_ws_layout(bp, log->n_events, log->n_activities, n_views, t.tile, t.pair_cap, t.rec_cap,
-                              t.desc_cap, t.cell_cap);
+                              t.cell_cap);
     const BatchedOutDev o{out->edge_off, out->src, out->dst, out->count, out->dt_sum, out->dt_min,
                           out->dt_max, out->dt_mean, out->start_count, out->end_count, out->act_count,
                           out->n_events, out->n_cases, out->cap_edges, out->required, out->status};

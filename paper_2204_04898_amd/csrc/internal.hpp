@@ -215,7 +215,7 @@ struct ViewWs {
     int32_t tile;
     int32_t n_buckets;
     int64_t n_tiles;
-    int64_t pair_cap, rec_cap, desc_cap, cell_cap;
+    int64_t pair_cap, rec_cap, cell_cap;
     int64_t* p0;            // [V] event slice of each view
     int64_t* p1;
     uint32_t* tcount;       // [tiles + 2] overlapping views per tile
@@ -227,10 +227,9 @@ struct ViewWs {
     int64_t* part64;
     uint16_t* rec_cell;     // [rec_cap] records: cell within its bucket (logs with a case of
     uint64_t* rec_gap;      //   2^52 time units or more), gap; else cell << 52 | gap in rec_gap
-    uint32_t* pair_dbase;   // [pair_cap] first descriptor of each (tile, view) pair
-    uint32_t* pair_nd;      // [pair_cap] its descriptors (non-empty buckets)
-    uint16_t* d_q;          // [desc_cap] run descriptors: bucket of the run
-    uint32_t* d_rel;        //   first record of the run within its (view, bucket) segment
+    uint32_t* pair_kept;    // [pair_cap] nonzero when the (tile, view) pair has a kept event
+    uint32_t* pair_rel;     // [pair_cap * n_buckets] place of the pair's run of records
+                            //   inside each (view, bucket) segment (non-empty runs only)
     int64_t n_vb;           // V * n_buckets (view, bucket) pairs
     uint32_t* vb_cnt;       // [n_vb] records of each (view, bucket)
     int64_t* vb_base;       // [n_vb] its segment's first record (exclusive scan)
@@ -250,7 +249,7 @@ struct ViewWs {
 };
 int64_t view_buckets(int32_t A);
 ViewWs view_ws_layout(Bump& b, int64_t n, int32_t A, int32_t V, int32_t tile, int64_t pair_cap,
-                      int64_t rec_cap, int64_t desc_cap, int64_t cell_cap);
+                      int64_t rec_cap, int64_t cell_cap);
 struct BatchedOutDev {
     int64_t* edge_off;
     int32_t* src;
@@ -303,11 +302,11 @@ hipError_t launch_filter_cases(const pm4g_prepared* p, const pm4g_case_filter* f
 
 hipError_t launch_views_plan(const pm4g_prepared* p, const pm4g_view* views, int32_t V, ViewWs w,
                              BatchedOutDev out, hipStream_t s);
-// Count walk: per (tile, view) pair its records per bucket, one descriptor per
-// non-empty bucket; record and descriptor totals in scal[0], scal[1].
+// Count walk: per (tile, view) pair its records per bucket; each non-empty
+// run's place inside its (view, bucket) segment.
 hipError_t launch_views_count(const pm4g_prepared* p, const pm4g_view* views, const uint64_t* masks,
                               ViewWs w, int grid, hipStream_t s);
-// After the descriptors are sorted and placed: write walk into runs.
+// After the segments are placed: write walk into the runs.
 hipError_t launch_views_write(const pm4g_prepared* p, const pm4g_view* views, const uint64_t* masks,
                               ViewWs w, int grid, hipStream_t s);
 hipError_t launch_views_reduce(const pm4g_prepared* p, const pm4g_view* views, const uint64_t* masks, int32_t V,

@@ -17,14 +17,16 @@
 //   k_view_tile_scan per-tile counts of overlapping views, offsets
 //   k_view_fill      per-tile lists of overlapping views
 //   k_view_count /   tile-major: a block stages one tile of the log in LDS;
-//   k_view_write     each wave takes one overlapping view and walks the tile 64
-//                    events at a time: ballots give the previous kept event of
-//                    the same case, carried across windows and (by a backward
-//                    search) across tiles.  A pair gives a record (cell = x*A+y,
-//                    gap); a start gives (A*A + y, 0).  The walk runs twice:
+//   k_view_write     each wave takes one overlapping view and walks the tile:
+//                    the view's predicate lists the kept positions (ballots),
+//                    and the kept events, 64 at a time, find the previous kept
+//                    event in the neighbouring lane, carried across groups and
+//                    (by a backward search) across tiles.  A pair gives a
+//                    record (cell = x*A+y, gap); a start gives (A*A + y, 0).
+//                    The walk runs twice:
 //                    count per cell bucket (cell >> 12) and take each run's
-//                    place in its (view, bucket) segment with one atomic (one
-//                    descriptor per (tile, view, bucket) run), then write runs
+//                    place in its (view, bucket) segment with one atomic (kept
+//                    per (tile, view, bucket)), then write the runs
 //   scans            (view, bucket) counters -> segment places; non-empty
 //                    pairs -> the segment list
 //   k_view_agg       one block per (view, bucket) segment: 4096-cell LDS table;
@@ -52,7 +54,6 @@ constexpr int kMaskWords = PM4G_BATCHED_MAX_ACTIVITIES / 64;
 constexpr int kAB2 = 1024;                // threads per aggregation block
 constexpr uint64_t kRecGapLimit = 1ull << 52;   // gaps below it share a u64 with the cell
 
-__device__ __forceinline__ int hi_bit(uint64_t m) { return 63 - __clzll((long long)m); }
 
 // Value of lane l (l the same in every lane: read into a scalar register, no
 // LDS round trip as a shuffle would take).
@@ -70,20 +71,18 @@ int64_t view_buckets(int32_t A) {
 }
 
 ViewWs view_ws_layout(Bump& b, int64_t n, int32_t A, int32_t V, int32_t tile, int64_t pair_cap,
-                      int64_t rec_cap, int64_t desc_cap, int64_t cell_cap) {
+                      int64_t rec_cap, int64_t cell_cap) {
     ViewWs w{};
     const size_t cc = (size_t)(cell_cap > 0 ? cell_cap : 1);
     w.cell_cap = cell_cap;
     const int64_t tiles = (n + tile - 1) / tile;
     const size_t vm = (size_t)(V > 0 ? V : 1);
     const size_t rc = (size_t)(rec_cap > 0 ? rec_cap : 1);
-    const size_t dc = (size_t)(desc_cap > 0 ? desc_cap : 1);
     w.tile = tile;
     w.n_tiles = tiles;
     w.n_buckets = (int32_t)view_buckets(A);
     w.pair_cap = pair_cap;
     w.rec_cap = rec_cap;
-    w.desc_cap = desc_cap;
     w.p0 = b.take<int64_t>(vm);
     w.p1 = b.take<int64_t>(vm);
     w.tcount = b.take<uint32_t>((size_t)tiles + 2);
@@ -95,10 +94,8 @@ ViewWs view_ws_layout(Bump& b, int64_t n, int32_t A, int32_t V, int32_t tile, in
     w.part64 = b.take<int64_t>(dev::kScanGrid);
     w.rec_cell = b.take<uint16_t>(rc);
     w.rec_gap = b.take<uint64_t>(rc);
-    w.pair_dbase = b.take<uint32_t>((size_t)(pair_cap > 0 ? pair_cap : 1));
-    w.pair_nd = b.take<uint32_t>((size_t)(pair_cap > 0 ? pair_cap : 1));
-    w.d_q = b.take<uint16_t>(dc);
-    w.d_rel = b.take<uint32_t>(dc);
+    w.pair_kept = b.take<uint32_t>((size_t)(pair_cap > 0 ? pair_cap : 1));
+    w.pair_rel = b.take<uint32_t>((size_t)(pair_cap > 0 ? pair_cap : 1) * (size_t)w.n_buckets);
     w.n_vb = (int64_t)(V > 0 ? V : 0) * w.n_buckets;
     const size_t nvb = (size_t)(w.n_vb > 0 ? w.n_vb : 1);
     w.vb_cnt = b.take<uint32_t>(nvb);
@@ -121,18 +118,19 @@ ViewWs view_ws_layout(Bump& b, int64_t n, int32_t A, int32_t V, int32_t tile, in
 
 namespace {
 
-// scal: [0] records, [1] descriptor cursor, [2] #segments (u32 total
-// written at [8] as u32 by the scan, copied here), [3] temporary cell cursor,
-// [4] total output cells, [6] #views, [7] #pairs, [9] records placed (scan
-// total), [10] nonzero when some case lasts 2^52 time units or more (records
-// then keep the cell in a separate array), [11] (view, bucket) pairs, [12]
-// the gate after the count walk: 0, or the status that stops the call
+// scal: [2] #segments (u32 total written at [8] as u32 by the scan, copied
+// here), [3] temporary cell cursor, [4] total output cells, [6] #views, [7]
+// #pairs, [9] records (scan total), [10] nonzero when some case lasts 2^52
+// time units or more (records then keep the cell in a separate array), [11]
+// (view, bucket) pairs, [12] the gate after the count walk: 0, or the status
+// that stops the call
 //
 // Record places.  The count walk adds each (tile, view) pair's records per
 // bucket to the (view, bucket) counter with one atomic, whose old value is the
-// run's place inside that (view, bucket) segment; an exclusive scan of the
-// counters in (view, bucket) order gives the segments' places, so every
-// segment's records form one contiguous range in (view, bucket) order.
+// run's place inside that (view, bucket) segment (kept per pair and bucket);
+// an exclusive scan of the counters in (view, bucket) order gives the
+// segments' places, so every segment's records form one contiguous range in
+// (view, bucket) order.
 //
 // Records.  A record's gap is at most its case's duration, so when every case
 // of the log lasts less than 2^52 units a record is one u64 in rec_gap:
@@ -297,105 +295,122 @@ __device__ WalkState walk_init(const int32_t* case_s, const int32_t* act_s, cons
     return st;
 }
 
-// One walk over [e0, e1) of the staged tile (T0 = first position of the tile).
-// Every kept event yields one record; WRITE=false counts per bucket in
-// cursor[], WRITE=true takes record places from cursor[] (each bucket's
-// cursor starts at its run) and writes the records.
+// One walk over [e0, e1) of the staged tile (T0 = first position of the tile),
+// in rounds of kSub events.  Pass 1 tests the view's predicate on the round's
+// events and appends the kept positions to the wave's list; pass 2 takes the
+// listed kept events 64 at a time (a partial group waits for the next round,
+// except in the last one): lane l's previous kept event of the slice is lane
+// l - 1's (a DPP shift; lane 0 takes the carry, the last kept event before
+// the group), and the event starts its case's kept events iff that previous
+// one lies in another case or does not exist (cases are contiguous).  Every
+// kept event yields one record: WRITE=false counts per bucket in cursor[],
+// WRITE=true takes record places from cursor[] (each bucket's cursor starts
+// at its run) and writes the records.
+constexpr int kSub = 512;             // events per round (8 windows of 64)
+constexpr int kList = kSub + kWave;   // a round's kept positions plus the previous round's rest
+
 template <bool WRITE>
-__device__ void walk(const int32_t* s_case, const int16_t* s_act, const int64_t* s_ts, int64_t T0,
-                     int64_t e0, int64_t e1, WalkState st, int32_t A, int64_t tlo, int64_t thi,
-                     const uint64_t* mask, uint32_t* cursor, uint16_t* rec_cell, uint64_t* rec_gap, bool wide) {
-    const int64_t AA = (int64_t)A * A;
-    const uint64_t below = lanes_below();
-    for (int64_t b0 = e0; b0 < e1; b0 += kWave) {
-        const int64_t i = b0 + lane();
-        const bool in = i < e1;
-        int32_t c = 0, a = 0;
-        int64_t t = 0;
-        bool k = false;
-        if (in) {
-            const int li = (int)(i - T0);
-            c = s_case[li];
-            a = s_act[li];
-            t = s_ts[li];
-            k = kept(a, t, tlo, thi, mask);
+__device__ __forceinline__ void walk(const int32_t* __restrict__ s_case, const int16_t* __restrict__ s_act,
+                                     const int64_t* __restrict__ s_ts, int64_t T0, int64_t e0, int64_t e1,
+                                     WalkState st, int32_t A, int64_t tlo, int64_t thi,
+                                     const uint64_t* __restrict__ mask, uint16_t* __restrict__ list,
+                                     uint32_t* __restrict__ cursor, uint16_t* __restrict__ rec_cell,
+                                     uint64_t* __restrict__ rec_gap, bool wide) {
+    const int32_t AA = A * A;
+    // carry: the last kept event of the slice before the current group
+    bool pv = st.cr_valid;
+    int32_t pc = st.cur, pa = st.cr_a;
+    int64_t pt = st.cr_t;
+    int n = 0;   // listed kept positions (wave-uniform)
+    const int b1 = (int)(e1 - T0);
+    for (int r0 = (int)(e0 - T0); r0 < b1; r0 += kSub) {
+        const int r1 = r0 + kSub < b1 ? r0 + kSub : b1;
+        // all loads of the round issued before any use (positions past the
+        // round read its last event and are not kept)
+        constexpr int kU = kSub / kWave;
+        int32_t av[kU];
+        int64_t tv[kU];
+        uint64_t mv[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int i = r0 + u * kWave + lane();
+            const int ii = i < r1 ? i : r1 - 1;
+            av[u] = s_act[ii];
+            tv[u] = s_ts[ii];
         }
-        // lane l - 1's case (DPP wave shift right by one; lane 0 reads 0 and
-        // uses the carry below)
-        const int32_t cup = __builtin_amdgcn_update_dpp(0, c, 0x138, 0xF, 0xF, false);
-        bool starts;
-        if (lane() == 0) starts = !st.have_cur || c != st.cur;
-        else starts = c != cup;
-        starts = starts && in;
-        const uint64_t K = __ballot(k);
-        const uint64_t S = __ballot(starts);
-        if (K == 0) {   // wave-uniform: nothing kept in this step, only the carry moves
-            if (S) st.cr_valid = false;   // the last case began here, nothing of it kept yet
-            st.cur = lane_i32(c, hi_bit(__ballot(in)));
-            st.have_cur = true;
-            continue;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) mv[u] = mask[av[u] >> 6];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int i = r0 + u * kWave + lane();
+            const bool k = (i < r1) & (tv[u] >= tlo) & (tv[u] <= thi) & (((mv[u] >> (av[u] & 63)) & 1ull) != 0);
+            const uint64_t K = __ballot(k);
+            const uint32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(K >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)K, (uint32_t)n));
+            if (k) list[at] = (uint16_t)i;
+            n += __popcll(K);
         }
-        // The nearest lane j below this one that is kept or starts a case: when
-        // this lane starts its case it has no previous kept event; else a kept
-        // lane j is the previous kept event of the case (no start lies between),
-        // a non-kept start j means none is kept before this lane, and with no
-        // such lane the case began before the window (the carry).  Lane j's
-        // activity travels with its kept flag in bit 30 (activities < 2^30).
-        const uint64_t gb = (K | S) & below;
-        const int j = gb ? hi_bit(gb) : -1;
-        const int32_t aj = __shfl(a | (k ? 0x40000000 : 0), j < 0 ? 0 : j);
-        const int64_t tj = __shfl(t, j < 0 ? 0 : j);
-        if (k) {
-            bool has_prev;
-            int32_t pa;
-            int64_t pt;
-            if (starts) {
-                has_prev = false;
-                pa = 0;
-                pt = 0;
-            } else if (j < 0) {
-                has_prev = st.cr_valid;
-                pa = st.cr_a;
-                pt = st.cr_t;
-            } else {
-                has_prev = (aj & 0x40000000) != 0;
-                pa = aj & 0x3FFFFFFF;
-                pt = tj;
+        __builtin_amdgcn_wave_barrier();
+        const bool last = r1 >= b1;
+        int c0 = 0;
+        for (; c0 + kWave <= n || (last && c0 < n); c0 += kWave) {
+            const int j = c0 + lane();
+            const bool in = j < n;
+            int32_t c = 0, a = 0;
+            int64_t t = 0;
+            if (in) {
+                const int q = list[j];
+                c = s_case[q];
+                a = s_act[q];
+                t = s_ts[q];
             }
-            const int64_t cell = has_prev ? (int64_t)pa * A + a : AA + a;
-            const uint64_t gap = has_prev ? (uint64_t)t - (uint64_t)pt : 0ull;
-            const uint32_t slot = atomicAdd(&cursor[(uint32_t)(cell >> 12)], 1u);
-            if (WRITE) {   // slot: the record's place (the cursor starts at its run)
-                const uint64_t q = (uint64_t)(cell & (kCellsPerTable - 1));
-                if (wide) {
-                    rec_cell[slot] = (uint16_t)q;
-                    rec_gap[slot] = gap;
-                } else {
-                    rec_gap[slot] = (q << 52) | gap;
+            // lane l - 1's event: a DPP wave shift right by one, whose lane 0
+            // (no source lane) keeps the first operand, the carry
+            const int32_t cq = __builtin_amdgcn_update_dpp(pc, c, 0x138, 0xF, 0xF, false);
+            const int32_t aq = __builtin_amdgcn_update_dpp(pa, a, 0x138, 0xF, 0xF, false);
+            const uint32_t tql = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)pt, (int)(uint32_t)t,
+                                                                       0x138, 0xF, 0xF, false);
+            const uint32_t tqh = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)((uint64_t)pt >> 32),
+                                                                       (int)(uint32_t)((uint64_t)t >> 32),
+                                                                       0x138, 0xF, 0xF, false);
+            const uint64_t tq = ((uint64_t)tqh << 32) | tql;
+            const bool starts = (lane() == 0 && !pv) || c != cq;
+            if (in) {
+                const int32_t cell = starts ? AA + a : aq * A + a;
+                const uint64_t gap = starts ? 0ull : (uint64_t)t - tq;
+                const uint32_t slot = atomicAdd(&cursor[(uint32_t)cell >> 12], 1u);
+                if (WRITE) {   // slot: the record's place (the cursor starts at its run)
+                    const uint64_t qc = (uint64_t)(cell & (kCellsPerTable - 1));
+                    if (wide) {
+                        rec_cell[slot] = (uint16_t)qc;
+                        rec_gap[slot] = gap;
+                    } else {
+                        rec_gap[slot] = (qc << 52) | gap;
+                    }
                 }
             }
+            const int ll = (n - c0 < kWave ? n - c0 : kWave) - 1;
+            pv = true;
+            pc = lane_i32(c, ll);
+            pa = lane_i32(a, ll);
+            pt = lane_i64(t, ll);
         }
-        // carry to the next window
-        const int lastS = S ? hi_bit(S) : -1;
-        const uint64_t Klast = lastS < 0 ? K : (K & ~((uint64_t(1) << lastS) - 1));
-        const int lk = Klast ? hi_bit(Klast) : 0;
-        const int32_t ak = lane_i32(a, lk);
-        const int64_t tk = lane_i64(t, lk);
-        if (Klast) {
-            st.cr_valid = true;
-            st.cr_a = ak;
-            st.cr_t = tk;
-        } else if (lastS >= 0) {
-            st.cr_valid = false;
+        // the rest (fewer than 64) moves to the front of the list
+        if (c0 > 0 && c0 < n) {
+            const int rest = n - c0;
+            uint16_t x = 0;
+            if (lane() < rest) x = list[c0 + lane()];
+            __builtin_amdgcn_wave_barrier();
+            if (lane() < rest) list[lane()] = x;
         }
-        const int lin = hi_bit(__ballot(in));
-        st.cur = lane_i32(c, lin);
-        st.have_cur = true;
+        n -= c0;
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
-// Count walk.  Rounds of one view per wave: the block reserves the round's
-// descriptors with one atomic (and adds the round's records to the total).
+// Count walk.  Each wave takes the tile's overlapping views in turn; after a
+// view's walk, each non-empty bucket's run takes its place in the (view,
+// bucket) segment with one atomic on the segment's counter.
 template <int TILE>
 __global__ __launch_bounds__(kVB) void k_view_count(const int32_t* __restrict__ case_s,
                                                     const int32_t* __restrict__ act_s,
@@ -407,8 +422,7 @@ __global__ __launch_bounds__(kVB) void k_view_count(const int32_t* __restrict__ 
     __shared__ int64_t s_ts[TILE];
     __shared__ uint64_t s_mask[kVW][kMaskWords];
     __shared__ uint32_t s_cur[kVW][kMaxBuckets];
-    __shared__ uint32_t s_rrun[kVW], s_drun[kVW];
-    __shared__ int64_t s_dbase[kVW];
+    __shared__ uint16_t s_list[kVW][kList];
 
     const int wv = threadIdx.x / kWave;
     const int NB = w.n_buckets;
@@ -427,71 +441,26 @@ __global__ __launch_bounds__(kVB) void k_view_count(const int32_t* __restrict__ 
         __syncthreads();
         const uint32_t cnt = w.tcount[tile];
         const int64_t off = w.toff[tile];
-        for (uint32_t j0 = 0; j0 < cnt; j0 += kVW) {   // block-uniform
-            const uint32_t j = j0 + wv;
-            const bool has = j < cnt;
-            uint32_t v = 0, run = 0, nne = 0;
-            if (has) {   // wave-uniform
-                v = w.list[off + j];
-                const pm4g_view vw = views[v];
-                const int64_t p0 = w.p0[v], p1 = w.p1[v];
-                for (int q = lane(); q < MW; q += kWave) mask[q] = masks[(size_t)v * MW + q];
-                const int64_t e0 = T0 > p0 ? T0 : p0;
-                const int64_t e1 = T1 < p1 ? T1 : p1;
-                const WalkState st = walk_init(case_s, act_s, ts_s, e0, p0, vw.t_lo, vw.t_hi, mask);
-                for (int q = lane(); q < NB; q += kWave) cur[q] = 0;
-                walk<false>(s_case, s_act, s_ts, T0, e0, e1, st, A, vw.t_lo, vw.t_hi, mask, cur,
-                            w.rec_cell, w.rec_gap, false);
-                for (int q0 = 0; q0 < NB; q0 += kWave) {
-                    const int q = q0 + lane();
-                    const uint32_t c = q < NB ? cur[q] : 0u;
-                    run += (uint32_t)wave_sum((uint64_t)c);
-                    nne += (uint32_t)__popcll(__ballot(c != 0));
-                }
+        for (uint32_t j = wv; j < cnt; j += kVW) {
+            const uint32_t v = w.list[off + j];
+            const pm4g_view vw = views[v];
+            const int64_t p0 = w.p0[v], p1 = w.p1[v];
+            for (int q = lane(); q < MW; q += kWave) mask[q] = masks[(size_t)v * MW + q];
+            const int64_t e0 = T0 > p0 ? T0 : p0;
+            const int64_t e1 = T1 < p1 ? T1 : p1;
+            const WalkState st = walk_init(case_s, act_s, ts_s, e0, p0, vw.t_lo, vw.t_hi, mask);
+            for (int q = lane(); q < NB; q += kWave) cur[q] = 0;
+            walk<false>(s_case, s_act, s_ts, T0, e0, e1, st, A, vw.t_lo, vw.t_hi, mask, s_list[wv], cur,
+                        w.rec_cell, w.rec_gap, false);
+            uint32_t* rel = w.pair_rel + (size_t)(off + j) * (size_t)NB;
+            uint64_t any = 0;
+            for (int q0 = 0; q0 < NB; q0 += kWave) {
+                const int q = q0 + lane();
+                const uint32_t c = q < NB ? cur[q] : 0u;
+                any |= __ballot(c != 0);
+                if (c != 0) rel[q] = atomicAdd(&w.vb_cnt[(size_t)v * NB + q], c);
             }
-            if (lane() == 0) {
-                s_rrun[wv] = run;
-                s_drun[wv] = nne;
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                uint64_t rt = 0, dt = 0;
-                for (int k = 0; k < kVW; ++k) {
-                    rt += s_rrun[k];
-                    dt += s_drun[k];
-                }
-                if (rt) atomicAdd(reinterpret_cast<unsigned long long*>(&w.scal[0]), (unsigned long long)rt);
-                uint64_t db = 0;
-                if (dt) db = atomicAdd(reinterpret_cast<unsigned long long*>(&w.scal[1]), (unsigned long long)dt);
-                for (int k = 0; k < kVW; ++k) {
-                    s_dbase[k] = (int64_t)db;
-                    db += s_drun[k];
-                }
-            }
-            __syncthreads();
-            if (has) {   // wave-uniform
-                const int64_t dbase = s_dbase[wv];
-                const bool ok = dbase + (int64_t)nne <= w.desc_cap;
-                if (lane() == 0) {
-                    w.pair_dbase[off + j] = (uint32_t)dbase;
-                    w.pair_nd[off + j] = ok ? nne : 0u;
-                }
-                uint32_t drun = 0;
-                for (int q0 = 0; q0 < NB; q0 += kWave) {
-                    const int q = q0 + lane();
-                    const uint32_t c = q < NB ? cur[q] : 0u;
-                    const uint64_t nzm = __ballot(c != 0);
-                    if (c != 0) {
-                        const uint32_t rel = atomicAdd(&w.vb_cnt[(size_t)v * NB + q], c);
-                        if (ok) {
-                            const int64_t d = dbase + drun + __popcll(nzm & lanes_below());
-                            w.d_q[d] = (uint16_t)q;
-                            w.d_rel[d] = rel;
-                        }
-                    }
-                    drun += (uint32_t)__popcll(nzm);
-                }
-            }
+            if (lane() == 0) w.pair_kept[off + j] = any != 0 ? 1u : 0u;
         }
         __syncthreads();
     }
@@ -510,8 +479,10 @@ __global__ __launch_bounds__(kVB) void k_view_write(const int32_t* __restrict__ 
     __shared__ int64_t s_ts[TILE];
     __shared__ uint64_t s_mask[kVW][kMaskWords];
     __shared__ uint32_t s_cur[kVW][kMaxBuckets];
+    __shared__ uint16_t s_list[kVW][kList];
 
     const int wv = threadIdx.x / kWave;
+    const int NB = w.n_buckets;
     const int MW = (A + 63) / 64;
     const bool wide = w.scal[10] != 0;
     uint64_t* mask = s_mask[wv];
@@ -532,8 +503,7 @@ __global__ __launch_bounds__(kVB) void k_view_write(const int32_t* __restrict__ 
         const uint32_t cnt = w.tcount[tile];
         const int64_t off = w.toff[tile];
         for (uint32_t j = wv; j < cnt; j += kVW) {
-            const uint32_t nd = w.pair_nd[off + j];
-            if (nd == 0) continue;   // no kept event
+            if (!w.pair_kept[off + j]) continue;   // no kept event
             const uint32_t v = w.list[off + j];
             const pm4g_view vw = views[v];
             const int64_t p0 = w.p0[v], p1 = w.p1[v];
@@ -541,27 +511,24 @@ __global__ __launch_bounds__(kVB) void k_view_write(const int32_t* __restrict__ 
             const int64_t e0 = T0 > p0 ? T0 : p0;
             const int64_t e1 = T1 < p1 ? T1 : p1;
             const WalkState st = walk_init(case_s, act_s, ts_s, e0, p0, vw.t_lo, vw.t_hi, mask);
-            // cursors: the runs' first records (buckets without a run get no event)
-            const uint32_t db = w.pair_dbase[off + j];
-            for (uint32_t k = lane(); k < nd; k += kWave) {
-                const uint32_t q = w.d_q[db + k];
-                cur[q] = (uint32_t)(w.vb_base[(size_t)v * w.n_buckets + q] + w.d_rel[db + k]);
-            }
-            walk<true>(s_case, s_act, s_ts, T0, e0, e1, st, A, vw.t_lo, vw.t_hi, mask, cur,
+            // cursors: the runs' first records (buckets without a run get no record)
+            const uint32_t* rel = w.pair_rel + (size_t)(off + j) * (size_t)NB;
+            for (int q = lane(); q < NB; q += kWave) cur[q] = (uint32_t)(w.vb_base[(size_t)v * NB + q] + rel[q]);
+            walk<true>(s_case, s_act, s_ts, T0, e0, e1, st, A, vw.t_lo, vw.t_hi, mask, s_list[wv], cur,
                        w.rec_cell, w.rec_gap, wide);
         }
         __syncthreads();
     }
 }
 
-// The gate after the count walk: every capacity the later kernels write into
-// is known now; if one is short (or the records exceed 32-bit places) the
-// call stops here, reported by k_view_finish.
+// The gate after the count walk and the segment scans: every capacity the
+// later kernels write into is known now; if one is short (or the records
+// exceed 32-bit places) the call stops here, reported by k_view_finish.
 __global__ void k_view_gate(ViewWs w) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         int64_t g = 0;
-        if (w.scal[7] > w.pair_cap || w.scal[0] > w.rec_cap || w.scal[1] > w.desc_cap) g = PM4G_E_CAPACITY;
-        if (w.scal[7] <= w.pair_cap && w.scal[0] > (int64_t)0xFFFFFFFF) g = PM4G_E_INVALID;
+        if (w.scal[7] > w.pair_cap || w.scal[9] > w.rec_cap) g = PM4G_E_CAPACITY;
+        if (w.scal[7] <= w.pair_cap && w.scal[9] > (int64_t)0xFFFFFFFF) g = PM4G_E_INVALID;
         w.scal[12] = g;
     }
 }
@@ -794,8 +761,8 @@ __global__ void k_view_finish(int32_t V, ViewWs w, BatchedOutDev out) {
         const bool pairs_short = w.scal[7] > w.pair_cap;   // then the count walk did not run
         out.edge_off[V] = gate ? 0 : w.scal[4];
         out.required[0] = gate ? 0 : w.scal[4];             // unknown until the records are placed
-        out.required[1] = pairs_short ? 0 : w.scal[0];
-        out.required[2] = pairs_short ? 0 : w.scal[1];
+        out.required[1] = pairs_short ? 0 : w.scal[9];
+        out.required[2] = w.scal[7] * (int64_t)w.n_buckets;   // run places: pairs x buckets
         out.required[3] = w.scal[7];
         out.required[4] = gate ? 0 : w.scal[3];
         if (gate) set_status(out.status, (int32_t)gate);
@@ -853,10 +820,10 @@ hipError_t launch_views_reduce(const pm4g_prepared* p, const pm4g_view* views, c
     const int32_t A = p->n_activities;
     {
         ProfScope ps(P_VIEW_PLACE, s);
-        k_view_gate<<<1, 64, 0, s>>>(w);
         k_view_vb_flags<<<1024, 256, 0, s>>>(w, V);
         dev::excl_scan<int64_t>(w.vb_cnt, &w.scal[11], w.vb_base, w.part64, &w.scal[9], s);
         dev::excl_scan<uint32_t>(w.vb_flag, &w.scal[11], w.vb_seg, w.part32, (uint32_t*)&w.scal[8], s);
+        k_view_gate<<<1, 64, 0, s>>>(w);
         k_view_segs<<<1024, 256, 0, s>>>(w);
     }
     {

@@ -545,8 +545,6 @@ def pm4g_dfg_batched(prep: Prepared, views: torch.Tensor, masks: torch.Tensor, n
             t.pair_capacity = grow(t.pair_capacity, req[3])
         if req[1] > 0:
             t.record_capacity = grow(t.record_capacity, req[1])
-        if req[2] > 0:
-            t.descriptor_capacity = grow(t.descriptor_capacity, req[2])
         if req[4] > 0:
             t.cell_capacity = grow(t.cell_capacity, req[4])
         if req[0] > o["cap_edges"]:

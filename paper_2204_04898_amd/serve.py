@@ -315,26 +315,24 @@ class GpuExecutor:
         return 4 * S if r.kind == "variants" else S
 
     # capacities of one view in a batched call: one record per kept event
-    # (at most the slice's events), the (tile, view) pairs its slice spans,
-    # a descriptor per (tile, view, bucket) run, cells and output cells at
-    # most one per kept event and A*A (+A start cells) per view
+    # (at most the slice's events), the (tile, view) pairs its slice spans
+    # (the library keeps a run place per pair and cell bucket), cells and
+    # output cells at most one per kept event and A*A (+A start cells) per view
     _TILE = 2048   # the smaller tile: its pair count bounds the larger one's
 
-    def _caps(self, r: Request) -> tuple[int, int, int, int, int]:
+    def _caps(self, r: Request) -> tuple[int, int, int, int]:
         A = self.logs[r.log]["prep"].n_activities
         S = self.slice_events(r)
         pairs = S // self._TILE + 2
-        nb = (A * (A + 1) + 4095) // 4096
-        return (S + 1, pairs, pairs * nb, min(S, A * (A + 1)) + 1, min(S, A * A) + 1)
+        return (S + 1, pairs, min(S, A * (A + 1)) + 1, min(S, A * A) + 1)
 
     def _batched_tuning(self, rs: list[Request]):
         caps = [self._caps(r) for r in rs]
         t = self.pm4g.BatchedTuning()
         t.record_capacity = sum(c[0] for c in caps)
         t.pair_capacity = sum(c[1] for c in caps)
-        t.descriptor_capacity = sum(c[2] for c in caps)
-        t.cell_capacity = sum(c[3] for c in caps)
-        return t, sum(c[4] for c in caps)
+        t.cell_capacity = sum(c[2] for c in caps)
+        return t, sum(c[3] for c in caps)
 
     def estimate(self, r: Request) -> int:
         """Device bytes the request makes its batch allocate: the library's

@@ -141,7 +141,7 @@ def tune_batched(prep, views, masks, n_views: int, reps: int = 3, candidates=CAN
     out = pm4g.pm4g_dfg_batched(prep, views, masks, n_views, tuning=pm4g.BatchedTuning())
     req = [int(x) for x in out["required"].cpu().tolist()]
     caps = dict(pair_capacity=int(req[3] * 1.1) + 1024, record_capacity=int(req[1] * 1.1) + 1024,
-                descriptor_capacity=int(req[2] * 1.1) + 1024, cell_capacity=int(req[4] * 1.1) + 1024)
+                cell_capacity=int(req[4] * 1.1) + 1024)
     tunings: dict = {}
 
     def run(c):
@@ -152,7 +152,6 @@ def tune_batched(prep, views, masks, n_views: int, reps: int = 3, candidates=CAN
             o = pm4g.pm4g_dfg_batched(prep, views, masks, n_views, tuning=t, out=out)
             r = [int(x) for x in o["required"].cpu().tolist()]
             t.pair_capacity = max(t.pair_capacity, int(r[3] * 1.1) + 1024)
-            t.descriptor_capacity = max(t.descriptor_capacity, int(r[2] * 1.1) + 1024)
             tunings[c] = t
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -108,7 +108,7 @@ def test_views_capacity_retry():
     """Tiny capacities force the PM4G_E_CAPACITY path; the binding retries with what was required."""
     log = synth.config_log(3, 0.002)
     views = synth.make_views(log, 16, seed=11, min_events=100, max_events=100_000)
-    t = pm4g.BatchedTuning(pair_capacity=8, record_capacity=64, descriptor_capacity=16, cell_capacity=16)
+    t = pm4g.BatchedTuning(pair_capacity=8, record_capacity=64, cell_capacity=16)
     check_views(log, views, tuning=t)
 
 
@@ -179,7 +179,6 @@ def test_batched_call_does_not_wait_and_reports_capacity_on_the_device():
     req = o["required"].cpu().numpy()
     assert req[1] > 64 and req[3] > 0
     tun.record_capacity = int(req[1])
-    tun.descriptor_capacity = max(int(req[2]), 1)
     for _ in range(3):   # the cell counts become known once the records fit
         need = int(L.pm4g_batched_workspace_bytes(prep.n_events, A, V, ctypes.byref(tun)))
         with torch.cuda.stream(s):

@@ -146,25 +146,25 @@ void variants(int64_t n) {
 
 // Batched views: per tile a view count at p0 / tile and a decrement at
 // (p1 - 1) / tile + 1 <= tiles, their scan with the total at [tiles]; tile
-// lists, records and descriptors bounded by their capacities (checked on the
-// device before any write past them); V * buckets (view, bucket) counters and
-// segments with the segment total at [segments]; scal up to [12].
-void views(int64_t n, int32_t A, int32_t V, int32_t tile, int64_t pair_cap, int64_t rec_cap, int64_t desc_cap,
-           int64_t cell_cap) {
+// lists and records bounded by their capacities (checked on the device before
+// any write past them), a kept flag per pair and a run place per (pair,
+// bucket); V * buckets (view, bucket) counters and segments with the segment
+// total at [segments]; scal up to [12].
+void views(int64_t n, int32_t A, int32_t V, int32_t tile, int64_t pair_cap, int64_t rec_cap, int64_t cell_cap) {
     Bump b(kBase);
-    const ViewWs w = view_ws_layout(b, n, A, V, tile, pair_cap, rec_cap, desc_cap, cell_cap);
+    const ViewWs w = view_ws_layout(b, n, A, V, tile, pair_cap, rec_cap, cell_cap);
     const int64_t tiles = ceil_div(n, tile), nvb = at_least1((int64_t)V * view_buckets(A)), vm = at_least1(V);
     check(tag("views", n, A, V) + "/" + std::to_string(tile), b.off,
           {NEED(w, p0, vm), NEED(w, p1, vm), NEED(w, tcount, tiles + 2), NEED(w, toff, tiles + 1),
            NEED(w, tcursor, tiles + 1), NEED(w, list, at_least1(pair_cap)), NEED(w, scal, 13),
            NEED(w, part32, dev::kScanGrid), NEED(w, part64, dev::kScanGrid), NEED(w, rec_cell, at_least1(rec_cap)),
-           NEED(w, rec_gap, at_least1(rec_cap)), NEED(w, pair_dbase, at_least1(pair_cap)),
-           NEED(w, pair_nd, at_least1(pair_cap)), NEED(w, d_q, at_least1(desc_cap)),
-           NEED(w, d_rel, at_least1(desc_cap)), NEED(w, vb_cnt, nvb), NEED(w, vb_base, nvb), NEED(w, vb_flag, nvb),
-           NEED(w, vb_seg, nvb), NEED(w, seg_key, nvb), NEED(w, seg_rec, nvb + 1), NEED(w, seg_cells, nvb),
-           NEED(w, seg_tmp, nvb), NEED(w, seg_out, nvb), NEED(w, view_cells, vm), NEED(w, t_cell, at_least1(cell_cap)),
-           NEED(w, t_count, at_least1(cell_cap)), NEED(w, t_sum, at_least1(cell_cap)),
-           NEED(w, t_min, at_least1(cell_cap)), NEED(w, t_max, at_least1(cell_cap))});
+           NEED(w, rec_gap, at_least1(rec_cap)), NEED(w, pair_kept, at_least1(pair_cap)),
+           NEED(w, pair_rel, at_least1(pair_cap) * view_buckets(A)), NEED(w, vb_cnt, nvb), NEED(w, vb_base, nvb),
+           NEED(w, vb_flag, nvb), NEED(w, vb_seg, nvb), NEED(w, seg_key, nvb), NEED(w, seg_rec, nvb + 1),
+           NEED(w, seg_cells, nvb), NEED(w, seg_tmp, nvb), NEED(w, seg_out, nvb), NEED(w, view_cells, vm),
+           NEED(w, t_cell, at_least1(cell_cap)), NEED(w, t_count, at_least1(cell_cap)),
+           NEED(w, t_sum, at_least1(cell_cap)), NEED(w, t_min, at_least1(cell_cap)),
+           NEED(w, t_max, at_least1(cell_cap))});
 }
 
 // Event filters: one count per kFilterTile tile of the scanned range, its scan
@@ -274,8 +274,8 @@ int main() {
             for (int32_t tile : {256, 4096}) {
                 const int64_t tiles = ceil_div(n, tile);
                 const int64_t pair_cap = 4 * (tiles + V) + 1024, rec_cap = std::max<int64_t>(n, 4096);
-                views(n, 512, V, tile, pair_cap, rec_cap, 8 * pair_cap, std::max<int64_t>(rec_cap / 2, 4096));
-                views(n, 64, V, tile, 1, 1, 1, 1);
+                views(n, 512, V, tile, pair_cap, rec_cap, std::max<int64_t>(rec_cap / 2, 4096));
+                views(n, 64, V, tile, 1, 1, 1);
             }
         parquet(n);
     }
