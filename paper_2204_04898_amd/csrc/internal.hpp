@@ -227,7 +227,8 @@ struct ViewWs {
     int64_t* part64;
     uint16_t* rec_cell;     // [rec_cap] records: cell within its bucket (logs with a case of
     uint64_t* rec_gap;      //   2^52 time units or more), gap; else cell << 52 | gap in rec_gap
-    uint32_t* pair_kept;    // [pair_cap] nonzero when the (tile, view) pair has a kept event
+    uint4* pair_carry;      // [pair_cap] per (tile, view) pair: the walk's initial carry and
+                            //   whether it keeps an event
     uint32_t* pair_rel;     // [pair_cap * n_buckets] place of the pair's run of records
                             //   inside each (view, bucket) segment (non-empty runs only)
     int64_t n_vb;           // V * n_buckets (view, bucket) pairs

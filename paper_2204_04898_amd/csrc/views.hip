@@ -94,7 +94,7 @@ ViewWs view_ws_layout(Bump& b, int64_t n, int32_t A, int32_t V, int32_t tile, in
     w.part64 = b.take<int64_t>(dev::kScanGrid);
     w.rec_cell = b.take<uint16_t>(rc);
     w.rec_gap = b.take<uint64_t>(rc);
-    w.pair_kept = b.take<uint32_t>((size_t)(pair_cap > 0 ? pair_cap : 1));
+    w.pair_carry = b.take<uint4>((size_t)(pair_cap > 0 ? pair_cap : 1));
     w.pair_rel = b.take<uint32_t>((size_t)(pair_cap > 0 ? pair_cap : 1) * (size_t)w.n_buckets);
     w.n_vb = (int64_t)(V > 0 ? V : 0) * w.n_buckets;
     const size_t nvb = (size_t)(w.n_vb > 0 ? w.n_vb : 1);
@@ -308,6 +308,65 @@ __device__ WalkState walk_init(const int32_t* case_s, const int32_t* act_s, cons
 // at its run) and writes the records.
 constexpr int kSub = 512;             // events per round (8 windows of 64)
 constexpr int kList = kSub + kWave;   // a round's kept positions plus the previous round's rest
+constexpr int kListAlloc = kList + kWave;   // and a slot per lane for the events not kept
+
+// Pass 1 over [r0, r1) (FULL: r1 = r0 + kSub): all loads issued before any
+// use; returns the list length.  mask32: the view's activity mask as 32-bit
+// words (bit a of the mask is bit a & 31 of word a >> 5).
+template <bool FULL>
+__device__ __forceinline__ int list_kept(const int16_t* __restrict__ s_act, const int64_t* __restrict__ s_ts,
+                                         int r0, int r1, int64_t tlo, int64_t thi,
+                                         const uint32_t* __restrict__ mask32, uint16_t* __restrict__ list, int n) {
+    constexpr int kU = kSub / kWave;
+    int32_t av[kU];
+    int64_t tv[kU];
+    uint32_t mv[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const int i = r0 + u * kWave + lane();
+        const int ii = FULL ? i : (i < r1 ? i : r1 - 1);   // past the round: its last event, not kept
+        av[u] = s_act[ii];
+        tv[u] = s_ts[ii];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) mv[u] = mask32[av[u] >> 5];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        // one ballot per comparison (each folds to the comparison's lane
+        // mask); every lane stores, the kept ones at their list place, the
+        // others at their own slot past the list (no branch)
+        const int i = r0 + u * kWave + lane();
+        const bool ki = FULL || i < r1;
+        const bool ka = __builtin_amdgcn_ubfe(mv[u], (uint32_t)av[u], 1u) != 0;   // bit a & 31
+        const bool k1 = tv[u] >= tlo;
+        const bool k2 = tv[u] <= thi;
+        uint64_t K = __builtin_amdgcn_ballot_w64(ka) & __builtin_amdgcn_ballot_w64(k1) &
+                     __builtin_amdgcn_ballot_w64(k2);
+        if (!FULL) K &= __builtin_amdgcn_ballot_w64(ki);
+        const uint32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(K >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)K, 0u));
+        list[(ki & ka & k1 & k2) ? (uint32_t)n + at : (uint32_t)(kList + lane())] = (uint16_t)i;
+        n += __popcll(K);
+    }
+    return n;
+}
+
+struct KeptEv {
+    int32_t c, a;
+    int64_t t;
+};
+
+__device__ __forceinline__ KeptEv kept_event(const int32_t* __restrict__ s_case, const int16_t* __restrict__ s_act,
+                                             const int64_t* __restrict__ s_ts, const uint16_t* __restrict__ list,
+                                             int j, int n) {
+    KeptEv e{0, 0, 0};
+    if (j < n) {
+        const int q = list[j];
+        e.c = s_case[q];
+        e.a = s_act[q];
+        e.t = s_ts[q];
+    }
+    return e;
+}
 
 template <bool WRITE>
 __device__ __forceinline__ void walk(const int32_t* __restrict__ s_case, const int16_t* __restrict__ s_act,
@@ -317,6 +376,7 @@ __device__ __forceinline__ void walk(const int32_t* __restrict__ s_case, const i
                                      uint32_t* __restrict__ cursor, uint16_t* __restrict__ rec_cell,
                                      uint64_t* __restrict__ rec_gap, bool wide) {
     const int32_t AA = A * A;
+    const uint32_t* mask32 = reinterpret_cast<const uint32_t*>(mask);
     // carry: the last kept event of the slice before the current group
     bool pv = st.cr_valid;
     int32_t pc = st.cur, pa = st.cr_a;
@@ -325,59 +385,28 @@ __device__ __forceinline__ void walk(const int32_t* __restrict__ s_case, const i
     const int b1 = (int)(e1 - T0);
     for (int r0 = (int)(e0 - T0); r0 < b1; r0 += kSub) {
         const int r1 = r0 + kSub < b1 ? r0 + kSub : b1;
-        // all loads of the round issued before any use (positions past the
-        // round read its last event and are not kept)
-        constexpr int kU = kSub / kWave;
-        int32_t av[kU];
-        int64_t tv[kU];
-        uint64_t mv[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int i = r0 + u * kWave + lane();
-            const int ii = i < r1 ? i : r1 - 1;
-            av[u] = s_act[ii];
-            tv[u] = s_ts[ii];
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) mv[u] = mask[av[u] >> 6];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int i = r0 + u * kWave + lane();
-            const bool k = (i < r1) & (tv[u] >= tlo) & (tv[u] <= thi) & (((mv[u] >> (av[u] & 63)) & 1ull) != 0);
-            const uint64_t K = __ballot(k);
-            const uint32_t at = __builtin_amdgcn_mbcnt_hi((uint32_t)(K >> 32),
-                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)K, (uint32_t)n));
-            if (k) list[at] = (uint16_t)i;
-            n += __popcll(K);
-        }
+        if (r1 - r0 == kSub) n = list_kept<true>(s_act, s_ts, r0, r1, tlo, thi, mask32, list, n);
+        else n = list_kept<false>(s_act, s_ts, r0, r1, tlo, thi, mask32, list, n);
         __builtin_amdgcn_wave_barrier();
         const bool last = r1 >= b1;
         int c0 = 0;
         for (; c0 + kWave <= n || (last && c0 < n); c0 += kWave) {
-            const int j = c0 + lane();
-            const bool in = j < n;
-            int32_t c = 0, a = 0;
-            int64_t t = 0;
-            if (in) {
-                const int q = list[j];
-                c = s_case[q];
-                a = s_act[q];
-                t = s_ts[q];
-            }
+            const bool in = c0 + lane() < n;
+            const KeptEv e = kept_event(s_case, s_act, s_ts, list, c0 + lane(), n);
             // lane l - 1's event: a DPP wave shift right by one, whose lane 0
             // (no source lane) keeps the first operand, the carry
-            const int32_t cq = __builtin_amdgcn_update_dpp(pc, c, 0x138, 0xF, 0xF, false);
-            const int32_t aq = __builtin_amdgcn_update_dpp(pa, a, 0x138, 0xF, 0xF, false);
-            const uint32_t tql = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)pt, (int)(uint32_t)t,
+            const int32_t cq = __builtin_amdgcn_update_dpp(pc, e.c, 0x138, 0xF, 0xF, false);
+            const int32_t aq = __builtin_amdgcn_update_dpp(pa, e.a, 0x138, 0xF, 0xF, false);
+            const uint32_t tql = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)pt, (int)(uint32_t)e.t,
                                                                        0x138, 0xF, 0xF, false);
             const uint32_t tqh = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)((uint64_t)pt >> 32),
-                                                                       (int)(uint32_t)((uint64_t)t >> 32),
+                                                                       (int)(uint32_t)((uint64_t)e.t >> 32),
                                                                        0x138, 0xF, 0xF, false);
             const uint64_t tq = ((uint64_t)tqh << 32) | tql;
-            const bool starts = (lane() == 0 && !pv) || c != cq;
+            const bool starts = (lane() == 0 && !pv) || e.c != cq;
             if (in) {
-                const int32_t cell = starts ? AA + a : aq * A + a;
-                const uint64_t gap = starts ? 0ull : (uint64_t)t - tq;
+                const int32_t cell = starts ? AA + e.a : aq * A + e.a;
+                const uint64_t gap = starts ? 0ull : (uint64_t)e.t - tq;
                 const uint32_t slot = atomicAdd(&cursor[(uint32_t)cell >> 12], 1u);
                 if (WRITE) {   // slot: the record's place (the cursor starts at its run)
                     const uint64_t qc = (uint64_t)(cell & (kCellsPerTable - 1));
@@ -391,9 +420,9 @@ __device__ __forceinline__ void walk(const int32_t* __restrict__ s_case, const i
             }
             const int ll = (n - c0 < kWave ? n - c0 : kWave) - 1;
             pv = true;
-            pc = lane_i32(c, ll);
-            pa = lane_i32(a, ll);
-            pt = lane_i64(t, ll);
+            pc = lane_i32(e.c, ll);
+            pa = lane_i32(e.a, ll);
+            pt = lane_i64(e.t, ll);
         }
         // the rest (fewer than 64) moves to the front of the list
         if (c0 > 0 && c0 < n) {
@@ -403,14 +432,23 @@ __device__ __forceinline__ void walk(const int32_t* __restrict__ s_case, const i
             __builtin_amdgcn_wave_barrier();
             if (lane() < rest) list[lane()] = x;
         }
-        n -= c0;
+        n = c0 < n ? n - c0 : 0;
         __builtin_amdgcn_wave_barrier();
     }
 }
 
-// Count walk.  Each wave takes the tile's overlapping views in turn; after a
-// view's walk, each non-empty bucket's run takes its place in the (view,
-// bucket) segment with one atomic on the segment's counter.
+// The tile's (view) pairs are taken in turn by the block's waves: the first
+// kVW by wave index, the others from an LDS counter as waves finish theirs.
+__device__ __forceinline__ uint32_t next_pair(uint32_t* s_next) {
+    uint32_t j = 0;
+    if (lane() == 0) j = atomicAdd(s_next, 1u);
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)j);
+}
+
+// Count walk.  After a view's walk, each non-empty bucket's run takes its
+// place in the (view, bucket) segment with one atomic on the segment's
+// counter; the walk's initial carry and whether the pair keeps an event are
+// kept for the write walk (pair_carry: ts, case, act | valid << 30 | kept << 31).
 template <int TILE>
 __global__ __launch_bounds__(kVB) void k_view_count(const int32_t* __restrict__ case_s,
                                                     const int32_t* __restrict__ act_s,
@@ -422,7 +460,8 @@ __global__ __launch_bounds__(kVB) void k_view_count(const int32_t* __restrict__ 
     __shared__ int64_t s_ts[TILE];
     __shared__ uint64_t s_mask[kVW][kMaskWords];
     __shared__ uint32_t s_cur[kVW][kMaxBuckets];
-    __shared__ uint16_t s_list[kVW][kList];
+    __shared__ uint16_t s_list[kVW][kListAlloc];
+    __shared__ uint32_t s_next;
 
     const int wv = threadIdx.x / kWave;
     const int NB = w.n_buckets;
@@ -438,10 +477,11 @@ __global__ __launch_bounds__(kVB) void k_view_count(const int32_t* __restrict__ 
             s_act[i - T0] = (int16_t)act_s[i];
             s_ts[i - T0] = ts_s[i];
         }
+        if (threadIdx.x == 0) s_next = kVW;
         __syncthreads();
         const uint32_t cnt = w.tcount[tile];
         const int64_t off = w.toff[tile];
-        for (uint32_t j = wv; j < cnt; j += kVW) {
+        for (uint32_t j = wv; j < cnt; j = next_pair(&s_next)) {
             const uint32_t v = w.list[off + j];
             const pm4g_view vw = views[v];
             const int64_t p0 = w.p0[v], p1 = w.p1[v];
@@ -460,14 +500,20 @@ __global__ __launch_bounds__(kVB) void k_view_count(const int32_t* __restrict__ 
                 any |= __ballot(c != 0);
                 if (c != 0) rel[q] = atomicAdd(&w.vb_cnt[(size_t)v * NB + q], c);
             }
-            if (lane() == 0) w.pair_kept[off + j] = any != 0 ? 1u : 0u;
+            if (lane() == 0) {
+                const uint32_t aw = (uint32_t)(st.cr_valid ? st.cr_a : 0) | (st.cr_valid ? 1u << 30 : 0u) |
+                                    (any != 0 ? 1u << 31 : 0u);
+                w.pair_carry[off + j] = make_uint4((uint32_t)(uint64_t)st.cr_t, (uint32_t)((uint64_t)st.cr_t >> 32),
+                                                   (uint32_t)st.cur, aw);
+            }
         }
         __syncthreads();
     }
 }
 
 // Write walk: each (tile, view) pair's buckets start at their runs' places in
-// the segment-contiguous record layout.
+// the segment-contiguous record layout; the walk starts from the carry the
+// count walk found.
 template <int TILE>
 __global__ __launch_bounds__(kVB) void k_view_write(const int32_t* __restrict__ case_s,
                                                     const int32_t* __restrict__ act_s,
@@ -479,7 +525,9 @@ __global__ __launch_bounds__(kVB) void k_view_write(const int32_t* __restrict__ 
     __shared__ int64_t s_ts[TILE];
     __shared__ uint64_t s_mask[kVW][kMaskWords];
     __shared__ uint32_t s_cur[kVW][kMaxBuckets];
-    __shared__ uint16_t s_list[kVW][kList];
+    __shared__ uint16_t s_list[kVW][kListAlloc];
+    __shared__ uint32_t s_next;
+    constexpr int kQ = (kMaxBuckets + kWave - 1) / kWave;   // buckets per lane
 
     const int wv = threadIdx.x / kWave;
     const int NB = w.n_buckets;
@@ -499,21 +547,40 @@ __global__ __launch_bounds__(kVB) void k_view_write(const int32_t* __restrict__ 
             s_act[i - T0] = (int16_t)act_s[i];
             s_ts[i - T0] = ts_s[i];
         }
+        if (threadIdx.x == 0) s_next = kVW;
         __syncthreads();
         const uint32_t cnt = w.tcount[tile];
         const int64_t off = w.toff[tile];
-        for (uint32_t j = wv; j < cnt; j += kVW) {
-            if (!w.pair_kept[off + j]) continue;   // no kept event
+        for (uint32_t j = wv; j < cnt; j = next_pair(&s_next)) {
+            const uint4 cy = w.pair_carry[off + j];
+            if (!(cy.w >> 31)) continue;   // no kept event
             const uint32_t v = w.list[off + j];
+            // the runs' first records (buckets without a run get no record),
+            // loaded before anything waits
+            const uint32_t* rel = w.pair_rel + (size_t)(off + j) * (size_t)NB;
+            const int64_t* vbb = w.vb_base + (size_t)v * NB;
+            uint32_t qv[kQ];
+#pragma unroll
+            for (int u = 0; u < kQ; ++u) {
+                const int q = u * kWave + lane();
+                qv[u] = q < NB ? (uint32_t)vbb[q] + rel[q] : 0u;
+            }
             const pm4g_view vw = views[v];
             const int64_t p0 = w.p0[v], p1 = w.p1[v];
             for (int q = lane(); q < MW; q += kWave) mask[q] = masks[(size_t)v * MW + q];
+#pragma unroll
+            for (int u = 0; u < kQ; ++u) {
+                const int q = u * kWave + lane();
+                if (q < NB) cur[q] = qv[u];
+            }
             const int64_t e0 = T0 > p0 ? T0 : p0;
             const int64_t e1 = T1 < p1 ? T1 : p1;
-            const WalkState st = walk_init(case_s, act_s, ts_s, e0, p0, vw.t_lo, vw.t_hi, mask);
-            // cursors: the runs' first records (buckets without a run get no record)
-            const uint32_t* rel = w.pair_rel + (size_t)(off + j) * (size_t)NB;
-            for (int q = lane(); q < NB; q += kWave) cur[q] = (uint32_t)(w.vb_base[(size_t)v * NB + q] + rel[q]);
+            WalkState st;
+            st.have_cur = true;
+            st.cur = (int32_t)cy.z;
+            st.cr_valid = (cy.w >> 30) & 1u;
+            st.cr_a = (int32_t)(cy.w & 0x3FFFFFFFu);
+            st.cr_t = (int64_t)(((uint64_t)cy.y << 32) | cy.x);
             walk<true>(s_case, s_act, s_ts, T0, e0, e1, st, A, vw.t_lo, vw.t_hi, mask, s_list[wv], cur,
                        w.rec_cell, w.rec_gap, wide);
         }

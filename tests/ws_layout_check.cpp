@@ -147,7 +147,7 @@ void variants(int64_t n) {
 // Batched views: per tile a view count at p0 / tile and a decrement at
 // (p1 - 1) / tile + 1 <= tiles, their scan with the total at [tiles]; tile
 // lists and records bounded by their capacities (checked on the device before
-// any write past them), a kept flag per pair and a run place per (pair,
+// any write past them), a carry per pair and a run place per (pair,
 // bucket); V * buckets (view, bucket) counters and segments with the segment
 // total at [segments]; scal up to [12].
 void views(int64_t n, int32_t A, int32_t V, int32_t tile, int64_t pair_cap, int64_t rec_cap, int64_t cell_cap) {
@@ -158,7 +158,7 @@ void views(int64_t n, int32_t A, int32_t V, int32_t tile, int64_t pair_cap, int6
           {NEED(w, p0, vm), NEED(w, p1, vm), NEED(w, tcount, tiles + 2), NEED(w, toff, tiles + 1),
            NEED(w, tcursor, tiles + 1), NEED(w, list, at_least1(pair_cap)), NEED(w, scal, 13),
            NEED(w, part32, dev::kScanGrid), NEED(w, part64, dev::kScanGrid), NEED(w, rec_cell, at_least1(rec_cap)),
-           NEED(w, rec_gap, at_least1(rec_cap)), NEED(w, pair_kept, at_least1(pair_cap)),
+           NEED(w, rec_gap, at_least1(rec_cap)), NEED(w, pair_carry, at_least1(pair_cap)),
            NEED(w, pair_rel, at_least1(pair_cap) * view_buckets(A)), NEED(w, vb_cnt, nvb), NEED(w, vb_base, nvb),
            NEED(w, vb_flag, nvb), NEED(w, vb_seg, nvb), NEED(w, seg_key, nvb), NEED(w, seg_rec, nvb + 1),
            NEED(w, seg_cells, nvb), NEED(w, seg_tmp, nvb), NEED(w, seg_out, nvb), NEED(w, view_cells, vm),
