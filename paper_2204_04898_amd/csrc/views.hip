@@ -746,17 +746,35 @@ __global__ void k_view_copy(int32_t A, ViewWs w, BatchedOutDev out) {
     for (int64_t g = wv; g < S; g += nw) {
         const int64_t src = w.seg_tmp[g], dst = w.seg_out[g];
         const uint32_t m = w.seg_cells[g];
-        for (uint32_t r = lane(); r < m; r += kWave) {
-            const uint32_t cell = w.t_cell[src + r];
-            const uint32_t cnt = w.t_count[src + r];
-            const uint64_t sum = w.t_sum[src + r];
-            out.src[dst + r] = (int32_t)(cell / (uint32_t)A);
-            out.dst[dst + r] = (int32_t)(cell % (uint32_t)A);
-            out.count[dst + r] = cnt;
-            out.dt_sum[dst + r] = (int64_t)sum;
-            out.dt_min[dst + r] = w.t_min[src + r];
-            out.dt_max[dst + r] = w.t_max[src + r];
-            if (out.dt_mean) out.dt_mean[dst + r] = (double)(int64_t)sum / (double)(int64_t)cnt;
+        constexpr int kU = 4;   // all loads of kU steps issued before the stores
+        for (uint32_t r0 = 0; r0 < m; r0 += kU * kWave) {
+            uint32_t cell[kU], cnt[kU];
+            uint64_t sum[kU];
+            int64_t mn[kU], mx[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const uint32_t r = r0 + u * kWave + lane();
+                if (r < m) {
+                    cell[u] = w.t_cell[src + r];
+                    cnt[u] = w.t_count[src + r];
+                    sum[u] = w.t_sum[src + r];
+                    mn[u] = w.t_min[src + r];
+                    mx[u] = w.t_max[src + r];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const uint32_t r = r0 + u * kWave + lane();
+                if (r < m) {
+                    out.src[dst + r] = (int32_t)(cell[u] / (uint32_t)A);
+                    out.dst[dst + r] = (int32_t)(cell[u] % (uint32_t)A);
+                    out.count[dst + r] = cnt[u];
+                    out.dt_sum[dst + r] = (int64_t)sum[u];
+                    out.dt_min[dst + r] = mn[u];
+                    out.dt_max[dst + r] = mx[u];
+                    if (out.dt_mean) out.dt_mean[dst + r] = (double)(int64_t)sum[u] / (double)(int64_t)cnt[u];
+                }
+            }
         }
     }
 }
@@ -765,8 +783,10 @@ __global__ void k_view_copy(int32_t A, ViewWs w, BatchedOutDev out) {
 // cells into row and column sums; derive activity and end counts.
 __global__ __launch_bounds__(256) void k_view_acts(int32_t V, int32_t A, ViewWs w,
                                                    BatchedOutDev out) {
-    __shared__ unsigned long long rows[PM4G_BATCHED_MAX_ACTIVITIES];
-    __shared__ unsigned long long cols[PM4G_BATCHED_MAX_ACTIVITIES];
+    __shared__ uint32_t rows[PM4G_BATCHED_MAX_ACTIVITIES];   // at most the view's kept events (< 2^31)
+    __shared__ uint32_t cols[PM4G_BATCHED_MAX_ACTIVITIES];
+    __shared__ int64_t s_src[kMaxBuckets];
+    __shared__ uint32_t s_m[kMaxBuckets];
     __shared__ int64_t red[2][256 / kWave];
     const int64_t S = w.scal[2];
     const uint32_t NB = (uint32_t)w.n_buckets;
@@ -781,14 +801,41 @@ __global__ __launch_bounds__(256) void k_view_acts(int32_t V, int32_t A, ViewWs 
             if (w.seg_key[mid] < (uint32_t)v * NB) lo = mid + 1;
             else hi = mid;
         }
-        for (int64_t g = lo; g < S && w.seg_key[g] / NB == (uint32_t)v; ++g) {
-            const int64_t src = w.seg_tmp[g];
-            const uint32_t m = w.seg_cells[g];
-            for (uint32_t r = threadIdx.x; r < m; r += 256) {
-                const uint32_t cell = w.t_cell[src + r];
-                const unsigned long long c = w.t_count[src + r];
-                atomicAdd(&rows[cell / (uint32_t)A], c);
-                atomicAdd(&cols[cell % (uint32_t)A], c);
+        // the view's segments (at most NB): their places and cell counts to LDS
+        int ns = 0;
+        for (int k0 = 0; k0 < (int)NB; k0 += 256) {
+            const int k = k0 + threadIdx.x;
+            const bool mine = k < (int)NB && lo + k < S && w.seg_key[lo + k] / NB == (uint32_t)v;
+            if (mine) {
+                s_src[k] = w.seg_tmp[lo + k];
+                s_m[k] = w.seg_cells[lo + k];
+            }
+            ns += __syncthreads_count(mine);
+        }
+        __syncthreads();
+        for (int g = 0; g < ns; ++g) {
+            const int64_t src = s_src[g];
+            const uint32_t m = s_m[g];
+            constexpr int kU = 2;
+            for (uint32_t r0 = 0; r0 < m; r0 += kU * 256) {
+                uint32_t cell[kU], c[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const uint32_t r = r0 + u * 256 + threadIdx.x;
+                    cell[u] = 0;
+                    c[u] = 0;
+                    if (r < m) {
+                        cell[u] = w.t_cell[src + r];
+                        c[u] = w.t_count[src + r];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    if (c[u]) {
+                        atomicAdd(&rows[cell[u] / (uint32_t)A], c[u]);
+                        atomicAdd(&cols[cell[u] % (uint32_t)A], c[u]);
+                    }
+                }
             }
         }
         __syncthreads();
