@@ -624,22 +624,24 @@ __global__ void k_view_segs(ViewWs w) {
     }
 }
 
-__device__ __forceinline__ void view_agg_rec(uint32_t* scount, uint64_t* ssum, int64_t* smin, int64_t* smax,
+// smm: each cell's min and max side by side, read with one 16-byte load (a
+// stale pair only makes an atomic run that was not needed: min only falls
+// and max only rises).
+__device__ __forceinline__ void view_agg_rec(uint32_t* scount, uint64_t* ssum, int64_t* smm,
                                              uint32_t cell, uint64_t gap) {
     const int64_t gg = (int64_t)gap;
     atomicAdd(&scount[cell], 1u);
     atomicAdd(reinterpret_cast<unsigned long long*>(&ssum[cell]), (unsigned long long)gap);
-    if (gg < __hip_atomic_load(&smin[cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
-        __hip_atomic_fetch_min(&smin[cell], gg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (gg > __hip_atomic_load(&smax[cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
-        __hip_atomic_fetch_max(&smax[cell], gg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const longlong2 mm = *reinterpret_cast<const longlong2*>(&smm[2 * cell]);
+    if (gg < mm.x) __hip_atomic_fetch_min(&smm[2 * cell], gg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (gg > mm.y) __hip_atomic_fetch_max(&smm[2 * cell + 1], gg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Records [r, r1) of a segment, this thread's share (stride kAB2), into the
 // LDS table; WIDE: the cell sits in rec_cell, else in the top 12 bits.
 template <bool WIDE>
 __device__ __forceinline__ void agg_records(const ViewWs& w, int64_t r, int64_t r1, uint32_t* scount,
-                                            uint64_t* ssum, int64_t* smin, int64_t* smax) {
+                                            uint64_t* ssum, int64_t* smm) {
     constexpr int kU = 4;   // records in flight per thread
     for (; r + (kU - 1) * kAB2 < r1; r += kU * kAB2) {
         uint64_t x[kU];
@@ -651,12 +653,12 @@ __device__ __forceinline__ void agg_records(const ViewWs& w, int64_t r, int64_t 
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u)
-            view_agg_rec(scount, ssum, smin, smax, WIDE ? cell[u] : (uint32_t)(x[u] >> 52),
+            view_agg_rec(scount, ssum, smm, WIDE ? cell[u] : (uint32_t)(x[u] >> 52),
                          WIDE ? x[u] : (x[u] & (kRecGapLimit - 1)));
     }
     for (; r < r1; r += kAB2) {
         const uint64_t x = w.rec_gap[r];
-        view_agg_rec(scount, ssum, smin, smax, WIDE ? (uint32_t)w.rec_cell[r] : (uint32_t)(x >> 52),
+        view_agg_rec(scount, ssum, smm, WIDE ? (uint32_t)w.rec_cell[r] : (uint32_t)(x >> 52),
                      WIDE ? x : (x & (kRecGapLimit - 1)));
     }
 }
@@ -667,8 +669,7 @@ __device__ __forceinline__ void agg_records(const ViewWs& w, int64_t r, int64_t 
 __global__ __launch_bounds__(kAB2) void k_view_agg(int32_t A, ViewWs w, BatchedOutDev out) {
     __shared__ uint32_t scount[kCellsPerTable];
     __shared__ uint64_t ssum[kCellsPerTable];
-    __shared__ int64_t smin[kCellsPerTable];
-    __shared__ int64_t smax[kCellsPerTable];
+    __shared__ __align__(16) int64_t smm[2 * kCellsPerTable];
     __shared__ uint32_t tmp[kAB2 / kWave + 1];
     __shared__ int64_t s_base;
     if (w.scal[12] != 0) return;
@@ -679,8 +680,8 @@ __global__ __launch_bounds__(kAB2) void k_view_agg(int32_t A, ViewWs w, BatchedO
     for (int c = threadIdx.x; c < kCellsPerTable; c += kAB2) {
         scount[c] = 0;
         ssum[c] = 0;
-        smin[c] = INT64_MAX;
-        smax[c] = INT64_MIN;
+        smm[2 * c] = INT64_MAX;
+        smm[2 * c + 1] = INT64_MIN;
     }
     __syncthreads();
     for (int64_t g = blockIdx.x; g < S; g += gridDim.x) {
@@ -688,8 +689,8 @@ __global__ __launch_bounds__(kAB2) void k_view_agg(int32_t A, ViewWs w, BatchedO
         const uint32_t v = key / (uint32_t)NB;
         const uint32_t bk = key % (uint32_t)NB;
         const int64_t r1 = w.seg_rec[g + 1];
-        if (wide) agg_records<true>(w, w.seg_rec[g] + threadIdx.x, r1, scount, ssum, smin, smax);
-        else agg_records<false>(w, w.seg_rec[g] + threadIdx.x, r1, scount, ssum, smin, smax);
+        if (wide) agg_records<true>(w, w.seg_rec[g] + threadIdx.x, r1, scount, ssum, smm);
+        else agg_records<false>(w, w.seg_rec[g] + threadIdx.x, r1, scount, ssum, smm);
         __syncthreads();
         // compaction in cell order; start cells go straight to the start counts
         constexpr int kPer = kCellsPerTable / kAB2;   // 4 cells per thread, blocked
@@ -724,14 +725,14 @@ __global__ __launch_bounds__(kAB2) void k_view_agg(int32_t A, ViewWs w, BatchedO
                 w.t_cell[at] = (uint32_t)((int64_t)bk * kCellsPerTable + c);
                 w.t_count[at] = scount[c];
                 w.t_sum[at] = ssum[c];
-                w.t_min[at] = smin[c];
-                w.t_max[at] = smax[c];
+                w.t_min[at] = smm[2 * c];
+                w.t_max[at] = smm[2 * c + 1];
                 ++rr;
             }
             scount[c] = 0;   // reset for the next segment
             ssum[c] = 0;
-            smin[c] = INT64_MAX;
-            smax[c] = INT64_MIN;
+            smm[2 * c] = INT64_MAX;
+            smm[2 * c + 1] = INT64_MIN;
         }
         __syncthreads();
     }
