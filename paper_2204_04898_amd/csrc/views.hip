@@ -437,6 +437,25 @@ __device__ __forceinline__ void walk(const int32_t* __restrict__ s_case, const i
     }
 }
 
+// Tile order of the walks: chunks of kXcdChunk consecutive tiles are dealt
+// round-robin to the 8 XCDs (block b runs on XCD b % 8) and an XCD's blocks
+// stride over its chunks' tiles, so neighbouring tiles, whose runs of records
+// sit side by side in the record segments, are written through the same L2,
+// while the chunks keep the XCDs' loads even along the log.  The block's i-th
+// tile, or -1 past the end (the order is increasing in i).
+constexpr int64_t kXcdChunk = 64;
+__device__ __forceinline__ int64_t walk_tile(int64_t i, int64_t n_tiles) {
+    const int64_t G = gridDim.x, b = blockIdx.x;
+    int64_t t;
+    if (G % 8 != 0) {
+        t = b + i * G;
+    } else {
+        const int64_t x = b % 8, s = b / 8 + i * (G / 8);
+        t = ((s / kXcdChunk) * 8 + x) * kXcdChunk + s % kXcdChunk;
+    }
+    return t < n_tiles ? t : -1;
+}
+
 // The tile's (view) pairs are taken in turn by the block's waves: the first
 // kVW by wave index, the others from an LDS counter as waves finish theirs.
 __device__ __forceinline__ uint32_t next_pair(uint32_t* s_next) {
@@ -469,7 +488,7 @@ __global__ __launch_bounds__(kVB) void k_view_count(const int32_t* __restrict__ 
     uint64_t* mask = s_mask[wv];
     uint32_t* cur = s_cur[wv];
     if (w.scal[7] > w.pair_cap) return;   // the tile lists are incomplete: the gate stops the call
-    for (int64_t tile = blockIdx.x; tile < w.n_tiles; tile += gridDim.x) {
+    for (int64_t it = 0, tile; (tile = walk_tile(it, w.n_tiles)) >= 0; ++it) {
         const int64_t T0 = tile * TILE;
         const int64_t T1 = (T0 + TILE) < n ? (T0 + TILE) : n;
         for (int64_t i = T0 + threadIdx.x; i < T1; i += kVB) {
@@ -536,10 +555,7 @@ __global__ __launch_bounds__(kVB) void k_view_write(const int32_t* __restrict__ 
     uint64_t* mask = s_mask[wv];
     uint32_t* cur = s_cur[wv];
     if (w.scal[12] != 0) return;   // a capacity is short: no record is written
-    // tiles interleaved over the grid and so over the XCDs (contiguous per-XCD
-    // ranges measured slower here: a tile's work follows the number of views
-    // overlapping it, which varies along the log)
-    for (int64_t tile = blockIdx.x; tile < w.n_tiles; tile += gridDim.x) {
+    for (int64_t it = 0, tile; (tile = walk_tile(it, w.n_tiles)) >= 0; ++it) {
         const int64_t T0 = tile * TILE;
         const int64_t T1 = (T0 + TILE) < n ? (T0 + TILE) : n;
         for (int64_t i = T0 + threadIdx.x; i < T1; i += kVB) {
