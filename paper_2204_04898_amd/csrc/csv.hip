@@ -573,6 +573,29 @@ __device__ __forceinline__ uint32_t insert(CsvSlot* tab, int64_t tsize, uint64_t
     }
 }
 
+// Both values of a row: when each is already at its home slot (the common
+// case: the tables are at least twice the rows) the two lookups share their
+// memory round trips; otherwise one insert after the other.
+__device__ __forceinline__ void insert2(CsvSlot* t0, CsvSlot* t1, int64_t tsize, uint64_t h0, uint64_t h1,
+                                        uint32_t r, bool* claimed, uint32_t* s0, uint32_t* s1) {
+    const uint64_t i0 = h0 & (uint64_t)(tsize - 1), i1 = h1 & (uint64_t)(tsize - 1);
+    const unsigned long long c0 = __hip_atomic_load(reinterpret_cast<unsigned long long*>(&t0[i0].hash),
+                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long c1 = __hip_atomic_load(reinterpret_cast<unsigned long long*>(&t1[i1].hash),
+                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (c0 == h0 && c1 == h1) {
+        const uint32_t f0 = __hip_atomic_load(&t0[i0].first, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t f1 = __hip_atomic_load(&t1[i1].first, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (r < f0) atomicMin(&t0[i0].first, r);
+        if (r < f1) atomicMin(&t1[i1].first, r);
+        *s0 = (uint32_t)i0;
+        *s1 = (uint32_t)i1;
+        return;
+    }
+    *s0 = insert(t0, tsize, h0, r, &claimed[0]);
+    *s1 = insert(t1, tsize, h1, r, &claimed[1]);
+}
+
 // Bytes of the text already staged in LDS: [lo, lo + len) at stage[0..).
 struct StagedBytes {
     static constexpr bool kStaged = true;
@@ -729,8 +752,10 @@ __device__ __forceinline__ void parse_row(Src B, int64_t r, int64_t a, int64_t e
     w.flen[2 * r] = (int32_t)(ce - cb);
     w.foff[2 * r + 1] = ab;
     w.flen[2 * r + 1] = (int32_t)(ae - ab);
-    w.slot[2 * r] = insert(w.table, w.tsize, hc, (uint32_t)r, &claimed[0]);
-    w.slot[2 * r + 1] = insert(w.table + w.tsize, w.tsize, ha, (uint32_t)r, &claimed[1]);
+    uint32_t s0, s1;
+    insert2(w.table, w.table + w.tsize, w.tsize, hc, ha, (uint32_t)r, claimed, &s0, &s1);
+    w.slot[2 * r] = s0;
+    w.slot[2 * r + 1] = s1;
     bool ok = te - tb <= kTsMax;
     if (ok) {
         int64_t t;
@@ -818,20 +843,68 @@ __global__ __launch_bounds__(256) void k_csv_parse(const uint8_t* __restrict__ t
 }
 
 // Every row's value against its slot's first row, byte by byte: equal values,
-// or a hash collision (scal[4]: the call is repeated with another seed).
+// or a hash collision (scal[4]: the call is repeated with another seed).  A
+// thread takes two rows per step, and the four (row, field) items go through
+// each stage together (slot, first row, field ranges, first 16 bytes) so that
+// their loads are in flight at once; longer or unequal fields take the
+// general comparison.
 __global__ __launch_bounds__(256) void k_csv_verify(const uint8_t* __restrict__ text, int64_t n_bytes, CsvWs w) {
     const int64_t rows = w.scal[2];
     if (w.scal[3] != INT64_MAX) return;   // a parse error ends the call
     const bool aligned = (reinterpret_cast<uintptr_t>(text) & 7) == 0;
-    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < rows; r += (int64_t)gridDim.x * 256) {
-        for (int k = 0; k < 2; ++k) {
-            const uint32_t first = w.table[k * w.tsize + w.slot[2 * r + k]].first;
-            if (first == (uint32_t)r) continue;
-            const int64_t b1 = w.foff[2 * r + k], e1 = b1 + w.flen[2 * r + k];
-            const int64_t b2 = w.foff[2 * (int64_t)first + k], e2 = b2 + w.flen[2 * (int64_t)first + k];
-            if (e1 - b1 == e2 - b2 && raw_equal(text, n_bytes, b1, b2, e1 - b1, aligned)) continue;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    constexpr int kJ = 4;   // two rows x two fields
+    for (int64_t r0 = (int64_t)blockIdx.x * 256 + threadIdx.x; r0 < rows; r0 += 2 * stride) {
+        int64_t row[kJ];
+        uint32_t sl[kJ], first[kJ];
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) {
+            row[j] = r0 + (j >> 1) * stride;
+            sl[j] = row[j] < rows ? w.slot[2 * row[j] + (j & 1)] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kJ; ++j)
+            first[j] = row[j] < rows ? w.table[(j & 1) * w.tsize + sl[j]].first : (uint32_t)row[j];
+        bool need[kJ];
+        int64_t b1[kJ], b2[kJ];
+        int32_t l1[kJ], l2[kJ];
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) {
+            need[j] = row[j] < rows && first[j] != (uint32_t)row[j];
+            const int64_t r = need[j] ? row[j] : 0, f = need[j] ? (int64_t)first[j] : 0;
+            b1[j] = w.foff[2 * r + (j & 1)];
+            l1[j] = w.flen[2 * r + (j & 1)];
+            b2[j] = w.foff[2 * f + (j & 1)];
+            l2[j] = w.flen[2 * f + (j & 1)];
+        }
+        // fields of at most 16 bytes whose aligned words lie inside the text
+        bool quick[kJ];
+        uint64_t x0[kJ], x1[kJ], y0[kJ], y1[kJ];
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) {
+            quick[j] = need[j] && aligned && l1[j] == l2[j] && l1[j] <= 16 && b1[j] + 24 <= n_bytes &&
+                       b2[j] + 24 <= n_bytes;
+            x0[j] = x1[j] = y0[j] = y1[j] = 0;
+            if (quick[j]) {
+                x0[j] = word_at(text, b1[j]);
+                x1[j] = word_at(text, b1[j] + 8);
+                y0[j] = word_at(text, b2[j]);
+                y1[j] = word_at(text, b2[j] + 8);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) {
+            if (!need[j]) continue;
+            if (quick[j]) {
+                const int L = l1[j];
+                const uint64_t m0 = L >= 8 ? ~0ull : ((1ull << (8 * L)) - 1);
+                const uint64_t m1 = L >= 16 ? ~0ull : (L <= 8 ? 0ull : ((1ull << (8 * (L - 8))) - 1));
+                if (((x0[j] ^ y0[j]) & m0) == 0 && ((x1[j] ^ y1[j]) & m1) == 0) continue;
+            } else if (l1[j] == l2[j] && raw_equal(text, n_bytes, b1[j], b2[j], l1[j], aligned)) {
+                continue;
+            }
             Bytes B1(text, n_bytes), B2(text, n_bytes);
-            if (!same_value(B1, b1, e1, B2, b2, e2)) w.scal[4] = 1;
+            if (!same_value(B1, b1[j], b1[j] + l1[j], B2, b2[j], b2[j] + l2[j])) w.scal[4] = 1;
         }
     }
 }
