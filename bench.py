@@ -313,7 +313,7 @@ def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int, autot
         res = tuner.tune_batched(prep, vd, md, n_views, reps=2, log=log_progress)
         log_progress(f"views: autotune sweep {time.perf_counter() - t0:.1f} s")
         tune = res["tuning"]
-        tuned = {k: res["best"][k] for k in ("tile_events", "emit_blocks", "agg_blocks")}
+        tuned = {k: res["best"][k] for k in ("tile_events", "emit_blocks", "agg_blocks", "launch")}
         tuned["sweep"] = len(res["table"])
     else:   # the cached launch shape (library defaults without a cache entry)
         tune = pm4g.BatchedTuning(pair_capacity=int(req[3] * 1.1) + 1024,
@@ -324,6 +324,7 @@ def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int, autot
             tune.tile_events = int(hit["tile_events"])
             tune.emit_blocks = int(hit["emit_blocks"])
             tune.agg_blocks = int(hit["agg_blocks"])
+            tune.launch = int(hit.get("launch", 1))
     out = pm4g.pm4g_dfg_batched(prep, vd, md, n_views, tuning=tune, out=out)
     torch.cuda.synchronize()
     pm4g.profile_enable(True)
@@ -336,10 +337,24 @@ def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int, autot
     vprof = pm4g.profile_read()
     pm4g.profile_enable(False)
     view_stages = {name: tot / steps for name, (tot, cnt) in vprof.items() if cnt}
+    # the other launch mode on the same calls: the whole call as one persistent
+    # launch (launch 0) against one launch per phase (launch 1)
+    other = pm4g.BatchedTuning.from_buffer_copy(tune)
+    other.launch = 1 - tune.launch
+    if other.launch == 1 and other.emit_blocks == 0:
+        other.emit_blocks, other.agg_blocks = 2048, 256
+    pm4g.pm4g_dfg_batched(prep, vd, md, n_views, tuning=other, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pm4g.pm4g_dfg_batched(prep, vd, md, n_views, tuning=other, out=out)
+    torch.cuda.synchronize()
+    other_ms = (time.perf_counter() - t0) / steps * 1e3
     # per-view launches of the same entry point on a sample of the views
+    # (one launch per phase: the faster form for one small view)
     idx = np.linspace(0, n_views - 1, per_view_sample).astype(int)
     one_t = pm4g.BatchedTuning(pair_capacity=int(req[3]) + 1024, record_capacity=int(req[1]) + 1024,
-                               cell_capacity=int(req[4]) + 1024)
+                               cell_capacity=int(req[4]) + 1024, launch=1)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for v in idx:
@@ -372,9 +387,14 @@ def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int, autot
             "per_view_launch_sample": len(idx),
             "speedup_vs_per_view_launches": per_view_s * n_views / dt,
             "stages_ms_per_call": view_stages,
+            "ms_per_call_by_launch": {("one persistent launch" if tune.launch == 0 else "one launch per phase"):
+                                      dt * 1e3,
+                                      ("one persistent launch" if other.launch == 0 else "one launch per phase"):
+                                      other_ms},
             "tuning": tuned if tuned is not None else {"tile_events": tune.tile_events or 4096,
                                                        "emit_blocks": tune.emit_blocks or 2048,
-                                                       "agg_blocks": tune.agg_blocks or 512}}
+                                                       "agg_blocks": tune.agg_blocks or 512,
+                                                       "launch": tune.launch}}
 
 
 def bench_cases(log, prep, steps: int = 5) -> dict:

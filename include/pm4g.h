@@ -233,7 +233,10 @@ typedef struct {
 /*
  * Launch shape and internal capacities of pm4g_dfg_batched (NULL or zero
  * fields: defaults).  tile_events is 2048 or 4096 (events of the log staged
- * per block); emit_blocks and agg_blocks are grid sizes; the capacities size
+ * per block); launch is 0 (the whole call as one persistent cooperative
+ * launch on a grid of resident blocks) or 1 (one launch per phase, on the
+ * grids emit_blocks and agg_blocks for the walks and the aggregation); the
+ * capacities size
  * the workspace: (tile, view) pairs, records (one per kept event) and
  * aggregated cells (before compaction into the output); each pair also holds
  * one run place per bucket of 4096 cells.  descriptor_capacity is ignored
@@ -243,7 +246,7 @@ typedef struct {
     int32_t tile_events;
     int32_t emit_blocks;
     int32_t agg_blocks;
-    int32_t reserved;
+    int32_t launch;
     int64_t pair_capacity;
     int64_t record_capacity;
     int64_t descriptor_capacity;

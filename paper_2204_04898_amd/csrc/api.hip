@@ -48,7 +48,7 @@ constexpr int64_t kMaxEvents = (int64_t(1) << 31) - 1;
 
 __global__ void k_set_status(int32_t* status, int32_t code) { *status = code; }
 struct BatchedTune {
-    int tile, emit_blocks, agg_blocks;
+    int tile, emit_blocks, agg_blocks, launch;
     int64_t pair_cap, rec_cap, cell_cap;
 };
 
@@ -63,6 +63,11 @@ int resolve_tuning(const pm4g_batched_tuning* t, int64_t n, int32_t V, BatchedTu
         set_err("negative or oversized tuning field");
         return PM4G_E_INVALID;
     }
+    if (t && t->launch != 0 && t->launch != 1) {
+        set_err("launch must be 0 (one persistent launch) or 1 (one launch per phase)");
+        return PM4G_E_INVALID;
+    }
+    r->launch = t ? t->launch : 0;
     r->tile = (t && t->tile_events) ? t->tile_events : 4096;
     r->emit_blocks = (t && t->emit_blocks) ? t->emit_blocks : 2048;
     r->agg_blocks = (t && t->agg_blocks) ? t->agg_blocks : 512;
@@ -748,9 +753,13 @@ int pm4g_dfg_batched(const pm4g_prepared* log, const pm4g_view* views, const uin
     const BatchedOutDev o{out->edge_off, out->src, out->dst, out->count, out->dt_sum, out->dt_min,
                           out->dt_max, out->dt_mean, out->start_count, out->end_count, out->act_count,
                           out->n_events, out->n_cases, out->cap_edges, out->required, out->status};
-    PM4G_HIP(launch_views_plan(log, views, n_views, w, o, s));
-    PM4G_HIP(launch_views_count(log, views, act_masks, w, t.emit_blocks, s));
-    PM4G_HIP(launch_views_reduce(log, views, act_masks, n_views, w, o, t.emit_blocks, t.agg_blocks, s));
+    if (t.launch == 0) {
+        PM4G_HIP(launch_views_fused(log, views, act_masks, n_views, w, o, s));
+    } else {
+        PM4G_HIP(launch_views_plan(log, views, n_views, w, o, s));
+        PM4G_HIP(launch_views_count(log, views, act_masks, w, t.emit_blocks, s));
+        PM4G_HIP(launch_views_reduce(log, views, act_masks, n_views, w, o, t.emit_blocks, t.agg_blocks, s));
+    }
     return PM4G_OK;
 }
 

@@ -211,6 +211,7 @@ hipError_t launch_variants(const int32_t* act_s, const int64_t* case_off, const 
                            VarOutDev out, uint32_t debug_hash_bits, hipStream_t s);
 
 // ---- batched views (views.hip) ----
+constexpr int kViewMaxBlocks = 1024;   // blocks of the persistent launch, at most
 struct ViewWs {
     int32_t tile;
     int32_t n_buckets;
@@ -225,6 +226,8 @@ struct ViewWs {
     int64_t* scal;          // cursors and totals
     uint32_t* part32;
     int64_t* part64;
+    int64_t* part64b;       // a second scan's partial sums (the persistent launch scans two at once)
+    uint64_t* bar;          // [kViewMaxBlocks + 1] grid barrier words of the persistent launch
     uint16_t* rec_cell;     // [rec_cap] records: cell within its bucket (logs with a case of
     uint64_t* rec_gap;      //   2^52 time units or more), gap; else cell << 52 | gap in rec_gap
     uint4* pair_carry;      // [pair_cap] per (tile, view) pair: the walk's initial carry and
@@ -312,6 +315,10 @@ hipError_t launch_views_write(const pm4g_prepared* p, const pm4g_view* views, co
                               ViewWs w, int grid, hipStream_t s);
 hipError_t launch_views_reduce(const pm4g_prepared* p, const pm4g_view* views, const uint64_t* masks, int32_t V,
                                ViewWs w, BatchedOutDev out, int emit_grid, int agg_grid, hipStream_t s);
+// The whole call as one persistent cooperative launch (the same phases, grid
+// barriers in between).
+hipError_t launch_views_fused(const pm4g_prepared* p, const pm4g_view* views, const uint64_t* masks, int32_t V,
+                              ViewWs w, BatchedOutDev out, hipStream_t s);
 
 
 // ---- eventually-follows graph and temporal profile (efg.hip) ----

@@ -14,7 +14,8 @@ const char* kNames[P_COUNT] = {
     "variant_hash", "variant_sort", "variant_group", "variant_order", "variant_emit",
     "view_plan",    "view_emit",  "view_place",  "view_agg",      "view_out",
     "view_filter",  "dfg_count",  "view_write", "cases",         "case_filter",
-    "df_filter",    "efg",        "sample",        "csv",          "parquet"};
+    "df_filter",    "efg",        "sample",        "csv",          "parquet",
+    "view_fused"};
 
 struct Rec {
     int id;

@@ -38,6 +38,7 @@ enum ProfId {
     P_SAMPLE,
     P_CSV,
     P_PARQUET,
+    P_VIEW_FUSED,
     P_COUNT
 };
 

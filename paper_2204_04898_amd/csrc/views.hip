@@ -37,6 +37,9 @@
 //                    and the row / column sums
 #include <math.h>
 
+#include <atomic>
+#include <random>
+
 #include "common.hpp"
 #include "devsort.hpp"
 #include "internal.hpp"
@@ -52,7 +55,16 @@ constexpr int kVW = kVB / kWave;
 constexpr int kMaxBuckets = 264;          // >= ceil(1024 * 1025 / 4096) = 257
 constexpr int kMaskWords = PM4G_BATCHED_MAX_ACTIVITIES / 64;
 constexpr int kAB2 = 1024;                // threads per aggregation block
+constexpr int kFT = 1024;                 // threads per block of the persistent launch
 constexpr uint64_t kRecGapLimit = 1ull << 52;   // gaps below it share a u64 with the cell
+
+// A phase's view of the grid: block bid of nblk.  A phase launched as a
+// kernel of its own takes blockIdx / gridDim; the single persistent launch
+// runs every phase on its own grid, with grid barriers in between.
+struct Grid {
+    int64_t bid, nblk;
+};
+__device__ __forceinline__ Grid hw_grid() { return Grid{(int64_t)blockIdx.x, (int64_t)gridDim.x}; }
 
 
 // Value of lane l (l the same in every lane: read into a scalar register, no
@@ -92,6 +104,8 @@ ViewWs view_ws_layout(Bump& b, int64_t n, int32_t A, int32_t V, int32_t tile, in
     w.scal = b.take<int64_t>(16);
     w.part32 = b.take<uint32_t>(dev::kScanGrid);
     w.part64 = b.take<int64_t>(dev::kScanGrid);
+    w.part64b = b.take<int64_t>(dev::kScanGrid);
+    w.bar = b.take<uint64_t>(kViewMaxBlocks + 1);
     w.rec_cell = b.take<uint16_t>(rc);
     w.rec_gap = b.take<uint64_t>(rc);
     w.pair_carry = b.take<uint4>((size_t)(pair_cap > 0 ? pair_cap : 1));
@@ -137,10 +151,10 @@ namespace {
 // cell within its bucket (12 bits) << 52 | gap.  Otherwise the cell goes to
 // rec_cell and the full gap to rec_gap.
 
-__global__ void k_view_init(ViewWs w, int32_t V, int32_t A, const int32_t* status_in,
-                            BatchedOutDev out) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void ph_init(Grid gd, ViewWs w, int32_t V, int32_t A, const int32_t* status_in,
+                                        BatchedOutDev out) {
+    const int64_t stride = (int64_t)gd.nblk * blockDim.x;
+    const int64_t i0 = (int64_t)gd.bid * blockDim.x + threadIdx.x;
     for (int64_t i = i0; i < w.n_tiles + 2; i += stride) {
         w.tcount[i] = 0;
         w.tcursor[i] = 0;
@@ -159,18 +173,27 @@ __global__ void k_view_init(ViewWs w, int32_t V, int32_t A, const int32_t* statu
     }
 }
 
+__global__ void k_view_init(ViewWs w, int32_t V, int32_t A, const int32_t* status_in, BatchedOutDev out) {
+    ph_init(hw_grid(), w, V, A, status_in, out);
+}
+
 // Sets scal[10] when a case of the log lasts 2^52 time units or more (its
 // last timestamp minus its first; the prepared log is sorted by (case, ts)).
-__global__ void k_view_span(const int64_t* __restrict__ case_off, const int64_t* __restrict__ ts_s,
-                            const int64_t* n_cases, ViewWs w) {
+__device__ __forceinline__ void ph_span(Grid gd, const int64_t* __restrict__ case_off,
+                                        const int64_t* __restrict__ ts_s, const int64_t* n_cases, ViewWs w) {
     const int64_t C = *n_cases;
     bool wide = false;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < C;
-         c += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t c = (int64_t)gd.bid * blockDim.x + threadIdx.x; c < C;
+         c += (int64_t)gd.nblk * blockDim.x) {
         const uint64_t d = (uint64_t)ts_s[case_off[c + 1] - 1] - (uint64_t)ts_s[case_off[c]];
         wide |= d >= kRecGapLimit;
     }
     if (__ballot(wide) != 0 && lane() == 0) atomicOr(reinterpret_cast<unsigned long long*>(&w.scal[10]), 1ull);
+}
+
+__global__ void k_view_span(const int64_t* __restrict__ case_off, const int64_t* __restrict__ ts_s,
+                            const int64_t* n_cases, ViewWs w) {
+    ph_span(hw_grid(), case_off, ts_s, n_cases, w);
 }
 
 __device__ int64_t lower_bound_i32(const int32_t* a, int64_t n, int32_t x) {
@@ -184,11 +207,11 @@ __device__ int64_t lower_bound_i32(const int32_t* a, int64_t n, int32_t x) {
 }
 
 // Event slice of every view (whole cases) and the per-tile overlap differences.
-__global__ void k_view_slice(const pm4g_view* views, int32_t V, const int64_t* case_off,
-                             const int32_t* case_code, const int64_t* n_cases, ViewWs w) {
+__device__ __forceinline__ void ph_slice(Grid gd, const pm4g_view* views, int32_t V, const int64_t* case_off,
+                                         const int32_t* case_code, const int64_t* n_cases, ViewWs w) {
     const int64_t C = *n_cases;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V;
-         v += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t v = (int64_t)gd.bid * blockDim.x + threadIdx.x; v < V;
+         v += (int64_t)gd.nblk * blockDim.x) {
         const pm4g_view vw = views[v];
         int64_t p0 = 0, p1 = 0;
         if (vw.case_lo < vw.case_hi && vw.t_lo <= vw.t_hi) {
@@ -204,9 +227,15 @@ __global__ void k_view_slice(const pm4g_view* views, int32_t V, const int64_t* c
     }
 }
 
+__global__ void k_view_slice(const pm4g_view* views, int32_t V, const int64_t* case_off,
+                             const int32_t* case_code, const int64_t* n_cases, ViewWs w) {
+    ph_slice(hw_grid(), views, V, case_off, case_code, n_cases, w);
+}
+
 // tcount holds differences; one block turns them into counts and offsets.
-__global__ __launch_bounds__(1024) void k_view_tile_scan(ViewWs w) {
+__device__ __forceinline__ void ph_tile_scan(Grid gd, ViewWs w) {
     __shared__ uint32_t tmp[1024 / kWave + 1];
+    if (gd.bid != 0) return;   // one block (of 1024 threads)
     uint32_t run_cnt = 0, run_off = 0;
     const int64_t nt = w.n_tiles;
     for (int64_t t0 = 0; t0 < nt; t0 += 1024) {
@@ -230,11 +259,13 @@ __global__ __launch_bounds__(1024) void k_view_tile_scan(ViewWs w) {
     }
 }
 
+__global__ __launch_bounds__(1024) void k_view_tile_scan(ViewWs w) { ph_tile_scan(hw_grid(), w); }
+
 // One wave per view, its lanes over the view's tiles (a view can span
 // thousands of tiles; one thread per view made that a serial atomic chain).
-__global__ void k_view_fill(int32_t V, ViewWs w) {
-    const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+__device__ __forceinline__ void ph_fill(Grid gd, int32_t V, ViewWs w) {
+    const int64_t wv = ((int64_t)gd.bid * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nw = (int64_t)gd.nblk * blockDim.x / kWave;
     for (int64_t v = wv; v < V; v += nw) {
         const int64_t p0 = w.p0[v], p1 = w.p1[v];
         if (p1 <= p0) continue;
@@ -245,6 +276,8 @@ __global__ void k_view_fill(int32_t V, ViewWs w) {
         }
     }
 }
+
+__global__ void k_view_fill(int32_t V, ViewWs w) { ph_fill(hw_grid(), V, w); }
 
 __device__ __forceinline__ bool kept(int32_t a, int64_t t, int64_t tlo, int64_t thi, const uint64_t* mask) {
     return t >= tlo && t <= thi && ((mask[a >> 6] >> (a & 63)) & 1ull);
@@ -437,6 +470,18 @@ __device__ __forceinline__ void walk(const int32_t* __restrict__ s_case, const i
     }
 }
 
+// LDS of a walk block (NW waves over a TILE-event tile).
+template <int TILE, int NW>
+struct WalkSmem {
+    int32_t s_case[TILE];
+    int16_t s_act[TILE];
+    int64_t s_ts[TILE];
+    uint64_t s_mask[NW][kMaskWords];
+    uint32_t s_cur[NW][kMaxBuckets];
+    uint16_t s_list[NW][kListAlloc];
+    uint32_t s_next;
+};
+
 // Tile order of the walks: chunks of kXcdChunk consecutive tiles are dealt
 // round-robin to the 8 XCDs (block b runs on XCD b % 8) and an XCD's blocks
 // stride over its chunks' tiles, so neighbouring tiles, whose runs of records
@@ -444,8 +489,8 @@ __device__ __forceinline__ void walk(const int32_t* __restrict__ s_case, const i
 // while the chunks keep the XCDs' loads even along the log.  The block's i-th
 // tile, or -1 past the end (the order is increasing in i).
 constexpr int64_t kXcdChunk = 64;
-__device__ __forceinline__ int64_t walk_tile(int64_t i, int64_t n_tiles) {
-    const int64_t G = gridDim.x, b = blockIdx.x;
+__device__ __forceinline__ int64_t walk_tile(Grid gd, int64_t i, int64_t n_tiles) {
+    const int64_t G = gd.nblk, b = gd.bid;
     int64_t t;
     if (G % 8 != 0) {
         t = b + i * G;
@@ -468,27 +513,26 @@ __device__ __forceinline__ uint32_t next_pair(uint32_t* s_next) {
 // place in the (view, bucket) segment with one atomic on the segment's
 // counter; the walk's initial carry and whether the pair keeps an event are
 // kept for the write walk (pair_carry: ts, case, act | valid << 30 | kept << 31).
-template <int TILE>
-__global__ __launch_bounds__(kVB) void k_view_count(const int32_t* __restrict__ case_s,
-                                                    const int32_t* __restrict__ act_s,
-                                                    const int64_t* __restrict__ ts_s, int64_t n, int32_t A,
-                                                    const pm4g_view* __restrict__ views,
-                                                    const uint64_t* __restrict__ masks, ViewWs w) {
-    __shared__ int32_t s_case[TILE];
-    __shared__ int16_t s_act[TILE];
-    __shared__ int64_t s_ts[TILE];
-    __shared__ uint64_t s_mask[kVW][kMaskWords];
-    __shared__ uint32_t s_cur[kVW][kMaxBuckets];
-    __shared__ uint16_t s_list[kVW][kListAlloc];
-    __shared__ uint32_t s_next;
+template <int TILE, int NW>
+__device__ __forceinline__ void ph_count(Grid gd, const int32_t* __restrict__ case_s,
+                                        const int32_t* __restrict__ act_s,
+                                        const int64_t* __restrict__ ts_s, int64_t n, int32_t A,
+                                        const pm4g_view* __restrict__ views,
+                                        const uint64_t* __restrict__ masks, ViewWs w,
+                                        WalkSmem<TILE, NW>& S) {
+    int32_t* s_case = S.s_case;
+    int16_t* s_act = S.s_act;
+    int64_t* s_ts = S.s_ts;
+    constexpr int kVB = NW * kWave;
 
     const int wv = threadIdx.x / kWave;
     const int NB = w.n_buckets;
     const int MW = (A + 63) / 64;
-    uint64_t* mask = s_mask[wv];
-    uint32_t* cur = s_cur[wv];
+    uint64_t* mask = S.s_mask[wv];
+    uint32_t* cur = S.s_cur[wv];
     if (w.scal[7] > w.pair_cap) return;   // the tile lists are incomplete: the gate stops the call
-    for (int64_t it = 0, tile; (tile = walk_tile(it, w.n_tiles)) >= 0; ++it) {
+    for (int64_t it = 0, tile; (tile = walk_tile(gd, it, w.n_tiles)) >= 0; ++it) {
+        if (w.tcount[tile] == 0) continue;   // no view overlaps the tile (block-uniform)
         const int64_t T0 = tile * TILE;
         const int64_t T1 = (T0 + TILE) < n ? (T0 + TILE) : n;
         for (int64_t i = T0 + threadIdx.x; i < T1; i += kVB) {
@@ -496,11 +540,11 @@ __global__ __launch_bounds__(kVB) void k_view_count(const int32_t* __restrict__ 
             s_act[i - T0] = (int16_t)act_s[i];
             s_ts[i - T0] = ts_s[i];
         }
-        if (threadIdx.x == 0) s_next = kVW;
+        if (threadIdx.x == 0) S.s_next = NW;
         __syncthreads();
         const uint32_t cnt = w.tcount[tile];
         const int64_t off = w.toff[tile];
-        for (uint32_t j = wv; j < cnt; j = next_pair(&s_next)) {
+        for (uint32_t j = wv; j < cnt; j = next_pair(&S.s_next)) {
             const uint32_t v = w.list[off + j];
             const pm4g_view vw = views[v];
             const int64_t p0 = w.p0[v], p1 = w.p1[v];
@@ -509,7 +553,7 @@ __global__ __launch_bounds__(kVB) void k_view_count(const int32_t* __restrict__ 
             const int64_t e1 = T1 < p1 ? T1 : p1;
             const WalkState st = walk_init(case_s, act_s, ts_s, e0, p0, vw.t_lo, vw.t_hi, mask);
             for (int q = lane(); q < NB; q += kWave) cur[q] = 0;
-            walk<false>(s_case, s_act, s_ts, T0, e0, e1, st, A, vw.t_lo, vw.t_hi, mask, s_list[wv], cur,
+            walk<false>(s_case, s_act, s_ts, T0, e0, e1, st, A, vw.t_lo, vw.t_hi, mask, S.s_list[wv], cur,
                         w.rec_cell, w.rec_gap, false);
             uint32_t* rel = w.pair_rel + (size_t)(off + j) * (size_t)NB;
             uint64_t any = 0;
@@ -530,32 +574,41 @@ __global__ __launch_bounds__(kVB) void k_view_count(const int32_t* __restrict__ 
     }
 }
 
+template <int TILE>
+__global__ __launch_bounds__(kVB) void k_view_count(const int32_t* __restrict__ case_s,
+                                        const int32_t* __restrict__ act_s,
+                                        const int64_t* __restrict__ ts_s, int64_t n, int32_t A,
+                                        const pm4g_view* __restrict__ views,
+                                        const uint64_t* __restrict__ masks, ViewWs w) {
+    __shared__ WalkSmem<TILE, kVW> S;
+    ph_count<TILE, kVW>(hw_grid(), case_s, act_s, ts_s, n, A, views, masks, w, S);
+}
+
 // Write walk: each (tile, view) pair's buckets start at their runs' places in
 // the segment-contiguous record layout; the walk starts from the carry the
 // count walk found.
-template <int TILE>
-__global__ __launch_bounds__(kVB) void k_view_write(const int32_t* __restrict__ case_s,
-                                                    const int32_t* __restrict__ act_s,
-                                                    const int64_t* __restrict__ ts_s, int64_t n, int32_t A,
-                                                    const pm4g_view* __restrict__ views,
-                                                    const uint64_t* __restrict__ masks, ViewWs w) {
-    __shared__ int32_t s_case[TILE];
-    __shared__ int16_t s_act[TILE];
-    __shared__ int64_t s_ts[TILE];
-    __shared__ uint64_t s_mask[kVW][kMaskWords];
-    __shared__ uint32_t s_cur[kVW][kMaxBuckets];
-    __shared__ uint16_t s_list[kVW][kListAlloc];
-    __shared__ uint32_t s_next;
+template <int TILE, int NW>
+__device__ __forceinline__ void ph_write(Grid gd, const int32_t* __restrict__ case_s,
+                                        const int32_t* __restrict__ act_s,
+                                        const int64_t* __restrict__ ts_s, int64_t n, int32_t A,
+                                        const pm4g_view* __restrict__ views,
+                                        const uint64_t* __restrict__ masks, ViewWs w,
+                                        WalkSmem<TILE, NW>& S) {
+    int32_t* s_case = S.s_case;
+    int16_t* s_act = S.s_act;
+    int64_t* s_ts = S.s_ts;
+    constexpr int kVB = NW * kWave;
     constexpr int kQ = (kMaxBuckets + kWave - 1) / kWave;   // buckets per lane
 
     const int wv = threadIdx.x / kWave;
     const int NB = w.n_buckets;
     const int MW = (A + 63) / 64;
     const bool wide = w.scal[10] != 0;
-    uint64_t* mask = s_mask[wv];
-    uint32_t* cur = s_cur[wv];
+    uint64_t* mask = S.s_mask[wv];
+    uint32_t* cur = S.s_cur[wv];
     if (w.scal[12] != 0) return;   // a capacity is short: no record is written
-    for (int64_t it = 0, tile; (tile = walk_tile(it, w.n_tiles)) >= 0; ++it) {
+    for (int64_t it = 0, tile; (tile = walk_tile(gd, it, w.n_tiles)) >= 0; ++it) {
+        if (w.tcount[tile] == 0) continue;   // no view overlaps the tile (block-uniform)
         const int64_t T0 = tile * TILE;
         const int64_t T1 = (T0 + TILE) < n ? (T0 + TILE) : n;
         for (int64_t i = T0 + threadIdx.x; i < T1; i += kVB) {
@@ -563,11 +616,11 @@ __global__ __launch_bounds__(kVB) void k_view_write(const int32_t* __restrict__ 
             s_act[i - T0] = (int16_t)act_s[i];
             s_ts[i - T0] = ts_s[i];
         }
-        if (threadIdx.x == 0) s_next = kVW;
+        if (threadIdx.x == 0) S.s_next = NW;
         __syncthreads();
         const uint32_t cnt = w.tcount[tile];
         const int64_t off = w.toff[tile];
-        for (uint32_t j = wv; j < cnt; j = next_pair(&s_next)) {
+        for (uint32_t j = wv; j < cnt; j = next_pair(&S.s_next)) {
             const uint4 cy = w.pair_carry[off + j];
             if (!(cy.w >> 31)) continue;   // no kept event
             const uint32_t v = w.list[off + j];
@@ -597,18 +650,28 @@ __global__ __launch_bounds__(kVB) void k_view_write(const int32_t* __restrict__ 
             st.cr_valid = (cy.w >> 30) & 1u;
             st.cr_a = (int32_t)(cy.w & 0x3FFFFFFFu);
             st.cr_t = (int64_t)(((uint64_t)cy.y << 32) | cy.x);
-            walk<true>(s_case, s_act, s_ts, T0, e0, e1, st, A, vw.t_lo, vw.t_hi, mask, s_list[wv], cur,
+            walk<true>(s_case, s_act, s_ts, T0, e0, e1, st, A, vw.t_lo, vw.t_hi, mask, S.s_list[wv], cur,
                        w.rec_cell, w.rec_gap, wide);
         }
         __syncthreads();
     }
 }
 
+template <int TILE>
+__global__ __launch_bounds__(kVB) void k_view_write(const int32_t* __restrict__ case_s,
+                                        const int32_t* __restrict__ act_s,
+                                        const int64_t* __restrict__ ts_s, int64_t n, int32_t A,
+                                        const pm4g_view* __restrict__ views,
+                                        const uint64_t* __restrict__ masks, ViewWs w) {
+    __shared__ WalkSmem<TILE, kVW> S;
+    ph_write<TILE, kVW>(hw_grid(), case_s, act_s, ts_s, n, A, views, masks, w, S);
+}
+
 // The gate after the count walk and the segment scans: every capacity the
 // later kernels write into is known now; if one is short (or the records
 // exceed 32-bit places) the call stops here, reported by k_view_finish.
-__global__ void k_view_gate(ViewWs w) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+__device__ __forceinline__ void ph_gate(Grid gd, ViewWs w) {
+    if (threadIdx.x == 0 && gd.bid == 0) {
         int64_t g = 0;
         if (w.scal[7] > w.pair_cap || w.scal[9] > w.rec_cap) g = PM4G_E_CAPACITY;
         if (w.scal[7] <= w.pair_cap && w.scal[9] > (int64_t)0xFFFFFFFF) g = PM4G_E_INVALID;
@@ -616,29 +679,54 @@ __global__ void k_view_gate(ViewWs w) {
     }
 }
 
-__global__ void k_view_vb_flags(ViewWs w, int32_t V) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < w.n_vb;
-         i += (int64_t)gridDim.x * blockDim.x)
+__global__ void k_view_gate(ViewWs w) { ph_gate(hw_grid(), w); }
+
+__device__ __forceinline__ void ph_vb_flags(Grid gd, ViewWs w, int32_t V) {
+    for (int64_t i = (int64_t)gd.bid * blockDim.x + threadIdx.x; i < w.n_vb;
+         i += (int64_t)gd.nblk * blockDim.x)
         w.vb_flag[i] = w.vb_cnt[i] != 0 ? 1u : 0u;
-    if (blockIdx.x == 0 && threadIdx.x == 0) w.scal[6] = V;
+    if (gd.bid == 0 && threadIdx.x == 0) w.scal[6] = V;
 }
+
+__global__ void k_view_vb_flags(ViewWs w, int32_t V) { ph_vb_flags(hw_grid(), w, V); }
 
 // Segments: the non-empty (view, bucket) pairs in increasing order, each with
 // its first record; the records' total closes the list.
-__global__ void k_view_segs(ViewWs w) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < w.n_vb;
-         i += (int64_t)gridDim.x * blockDim.x) {
+__device__ __forceinline__ void ph_segs(Grid gd, ViewWs w) {
+    for (int64_t i = (int64_t)gd.bid * blockDim.x + threadIdx.x; i < w.n_vb;
+         i += (int64_t)gd.nblk * blockDim.x) {
         if (!w.vb_flag[i]) continue;
         const uint32_t g = w.vb_seg[i];
         w.seg_key[g] = (uint32_t)i;
         w.seg_rec[g] = w.vb_base[i];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (gd.bid == 0 && threadIdx.x == 0) {
         const int64_t S = (int64_t)((uint32_t*)&w.scal[8])[0];
         w.seg_rec[S] = w.scal[9];
         w.scal[2] = S;
     }
 }
+
+__global__ void k_view_segs(ViewWs w) { ph_segs(hw_grid(), w); }
+
+// LDS of an aggregation block: one 4096-cell table.
+struct AggSmem {
+    uint32_t scount[kCellsPerTable];
+    uint64_t ssum[kCellsPerTable];
+    alignas(16) int64_t smm[2 * kCellsPerTable];   // min, max of each cell side by side
+    uint32_t tmp[kAB2 / kWave + 1];
+    int64_t s_base;
+};
+
+// LDS of an activity-count block.
+template <int BLOCK>
+struct ActsSmem {
+    uint32_t rows[PM4G_BATCHED_MAX_ACTIVITIES];
+    uint32_t cols[PM4G_BATCHED_MAX_ACTIVITIES];
+    int64_t s_src[kMaxBuckets];
+    uint32_t s_m[kMaxBuckets];
+    int64_t red[2][BLOCK / kWave];
+};
 
 // smm: each cell's min and max side by side, read with one 16-byte load (a
 // stale pair only makes an atomic run that was not needed: min only falls
@@ -682,12 +770,12 @@ __device__ __forceinline__ void agg_records(const ViewWs& w, int64_t r, int64_t 
 // One block per (view, bucket) segment: its records are one contiguous range,
 // streamed into a 4096-cell LDS table; after compaction only the touched
 // cells are reset, so the table is cleared once per block.
-__global__ __launch_bounds__(kAB2) void k_view_agg(int32_t A, ViewWs w, BatchedOutDev out) {
-    __shared__ uint32_t scount[kCellsPerTable];
-    __shared__ uint64_t ssum[kCellsPerTable];
-    __shared__ __align__(16) int64_t smm[2 * kCellsPerTable];
-    __shared__ uint32_t tmp[kAB2 / kWave + 1];
-    __shared__ int64_t s_base;
+__device__ __forceinline__ void ph_agg(Grid gd, int32_t A, ViewWs w, BatchedOutDev out, AggSmem& L) {
+    uint32_t* scount = L.scount;
+    uint64_t* ssum = L.ssum;
+    int64_t* smm = L.smm;
+    uint32_t* tmp = L.tmp;
+    int64_t& s_base = L.s_base;
     if (w.scal[12] != 0) return;
     const int64_t S = w.scal[2];
     const int64_t AA = (int64_t)A * A;
@@ -700,7 +788,7 @@ __global__ __launch_bounds__(kAB2) void k_view_agg(int32_t A, ViewWs w, BatchedO
         smm[2 * c + 1] = INT64_MIN;
     }
     __syncthreads();
-    for (int64_t g = blockIdx.x; g < S; g += gridDim.x) {
+    for (int64_t g = gd.bid; g < S; g += gd.nblk) {
         const uint32_t key = w.seg_key[g];
         const uint32_t v = key / (uint32_t)NB;
         const uint32_t bk = key % (uint32_t)NB;
@@ -754,12 +842,17 @@ __global__ __launch_bounds__(kAB2) void k_view_agg(int32_t A, ViewWs w, BatchedO
     }
 }
 
-__global__ void k_view_copy(int32_t A, ViewWs w, BatchedOutDev out) {
+__global__ __launch_bounds__(kAB2) void k_view_agg(int32_t A, ViewWs w, BatchedOutDev out) {
+    __shared__ AggSmem S;
+    ph_agg(hw_grid(), A, w, out, S);
+}
+
+__device__ __forceinline__ void ph_copy(Grid gd, int32_t A, ViewWs w, BatchedOutDev out) {
     const int64_t S = w.scal[2];
     const bool fits = w.scal[12] == 0 && w.scal[4] <= out.cap_edges && w.scal[3] <= w.cell_cap;
     if (!fits) return;
-    const int wv = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int nw = gridDim.x * blockDim.x / kWave;
+    const int wv = (gd.bid * blockDim.x + threadIdx.x) / kWave;
+    const int nw = gd.nblk * blockDim.x / kWave;
     for (int64_t g = wv; g < S; g += nw) {
         const int64_t src = w.seg_tmp[g], dst = w.seg_out[g];
         const uint32_t m = w.seg_cells[g];
@@ -796,20 +889,22 @@ __global__ void k_view_copy(int32_t A, ViewWs w, BatchedOutDev out) {
     }
 }
 
+__global__ void k_view_copy(int32_t A, ViewWs w, BatchedOutDev out) { ph_copy(hw_grid(), A, w, out); }
+
 // Per view: its segments form a run of the sorted segment list; fold their
 // cells into row and column sums; derive activity and end counts.
-__global__ __launch_bounds__(256) void k_view_acts(int32_t V, int32_t A, ViewWs w,
-                                                   BatchedOutDev out) {
-    __shared__ uint32_t rows[PM4G_BATCHED_MAX_ACTIVITIES];   // at most the view's kept events (< 2^31)
-    __shared__ uint32_t cols[PM4G_BATCHED_MAX_ACTIVITIES];
-    __shared__ int64_t s_src[kMaxBuckets];
-    __shared__ uint32_t s_m[kMaxBuckets];
-    __shared__ int64_t red[2][256 / kWave];
+template <int BLOCK>
+__device__ __forceinline__ void ph_acts(Grid gd, int32_t V, int32_t A, ViewWs w, BatchedOutDev out,
+                                        ActsSmem<BLOCK>& L) {
+    uint32_t* rows = L.rows;   // at most the view's kept events (< 2^31)
+    uint32_t* cols = L.cols;
+    int64_t* s_src = L.s_src;
+    uint32_t* s_m = L.s_m;
     const int64_t S = w.scal[2];
     const uint32_t NB = (uint32_t)w.n_buckets;
     if (w.scal[12] != 0 || w.scal[3] > w.cell_cap) return;   // temporary cells were not all written
-    for (int64_t v = blockIdx.x; v < V; v += gridDim.x) {
-        for (int a = threadIdx.x; a < A; a += 256) rows[a] = cols[a] = 0;
+    for (int64_t v = gd.bid; v < V; v += gd.nblk) {
+        for (int a = threadIdx.x; a < A; a += BLOCK) rows[a] = cols[a] = 0;
         __syncthreads();
         // first segment of this view: lower bound of key v*NB over segment keys
         int64_t lo = 0, hi = S;
@@ -820,7 +915,7 @@ __global__ __launch_bounds__(256) void k_view_acts(int32_t V, int32_t A, ViewWs 
         }
         // the view's segments (at most NB): their places and cell counts to LDS
         int ns = 0;
-        for (int k0 = 0; k0 < (int)NB; k0 += 256) {
+        for (int k0 = 0; k0 < (int)NB; k0 += BLOCK) {
             const int k = k0 + threadIdx.x;
             const bool mine = k < (int)NB && lo + k < S && w.seg_key[lo + k] / NB == (uint32_t)v;
             if (mine) {
@@ -834,11 +929,11 @@ __global__ __launch_bounds__(256) void k_view_acts(int32_t V, int32_t A, ViewWs 
             const int64_t src = s_src[g];
             const uint32_t m = s_m[g];
             constexpr int kU = 2;
-            for (uint32_t r0 = 0; r0 < m; r0 += kU * 256) {
+            for (uint32_t r0 = 0; r0 < m; r0 += kU * BLOCK) {
                 uint32_t cell[kU], c[kU];
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
-                    const uint32_t r = r0 + u * 256 + threadIdx.x;
+                    const uint32_t r = r0 + u * BLOCK + threadIdx.x;
                     cell[u] = 0;
                     c[u] = 0;
                     if (r < m) {
@@ -857,7 +952,7 @@ __global__ __launch_bounds__(256) void k_view_acts(int32_t V, int32_t A, ViewWs 
         }
         __syncthreads();
         int64_t ne = 0, nc = 0;
-        for (int a = threadIdx.x; a < A; a += 256) {
+        for (int a = threadIdx.x; a < A; a += BLOCK) {
             const size_t at = (size_t)v * A + a;
             const int64_t st = out.start_count[at];
             const int64_t act = st + (int64_t)cols[a];
@@ -869,15 +964,15 @@ __global__ __launch_bounds__(256) void k_view_acts(int32_t V, int32_t A, ViewWs 
         ne = wave_sum(ne);
         nc = wave_sum(nc);
         if (lane() == 0) {
-            red[0][threadIdx.x / kWave] = ne;
-            red[1][threadIdx.x / kWave] = nc;
+            L.red[0][threadIdx.x / kWave] = ne;
+            L.red[1][threadIdx.x / kWave] = nc;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
             int64_t a = 0, b = 0;
-            for (int k = 0; k < 256 / kWave; ++k) {
-                a += red[0][k];
-                b += red[1][k];
+            for (int k = 0; k < BLOCK / kWave; ++k) {
+                a += L.red[0][k];
+                b += L.red[1][k];
             }
             out.n_events[v] = a;
             out.n_cases[v] = b;
@@ -886,8 +981,13 @@ __global__ __launch_bounds__(256) void k_view_acts(int32_t V, int32_t A, ViewWs 
     }
 }
 
-__global__ void k_view_finish(int32_t V, ViewWs w, BatchedOutDev out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+__global__ __launch_bounds__(256) void k_view_acts(int32_t V, int32_t A, ViewWs w, BatchedOutDev out) {
+    __shared__ ActsSmem<256> S;
+    ph_acts<256>(hw_grid(), V, A, w, out, S);
+}
+
+__device__ __forceinline__ void ph_finish(Grid gd, int32_t V, ViewWs w, BatchedOutDev out) {
+    if (threadIdx.x == 0 && gd.bid == 0) {
         const int64_t gate = w.scal[12];
         const bool pairs_short = w.scal[7] > w.pair_cap;   // then the count walk did not run
         out.edge_off[V] = gate ? 0 : w.scal[4];
@@ -901,7 +1001,231 @@ __global__ void k_view_finish(int32_t V, ViewWs w, BatchedOutDev out) {
     }
 }
 
+__global__ void k_view_finish(int32_t V, ViewWs w, BatchedOutDev out) { ph_finish(hw_grid(), V, w, out); }
+
+
+// ---- the single persistent launch ----
+
+// Exclusive scans over the persistent grid: per-block sums of contiguous
+// chunks, one block scans the sums (nblk <= 1024 = the block size), each block
+// applies its prefix.
+template <typename T>
+__device__ __forceinline__ void gscan_reduce(Grid gd, const uint32_t* in, int64_t n, T* partial) {
+    __shared__ T red[kFT / kWave];
+    const int64_t chunk = (n + gd.nblk - 1) / gd.nblk;
+    const int64_t b0 = gd.bid * chunk;
+    const int64_t b1 = (b0 + chunk) < n ? (b0 + chunk) : n;
+    T sum = 0;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += kFT) sum += in[i];
+    sum = wave_sum(sum);
+    if (lane() == 0) red[threadIdx.x / kWave] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T t = 0;
+        for (int k = 0; k < kFT / kWave; ++k) t += red[k];
+        partial[gd.bid] = t;
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ void gscan_top(Grid gd, T* partial, T* total) {
+    __shared__ T tmp[kFT / kWave + 1];
+    if (gd.bid != 0) return;
+    const T v = (int64_t)threadIdx.x < gd.nblk ? partial[threadIdx.x] : (T)0;
+    T tot;
+    const T ex = block_excl_sum<kFT>(v, tmp, &tot);
+    if ((int64_t)threadIdx.x < gd.nblk) partial[threadIdx.x] = ex;
+    if (threadIdx.x == 0 && total) *total = tot;
+}
+
+template <typename T>
+__device__ __forceinline__ void gscan_apply(Grid gd, const uint32_t* in, int64_t n, const T* partial, T* out) {
+    __shared__ T tmp[kFT / kWave + 1];
+    const int64_t chunk = (n + gd.nblk - 1) / gd.nblk;
+    const int64_t b0 = gd.bid * chunk;
+    const int64_t b1 = (b0 + chunk) < n ? (b0 + chunk) : n;
+    T run = partial[gd.bid];
+    for (int64_t c0 = b0; c0 < b1; c0 += kFT) {   // block-uniform
+        const int64_t i = c0 + threadIdx.x;
+        const T v = i < b1 ? (T)in[i] : (T)0;
+        T tot;
+        const T ex = block_excl_sum<kFT>(v, tmp, &tot);
+        if (i < b1) out[i] = run + ex;
+        run += tot;
+    }
+}
+
+// Grid barrier of the persistent launch (every block resident: a cooperative
+// launch).  Block b announces its arrival at barrier k by writing the tag
+// (call epoch << 6 | k) into bar[b]; block 0 waits until every block has
+// announced it and publishes the tag in bar[kViewMaxBlocks]; the others wait
+// for that.  Tags are unique per call, so words left in the workspace by
+// earlier calls never match.  The release fence before the arrival and the
+// acquire fence after the wait make each phase's writes visible to the next
+// phase on every XCD.  A wait is bounded: past kBarrierPolls polls (seconds,
+// far beyond any phase) the call's status becomes PM4G_E_DEVICE and the
+// block goes on, so a broken schedule ends the call instead of hanging it.
+constexpr int64_t kBarrierPolls = int64_t(1) << 22;
+
+__device__ void grid_barrier(Grid gd, uint64_t* bar, uint64_t tag, int32_t* status) {
+    __syncthreads();
+    if (threadIdx.x < kWave) {
+        __threadfence();
+        if (lane() == 0) __hip_atomic_store(&bar[gd.bid], tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        bool late = false;
+        if (gd.bid == 0) {
+            for (int64_t b0 = 0; b0 < gd.nblk; b0 += kWave) {
+                const int64_t b = b0 + lane();
+                int64_t polls = 0;
+                for (;;) {
+                    const bool here = b >= gd.nblk ||
+                                      __hip_atomic_load(&bar[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == tag;
+                    if (__ballot(!here) == 0) break;
+                    if (++polls > kBarrierPolls) {
+                        late = true;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            __threadfence();
+            if (lane() == 0) __hip_atomic_store(&bar[kViewMaxBlocks], tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (lane() == 0) {
+            int64_t polls = 0;
+            while (__hip_atomic_load(&bar[kViewMaxBlocks], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != tag) {
+                if (++polls > kBarrierPolls) {
+                    late = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        if (late && lane() == 0) set_status(status, PM4G_E_DEVICE);
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+struct FusedArgs {
+    const int32_t* case_s;
+    const int32_t* act_s;
+    const int64_t* ts_s;
+    const int64_t* case_off;
+    const int32_t* case_code;
+    const int64_t* n_cases;
+    const int32_t* status_in;
+    const pm4g_view* views;
+    const uint64_t* masks;
+    int64_t n;
+    int32_t A, V;
+    uint64_t epoch;
+    ViewWs w;
+    BatchedOutDev out;
+};
+
+template <int TILE>
+union FusedSmem {
+    WalkSmem<TILE, kFT / kWave> walk;
+    AggSmem agg;
+    ActsSmem<kFT> acts;
+};
+
+// The whole batched call in one launch: the phases of the per-phase kernels,
+// in the same order, separated by grid barriers.
+template <int TILE>
+__global__ __launch_bounds__(kFT) void k_view_fused(FusedArgs a) {
+    __shared__ FusedSmem<TILE> sm;
+    const Grid gd = hw_grid();
+    ViewWs& w = a.w;
+    const int32_t V = a.V, A = a.A;
+    uint64_t k = a.epoch << 6;
+    int32_t* st = a.out.status;
+    ph_init(gd, w, V, A, a.status_in, a.out);
+    grid_barrier(gd, w.bar, ++k, st);
+    ph_span(gd, a.case_off, a.ts_s, a.n_cases, w);
+    ph_slice(gd, a.views, V, a.case_off, a.case_code, a.n_cases, w);
+    grid_barrier(gd, w.bar, ++k, st);
+    ph_tile_scan(gd, w);
+    grid_barrier(gd, w.bar, ++k, st);
+    ph_fill(gd, V, w);
+    grid_barrier(gd, w.bar, ++k, st);
+    ph_count<TILE, kFT / kWave>(gd, a.case_s, a.act_s, a.ts_s, a.n, A, a.views, a.masks, w, sm.walk);
+    grid_barrier(gd, w.bar, ++k, st);
+    ph_vb_flags(gd, w, V);
+    grid_barrier(gd, w.bar, ++k, st);
+    {
+        const int64_t nvb = w.scal[11];
+        gscan_reduce<int64_t>(gd, w.vb_cnt, nvb, w.part64);
+        gscan_reduce<uint32_t>(gd, w.vb_flag, nvb, w.part32);
+        grid_barrier(gd, w.bar, ++k, st);
+        gscan_top<int64_t>(gd, w.part64, &w.scal[9]);
+        gscan_top<uint32_t>(gd, w.part32, reinterpret_cast<uint32_t*>(&w.scal[8]));
+        grid_barrier(gd, w.bar, ++k, st);
+        gscan_apply<int64_t>(gd, w.vb_cnt, nvb, w.part64, w.vb_base);
+        gscan_apply<uint32_t>(gd, w.vb_flag, nvb, w.part32, w.vb_seg);
+        grid_barrier(gd, w.bar, ++k, st);
+    }
+    ph_gate(gd, w);
+    ph_segs(gd, w);
+    grid_barrier(gd, w.bar, ++k, st);
+    ph_write<TILE, kFT / kWave>(gd, a.case_s, a.act_s, a.ts_s, a.n, A, a.views, a.masks, w, sm.walk);
+    grid_barrier(gd, w.bar, ++k, st);
+    ph_agg(gd, A, w, a.out, sm.agg);
+    grid_barrier(gd, w.bar, ++k, st);
+    {
+        const int64_t S = w.scal[2];
+        gscan_reduce<int64_t>(gd, w.seg_cells, S, w.part64);
+        gscan_reduce<int64_t>(gd, w.view_cells, V, w.part64b);
+        grid_barrier(gd, w.bar, ++k, st);
+        gscan_top<int64_t>(gd, w.part64, &w.scal[4]);
+        gscan_top<int64_t>(gd, w.part64b, nullptr);
+        grid_barrier(gd, w.bar, ++k, st);
+        gscan_apply<int64_t>(gd, w.seg_cells, S, w.part64, w.seg_out);
+        gscan_apply<int64_t>(gd, w.view_cells, V, w.part64b, a.out.edge_off);
+        grid_barrier(gd, w.bar, ++k, st);
+    }
+    ph_copy(gd, A, w, a.out);
+    ph_acts<kFT>(gd, V, A, w, a.out, sm.acts);
+    grid_barrier(gd, w.bar, ++k, st);
+    ph_finish(gd, V, w, a.out);
+}
+
 }  // namespace
+
+// Grid of the persistent launch on the current device: every block resident
+// (blocks per CU from the occupancy query, times the CUs), at most
+// kViewMaxBlocks.
+static int fused_grid(int tile) {
+    static int cache[64][2] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    int& g = cache[dev][tile == 2048 ? 0 : 1];
+    if (g == 0) {
+        int cus = 0, per = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+        const void* fn = tile == 2048 ? (const void*)k_view_fused<2048> : (const void*)k_view_fused<4096>;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kFT, 0) != hipSuccess) return 0;
+        const int64_t t = (int64_t)cus * per;
+        g = (int)(t < kViewMaxBlocks ? t : kViewMaxBlocks);
+    }
+    return g;
+}
+
+hipError_t launch_views_fused(const pm4g_prepared* p, const pm4g_view* views, const uint64_t* masks, int32_t V,
+                              ViewWs w, BatchedOutDev out, hipStream_t s) {
+    ProfScope ps(P_VIEW_FUSED, s);
+    // call epochs: distinct per call (and, from a random start, from any word
+    // an earlier owner of the workspace left behind)
+    static std::atomic<uint64_t> epoch{std::random_device{}() * 0x9E3779B97F4A7C15ull};
+    const int grid = fused_grid(w.tile);
+    if (grid <= 0) return hipErrorInvalidConfiguration;
+    FusedArgs a{p->case_s, p->act_s, p->ts_s, p->case_off, p->case_code, p->n_cases, p->status, views, masks,
+                p->n_events, p->n_activities, V, epoch.fetch_add(1) & ((uint64_t(1) << 57) - 1), w, out};
+    void* args[] = {&a};
+    const void* fn = w.tile == 2048 ? (const void*)k_view_fused<2048> : (const void*)k_view_fused<4096>;
+    return hipLaunchCooperativeKernel(fn, dim3((unsigned)grid), dim3(kFT), args, 0, s);
+}
 
 hipError_t launch_views_plan(const pm4g_prepared* p, const pm4g_view* views, int32_t V, ViewWs w,
                              BatchedOutDev out, hipStream_t s) {

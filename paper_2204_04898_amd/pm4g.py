@@ -70,7 +70,7 @@ class BatchedTuning(ctypes.Structure):
     """Launch shape and capacities of pm4g_dfg_batched (zero fields: library defaults)."""
 
     _fields_ = [("tile_events", ctypes.c_int32), ("emit_blocks", ctypes.c_int32),
-                ("agg_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("agg_blocks", ctypes.c_int32), ("launch", ctypes.c_int32),
                 ("pair_capacity", ctypes.c_int64), ("record_capacity", ctypes.c_int64),
                 ("descriptor_capacity", ctypes.c_int64), ("cell_capacity", ctypes.c_int64)]
 
@@ -509,7 +509,7 @@ def pm4g_dfg_batched(prep: Prepared, views: torch.Tensor, masks: torch.Tensor, n
     A = prep.n_activities
     dev = prep.case_s.device
     t = BatchedTuning() if tuning is None else BatchedTuning.from_buffer_copy(tuning)
-    if t.tile_events == 0 and t.emit_blocks == 0 and t.agg_blocks == 0:
+    if t.tile_events == 0 and t.emit_blocks == 0 and t.agg_blocks == 0 and t.launch == 0:
         # launch shape from the autotune cache (capacities: the tuning's or the library's)
         from . import tune
         hit = tune.default_cache().lookup(A, n_views, prep.n_events)
@@ -517,6 +517,7 @@ def pm4g_dfg_batched(prep: Prepared, views: torch.Tensor, masks: torch.Tensor, n
             t.tile_events = int(hit["tile_events"])
             t.emit_blocks = int(hit["emit_blocks"])
             t.agg_blocks = int(hit["agg_blocks"])
+            t.launch = int(hit.get("launch", 1))
     # output cells: at most A*A per view and one per kept event
     cap = int(cap_edges) if cap_edges is not None else \
         max(1024, min(int(n_views) * A * A, prep.n_events, 1 << 24))

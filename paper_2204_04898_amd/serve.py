@@ -329,6 +329,9 @@ class GpuExecutor:
     def _batched_tuning(self, rs: list[Request]):
         caps = [self._caps(r) for r in rs]
         t = self.pm4g.BatchedTuning()
+        # one launch per phase: the workers' batches interleave on the device
+        # (a persistent launch holds every CU until it ends)
+        t.launch = 1
         t.record_capacity = sum(c[0] for c in caps)
         t.pair_capacity = sum(c[1] for c in caps)
         t.cell_capacity = sum(c[2] for c in caps)

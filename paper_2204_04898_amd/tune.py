@@ -2,11 +2,12 @@
 
 Drill-down (Sec. 1) asks for many small views of one formatted log; the
 batched call computes the DFGs of all of them in one pass, and its speed
-depends on the launch shape: the events staged per block (tile_events), the
-grid of the walk that emits the per-view records (emit_blocks) and the grid of
-the per-view aggregation (agg_blocks).  The best shape moves with the
-activity count, the number of views and the log size, so it is measured, not
-guessed:
+depends on the launch shape: the events staged per block (tile_events), and
+either the whole call as one persistent launch on a grid of resident blocks
+(launch 0) or one launch per phase (launch 1) with the grid of the walks that
+emit the per-view records (emit_blocks) and the grid of the per-view
+aggregation (agg_blocks).  The best shape moves with the activity count, the
+number of views and the log size, so it is measured, not guessed:
 
   sweep()   times every candidate shape with a caller-given runner, keeps the
             fastest (median of the repetitions), returns the whole table;
@@ -32,7 +33,9 @@ from typing import Callable, Iterable
 TILES = (2048, 4096)
 EMIT_BLOCKS = (256, 512, 1024, 2048)
 AGG_BLOCKS = (256, 512, 1024)
-CANDIDATES = tuple((t, e, a) for t in TILES for e in EMIT_BLOCKS for a in AGG_BLOCKS)
+# (tile_events, emit_blocks, agg_blocks, launch): the persistent launch sizes its own grid
+CANDIDATES = tuple((t, 0, 0, 0) for t in TILES) + \
+    tuple((t, e, a, 1) for t in TILES for e in EMIT_BLOCKS for a in AGG_BLOCKS)
 
 DEFAULT_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
@@ -55,7 +58,7 @@ def _parse(key: str) -> tuple[int, int, int]:
 
 
 class Cache:
-    """JSON file of {key: {"tile_events", "emit_blocks", "agg_blocks", "ms", ...}}."""
+    """JSON file of {key: {"tile_events", "emit_blocks", "agg_blocks", "launch", "ms", ...}}."""
 
     def __init__(self, path: str | None = None):
         self.path = path or os.environ.get("PM4G_TUNE_CACHE", DEFAULT_PATH)
@@ -110,8 +113,8 @@ class Cache:
         return key
 
 
-def sweep(run: Callable[[tuple[int, int, int]], float], candidates: Iterable[tuple[int, int, int]] = CANDIDATES,
-          reps: int = 3) -> tuple[tuple[int, int, int], list[dict]]:
+def sweep(run: Callable[[tuple], float], candidates: Iterable[tuple] = CANDIDATES,
+          reps: int = 3) -> tuple[tuple, list[dict]]:
     """Times each candidate `reps` times with run(candidate) -> seconds (after
     one untimed call); returns the candidate with the smallest median and the
     table of medians.  Ties go to the earlier candidate."""
@@ -121,7 +124,8 @@ def sweep(run: Callable[[tuple[int, int, int]], float], candidates: Iterable[tup
         run(c)   # warm-up: capacities, code objects
         ts = [float(run(c)) for _ in range(max(1, reps))]
         med = statistics.median(ts)
-        table.append({"tile_events": c[0], "emit_blocks": c[1], "agg_blocks": c[2], "ms": med * 1e3})
+        table.append({"tile_events": c[0], "emit_blocks": c[1], "agg_blocks": c[2],
+                      "launch": c[3] if len(c) > 3 else 1, "ms": med * 1e3})
         if best_t is None or med < best_t:
             best, best_t = c, med
     if best is None:
@@ -147,7 +151,8 @@ def tune_batched(prep, views, masks, n_views: int, reps: int = 3, candidates=CAN
     def run(c):
         t = tunings.get(c)
         if t is None:
-            t = pm4g.BatchedTuning(tile_events=c[0], emit_blocks=c[1], agg_blocks=c[2], **caps)
+            t = pm4g.BatchedTuning(tile_events=c[0], emit_blocks=c[1], agg_blocks=c[2],
+                                   launch=c[3] if len(c) > 3 else 1, **caps)
             # the pair count depends on the tile: let one call size it
             o = pm4g.pm4g_dfg_batched(prep, views, masks, n_views, tuning=t, out=out)
             r = [int(x) for x in o["required"].cpu().tolist()]
@@ -160,11 +165,13 @@ def tune_batched(prep, views, masks, n_views: int, reps: int = 3, candidates=CAN
 
     best, table = sweep(run, candidates, reps)
     entry = {"tile_events": best[0], "emit_blocks": best[1], "agg_blocks": best[2],
+             "launch": best[3] if len(best) > 3 else 1,
              "ms": min(r["ms"] for r in table), "n_activities": int(prep.n_activities),
              "n_views": int(n_views), "n_events": int(prep.n_events)}
     (cache or Cache()).store(prep.n_activities, n_views, prep.n_events, entry)
     if log:
-        log(f"autotune: best tile {best[0]} emit {best[1]} agg {best[2]} at {entry['ms']:.2f} ms")
+        log(f"autotune: best tile {best[0]} emit {best[1]} agg {best[2]} launch {entry['launch']} "
+            f"at {entry['ms']:.2f} ms")
     return {"best": entry, "table": table, "tuning": tunings[best]}
 
 

@@ -46,12 +46,15 @@ def check_views(log, views, tuning=None, sample=None):
     return res
 
 
+@pytest.mark.parametrize("launch", [0, 1])
 @pytest.mark.parametrize("tile", [2048, 4096])
-def test_views_scaled_workload(tile):
+def test_views_scaled_workload(tile, launch):
+    """Both launch modes: the whole call as one persistent launch (0) and one
+    launch per phase (1)."""
     log = synth.config_log(3, 0.004)          # ~400k events, 512 activities
     views = synth.make_views(log, 48, seed=7, min_events=50, max_events=300_000)
-    note(f"views: N={log.n_events} V={views.n_views} tile={tile}")
-    t = pm4g.BatchedTuning(tile_events=tile)
+    note(f"views: N={log.n_events} V={views.n_views} tile={tile} launch={launch}")
+    t = pm4g.BatchedTuning(tile_events=tile, launch=launch)
     check_views(log, views, tuning=t)
 
 
@@ -79,7 +82,8 @@ def test_views_small_activity_set_and_edge_views():
     assert res[base.n_views + 1]["n_events"] == 0
 
 
-def test_views_long_cases_cross_tiles():
+@pytest.mark.parametrize("launch", [0, 1])
+def test_views_long_cases_cross_tiles(launch):
     """Cases longer than a tile: the previous kept event comes from an earlier tile."""
     rng = np.random.default_rng(9)
     lens = [9000, 3, 5000, 1, 2500] + list(rng.integers(1, 40, 400))
@@ -101,14 +105,15 @@ def test_views_long_cases_cross_tiles():
         for x in rng.choice(A, rng.integers(1, A + 1), replace=False):
             masks[v, 0] |= np.uint64(1) << np.uint64(x)
     views = synth.Views(case_lo=lo, case_hi=hi, t_lo=tl, t_hi=th, masks=masks)
-    check_views(log, views, tuning=pm4g.BatchedTuning(tile_events=2048))
+    check_views(log, views, tuning=pm4g.BatchedTuning(tile_events=2048, launch=launch))
 
 
-def test_views_capacity_retry():
+@pytest.mark.parametrize("launch", [0, 1])
+def test_views_capacity_retry(launch):
     """Tiny capacities force the PM4G_E_CAPACITY path; the binding retries with what was required."""
     log = synth.config_log(3, 0.002)
     views = synth.make_views(log, 16, seed=11, min_events=100, max_events=100_000)
-    t = pm4g.BatchedTuning(pair_capacity=8, record_capacity=64, cell_capacity=16)
+    t = pm4g.BatchedTuning(pair_capacity=8, record_capacity=64, cell_capacity=16, launch=launch)
     check_views(log, views, tuning=t)
 
 

@@ -56,11 +56,19 @@ def test_sweep_picks_fastest_median():
 
 
 def test_sweep_median_ignores_one_outlier():
-    seq = {(2048, 256, 256): iter([9, 1.0, 50.0, 1.0]), (4096, 256, 256): iter([9, 2.0, 2.0, 2.0])}
+    seq = {(2048, 256, 256, 1): iter([9, 1.0, 50.0, 1.0]), (4096, 256, 256, 1): iter([9, 2.0, 2.0, 2.0])}
     best, _ = tune.sweep(lambda c: next(seq[c]), candidates=list(seq), reps=3)
-    assert best == (2048, 256, 256)
+    assert best == (2048, 256, 256, 1)
 
 
 def test_sweep_rejects_empty():
     with pytest.raises(ValueError):
         tune.sweep(lambda c: 1.0, candidates=[])
+
+
+def test_candidates_cover_both_launch_modes():
+    """The sweep weighs the persistent launch (its grid sized by the library)
+    against one launch per phase for every tile size."""
+    modes = {(c[0], c[3]) for c in tune.CANDIDATES}
+    assert modes == {(t, m) for t in tune.TILES for m in (0, 1)}
+    assert all(c[1] == 0 and c[2] == 0 for c in tune.CANDIDATES if c[3] == 0)

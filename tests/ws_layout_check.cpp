@@ -157,7 +157,8 @@ void views(int64_t n, int32_t A, int32_t V, int32_t tile, int64_t pair_cap, int6
     check(tag("views", n, A, V) + "/" + std::to_string(tile), b.off,
           {NEED(w, p0, vm), NEED(w, p1, vm), NEED(w, tcount, tiles + 2), NEED(w, toff, tiles + 1),
            NEED(w, tcursor, tiles + 1), NEED(w, list, at_least1(pair_cap)), NEED(w, scal, 13),
-           NEED(w, part32, dev::kScanGrid), NEED(w, part64, dev::kScanGrid), NEED(w, rec_cell, at_least1(rec_cap)),
+           NEED(w, part32, dev::kScanGrid), NEED(w, part64, dev::kScanGrid), NEED(w, part64b, dev::kScanGrid),
+           NEED(w, bar, kViewMaxBlocks + 1), NEED(w, rec_cell, at_least1(rec_cap)),
            NEED(w, rec_gap, at_least1(rec_cap)), NEED(w, pair_carry, at_least1(pair_cap)),
            NEED(w, pair_rel, at_least1(pair_cap) * view_buckets(A)), NEED(w, vb_cnt, nvb), NEED(w, vb_base, nvb),
            NEED(w, vb_flag, nvb), NEED(w, vb_seg, nvb), NEED(w, seg_key, nvb), NEED(w, seg_rec, nvb + 1),
