@@ -291,7 +291,8 @@ def cpu_model() -> str | None:
     return None
 
 
-def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int, autotune: bool = True) -> dict:
+def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int, autotune: bool = True,
+                compare_launch: bool = True) -> dict:
     """Batched drill-down views over the prepared log: one call for all views,
     against a loop of one-view calls of the same entry point."""
     import numpy as np
@@ -343,13 +344,15 @@ def bench_views(log, prep, n_views: int, steps: int, per_view_sample: int, autot
     other.launch = 1 - tune.launch
     if other.launch == 1 and other.emit_blocks == 0:
         other.emit_blocks, other.agg_blocks = 2048, 256
-    pm4g.pm4g_dfg_batched(prep, vd, md, n_views, tuning=other, out=out)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
+    other_ms = None
+    if compare_launch:
         pm4g.pm4g_dfg_batched(prep, vd, md, n_views, tuning=other, out=out)
-    torch.cuda.synchronize()
-    other_ms = (time.perf_counter() - t0) / steps * 1e3
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            pm4g.pm4g_dfg_batched(prep, vd, md, n_views, tuning=other, out=out)
+        torch.cuda.synchronize()
+        other_ms = (time.perf_counter() - t0) / steps * 1e3
     # per-view launches of the same entry point on a sample of the views
     # (one launch per phase: the faster form for one small view)
     idx = np.linspace(0, n_views - 1, per_view_sample).astype(int)
@@ -895,6 +898,9 @@ def main() -> int:
     ap.add_argument("--views", type=int, default=4096, help="batched drill-down views (0: skip)")
     ap.add_argument("--view-steps", type=int, default=3)
     ap.add_argument("--per-view-sample", type=int, default=64)
+    ap.add_argument("--no-launch-compare", action="store_true",
+                    help="views: do not time the other launch mode (rocprofv3 --kernel-trace stops on "
+                         "cooperative launches)")
     ap.add_argument("--no-autotune", action="store_true", help="batched views with the cached launch shape (no sweep)")
     ap.add_argument("--tune-cache", default=None, help="autotune cache file (default: the package's)")
     ap.add_argument("--no-cases", action="store_true", help="skip the cases-dataframe and case-filter timing")
@@ -1046,7 +1052,8 @@ def main() -> int:
         if args.tune_cache:
             os.environ["PM4G_TUNE_CACHE"] = args.tune_cache
         out["batched_views"] = bench_views(log, prep, args.views, args.view_steps, args.per_view_sample,
-                                           autotune=not args.no_autotune)
+                                           autotune=not args.no_autotune,
+                                           compare_launch=not args.no_launch_compare)
     if k == 3 and not args.no_cases:
         log_progress("cases dataframe and case filters")
         out["cases"] = bench_cases(log, prep)

@@ -140,6 +140,19 @@ def test_full_4096_views(big, big_oracle):
         kept = list(ex.map(check, range(views.n_views)))
     note(f"4096 views checked: {sum(kept)} kept events")
 
+    # the other launch mode gives the same bytes: the whole call as one
+    # persistent launch and one launch per phase
+    for launch in (0, 1):
+        t = pm4g.BatchedTuning(tile_events=4096, launch=launch)
+        o2 = pm4g.pm4g_dfg_batched(prep, vd, md, views.n_views, tuning=t)
+        note(f"launch mode {launch}: compared with the checked call")
+        for k in ("edge_off", "src", "dst", "count", "dt_sum", "dt_min", "dt_max", "start_count",
+                  "end_count", "act_count", "n_events", "n_cases"):
+            m = int(o["edge_off"][views.n_views].item()) if k in ("src", "dst", "count", "dt_sum", "dt_min",
+                                                                  "dt_max") else None
+            a, b = (o[k], o2[k]) if m is None else (o[k][:m], o2[k][:m])
+            assert torch.equal(a, b), (launch, k)
+
 
 def _u128(lo, hi):
     return [int(a) + (int(b) << 64) for a, b in zip(lo.ravel(), hi.ravel())]
