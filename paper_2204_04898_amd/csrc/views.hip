@@ -889,7 +889,7 @@ __device__ __forceinline__ void ph_copy(Grid gd, int32_t A, ViewWs w, BatchedOut
     }
 }
 
-__global__ void k_view_copy(int32_t A, ViewWs w, BatchedOutDev out) { ph_copy(hw_grid(), A, w, out); }
+
 
 // Per view: its segments form a run of the sorted segment list; fold their
 // cells into row and column sums; derive activity and end counts.
@@ -981,9 +981,18 @@ __device__ __forceinline__ void ph_acts(Grid gd, int32_t V, int32_t A, ViewWs w,
     }
 }
 
-__global__ __launch_bounds__(256) void k_view_acts(int32_t V, int32_t A, ViewWs w, BatchedOutDev out) {
+// The copy and the activity counts read the same temporary cells and write
+// disjoint outputs: one launch, its first kOutCopyBlocks blocks copying and the
+// others counting, so that the two latency-bound phases overlap.
+constexpr int64_t kOutCopyBlocks = 2048;
+
+__global__ __launch_bounds__(256) void k_view_out(int32_t V, int32_t A, ViewWs w, BatchedOutDev out) {
     __shared__ ActsSmem<256> S;
-    ph_acts<256>(hw_grid(), V, A, w, out, S);
+    if ((int64_t)blockIdx.x < kOutCopyBlocks)
+        ph_copy(Grid{(int64_t)blockIdx.x, kOutCopyBlocks}, A, w, out);
+    else
+        ph_acts<256>(Grid{(int64_t)blockIdx.x - kOutCopyBlocks, (int64_t)gridDim.x - kOutCopyBlocks}, V, A, w,
+                     out, S);
 }
 
 __device__ __forceinline__ void ph_finish(Grid gd, int32_t V, ViewWs w, BatchedOutDev out) {
@@ -1293,8 +1302,7 @@ hipError_t launch_views_reduce(const pm4g_prepared* p, const pm4g_view* views, c
         ProfScope ps(P_VIEW_OUT, s);
         dev::excl_scan<int64_t>(w.seg_cells, &w.scal[2], w.seg_out, w.part64, &w.scal[4], s);
         dev::excl_scan<int64_t>(w.view_cells, &w.scal[6], out.edge_off, w.part64, (int64_t*)nullptr, s);
-        k_view_copy<<<2048, 256, 0, s>>>(A, w, out);
-        k_view_acts<<<2048, 256, 0, s>>>(V, A, w, out);
+        k_view_out<<<(unsigned)(kOutCopyBlocks + 2048), 256, 0, s>>>(V, A, w, out);
         k_view_finish<<<1, 1, 0, s>>>(V, w, out);
     }
     return hipGetLastError();
