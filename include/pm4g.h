@@ -314,7 +314,7 @@ int pm4g_dfg_prepared_noalloc(const pm4g_prepared *log, const pm4g_dfg_out *out,
  * n_views * ceil(A/64) words, bit a of word a/64 of row v selects activity a
  * for view v).  Requires A <= PM4G_BATCHED_MAX_ACTIVITIES.  Does not
  * synchronise: every capacity is checked on the device.  When one is short
- * -- the pair, record, descriptor or cell capacity of `tuning`, or cap_edges
+ * -- the pair, record or cell capacity of `tuning`, or cap_edges
  * -- out->status becomes PM4G_E_CAPACITY and out->required holds the sizes
  * known at that point (0 for those that are not: the output and cell counts
  * are known only once the records fit): call again with larger capacities
@@ -322,6 +322,12 @@ int pm4g_dfg_prepared_noalloc(const pm4g_prepared *log, const pm4g_dfg_out *out,
  * one call give status PM4G_E_INVALID (split the views).  n_views times the
  * number of 4096-cell buckets of the A*(A+1) cells, ceil(A*(A+1)/4096), must
  * stay below 2^32 (else PM4G_E_INVALID, returned, and a workspace size of 0).
+ * With tuning->launch 0 (the default) the call is one cooperative launch of
+ * one block per compute unit: its phases meet at grid barriers whose waits
+ * are bounded, and a barrier that does not complete within seconds sets
+ * out->status to PM4G_E_DEVICE (the outputs are then not valid) instead of
+ * hanging; a failed cooperative launch returns PM4G_E_DEVICE.  With launch 1
+ * each phase is a launch of its own.  Both give the same bytes.
  */
 size_t pm4g_batched_workspace_bytes(int64_t n_events, int32_t n_activities, int32_t n_views,
                                     const pm4g_batched_tuning *tuning);
