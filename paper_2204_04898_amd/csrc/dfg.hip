@@ -1,6 +1,7 @@
-// Directly-follows graph aggregation over a prepared log (Sec. 3,
-// directly-follows level: frequency / performance DFG; start/end activities;
-// occurrences per activity).  For position i of the ordered log, the event
+// Directly-follows graph aggregation over a prepared log (Sec. 3, the
+// aggregations over consecutive event pairs: frequency and performance DFG;
+// start and end activities; how often each activity occurs).  For position i
+// of the ordered log, the event
 // directly follows i-1 iff both have the same case; the pair contributes to
 // cell act_s[i-1]*A + act_s[i] with gap ts_s[i] - ts_s[i-1] (mod 2^64).
 //
