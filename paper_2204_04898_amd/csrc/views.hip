@@ -1142,62 +1142,101 @@ union FusedSmem {
 
 // The whole batched call in one launch: the phases of the per-phase kernels,
 // in the same order, separated by grid barriers.
+// The kernel's arguments are read through a pointer that each phase takes
+// anew from an empty register move the compiler cannot see through, so a
+// phase loads the fields it uses instead of the whole set staying live (in
+// scalar registers, then spilled) across the launch.
+typedef const FusedArgs __attribute__((address_space(4))) KernArgs;   // the kernel-argument segment
+__device__ __forceinline__ FusedArgs fresh(KernArgs* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("" : "+s"(p));
+    return *p;
+#else
+    (void)p;   // the host pass compiles device code it never runs
+    return FusedArgs{};
+#endif
+}
+
 template <int TILE>
-__global__ __launch_bounds__(kFT) void k_view_fused(FusedArgs a) {
+__global__ __launch_bounds__(kFT) void k_view_fused(FusedArgs args) {
     __shared__ FusedSmem<TILE> sm;
     const Grid gd = hw_grid();
-    ViewWs& w = a.w;
-    const int32_t V = a.V, A = a.A;
-    uint64_t k = a.epoch << 6;
-    int32_t* st = a.out.status;
-    ph_init(gd, w, V, A, a.status_in, a.out);
-    grid_barrier(gd, w.bar, ++k, st);
-    ph_span(gd, a.case_off, a.ts_s, a.n_cases, w);
-    ph_slice(gd, a.views, V, a.case_off, a.case_code, a.n_cases, w);
-    grid_barrier(gd, w.bar, ++k, st);
-    ph_tile_scan(gd, w);
-    grid_barrier(gd, w.bar, ++k, st);
-    ph_fill(gd, V, w);
-    grid_barrier(gd, w.bar, ++k, st);
-    ph_count<TILE, kFT / kWave>(gd, a.case_s, a.act_s, a.ts_s, a.n, A, a.views, a.masks, w, sm.walk);
-    grid_barrier(gd, w.bar, ++k, st);
-    ph_vb_flags(gd, w, V);
-    grid_barrier(gd, w.bar, ++k, st);
+    KernArgs* ap = (KernArgs*)__builtin_amdgcn_kernarg_segment_ptr();
+    uint64_t k = args.epoch << 6;
+    int32_t* st = args.out.status;
+    uint64_t* bar = args.w.bar;
+#define PA (fresh(ap))
+    ph_init(gd, PA.w, PA.V, PA.A, PA.status_in, PA.out);
+    grid_barrier(gd, bar, ++k, st);
+    ph_span(gd, PA.case_off, PA.ts_s, PA.n_cases, PA.w);
+    ph_slice(gd, PA.views, PA.V, PA.case_off, PA.case_code, PA.n_cases, PA.w);
+    grid_barrier(gd, bar, ++k, st);
+    ph_tile_scan(gd, PA.w);
+    grid_barrier(gd, bar, ++k, st);
+    ph_fill(gd, PA.V, PA.w);
+    grid_barrier(gd, bar, ++k, st);
     {
+        const FusedArgs a = PA;
+        ph_count<TILE, kFT / kWave>(gd, a.case_s, a.act_s, a.ts_s, a.n, a.A, a.views, a.masks, a.w, sm.walk);
+    }
+    grid_barrier(gd, bar, ++k, st);
+    ph_vb_flags(gd, PA.w, PA.V);
+    grid_barrier(gd, bar, ++k, st);
+    {
+        const ViewWs w = PA.w;
         const int64_t nvb = w.scal[11];
         gscan_reduce<int64_t>(gd, w.vb_cnt, nvb, w.part64);
         gscan_reduce<uint32_t>(gd, w.vb_flag, nvb, w.part32);
-        grid_barrier(gd, w.bar, ++k, st);
+    }
+    grid_barrier(gd, bar, ++k, st);
+    {
+        const ViewWs w = PA.w;
         gscan_top<int64_t>(gd, w.part64, &w.scal[9]);
         gscan_top<uint32_t>(gd, w.part32, reinterpret_cast<uint32_t*>(&w.scal[8]));
-        grid_barrier(gd, w.bar, ++k, st);
+    }
+    grid_barrier(gd, bar, ++k, st);
+    {
+        const ViewWs w = PA.w;
+        const int64_t nvb = w.scal[11];
         gscan_apply<int64_t>(gd, w.vb_cnt, nvb, w.part64, w.vb_base);
         gscan_apply<uint32_t>(gd, w.vb_flag, nvb, w.part32, w.vb_seg);
-        grid_barrier(gd, w.bar, ++k, st);
     }
-    ph_gate(gd, w);
-    ph_segs(gd, w);
-    grid_barrier(gd, w.bar, ++k, st);
-    ph_write<TILE, kFT / kWave>(gd, a.case_s, a.act_s, a.ts_s, a.n, A, a.views, a.masks, w, sm.walk);
-    grid_barrier(gd, w.bar, ++k, st);
-    ph_agg(gd, A, w, a.out, sm.agg);
-    grid_barrier(gd, w.bar, ++k, st);
+    grid_barrier(gd, bar, ++k, st);
+    ph_gate(gd, PA.w);
+    ph_segs(gd, PA.w);
+    grid_barrier(gd, bar, ++k, st);
     {
-        const int64_t S = w.scal[2];
-        gscan_reduce<int64_t>(gd, w.seg_cells, S, w.part64);
-        gscan_reduce<int64_t>(gd, w.view_cells, V, w.part64b);
-        grid_barrier(gd, w.bar, ++k, st);
-        gscan_top<int64_t>(gd, w.part64, &w.scal[4]);
-        gscan_top<int64_t>(gd, w.part64b, nullptr);
-        grid_barrier(gd, w.bar, ++k, st);
-        gscan_apply<int64_t>(gd, w.seg_cells, S, w.part64, w.seg_out);
-        gscan_apply<int64_t>(gd, w.view_cells, V, w.part64b, a.out.edge_off);
-        grid_barrier(gd, w.bar, ++k, st);
+        const FusedArgs a = PA;
+        ph_write<TILE, kFT / kWave>(gd, a.case_s, a.act_s, a.ts_s, a.n, a.A, a.views, a.masks, a.w, sm.walk);
     }
-    ph_copy(gd, A, w, a.out);
-    ph_acts<kFT>(gd, V, A, w, a.out, sm.acts);
-    grid_barrier(gd, w.bar, ++k, st);
-    ph_finish(gd, V, w, a.out);
+    grid_barrier(gd, bar, ++k, st);
+    ph_agg(gd, PA.A, PA.w, PA.out, sm.agg);
+    grid_barrier(gd, bar, ++k, st);
+    {
+        const FusedArgs a = PA;
+        const int64_t S = a.w.scal[2];
+        gscan_reduce<int64_t>(gd, a.w.seg_cells, S, a.w.part64);
+        gscan_reduce<int64_t>(gd, a.w.view_cells, a.V, a.w.part64b);
+    }
+    grid_barrier(gd, bar, ++k, st);
+    {
+        const FusedArgs a = PA;
+        gscan_top<int64_t>(gd, a.w.part64, &a.w.scal[4]);
+        gscan_top<int64_t>(gd, a.w.part64b, nullptr);
+    }
+    grid_barrier(gd, bar, ++k, st);
+    {
+        const FusedArgs a = PA;
+        const int64_t S = a.w.scal[2];
+        gscan_apply<int64_t>(gd, a.w.seg_cells, S, a.w.part64, a.w.seg_out);
+        gscan_apply<int64_t>(gd, a.w.view_cells, a.V, a.w.part64b, a.out.edge_off);
+    }
+    grid_barrier(gd, bar, ++k, st);
+    ph_copy(gd, PA.A, PA.w, PA.out);
+    ph_acts<kFT>(gd, PA.V, PA.A, PA.w, PA.out, sm.acts);
+    grid_barrier(gd, bar, ++k, st);
+    ph_finish(gd, PA.V, PA.w, PA.out);
+#undef PA
 }
 
 }  // namespace
