@@ -1232,8 +1232,12 @@ __global__ __launch_bounds__(kFT) void k_view_fused(FusedArgs args) {
         gscan_apply<int64_t>(gd, a.w.view_cells, a.V, a.w.part64b, a.out.edge_off);
     }
     grid_barrier(gd, bar, ++k, st);
-    ph_copy(gd, PA.A, PA.w, PA.out);
-    ph_acts<kFT>(gd, PA.V, PA.A, PA.w, PA.out, sm.acts);
+    {   // the copy on half of the blocks, the activity counts on the other half
+        const int64_t half = gd.nblk / 2 > 0 ? gd.nblk / 2 : 1;
+        if (gd.bid < half || gd.nblk < 2) ph_copy(Grid{gd.bid, half}, PA.A, PA.w, PA.out);
+        if (gd.bid >= half || gd.nblk < 2)
+            ph_acts<kFT>(gd.nblk < 2 ? gd : Grid{gd.bid - half, gd.nblk - half}, PA.V, PA.A, PA.w, PA.out, sm.acts);
+    }
     grid_barrier(gd, bar, ++k, st);
     ph_finish(gd, PA.V, PA.w, PA.out);
 #undef PA
