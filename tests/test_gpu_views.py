@@ -206,3 +206,33 @@ def test_batched_call_does_not_wait_and_reports_capacity_on_the_device():
         for k in ("src", "dst", "count", "dt_sum", "dt_min", "dt_max"):
             assert np.array_equal(res[v][k], sp[k]), (v, k)
         assert res[v]["n_events"] == ref["n_events"], v
+
+
+@pytest.mark.parametrize("n_events,n_views", [(1, 1), (1, 0), (5000, 0), (5000, 1), (70_000, 3)])
+def test_launch_modes_on_small_and_empty_calls(n_events, n_views):
+    """One event, no views, one view: the persistent launch (every phase on a
+    grid of resident blocks, most of them idle) and the per-phase launches give
+    the oracle's tables."""
+    rng = np.random.default_rng(n_events + 7 * n_views)
+    A = 20
+    C = max(1, n_events // 9)
+    case = np.sort(rng.integers(0, C, n_events)).astype(np.int32)
+    case[0] = 0
+    _, case = np.unique(case, return_inverse=True)
+    case = case.astype(np.int32)
+    act = rng.integers(0, A, n_events).astype(np.int32)
+    ts = rng.integers(0, 10**9, n_events, dtype=np.int64)
+    perm = rng.permutation(n_events)
+    lens = np.bincount(case).astype(np.int64)
+    log = synth.Log(case=case[perm], act=act[perm], ts=ts[perm], n_activities=A, presorted=False,
+                    lengths_by_code=lens)
+    nc = int(case.max()) + 1
+    lo = rng.integers(0, nc, n_views).astype(np.int32)
+    hi = np.minimum(lo + rng.integers(1, nc + 1, n_views), nc).astype(np.int32)
+    views = synth.Views(case_lo=lo, case_hi=hi, t_lo=np.full(n_views, 10**8, np.int64),
+                        t_hi=np.full(n_views, 9 * 10**8, np.int64),
+                        masks=np.full((n_views, 1), np.uint64((1 << A) - 1 - 6)))
+    for launch in (0, 1):
+        note(f"launch {launch}: N={n_events} V={n_views}")
+        res = check_views(log, views, tuning=pm4g.BatchedTuning(tile_events=4096, launch=launch))
+        assert len(res) == n_views
